@@ -1,0 +1,230 @@
+/*
+ * lbell.h - C ABI of the MI355X (gfx950) lattice Boltzmann library for rigid
+ * ellipsoidal particles.
+ *
+ * Method: Thampi, Stratford, Henrich, "Simulating dynamics of ellipsoidal
+ * particles using lattice Boltzmann method" (arXiv 2403.05443).  One call of
+ * lb_step advances every box by the algorithm of the paper's Appendix A:
+ *   collide (Sec. II.A) -> stream, skipping links into solid nodes ->
+ *   velocity-independent force/torque F0, T0 (eqs. F0, T0) ->
+ *   lab-frame inertia I(t) and dI/dt (eqs. Irot, Irotdiff) ->
+ *   implicit 6x6 solve for U(t+1), Omega(t+1) (eqs. Fdiscrete, Tdiscrete) ->
+ *   link bounce-back with moving-boundary term (eqs. fb, ub / ubsquirmer) ->
+ *   position and quaternion update (eqs. posupdate, qnplus0, qnplus1) ->
+ *   remap of solid/fluid/boundary nodes (eq. ellipsoidsurface) ->
+ *   drag matrices zeta (eqs. drag1-drag4).
+ *
+ * Conventions (all of them are fixed by this header):
+ *  - Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3.  D3Q19 velocity order
+ *      0:(0,0,0) 1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1)
+ *      6:(0,0,-1) 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0) 11:(1,0,1)
+ *      12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1) 16:(0,-1,-1)
+ *      17:(0,1,-1) 18:(0,-1,1); the opposite of an odd i is i+1.
+ *      Weights 1/3 (rest), 1/18 (axis), 1/36 (diagonal).
+ *  - Nodes sit at integer coordinates 0..n-1; site index = x + nx*(y + ny*z).
+ *  - Quaternions are Hamilton, scalar first, rotating body to lab
+ *    (s_lab = q s_body q^-1, Sec. II.D); Omega is in the lab frame.
+ *  - Body axes: semi-axis a lies along body x, b along body y, c along body z.
+ *  - A node is solid when (x-x_c)^T A (x-x_c) < 1 (strict), evaluated with the
+ *    minimum-image separation in every periodic direction.
+ *  - Every call returns lb_status; 0 is success, negative values are errors.
+ *    Nothing throws or aborts across this boundary.  A context is not
+ *    thread-safe; use one per host thread.
+ *  - Device memory is owned by the caller: lb_init receives one device
+ *    buffer (the arena) and a hipStream_t; the library never allocates
+ *    device memory and never frees the arena.  Host pointers passed in are
+ *    read (or written) during the call only.
+ */
+#ifndef LBELL_H
+#define LBELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int lb_status;
+#define LB_OK          0
+#define LB_EINVAL     -1   /* bad argument or configuration                     */
+#define LB_ENOMEM     -2   /* arena too small, or a fixed capacity exhausted     */
+#define LB_EDEVICE    -3   /* a HIP runtime call failed                          */
+#define LB_ESTATE     -4   /* call not valid in the current state               */
+#define LB_EOVERLAP   -5   /* particle overlaps another particle or a wall      */
+#define LB_ENONFINITE -6   /* non-finite value, singular 6x6 system, or |U|>0.5 */
+#define LB_ERANGE     -7   /* caller buffer too small (required size returned)  */
+#define LB_EIO        -8   /* checkpoint file could not be read or written      */
+
+/* Collision operators (Sec. II.A). */
+#define LB_BGK 0   /* single relaxation time: f* = f - (f - f_eq)/tau                  */
+#define LB_TRT 1   /* two relaxation times; tau+ = tau, Lambda = (tau+-1/2)(tau--1/2)  */
+#define LB_REG 2   /* hydrodynamic (stress) modes relaxed with tau, non-hydrodynamic
+                      (ghost) modes relaxed instantaneously (end of Sec. II.A)         */
+
+/* Population storage.  All but LB_FP64 store deviations f_i - w_i*rho0; the
+ * half-precision formats store 2^scale_log2 * (f_i - w_i*rho0).  Collision
+ * arithmetic is FP64 for LB_FP64 and FP32 otherwise; particle quantities are
+ * always FP64. */
+#define LB_FP64 0
+#define LB_FP32 1
+#define LB_FP16 2
+#define LB_BF16 3
+
+typedef struct lb_config {
+    int    lattice;         /* must be 19                                              */
+    int    collision;       /* LB_BGK, LB_TRT or LB_REG                                */
+    double tau;             /* relaxation time (TRT: tau+), nu = (tau - 1/2)/3, > 1/2  */
+    double magic;           /* TRT Lambda; default 3/16                                */
+    int    storage;         /* LB_FP64 / LB_FP32 / LB_FP16 / LB_BF16                   */
+    int    scale_log2;      /* half formats: storage scale exponent; 0 = derive from
+                               velocity_scale as floor(log2(0.25/(velocity_scale/6)))  */
+    double velocity_scale;  /* largest fluid speed expected; default 1e-3              */
+    double rho0;            /* mean density; must be 1                                 */
+    int    counterforce;    /* 1: add g = -sum(F_ext)/N_fluid to every fluid node each
+                               step so that total momentum stays zero (default 0)      */
+    int    max_particles;   /* particle capacity over all boxes (default 1 per box)    */
+    double max_semi_axis;   /* largest semi-axis any particle may have (default 8)     */
+} lb_config;
+
+typedef struct lb_box {
+    int    nx, ny, nz;      /* box edge lengths, each >= 4                             */
+    int    walls;           /* 0: periodic in y; 1: solid walls at y=0 and y=ny-1,
+                               moving with wall_lo / wall_hi (bounce-back links)       */
+    double wall_lo[3];      /* velocity of the wall layer y = 0                        */
+    double wall_hi[3];      /* velocity of the wall layer y = ny-1                     */
+    int    init;            /* 0: fluid at rest; 1: Couette profile between the walls  */
+} lb_box;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Fills *cfg with defaults: D3Q19, BGK, tau = 1, magic = 3/16, FP32 storage,
+ * rho0 = 1, no counter-force, max_semi_axis = 8, max_particles = 0 (meaning
+ * one per box at lb_init). */
+lb_status lb_config_default(lb_config* cfg);
+
+/* Device bytes lb_init needs for this configuration and box list, or 0 if the
+ * arguments are invalid.  boxes: host array of nboxes entries. */
+size_t lb_arena_bytes(const lb_config* cfg, int nboxes, const lb_box* boxes);
+
+/* Creates a context over nboxes independent boxes.  dev_arena: device buffer
+ * of at least lb_arena_bytes() bytes, 256-byte aligned, owned by the caller
+ * and kept alive until lb_destroy.  hip_stream: the hipStream_t all work is
+ * enqueued on (NULL = the default stream).  Populations are initialised to
+ * f_eq(rho0, u0) with u0 = 0, or the wall-driven Couette profile (init = 1),
+ * including its first-order non-equilibrium part.  Synchronises the stream. */
+lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes,
+                  void* dev_arena, size_t arena_bytes, void* hip_stream,
+                  lb_ctx** out);
+
+/* Adds a rigid ellipsoid (Sec. II.B, eq. ellipsoidsurface) to box `box`.
+ * centre: lab position (any real value; wrapped into the box).  semi_axes:
+ * (a, b, c) > 0 along body x, y, z.  quat: orientation, normalised if
+ * | |q| - 1 | <= 1e-6, else LB_EINVAL.  The particle density defaults to rho0,
+ * so its mass is M = rho0 * 4/3 pi a b c and its body inertia is
+ * diag(M(b^2+c^2)/5, M(a^2+c^2)/5, M(a^2+b^2)/5) (Sec. II.D).  Nodes inside
+ * become solid and their fluid is discarded; boundary links and drag
+ * matrices are built.  LB_EINVAL if 2*max(a,b,c)+2 exceeds a box dimension
+ * or max(a,b,c) > cfg.max_semi_axis; LB_EOVERLAP if a node would belong to
+ * another particle or a wall; LB_ENOMEM when the capacity is exhausted.
+ * *id receives a dense particle id (0, 1, ...).  Synchronises. */
+lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3],
+                           const double semi_axes[3], const double quat[4],
+                           int* id);
+
+/* Constant external force and torque on particle id (lab frame); they enter
+ * the right-hand sides of eqs. Fdiscrete and Tdiscrete. */
+lb_status lb_set_external(lb_ctx* ctx, int id, const double F[3], const double T[3]);
+
+/* Spheroidal squirmer slip (Sec. III.D, eqs. squirmer, ubsquirmer): the
+ * boundary velocity gains u_s = -B1 (s.e) s - B2 zeta (s.e) s, with e the body
+ * x axis.  Requires b == c.  B1 = B2 = 0 switches it off. */
+lb_status lb_set_squirmer(lb_ctx* ctx, int id, double B1, double B2);
+
+/* Overwrites the particle's translational and angular velocity (lab frame). */
+lb_status lb_set_velocity(lb_ctx* ctx, int id, const double U[3], const double W[3]);
+
+/* Particle density (default rho0); rescales M and the body inertia. */
+lb_status lb_set_particle_density(lb_ctx* ctx, int id, double rho_p);
+
+/* Enqueues n time steps (Appendix A, steps 1-10) of every box on the stream
+ * and returns without waiting.  Device-side errors (overlap, non-finite
+ * velocity, singular system, capacity overflow) are latched and reported by
+ * the next synchronising call. */
+lb_status lb_step(lb_ctx* ctx, int n);
+
+/* Waits for the stream; returns the first latched device error, if any. */
+lb_status lb_sync(lb_ctx* ctx);
+
+/* Hydrodynamic force and torque on particle id over the last step
+ * (eqs. Fsplit, Tsplit): F = F0 + Fslip - zeta_FU U(t+1) - zeta_FW W(t+1)
+ * plus the impulse of nodes covered or uncovered in the previous remap;
+ * torque about the centre.  External loads are not included.  Synchronises. */
+lb_status lb_get_force_torque(lb_ctx* ctx, int id, double F[3], double T[3]);
+
+/* Position (unwrapped: initial centre plus accumulated displacement),
+ * orientation, velocity and angular velocity of particle id.  Any output
+ * pointer may be NULL.  Synchronises. */
+lb_status lb_get_particle(lb_ctx* ctx, int id, double x[3], double q[4],
+                          double U[3], double W[3]);
+
+/* Book-keeping of particle id: mass M, undistributed mass dm of covered and
+ * uncovered nodes (returned to the fluid at the next bounce-back), pending
+ * momentum P[3] and angular momentum L[3] of those nodes (added to the next
+ * implicit solve), and the current number of boundary links.  Any output
+ * pointer may be NULL.  Synchronises. */
+lb_status lb_get_particle_aux(lb_ctx* ctx, int id, double* M, double* dm,
+                              double P[3], double L[3], int* nlinks);
+
+/* Boundary links (x, b) of particle id: x fluid, x + c_b solid (Sec. II.B).
+ * site[k] is the site index of x, dir[k] is b (1..18).  Order: deterministic,
+ * not sorted.  If cap < the number of links, nothing is copied, *n is set and
+ * LB_ERANGE returned.  Synchronises. */
+lb_status lb_get_links(lb_ctx* ctx, int id, uint32_t* site, uint8_t* dir,
+                       int cap, int* n);
+
+/* Node map of box: 0 = fluid, id+1 = solid node of particle id, 0xFFFF = wall.
+ * owner: host array of nx*ny*nz entries.  Synchronises. */
+lb_status lb_get_mask(lb_ctx* ctx, int box, uint16_t* owner);
+
+/* Density and velocity of the (pre-collision) fluid at every site of box,
+ * rho[site], u[3*site + k]; solid and wall sites report rho = 0, u = 0.
+ * Either pointer may be NULL.  Synchronises. */
+lb_status lb_get_fields(lb_ctx* ctx, int box, double* rho, double* u);
+
+/* Conserved mass of box: sum of rho over fluid nodes plus dm of its particles.
+ * Momentum: sum of rho*u over fluid nodes (particles not included).
+ * Synchronises. */
+lb_status lb_get_mass(lb_ctx* ctx, int box, double* mass);
+lb_status lb_get_momentum(lb_ctx* ctx, int box, double P[3]);
+
+/* Counts non-finite populations on fluid nodes of box.  Synchronises. */
+lb_status lb_check_finite(lb_ctx* ctx, int box, long long* count);
+
+/* Number of completed steps. */
+lb_status lb_get_step(lb_ctx* ctx, long long* step);
+
+/* Checkpoint: every population, node map, link list and particle record plus
+ * the step counter, to a binary file; lb_load restores it into a context made
+ * with the same configuration and boxes.  LB_EIO on file errors, LB_EINVAL on
+ * a mismatching file.  Synchronise. */
+lb_status lb_save(lb_ctx* ctx, const char* path);
+lb_status lb_load(lb_ctx* ctx, const char* path);
+
+/* Test hook: sets the pre-collision population dir of site in box to
+ * w_dir*rho0 + value (so value is the deviation; NaN allowed).  Synchronises. */
+lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value);
+
+/* Releases host resources of ctx (not the arena).  Synchronises. */
+lb_status lb_destroy(lb_ctx* ctx);
+
+/* Static text for a status code. */
+const char* lb_status_str(lb_status s);
+
+/* Text of the last error recorded in ctx ("" if none). */
+const char* lb_last_error(lb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBELL_H */
