@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Throughput of the full LB time step (collide-stream + particle phase) on one
+MI355X, in million lattice-site updates per second (MLUPS), with the
+collide-stream kernel's fraction of the HBM roofline and the FP64 CPU oracle
+timed on the host beside it.
+
+Default workload: the inclined sedimenting spheroid, 128^3 periodic box,
+D3Q19 TRT (Lambda = 3/16, tau+ = 0.8), spheroid a=6, b=c=2 at 45 deg to a
+5e-4 force, counter-force on, FP32 population storage.  Inputs are resident in
+device memory before the timed region starts.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 is refused.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 MLUPS + % HBM roofline; steps to steady state, plain vs surrogate"
+HBM_PEAK_GBS = 8000.0
+BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32", "bf16": "f32"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_stream_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2403_05443_amd", "csrc", "k_stream.hip")
+
+
+def build_lattice(W, device="cuda:0"):
+    from paper_2403_05443_amd import Lattice, make_box
+    boxes = [make_box(*b.shape, walls=b.walls, wall_lo=b.wall_lo, wall_hi=b.wall_hi, init=b.init)
+             for b in W.boxes]
+    lat = Lattice(boxes, collision=W.collision, tau=W.tau, magic=W.magic, storage=W.storage,
+                  counterforce=W.counterforce, velocity_scale=W.velocity_scale,
+                  max_particles=max(1, len(W.particles)), max_semi_axis=W.max_semi_axis, device=device)
+    for p in W.particles:
+        pid = lat.add_ellipsoid(p.centre, p.axes, p.quat, box=p.box)
+        lat.set_external(pid, p.force, p.torque)
+        if p.squirmer != (0.0, 0.0):
+            lat.set_squirmer(pid, *p.squirmer)
+    return lat
+
+
+def traffic_record(src_sha, workload, storage):
+    """HBM bytes per collide-stream launch from the committed counter
+    summary, only if it was taken on this kernel source and workload."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    key = f"{workload}/{storage}"
+    ent = rec.get("entries", {}).get(key)
+    if not ent or rec.get("source_sha256") != src_sha:
+        return None
+    return ent.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(W, seconds):
+    """The oracle as it stands, on the same workload, for a bounded number of
+    steps on the host cores."""
+    import oracle
+    b = W.boxes[0]
+    o = oracle.OracleSim(b.shape, W.collision, W.tau, magic=W.magic, walls=b.walls, wall_lo=b.wall_lo,
+                         wall_hi=b.wall_hi, init=b.init, counterforce=W.counterforce)
+    for p in W.particles:
+        pid = o.add_ellipsoid(p.centre, p.axes, p.quat)
+        o.set_external(pid, p.force, p.torque)
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, int(seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(W.sites * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{W.name}: {n} oracle steps of the {b.shape[0]}x{b.shape[1]}x{b.shape[2]} box "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="fp32", choices=sorted(BYTES))
+    ap.add_argument("--size", type=int, default=128, help="box edge of the inclined-spheroid workload")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_05443_amd import workloads
+    W = workloads.c2(args.storage, args.size)
+    lat = build_lattice(W)
+    N = W.sites
+    lat.step(args.warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    lat.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    lat.sync()
+    mlups = N * args.steps / (ms / 1e3) / 1e6
+
+    # per-kernel durations from HIP events on the library's stream
+    psteps = min(args.steps, 500)
+    ms_c, ms_p = lat.profile_step(psteps)
+    k1 = ms_c / psteps
+    alg_bytes = 38 * BYTES[args.storage] * N
+    achieved = alg_bytes / (k1 / 1e3) / 1e9
+    src_sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    traffic = traffic_record(src_sha, W.name, args.storage)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.storage],
+        "data": "synthetic",
+        "config": {"workload": W.name, "sites": N, "storage": args.storage, "collision": "trt",
+                   "tau_plus": W.tau, "lambda": W.magic, "particles": len(W.particles),
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_collide_stream", "bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": round(k1, 5)},
+        "phase_ms_per_step": {"collide_stream": round(k1, 5), "particle": round(ms_p / psteps, 5)},
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

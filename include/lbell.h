@@ -153,6 +153,12 @@ lb_status lb_set_particle_density(lb_ctx* ctx, int id, double rho_p);
  * the next synchronising call. */
 lb_status lb_step(lb_ctx* ctx, int n);
 
+/* Runs n steps exactly as lb_step does, recording HIP events on the stream
+ * around the collide-stream launch and around the particle phase of every
+ * step; *ms_collide and *ms_particle receive the summed GPU durations in
+ * milliseconds (either may be NULL).  Synchronises. */
+lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_particle);
+
 /* Waits for the stream; returns the first latched device error, if any. */
 lb_status lb_sync(lb_ctx* ctx);
 

@@ -1,0 +1,632 @@
+// k_particle.hip - the particle phase of one time step, one work-group per
+// particle (Appendix A, steps 3-9):
+//
+//   k_particle_solve  F0, T0 over the boundary links (eqs. F0, T0; FP64,
+//                     wave shuffles + LDS), lab inertia and its rate
+//                     (eqs. Irot, Irotdiff), implicit 6x6 solve (eqs.
+//                     Fdiscrete, Tdiscrete), link bounce-back with the
+//                     moving-boundary term (eqs. fb, ub, ubsquirmer), then
+//                     position and quaternion update (eqs. posupdate,
+//                     qnplus0, qnplus1).
+//   k_particle_remap  FP64 inside test of eq. ellipsoidsurface over the
+//                     particle's window, covered/uncovered node book-keeping,
+//                     boundary-link list by LDS-staged compaction in a fixed
+//                     (window, direction) order, and the drag matrices of
+//                     eqs. drag1-drag4.
+//
+// Links are packed as site | dir << 27.  All particle quantities are FP64.
+#include "lbell_dev.h"
+#include "lbell_launch.h"
+
+namespace lbd {
+
+__host__ __device__ constexpr unsigned long long pack_dir(int axis) {
+    unsigned long long v = 0;
+    for (int i = 0; i < NQ; ++i)
+        v |= (unsigned long long)((axis == 0 ? cx(i) : (axis == 1 ? cy(i) : cz(i))) + 1) << (2 * i);
+    return v;
+}
+constexpr unsigned long long CXP = pack_dir(0), CYP = pack_dir(1), CZP = pack_dir(2);
+__device__ __forceinline__ int rcx(int b) { return (int)((CXP >> (2 * b)) & 3ull) - 1; }
+__device__ __forceinline__ int rcy(int b) { return (int)((CYP >> (2 * b)) & 3ull) - 1; }
+__device__ __forceinline__ int rcz(int b) { return (int)((CZP >> (2 * b)) & 3ull) - 1; }
+__device__ __forceinline__ int rw36(int b) { return b == 0 ? 12 : (b <= 6 ? 2 : 1); }
+__device__ __forceinline__ int ropp(int b) { return b == 0 ? 0 : ((b & 1) ? b + 1 : b - 1); }
+
+__device__ __forceinline__ double minimg(double d, int n) {
+    if (d >= 0.5 * n) d -= n;
+    else if (d < -0.5 * n) d += n;
+    return d;
+}
+
+// Rotation matrix of q (body -> lab, s_lab = q s_body q^-1).
+__device__ __forceinline__ void rotmat(const double q[4], double R[3][3]) {
+    const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    R[0][0] = 1 - 2 * (q2 * q2 + q3 * q3);
+    R[0][1] = 2 * (q1 * q2 - q0 * q3);
+    R[0][2] = 2 * (q1 * q3 + q0 * q2);
+    R[1][0] = 2 * (q1 * q2 + q0 * q3);
+    R[1][1] = 1 - 2 * (q1 * q1 + q3 * q3);
+    R[1][2] = 2 * (q2 * q3 - q0 * q1);
+    R[2][0] = 2 * (q1 * q3 - q0 * q2);
+    R[2][1] = 2 * (q2 * q3 + q0 * q1);
+    R[2][2] = 1 - 2 * (q1 * q1 + q2 * q2);
+}
+
+// Solid test of eq. ellipsoidsurface.  Body coordinates come from eq.
+// vectrotn with q^-1; the operation order is fixed and contraction is off so
+// the decision is reproducible bit for bit by any IEEE FP64 evaluation of the
+// same expression.
+__device__ __forceinline__ bool inside_test(const double xc[3], const double q[4], const double ia2[3],
+                                            int x, int y, int z, int nx, int ny, int nz) {
+#pragma clang fp contract(off)
+    const double d0 = minimg((double)x - xc[0], nx);
+    const double d1 = minimg((double)y - xc[1], ny);
+    const double d2 = minimg((double)z - xc[2], nz);
+    const double q0 = q[0], p1 = -q[1], p2 = -q[2], p3 = -q[3];
+    const double a0 = (2.0 * q0) * q0 - 1.0;
+    const double ps = (p1 * d0 + p2 * d1) + p3 * d2;
+    const double c0 = p2 * d2 - p3 * d1;
+    const double c1 = p3 * d0 - p1 * d2;
+    const double c2 = p1 * d1 - p2 * d0;
+    const double u = (a0 * d0 + (2.0 * ps) * p1) + (2.0 * q0) * c0;
+    const double v = (a0 * d1 + (2.0 * ps) * p2) + (2.0 * q0) * c1;
+    const double w = (a0 * d2 + (2.0 * ps) * p3) + (2.0 * q0) * c2;
+    const double Q = ((u * u) * ia2[0] + (v * v) * ia2[1]) + (w * w) * ia2[2];
+    return Q < 1.0;
+}
+
+// Spheroidal squirmer slip (eq. squirmer) at lab offset d from the centre;
+// e = body x axis in the lab frame, a = semi-axis along e, b = the other two.
+__device__ __forceinline__ void squirmer_slip(double a, double b, const double e[3], double B1, double B2,
+                                              const double d[3], double us[3]) {
+    const double z = d[0] * e[0] + d[1] * e[1] + d[2] * e[2];
+    const double rv0 = d[0] - z * e[0], rv1 = d[1] - z * e[1], rv2 = d[2] - z * e[2];
+    const double r = sqrt(rv0 * rv0 + rv1 * rv1 + rv2 * rv2);
+    us[0] = us[1] = us[2] = 0.0;
+    if (r == 0.0) return;
+    const double zc = fmin(fmax(z, -a), a);
+    const double eps = sqrt(1.0 - (b * b) / (a * a));
+    const double den = sqrt(a * a - eps * eps * zc * zc);
+    const double sa = -sqrt(a * a - zc * zc) / den;        // s . e
+    const double sr = sqrt(1.0 - eps * eps) * zc / den;   // s . e_perp
+    double zeta;
+    if (eps > 1e-8)
+        zeta = (sqrt(r * r + (z + a * eps) * (z + a * eps)) - sqrt(r * r + (z - a * eps) * (z - a * eps))) /
+               (2.0 * a * eps);
+    else
+        zeta = z / sqrt(r * r + z * z);
+    const double k = -sa * (B1 + B2 * zeta);
+    const double ir = 1.0 / r;
+    us[0] = k * (sa * e[0] + sr * rv0 * ir);
+    us[1] = k * (sa * e[1] + sr * rv1 * ir);
+    us[2] = k * (sa * e[2] + sr * rv2 * ir);
+}
+
+__device__ __forceinline__ double wsum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wsumi(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Deterministic block reduction of N doubles; result valid on thread 0.
+template <int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double (*red)[PBLOCK / 64]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double s = wsum64(v[k]);
+        if (lane == 0) red[k][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s = 0;
+            for (int w = 0; w < PBLOCK / 64; ++w) s += red[k][w];
+            v[k] = s;
+        }
+    }
+}
+
+// Where node (x,y,z) keeps its pre-collision population i in the pull
+// layout, and what the collide kernel adds when it reads it (wall rows).
+__device__ __forceinline__ void pre_slot(const BoxDesc& B, double rho0, int i, int x, int y, int z, int& dir,
+                                         int& slot, double& add) {
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int sy = wrap(y - rcy(i), ny);
+    if (B.walls && rcy(i) != 0 && (sy == 0 || sy == ny - 1)) {
+        const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
+        dir = ropp(i);
+        slot = x + nx * (y + ny * z);
+        add = (rw36(i) / 6.0) * rho0 * (rcx(i) * uw[0] + rcy(i) * uw[1] + rcz(i) * uw[2]);
+    } else {
+        dir = i;
+        slot = wrap(x - rcx(i), nx) + nx * (sy + ny * wrap(z - rcz(i), nz));
+        add = 0.0;
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    __shared__ double red[12][PBLOCK / 64];
+    __shared__ double bc[8];
+    __shared__ double A[6][7];  // the 6x6 system, eliminated by thread 0 (LDS, not private stack)
+    const int p = a.first + (int)blockIdx.x;
+    PartDev* P = a.parts + p;
+    const BoxDesc& B = a.boxes[P->box];
+    T* f = (T*)a.f + B.foff;
+    const long long st = B.stride;
+    const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
+    const double xc[3] = {P->xc[0], P->xc[1], P->xc[2]};
+    const double q[4] = {P->q[0], P->q[1], P->q[2], P->q[3]};
+    const double B1 = P->B1, B2 = P->B2, ax = P->axes[0], bx = P->axes[1];
+    const bool sq = B1 != 0.0 || B2 != 0.0;
+    const int nl = P->nlinks;
+    const uint32_t* L = a.links + P->lbase;
+    const double inv = a.kp.inv_scale, scl = a.kp.scale, rho0 = a.kp.rho0;
+    double Rm[3][3];
+    rotmat(q, Rm);
+    const double e[3] = {Rm[0][0], Rm[1][0], Rm[2][0]};
+
+    // step 3: velocity-independent force and torque (+ slip part)
+    double acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+    for (int l = tid; l < nl; l += PBLOCK) {
+        const uint32_t code = L[l];
+        const int s = (int)(code & SITE_MASK), b = (int)(code >> SITE_BITS);
+        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b);
+        const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
+                             minimg(((double)z + 0.5 * c2) - xc[2], nz)};
+        const double rc0 = r[1] * c2 - r[2] * c1, rc1 = r[2] * c0 - r[0] * c2, rc2 = r[0] * c1 - r[1] * c0;
+        const double fb2 = 2.0 * S::ld64(f + (long long)b * st + s, inv);
+        acc[0] += fb2 * c0;
+        acc[1] += fb2 * c1;
+        acc[2] += fb2 * c2;
+        acc[3] += fb2 * rc0;
+        acc[4] += fb2 * rc1;
+        acc[5] += fb2 * rc2;
+        if (sq) {
+            double us[3];
+            squirmer_slip(ax, bx, e, B1, B2, r, us);
+            const double kuc = (rw36(b) / 6.0) * rho0 * (us[0] * c0 + us[1] * c1 + us[2] * c2);
+            acc[6] -= kuc * c0;
+            acc[7] -= kuc * c1;
+            acc[8] -= kuc * c2;
+            acc[9] -= kuc * rc0;
+            acc[10] -= kuc * rc1;
+            acc[11] -= kuc * rc2;
+        }
+    }
+    block_reduce<12>(acc, red);
+
+    if (tid == 0) {
+        // step 4: I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x with W = Omega(t)
+        const double Ib[3] = {P->Ib[0], P->Ib[1], P->Ib[2]};
+        const double M = P->M;
+        const double U0[3] = {P->U[0], P->U[1], P->U[2]}, W0[3] = {P->W[0], P->W[1], P->W[2]};
+        double Il[3][3], Id[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                Il[i][j] = Rm[i][0] * Ib[0] * Rm[j][0] + Rm[i][1] * Ib[1] * Rm[j][1] + Rm[i][2] * Ib[2] * Rm[j][2];
+        const double Wx[3][3] = {{0, -W0[2], W0[1]}, {W0[2], 0, -W0[0]}, {-W0[1], W0[0], 0}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0;
+                for (int k = 0; k < 3; ++k) s += Wx[i][k] * Il[k][j] - Il[i][k] * Wx[k][j];
+                Id[i][j] = s;
+            }
+        // step 5: [M + zFU, zFW; zTU, I' + dI/dt + zTW] [U'; W'] = [M U + F0 + ...; I' W + T0 + ...]
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) A[i][j] = P->zeta[6 * i + j];
+        for (int i = 0; i < 3; ++i) {
+            A[i][i] += M;
+            for (int j = 0; j < 3; ++j) A[3 + i][3 + j] += Il[i][j] + Id[i][j];
+            A[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P->Fext[i] + P->Pp[i];
+            A[3 + i][6] = (Il[i][0] * W0[0] + Il[i][1] * W0[1] + Il[i][2] * W0[2]) + acc[3 + i] + acc[9 + i] +
+                          P->Text[i] + P->Lp[i];
+        }
+        bool ok = true;
+        for (int k = 0; k < 6; ++k) {  // Gaussian elimination, partial pivoting
+            int pv = k;
+            for (int r = k + 1; r < 6; ++r)
+                if (fabs(A[r][k]) > fabs(A[pv][k])) pv = r;
+            if (!(fabs(A[pv][k]) > 1e-300)) {
+                ok = false;
+                break;
+            }
+            if (pv != k)
+                for (int c = 0; c < 7; ++c) {
+                    const double tmp = A[k][c];
+                    A[k][c] = A[pv][c];
+                    A[pv][c] = tmp;
+                }
+            for (int r = k + 1; r < 6; ++r) {
+                const double m = A[r][k] / A[k][k];
+                for (int c = k; c < 7; ++c) A[r][c] -= m * A[k][c];
+            }
+        }
+        double sol[6] = {0, 0, 0, 0, 0, 0};
+        if (ok)
+            for (int r = 5; r >= 0; --r) {
+                double s = A[r][6];
+                for (int c = r + 1; c < 6; ++c) s -= A[r][c] * sol[c];
+                sol[r] = s / A[r][r];
+            }
+        bool bad = !ok;
+        for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
+        for (int k = 0; k < 3; ++k) bad = bad || fabs(sol[k]) > 0.5;
+        if (bad) {
+            atomicOr(a.flags, (int)F_NONFINITE);
+            for (int k = 0; k < 6; ++k) sol[k] = k < 3 ? U0[k] : W0[k - 3];
+        }
+        // hydrodynamic force and torque over the step (eqs. Fsplit, Tsplit)
+        for (int i = 0; i < 3; ++i) {
+            double zf = 0, zt = 0;
+            for (int j = 0; j < 6; ++j) {
+                zf += P->zeta[6 * i + j] * sol[j];
+                zt += P->zeta[6 * (3 + i) + j] * sol[j];
+            }
+            P->F[i] = acc[i] + acc[6 + i] + P->Pp[i] - zf;
+            P->T[i] = acc[3 + i] + acc[9 + i] + P->Lp[i] - zt;
+            P->Pp[i] = 0.0;
+            P->Lp[i] = 0.0;
+        }
+        for (int k = 0; k < 6; ++k) bc[k] = sol[k];
+        bc[6] = P->wsum > 0.0 ? P->dm / P->wsum : 0.0;
+        // step 7 (its inputs are fixed now; the links below use x_c(t), q(t) from registers)
+        double Wm[3];
+        for (int i = 0; i < 3; ++i) {
+            const int n3 = i == 0 ? nx : (i == 1 ? ny : nz);
+            const double dx = 0.5 * (sol[i] + U0[i]);
+            double xn = xc[i] + dx;
+            if (xn >= n3) xn -= n3;
+            if (xn < 0.0) xn += n3;
+            P->xc[i] = xn;
+            P->xu[i] += dx;
+            P->U[i] = sol[i];
+            P->W[i] = sol[3 + i];
+            Wm[i] = 0.5 * (W0[i] + sol[3 + i]);
+        }
+        const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
+        if (nrm != 0.0) {
+            const double c = cos(0.5 * nrm), sn = sin(0.5 * nrm);
+            const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
+            P->q[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
+            P->q[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
+            P->q[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
+            P->q[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+        }
+        P->dm = 0.0;
+    }
+    __syncthreads();
+
+    // step 6: bounce-back into the solid slot the fluid node pulls next step
+    const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / 36.0;
+    for (int l = tid; l < nl; l += PBLOCK) {
+        const uint32_t code = L[l];
+        const int s = (int)(code & SITE_MASK), b = (int)(code >> SITE_BITS);
+        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b);
+        const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
+                             minimg(((double)z + 0.5 * c2) - xc[2], nz)};
+        double ub[3] = {Un[0] + (Wn[1] * r[2] - Wn[2] * r[1]), Un[1] + (Wn[2] * r[0] - Wn[0] * r[2]),
+                        Un[2] + (Wn[0] * r[1] - Wn[1] * r[0])};
+        if (sq) {
+            double us[3];
+            squirmer_slip(ax, bx, e, B1, B2, r, us);
+            ub[0] += us[0];
+            ub[1] += us[1];
+            ub[2] += us[2];
+        }
+        const int w36 = rw36(b);
+        const double fb = S::ld64(f + (long long)b * st + s, inv);
+        const double val = fb - (w36 / 6.0) * rho0 * (ub[0] * c0 + ub[1] * c1 + ub[2] * c2) + dmw * w36;
+        const int dst = wrap(x + c0, nx) + nx * (wrap(y + c1, ny) + ny * wrap(z + c2, nz));
+        S::st64(f + (long long)ropp(b) * st + dst, val, scl);
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    extern __shared__ uint32_t smem[];
+    uint32_t* bits = smem;
+    uint32_t* stage = smem + a.lds_words;
+    __shared__ double red[22][PBLOCK / 64];
+    __shared__ int wtot[PBLOCK / 64];
+    __shared__ int ired[8][PBLOCK / 64];
+
+    const int p = a.first + (int)blockIdx.x;
+    PartDev* P = a.parts + p;
+    const int bi = P->box;
+    const BoxDesc& B = a.boxes[bi];
+    T* f = (T*)a.f + B.foff;
+    uint16_t* om = a.omap + B.ooff;
+    const long long st = B.stride;
+    const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const uint16_t me = (uint16_t)(p + 1);
+    const int mode = a.mode;
+    const double xc[3] = {P->xc[0], P->xc[1], P->xc[2]};
+    const double q[4] = {P->q[0], P->q[1], P->q[2], P->q[3]};
+    const double ia2[3] = {P->ia2[0], P->ia2[1], P->ia2[2]};
+    const double U[3] = {P->U[0], P->U[1], P->U[2]}, W[3] = {P->W[0], P->W[1], P->W[2]};
+    const double inv = a.kp.inv_scale, scl = a.kp.scale, rho0 = a.kp.rho0;
+
+    // window: axis-aligned bounding box of the ellipsoid plus two nodes
+    double Rm[3][3];
+    rotmat(q, Rm);
+    int lo[3], wn[3];
+    const int n3[3] = {nx, ny, nz};
+    bool whole[3];
+    for (int k = 0; k < 3; ++k) {
+        const double h = sqrt((Rm[k][0] * P->axes[0]) * (Rm[k][0] * P->axes[0]) +
+                              (Rm[k][1] * P->axes[1]) * (Rm[k][1] * P->axes[1]) +
+                              (Rm[k][2] * P->axes[2]) * (Rm[k][2] * P->axes[2]));
+        lo[k] = (int)floor(xc[k] - h) - 2;
+        wn[k] = (int)floor(xc[k] + h) + 2 - lo[k] + 1;
+        whole[k] = wn[k] >= n3[k];
+        if (whole[k]) {
+            lo[k] = 0;
+            wn[k] = n3[k];
+        }
+    }
+    const int nsites = wn[0] * wn[1] * wn[2];
+    if (((nsites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32) > a.lds_words) {
+        if (tid == 0) atomicOr(a.flags, (int)F_WINDOW);
+        return;
+    }
+
+    // pass 1: solid test, node-map update, covered / uncovered nodes
+    double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
+    int nsol = 0;
+    for (int base = 0; base < nsites; base += PBLOCK) {
+        const int i = base + tid;
+        bool in = false;
+        if (i < nsites) {
+            const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
+            const int gx = wrap(lo[0] + wx, nx), gy = wrap(lo[1] + wy, ny), gz = wrap(lo[2] + wz, nz);
+            const int s = gx + nx * (gy + ny * gz);
+            const uint16_t own = om[s];
+            if (mode == 2) {
+                if (own == me) om[s] = 0;
+            } else {
+                in = inside_test(xc, q, ia2, gx, gy, gz, nx, ny, nz);
+                if (in && own != 0 && own != me) {
+                    atomicOr(a.flags, (int)F_OVERLAP);
+                    in = false;
+                }
+                const bool old = own == me;
+                if (in != old) {
+                    if (mode == 0) {
+                        const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
+                                             minimg((double)gz - xc[2], nz)};
+                        if (in) {  // covered: its fluid mass and momentum go to the particle
+                            double m = 0, pm[3] = {0, 0, 0};
+                            for (int j = 0; j < NQ; ++j) {
+                                int dir, slot;
+                                double add;
+                                pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
+                                const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
+                                m += v;
+                                pm[0] += rcx(j) * v;
+                                pm[1] += rcy(j) * v;
+                                pm[2] += rcz(j) * v;
+                            }
+                            tacc[0] += rho0 + m;
+                            tacc[1] += pm[0];
+                            tacc[2] += pm[1];
+                            tacc[3] += pm[2];
+                            tacc[4] += r[1] * pm[2] - r[2] * pm[1];
+                            tacc[5] += r[2] * pm[0] - r[0] * pm[2];
+                            tacc[6] += r[0] * pm[1] - r[1] * pm[0];
+                        } else {  // uncovered: f = f_eq(rho0, U + W x r), paid by the particle
+                            const double u[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]), U[1] + (W[2] * r[0] - W[0] * r[2]),
+                                                 U[2] + (W[0] * r[1] - W[1] * r[0])};
+                            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                            for (int j = 0; j < NQ; ++j) {
+                                int dir, slot;
+                                double add;
+                                pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
+                                const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
+                                const double dev = (rw36(j) / 36.0) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                                S::st64(f + (long long)dir * st + slot, dev - add, scl);
+                            }
+                            tacc[0] -= rho0;
+                            const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
+                            tacc[1] -= pu[0];
+                            tacc[2] -= pu[1];
+                            tacc[3] -= pu[2];
+                            tacc[4] -= r[1] * pu[2] - r[2] * pu[1];
+                            tacc[5] -= r[2] * pu[0] - r[0] * pu[2];
+                            tacc[6] -= r[0] * pu[1] - r[1] * pu[0];
+                        }
+                    }
+                    om[s] = in ? me : (uint16_t)0;
+                }
+                nsol += in ? 1 : 0;
+            }
+        }
+        const unsigned long long m = __ballot(in);
+        if (lane == 0) {
+            const int w0 = (base + wv * 64) >> 5;
+            bits[w0] = (uint32_t)m;
+            bits[w0 + 1] = (uint32_t)(m >> 32);
+        }
+    }
+    __syncthreads();
+
+    if (mode == 2) {
+        if (tid == 0) {
+            atomicAdd(&a.rt[bi].n_solid, -P->n_solid);
+            P->n_solid = 0;
+            P->nlinks = 0;
+        }
+        return;
+    }
+
+    // pass 2: boundary links (fluid x, x + c_b solid here), staged in LDS and
+    // written in (window index, direction) order; drag-matrix sums per link
+    int running = 0;
+    int cnt6[6] = {0, 0, 0, 0, 0, 0}, w36s = 0;
+    double zfw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ztw[6] = {0, 0, 0, 0, 0, 0};
+    const int lcap = P->lcap;
+    uint32_t* L = a.links + P->lbase;
+    for (int base = 0; base < nsites; base += PBLOCK) {
+        const int i = base + tid;
+        uint32_t lm = 0;
+        int s = 0, gx = 0, gy = 0, gz = 0;
+        if (i < nsites && !((bits[i >> 5] >> (i & 31)) & 1u)) {
+            const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
+            gx = wrap(lo[0] + wx, nx);
+            gy = wrap(lo[1] + wy, ny);
+            gz = wrap(lo[2] + wz, nz);
+            s = gx + nx * (gy + ny * gz);
+            if (om[s] == 0) {
+#pragma unroll
+                for (int b = 1; b < NQ; ++b) {
+                    int nwx = wx + cx(b), nwy = wy + cy(b), nwz = wz + cz(b);
+                    if (whole[0]) nwx = wrap(nwx, wn[0]);
+                    else if (nwx < 0 || nwx >= wn[0]) continue;
+                    if (whole[1]) nwy = wrap(nwy, wn[1]);
+                    else if (nwy < 0 || nwy >= wn[1]) continue;
+                    if (whole[2]) nwz = wrap(nwz, wn[2]);
+                    else if (nwz < 0 || nwz >= wn[2]) continue;
+                    const int ni = nwx + wn[0] * (nwy + wn[1] * nwz);
+                    if ((bits[ni >> 5] >> (ni & 31)) & 1u) lm |= 1u << b;
+                }
+            }
+        }
+        const int cnt = __popc(lm);
+        int incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int nb = __shfl_up(incl, o);
+            if (lane >= o) incl += nb;
+        }
+        if (lane == 63) wtot[wv] = incl;
+        __syncthreads();
+        int off = incl - cnt, total = 0;
+        for (int w = 0; w < PBLOCK / 64; ++w) {
+            if (w < wv) off += wtot[w];
+            total += wtot[w];
+        }
+        uint32_t mm = lm;
+        while (mm) {
+            const int b = __ffs(mm) - 1;
+            mm &= mm - 1;
+            stage[off++] = (uint32_t)s | ((uint32_t)b << SITE_BITS);
+            const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b), w36 = rw36(b);
+            const double r0 = minimg(((double)gx + 0.5 * c0) - xc[0], nx);
+            const double r1 = minimg(((double)gy + 0.5 * c1) - xc[1], ny);
+            const double r2 = minimg(((double)gz + 0.5 * c2) - xc[2], nz);
+            const double rc[3] = {r1 * c2 - r2 * c1, r2 * c0 - r0 * c2, r0 * c1 - r1 * c0};
+            const int cc[3] = {c0, c1, c2};
+            cnt6[0] += w36 * c0 * c0;
+            cnt6[1] += w36 * c0 * c1;
+            cnt6[2] += w36 * c0 * c2;
+            cnt6[3] += w36 * c1 * c1;
+            cnt6[4] += w36 * c1 * c2;
+            cnt6[5] += w36 * c2 * c2;
+            w36s += w36;
+            for (int ii = 0; ii < 3; ++ii)
+                for (int jj = 0; jj < 3; ++jj) zfw[3 * ii + jj] += (double)(w36 * cc[ii]) * rc[jj];
+            ztw[0] += w36 * rc[0] * rc[0];
+            ztw[1] += w36 * rc[0] * rc[1];
+            ztw[2] += w36 * rc[0] * rc[2];
+            ztw[3] += w36 * rc[1] * rc[1];
+            ztw[4] += w36 * rc[1] * rc[2];
+            ztw[5] += w36 * rc[2] * rc[2];
+        }
+        __syncthreads();
+        for (int j = tid; j < total; j += PBLOCK) {
+            const int idx = running + j;
+            if (idx < lcap) L[idx] = stage[j];
+        }
+        running += total;
+        __syncthreads();
+    }
+    if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
+
+    double all[22];
+    for (int k = 0; k < 7; ++k) all[k] = tacc[k];
+    for (int k = 0; k < 9; ++k) all[7 + k] = zfw[k];
+    for (int k = 0; k < 6; ++k) all[16 + k] = ztw[k];
+    block_reduce<22>(all, red);
+    int iv[8] = {cnt6[0], cnt6[1], cnt6[2], cnt6[3], cnt6[4], cnt6[5], w36s, nsol};
+    for (int k = 0; k < 8; ++k) {
+        const int s = wsumi(iv[k]);
+        if (lane == 0) ired[k][wv] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int tot[8];
+        for (int k = 0; k < 8; ++k) {
+            tot[k] = 0;
+            for (int w = 0; w < PBLOCK / 64; ++w) tot[k] += ired[k][w];
+        }
+        // zeta_FU = (2 rho0 / c_s^2) sum w c c = rho0 * (integer sum of 36 w c c) / 6
+        const int fu[3][3] = {{tot[0], tot[1], tot[2]}, {tot[1], tot[3], tot[4]}, {tot[2], tot[4], tot[5]}};
+        const double tw[3][3] = {{all[16], all[17], all[18]}, {all[17], all[19], all[20]}, {all[18], all[20], all[21]}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                P->zeta[6 * i + j] = rho0 * fu[i][j] / 6.0;
+                P->zeta[6 * i + 3 + j] = rho0 * all[7 + 3 * i + j] / 6.0;
+                P->zeta[6 * (3 + i) + j] = rho0 * all[7 + 3 * j + i] / 6.0;
+                P->zeta[6 * (3 + i) + 3 + j] = rho0 * tw[i][j] / 6.0;
+            }
+        P->wsum = tot[6] / 36.0;
+        P->nlinks = running < lcap ? running : lcap;
+        if (mode == 0) {
+            P->dm += all[0];
+            for (int k = 0; k < 3; ++k) {
+                P->Pp[k] += all[1 + k];
+                P->Lp[k] += all[4 + k];
+            }
+        }
+        atomicAdd(&a.rt[bi].n_solid, tot[7] - P->n_solid);
+        P->n_solid = tot[7];
+    }
+}
+
+// ------------------------------- launchers ----------------------------------
+
+size_t particle_remap_lds_bytes(int lds_words) { return (size_t)(lds_words + PBLOCK * 18) * sizeof(uint32_t); }
+
+hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    switch (a.kp.storage) {
+        case ST_F64: hipLaunchKernelGGL(k_particle_solve<ST_F64>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        case ST_F32: hipLaunchKernelGGL(k_particle_solve<ST_F32>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        case ST_F16: hipLaunchKernelGGL(k_particle_solve<ST_F16>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_particle_solve<ST_BF16>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t remap_one(const LaunchPart& a, hipStream_t st) {
+    const size_t lds = particle_remap_lds_bytes(a.lds_words);
+    hipLaunchKernelGGL(k_particle_remap<ST>, dim3(a.count), dim3(PBLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_particle_remap(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    switch (a.kp.storage) {
+        case ST_F64: return remap_one<ST_F64>(a, st);
+        case ST_F32: return remap_one<ST_F32>(a, st);
+        case ST_F16: return remap_one<ST_F16>(a, st);
+        default: return remap_one<ST_BF16>(a, st);
+    }
+}
+
+}  // namespace lbd

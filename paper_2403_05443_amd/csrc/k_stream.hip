@@ -1,0 +1,397 @@
+// k_stream.hip - fused collide + stream (pull) over all boxes, plus the
+// per-site initialisation and read-out kernels that see the lattice exactly
+// as the collide kernel does.
+//
+// Storage: structure of arrays per box, f[dir * stride + site], ping-pong
+// buffers.  The value stored at (site, i) after a step is the post-collision
+// population f*_i(site), i.e. the pre-collision population that site + c_i
+// pulls at the next step (Sec. II.A: f_i(x + c_i, t + 1) = f*_i(x, t)).
+// Link bounce-back on particles (Sec. II.B) writes the reflected value into
+// the slot of the solid node that the fluid node pulls from, so this kernel
+// needs no node map.  Moving walls (Sec. III.C set-up) are handled here: a
+// pull from a wall row is replaced by the reflected own population plus the
+// moving-boundary term of eq. fb.
+#include "lbell_dev.h"
+#include "lbell_launch.h"
+
+namespace lbd {
+
+template <int ST>
+struct Pull {
+    using S = Store<ST>;
+    using T = typename S::T;
+    using R = typename S::R;
+
+    // Pre-collision populations of fluid site (x,y,z) as deviations.
+    static __device__ __forceinline__ void pull(const BoxDesc& B, const T* __restrict__ fi, int s,
+                                                int x, int y, int z, R inv_scale, R rho0,
+                                                bool walls, R (&f)[NQ]) {
+        const int nx = B.nx, ny = B.ny, nz = B.nz;
+        const long long st = B.stride;
+        const int xs0 = x == nx - 1 ? 0 : x + 1, xs2 = x == 0 ? nx - 1 : x - 1;
+        const int ys0 = y == ny - 1 ? 0 : y + 1, ys2 = y == 0 ? ny - 1 : y - 1;
+        const int zs0 = z == nz - 1 ? 0 : z + 1, zs2 = z == 0 ? nz - 1 : z - 1;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            // source node x - c_i
+            const int sx = cx(i) == 1 ? xs2 : (cx(i) == -1 ? xs0 : x);
+            const int sy = cy(i) == 1 ? ys2 : (cy(i) == -1 ? ys0 : y);
+            const int sz = cz(i) == 1 ? zs2 : (cz(i) == -1 ? zs0 : z);
+            if (walls && cy(i) != 0 && (sy == 0 || sy == ny - 1)) {
+                const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
+                const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
+                f[i] = S::ld(fi + (long long)opp(i) * st + s, inv_scale) +
+                       (R)(6.0 * wgt(i)) * rho0 * cu;
+            } else {
+                const int src = sx + nx * (sy + ny * sz);
+                f[i] = S::ld(fi + (long long)i * st + src, inv_scale);
+            }
+        }
+    }
+};
+
+// Collision on deviations d_i = f_i - w_i rho0 (algebraically identical to
+// the full-population forms of Sec. II.A).
+template <typename R, int COLL>
+__device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf, R g0, R g1, R g2) {
+    R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        drho += f[i];
+        if (cx(i)) jx += cx(i) * f[i];
+        if (cy(i)) jy += cy(i) * f[i];
+        if (cz(i)) jz += cz(i) * f[i];
+    }
+    const R rho = rho0 + drho;
+    const R ir = R(1) / rho;
+    const R ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    if (COLL == 0) {  // BGK
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
+            const R feq = R(wgt(i)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - usq));
+            f[i] = f[i] - om * (f[i] - feq);
+        }
+    } else if (COLL == 1) {  // TRT
+        {
+            const R feq = R(wgt(0)) * (drho - rho * usq);
+            f[0] = f[0] - om * (f[0] - feq);
+        }
+#pragma unroll
+        for (int i = 1; i < NQ; i += 2) {
+            const int o = i + 1;
+            const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
+            const R ep = R(wgt(i)) * (drho + rho * (R(4.5) * cu * cu - usq));
+            const R em = R(wgt(i)) * rho * R(3) * cu;
+            const R fp = R(0.5) * (f[i] + f[o]), fm = R(0.5) * (f[i] - f[o]);
+            const R a = om * (fp - ep), b = omm * (fm - em);
+            f[i] = f[i] - a - b;
+            f[o] = f[o] - a + b;
+        }
+    } else {  // hydrodynamic modes relaxed with tau, ghost modes to equilibrium
+        R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+        for (int i = 1; i < NQ; ++i) {
+            if (cx(i)) pxx += f[i];
+            if (cy(i)) pyy += f[i];
+            if (cz(i)) pzz += f[i];
+            if (cx(i) && cy(i)) pxy += R(cx(i) * cy(i)) * f[i];
+            if (cx(i) && cz(i)) pxz += R(cx(i) * cz(i)) * f[i];
+            if (cy(i) && cz(i)) pyz += R(cy(i) * cz(i)) * f[i];
+        }
+        // X = rho u u + (1 - 1/tau) (sum d c c - drho/3 I - rho u u)
+        const R k1 = R(1) - om, d3 = drho * R(1.0 / 3.0);
+        const R xxx = rho * ux * ux + k1 * (pxx - d3 - rho * ux * ux);
+        const R xyy = rho * uy * uy + k1 * (pyy - d3 - rho * uy * uy);
+        const R xzz = rho * uz * uz + k1 * (pzz - d3 - rho * uz * uz);
+        const R xxy = rho * ux * uy + k1 * (pxy - rho * ux * uy);
+        const R xxz = rho * ux * uz + k1 * (pxz - rho * ux * uz);
+        const R xyz = rho * uy * uz + k1 * (pyz - rho * uy * uz);
+        const R tr3 = (xxx + xyy + xzz) * R(1.0 / 3.0);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
+            R cxc = 0;
+            if (cx(i)) cxc += xxx;
+            if (cy(i)) cxc += xyy;
+            if (cz(i)) cxc += xzz;
+            if (cx(i) && cy(i)) cxc += R(2 * cx(i) * cy(i)) * xxy;
+            if (cx(i) && cz(i)) cxc += R(2 * cx(i) * cz(i)) * xxz;
+            if (cy(i) && cz(i)) cxc += R(2 * cy(i) * cz(i)) * xyz;
+            f[i] = R(wgt(i)) * (drho + R(3) * rho * cu + R(4.5) * (cxc - tr3));
+        }
+    }
+    if (cf) {  // uniform counter-force, w_i (c_i . g) / c_s^2
+#pragma unroll
+        for (int i = 1; i < NQ; ++i)
+            f[i] += R(3.0 * wgt(i)) * rho0 * (R(cx(i)) * g0 + R(cy(i)) * g1 + R(cz(i)) * g2);
+    }
+}
+
+template <int ST, int COLL, bool WALLS>
+__global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restrict__ boxes,
+                                                         const BoxRT* __restrict__ rt,
+                                                         const int* __restrict__ tile_box,
+                                                         const typename Store<ST>::T* __restrict__ fin,
+                                                         typename Store<ST>::T* __restrict__ fout,
+                                                         KParams kp) {
+    using S = Store<ST>;
+    using R = typename S::R;
+    const int tile = blockIdx.x;
+    const int bi = tile_box[tile];
+    const BoxDesc& B = boxes[bi];
+    const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
+    if (s >= B.n) return;
+    const int nx = B.nx, ny = B.ny;
+    const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+    const bool walls = WALLS && B.walls;
+    if (walls && (y == 0 || y == ny - 1)) return;
+    const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
+    R f[NQ];
+    Pull<ST>::pull(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
+    R g0 = 0, g1 = 0, g2 = 0;
+    const bool cf = B.counterforce != 0;
+    if (cf) {
+        const double nf = (double)(B.n - B.n_wall - rt[bi].n_solid);
+        g0 = (R)(-B.fext[0] / nf);
+        g1 = (R)(-B.fext[1] / nf);
+        g2 = (R)(-B.fext[2] / nf);
+    }
+    collide<R, COLL>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
+    typename S::T* fo = fout + B.foff;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) S::st(fo + (long long)i * B.stride + s, f[i], scl);
+}
+
+// Initial state: every slot holds the pre-collision population its reader
+// pulls at the first step, f_eq(rho0, u0) plus the first-order
+// non-equilibrium part of the Couette profile (zero at rest).
+template <int ST>
+__global__ __launch_bounds__(TILE) void k_init(const BoxDesc* __restrict__ boxes,
+                                               const int* __restrict__ tile_box,
+                                               typename Store<ST>::T* __restrict__ f0,
+                                               typename Store<ST>::T* __restrict__ f1,
+                                               const int* __restrict__ box_init, KParams kp) {
+    using S = Store<ST>;
+    const int tile = blockIdx.x;
+    const int bi = tile_box[tile];
+    const BoxDesc& B = boxes[bi];
+    const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
+    if (s >= B.n) return;
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+    const bool couette = box_init[bi] == 1 && B.walls;
+    const double H = ny - 2.0;
+    double gr[3] = {0, 0, 0};
+    if (couette)
+        for (int k = 0; k < 3; ++k) gr[k] = (B.wall_hi[k] - B.wall_lo[k]) / H;
+    const double tau = 1.0 / kp.omega, rho0 = kp.rho0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        // reader of slot (s, i) is node s + c_i
+        int yd = y + cy(i);
+        double val = 0.0;
+        const bool wall_here = B.walls && (y == 0 || y == ny - 1);
+        auto dev = [&](int j, int yy) {  // pre-collision deviation of f_j at fluid row yy
+            if (!couette) return 0.0;
+            double u[3];
+            for (int k = 0; k < 3; ++k) u[k] = B.wall_lo[k] + gr[k] * (yy - 0.5);
+            const double cu = cx(j) * u[0] + cy(j) * u[1] + cz(j) * u[2];
+            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            const double qg = cy(j) * (cx(j) * gr[0] + cz(j) * gr[2]);
+            return wgt(j) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) - tau * wgt(j) * rho0 * 3.0 * qg;
+        };
+        if (!wall_here) {
+            if (B.walls && (yd == 0 || yd == ny - 1)) {
+                // slot consumed by bounce-back at s: f_opp(i)(s) = slot + 6 w (u_w . c_opp(i))
+                const int o = opp(i);
+                const double* uw = yd == 0 ? B.wall_lo : B.wall_hi;
+                const double cu = cx(o) * uw[0] + cy(o) * uw[1] + cz(o) * uw[2];
+                val = dev(o, y) - 6.0 * wgt(o) * rho0 * cu;
+            } else {
+                val = dev(i, wrap(yd, ny));
+            }
+        }
+        (void)nz;
+        (void)x;
+        (void)z;
+        S::st64(f0 + B.foff + (long long)i * B.stride + s, val, kp.scale);
+        S::st64(f1 + B.foff + (long long)i * B.stride + s, val, kp.scale);
+    }
+}
+
+// Pre-collision density / velocity of fluid sites of one box, for a chunk of
+// sites [s0, s0 + count): out[4*k] = rho, out[4*k+1..3] = u (zeros elsewhere).
+template <int ST>
+__global__ __launch_bounds__(TILE) void k_fields(const BoxDesc* __restrict__ boxes, int bi,
+                                                 const uint16_t* __restrict__ omap,
+                                                 const typename Store<ST>::T* __restrict__ fin,
+                                                 int s0, int count, double* __restrict__ out,
+                                                 KParams kp) {
+    using R = typename Store<ST>::R;
+    const BoxDesc& B = boxes[bi];
+    const int k = blockIdx.x * TILE + (int)threadIdx.x;
+    if (k >= count) return;
+    const int s = s0 + k;
+    double rho = 0, u[3] = {0, 0, 0};
+    if (omap[B.ooff + s] == 0) {
+        const int nx = B.nx, ny = B.ny;
+        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        R f[NQ];
+        Pull<ST>::pull(B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        double d = 0, j[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            d += (double)f[i];
+            j[0] += cx(i) * (double)f[i];
+            j[1] += cy(i) * (double)f[i];
+            j[2] += cz(i) * (double)f[i];
+        }
+        rho = kp.rho0 + d;
+        for (int c = 0; c < 3; ++c) u[c] = j[c] / rho;
+    }
+    out[4 * k] = rho;
+    out[4 * k + 1] = u[0];
+    out[4 * k + 2] = u[1];
+    out[4 * k + 3] = u[2];
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Per-block sums over fluid sites: [count, sum(d rho), j_x, j_y, j_z, non-finite].
+template <int ST>
+__global__ __launch_bounds__(TILE) void k_moments(const BoxDesc* __restrict__ boxes, int bi,
+                                                  const uint16_t* __restrict__ omap,
+                                                  const typename Store<ST>::T* __restrict__ fin,
+                                                  double* __restrict__ partial, KParams kp) {
+    using R = typename Store<ST>::R;
+    const BoxDesc& B = boxes[bi];
+    const int s = blockIdx.x * TILE + (int)threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (s < B.n && omap[B.ooff + s] == 0) {
+        const int nx = B.nx, ny = B.ny;
+        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        R f[NQ];
+        Pull<ST>::pull(B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        v[0] = 1.0;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const double fi = (double)f[i];
+            if (!isfinite(fi)) v[5] += 1.0;
+            v[1] += fi;
+            v[2] += cx(i) * fi;
+            v[3] += cy(i) * fi;
+            v[4] += cz(i) * fi;
+        }
+    }
+    __shared__ double red[6][TILE / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < 6; ++k) {
+        const double w = wave_sum_d(v[k]);
+        if (lane == 0) red[k][wv] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double a = 0;
+        for (int w = 0; w < TILE / 64; ++w) a += red[threadIdx.x][w];
+        partial[(long long)blockIdx.x * 6 + threadIdx.x] = a;
+    }
+}
+
+template <int ST>
+__global__ void k_poke(const BoxDesc* __restrict__ boxes, int bi, typename Store<ST>::T* __restrict__ f,
+                       int s, int dir, double val, KParams kp) {
+    const BoxDesc& B = boxes[bi];
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+    int slot = wrap(x - cx(dir), nx) + nx * (wrap(y - cy(dir), ny) + ny * wrap(z - cz(dir), nz));
+    Store<ST>::st64(f + B.foff + (long long)dir * B.stride + slot, val, kp.scale);
+}
+
+// ------------------------------- launchers ----------------------------------
+
+template <int ST, int COLL>
+static hipError_t cs_walls(bool walls, const LaunchCS& a, hipStream_t st) {
+    using T = typename Store<ST>::T;
+    dim3 grid(a.ntiles), blk(TILE);
+    if (walls)
+        hipLaunchKernelGGL((k_collide_stream<ST, COLL, true>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
+                           (const T*)a.fin, (T*)a.fout, a.kp);
+    else
+        hipLaunchKernelGGL((k_collide_stream<ST, COLL, false>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
+                           (const T*)a.fin, (T*)a.fout, a.kp);
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t cs_coll(const LaunchCS& a, hipStream_t st) {
+    switch (a.kp.collision) {
+        case 0: return cs_walls<ST, 0>(a.walls, a, st);
+        case 1: return cs_walls<ST, 1>(a.walls, a, st);
+        default: return cs_walls<ST, 2>(a.walls, a, st);
+    }
+}
+
+hipError_t launch_collide_stream(const LaunchCS& a, hipStream_t st) {
+    switch (a.kp.storage) {
+        case ST_F64: return cs_coll<ST_F64>(a, st);
+        case ST_F32: return cs_coll<ST_F32>(a, st);
+        case ST_F16: return cs_coll<ST_F16>(a, st);
+        default: return cs_coll<ST_BF16>(a, st);
+    }
+}
+
+#define LB_DISPATCH_ST(ST_VAR, CALL)                 \
+    switch (ST_VAR) {                                \
+        case ST_F64: { constexpr int SS = ST_F64; CALL; } break; \
+        case ST_F32: { constexpr int SS = ST_F32; CALL; } break; \
+        case ST_F16: { constexpr int SS = ST_F16; CALL; } break; \
+        default: { constexpr int SS = ST_BF16; CALL; } break;    \
+    }
+
+hipError_t launch_init(const BoxDesc* boxes, const int* tile_box, int ntiles, void* f0, void* f1,
+                       const int* box_init, const KParams& kp, hipStream_t st) {
+    LB_DISPATCH_ST(kp.storage, {
+        using T = typename Store<SS>::T;
+        hipLaunchKernelGGL((k_init<SS>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, (T*)f0, (T*)f1,
+                           box_init, kp);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const BoxDesc* boxes, int bi, const uint16_t* omap, const void* fin, int s0,
+                         int count, double* out, const KParams& kp, hipStream_t st) {
+    const int nb = (count + TILE - 1) / TILE;
+    LB_DISPATCH_ST(kp.storage, {
+        using T = typename Store<SS>::T;
+        hipLaunchKernelGGL((k_fields<SS>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin, s0,
+                           count, out, kp);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const BoxDesc* boxes, int bi, int n, const uint16_t* omap, const void* fin,
+                          double* partial, const KParams& kp, hipStream_t st) {
+    const int nb = (n + TILE - 1) / TILE;
+    LB_DISPATCH_ST(kp.storage, {
+        using T = typename Store<SS>::T;
+        hipLaunchKernelGGL((k_moments<SS>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin,
+                           partial, kp);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_poke(const BoxDesc* boxes, int bi, void* f, int s, int dir, double val, const KParams& kp,
+                       hipStream_t st) {
+    LB_DISPATCH_ST(kp.storage, {
+        using T = typename Store<SS>::T;
+        hipLaunchKernelGGL((k_poke<SS>), dim3(1), dim3(1), 0, st, boxes, bi, (T*)f, s, dir, val, kp);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace lbd

@@ -1,0 +1,826 @@
+// lbell_api.hip - the C ABI declared in include/lbell.h: context set-up over a
+// caller-owned device arena, particle management, time stepping (kernel
+// launches only; every step of the method runs in the HIP kernels) and
+// read-back.  Host code only.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbell.h"
+#include "lbell_dev.h"
+#include "lbell_launch.h"
+
+using namespace lbd;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int FIELDS_CHUNK = 1 << 18;  // sites per read-back chunk
+constexpr int MAX_LDS_WORDS = 11008;   // window bitmask budget (with the 18 KB stage, < 64 KB)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
+           flags = 0, scratch = 0, total = 0;
+    std::vector<long long> foff, stride, ooff;
+    std::vector<int> tile0, ntiles;
+    long long pop_elems = 0, omap_elems = 0, link_pool = 0;
+    int total_tiles = 0, max_particles = 0, lds_words = 0;
+    size_t scratch_bytes = 0;
+};
+
+long long link_cap_for(double amax) {
+    // 16 links per unit of the circumscribed sphere's area plus a floor: the
+    // discrete surface carries about 5.5 links per unit area
+    return (long long)(16.0 * 4.0 * M_PI * amax * amax) + 1024;
+}
+
+int lds_words_for(double amax) {
+    const int wn = 2 * (int)std::ceil(amax) + 7;
+    const long long sites = (long long)wn * wn * wn;
+    return (int)(((sites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32));
+}
+
+bool valid_cfg(const lb_config* c, int nboxes, const lb_box* boxes, std::string* why) {
+    auto bad = [&](const char* m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (!c || !boxes || nboxes <= 0) return bad("null config / boxes or nboxes <= 0");
+    if (c->lattice != 19) return bad("only the D3Q19 lattice is implemented");
+    if (c->collision < 0 || c->collision > 2) return bad("unknown collision");
+    if (!(c->tau > 0.5)) return bad("tau must exceed 1/2");
+    if (c->collision == LB_TRT && !(c->magic > 0)) return bad("TRT needs magic > 0");
+    if (c->storage < 0 || c->storage > 3) return bad("unknown storage");
+    if (c->rho0 != 1.0) return bad("rho0 must be 1");
+    if (!(c->max_semi_axis > 0)) return bad("max_semi_axis must be positive");
+    if (lds_words_for(c->max_semi_axis) > MAX_LDS_WORDS) return bad("max_semi_axis too large for the remap window");
+    for (int b = 0; b < nboxes; ++b) {
+        const lb_box& B = boxes[b];
+        if (B.nx < 4 || B.ny < 4 || B.nz < 4) return bad("box edges must be >= 4");
+        const long long n = (long long)B.nx * B.ny * B.nz;
+        if (n > (1ll << SITE_BITS)) return bad("box larger than 2^27 sites");
+        if (B.walls != 0 && B.walls != 1) return bad("walls must be 0 or 1");
+        if (B.walls && (B.wall_lo[1] != 0.0 || B.wall_hi[1] != 0.0)) return bad("walls cannot move along y");
+        if (B.init == 1 && !B.walls) return bad("Couette start needs walls");
+    }
+    return true;
+}
+
+Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
+    Layout L;
+    const int es = storage_bytes(c->storage);
+    long long off = 0, ooff = 0;
+    int tiles = 0;
+    size_t maxpart = 0;
+    for (int b = 0; b < nboxes; ++b) {
+        const long long n = (long long)boxes[b].nx * boxes[b].ny * boxes[b].nz;
+        // direction planes padded so that the 19 streams do not start on the
+        // same memory channel
+        const long long stride = (long long)align_up((size_t)n, 64) + 64;
+        L.foff.push_back(off);
+        L.stride.push_back(stride);
+        off += (long long)align_up((size_t)(NQ * stride), 128);
+        L.ooff.push_back(ooff);
+        ooff += (long long)align_up((size_t)n, 128);
+        const int nt = (int)((n + TILE - 1) / TILE);
+        L.tile0.push_back(tiles);
+        L.ntiles.push_back(nt);
+        tiles += nt;
+        maxpart = std::max(maxpart, (size_t)((n + TILE - 1) / TILE) * 6 * sizeof(double));
+    }
+    L.pop_elems = off;
+    L.omap_elems = ooff;
+    L.total_tiles = tiles;
+    L.max_particles = c->max_particles > 0 ? c->max_particles : nboxes;
+    L.link_pool = (long long)L.max_particles * link_cap_for(c->max_semi_axis);
+    L.lds_words = lds_words_for(c->max_semi_axis);
+    L.scratch_bytes = std::max(maxpart, (size_t)FIELDS_CHUNK * 4 * sizeof(double));
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p = align_up(p + bytes, ALIGN);
+        return at;
+    };
+    L.f0 = take((size_t)off * es);
+    L.f1 = take((size_t)off * es);
+    L.omap = take((size_t)ooff * sizeof(uint16_t));
+    L.boxes = take(sizeof(BoxDesc) * nboxes);
+    L.rt = take(sizeof(BoxRT) * nboxes);
+    L.tile_box = take(sizeof(int) * tiles);
+    L.box_init = take(sizeof(int) * nboxes);
+    L.parts = take(sizeof(PartDev) * L.max_particles);
+    L.links = take(sizeof(uint32_t) * L.link_pool);
+    L.flags = take(sizeof(int) * 4);
+    L.scratch = take(L.scratch_bytes);
+    L.total = p;
+    return L;
+}
+
+struct PartHost {
+    int box;
+    double Fext[3], Text[3];
+    double axes[3];
+};
+
+}  // namespace
+
+struct lb_ctx {
+    lb_config cfg;
+    std::vector<lb_box> boxes;
+    Layout L;
+    hipStream_t stream = nullptr;
+    char* arena = nullptr;
+    std::vector<BoxDesc> hbox;
+    std::vector<PartHost> hpart;
+    int np = 0;
+    long long link_used = 0;
+    int cur = 0;  // buffer holding the current state: 0 -> f0, 1 -> f1
+    long long step = 0;
+    KParams kp{};
+    bool any_walls = false;
+    std::string err;
+
+    template <typename T>
+    T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
+    void* fbuf(int which) { return arena + (which ? L.f1 : L.f0); }
+};
+
+namespace {
+
+lb_status fail(lb_ctx* c, lb_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+lb_status hip_check(lb_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return LB_OK;
+    return fail(c, LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPC(expr)                                              \
+    do {                                                        \
+        lb_status _s = hip_check(ctx, (expr), #expr);           \
+        if (_s != LB_OK) return _s;                             \
+    } while (0)
+
+lb_status flags_status(lb_ctx* ctx) {
+    int fl[4] = {0, 0, 0, 0};
+    HIPC(hipMemcpyAsync(fl, ctx->at<int>(ctx->L.flags), sizeof fl, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    if (fl[0] == 0) return LB_OK;
+    int z[4] = {0, 0, 0, 0};
+    HIPC(hipMemcpyAsync(ctx->at<int>(ctx->L.flags), z, sizeof z, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    if (fl[0] & F_OVERLAP) return fail(ctx, LB_EOVERLAP, "a node was claimed by two particles or a particle and a wall");
+    if (fl[0] & F_NONFINITE) return fail(ctx, LB_ENONFINITE, "singular system, non-finite or |U| > 0.5 particle velocity");
+    if (fl[0] & F_LINKS) return fail(ctx, LB_ENOMEM, "boundary-link capacity exceeded");
+    return fail(ctx, LB_ENOMEM, "remap window exceeds the LDS budget");
+}
+
+LaunchPart part_launch(lb_ctx* ctx, int first, int count, int mode) {
+    LaunchPart a{};
+    a.boxes = ctx->at<BoxDesc>(ctx->L.boxes);
+    a.rt = ctx->at<BoxRT>(ctx->L.rt);
+    a.parts = ctx->at<PartDev>(ctx->L.parts);
+    a.links = ctx->at<uint32_t>(ctx->L.links);
+    a.omap = ctx->at<uint16_t>(ctx->L.omap);
+    a.f = ctx->fbuf(ctx->cur);
+    a.flags = ctx->at<int>(ctx->L.flags);
+    a.first = first;
+    a.count = count;
+    a.kp = ctx->kp;
+    a.lds_words = ctx->L.lds_words;
+    a.mode = mode;
+    return a;
+}
+
+lb_status upload_box(lb_ctx* ctx, int b) {
+    HIPC(hipMemcpyAsync(ctx->at<BoxDesc>(ctx->L.boxes) + b, &ctx->hbox[b], sizeof(BoxDesc), hipMemcpyHostToDevice,
+                        ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+}
+
+template <typename T>
+lb_status write_part_field(lb_ctx* ctx, int id, size_t offset, const T* src, size_t count) {
+    char* dst = reinterpret_cast<char*>(ctx->at<PartDev>(ctx->L.parts) + id) + offset;
+    HIPC(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+}
+
+lb_status read_part(lb_ctx* ctx, int id, PartDev* out) {
+    HIPC(hipMemcpyAsync(out, ctx->at<PartDev>(ctx->L.parts) + id, sizeof(PartDev), hipMemcpyDeviceToHost,
+                        ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+}
+
+void set_mass(PartDev& P, double rho_p) {
+    const double a = P.axes[0], b = P.axes[1], c = P.axes[2];
+    P.M = rho_p * 4.0 / 3.0 * M_PI * a * b * c;
+    P.Ib[0] = P.M * (b * b + c * c) / 5.0;
+    P.Ib[1] = P.M * (a * a + c * c) / 5.0;
+    P.Ib[2] = P.M * (a * a + b * b) / 5.0;
+}
+
+lb_status check_id(lb_ctx* ctx, int id) {
+    if (!ctx) return LB_EINVAL;
+    if (id < 0 || id >= ctx->np) return fail(ctx, LB_EINVAL, "no such particle id");
+    return LB_OK;
+}
+
+lb_status box_fext_update(lb_ctx* ctx, int b) {
+    double s[3] = {0, 0, 0};
+    for (int p = 0; p < ctx->np; ++p)
+        if (ctx->hpart[p].box == b)
+            for (int k = 0; k < 3; ++k) s[k] += ctx->hpart[p].Fext[k];
+    for (int k = 0; k < 3; ++k) ctx->hbox[b].fext[k] = s[k];
+    return upload_box(ctx, b);
+}
+
+lb_status moments(lb_ctx* ctx, int box, double out[6]) {
+    const BoxDesc& B = ctx->hbox[box];
+    const int nb = (B.n + TILE - 1) / TILE;
+    double* partial = ctx->at<double>(ctx->L.scratch);
+    HIPC(launch_moments(ctx->at<BoxDesc>(ctx->L.boxes), box, B.n, ctx->at<uint16_t>(ctx->L.omap), ctx->fbuf(ctx->cur),
+                        partial, ctx->kp, ctx->stream));
+    std::vector<double> h((size_t)nb * 6);
+    HIPC(hipMemcpyAsync(h.data(), partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    // Neumaier summation of the per-block partials, in block order
+    for (int k = 0; k < 6; ++k) {
+        double s = 0, c = 0;
+        for (int b = 0; b < nb; ++b) {
+            const double v = h[(size_t)b * 6 + k], t = s + v;
+            c += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+            s = t;
+        }
+        out[k] = s + c;
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_config_default(lb_config* cfg) {
+    if (!cfg) return LB_EINVAL;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->lattice = 19;
+    cfg->collision = LB_BGK;
+    cfg->tau = 1.0;
+    cfg->magic = 3.0 / 16.0;
+    cfg->storage = LB_FP32;
+    cfg->scale_log2 = 0;
+    cfg->velocity_scale = 1e-3;
+    cfg->rho0 = 1.0;
+    cfg->counterforce = 0;
+    cfg->max_particles = 0;
+    cfg->max_semi_axis = 8.0;
+    return LB_OK;
+}
+
+size_t lb_arena_bytes(const lb_config* cfg, int nboxes, const lb_box* boxes) {
+    if (!valid_cfg(cfg, nboxes, boxes, nullptr)) return 0;
+    return make_layout(cfg, nboxes, boxes).total;
+}
+
+lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* dev_arena, size_t arena_bytes,
+                  void* hip_stream, lb_ctx** out) {
+    if (!out) return LB_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!valid_cfg(cfg, nboxes, boxes, &why)) {
+        std::fprintf(stderr, "lb_init: %s\n", why.c_str());
+        return LB_EINVAL;
+    }
+    if (!dev_arena || ((uintptr_t)dev_arena % ALIGN) != 0) return LB_EINVAL;
+    lb_ctx* ctx = new lb_ctx();
+    ctx->cfg = *cfg;
+    ctx->boxes.assign(boxes, boxes + nboxes);
+    ctx->L = make_layout(cfg, nboxes, boxes);
+    if (arena_bytes < ctx->L.total) {
+        delete ctx;
+        return LB_ENOMEM;
+    }
+    ctx->arena = (char*)dev_arena;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->hpart.resize(ctx->L.max_particles);
+    // relaxation rates and storage scale
+    KParams& kp = ctx->kp;
+    kp.omega = 1.0 / cfg->tau;
+    kp.omega_m = cfg->collision == LB_TRT ? 1.0 / (0.5 + cfg->magic / (cfg->tau - 0.5)) : kp.omega;
+    kp.rho0 = cfg->rho0;
+    kp.collision = cfg->collision;
+    kp.storage = cfg->storage;
+    int e = 0;
+    if (cfg->storage == LB_FP16 || cfg->storage == LB_BF16) {
+        e = cfg->scale_log2;
+        if (e == 0) {
+            const double dmax = (cfg->velocity_scale > 0 ? cfg->velocity_scale : 1e-3) / 6.0;
+            e = (int)std::floor(std::log2(0.25 / dmax));
+        }
+    }
+    kp.scale = std::ldexp(1.0, e);
+    kp.inv_scale = std::ldexp(1.0, -e);
+    // box descriptors and tile table
+    ctx->hbox.resize(nboxes);
+    std::vector<int> tile_box(ctx->L.total_tiles), init(nboxes);
+    for (int b = 0; b < nboxes; ++b) {
+        BoxDesc& D = ctx->hbox[b];
+        std::memset(&D, 0, sizeof D);
+        const lb_box& X = boxes[b];
+        D.nx = X.nx;
+        D.ny = X.ny;
+        D.nz = X.nz;
+        D.n = X.nx * X.ny * X.nz;
+        D.foff = ctx->L.foff[b];
+        D.stride = ctx->L.stride[b];
+        D.ooff = ctx->L.ooff[b];
+        D.walls = X.walls;
+        D.n_wall = X.walls ? 2 * X.nx * X.nz : 0;
+        D.tile0 = ctx->L.tile0[b];
+        D.ntiles = ctx->L.ntiles[b];
+        D.counterforce = cfg->counterforce;
+        for (int k = 0; k < 3; ++k) {
+            D.wall_lo[k] = X.wall_lo[k];
+            D.wall_hi[k] = X.wall_hi[k];
+        }
+        for (int t = 0; t < D.ntiles; ++t) tile_box[D.tile0 + t] = b;
+        init[b] = X.init;
+        ctx->any_walls = ctx->any_walls || X.walls;
+    }
+    // node map: walls 0xFFFF, everything else fluid
+    std::vector<uint16_t> om((size_t)ctx->L.omap_elems, 0);
+    for (int b = 0; b < nboxes; ++b) {
+        const BoxDesc& D = ctx->hbox[b];
+        if (!D.walls) continue;
+        for (int z = 0; z < D.nz; ++z)
+            for (int x = 0; x < D.nx; ++x) {
+                om[D.ooff + x + (size_t)D.nx * (0 + (size_t)D.ny * z)] = 0xFFFF;
+                om[D.ooff + x + (size_t)D.nx * ((D.ny - 1) + (size_t)D.ny * z)] = 0xFFFF;
+            }
+    }
+    std::vector<BoxRT> rt(nboxes);
+    std::memset(rt.data(), 0, sizeof(BoxRT) * nboxes);
+    hipError_t he = hipSuccess;
+    auto H = [&](hipError_t x) {
+        if (he == hipSuccess) he = x;
+    };
+    H(hipMemcpyAsync(ctx->at<BoxDesc>(ctx->L.boxes), ctx->hbox.data(), sizeof(BoxDesc) * nboxes,
+                     hipMemcpyHostToDevice, ctx->stream));
+    H(hipMemcpyAsync(ctx->at<BoxRT>(ctx->L.rt), rt.data(), sizeof(BoxRT) * nboxes, hipMemcpyHostToDevice,
+                     ctx->stream));
+    H(hipMemcpyAsync(ctx->at<int>(ctx->L.tile_box), tile_box.data(), sizeof(int) * tile_box.size(),
+                     hipMemcpyHostToDevice, ctx->stream));
+    H(hipMemcpyAsync(ctx->at<int>(ctx->L.box_init), init.data(), sizeof(int) * nboxes, hipMemcpyHostToDevice,
+                     ctx->stream));
+    H(hipMemcpyAsync(ctx->at<uint16_t>(ctx->L.omap), om.data(), sizeof(uint16_t) * om.size(), hipMemcpyHostToDevice,
+                     ctx->stream));
+    H(hipMemsetAsync(ctx->at<int>(ctx->L.flags), 0, sizeof(int) * 4, ctx->stream));
+    H(launch_init(ctx->at<BoxDesc>(ctx->L.boxes), ctx->at<int>(ctx->L.tile_box), ctx->L.total_tiles, ctx->fbuf(0),
+                  ctx->fbuf(1), ctx->at<int>(ctx->L.box_init), kp, ctx->stream));
+    H(hipStreamSynchronize(ctx->stream));
+    if (he != hipSuccess) {
+        std::fprintf(stderr, "lb_init: %s\n", hipGetErrorString(he));
+        delete ctx;
+        return LB_EDEVICE;
+    }
+    *out = ctx;
+    return LB_OK;
+}
+
+lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const double semi_axes[3],
+                           const double quat[4], int* id) {
+    if (!ctx || !centre || !semi_axes || !quat) return LB_EINVAL;
+    if (box < 0 || box >= (int)ctx->boxes.size()) return fail(ctx, LB_EINVAL, "no such box");
+    if (ctx->np >= ctx->L.max_particles) return fail(ctx, LB_ENOMEM, "particle capacity exhausted");
+    const BoxDesc& B = ctx->hbox[box];
+    const double amax = std::max(semi_axes[0], std::max(semi_axes[1], semi_axes[2]));
+    for (int k = 0; k < 3; ++k)
+        if (!(semi_axes[k] > 0) || !std::isfinite(centre[k])) return fail(ctx, LB_EINVAL, "bad axes or centre");
+    const int dmin = std::min(B.nx, std::min(B.ny, B.nz));
+    if (2 * amax + 2 > dmin) return fail(ctx, LB_EINVAL, "particle does not fit the box");
+    if (amax > ctx->cfg.max_semi_axis) return fail(ctx, LB_EINVAL, "semi-axis above cfg.max_semi_axis");
+    const double nq = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+    if (!(std::fabs(nq - 1.0) <= 1e-6)) return fail(ctx, LB_EINVAL, "quaternion is not unit");
+    const long long cap = link_cap_for(amax);
+    if (ctx->link_used + cap > ctx->L.link_pool) return fail(ctx, LB_ENOMEM, "link pool exhausted");
+    PartDev P;
+    std::memset(&P, 0, sizeof P);
+    const int n3[3] = {B.nx, B.ny, B.nz};
+    for (int k = 0; k < 4; ++k) P.q[k] = quat[k] / nq;
+    for (int k = 0; k < 3; ++k) {
+        double c = centre[k];
+        if (c >= n3[k]) c -= n3[k] * std::floor(c / n3[k]);
+        if (c < 0) c += n3[k] * std::ceil(-c / n3[k]);
+        P.xc[k] = c;
+        P.xu[k] = centre[k];
+        P.axes[k] = semi_axes[k];
+        P.ia2[k] = 1.0 / (semi_axes[k] * semi_axes[k]);
+    }
+    set_mass(P, ctx->cfg.rho0);
+    P.box = box;
+    P.lcap = (int)cap;
+    P.lbase = ctx->link_used;
+    const int pid = ctx->np;
+    HIPC(hipMemcpyAsync(ctx->at<PartDev>(ctx->L.parts) + pid, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(launch_particle_remap(part_launch(ctx, pid, 1, 1), ctx->stream));
+    lb_status s = flags_status(ctx);
+    if (s != LB_OK) {
+        HIPC(launch_particle_remap(part_launch(ctx, pid, 1, 2), ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        return s;
+    }
+    ctx->link_used += cap;
+    PartHost& h = ctx->hpart[pid];
+    std::memset(&h, 0, sizeof h);
+    h.box = box;
+    for (int k = 0; k < 3; ++k) h.axes[k] = semi_axes[k];
+    ctx->np++;
+    if (id) *id = pid;
+    return LB_OK;
+}
+
+lb_status lb_set_external(lb_ctx* ctx, int id, const double F[3], const double T[3]) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    if (!F || !T) return LB_EINVAL;
+    for (int k = 0; k < 3; ++k) {
+        ctx->hpart[id].Fext[k] = F[k];
+        ctx->hpart[id].Text[k] = T[k];
+    }
+    s = write_part_field(ctx, id, offsetof(PartDev, Fext), F, 3);
+    if (s != LB_OK) return s;
+    s = write_part_field(ctx, id, offsetof(PartDev, Text), T, 3);
+    if (s != LB_OK) return s;
+    return box_fext_update(ctx, ctx->hpart[id].box);
+}
+
+lb_status lb_set_squirmer(lb_ctx* ctx, int id, double B1, double B2) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    const double* ax = ctx->hpart[id].axes;
+    if ((B1 != 0 || B2 != 0) && (std::fabs(ax[1] - ax[2]) > 1e-12 * ax[1] || ax[0] < ax[1]))
+        return fail(ctx, LB_EINVAL, "squirmer needs a prolate spheroid, a >= b == c");
+    const double v[2] = {B1, B2};
+    return write_part_field(ctx, id, offsetof(PartDev, B1), v, 2);
+}
+
+lb_status lb_set_velocity(lb_ctx* ctx, int id, const double U[3], const double W[3]) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    if (!U || !W) return LB_EINVAL;
+    s = write_part_field(ctx, id, offsetof(PartDev, U), U, 3);
+    if (s != LB_OK) return s;
+    return write_part_field(ctx, id, offsetof(PartDev, W), W, 3);
+}
+
+lb_status lb_set_particle_density(lb_ctx* ctx, int id, double rho_p) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    if (!(rho_p > 0)) return LB_EINVAL;
+    PartDev P;
+    s = read_part(ctx, id, &P);
+    if (s != LB_OK) return s;
+    set_mass(P, rho_p);
+    s = write_part_field(ctx, id, offsetof(PartDev, M), &P.M, 1);
+    if (s != LB_OK) return s;
+    return write_part_field(ctx, id, offsetof(PartDev, Ib), P.Ib, 3);
+}
+
+namespace {
+lb_status launch_collide(lb_ctx* ctx) {
+    LaunchCS cs{};
+    cs.boxes = ctx->at<BoxDesc>(ctx->L.boxes);
+    cs.rt = ctx->at<BoxRT>(ctx->L.rt);
+    cs.tile_box = ctx->at<int>(ctx->L.tile_box);
+    cs.ntiles = ctx->L.total_tiles;
+    cs.fin = ctx->fbuf(ctx->cur);
+    cs.fout = ctx->fbuf(ctx->cur ^ 1);
+    cs.kp = ctx->kp;
+    cs.walls = ctx->any_walls;
+    HIPC(launch_collide_stream(cs, ctx->stream));
+    ctx->cur ^= 1;
+    return LB_OK;
+}
+
+lb_status launch_particles(lb_ctx* ctx) {
+    if (ctx->np == 0) return LB_OK;
+    const LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
+    HIPC(launch_particle_solve(a, ctx->stream));
+    HIPC(launch_particle_remap(a, ctx->stream));
+    return LB_OK;
+}
+}  // namespace
+
+lb_status lb_step(lb_ctx* ctx, int n) {
+    if (!ctx || n < 0) return LB_EINVAL;
+    for (int k = 0; k < n; ++k) {
+        lb_status s = launch_collide(ctx);
+        if (s == LB_OK) s = launch_particles(ctx);
+        if (s != LB_OK) return s;
+        ctx->step++;
+    }
+    return LB_OK;
+}
+
+lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_particle) {
+    if (!ctx || n < 0) return LB_EINVAL;
+    std::vector<hipEvent_t> ev((size_t)3 * n);
+    for (auto& e : ev) HIPC(hipEventCreate(&e));
+    lb_status s = LB_OK;
+    for (int k = 0; k < n && s == LB_OK; ++k) {
+        HIPC(hipEventRecord(ev[3 * k], ctx->stream));
+        s = launch_collide(ctx);
+        HIPC(hipEventRecord(ev[3 * k + 1], ctx->stream));
+        if (s == LB_OK) s = launch_particles(ctx);
+        HIPC(hipEventRecord(ev[3 * k + 2], ctx->stream));
+        ctx->step++;
+    }
+    HIPC(hipStreamSynchronize(ctx->stream));
+    double c = 0, p = 0;
+    for (int k = 0; k < n; ++k) {
+        float a = 0, b = 0;
+        HIPC(hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]));
+        HIPC(hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]));
+        c += a;
+        p += b;
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    if (ms_collide) *ms_collide = c;
+    if (ms_particle) *ms_particle = p;
+    return s;
+}
+
+lb_status lb_sync(lb_ctx* ctx) {
+    if (!ctx) return LB_EINVAL;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return flags_status(ctx);
+}
+
+lb_status lb_get_force_torque(lb_ctx* ctx, int id, double F[3], double T[3]) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    PartDev P;
+    s = read_part(ctx, id, &P);
+    if (s != LB_OK) return s;
+    for (int k = 0; k < 3; ++k) {
+        if (F) F[k] = P.F[k];
+        if (T) T[k] = P.T[k];
+    }
+    return flags_status(ctx);
+}
+
+lb_status lb_get_particle(lb_ctx* ctx, int id, double x[3], double q[4], double U[3], double W[3]) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    PartDev P;
+    s = read_part(ctx, id, &P);
+    if (s != LB_OK) return s;
+    for (int k = 0; k < 3; ++k) {
+        if (x) x[k] = P.xu[k];
+        if (U) U[k] = P.U[k];
+        if (W) W[k] = P.W[k];
+    }
+    if (q)
+        for (int k = 0; k < 4; ++k) q[k] = P.q[k];
+    return flags_status(ctx);
+}
+
+lb_status lb_get_particle_aux(lb_ctx* ctx, int id, double* M, double* dm, double P3[3], double L3[3], int* nlinks) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    PartDev P;
+    s = read_part(ctx, id, &P);
+    if (s != LB_OK) return s;
+    if (M) *M = P.M;
+    if (dm) *dm = P.dm;
+    for (int k = 0; k < 3; ++k) {
+        if (P3) P3[k] = P.Pp[k];
+        if (L3) L3[k] = P.Lp[k];
+    }
+    if (nlinks) *nlinks = P.nlinks;
+    return LB_OK;
+}
+
+lb_status lb_get_links(lb_ctx* ctx, int id, uint32_t* site, uint8_t* dir, int cap, int* n) {
+    lb_status s = check_id(ctx, id);
+    if (s != LB_OK) return s;
+    PartDev P;
+    s = read_part(ctx, id, &P);
+    if (s != LB_OK) return s;
+    if (n) *n = P.nlinks;
+    if (cap < P.nlinks) return LB_ERANGE;
+    std::vector<uint32_t> codes((size_t)std::max(P.nlinks, 1));
+    if (P.nlinks > 0) {
+        HIPC(hipMemcpyAsync(codes.data(), ctx->at<uint32_t>(ctx->L.links) + P.lbase, sizeof(uint32_t) * P.nlinks,
+                            hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    for (int k = 0; k < P.nlinks; ++k) {
+        if (site) site[k] = codes[k] & SITE_MASK;
+        if (dir) dir[k] = (uint8_t)(codes[k] >> SITE_BITS);
+    }
+    return LB_OK;
+}
+
+lb_status lb_get_mask(lb_ctx* ctx, int box, uint16_t* owner) {
+    if (!ctx || !owner || box < 0 || box >= (int)ctx->boxes.size()) return LB_EINVAL;
+    const BoxDesc& B = ctx->hbox[box];
+    HIPC(hipMemcpyAsync(owner, ctx->at<uint16_t>(ctx->L.omap) + B.ooff, sizeof(uint16_t) * B.n, hipMemcpyDeviceToHost,
+                        ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+}
+
+lb_status lb_get_fields(lb_ctx* ctx, int box, double* rho, double* u) {
+    if (!ctx || box < 0 || box >= (int)ctx->boxes.size()) return LB_EINVAL;
+    const BoxDesc& B = ctx->hbox[box];
+    double* tmp = ctx->at<double>(ctx->L.scratch);
+    std::vector<double> h((size_t)FIELDS_CHUNK * 4);
+    for (int s0 = 0; s0 < B.n; s0 += FIELDS_CHUNK) {
+        const int cnt = std::min(FIELDS_CHUNK, B.n - s0);
+        HIPC(launch_fields(ctx->at<BoxDesc>(ctx->L.boxes), box, ctx->at<uint16_t>(ctx->L.omap), ctx->fbuf(ctx->cur),
+                           s0, cnt, tmp, ctx->kp, ctx->stream));
+        HIPC(hipMemcpyAsync(h.data(), tmp, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k < cnt; ++k) {
+            if (rho) rho[s0 + k] = h[4 * (size_t)k];
+            if (u)
+                for (int c = 0; c < 3; ++c) u[3 * (size_t)(s0 + k) + c] = h[4 * (size_t)k + 1 + c];
+        }
+    }
+    return LB_OK;
+}
+
+lb_status lb_get_mass(lb_ctx* ctx, int box, double* mass) {
+    if (!ctx || !mass || box < 0 || box >= (int)ctx->boxes.size()) return LB_EINVAL;
+    double m[6];
+    lb_status s = moments(ctx, box, m);
+    if (s != LB_OK) return s;
+    double tot = m[0] * ctx->cfg.rho0 + m[1];
+    for (int p = 0; p < ctx->np; ++p)
+        if (ctx->hpart[p].box == box) {
+            double dm = 0;
+            s = lb_get_particle_aux(ctx, p, nullptr, &dm, nullptr, nullptr, nullptr);
+            if (s != LB_OK) return s;
+            tot += dm;
+        }
+    *mass = tot;
+    return LB_OK;
+}
+
+lb_status lb_get_momentum(lb_ctx* ctx, int box, double P[3]) {
+    if (!ctx || !P || box < 0 || box >= (int)ctx->boxes.size()) return LB_EINVAL;
+    double m[6];
+    lb_status s = moments(ctx, box, m);
+    if (s != LB_OK) return s;
+    for (int k = 0; k < 3; ++k) P[k] = m[2 + k];
+    return LB_OK;
+}
+
+lb_status lb_check_finite(lb_ctx* ctx, int box, long long* count) {
+    if (!ctx || !count || box < 0 || box >= (int)ctx->boxes.size()) return LB_EINVAL;
+    double m[6];
+    lb_status s = moments(ctx, box, m);
+    if (s != LB_OK) return s;
+    *count = (long long)m[5];
+    return LB_OK;
+}
+
+lb_status lb_get_step(lb_ctx* ctx, long long* step) {
+    if (!ctx || !step) return LB_EINVAL;
+    *step = ctx->step;
+    return LB_OK;
+}
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int version, nboxes, storage, np, cur, pad;
+    long long step, pop_elems, omap_elems, link_used;
+    size_t part_bytes;
+};
+}  // namespace
+
+lb_status lb_save(lb_ctx* ctx, const char* path) {
+    if (!ctx || !path) return LB_EINVAL;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(ctx, LB_EIO, "cannot open checkpoint for writing");
+    CkptHeader h{};
+    std::memcpy(h.magic, "LBELLCK1", 8);
+    h.version = 1;
+    h.nboxes = (int)ctx->boxes.size();
+    h.storage = ctx->cfg.storage;
+    h.np = ctx->np;
+    h.cur = ctx->cur;
+    h.step = ctx->step;
+    h.pop_elems = ctx->L.pop_elems;
+    h.omap_elems = ctx->L.omap_elems;
+    h.link_used = ctx->link_used;
+    h.part_bytes = sizeof(PartDev);
+    const size_t es = storage_bytes(ctx->cfg.storage);
+    std::vector<char> buf;
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
+    auto dump = [&](const void* dptr, size_t bytes) {
+        if (!ok) return;
+        buf.resize(std::max(bytes, (size_t)1));
+        if (hipMemcpy(buf.data(), dptr, bytes, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        if (ok && bytes && std::fwrite(buf.data(), 1, bytes, fp) != bytes) ok = false;
+    };
+    dump(ctx->fbuf(ctx->cur), (size_t)ctx->L.pop_elems * es);
+    dump(ctx->at<char>(ctx->L.omap), (size_t)ctx->L.omap_elems * sizeof(uint16_t));
+    dump(ctx->at<char>(ctx->L.rt), sizeof(BoxRT) * ctx->boxes.size());
+    dump(ctx->at<char>(ctx->L.parts), sizeof(PartDev) * ctx->np);
+    dump(ctx->at<char>(ctx->L.links), sizeof(uint32_t) * ctx->link_used);
+    if (ok) ok = std::fwrite(ctx->hpart.data(), sizeof(PartHost), ctx->np, fp) == (size_t)ctx->np;
+    if (std::fclose(fp) != 0) ok = false;
+    return ok ? LB_OK : fail(ctx, LB_EIO, "checkpoint write failed");
+}
+
+lb_status lb_load(lb_ctx* ctx, const char* path) {
+    if (!ctx || !path) return LB_EINVAL;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(ctx, LB_EIO, "cannot open checkpoint");
+    CkptHeader h{};
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1;
+    if (!ok || std::memcmp(h.magic, "LBELLCK1", 8) != 0) {
+        std::fclose(fp);
+        return fail(ctx, LB_EIO, "not a checkpoint");
+    }
+    if (h.nboxes != (int)ctx->boxes.size() || h.storage != ctx->cfg.storage || h.pop_elems != ctx->L.pop_elems ||
+        h.omap_elems != ctx->L.omap_elems || h.np > ctx->L.max_particles || h.link_used > ctx->L.link_pool ||
+        h.part_bytes != sizeof(PartDev)) {
+        std::fclose(fp);
+        return fail(ctx, LB_EINVAL, "checkpoint does not match this context");
+    }
+    HIPC(hipStreamSynchronize(ctx->stream));
+    const size_t es = storage_bytes(ctx->cfg.storage);
+    std::vector<char> buf;
+    auto load = [&](void* dptr, size_t bytes) {
+        if (!ok) return;
+        buf.resize(std::max(bytes, (size_t)1));
+        if (bytes && std::fread(buf.data(), 1, bytes, fp) != bytes) ok = false;
+        if (ok && hipMemcpy(dptr, buf.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    };
+    ctx->cur = h.cur;
+    load(ctx->fbuf(ctx->cur), (size_t)h.pop_elems * es);
+    load(ctx->at<char>(ctx->L.omap), (size_t)h.omap_elems * sizeof(uint16_t));
+    load(ctx->at<char>(ctx->L.rt), sizeof(BoxRT) * ctx->boxes.size());
+    load(ctx->at<char>(ctx->L.parts), sizeof(PartDev) * h.np);
+    load(ctx->at<char>(ctx->L.links), sizeof(uint32_t) * h.link_used);
+    if (ok) ok = std::fread(ctx->hpart.data(), sizeof(PartHost), h.np, fp) == (size_t)h.np;
+    std::fclose(fp);
+    if (!ok) return fail(ctx, LB_EIO, "checkpoint read failed");
+    ctx->np = h.np;
+    ctx->step = h.step;
+    ctx->link_used = h.link_used;
+    for (int b = 0; b < (int)ctx->boxes.size(); ++b) {
+        lb_status s = box_fext_update(ctx, b);
+        if (s != LB_OK) return s;
+    }
+    return LB_OK;
+}
+
+lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value) {
+    if (!ctx || box < 0 || box >= (int)ctx->boxes.size() || dir < 0 || dir >= NQ) return LB_EINVAL;
+    if (site < 0 || site >= ctx->hbox[box].n) return LB_EINVAL;
+    HIPC(launch_poke(ctx->at<BoxDesc>(ctx->L.boxes), box, ctx->fbuf(ctx->cur), site, dir, value, ctx->kp,
+                     ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+}
+
+lb_status lb_destroy(lb_ctx* ctx) {
+    if (!ctx) return LB_EINVAL;
+    hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return LB_OK;
+}
+
+const char* lb_status_str(lb_status s) {
+    switch (s) {
+        case LB_OK: return "ok";
+        case LB_EINVAL: return "invalid argument";
+        case LB_ENOMEM: return "capacity exhausted";
+        case LB_EDEVICE: return "HIP runtime error";
+        case LB_ESTATE: return "invalid state";
+        case LB_EOVERLAP: return "particle overlap";
+        case LB_ENONFINITE: return "non-finite or singular particle update";
+        case LB_ERANGE: return "buffer too small";
+        case LB_EIO: return "checkpoint I/O error";
+        default: return "unknown status";
+    }
+}
+
+const char* lb_last_error(lb_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"

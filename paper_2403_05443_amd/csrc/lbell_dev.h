@@ -1,0 +1,134 @@
+// lbell_dev.h - device-side data structures and lattice constants of the HIP
+// library (internal; not part of the C ABI).  Written for gfx950 (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbd {
+
+constexpr int NQ = 19;
+constexpr int TILE = 256;        // sites per K1 work-group
+constexpr int PBLOCK = 256;      // threads per particle work-group
+constexpr int SITE_BITS = 27;    // link code: site | dir << 27
+constexpr uint32_t SITE_MASK = (1u << SITE_BITS) - 1u;
+
+// D3Q19, order fixed by the ABI: rest, 6 axis, 12 diagonal; opposite of odd i is i+1.
+__host__ __device__ constexpr int cx(int i) {
+    return i == 1 || i == 7 || i == 9 || i == 11 || i == 13 ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int i) {
+    return i == 3 || i == 7 || i == 10 || i == 15 || i == 17 ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 ? -1 : 0);
+}
+__host__ __device__ constexpr int cz(int i) {
+    return i == 5 || i == 11 || i == 14 || i == 15 || i == 18 ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// 36 * w_i as an integer (12, 2, 1): link weights in exact integer form
+__host__ __device__ constexpr int w36(int i) { return i == 0 ? 12 : (i <= 6 ? 2 : 1); }
+
+enum Flags : int {
+    F_OVERLAP = 1,      // a node claimed by two particles or a particle and a wall
+    F_NONFINITE = 2,    // singular 6x6 or non-finite / too fast particle
+    F_LINKS = 4,        // link capacity exceeded
+    F_WINDOW = 8,       // remap window larger than the LDS budget
+};
+
+struct BoxDesc {
+    int nx, ny, nz, n;
+    long long foff;       // element offset of the box's population block
+    long long stride;     // elements between direction planes
+    long long ooff;       // element offset of the box's node map
+    int walls, n_wall;
+    int tile0, ntiles;
+    int counterforce, pad0;
+    double wall_lo[3], wall_hi[3];
+    double fext[3];       // sum of external forces on this machine's particles
+};
+
+struct BoxRT {            // mutated by kernels
+    int n_solid;
+    int pad[3];
+};
+
+struct PartDev {
+    double xc[3];         // centre, wrapped into the box
+    double xu[3];         // centre, unwrapped
+    double q[4];          // orientation (scalar first, body -> lab)
+    double U[3], W[3];    // velocity, angular velocity (lab)
+    double axes[3];       // semi-axes a, b, c along body x, y, z
+    double ia2[3];        // 1 / axis^2, computed on the host
+    double M, Ib[3];      // mass and body inertia
+    double Fext[3], Text[3];
+    double B1, B2;        // squirmer modes
+    double zeta[36];      // [F;T] x [U;W] drag matrix of the current links
+    double dm, Pp[3], Lp[3];  // pending mass / momentum / angular momentum of transitions
+    double F[3], T[3];    // hydrodynamic force and torque of the last step
+    double wsum;          // sum of w_b over the current links
+    int box, nlinks, lcap, n_solid;
+    long long lbase;      // offset of this particle's links in the pool
+};
+
+struct KParams {
+    double omega, omega_m;    // 1/tau (TRT: 1/tau+), TRT 1/tau-
+    double scale, inv_scale;  // half formats: stored = scale * deviation
+    double rho0;
+    int collision, storage;
+};
+
+__host__ __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+}  // namespace lbd
+
+namespace lbd {
+
+// Population storage formats (values of lb_config.storage).
+constexpr int ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3;
+
+// Stored value <-> deviation f_i - w_i rho0 in the collision precision R.
+template <int ST> struct Store;
+template <> struct Store<ST_F64> {
+    using T = double;
+    using R = double;
+    static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
+    static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+    static __device__ __forceinline__ double ld64(const T* p, double) { return *p; }
+    static __device__ __forceinline__ void st64(T* p, double v, double) { *p = v; }
+};
+template <> struct Store<ST_F32> {
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
+    static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+    static __device__ __forceinline__ double ld64(const T* p, double) { return (double)*p; }
+    static __device__ __forceinline__ void st64(T* p, double v, double) { *p = (float)v; }
+};
+template <> struct Store<ST_F16> {
+    using T = _Float16;
+    using R = float;
+    static __device__ __forceinline__ R ld(const T* p, R inv) { return (float)*p * inv; }
+    static __device__ __forceinline__ void st(T* p, R v, R s) { *p = (_Float16)(v * s); }
+    static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)(float)*p * inv; }
+    static __device__ __forceinline__ void st64(T* p, double v, double s) { *p = (_Float16)(float)(v * s); }
+};
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+template <> struct Store<ST_BF16> {
+    using T = uint16_t;
+    using R = float;
+    static __device__ __forceinline__ R ld(const T* p, R inv) { return bf16_to_f32(*p) * inv; }
+    static __device__ __forceinline__ void st(T* p, R v, R s) { *p = f32_to_bf16(v * s); }
+    static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)bf16_to_f32(*p) * inv; }
+    static __device__ __forceinline__ void st64(T* p, double v, double s) { *p = f32_to_bf16((float)(v * s)); }
+};
+
+__host__ __device__ inline int storage_bytes(int st) { return st == ST_F64 ? 8 : (st == ST_F32 ? 4 : 2); }
+
+}  // namespace lbd

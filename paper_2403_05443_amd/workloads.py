@@ -1,0 +1,138 @@
+"""Seeded synthetic workloads shaped like the paper's set-ups.
+
+This module only draws numbers and states parameters (box sizes, particle
+poses, loads); it holds none of the method's arithmetic, so both the oracle
+tests and the GPU library can take their inputs from it.  All randomness
+comes from one SplitMix64 stream (Steele, Lea & Flood 2014) per workload,
+seed = 2403054430 + workload index.
+"""
+import math
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+SEED0 = 2403054430
+MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 generator with its published constants."""
+
+    def __init__(self, seed):
+        self.s = seed & MASK64
+
+    def next_u64(self):
+        self.s = (self.s + 0x9E3779B97F4A7C15) & MASK64
+        z = self.s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self, lo=0.0, hi=1.0):
+        return lo + (hi - lo) * ((self.next_u64() >> 11) * (1.0 / (1 << 53)))
+
+    def normal(self):
+        u1 = max(self.uniform(), 1e-300)
+        u2 = self.uniform()
+        return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+    def unit_quaternion(self):
+        """Uniform on S^3: normalised 4-D Gaussian."""
+        while True:
+            q = [self.normal() for _ in range(4)]
+            n = math.sqrt(sum(v * v for v in q))
+            if n > 1e-12:
+                return tuple(v / n for v in q)
+
+    def unit_vector(self):
+        while True:
+            v = [self.normal() for _ in range(3)]
+            n = math.sqrt(sum(x * x for x in v))
+            if n > 1e-12:
+                return tuple(x / n for x in v)
+
+
+@dataclass
+class Particle:
+    centre: Tuple[float, float, float]
+    axes: Tuple[float, float, float]
+    quat: Tuple[float, float, float, float]
+    force: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    torque: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    squirmer: Tuple[float, float] = (0.0, 0.0)
+    box: int = 0
+
+
+@dataclass
+class Box:
+    shape: Tuple[int, int, int]
+    walls: bool = False
+    wall_lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    wall_hi: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    init: str = "rest"
+
+
+@dataclass
+class Workload:
+    name: str
+    boxes: List[Box]
+    particles: List[Particle]
+    collision: str
+    tau: float
+    storage: str
+    steps: int
+    magic: float = 3.0 / 16.0
+    counterforce: bool = False
+    velocity_scale: float = 1e-3
+    max_semi_axis: float = 8.0
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def sites(self):
+        return sum(b.shape[0] * b.shape[1] * b.shape[2] for b in self.boxes)
+
+
+def quat_axis_angle(axis, angle):
+    n = math.sqrt(sum(a * a for a in axis))
+    s = math.sin(0.5 * angle) / n
+    return (math.cos(0.5 * angle), axis[0] * s, axis[1] * s, axis[2] * s)
+
+
+def c1(storage="fp64"):
+    """32^3 periodic, BGK tau=1, a=4 b=c=2 along x, centred, F = 1e-4 x, 500 steps."""
+    return Workload("c1_settling_32", [Box((32, 32, 32))],
+                    [Particle((15.5, 15.5, 15.5), (4.0, 2.0, 2.0), (1.0, 0.0, 0.0, 0.0), force=(1e-4, 0, 0))],
+                    "bgk", 1.0, storage, 500, counterforce=True, velocity_scale=2e-5)
+
+
+def c1r(storage="fp64"):
+    """c1 with a seeded random orientation and a torque (non-zero rotation)."""
+    g = SplitMix64(SEED0 + 0)
+    q = g.unit_quaternion()
+    return Workload("c1r_settling_32_random", [Box((32, 32, 32))],
+                    [Particle((15.5, 15.5, 15.5), (4.0, 2.0, 2.0), q, force=(1e-4, 0, 0),
+                              torque=(0.0, 0.0, 1e-3))],
+                    "bgk", 1.0, storage, 500, counterforce=True, velocity_scale=2e-5)
+
+
+def c2(storage="fp32", L=128):
+    """L^3 periodic (128 by default), TRT Lambda=3/16 with tau+ = 0.8
+    (nu = 0.1), spheroid a=6, b=c=2, long axis at 45 deg to a force 5e-4
+    along z, 20 000 steps."""
+    # body x -> (sin 45, 0, cos 45): rotation about y by +45 deg maps x -> (cos, 0, -sin)
+    q = quat_axis_angle((0.0, 1.0, 0.0), -math.pi / 4)
+    c = (L - 1) / 2.0
+    return Workload(f"c2_inclined_{L}", [Box((L, L, L))],
+                    [Particle((c, c, c), (6.0, 2.0, 2.0), q, force=(0.0, 0.0, 5e-4))],
+                    "trt", 0.8, storage, 20000, counterforce=True, velocity_scale=1e-4)
+
+
+def c3(r=3, seed_index=1, storage="fp32"):
+    """64 x 128 x 64 between walls y=0 and y=127 moving at -/+0.01 along x,
+    BGK tau=0.8, neutrally buoyant spheroid b=c=3, a=3r, seeded orientation."""
+    g = SplitMix64(SEED0 + 2 + 1000 * seed_index + r)
+    q = g.unit_quaternion()
+    return Workload(f"c3_jeffery_r{r}_s{seed_index}",
+                    [Box((64, 128, 64), walls=True, wall_lo=(-0.01, 0, 0), wall_hi=(0.01, 0, 0), init="couette")],
+                    [Particle((31.5, 63.5, 31.5), (3.0 * r, 3.0, 3.0), q)],
+                    "bgk", 0.8, storage, 0, velocity_scale=0.01, max_semi_axis=12.0,
+                    notes={"shear_rate": 0.02 / 126.0})
