@@ -81,6 +81,53 @@ def cpu_baseline(W, seconds):
                       f"({dt:.1f} s)"}
 
 
+def _pmc_rows(d):
+    """(kernel name, counter value) of every dispatch in a rocprofv3 --pmc csv tree."""
+    import csv
+    import glob
+    out = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes):
+    """HBM bytes per collide-stream launch from FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled by what the same counter reads for the copy
+    probe of known size."""
+    from paper_2403_05443_amd import workloads
+    W = workloads.c2(storage, size)
+    res = {}
+    for name, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _pmc_rows(d)
+        probe = [v for k, v in rows if "k_copy_probe" in k]
+        k1 = [v for k, v in rows if "collide_stream" in k]
+        if not probe or not k1:
+            raise SystemExit(f"no copy-probe / collide-stream dispatches under {d}")
+        probe_kib = sorted(probe)[len(probe) // 2]
+        scale = probe_bytes / (probe_kib * 1024.0)
+        res[name] = {"counter_kib_per_launch": sum(k1) / len(k1), "probe_kib": probe_kib, "scale": scale,
+                     "bytes_per_launch": sum(k1) / len(k1) * 1024.0 * scale}
+    src_sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("source_sha256") != src_sha:
+            rec = {}
+    except (OSError, ValueError):
+        rec = {}
+    rec["source_sha256"] = src_sha
+    rec["kernel"] = "k_collide_stream / k_collide_stream_rows"
+    rec.setdefault("entries", {})[f"{W.name}/{storage}"] = {
+        "fetch": res["fetch"], "write": res["write"],
+        "algorithmic_bytes_per_launch": 38 * BYTES[storage] * W.sites,
+        "traffic_bytes_per_launch": round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]),
+    }
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(rec["entries"][f"{W.name}/{storage}"]))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +137,15 @@ def main():
     ap.add_argument("--size", type=int, default=128, help="box edge of the inclined-spheroid workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-bytes", type=int, default=1 << 30,
+                    help="size of the copy used as the achievable-bandwidth reference")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
+                         "profiles/collide_stream_traffic.json and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, storage=args.storage, size=args.size, probe_bytes=args.probe_bytes)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not a measured path.", file=sys.stderr)
@@ -98,9 +153,12 @@ def main():
 
     import torch
     from paper_2403_05443_amd import workloads
+    from paper_2403_05443_amd import lbell
     W = workloads.c2(args.storage, args.size)
     lat = build_lattice(W)
     N = W.sites
+    variant, _ = lat.autotune(10)
+    copy_gbs = lbell.bandwidth_probe(args.probe_bytes, reps=5)
     lat.step(args.warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -141,8 +199,8 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_collide_stream", "bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(k1, 5)},
+                     "kernel": "k_collide_stream", "variant": variant, "bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": round(k1, 5), "copy_probe_gbs": round(copy_gbs, 1)},
         "phase_ms_per_step": {"collide_stream": round(k1, 5), "particle": round(ms_p / psteps, 5)},
         "wall_s": round(wall, 3),
     }

@@ -81,8 +81,10 @@ typedef struct lb_config {
                                velocity_scale as floor(log2(0.25/(velocity_scale/6)))  */
     double velocity_scale;  /* largest fluid speed expected; default 1e-3              */
     double rho0;            /* mean density; must be 1                                 */
-    int    counterforce;    /* 1: add g = -sum(F_ext)/N_fluid to every fluid node each
-                               step so that total momentum stays zero (default 0)      */
+    int    counterforce;    /* 1: a uniform force density g = -sum(F_ext)/N (N = non-wall
+                               nodes of the box) on all matter: every fluid node, and
+                               every particle by its solid-node count, so that total
+                               momentum stays zero (default 0)                        */
     int    max_particles;   /* particle capacity over all boxes (default 1 per box)    */
     double max_semi_axis;   /* largest semi-axis any particle may have (default 8)     */
 } lb_config;
@@ -158,6 +160,22 @@ lb_status lb_step(lb_ctx* ctx, int n);
  * step; *ms_collide and *ms_particle receive the summed GPU durations in
  * milliseconds (either may be NULL).  Synchronises. */
 lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_particle);
+
+/* Tuner: times every applicable collide-stream variant (generic tiles; the
+ * row-wave kernel for a single box with nx = 64, 128 or 256; the same with
+ * non-temporal stores) over `reps` launches each and keeps the fastest for
+ * this context.  The timing launches map the current populations to the
+ * spare buffer only, so the simulation state is unchanged.  *variant and
+ * *ms_best (milliseconds per launch) may be NULL.  Synchronises. */
+lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best);
+
+/* Bandwidth reference: copies `bytes` (a multiple of 16, both pointers
+ * 16-byte aligned device memory owned by the caller) from src to dst `reps`
+ * times on hip_stream with 16-byte accesses, after one warm-up copy, and
+ * returns the achieved read+write rate in GB/s (2 * bytes per copy).  Needs
+ * no context.  Synchronises the stream. */
+lb_status lb_bandwidth_probe(void* dst, const void* src, size_t bytes, void* hip_stream, int reps,
+                             double* gbs);
 
 /* Waits for the stream; returns the first latched device error, if any. */
 lb_status lb_sync(lb_ctx* ctx);

@@ -22,8 +22,10 @@
  *       node: f = f_eq(rho0, U + Omega x r) and the particle pays for it; the
  *       mass difference dm is returned at the next bounce-back spread over the
  *       links as dm * w_b / sum_b w_b;
- *   R10 optional counter-force g = -sum F_ext / N_fluid on every fluid node,
- *       f* += w_i (c_i . g)/c_s^2 after collision;
+ *   R10 optional counter-force: a uniform force density g = -sum F_ext / N on
+ *       all matter of the box (N = non-wall nodes), so total momentum stays
+ *       zero: every fluid node gets f* += w_i (c_i . g)/c_s^2 after collision
+ *       and every particle gets (its solid node count) * g on top of F_ext;
  *   R11 squirmer slip evaluated at the boundary node with the axial
  *       coordinate clamped to [-a, a];
  *   R12 the Couette start includes the first-order non-equilibrium part.
@@ -682,9 +684,15 @@ int or_set_density(or_sim* s, int id, double rho_p) {
 
 /* ------------------------ one iteration, Appendix A ---------------------- */
 
-static int count_fluid(const or_sim* s) {
+static int count_nonwall(const or_sim* s) {
     int st, n = 0;
-    for (st = 0; st < s->n; st++) n += s->node[st] == 0;
+    for (st = 0; st < s->n; st++) n += s->node[st] != -1;
+    return n;
+}
+
+static int count_solid(const or_sim* s, int pid) {
+    int st, n = 0;
+    for (st = 0; st < s->n; st++) n += s->node[st] == pid + 1;
     return n;
 }
 
@@ -695,10 +703,10 @@ static int step_once(or_sim* s) {
 
     if (s->counterforce && s->np > 0) {
         double Ft[3] = {0, 0, 0};
-        int nf = count_fluid(s);
+        int nall = count_nonwall(s);
         for (pid = 0; pid < s->np; pid++)
             for (k = 0; k < 3; k++) Ft[k] += s->p[pid].Fext[k];
-        for (k = 0; k < 3; k++) g[k] = -Ft[k] / nf;
+        for (k = 0; k < 3; k++) g[k] = -Ft[k] / nall;
     }
 
     /* step 1: collision on every fluid node (+ counter-force, R10) */
@@ -726,8 +734,12 @@ static int step_once(or_sim* s) {
     for (pid = 0; pid < s->np; pid++) {
         opart* p = &s->p[pid];
         double F0[3] = {0, 0, 0}, T0[3] = {0, 0, 0}, Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0};
-        double Il[9], Id[9], A[36], rhs[6], sol[6], Iw[3];
+        double Il[9], Id[9], A[36], rhs[6], sol[6], Iw[3], Fcf[3] = {0, 0, 0};
         int l, i, j;
+        if (s->counterforce) {  /* R10: the counter-force density acting on the particle's nodes */
+            int ns = count_solid(s, pid);
+            for (k = 0; k < 3; k++) Fcf[k] = ns * g[k];
+        }
         /* step 3: eqs. F0, T0 from post-collision populations (+ squirmer slip) */
         for (l = 0; l < p->nlinks; l++) {
             int stl = p->lsite[l], b = p->ldir[l];
@@ -761,7 +773,7 @@ static int step_once(or_sim* s) {
         }
         for (i = 0; i < 3; i++) Iw[i] = Il[3 * i] * p->W[0] + Il[3 * i + 1] * p->W[1] + Il[3 * i + 2] * p->W[2];
         for (i = 0; i < 3; i++) {
-            rhs[i] = p->M * p->U[i] + F0[i] + Fs[i] + p->Fext[i] + p->Pp[i];
+            rhs[i] = p->M * p->U[i] + F0[i] + Fs[i] + p->Fext[i] + Fcf[i] + p->Pp[i];
             rhs[3 + i] = Iw[i] + T0[i] + Ts[i] + p->Text[i] + p->Lp[i];
         }
         if (or_solve6(A, rhs, sol) != 0) return -6;

@@ -114,7 +114,7 @@ __device__ __forceinline__ int wsumi(int v) {
 
 // Deterministic block reduction of N doubles; result valid on thread 0.
 template <int N>
-__device__ __forceinline__ void block_reduce(double (&v)[N], double (*red)[PBLOCK / 64]) {
+__device__ __forceinline__ void block_reduce(double (&v)[N], double (*red)[PWAVES]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -122,14 +122,23 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double (*red)[PBLOC
         if (lane == 0) red[k][wv] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double s = 0;
-            for (int w = 0; w < PBLOCK / 64; ++w) s += red[k][w];
-            v[k] = s;
-        }
+    if (threadIdx.x < N) {
+        double s = 0;
+        for (int w = 0; w < PWAVES; ++w) s += red[threadIdx.x][w];
+        red[threadIdx.x][0] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = red[k][0];
+}
+
+// The particle record is read once, cooperatively, into LDS.
+__device__ __forceinline__ void stage_particle(const PartDev* P, PartDev* S) {
+    static_assert(sizeof(PartDev) % 8 == 0, "PartDev must be a whole number of 8-byte words");
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(P);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(S);
+    for (int k = threadIdx.x; k < (int)(sizeof(PartDev) / 8); k += blockDim.x) dst[k] = src[k];
+    __syncthreads();
 }
 
 // Where node (x,y,z) keeps its pre-collision population i in the pull
@@ -150,43 +159,158 @@ __device__ __forceinline__ void pre_slot(const BoxDesc& B, double rho0, int i, i
     }
 }
 
+// Per-thread partial sums of eqs. drag1-drag4 (36 w_b as integers 2 / 1).
+struct ZAcc {
+    int cnt6[6];
+    int w36s;
+    double zfw[9];
+    double ztw[6];
+    __device__ void clear() {
+        for (int k = 0; k < 6; ++k) cnt6[k] = 0;
+        w36s = 0;
+        for (int k = 0; k < 9; ++k) zfw[k] = 0.0;
+        for (int k = 0; k < 6; ++k) ztw[k] = 0.0;
+    }
+    __device__ __forceinline__ void add(int b, int gx, int gy, int gz, const double xc[3], int nx, int ny, int nz) {
+        const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b), w36 = rw36(b);
+        const double r0 = minimg(((double)gx + 0.5 * c0) - xc[0], nx);
+        const double r1 = minimg(((double)gy + 0.5 * c1) - xc[1], ny);
+        const double r2 = minimg(((double)gz + 0.5 * c2) - xc[2], nz);
+        const double rc[3] = {r1 * c2 - r2 * c1, r2 * c0 - r0 * c2, r0 * c1 - r1 * c0};
+        const int cc[3] = {c0, c1, c2};
+        cnt6[0] += w36 * c0 * c0;
+        cnt6[1] += w36 * c0 * c1;
+        cnt6[2] += w36 * c0 * c2;
+        cnt6[3] += w36 * c1 * c1;
+        cnt6[4] += w36 * c1 * c2;
+        cnt6[5] += w36 * c2 * c2;
+        w36s += w36;
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) zfw[3 * ii + jj] += (double)(w36 * cc[ii]) * rc[jj];
+        ztw[0] += w36 * rc[0] * rc[0];
+        ztw[1] += w36 * rc[0] * rc[1];
+        ztw[2] += w36 * rc[0] * rc[2];
+        ztw[3] += w36 * rc[1] * rc[1];
+        ztw[4] += w36 * rc[1] * rc[2];
+        ztw[5] += w36 * rc[2] * rc[2];
+    }
+};
+
+
+// Remap window of a particle: axis-aligned bounding box of the ellipsoid plus
+// two nodes (the whole axis when that is at least the box edge).
+__device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc& B, int lo[3], int wn[3],
+                                                bool whole[3]) {
+    double Rm[3][3];
+    rotmat(P.q, Rm);
+    const int n3[3] = {B.nx, B.ny, B.nz};
+    for (int k = 0; k < 3; ++k) {
+        const double h = sqrt((Rm[k][0] * P.axes[0]) * (Rm[k][0] * P.axes[0]) +
+                              (Rm[k][1] * P.axes[1]) * (Rm[k][1] * P.axes[1]) +
+                              (Rm[k][2] * P.axes[2]) * (Rm[k][2] * P.axes[2]));
+        lo[k] = (int)floor(P.xc[k] - h) - 2;
+        wn[k] = (int)floor(P.xc[k] + h) + 2 - lo[k] + 1;
+        whole[k] = wn[k] >= n3[k];
+        if (whole[k]) {
+            lo[k] = 0;
+            wn[k] = n3[k];
+        }
+    }
+}
+
+// Adds every collide-stream block touching the particle's window grown by
+// the set's margin to the near set (block-cooperative).
+__device__ void mark_near(const NearSet& ns, const BoxDesc& B, const int wlo[3], const int wwn[3]) {
+    const int n3[3] = {B.nx, B.ny, B.nz};
+    int lo[3], wn[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = wlo[k] - ns.margin;
+        wn[k] = wwn[k] + 2 * ns.margin;
+        if (wn[k] >= n3[k]) {
+            lo[k] = 0;
+            wn[k] = n3[k];
+        }
+    }
+    auto add = [&](int blk) {
+        if (atomicExch(ns.flags + blk, ns.epoch) != ns.epoch) ns.list[atomicAdd(ns.count, 1)] = blk;
+    };
+    const int nrows = wn[1] * wn[2];
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+        const int y = wrap(lo[1] + r % wn[1], B.ny), z = wrap(lo[2] + r / wn[1], B.nz);
+        const int row = y + B.ny * z;
+        if (ns.rows_geom) {
+            add(row >> 2);
+        } else {
+            // x-range [lo0, lo0 + wn0) of this row, split where it wraps
+            int xa = wrap(lo[0], B.nx), len = wn[0];
+            while (len > 0) {
+                const int seg = min(len, B.nx - xa);
+                const int s0 = B.nx * row + xa, s1 = s0 + seg - 1;
+                for (int t = s0 / TILE; t <= s1 / TILE; ++t) add(B.tile0 + t);
+                len -= seg;
+                xa = 0;
+            }
+        }
+    }
+}
+
 template <int ST>
 __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
     using S = Store<ST>;
     using T = typename S::T;
-    __shared__ double red[12][PBLOCK / 64];
+    __shared__ PartDev P;
+    __shared__ double red[12][PWAVES];
     __shared__ double bc[8];
-    __shared__ double A[6][7];  // the 6x6 system, eliminated by thread 0 (LDS, not private stack)
+    __shared__ double A[6][7];  // the 6x6 system, eliminated by thread 0
     const int p = a.first + (int)blockIdx.x;
-    PartDev* P = a.parts + p;
-    const BoxDesc& B = a.boxes[P->box];
+    PartDev* Pg = a.parts + p;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.near.count) *a.near.count = 0;  // filled by the remap
+    stage_particle(Pg, &P);
+    const BoxDesc& B = a.boxes[P.box];
     T* f = (T*)a.f + B.foff;
     const long long st = B.stride;
     const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
-    const double xc[3] = {P->xc[0], P->xc[1], P->xc[2]};
-    const double q[4] = {P->q[0], P->q[1], P->q[2], P->q[3]};
-    const double B1 = P->B1, B2 = P->B2, ax = P->axes[0], bx = P->axes[1];
+    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
+    const double q[4] = {P.q[0], P.q[1], P.q[2], P.q[3]};
+    const double B1 = P.B1, B2 = P.B2, ax = P.axes[0], bx = P.axes[1];
     const bool sq = B1 != 0.0 || B2 != 0.0;
-    const int nl = P->nlinks;
-    const uint32_t* L = a.links + P->lbase;
+    const int nl = P.nlinks;
+    const uint32_t* L = a.links + P.lbase;
     const double inv = a.kp.inv_scale, scl = a.kp.scale, rho0 = a.kp.rho0;
     double Rm[3][3];
     rotmat(q, Rm);
     const double e[3] = {Rm[0][0], Rm[1][0], Rm[2][0]};
 
+    // links of this thread: codes and post-collision populations stay in
+    // registers from the force reduction to the bounce-back
+    uint32_t code[KREG];
+    double fbv[KREG];
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) {
+        const int l = tid + k * PBLOCK;
+        code[k] = l < nl ? L[l] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) {
+        const int l = tid + k * PBLOCK;
+        const int s = (int)(code[k] & SITE_MASK), b = (int)(code[k] >> SITE_BITS);
+        fbv[k] = l < nl ? S::ld64(f + (long long)b * st + s, inv) : 0.0;
+    }
+
     // step 3: velocity-independent force and torque (+ slip part)
     double acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-    for (int l = tid; l < nl; l += PBLOCK) {
-        const uint32_t code = L[l];
-        const int s = (int)(code & SITE_MASK), b = (int)(code >> SITE_BITS);
+    auto accumulate = [&](uint32_t cd, double fb) {
+        const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
         const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
         const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b);
         const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
                              minimg(((double)z + 0.5 * c2) - xc[2], nz)};
         const double rc0 = r[1] * c2 - r[2] * c1, rc1 = r[2] * c0 - r[0] * c2, rc2 = r[0] * c1 - r[1] * c0;
-        const double fb2 = 2.0 * S::ld64(f + (long long)b * st + s, inv);
+        const double fb2 = 2.0 * fb;
         acc[0] += fb2 * c0;
         acc[1] += fb2 * c1;
         acc[2] += fb2 * c2;
@@ -204,34 +328,42 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
             acc[10] -= kuc * rc1;
             acc[11] -= kuc * rc2;
         }
+    };
+#pragma unroll
+    for (int k = 0; k < KREG; ++k)
+        if (tid + k * PBLOCK < nl) accumulate(code[k], fbv[k]);
+    for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
+        const uint32_t cd = L[l];
+        accumulate(cd, S::ld64(f + (long long)(cd >> SITE_BITS) * st + (int)(cd & SITE_MASK), inv));
     }
     block_reduce<12>(acc, red);
 
     if (tid == 0) {
         // step 4: I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x with W = Omega(t)
-        const double Ib[3] = {P->Ib[0], P->Ib[1], P->Ib[2]};
-        const double M = P->M;
-        const double U0[3] = {P->U[0], P->U[1], P->U[2]}, W0[3] = {P->W[0], P->W[1], P->W[2]};
+        const double M = P.M;
+        const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
         double Il[3][3], Id[3][3];
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j)
-                Il[i][j] = Rm[i][0] * Ib[0] * Rm[j][0] + Rm[i][1] * Ib[1] * Rm[j][1] + Rm[i][2] * Ib[2] * Rm[j][2];
+                Il[i][j] = Rm[i][0] * P.Ib[0] * Rm[j][0] + Rm[i][1] * P.Ib[1] * Rm[j][1] + Rm[i][2] * P.Ib[2] * Rm[j][2];
         const double Wx[3][3] = {{0, -W0[2], W0[1]}, {W0[2], 0, -W0[0]}, {-W0[1], W0[0], 0}};
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
-                double s = 0;
-                for (int k = 0; k < 3; ++k) s += Wx[i][k] * Il[k][j] - Il[i][k] * Wx[k][j];
-                Id[i][j] = s;
+                double sum = 0;
+                for (int k = 0; k < 3; ++k) sum += Wx[i][k] * Il[k][j] - Il[i][k] * Wx[k][j];
+                Id[i][j] = sum;
             }
         // step 5: [M + zFU, zFW; zTU, I' + dI/dt + zTW] [U'; W'] = [M U + F0 + ...; I' W + T0 + ...]
         for (int i = 0; i < 6; ++i)
-            for (int j = 0; j < 6; ++j) A[i][j] = P->zeta[6 * i + j];
+            for (int j = 0; j < 6; ++j) A[i][j] = P.zeta[6 * i + j];
         for (int i = 0; i < 3; ++i) {
             A[i][i] += M;
             for (int j = 0; j < 3; ++j) A[3 + i][3 + j] += Il[i][j] + Id[i][j];
-            A[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P->Fext[i] + P->Pp[i];
+            // counter-force density on the particle's own nodes (box-wide g = -sum F_ext / N)
+            const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
+            A[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
             A[3 + i][6] = (Il[i][0] * W0[0] + Il[i][1] * W0[1] + Il[i][2] * W0[2]) + acc[3 + i] + acc[9 + i] +
-                          P->Text[i] + P->Lp[i];
+                          P.Text[i] + P.Lp[i];
         }
         bool ok = true;
         for (int k = 0; k < 6; ++k) {  // Gaussian elimination, partial pivoting
@@ -256,13 +388,18 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
         double sol[6] = {0, 0, 0, 0, 0, 0};
         if (ok)
             for (int r = 5; r >= 0; --r) {
-                double s = A[r][6];
-                for (int c = r + 1; c < 6; ++c) s -= A[r][c] * sol[c];
-                sol[r] = s / A[r][r];
+                double sum = A[r][6];
+                for (int c = r + 1; c < 6; ++c) sum -= A[r][c] * sol[c];
+                sol[r] = sum / A[r][r];
             }
         bool bad = !ok;
         for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
-        for (int k = 0; k < 3; ++k) bad = bad || fabs(sol[k]) > 0.5;
+        {  // surface speed |U| + |Omega| max(a,b,c) must stay below half a node per step
+            const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
+            const double sp = sqrt(sol[0] * sol[0] + sol[1] * sol[1] + sol[2] * sol[2]) +
+                              sqrt(sol[3] * sol[3] + sol[4] * sol[4] + sol[5] * sol[5]) * amax;
+            bad = bad || !(sp <= 0.5);
+        }
         if (bad) {
             atomicOr(a.flags, (int)F_NONFINITE);
             for (int k = 0; k < 6; ++k) sol[k] = k < 3 ? U0[k] : W0[k - 3];
@@ -271,16 +408,16 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
         for (int i = 0; i < 3; ++i) {
             double zf = 0, zt = 0;
             for (int j = 0; j < 6; ++j) {
-                zf += P->zeta[6 * i + j] * sol[j];
-                zt += P->zeta[6 * (3 + i) + j] * sol[j];
+                zf += P.zeta[6 * i + j] * sol[j];
+                zt += P.zeta[6 * (3 + i) + j] * sol[j];
             }
-            P->F[i] = acc[i] + acc[6 + i] + P->Pp[i] - zf;
-            P->T[i] = acc[3 + i] + acc[9 + i] + P->Lp[i] - zt;
-            P->Pp[i] = 0.0;
-            P->Lp[i] = 0.0;
+            Pg->F[i] = acc[i] + acc[6 + i] + P.Pp[i] - zf;
+            Pg->T[i] = acc[3 + i] + acc[9 + i] + P.Lp[i] - zt;
+            Pg->Pp[i] = 0.0;
+            Pg->Lp[i] = 0.0;
         }
         for (int k = 0; k < 6; ++k) bc[k] = sol[k];
-        bc[6] = P->wsum > 0.0 ? P->dm / P->wsum : 0.0;
+        bc[6] = P.wsum > 0.0 ? P.dm / P.wsum : 0.0;
         // step 7 (its inputs are fixed now; the links below use x_c(t), q(t) from registers)
         double Wm[3];
         for (int i = 0; i < 3; ++i) {
@@ -289,30 +426,29 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
             double xn = xc[i] + dx;
             if (xn >= n3) xn -= n3;
             if (xn < 0.0) xn += n3;
-            P->xc[i] = xn;
-            P->xu[i] += dx;
-            P->U[i] = sol[i];
-            P->W[i] = sol[3 + i];
+            Pg->xc[i] = xn;
+            Pg->xu[i] = P.xu[i] + dx;
+            Pg->U[i] = sol[i];
+            Pg->W[i] = sol[3 + i];
             Wm[i] = 0.5 * (W0[i] + sol[3 + i]);
         }
         const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
         if (nrm != 0.0) {
             const double c = cos(0.5 * nrm), sn = sin(0.5 * nrm);
             const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
-            P->q[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
-            P->q[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
-            P->q[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
-            P->q[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+            Pg->q[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
+            Pg->q[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
+            Pg->q[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
+            Pg->q[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
         }
-        P->dm = 0.0;
+        Pg->dm = 0.0;
     }
     __syncthreads();
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step
     const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / 36.0;
-    for (int l = tid; l < nl; l += PBLOCK) {
-        const uint32_t code = L[l];
-        const int s = (int)(code & SITE_MASK), b = (int)(code >> SITE_BITS);
+    auto bounce = [&](uint32_t cd, double fb) {
+        const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
         const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
         const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b);
         const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
@@ -327,10 +463,16 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
             ub[2] += us[2];
         }
         const int w36 = rw36(b);
-        const double fb = S::ld64(f + (long long)b * st + s, inv);
         const double val = fb - (w36 / 6.0) * rho0 * (ub[0] * c0 + ub[1] * c1 + ub[2] * c2) + dmw * w36;
         const int dst = wrap(x + c0, nx) + nx * (wrap(y + c1, ny) + ny * wrap(z + c2, nz));
         S::st64(f + (long long)ropp(b) * st + dst, val, scl);
+    };
+#pragma unroll
+    for (int k = 0; k < KREG; ++k)
+        if (tid + k * PBLOCK < nl) bounce(code[k], fbv[k]);
+    for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
+        const uint32_t cd = L[l];
+        bounce(cd, S::ld64(f + (long long)(cd >> SITE_BITS) * st + (int)(cd & SITE_MASK), inv));
     }
 }
 
@@ -341,13 +483,15 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
     extern __shared__ uint32_t smem[];
     uint32_t* bits = smem;
     uint32_t* stage = smem + a.lds_words;
-    __shared__ double red[22][PBLOCK / 64];
-    __shared__ int wtot[PBLOCK / 64];
-    __shared__ int ired[8][PBLOCK / 64];
+    __shared__ PartDev P;
+    __shared__ double red[22][PWAVES];
+    __shared__ int wtot[PWAVES];
+    __shared__ int ired[8][PWAVES];
 
     const int p = a.first + (int)blockIdx.x;
-    PartDev* P = a.parts + p;
-    const int bi = P->box;
+    PartDev* Pg = a.parts + p;
+    stage_particle(Pg, &P);
+    const int bi = P.box;
     const BoxDesc& B = a.boxes[bi];
     T* f = (T*)a.f + B.foff;
     uint16_t* om = a.omap + B.ooff;
@@ -356,30 +500,15 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
     const int lane = tid & 63, wv = tid >> 6;
     const uint16_t me = (uint16_t)(p + 1);
     const int mode = a.mode;
-    const double xc[3] = {P->xc[0], P->xc[1], P->xc[2]};
-    const double q[4] = {P->q[0], P->q[1], P->q[2], P->q[3]};
-    const double ia2[3] = {P->ia2[0], P->ia2[1], P->ia2[2]};
-    const double U[3] = {P->U[0], P->U[1], P->U[2]}, W[3] = {P->W[0], P->W[1], P->W[2]};
+    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
+    const double q[4] = {P.q[0], P.q[1], P.q[2], P.q[3]};
+    const double ia2[3] = {P.ia2[0], P.ia2[1], P.ia2[2]};
+    const double U[3] = {P.U[0], P.U[1], P.U[2]}, W[3] = {P.W[0], P.W[1], P.W[2]};
     const double inv = a.kp.inv_scale, scl = a.kp.scale, rho0 = a.kp.rho0;
 
-    // window: axis-aligned bounding box of the ellipsoid plus two nodes
-    double Rm[3][3];
-    rotmat(q, Rm);
     int lo[3], wn[3];
-    const int n3[3] = {nx, ny, nz};
     bool whole[3];
-    for (int k = 0; k < 3; ++k) {
-        const double h = sqrt((Rm[k][0] * P->axes[0]) * (Rm[k][0] * P->axes[0]) +
-                              (Rm[k][1] * P->axes[1]) * (Rm[k][1] * P->axes[1]) +
-                              (Rm[k][2] * P->axes[2]) * (Rm[k][2] * P->axes[2]));
-        lo[k] = (int)floor(xc[k] - h) - 2;
-        wn[k] = (int)floor(xc[k] + h) + 2 - lo[k] + 1;
-        whole[k] = wn[k] >= n3[k];
-        if (whole[k]) {
-            lo[k] = 0;
-            wn[k] = n3[k];
-        }
-    }
+    particle_window(P, B, lo, wn, whole);
     const int nsites = wn[0] * wn[1] * wn[2];
     if (((nsites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32) > a.lds_words) {
         if (tid == 0) atomicOr(a.flags, (int)F_WINDOW);
@@ -389,217 +518,258 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
     // pass 1: solid test, node-map update, covered / uncovered nodes
     double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
     int nsol = 0;
-    for (int base = 0; base < nsites; base += PBLOCK) {
-        const int i = base + tid;
-        bool in = false;
-        if (i < nsites) {
-            const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
-            const int gx = wrap(lo[0] + wx, nx), gy = wrap(lo[1] + wy, ny), gz = wrap(lo[2] + wz, nz);
-            const int s = gx + nx * (gy + ny * gz);
-            const uint16_t own = om[s];
-            if (mode == 2) {
-                if (own == me) om[s] = 0;
-            } else {
-                in = inside_test(xc, q, ia2, gx, gy, gz, nx, ny, nz);
-                if (in && own != 0 && own != me) {
-                    atomicOr(a.flags, (int)F_OVERLAP);
-                    in = false;
-                }
-                const bool old = own == me;
-                if (in != old) {
-                    if (mode == 0) {
-                        const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
-                                             minimg((double)gz - xc[2], nz)};
-                        if (in) {  // covered: its fluid mass and momentum go to the particle
-                            double m = 0, pm[3] = {0, 0, 0};
-                            for (int j = 0; j < NQ; ++j) {
-                                int dir, slot;
-                                double add;
-                                pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
-                                const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
-                                m += v;
-                                pm[0] += rcx(j) * v;
-                                pm[1] += rcy(j) * v;
-                                pm[2] += rcz(j) * v;
-                            }
-                            tacc[0] += rho0 + m;
-                            tacc[1] += pm[0];
-                            tacc[2] += pm[1];
-                            tacc[3] += pm[2];
-                            tacc[4] += r[1] * pm[2] - r[2] * pm[1];
-                            tacc[5] += r[2] * pm[0] - r[0] * pm[2];
-                            tacc[6] += r[0] * pm[1] - r[1] * pm[0];
-                        } else {  // uncovered: f = f_eq(rho0, U + W x r), paid by the particle
-                            const double u[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]), U[1] + (W[2] * r[0] - W[0] * r[2]),
-                                                 U[2] + (W[0] * r[1] - W[1] * r[0])};
-                            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-                            for (int j = 0; j < NQ; ++j) {
-                                int dir, slot;
-                                double add;
-                                pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
-                                const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
-                                const double dev = (rw36(j) / 36.0) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-                                S::st64(f + (long long)dir * st + slot, dev - add, scl);
-                            }
-                            tacc[0] -= rho0;
-                            const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
-                            tacc[1] -= pu[0];
-                            tacc[2] -= pu[1];
-                            tacc[3] -= pu[2];
-                            tacc[4] -= r[1] * pu[2] - r[2] * pu[1];
-                            tacc[5] -= r[2] * pu[0] - r[0] * pu[2];
-                            tacc[6] -= r[0] * pu[1] - r[1] * pu[0];
-                        }
-                    }
-                    om[s] = in ? me : (uint16_t)0;
-                }
-                nsol += in ? 1 : 0;
+    bool changed = false;
+    for (int base = 0; base < nsites; base += PBLOCK * KREG) {
+        uint16_t own[KREG];
+        int sidx[KREG], gxyz[KREG][3];
+#pragma unroll
+        for (int k = 0; k < KREG; ++k) {  // issue the node-map loads of the whole group first
+            const int i = base + k * PBLOCK + tid;
+            sidx[k] = -1;
+            own[k] = 0;
+            if (i < nsites) {
+                const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
+                gxyz[k][0] = wrap(lo[0] + wx, nx);
+                gxyz[k][1] = wrap(lo[1] + wy, ny);
+                gxyz[k][2] = wrap(lo[2] + wz, nz);
+                sidx[k] = gxyz[k][0] + nx * (gxyz[k][1] + ny * gxyz[k][2]);
+                own[k] = om[sidx[k]];
             }
         }
-        const unsigned long long m = __ballot(in);
-        if (lane == 0) {
-            const int w0 = (base + wv * 64) >> 5;
-            bits[w0] = (uint32_t)m;
-            bits[w0 + 1] = (uint32_t)(m >> 32);
+#pragma unroll
+        for (int k = 0; k < KREG; ++k) {
+            if (base + k * PBLOCK >= nsites) break;  // uniform over the block
+            bool in = false;
+            const int s = sidx[k];
+            if (s >= 0) {
+                const int gx = gxyz[k][0], gy = gxyz[k][1], gz = gxyz[k][2];
+                if (mode == 2) {
+                    if (own[k] == me) om[s] = 0;
+                } else {
+                    in = inside_test(xc, q, ia2, gx, gy, gz, nx, ny, nz);
+                    if (in && own[k] != 0 && own[k] != me) {
+                        atomicOr(a.flags, (int)F_OVERLAP);
+                        in = false;
+                    }
+                    const bool old = own[k] == me;
+                    if (in != old) {
+                        changed = true;
+                        if (mode == 0) {
+                            const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
+                                                 minimg((double)gz - xc[2], nz)};
+                            if (in) {  // covered: its fluid mass and momentum go to the particle
+                                double m = 0, pm[3] = {0, 0, 0};
+                                for (int j = 0; j < NQ; ++j) {
+                                    int dir, slot;
+                                    double add;
+                                    pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
+                                    const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
+                                    m += v;
+                                    pm[0] += rcx(j) * v;
+                                    pm[1] += rcy(j) * v;
+                                    pm[2] += rcz(j) * v;
+                                }
+                                tacc[0] += rho0 + m;
+                                tacc[1] += pm[0];
+                                tacc[2] += pm[1];
+                                tacc[3] += pm[2];
+                                tacc[4] += r[1] * pm[2] - r[2] * pm[1];
+                                tacc[5] += r[2] * pm[0] - r[0] * pm[2];
+                                tacc[6] += r[0] * pm[1] - r[1] * pm[0];
+                            } else {  // uncovered: f = f_eq(rho0, U + W x r), paid by the particle
+                                const double u[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]),
+                                                     U[1] + (W[2] * r[0] - W[0] * r[2]),
+                                                     U[2] + (W[0] * r[1] - W[1] * r[0])};
+                                const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                                for (int j = 0; j < NQ; ++j) {
+                                    int dir, slot;
+                                    double add;
+                                    pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
+                                    const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
+                                    const double dev = (rw36(j) / 36.0) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                                    S::st64(f + (long long)dir * st + slot, dev - add, scl);
+                                }
+                                tacc[0] -= rho0;
+                                const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
+                                tacc[1] -= pu[0];
+                                tacc[2] -= pu[1];
+                                tacc[3] -= pu[2];
+                                tacc[4] -= r[1] * pu[2] - r[2] * pu[1];
+                                tacc[5] -= r[2] * pu[0] - r[0] * pu[2];
+                                tacc[6] -= r[0] * pu[1] - r[1] * pu[0];
+                            }
+                        }
+                        om[s] = in ? me : (uint16_t)0;
+                    }
+                    nsol += in ? 1 : 0;
+                }
+            }
+            const unsigned long long m = __ballot(in);
+            if (lane == 0) {
+                const int w0 = (base + k * PBLOCK + wv * 64) >> 5;
+                bits[w0] = (uint32_t)m;
+                bits[w0 + 1] = (uint32_t)(m >> 32);
+            }
         }
     }
-    __syncthreads();
+    changed = __syncthreads_or(changed);
 
     if (mode == 2) {
         if (tid == 0) {
-            atomicAdd(&a.rt[bi].n_solid, -P->n_solid);
-            P->n_solid = 0;
-            P->nlinks = 0;
+            atomicAdd(&a.rt[bi].n_solid, -P.n_solid);
+            Pg->n_solid = 0;
+            Pg->nlinks = 0;
         }
         return;
     }
 
-    // pass 2: boundary links (fluid x, x + c_b solid here), staged in LDS and
-    // written in (window index, direction) order; drag-matrix sums per link
+    ZAcc z;
+    z.clear();
     int running = 0;
-    int cnt6[6] = {0, 0, 0, 0, 0, 0}, w36s = 0;
-    double zfw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ztw[6] = {0, 0, 0, 0, 0, 0};
-    const int lcap = P->lcap;
-    uint32_t* L = a.links + P->lbase;
-    for (int base = 0; base < nsites; base += PBLOCK) {
-        const int i = base + tid;
-        uint32_t lm = 0;
-        int s = 0, gx = 0, gy = 0, gz = 0;
-        if (i < nsites && !((bits[i >> 5] >> (i & 31)) & 1u)) {
-            const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
-            gx = wrap(lo[0] + wx, nx);
-            gy = wrap(lo[1] + wy, ny);
-            gz = wrap(lo[2] + wz, nz);
-            s = gx + nx * (gy + ny * gz);
-            if (om[s] == 0) {
+    const int lcap = P.lcap;
+    uint32_t* L = a.links + P.lbase;
+    if (mode == 0 && !changed) {
+        // no node changed state, so the link set is unchanged: only the drag
+        // matrices move with the centre
+        running = P.nlinks;
+        for (int l = tid; l < running; l += PBLOCK) {
+            const uint32_t cd = L[l];
+            const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
+            const int x = s % nx, t = s / nx, y = t % ny, zz = t / ny;
+            z.add(b, x, y, zz, xc, nx, ny, nz);
+        }
+    } else {
+        // pass 2: boundary links (fluid x, x + c_b solid here), staged in LDS
+        // and written in (window index, direction) order
+        for (int base = 0; base < nsites; base += PBLOCK) {
+            const int i = base + tid;
+            uint32_t lm = 0;
+            int s = 0, gx = 0, gy = 0, gz = 0;
+            if (i < nsites && !((bits[i >> 5] >> (i & 31)) & 1u)) {
+                const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
+                gx = wrap(lo[0] + wx, nx);
+                gy = wrap(lo[1] + wy, ny);
+                gz = wrap(lo[2] + wz, nz);
+                s = gx + nx * (gy + ny * gz);
+                if (om[s] == 0) {
 #pragma unroll
-                for (int b = 1; b < NQ; ++b) {
-                    int nwx = wx + cx(b), nwy = wy + cy(b), nwz = wz + cz(b);
-                    if (whole[0]) nwx = wrap(nwx, wn[0]);
-                    else if (nwx < 0 || nwx >= wn[0]) continue;
-                    if (whole[1]) nwy = wrap(nwy, wn[1]);
-                    else if (nwy < 0 || nwy >= wn[1]) continue;
-                    if (whole[2]) nwz = wrap(nwz, wn[2]);
-                    else if (nwz < 0 || nwz >= wn[2]) continue;
-                    const int ni = nwx + wn[0] * (nwy + wn[1] * nwz);
-                    if ((bits[ni >> 5] >> (ni & 31)) & 1u) lm |= 1u << b;
+                    for (int b = 1; b < NQ; ++b) {
+                        int nwx = wx + cx(b), nwy = wy + cy(b), nwz = wz + cz(b);
+                        if (whole[0]) nwx = wrap(nwx, wn[0]);
+                        else if (nwx < 0 || nwx >= wn[0]) continue;
+                        if (whole[1]) nwy = wrap(nwy, wn[1]);
+                        else if (nwy < 0 || nwy >= wn[1]) continue;
+                        if (whole[2]) nwz = wrap(nwz, wn[2]);
+                        else if (nwz < 0 || nwz >= wn[2]) continue;
+                        const int ni = nwx + wn[0] * (nwy + wn[1] * nwz);
+                        if ((bits[ni >> 5] >> (ni & 31)) & 1u) lm |= 1u << b;
+                    }
                 }
             }
+            const int cnt = __popc(lm);
+            int incl = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int nb = __shfl_up(incl, o);
+                if (lane >= o) incl += nb;
+            }
+            if (lane == 63) wtot[wv] = incl;
+            __syncthreads();
+            int off = incl - cnt, total = 0;
+            for (int w = 0; w < PWAVES; ++w) {
+                if (w < wv) off += wtot[w];
+                total += wtot[w];
+            }
+            uint32_t mm = lm;
+            while (mm) {
+                const int b = __ffs(mm) - 1;
+                mm &= mm - 1;
+                z.add(b, gx, gy, gz, xc, nx, ny, nz);
+            }
+            for (int r0 = 0; r0 < total; r0 += STAGE) {
+                uint32_t m2 = lm;
+                int idx = off;
+                while (m2) {
+                    const int b = __ffs(m2) - 1;
+                    m2 &= m2 - 1;
+                    if (idx >= r0 && idx < r0 + STAGE) stage[idx - r0] = (uint32_t)s | ((uint32_t)b << SITE_BITS);
+                    ++idx;
+                }
+                __syncthreads();
+                const int n_r = min(STAGE, total - r0);
+                for (int j = tid; j < n_r; j += PBLOCK) {
+                    const int dst = running + r0 + j;
+                    if (dst < lcap) L[dst] = stage[j];
+                }
+                __syncthreads();
+            }
+            running += total;
         }
-        const int cnt = __popc(lm);
-        int incl = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int nb = __shfl_up(incl, o);
-            if (lane >= o) incl += nb;
-        }
-        if (lane == 63) wtot[wv] = incl;
-        __syncthreads();
-        int off = incl - cnt, total = 0;
-        for (int w = 0; w < PBLOCK / 64; ++w) {
-            if (w < wv) off += wtot[w];
-            total += wtot[w];
-        }
-        uint32_t mm = lm;
-        while (mm) {
-            const int b = __ffs(mm) - 1;
-            mm &= mm - 1;
-            stage[off++] = (uint32_t)s | ((uint32_t)b << SITE_BITS);
-            const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b), w36 = rw36(b);
-            const double r0 = minimg(((double)gx + 0.5 * c0) - xc[0], nx);
-            const double r1 = minimg(((double)gy + 0.5 * c1) - xc[1], ny);
-            const double r2 = minimg(((double)gz + 0.5 * c2) - xc[2], nz);
-            const double rc[3] = {r1 * c2 - r2 * c1, r2 * c0 - r0 * c2, r0 * c1 - r1 * c0};
-            const int cc[3] = {c0, c1, c2};
-            cnt6[0] += w36 * c0 * c0;
-            cnt6[1] += w36 * c0 * c1;
-            cnt6[2] += w36 * c0 * c2;
-            cnt6[3] += w36 * c1 * c1;
-            cnt6[4] += w36 * c1 * c2;
-            cnt6[5] += w36 * c2 * c2;
-            w36s += w36;
-            for (int ii = 0; ii < 3; ++ii)
-                for (int jj = 0; jj < 3; ++jj) zfw[3 * ii + jj] += (double)(w36 * cc[ii]) * rc[jj];
-            ztw[0] += w36 * rc[0] * rc[0];
-            ztw[1] += w36 * rc[0] * rc[1];
-            ztw[2] += w36 * rc[0] * rc[2];
-            ztw[3] += w36 * rc[1] * rc[1];
-            ztw[4] += w36 * rc[1] * rc[2];
-            ztw[5] += w36 * rc[2] * rc[2];
-        }
-        __syncthreads();
-        for (int j = tid; j < total; j += PBLOCK) {
-            const int idx = running + j;
-            if (idx < lcap) L[idx] = stage[j];
-        }
-        running += total;
-        __syncthreads();
+        if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
     }
-    if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
 
     double all[22];
     for (int k = 0; k < 7; ++k) all[k] = tacc[k];
-    for (int k = 0; k < 9; ++k) all[7 + k] = zfw[k];
-    for (int k = 0; k < 6; ++k) all[16 + k] = ztw[k];
+    for (int k = 0; k < 9; ++k) all[7 + k] = z.zfw[k];
+    for (int k = 0; k < 6; ++k) all[16 + k] = z.ztw[k];
     block_reduce<22>(all, red);
-    int iv[8] = {cnt6[0], cnt6[1], cnt6[2], cnt6[3], cnt6[4], cnt6[5], w36s, nsol};
+    const int iv[8] = {z.cnt6[0], z.cnt6[1], z.cnt6[2], z.cnt6[3], z.cnt6[4], z.cnt6[5], z.w36s, nsol};
     for (int k = 0; k < 8; ++k) {
-        const int s = wsumi(iv[k]);
-        if (lane == 0) ired[k][wv] = s;
+        const int sm = wsumi(iv[k]);
+        if (lane == 0) ired[k][wv] = sm;
     }
     __syncthreads();
     if (tid == 0) {
         int tot[8];
         for (int k = 0; k < 8; ++k) {
             tot[k] = 0;
-            for (int w = 0; w < PBLOCK / 64; ++w) tot[k] += ired[k][w];
+            for (int w = 0; w < PWAVES; ++w) tot[k] += ired[k][w];
         }
         // zeta_FU = (2 rho0 / c_s^2) sum w c c = rho0 * (integer sum of 36 w c c) / 6
         const int fu[3][3] = {{tot[0], tot[1], tot[2]}, {tot[1], tot[3], tot[4]}, {tot[2], tot[4], tot[5]}};
         const double tw[3][3] = {{all[16], all[17], all[18]}, {all[17], all[19], all[20]}, {all[18], all[20], all[21]}};
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
-                P->zeta[6 * i + j] = rho0 * fu[i][j] / 6.0;
-                P->zeta[6 * i + 3 + j] = rho0 * all[7 + 3 * i + j] / 6.0;
-                P->zeta[6 * (3 + i) + j] = rho0 * all[7 + 3 * j + i] / 6.0;
-                P->zeta[6 * (3 + i) + 3 + j] = rho0 * tw[i][j] / 6.0;
+                Pg->zeta[6 * i + j] = rho0 * fu[i][j] / 6.0;
+                Pg->zeta[6 * i + 3 + j] = rho0 * all[7 + 3 * i + j] / 6.0;
+                Pg->zeta[6 * (3 + i) + j] = rho0 * all[7 + 3 * j + i] / 6.0;
+                Pg->zeta[6 * (3 + i) + 3 + j] = rho0 * tw[i][j] / 6.0;
             }
-        P->wsum = tot[6] / 36.0;
-        P->nlinks = running < lcap ? running : lcap;
+        Pg->wsum = tot[6] / 36.0;
+        Pg->nlinks = running < lcap ? running : lcap;
         if (mode == 0) {
-            P->dm += all[0];
+            Pg->dm = P.dm + all[0];
             for (int k = 0; k < 3; ++k) {
-                P->Pp[k] += all[1 + k];
-                P->Lp[k] += all[4 + k];
+                Pg->Pp[k] = P.Pp[k] + all[1 + k];
+                Pg->Lp[k] = P.Lp[k] + all[4 + k];
             }
         }
-        atomicAdd(&a.rt[bi].n_solid, tot[7] - P->n_solid);
-        P->n_solid = tot[7];
+        if (tot[7] != P.n_solid) atomicAdd(&a.rt[bi].n_solid, tot[7] - P.n_solid);
+        Pg->n_solid = tot[7];
     }
+    if (mode == 0 && a.near.flags) mark_near(a.near, B, lo, wn);
 }
+
+// Near set from the particles' current positions (set-up and re-tuning).
+__global__ __launch_bounds__(256) void k_near_mark(LaunchPart a) {
+    const PartDev& P = a.parts[a.first + blockIdx.x];
+    const BoxDesc& B = a.boxes[P.box];
+    int lo[3], wn[3];
+    bool whole[3];
+    particle_window(P, B, lo, wn, whole);
+    mark_near(a.near, B, lo, wn);
+}
+
+
 
 // ------------------------------- launchers ----------------------------------
 
-size_t particle_remap_lds_bytes(int lds_words) { return (size_t)(lds_words + PBLOCK * 18) * sizeof(uint32_t); }
+hipError_t launch_near_mark(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_near_mark, dim3(a.count), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+size_t particle_remap_lds_bytes(int lds_words) { return (size_t)(lds_words + STAGE) * sizeof(uint32_t); }
 
 hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st) {
     if (a.count <= 0) return hipSuccess;

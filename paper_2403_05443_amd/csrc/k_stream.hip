@@ -26,6 +26,7 @@ struct Pull {
     static __device__ __forceinline__ void pull(const BoxDesc& B, const T* __restrict__ fi, int s,
                                                 int x, int y, int z, R inv_scale, R rho0,
                                                 bool walls, R (&f)[NQ]) {
+#pragma clang fp contract(off)
         const int nx = B.nx, ny = B.ny, nz = B.nz;
         const long long st = B.stride;
         const int xs0 = x == nx - 1 ? 0 : x + 1, xs2 = x == 0 ? nx - 1 : x - 1;
@@ -51,9 +52,13 @@ struct Pull {
 };
 
 // Collision on deviations d_i = f_i - w_i rho0 (algebraically identical to
-// the full-population forms of Sec. II.A).
+// the full-population forms of Sec. II.A).  FP contraction is off: every
+// collide-stream variant then rounds identically, so results never depend on
+// which variant the tuner picked (the kernel is bandwidth-bound; the extra
+// multiply-adds cost nothing measurable).
 template <typename R, int COLL>
 __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf, R g0, R g1, R g2) {
+#pragma clang fp contract(off)
     R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -135,10 +140,18 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
                                                          const int* __restrict__ tile_box,
                                                          const typename Store<ST>::T* __restrict__ fin,
                                                          typename Store<ST>::T* __restrict__ fout,
-                                                         KParams kp) {
+                                                         KParams kp, int part, const uint32_t* __restrict__ nflags,
+                                                         const int* __restrict__ nlist,
+                                                         const int* __restrict__ ncount, uint32_t epoch) {
     using S = Store<ST>;
     using R = typename S::R;
-    const int tile = blockIdx.x;
+    int tile = blockIdx.x;
+    if (part == 2) {
+        if (tile >= *ncount) return;
+        tile = nlist[tile];
+    } else if (part == 1 && nflags[tile] == epoch) {
+        return;
+    }
     const int bi = tile_box[tile];
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
@@ -152,16 +165,149 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
     Pull<ST>::pull(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
     R g0 = 0, g1 = 0, g2 = 0;
     const bool cf = B.counterforce != 0;
-    if (cf) {
-        const double nf = (double)(B.n - B.n_wall - rt[bi].n_solid);
-        g0 = (R)(-B.fext[0] / nf);
-        g1 = (R)(-B.fext[1] / nf);
-        g2 = (R)(-B.fext[2] / nf);
+    if (cf) {  // uniform force density on all matter of the box (fluid and particles)
+        const double nall = (double)(B.n - B.n_wall);
+        g0 = (R)(-B.fext[0] / nall);
+        g1 = (R)(-B.fext[1] / nall);
+        g2 = (R)(-B.fext[2] / nall);
     }
     collide<R, COLL>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
     typename S::T* fo = fout + B.foff;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) S::st(fo + (long long)i * B.stride + s, f[i], scl);
+}
+
+// Row-wave variant for boxes with nx = 64 K: one wavefront owns one x-row,
+// lane l holds the K consecutive sites [K l, K l + K).  Every direction plane
+// is read with one aligned K-wide vector load per lane; the +-1 shift of the
+// directions with c_x != 0 moves one element across lanes with a wave
+// rotation (ds_bpermute), which is also the periodic wrap of the row.
+template <typename T, int K>
+struct VecOf {
+    typedef T type __attribute__((ext_vector_type(K)));
+};
+template <typename T>
+struct VecOf<T, 1> {
+    typedef T type;
+};
+
+template <typename T, typename R, int K, int ST>
+__device__ __forceinline__ void ld_vec(const T* p, R inv, R (&v)[K]) {
+    using V = typename VecOf<T, K>::type;
+    const V x = *reinterpret_cast<const V*>(p);
+    if constexpr (K == 1) {
+        v[0] = Store<ST>::ld(&x, inv);
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const T e = x[j];
+            v[j] = Store<ST>::ld(&e, inv);
+        }
+    }
+}
+
+template <typename T, typename R, int K, int ST, bool NT>
+__device__ __forceinline__ void st_vec(T* p, R scl, const R (&v)[K]) {
+    using V = typename VecOf<T, K>::type;
+    V x;
+    if constexpr (K == 1) {
+        Store<ST>::st(&x, v[0], scl);
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            T e;
+            Store<ST>::st(&e, v[j], scl);
+            x[j] = e;
+        }
+    }
+    if constexpr (NT)
+        __builtin_nontemporal_store(x, reinterpret_cast<V*>(p));
+    else
+        *reinterpret_cast<V*>(p) = x;
+}
+
+template <int ST, int COLL, bool WALLS, int K, bool NT>
+__global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __restrict__ boxes,
+                                                             const BoxRT* __restrict__ rt, int bi,
+                                                             const typename Store<ST>::T* __restrict__ fin,
+                                                             typename Store<ST>::T* __restrict__ fout,
+                                                             KParams kp, int part,
+                                                             const uint32_t* __restrict__ nflags,
+                                                             const int* __restrict__ nlist,
+                                                             const int* __restrict__ ncount, uint32_t epoch) {
+#pragma clang fp contract(off)
+    using S = Store<ST>;
+    using T = typename S::T;
+    using R = typename S::R;
+    const BoxDesc& B = boxes[bi];
+    const int ny = B.ny, nz = B.nz, nx = 64 * K;
+    const int lane = threadIdx.x & 63;
+    int rb = blockIdx.x;
+    if (part == 2) {
+        if (rb >= *ncount) return;
+        rb = nlist[rb];
+    } else if (part == 1 && nflags[rb] == epoch) {
+        return;
+    }
+    const int row = rb * 4 + (threadIdx.x >> 6);
+    if (row >= ny * nz) return;
+    const int y = row % ny, z = row / ny;
+    const bool walls = WALLS && B.walls;
+    if (walls && (y == 0 || y == ny - 1)) return;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    const long long st = B.stride;
+    const T* fi = fin + B.foff;
+    const int x0 = K * lane;
+    const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
+    const int up = (lane + 63) & 63, dn = (lane + 1) & 63;
+    R f[K][NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int sy = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
+        const int sz = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
+        R v[K];
+        if (walls && cy(i) != 0 && (sy == 0 || sy == ny - 1)) {
+            const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
+            const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
+            ld_vec<T, R, K, ST>(fi + (long long)opp(i) * st + (long long)nx * (y + ny * z) + x0, inv, v);
+#pragma unroll
+            for (int j = 0; j < K; ++j) f[j][i] = v[j] + (R)(6.0 * wgt(i)) * rho0 * cu;
+            continue;
+        }
+        ld_vec<T, R, K, ST>(fi + (long long)i * st + (long long)nx * (sy + ny * sz) + x0, inv, v);
+        if (cx(i) == 1) {  // source x - 1
+            const R carry = __shfl(v[K - 1], up);
+#pragma unroll
+            for (int j = K - 1; j > 0; --j) v[j] = v[j - 1];
+            v[0] = carry;
+        } else if (cx(i) == -1) {  // source x + 1
+            const R carry = __shfl(v[0], dn);
+#pragma unroll
+            for (int j = 0; j < K - 1; ++j) v[j] = v[j + 1];
+            v[K - 1] = carry;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) f[j][i] = v[j];
+    }
+    R g0 = 0, g1 = 0, g2 = 0;
+    const bool cf = B.counterforce != 0;
+    if (cf) {  // uniform force density on all matter of the box (fluid and particles)
+        const double nall = (double)(B.n - B.n_wall);
+        g0 = (R)(-B.fext[0] / nall);
+        g1 = (R)(-B.fext[1] / nall);
+        g2 = (R)(-B.fext[2] / nall);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) collide<R, COLL>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
+    T* fo = fout + B.foff + (long long)nx * (y + ny * z) + x0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        R v[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = f[j][i];
+        st_vec<T, R, K, ST, NT>(fo + (long long)i * st, scl, v);
+    }
 }
 
 // Initial state: every slot holds the pre-collision population its reader
@@ -312,18 +458,43 @@ __global__ void k_poke(const BoxDesc* __restrict__ boxes, int bi, typename Store
     Store<ST>::st64(f + B.foff + (long long)dir * B.stride + slot, val, kp.scale);
 }
 
+// Plain device copy with 16-byte accesses, four per thread per iteration:
+// the achievable read+write bandwidth reference for the roofline, and the
+// known-size kernel that calibrates the HBM byte counters.
+__global__ __launch_bounds__(256) void k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                    size_t n16) {
+    const size_t stride = (size_t)gridDim.x * 256 * 4;
+    for (size_t i = ((size_t)blockIdx.x * 256 * 4) + threadIdx.x; i < n16; i += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + 256 * k < n16) v[k] = src[i + 256 * k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + 256 * k < n16) dst[i + 256 * k] = v[k];
+    }
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, bytes / 16);
+    return hipGetLastError();
+}
+
 // ------------------------------- launchers ----------------------------------
 
 template <int ST, int COLL>
 static hipError_t cs_walls(bool walls, const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
-    dim3 grid(a.ntiles), blk(TILE);
+    dim3 grid(a.part == 2 ? a.near_grid : a.ntiles), blk(TILE);
+    if (grid.x == 0) return hipSuccess;
     if (walls)
         hipLaunchKernelGGL((k_collide_stream<ST, COLL, true>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
-                           (const T*)a.fin, (T*)a.fout, a.kp);
+                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
+                           a.near_epoch);
     else
         hipLaunchKernelGGL((k_collide_stream<ST, COLL, false>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
-                           (const T*)a.fin, (T*)a.fout, a.kp);
+                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
+                           a.near_epoch);
     return hipGetLastError();
 }
 
@@ -336,7 +507,51 @@ static hipError_t cs_coll(const LaunchCS& a, hipStream_t st) {
     }
 }
 
+template <int ST, int COLL, int K, bool NT>
+static hipError_t rows_launch(bool walls, const LaunchCS& a, hipStream_t st) {
+    using T = typename Store<ST>::T;
+    const int rows = a.rows_ny * a.rows_nz;
+    dim3 grid(a.part == 2 ? a.near_grid : (rows + 3) / 4), blk(256);
+    if (grid.x == 0) return hipSuccess;
+    if (walls)
+        hipLaunchKernelGGL((k_collide_stream_rows<ST, COLL, true, K, NT>), grid, blk, 0, st, a.boxes, a.rt, 0,
+                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
+                           a.near_epoch);
+    else
+        hipLaunchKernelGGL((k_collide_stream_rows<ST, COLL, false, K, NT>), grid, blk, 0, st, a.boxes, a.rt, 0,
+                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
+                           a.near_epoch);
+    return hipGetLastError();
+}
+
+template <int ST, int COLL>
+static hipError_t rows_k(const LaunchCS& a, hipStream_t st) {
+    const bool nt = a.variant == 2;
+    switch (a.rows_k) {
+        case 1: return nt ? rows_launch<ST, COLL, 1, true>(a.walls, a, st) : rows_launch<ST, COLL, 1, false>(a.walls, a, st);
+        case 2: return nt ? rows_launch<ST, COLL, 2, true>(a.walls, a, st) : rows_launch<ST, COLL, 2, false>(a.walls, a, st);
+        default: return nt ? rows_launch<ST, COLL, 4, true>(a.walls, a, st) : rows_launch<ST, COLL, 4, false>(a.walls, a, st);
+    }
+}
+
+template <int ST>
+static hipError_t rows_coll(const LaunchCS& a, hipStream_t st) {
+    switch (a.kp.collision) {
+        case 0: return rows_k<ST, 0>(a, st);
+        case 1: return rows_k<ST, 1>(a, st);
+        default: return rows_k<ST, 2>(a, st);
+    }
+}
+
 hipError_t launch_collide_stream(const LaunchCS& a, hipStream_t st) {
+    if (a.variant != 0 && a.rows_k > 0) {
+        switch (a.kp.storage) {
+            case ST_F64: return rows_coll<ST_F64>(a, st);
+            case ST_F32: return rows_coll<ST_F32>(a, st);
+            case ST_F16: return rows_coll<ST_F16>(a, st);
+            default: return rows_coll<ST_BF16>(a, st);
+        }
+    }
     switch (a.kp.storage) {
         case ST_F64: return cs_coll<ST_F64>(a, st);
         case ST_F32: return cs_coll<ST_F32>(a, st);

@@ -4,6 +4,7 @@
 // read-back.  Host code only.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -18,13 +19,15 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int FIELDS_CHUNK = 1 << 18;  // sites per read-back chunk
-constexpr int MAX_LDS_WORDS = 11008;   // window bitmask budget (with the 18 KB stage, < 64 KB)
+constexpr int MAX_LDS_WORDS = 10240;   // window bitmask budget (40 KB; with the 16 KB stage < 64 KB)
+constexpr int NEAR_MARGIN = 2;         // nodes of the near set beyond each particle window
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
-           flags = 0, scratch = 0, total = 0;
+           flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, total = 0;
+    int near_blocks = 0;  // collide-stream blocks that a near set can name (per slot)
     std::vector<long long> foff, stride, ooff;
     std::vector<int> tile0, ntiles;
     long long pop_elems = 0, omap_elems = 0, link_pool = 0;
@@ -39,6 +42,7 @@ long long link_cap_for(double amax) {
 }
 
 int lds_words_for(double amax) {
+    // window edge <= 2 ceil(amax) + 6; one bit per window node, whole blocks of PBLOCK
     const int wn = 2 * (int)std::ceil(amax) + 7;
     const long long sites = (long long)wn * wn * wn;
     return (int)(((sites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32));
@@ -116,6 +120,10 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     L.links = take(sizeof(uint32_t) * L.link_pool);
     L.flags = take(sizeof(int) * 4);
     L.scratch = take(L.scratch_bytes);
+    L.near_blocks = std::max(tiles, (boxes[0].ny * boxes[0].nz + 3) / 4);
+    L.near_flags = take(sizeof(uint32_t) * 2 * L.near_blocks);
+    L.near_list = take(sizeof(int) * 2 * L.near_blocks);
+    L.near_count = take(sizeof(int) * 4);
     L.total = p;
     return L;
 }
@@ -142,6 +150,14 @@ struct lb_ctx {
     long long step = 0;
     KParams kp{};
     bool any_walls = false;
+    int k1_variant = 0;  // collide-stream variant in use (see LaunchCS)
+    int rows_k = 0;      // row-wave width, 0 when the box shape does not allow it
+    // second stream: particle phase concurrent with the far blocks (off by
+    // default: measured slower when the particle kernels' dependent loads
+    // queue behind the streaming kernel; LBELL_OVERLAP=1 turns it on)
+    bool overlap = false;
+    hipStream_t nstream = nullptr;
+    hipEvent_t evK = nullptr, evP = nullptr, evStart = nullptr;
     std::string err;
 
     template <typename T>
@@ -264,6 +280,8 @@ lb_status moments(lb_ctx* ctx, int box, double out[6]) {
     }
     return LB_OK;
 }
+
+lb_status near_rebuild(lb_ctx* ctx);
 
 }  // namespace
 
@@ -392,6 +410,29 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
         delete ctx;
         return LB_EDEVICE;
     }
+    // collide-stream variant: the row-wave kernel needs a single box whose x
+    // edge is 64, 128 or 256 sites
+    if (nboxes == 1 && (boxes[0].nx == 64 || boxes[0].nx == 128 || boxes[0].nx == 256)) {
+        ctx->rows_k = boxes[0].nx / 64;
+        ctx->k1_variant = 1;
+    }
+    if (const char* v = std::getenv("LBELL_K1_VARIANT")) ctx->k1_variant = std::atoi(v);
+    if (const char* v = std::getenv("LBELL_OVERLAP")) ctx->overlap = std::atoi(v) != 0;
+    {
+        hipError_t e2 = hipStreamCreateWithFlags(&ctx->nstream, hipStreamNonBlocking);
+        if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&ctx->evK, hipEventDisableTiming);
+        if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&ctx->evP, hipEventDisableTiming);
+        if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&ctx->evStart, hipEventDisableTiming);
+        if (e2 == hipSuccess)
+            e2 = hipMemsetAsync(ctx->arena + ctx->L.near_flags, 0, ctx->L.near_count + 4 * sizeof(int) - ctx->L.near_flags,
+                                ctx->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
+        if (e2 != hipSuccess) {
+            std::fprintf(stderr, "lb_init: %s\n", hipGetErrorString(e2));
+            lb_destroy(ctx);
+            return LB_EDEVICE;
+        }
+    }
     *out = ctx;
     return LB_OK;
 }
@@ -445,7 +486,7 @@ lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const d
     for (int k = 0; k < 3; ++k) h.axes[k] = semi_axes[k];
     ctx->np++;
     if (id) *id = pid;
-    return LB_OK;
+    return near_rebuild(ctx);
 }
 
 lb_status lb_set_external(lb_ctx* ctx, int id, const double F[3], const double T[3]) {
@@ -496,7 +537,7 @@ lb_status lb_set_particle_density(lb_ctx* ctx, int id, double rho_p) {
 }
 
 namespace {
-lb_status launch_collide(lb_ctx* ctx) {
+LaunchCS collide_args(lb_ctx* ctx, int variant) {
     LaunchCS cs{};
     cs.boxes = ctx->at<BoxDesc>(ctx->L.boxes);
     cs.rt = ctx->at<BoxRT>(ctx->L.rt);
@@ -506,28 +547,111 @@ lb_status launch_collide(lb_ctx* ctx) {
     cs.fout = ctx->fbuf(ctx->cur ^ 1);
     cs.kp = ctx->kp;
     cs.walls = ctx->any_walls;
-    HIPC(launch_collide_stream(cs, ctx->stream));
+    cs.variant = ctx->rows_k > 0 ? variant : 0;
+    cs.rows_k = ctx->rows_k;
+    cs.rows_ny = ctx->hbox[0].ny;
+    cs.rows_nz = ctx->hbox[0].nz;
+    cs.part = 0;
+    return cs;
+}
+
+// Near set of step t: slot t % 2, tagged with epoch t + 1.
+NearSet near_set(lb_ctx* ctx, long long t) {
+    NearSet ns{};
+    const int slot = (int)(t & 1);
+    ns.flags = ctx->at<uint32_t>(ctx->L.near_flags) + (size_t)slot * ctx->L.near_blocks;
+    ns.list = ctx->at<int>(ctx->L.near_list) + (size_t)slot * ctx->L.near_blocks;
+    ns.count = ctx->at<int>(ctx->L.near_count) + slot;
+    ns.epoch = (uint32_t)(t + 1);
+    ns.rows_geom = (ctx->rows_k > 0 && ctx->k1_variant != 0) ? 1 : 0;
+    ns.margin = NEAR_MARGIN;
+    return ns;
+}
+
+// Upper bound of the near-set size, the launch size of the near part.
+int near_grid(lb_ctx* ctx) {
+    const int R = 2 * (int)std::ceil(ctx->cfg.max_semi_axis) + 6 + 2 * NEAR_MARGIN;
+    const long long per = ctx->rows_k > 0 && ctx->k1_variant != 0 ? (long long)R * (R / 4 + 2)
+                                                                  : (long long)R * R * (R / TILE + 2);
+    return (int)std::min<long long>(ctx->L.near_blocks, per * std::max(ctx->np, 1));
+}
+
+lb_status launch_collide(lb_ctx* ctx) {
+    HIPC(launch_collide_stream(collide_args(ctx, ctx->k1_variant), ctx->stream));
     ctx->cur ^= 1;
     return LB_OK;
 }
 
-lb_status launch_particles(lb_ctx* ctx) {
+// Particle phase of the step whose collide-stream output is the current
+// buffer; also builds the near set of the next step from x(t + 1).
+lb_status launch_particles(lb_ctx* ctx, hipStream_t st) {
     if (ctx->np == 0) return LB_OK;
-    const LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
-    HIPC(launch_particle_solve(a, ctx->stream));
-    HIPC(launch_particle_remap(a, ctx->stream));
+    LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
+    a.near = near_set(ctx, ctx->step + 1);
+    HIPC(launch_particle_solve(a, st));
+    HIPC(launch_particle_remap(a, st));
     return LB_OK;
 }
+
+// Rebuilds the near set of the coming step from the current positions.
+// Both slots' tags are cleared first: a tag left from another step count (a
+// checkpoint load can move the counter back) must never match a new epoch.
+lb_status near_rebuild(lb_ctx* ctx) {
+    LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
+    a.near = near_set(ctx, ctx->step);
+    HIPC(hipMemsetAsync(ctx->arena + ctx->L.near_flags, 0, sizeof(uint32_t) * 2 * ctx->L.near_blocks, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->arena + ctx->L.near_count, 0, sizeof(int) * 4, ctx->stream));
+    HIPC(launch_near_mark(a, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return LB_OK;
+}
+
+// One step in two streams.  Caller's stream: near blocks, then far blocks.
+// Particle stream: after the near blocks, the particle phase of the same
+// step, concurrent with the far blocks.  The next step's near blocks wait for
+// the particle phase.  The near set of step t holds every block within a
+// margin of the particle windows at x(t) (built by the remap of step t - 1),
+// which covers all nodes the particle phase reads or writes at step t.
+lb_status step_overlapped(lb_ctx* ctx) {
+    LaunchCS far = collide_args(ctx, ctx->k1_variant), nr = far;
+    const NearSet ns = near_set(ctx, ctx->step);
+    far.part = 1;
+    nr.part = 2;
+    far.near_flags = nr.near_flags = ns.flags;
+    far.near_list = nr.near_list = ns.list;
+    far.near_count = nr.near_count = ns.count;
+    far.near_epoch = nr.near_epoch = ns.epoch;
+    nr.near_grid = near_grid(ctx);
+    HIPC(hipStreamWaitEvent(ctx->stream, ctx->evP, 0));
+    HIPC(launch_collide_stream(nr, ctx->stream));
+    HIPC(hipEventRecord(ctx->evK, ctx->stream));
+    HIPC(launch_collide_stream(far, ctx->stream));
+    HIPC(hipStreamWaitEvent(ctx->nstream, ctx->evK, 0));
+    ctx->cur ^= 1;
+    lb_status s = launch_particles(ctx, ctx->nstream);
+    if (s != LB_OK) return s;
+    HIPC(hipEventRecord(ctx->evP, ctx->nstream));
+    return LB_OK;
+}
+
 }  // namespace
 
 lb_status lb_step(lb_ctx* ctx, int n) {
     if (!ctx || n < 0) return LB_EINVAL;
+    if (n == 0) return LB_OK;
+    const bool ov = ctx->overlap && ctx->np > 0;
+    if (ov) {  // the particle stream starts after everything already on the caller's stream
+        HIPC(hipEventRecord(ctx->evStart, ctx->stream));
+        HIPC(hipStreamWaitEvent(ctx->nstream, ctx->evStart, 0));
+        HIPC(hipEventRecord(ctx->evP, ctx->stream));
+    }
     for (int k = 0; k < n; ++k) {
-        lb_status s = launch_collide(ctx);
-        if (s == LB_OK) s = launch_particles(ctx);
+        lb_status s = ov ? step_overlapped(ctx) : launch_collide(ctx);
+        if (s == LB_OK && !ov) s = launch_particles(ctx, ctx->stream);
         if (s != LB_OK) return s;
         ctx->step++;
     }
+    if (ov) HIPC(hipStreamWaitEvent(ctx->stream, ctx->evP, 0));  // join
     return LB_OK;
 }
 
@@ -540,7 +664,7 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
         HIPC(hipEventRecord(ev[3 * k], ctx->stream));
         s = launch_collide(ctx);
         HIPC(hipEventRecord(ev[3 * k + 1], ctx->stream));
-        if (s == LB_OK) s = launch_particles(ctx);
+        if (s == LB_OK) s = launch_particles(ctx, ctx->stream);
         HIPC(hipEventRecord(ev[3 * k + 2], ctx->stream));
         ctx->step++;
     }
@@ -557,6 +681,63 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
     if (ms_collide) *ms_collide = c;
     if (ms_particle) *ms_particle = p;
     return s;
+}
+
+lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best) {
+    if (!ctx || reps <= 0) return LB_EINVAL;
+    // The collide-stream kernel maps the current buffer to the other one and
+    // nothing else, so repeating it leaves the simulation state untouched.
+    const int nvar = ctx->rows_k > 0 ? 3 : 1;
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    int best = 0;
+    double tbest = 1e300;
+    for (int v = 0; v < nvar; ++v) {
+        const LaunchCS cs = collide_args(ctx, v);
+        HIPC(launch_collide_stream(cs, ctx->stream));  // warm-up
+        HIPC(hipEventRecord(e0, ctx->stream));
+        for (int r = 0; r < reps; ++r) HIPC(launch_collide_stream(cs, ctx->stream));
+        HIPC(hipEventRecord(e1, ctx->stream));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < tbest) {
+            tbest = ms / reps;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    const bool changed = ctx->k1_variant != best;
+    ctx->k1_variant = best;
+    if (variant) *variant = best;
+    if (ms_best) *ms_best = tbest;
+    return changed ? near_rebuild(ctx) : LB_OK;
+}
+
+lb_status lb_bandwidth_probe(void* dst, const void* src, size_t bytes, void* hip_stream, int reps, double* gbs) {
+    if (!dst || !src || bytes < 16 || (bytes % 16) != 0 || reps <= 0 || !gbs) return LB_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return LB_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return LB_EDEVICE;
+    const size_t per_block = (size_t)256 * 4 * 16;
+    const int blocks = (int)std::min<size_t>((size_t)cus * 16, (bytes + per_block - 1) / per_block);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB_EDEVICE;
+    bool ok = launch_copy_probe(src, dst, bytes, blocks, st) == hipSuccess;  // warm-up
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; r < reps && ok; ++r) ok = launch_copy_probe(src, dst, bytes, blocks, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!ok) return LB_EDEVICE;
+    *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return LB_OK;
 }
 
 lb_status lb_sync(lb_ctx* ctx) {
@@ -787,7 +968,7 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
         lb_status s = box_fext_update(ctx, b);
         if (s != LB_OK) return s;
     }
-    return LB_OK;
+    return near_rebuild(ctx);
 }
 
 lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value) {
@@ -802,6 +983,12 @@ lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value) {
 lb_status lb_destroy(lb_ctx* ctx) {
     if (!ctx) return LB_EINVAL;
     hipStreamSynchronize(ctx->stream);
+    if (ctx->nstream) {
+        hipStreamSynchronize(ctx->nstream);
+        hipStreamDestroy(ctx->nstream);
+    }
+    for (hipEvent_t e : {ctx->evK, ctx->evP, ctx->evStart})
+        if (e) hipEventDestroy(e);
     delete ctx;
     return LB_OK;
 }

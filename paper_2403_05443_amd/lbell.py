@@ -54,6 +54,8 @@ SIGNATURES = {
     "lb_set_particle_density": (C.c_int, [_VP, C.c_int, C.c_double]),
     "lb_step": (C.c_int, [_VP, C.c_int]),
     "lb_profile_step": (C.c_int, [_VP, C.c_int, _D, _D]),
+    "lb_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), _D]),
+    "lb_bandwidth_probe": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_int, _D]),
     "lb_sync": (C.c_int, [_VP]),
     "lb_get_force_torque": (C.c_int, [_VP, C.c_int, _D, _D]),
     "lb_get_particle": (C.c_int, [_VP, C.c_int, _D, _D, _D, _D]),
@@ -78,9 +80,14 @@ _lib = None
 
 
 def load():
-    """Load liblbell.so (built in-tree by __graft_entry__.build())."""
+    """Load liblbell.so (built in-tree by __graft_entry__.build()).
+
+    torch is imported first: its wheel carries its own HIP runtime, and the
+    library must bind to that same runtime (same soname) rather than bring a
+    second one into the process."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (load order: one HIP runtime per process)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         lib = C.CDLL(LIB_PATH)
@@ -110,6 +117,22 @@ def make_box(nx, ny, nz, walls=False, wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), init
         b.wall_hi[k] = float(wall_hi[k])
     b.init = {"rest": 0, "couette": 1}[init]
     return b
+
+
+def bandwidth_probe(nbytes=1 << 30, reps=10, device="cuda:0"):
+    """Achieved device copy bandwidth (read + write) in GB/s of the library's
+    16-byte-access copy kernel; buffers come from torch."""
+    import torch
+    lib = load()
+    nbytes = (int(nbytes) // 16) * 16
+    src = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    dst = torch.empty_like(src)
+    gbs = np.zeros(1)
+    st = lib.lb_bandwidth_probe(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), C.c_size_t(nbytes),
+                                C.c_void_p(torch.cuda.current_stream(device).cuda_stream), int(reps), _p(gbs))
+    if st != 0:
+        raise LBError(st, "bandwidth probe failed")
+    return gbs[0]
 
 
 class Lattice:
@@ -204,6 +227,12 @@ class Lattice:
         a, b = np.zeros(1), np.zeros(1)
         self._chk(self.lib.lb_profile_step(self.ctx, int(n), _p(a), _p(b)))
         return a[0], b[0]
+
+    def autotune(self, reps=20):
+        """Pick the fastest collide-stream variant; returns (variant, ms per launch)."""
+        v, ms = C.c_int(0), np.zeros(1)
+        self._chk(self.lib.lb_autotune(self.ctx, int(reps), C.byref(v), _p(ms)))
+        return v.value, ms[0]
 
     def sync(self):
         self._chk(self.lib.lb_sync(self.ctx))
