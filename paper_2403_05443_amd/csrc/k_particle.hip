@@ -103,16 +103,40 @@ __device__ __forceinline__ void squirmer_slip(double a, double b, const double e
     us[2] = k * (sa * e[2] + sr * rv2 * ir);
 }
 
+// Whole-wave sums with DPP row shifts and row broadcasts (plain VALU work, no
+// LDS traffic): row_shr 1, 2, 4, 8 give inclusive scans of each 16-lane row,
+// row_bcast 15 and 31 carry them across rows, so lane 63 ends with the total.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xf, true);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = dpp_i<CTRL, ROWMASK>(__double2loint(v));
+    const int hi = dpp_i<CTRL, ROWMASK>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wsum64(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_d<0x111, 0xf>(v);
+    v += dpp_d<0x112, 0xf>(v);
+    v += dpp_d<0x114, 0xf>(v);
+    v += dpp_d<0x118, 0xf>(v);
+    v += dpp_d<0x142, 0xa>(v);
+    v += dpp_d<0x143, 0xc>(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 __device__ __forceinline__ int wsumi(int v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_i<0x111, 0xf>(v);
+    v += dpp_i<0x112, 0xf>(v);
+    v += dpp_i<0x114, 0xf>(v);
+    v += dpp_i<0x118, 0xf>(v);
+    v += dpp_i<0x142, 0xa>(v);
+    v += dpp_i<0x143, 0xc>(v);
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
-// Deterministic block reduction of N doubles; result valid on thread 0.
+// Deterministic block reduction of N doubles; every thread gets the sums.
 template <int N>
 __device__ __forceinline__ void block_reduce(double (&v)[N], double (*red)[PWAVES]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -256,18 +280,22 @@ __device__ void mark_near(const NearSet& ns, const BoxDesc& B, const int wlo[3],
     }
 }
 
+struct SolveShm {
+    double red[12][PWAVES];
+    double bc[8];
+    double A[6][7];  // the 6x6 system, eliminated by thread 0
+};
+
+// Steps 3-7 for particle p whose record is staged in LDS (P).  The new state
+// goes to global memory; with keep_lds the LDS copy is updated as well.
 template <int ST>
-__global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
+__device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev& P, SolveShm& sh, bool keep_lds) {
     using S = Store<ST>;
     using T = typename S::T;
-    __shared__ PartDev P;
-    __shared__ double red[12][PWAVES];
-    __shared__ double bc[8];
-    __shared__ double A[6][7];  // the 6x6 system, eliminated by thread 0
-    const int p = a.first + (int)blockIdx.x;
+    double (*red)[PWAVES] = sh.red;
+    double* bc = sh.bc;
+    double (*A)[7] = sh.A;
     PartDev* Pg = a.parts + p;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.near.count) *a.near.count = 0;  // filled by the remap
-    stage_particle(Pg, &P);
     const BoxDesc& B = a.boxes[P.box];
     T* f = (T*)a.f + B.foff;
     const long long st = B.stride;
@@ -338,60 +366,90 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
     }
     block_reduce<12>(acc, red);
 
+    // steps 4-5: one lane per entry of [M + zFU, zFW; zTU, I' + dI/dt + zTW | rhs], with
+    // I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x (W = Omega(t))
+    const double M = P.M;
+    const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
+    if (tid < 42) {
+        const double Ib0 = P.Ib[0], Ib1 = P.Ib[1], Ib2 = P.Ib[2];
+        auto Il = [&](int i, int j) {
+            return Rm[i][0] * Ib0 * Rm[j][0] + Rm[i][1] * Ib1 * Rm[j][1] + Rm[i][2] * Ib2 * Rm[j][2];
+        };
+        auto Wx = [&](int i, int j) {
+            return i == j ? 0.0 : (i == 0 ? (j == 1 ? -W0[2] : W0[1]) : (i == 1 ? (j == 0 ? W0[2] : -W0[0])
+                                                                         : (j == 0 ? -W0[1] : W0[0])));
+        };
+        if (tid < 36) {
+            const int i = tid / 6, j = tid % 6;
+            double v = P.zeta[tid];
+            if (i == j && i < 3) v += M;
+            if (i >= 3 && j >= 3) {
+                const int ii = i - 3, jj = j - 3;
+                double d = 0;
+                for (int k = 0; k < 3; ++k) d += Wx(ii, k) * Il(k, jj) - Il(ii, k) * Wx(k, jj);
+                v += Il(ii, jj) + d;
+            }
+            A[i][j] = v;
+        } else {
+            const int i = tid - 36;
+            if (i < 3) {
+                // counter-force density on the particle's own nodes (box-wide g = -sum F_ext / N)
+                const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
+                A[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
+            } else {
+                const int ii = i - 3;
+                A[i][6] = (Il(ii, 0) * W0[0] + Il(ii, 1) * W0[1] + Il(ii, 2) * W0[2]) + acc[3 + ii] + acc[9 + ii] +
+                          P.Text[ii] + P.Lp[ii];
+            }
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
-        // step 4: I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x with W = Omega(t)
-        const double M = P.M;
-        const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
-        double Il[3][3], Id[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j)
-                Il[i][j] = Rm[i][0] * P.Ib[0] * Rm[j][0] + Rm[i][1] * P.Ib[1] * Rm[j][1] + Rm[i][2] * P.Ib[2] * Rm[j][2];
-        const double Wx[3][3] = {{0, -W0[2], W0[1]}, {W0[2], 0, -W0[0]}, {-W0[1], W0[0], 0}};
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                double sum = 0;
-                for (int k = 0; k < 3; ++k) sum += Wx[i][k] * Il[k][j] - Il[i][k] * Wx[k][j];
-                Id[i][j] = sum;
-            }
-        // step 5: [M + zFU, zFW; zTU, I' + dI/dt + zTW] [U'; W'] = [M U + F0 + ...; I' W + T0 + ...]
+        // Gaussian elimination with partial pivoting in registers (every
+        // index is a compile-time constant; row swaps are selects)
+        double R[6][7];
+#pragma unroll
         for (int i = 0; i < 6; ++i)
-            for (int j = 0; j < 6; ++j) A[i][j] = P.zeta[6 * i + j];
-        for (int i = 0; i < 3; ++i) {
-            A[i][i] += M;
-            for (int j = 0; j < 3; ++j) A[3 + i][3 + j] += Il[i][j] + Id[i][j];
-            // counter-force density on the particle's own nodes (box-wide g = -sum F_ext / N)
-            const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
-            A[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
-            A[3 + i][6] = (Il[i][0] * W0[0] + Il[i][1] * W0[1] + Il[i][2] * W0[2]) + acc[3 + i] + acc[9 + i] +
-                          P.Text[i] + P.Lp[i];
-        }
+#pragma unroll
+            for (int c = 0; c < 7; ++c) R[i][c] = A[i][c];
         bool ok = true;
-        for (int k = 0; k < 6; ++k) {  // Gaussian elimination, partial pivoting
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
             int pv = k;
+            double best = fabs(R[k][k]);
+#pragma unroll
             for (int r = k + 1; r < 6; ++r)
-                if (fabs(A[r][k]) > fabs(A[pv][k])) pv = r;
-            if (!(fabs(A[pv][k]) > 1e-300)) {
-                ok = false;
-                break;
-            }
-            if (pv != k)
-                for (int c = 0; c < 7; ++c) {
-                    const double tmp = A[k][c];
-                    A[k][c] = A[pv][c];
-                    A[pv][c] = tmp;
+                if (fabs(R[r][k]) > best) {
+                    best = fabs(R[r][k]);
+                    pv = r;
                 }
+            ok = ok && best > 1e-300;
+#pragma unroll
             for (int r = k + 1; r < 6; ++r) {
-                const double m = A[r][k] / A[k][k];
-                for (int c = k; c < 7; ++c) A[r][c] -= m * A[k][c];
+                const bool sw = pv == r;
+#pragma unroll
+                for (int c = k; c < 7; ++c) {
+                    const double t = R[k][c];
+                    R[k][c] = sw ? R[r][c] : t;
+                    R[r][c] = sw ? t : R[r][c];
+                }
+            }
+#pragma unroll
+            for (int r = k + 1; r < 6; ++r) {
+                const double m = R[r][k] / R[k][k];
+#pragma unroll
+                for (int c = k; c < 7; ++c) R[r][c] -= m * R[k][c];
             }
         }
-        double sol[6] = {0, 0, 0, 0, 0, 0};
-        if (ok)
-            for (int r = 5; r >= 0; --r) {
-                double sum = A[r][6];
-                for (int c = r + 1; c < 6; ++c) sum -= A[r][c] * sol[c];
-                sol[r] = sum / A[r][r];
-            }
+        double sol[6];
+#pragma unroll
+        for (int r = 5; r >= 0; --r) {
+            double sum = R[r][6];
+#pragma unroll
+            for (int c = r + 1; c < 6; ++c) sum -= R[r][c] * sol[c];
+            sol[r] = sum / R[r][r];
+        }
+        {
         bool bad = !ok;
         for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
         {  // surface speed |U| + |Omega| max(a,b,c) must stay below half a node per step
@@ -442,6 +500,19 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
             Pg->q[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
         }
         Pg->dm = 0.0;
+        if (keep_lds) {  // the remap that follows in the same work-group reads the new state here
+            for (int i = 0; i < 3; ++i) {
+                P.xc[i] = Pg->xc[i];
+                P.xu[i] = Pg->xu[i];
+                P.U[i] = sol[i];
+                P.W[i] = sol[3 + i];
+                P.Pp[i] = 0.0;
+                P.Lp[i] = 0.0;
+            }
+            for (int k = 0; k < 4; ++k) P.q[k] = Pg->q[k];
+            P.dm = 0.0;
+        }
+        }
     }
     __syncthreads();
 
@@ -477,20 +548,31 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
 }
 
 template <int ST>
-__global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
+__global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
+    __shared__ PartDev P;
+    __shared__ SolveShm sh;
+    const int p = a.first + (int)blockIdx.x;
+    stage_particle(a.parts + p, &P);
+    solve_phase<ST>(a, p, P, sh, false);
+}
+
+struct RemapShm {
+    double red[22][PWAVES];
+    int wtot[PWAVES];
+    int ired[8][PWAVES];
+};
+
+// Steps 8-9 for particle p with its (new) state staged in LDS (P).
+template <int ST>
+__device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const PartDev& P, RemapShm& sh, uint32_t* smem) {
     using S = Store<ST>;
     using T = typename S::T;
-    extern __shared__ uint32_t smem[];
     uint32_t* bits = smem;
     uint32_t* stage = smem + a.lds_words;
-    __shared__ PartDev P;
-    __shared__ double red[22][PWAVES];
-    __shared__ int wtot[PWAVES];
-    __shared__ int ired[8][PWAVES];
-
-    const int p = a.first + (int)blockIdx.x;
+    double (*red)[PWAVES] = sh.red;
+    int* wtot = sh.wtot;
+    int (*ired)[PWAVES] = sh.ired;
     PartDev* Pg = a.parts + p;
-    stage_particle(Pg, &P);
     const int bi = P.box;
     const BoxDesc& B = a.boxes[bi];
     T* f = (T*)a.f + B.foff;
@@ -718,35 +800,71 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
         if (lane == 0) ired[k][wv] = sm;
     }
     __syncthreads();
-    if (tid == 0) {
-        int tot[8];
-        for (int k = 0; k < 8; ++k) {
-            tot[k] = 0;
-            for (int w = 0; w < PWAVES; ++w) tot[k] += ired[k][w];
+    // one lane per output: zeta_FU = (2 rho0 / c_s^2) sum w c c = rho0 (integer sum of 36 w c c) / 6,
+    // the other blocks from the FP64 sums
+    auto itot = [&](int k) {
+        int t = 0;
+        for (int w = 0; w < PWAVES; ++w) t += ired[k][w];
+        return t;
+    };
+    if (tid < 36) {
+        const int i = tid / 6, j = tid % 6;
+        double z;
+        if (i < 3 && j < 3) {
+            const int lo_ = i < j ? i : j, hi_ = i < j ? j : i;  // upper-triangle index of (i, j)
+            z = rho0 * itot(lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5)) / 6.0;
+        } else if (i < 3) {
+            z = rho0 * red[7 + 3 * i + (j - 3)][0] / 6.0;
+        } else if (j < 3) {
+            z = rho0 * red[7 + 3 * j + (i - 3)][0] / 6.0;
+        } else {
+            const int ii = i - 3, jj = j - 3, lo_ = ii < jj ? ii : jj, hi_ = ii < jj ? jj : ii;
+            z = rho0 * red[16 + (lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5))][0] / 6.0;
         }
-        // zeta_FU = (2 rho0 / c_s^2) sum w c c = rho0 * (integer sum of 36 w c c) / 6
-        const int fu[3][3] = {{tot[0], tot[1], tot[2]}, {tot[1], tot[3], tot[4]}, {tot[2], tot[4], tot[5]}};
-        const double tw[3][3] = {{all[16], all[17], all[18]}, {all[17], all[19], all[20]}, {all[18], all[20], all[21]}};
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                Pg->zeta[6 * i + j] = rho0 * fu[i][j] / 6.0;
-                Pg->zeta[6 * i + 3 + j] = rho0 * all[7 + 3 * i + j] / 6.0;
-                Pg->zeta[6 * (3 + i) + j] = rho0 * all[7 + 3 * j + i] / 6.0;
-                Pg->zeta[6 * (3 + i) + 3 + j] = rho0 * tw[i][j] / 6.0;
-            }
-        Pg->wsum = tot[6] / 36.0;
+        Pg->zeta[tid] = z;
+    } else if (tid == 36) {
+        Pg->wsum = itot(6) / 36.0;
         Pg->nlinks = running < lcap ? running : lcap;
-        if (mode == 0) {
-            Pg->dm = P.dm + all[0];
-            for (int k = 0; k < 3; ++k) {
-                Pg->Pp[k] = P.Pp[k] + all[1 + k];
-                Pg->Lp[k] = P.Lp[k] + all[4 + k];
-            }
-        }
-        if (tot[7] != P.n_solid) atomicAdd(&a.rt[bi].n_solid, tot[7] - P.n_solid);
-        Pg->n_solid = tot[7];
+    } else if (tid >= 37 && tid < 44 && mode == 0) {
+        const int k = tid - 37;  // dm, Pp[3], Lp[3]
+        const double v = red[k][0];  // the block totals stay in LDS after the reduction
+        if (k == 0) Pg->dm = P.dm + v;
+        else if (k < 4) Pg->Pp[k - 1] = P.Pp[k - 1] + v;
+        else Pg->Lp[k - 4] = P.Lp[k - 4] + v;
+    } else if (tid == 44) {
+        const int ns = itot(7);
+        if (ns != P.n_solid) atomicAdd(&a.rt[bi].n_solid, ns - P.n_solid);
+        Pg->n_solid = ns;
     }
     if (mode == 0 && a.near.flags) mark_near(a.near, B, lo, wn);
+}
+
+template <int ST>
+__global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
+    extern __shared__ uint32_t smem[];
+    __shared__ PartDev P;
+    __shared__ RemapShm sh;
+    const int p = a.first + (int)blockIdx.x;
+    stage_particle(a.parts + p, &P);
+    remap_phase<ST>(a, p, P, sh, smem);
+}
+
+// Steps 3-9 in one work-group, for boxes that hold one particle: the record
+// is staged once, and the remap reads the bounce-back writes of its own
+// work-group (no other particle writes this box).
+template <int ST>
+__global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
+    extern __shared__ uint32_t smem[];
+    __shared__ PartDev P;
+    __shared__ union {
+        SolveShm s;
+        RemapShm r;
+    } sh;
+    const int p = a.first + (int)blockIdx.x;
+    stage_particle(a.parts + p, &P);
+    solve_phase<ST>(a, p, P, sh.s, true);
+    __syncthreads();  // bounce-back writes before the covered-node reads of the remap
+    remap_phase<ST>(a, p, P, sh.r, smem);
 }
 
 // Near set from the particles' current positions (set-up and re-tuning).
@@ -786,6 +904,18 @@ template <int ST>
 static hipError_t remap_one(const LaunchPart& a, hipStream_t st) {
     const size_t lds = particle_remap_lds_bytes(a.lds_words);
     hipLaunchKernelGGL(k_particle_remap<ST>, dim3(a.count), dim3(PBLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_particle_step(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    const size_t lds = particle_remap_lds_bytes(a.lds_words);
+    switch (a.kp.storage) {
+        case ST_F64: hipLaunchKernelGGL(k_particle_step<ST_F64>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        case ST_F32: hipLaunchKernelGGL(k_particle_step<ST_F32>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        case ST_F16: hipLaunchKernelGGL(k_particle_step<ST_F16>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        default: hipLaunchKernelGGL(k_particle_step<ST_BF16>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -142,9 +142,11 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
                                                          typename Store<ST>::T* __restrict__ fout,
                                                          KParams kp, int part, const uint32_t* __restrict__ nflags,
                                                          const int* __restrict__ nlist,
-                                                         const int* __restrict__ ncount, uint32_t epoch) {
+                                                         const int* __restrict__ ncount, uint32_t epoch,
+                                                         int* __restrict__ next_count) {
     using S = Store<ST>;
     using R = typename S::R;
+    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     int tile = blockIdx.x;
     if (part == 2) {
         if (tile >= *ncount) return;
@@ -234,11 +236,13 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
                                                              KParams kp, int part,
                                                              const uint32_t* __restrict__ nflags,
                                                              const int* __restrict__ nlist,
-                                                             const int* __restrict__ ncount, uint32_t epoch) {
+                                                             const int* __restrict__ ncount, uint32_t epoch,
+                                                             int* __restrict__ next_count) {
 #pragma clang fp contract(off)
     using S = Store<ST>;
     using T = typename S::T;
     using R = typename S::R;
+    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     const BoxDesc& B = boxes[bi];
     const int ny = B.ny, nz = B.nz, nx = 64 * K;
     const int lane = threadIdx.x & 63;
@@ -490,11 +494,11 @@ static hipError_t cs_walls(bool walls, const LaunchCS& a, hipStream_t st) {
     if (walls)
         hipLaunchKernelGGL((k_collide_stream<ST, COLL, true>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
                            (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch);
+                           a.near_epoch, a.next_count);
     else
         hipLaunchKernelGGL((k_collide_stream<ST, COLL, false>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
                            (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch);
+                           a.near_epoch, a.next_count);
     return hipGetLastError();
 }
 
@@ -516,11 +520,11 @@ static hipError_t rows_launch(bool walls, const LaunchCS& a, hipStream_t st) {
     if (walls)
         hipLaunchKernelGGL((k_collide_stream_rows<ST, COLL, true, K, NT>), grid, blk, 0, st, a.boxes, a.rt, 0,
                            (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch);
+                           a.near_epoch, a.next_count);
     else
         hipLaunchKernelGGL((k_collide_stream_rows<ST, COLL, false, K, NT>), grid, blk, 0, st, a.boxes, a.rt, 0,
                            (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch);
+                           a.near_epoch, a.next_count);
     return hipGetLastError();
 }
 

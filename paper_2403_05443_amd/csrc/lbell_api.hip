@@ -156,6 +156,7 @@ struct lb_ctx {
     // default: measured slower when the particle kernels' dependent loads
     // queue behind the streaming kernel; LBELL_OVERLAP=1 turns it on)
     bool overlap = false;
+    bool fused = true;  // one particle kernel per step when no box holds two particles (LBELL_FUSED=0: two kernels)
     hipStream_t nstream = nullptr;
     hipEvent_t evK = nullptr, evP = nullptr, evStart = nullptr;
     std::string err;
@@ -418,6 +419,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
     }
     if (const char* v = std::getenv("LBELL_K1_VARIANT")) ctx->k1_variant = std::atoi(v);
     if (const char* v = std::getenv("LBELL_OVERLAP")) ctx->overlap = std::atoi(v) != 0;
+    if (const char* v = std::getenv("LBELL_FUSED")) ctx->fused = std::atoi(v) != 0;
     {
         hipError_t e2 = hipStreamCreateWithFlags(&ctx->nstream, hipStreamNonBlocking);
         if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&ctx->evK, hipEventDisableTiming);
@@ -577,19 +579,36 @@ int near_grid(lb_ctx* ctx) {
 }
 
 lb_status launch_collide(lb_ctx* ctx) {
-    HIPC(launch_collide_stream(collide_args(ctx, ctx->k1_variant), ctx->stream));
+    LaunchCS cs = collide_args(ctx, ctx->k1_variant);
+    cs.next_count = ctx->np > 0 ? near_set(ctx, ctx->step + 1).count : nullptr;
+    HIPC(launch_collide_stream(cs, ctx->stream));
     ctx->cur ^= 1;
     return LB_OK;
 }
 
 // Particle phase of the step whose collide-stream output is the current
 // buffer; also builds the near set of the next step from x(t + 1).
+bool one_particle_per_box(lb_ctx* ctx) {
+    std::vector<int> cnt(ctx->boxes.size(), 0);
+    for (int p = 0; p < ctx->np; ++p)
+        if (++cnt[ctx->hpart[p].box] > 1) return false;
+    return true;
+}
+
 lb_status launch_particles(lb_ctx* ctx, hipStream_t st) {
     if (ctx->np == 0) return LB_OK;
     LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
     a.near = near_set(ctx, ctx->step + 1);
-    HIPC(launch_particle_solve(a, st));
-    HIPC(launch_particle_remap(a, st));
+    if (ctx->fused && one_particle_per_box(ctx)) {
+        // a box with one particle has no other writer, so solve and remap
+        // can share a work-group
+        HIPC(launch_particle_step(a, st));
+    } else {
+        // the kernel boundary orders every particle's bounce-back before any
+        // particle's covered-node reads
+        HIPC(launch_particle_solve(a, st));
+        HIPC(launch_particle_remap(a, st));
+    }
     return LB_OK;
 }
 
@@ -622,6 +641,7 @@ lb_status step_overlapped(lb_ctx* ctx) {
     far.near_count = nr.near_count = ns.count;
     far.near_epoch = nr.near_epoch = ns.epoch;
     nr.near_grid = near_grid(ctx);
+    nr.next_count = near_set(ctx, ctx->step + 1).count;  // emptied before the particle phase fills it
     HIPC(hipStreamWaitEvent(ctx->stream, ctx->evP, 0));
     HIPC(launch_collide_stream(nr, ctx->stream));
     HIPC(hipEventRecord(ctx->evK, ctx->stream));

@@ -10,7 +10,7 @@ constexpr int NQ = 19;
 constexpr int TILE = 256;        // sites per K1 work-group
 constexpr int PBLOCK = 512;      // threads per particle work-group
 constexpr int PWAVES = PBLOCK / 64;
-constexpr int KREG = 4;          // links per thread held in registers across phases
+constexpr int KREG = 2;          // links per thread held in registers across phases
 constexpr int STAGE = 4096;      // link codes staged in LDS per copy-out round
 constexpr int SITE_BITS = 27;    // link code: site | dir << 27
 constexpr uint32_t SITE_MASK = (1u << SITE_BITS) - 1u;

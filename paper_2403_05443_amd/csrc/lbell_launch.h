@@ -22,6 +22,7 @@ struct LaunchCS {
     const int* near_count;
     uint32_t near_epoch;    // a block is near iff its flag equals this step's epoch
     int near_grid;          // launch size of the near part (an upper bound of the set's size)
+    int* next_count;        // block 0 empties the next step's near list (it is filled by the particle phase)
 };
 
 // The near set: collide-stream blocks within a margin of some particle's
@@ -58,11 +59,12 @@ struct LaunchPart {
     KParams kp;
     int lds_words;    // 32-bit words of the remap window bitmask
     int mode;         // remap: 0 step, 1 add (no transitions), 2 remove
-    NearSet near;     // set of the next step: solve empties it, remap (mode 0) fills it
+    NearSet near;     // set of the next step: the preceding collide launch empties it, remap (mode 0) fills it
 };
 
 hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st);
 hipError_t launch_particle_remap(const LaunchPart& a, hipStream_t st);
+hipError_t launch_particle_step(const LaunchPart& a, hipStream_t st);  // solve + remap, one particle per box
 size_t particle_remap_lds_bytes(int lds_words);
 hipError_t launch_near_mark(const LaunchPart& a, hipStream_t st);
 

@@ -480,3 +480,27 @@ def test_checkpoint_reload_into_advanced_context(lb):
     for k, v in a.particle(pa).items():
         assert np.array_equal(v, b.particle(pb)[k]), k
     assert np.array_equal(a.fields()[1], b.fields()[1])
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_fused_particle_kernel_matches_two_kernels(lb, storage):
+    """One work-group doing solve + remap (boxes with one particle) gives the
+    same bits as the two-kernel path."""
+    runs = []
+    for fused in ("1", "0"):
+        os.environ["LBELL_FUSED"] = fused
+        try:
+            g, ids = _moving_lattice(lb, 0, (20, 18, 22), storage, nboxes=2)
+        finally:
+            del os.environ["LBELL_FUSED"]
+        g.step(60)
+        runs.append((g, ids))
+    (a, ia), (b, ib) = runs
+    for pa, pb in zip(ia, ib):
+        for k, v in a.particle(pa).items():
+            assert np.array_equal(v, b.particle(pb)[k]), k
+        Fa, Ta = a.force_torque(pa)
+        Fb, Tb = b.force_torque(pb)
+        assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb)
+    for bx in range(2):
+        assert np.array_equal(a.fields(bx)[1], b.fields(bx)[1])
