@@ -44,14 +44,15 @@ def build_lattice(W, device="cuda:0"):
     return lat
 
 
-def traffic_record(src_sha, workload, storage):
+def traffic_record(src_sha, workload, storage, variant):
     """HBM bytes per collide-stream launch from the committed counter
-    summary, only if it was taken on this kernel source and workload."""
+    summary, only if it was taken on this kernel source, workload and
+    variant."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    key = f"{workload}/{storage}"
+    key = f"{workload}/{storage}/v{variant}"
     ent = rec.get("entries", {}).get(key)
     if not ent or rec.get("source_sha256") != src_sha:
         return None
@@ -92,7 +93,7 @@ def _pmc_rows(d):
     return out
 
 
-def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes):
+def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes, variant):
     """HBM bytes per collide-stream launch from FETCH_SIZE and WRITE_SIZE (KiB
     per dispatch), each scaled by what the same counter reads for the copy
     probe of known size."""
@@ -102,12 +103,16 @@ def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes):
     for name, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _pmc_rows(d)
         probe = [v for k, v in rows if "k_copy_probe" in k]
-        k1 = [v for k, v in rows if "collide_stream" in k]
-        if not probe or not k1:
+        names = [k for k, _ in rows if "collide_stream" in k]
+        if not probe or not names:
             raise SystemExit(f"no copy-probe / collide-stream dispatches under {d}")
+        # the variant the tuner kept is the one launched in the timed steps: the most frequent
+        kname = max(set(names), key=names.count)
+        k1 = [v for k, v in rows if k == kname]
         probe_kib = sorted(probe)[len(probe) // 2]
         scale = probe_bytes / (probe_kib * 1024.0)
-        res[name] = {"counter_kib_per_launch": sum(k1) / len(k1), "probe_kib": probe_kib, "scale": scale,
+        res[name] = {"kernel": kname, "launches": len(k1),
+                     "counter_kib_per_launch": sum(k1) / len(k1), "probe_kib": probe_kib, "scale": scale,
                      "bytes_per_launch": sum(k1) / len(k1) * 1024.0 * scale}
     src_sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     try:
@@ -118,14 +123,54 @@ def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes):
         rec = {}
     rec["source_sha256"] = src_sha
     rec["kernel"] = "k_collide_stream / k_collide_stream_rows"
-    rec.setdefault("entries", {})[f"{W.name}/{storage}"] = {
+    rec.setdefault("entries", {})[f"{W.name}/{storage}/v{variant}"] = {
         "fetch": res["fetch"], "write": res["write"],
         "algorithmic_bytes_per_launch": 38 * BYTES[storage] * W.sites,
         "traffic_bytes_per_launch": round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]),
     }
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
-    print(json.dumps(rec["entries"][f"{W.name}/{storage}"]))
+    print(json.dumps(rec["entries"][f"{W.name}/{storage}/v{variant}"]))
+
+
+def measure(W, steps, warmup, graph_steps, variant=None, psteps=200):
+    """Times `steps` steps of workload W after `warmup` steps (collide-stream
+    variant from the tuner unless given); returns the lattice and a dict of
+    the measured figures."""
+    import torch
+    if variant is not None:
+        os.environ["LBELL_K1_VARIANT"] = str(variant)
+    try:
+        lat = build_lattice(W)
+    finally:
+        os.environ.pop("LBELL_K1_VARIANT", None)
+    if variant is None:
+        variant = lat.autotune(10)[0]
+    lat.set_graph(graph_steps)
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    lat.sync()
+    # collide-stream launch duration inside real steps: HIP events on the
+    # library's stream around every launch (each launch reads the buffer the
+    # step before wrote, as in the timed run)
+    n = min(steps, psteps)
+    ms_c, ms_p = lat.profile_step(n)
+    k1 = ms_c / n
+    alg = 38 * BYTES[W.storage] * W.sites
+    return lat, {
+        "mlups": W.sites * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps, "wall_s": wall,
+        "variant": variant, "k1_ms": k1, "alg_bytes": alg, "achieved_gbs": alg / (k1 / 1e3) / 1e9,
+        "phase_ms": {"collide_stream": ms_c / n, "particle": ms_p / n},
+    }
 
 
 def main():
@@ -135,6 +180,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="fp32", choices=sorted(BYTES))
     ap.add_argument("--size", type=int, default=128, help="box edge of the inclined-spheroid workload")
+    ap.add_argument("--graph", type=int, default=50, help="steps per HIP graph replay (0: plain launches)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="collide-stream variant to use instead of the tuner's choice (see lb_autotune)")
+    ap.add_argument("--ensemble-steps", type=int, default=200,
+                    help="steps of the 256-box FP16 ensemble reported beside the main line (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30,
@@ -144,66 +194,58 @@ def main():
                          "profiles/collide_stream_traffic.json and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc, storage=args.storage, size=args.size, probe_bytes=args.probe_bytes)
+        if args.variant is None:
+            raise SystemExit("--summarize-pmc needs the --variant the counter runs used")
+        summarize_pmc(*args.summarize_pmc, storage=args.storage, size=args.size, probe_bytes=args.probe_bytes,
+                      variant=args.variant)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from paper_2403_05443_amd import workloads
     from paper_2403_05443_amd import lbell
+    lbell.load()
     W = workloads.c2(args.storage, args.size)
-    lat = build_lattice(W)
-    N = W.sites
-    variant, _ = lat.autotune(10)
     copy_gbs = lbell.bandwidth_probe(args.probe_bytes, reps=5)
-    lat.step(args.warmup)
-    lat.sync()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    lat.step(args.steps)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    lat.sync()
-    mlups = N * args.steps / (ms / 1e3) / 1e6
-
-    # per-kernel durations from HIP events on the library's stream
-    psteps = min(args.steps, 500)
-    ms_c, ms_p = lat.profile_step(psteps)
-    k1 = ms_c / psteps
-    alg_bytes = 38 * BYTES[args.storage] * N
-    achieved = alg_bytes / (k1 / 1e3) / 1e9
+    lat, m = measure(W, args.steps, args.warmup, args.graph, variant=args.variant)
+    del lat
     src_sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    traffic = traffic_record(src_sha, W.name, args.storage)
+    traffic = traffic_record(src_sha, W.name, args.storage, m["variant"])
     out = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": round(m["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
+        "ms_per_step": round(m["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": W.name, "sites": N, "storage": args.storage, "collision": "trt",
+        "config": {"workload": W.name, "sites": W.sites, "storage": args.storage, "collision": "trt",
                    "tau_plus": W.tau, "lambda": W.magic, "particles": len(W.particles),
-                   "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_collide_stream", "variant": variant, "bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(k1, 5), "copy_probe_gbs": round(copy_gbs, 1)},
-        "phase_ms_per_step": {"collide_stream": round(k1, 5), "particle": round(ms_p / psteps, 5)},
-        "wall_s": round(wall, 3),
+                   "graph_steps": args.graph, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(m["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_collide_stream", "variant": m["variant"], "bytes_per_launch": m["alg_bytes"],
+                     "avg_launch_ms": round(m["k1_ms"], 5), "copy_probe_gbs": round(copy_gbs, 1)},
+        "phase_ms_per_step": {k: round(v, 5) for k, v in m["phase_ms"].items()},
+        "wall_s": round(m["wall_s"], 3),
     }
+    if args.ensemble_steps > 0:
+        We = workloads.c4("fp16")
+        lat, e = measure(We, args.ensemble_steps, 20, args.graph)
+        del lat
+        out["ensemble"] = {"workload": We.name, "boxes": len(We.boxes), "sites": We.sites, "storage": "fp16",
+                           "mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 4),
+                           "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 4),
+                           "k1_achieved_gbs": round(e["achieved_gbs"], 1),
+                           "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                           "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -155,19 +155,39 @@ lb_status lb_set_particle_density(lb_ctx* ctx, int id, double rho_p);
  * the next synchronising call. */
 lb_status lb_step(lb_ctx* ctx, int n);
 
-/* Runs n steps exactly as lb_step does, recording HIP events on the stream
- * around the collide-stream launch and around the particle phase of every
- * step; *ms_collide and *ms_particle receive the summed GPU durations in
+/* Runs n steps exactly as lb_step does (plain launches), timing each
+ * collide-stream launch with HIP events bound to the kernel's own start and
+ * end, and each particle phase with events recorded on the stream around its
+ * launches; *ms_collide and *ms_particle receive the summed GPU durations in
  * milliseconds (either may be NULL).  Synchronises. */
 lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_particle);
 
-/* Tuner: times every applicable collide-stream variant (generic tiles; the
- * row-wave kernel for a single box with nx = 64, 128 or 256; the same with
- * non-temporal stores) over `reps` launches each and keeps the fastest for
- * this context.  The timing launches map the current populations to the
- * spare buffer only, so the simulation state is unchanged.  *variant and
- * *ms_best (milliseconds per launch) may be NULL.  Synchronises. */
+/* Tuner: times every applicable collide-stream variant inside `reps` real
+ * time steps each (after one warm-up step per variant) and keeps the fastest
+ * for this context.  Variants:
+ *   0  generic 256-site tiles, one block per tile
+ *   1  row-wave kernel (single box with nx = 64, 128 or 256)
+ *   2  row-wave kernel with non-temporal stores (same condition)
+ *   3  generic tiles, XCD-chunked block order
+ *   4  generic, two tiles per block          5  the same, XCD-chunked
+ *   6  generic, XCD-chunked persistent grid (8 blocks per compute unit)
+ *   7  the same with two tiles per block
+ * With the two-stream schedule only 0-2 apply.  All variants give identical
+ * bits, so the (applicable variants) x (reps + 1) steps the tuner takes are
+ * ordinary steps of the simulation: the step counter advances by that many.
+ * *variant and *ms_best (milliseconds per collide-stream launch, HIP events
+ * around each launch) may be NULL.  Synchronises. */
 lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best);
+
+/* Graph replay.  With steps > 0, lb_step runs whole groups of `steps` time
+ * steps as one HIP graph launch each (the kernels of the group are captured
+ * on first use, on a private stream, and replayed on the context's stream;
+ * a capture is redone when the particle count, the collide-stream variant or
+ * the buffer parity differs from the captured one) and the remainder as
+ * plain launches.  The captured kernels clear what they need themselves (no
+ * memset nodes).  steps = 0 (the default) launches every kernel directly.
+ * LB_ESTATE with the two-stream schedule; LB_EINVAL for steps < 0. */
+lb_status lb_set_graph(lb_ctx* ctx, int steps);
 
 /* Bandwidth reference: copies `bytes` (a multiple of 16, both pointers
  * 16-byte aligned device memory owned by the caller) from src to dst `reps`

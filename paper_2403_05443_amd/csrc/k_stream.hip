@@ -11,6 +11,10 @@
 // needs no node map.  Moving walls (Sec. III.C set-up) are handled here: a
 // pull from a wall row is replaced by the reflected own population plus the
 // moving-boundary term of eq. fb.
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+
 #include "lbell_dev.h"
 #include "lbell_launch.h"
 
@@ -134,26 +138,13 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
     }
 }
 
+// One site of the generic tile kernel: pull, collide, store.
 template <int ST, int COLL, bool WALLS>
-__global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restrict__ boxes,
-                                                         const BoxRT* __restrict__ rt,
-                                                         const int* __restrict__ tile_box,
-                                                         const typename Store<ST>::T* __restrict__ fin,
-                                                         typename Store<ST>::T* __restrict__ fout,
-                                                         KParams kp, int part, const uint32_t* __restrict__ nflags,
-                                                         const int* __restrict__ nlist,
-                                                         const int* __restrict__ ncount, uint32_t epoch,
-                                                         int* __restrict__ next_count) {
+__device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
+                                            const typename Store<ST>::T* __restrict__ fin,
+                                            typename Store<ST>::T* __restrict__ fout, const KParams& kp, int tile) {
     using S = Store<ST>;
     using R = typename S::R;
-    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
-    int tile = blockIdx.x;
-    if (part == 2) {
-        if (tile >= *ncount) return;
-        tile = nlist[tile];
-    } else if (part == 1 && nflags[tile] == epoch) {
-        return;
-    }
     const int bi = tile_box[tile];
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
@@ -177,6 +168,58 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
     typename S::T* fo = fout + B.foff;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) S::st(fo + (long long)i * B.stride + s, f[i], scl);
+}
+
+// Generic tile kernel over every box of the context.  A virtual block covers
+// SPT consecutive 256-site tiles (one site per thread and tile).  Block order:
+// with XCD, the grid is 8 * m blocks and the virtual blocks are cut into 8
+// contiguous ranges, range k walked by the blocks with blockIdx % 8 == k (the
+// hardware deals consecutive blocks out to the 8 XCDs in turn, so neighbouring
+// tiles, which share cache lines at their edges, meet in one XCD's L2); a grid
+// smaller than the work (persistent launch) walks its range in strides of m.
+// Without XCD, block b takes virtual blocks b, b + grid, ...  The near-set
+// parts (part 1, 2) use SPT = 1 and the plain order only.
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD>
+__global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restrict__ boxes,
+                                                         const BoxRT* __restrict__ rt,
+                                                         const int* __restrict__ tile_box,
+                                                         const typename Store<ST>::T* __restrict__ fin,
+                                                         typename Store<ST>::T* __restrict__ fout,
+                                                         KParams kp, int part, const uint32_t* __restrict__ nflags,
+                                                         const int* __restrict__ nlist,
+                                                         const int* __restrict__ ncount, uint32_t epoch,
+                                                         int* __restrict__ next_count, int ntiles) {
+    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+    if (SPT == 1 && !XCD && part != 0) {
+        int tile = blockIdx.x;
+        if (part == 2) {
+            if (tile >= *ncount) return;
+            tile = nlist[tile];
+        } else if (nflags[tile] == epoch) {
+            return;
+        }
+        site_update<ST, COLL, WALLS>(boxes, tile_box, fin, fout, kp, tile);
+        return;
+    }
+    const int nvb = (ntiles + SPT - 1) / SPT;
+    int v, vend, vstep;
+    if (XCD) {
+        const int m = (int)gridDim.x >> 3, chunk = (nvb + 7) >> 3, k = (int)(blockIdx.x & 7);
+        v = k * chunk + (int)(blockIdx.x >> 3);
+        vend = min(nvb, (k + 1) * chunk);
+        vstep = m;
+    } else {
+        v = blockIdx.x;
+        vend = nvb;
+        vstep = gridDim.x;
+    }
+    for (; v < vend; v += vstep) {
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int tile = v * SPT + k;
+            if (tile < ntiles) site_update<ST, COLL, WALLS>(boxes, tile_box, fin, fout, kp, tile);
+        }
+    }
 }
 
 // Row-wave variant for boxes with nx = 64 K: one wavefront owns one x-row,
@@ -486,20 +529,46 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int block
 
 // ------------------------------- launchers ----------------------------------
 
+// A collide-stream launch; with timing events in the arguments they receive
+// the kernel's own start and end (no stream work between them).
+#define K1_LAUNCH(KERNEL, G, B, ST, ...)                                                   \
+    do {                                                                                 \
+        if (a.ev_start)                                                                  \
+            hipExtLaunchKernelGGL(KERNEL, G, B, 0, ST, a.ev_start, a.ev_stop, 0, __VA_ARGS__); \
+        else                                                                             \
+            hipLaunchKernelGGL(KERNEL, G, B, 0, ST, __VA_ARGS__);                          \
+    } while (0)
+
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD>
+static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
+    using T = typename Store<ST>::T;
+    const int nvb = (a.ntiles + SPT - 1) / SPT;
+    int g;
+    if (a.part == 2) g = a.near_grid;
+    else if (XCD) g = 8 * (a.grid > 0 ? std::max(1, a.grid / 8) : (nvb + 7) / 8);
+    else g = a.grid > 0 ? std::min(a.grid, nvb) : nvb;
+    if (g == 0 || a.ntiles == 0) return hipSuccess;
+    K1_LAUNCH((k_collide_stream<ST, COLL, WALLS, SPT, XCD>), dim3(g), dim3(TILE), st, a.boxes, a.rt, a.tile_box,
+              (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch,
+              a.next_count, a.ntiles);
+    return hipGetLastError();
+}
+
+template <int ST, int COLL, bool WALLS>
+static hipError_t cs_shape(const LaunchCS& a, hipStream_t st) {
+    if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false>(a, st);
+    switch (a.spt * 2 + (a.xcd ? 1 : 0)) {
+        case 2: return cs_one<ST, COLL, WALLS, 1, false>(a, st);
+        case 3: return cs_one<ST, COLL, WALLS, 1, true>(a, st);
+        case 4: return cs_one<ST, COLL, WALLS, 2, false>(a, st);
+        case 5: return cs_one<ST, COLL, WALLS, 2, true>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int ST, int COLL>
 static hipError_t cs_walls(bool walls, const LaunchCS& a, hipStream_t st) {
-    using T = typename Store<ST>::T;
-    dim3 grid(a.part == 2 ? a.near_grid : a.ntiles), blk(TILE);
-    if (grid.x == 0) return hipSuccess;
-    if (walls)
-        hipLaunchKernelGGL((k_collide_stream<ST, COLL, true>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
-                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch, a.next_count);
-    else
-        hipLaunchKernelGGL((k_collide_stream<ST, COLL, false>), grid, blk, 0, st, a.boxes, a.rt, a.tile_box,
-                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch, a.next_count);
-    return hipGetLastError();
+    return walls ? cs_shape<ST, COLL, true>(a, st) : cs_shape<ST, COLL, false>(a, st);
 }
 
 template <int ST>
@@ -518,13 +587,11 @@ static hipError_t rows_launch(bool walls, const LaunchCS& a, hipStream_t st) {
     dim3 grid(a.part == 2 ? a.near_grid : (rows + 3) / 4), blk(256);
     if (grid.x == 0) return hipSuccess;
     if (walls)
-        hipLaunchKernelGGL((k_collide_stream_rows<ST, COLL, true, K, NT>), grid, blk, 0, st, a.boxes, a.rt, 0,
-                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch, a.next_count);
+        K1_LAUNCH((k_collide_stream_rows<ST, COLL, true, K, NT>), grid, blk, st, a.boxes, a.rt, 0, (const T*)a.fin,
+                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count);
     else
-        hipLaunchKernelGGL((k_collide_stream_rows<ST, COLL, false, K, NT>), grid, blk, 0, st, a.boxes, a.rt, 0,
-                           (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
-                           a.near_epoch, a.next_count);
+        K1_LAUNCH((k_collide_stream_rows<ST, COLL, false, K, NT>), grid, blk, st, a.boxes, a.rt, 0, (const T*)a.fin,
+                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count);
     return hipGetLastError();
 }
 

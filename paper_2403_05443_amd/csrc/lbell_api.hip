@@ -150,7 +150,8 @@ struct lb_ctx {
     long long step = 0;
     KParams kp{};
     bool any_walls = false;
-    int k1_variant = 0;  // collide-stream variant in use (see LaunchCS)
+    int k1_variant = 0;  // collide-stream variant in use (index into K1_SHAPES)
+    int n_cu = 256;      // compute units of the device (persistent grid size)
     int rows_k = 0;      // row-wave width, 0 when the box shape does not allow it
     // second stream: particle phase concurrent with the far blocks (off by
     // default: measured slower when the particle kernels' dependent loads
@@ -159,6 +160,13 @@ struct lb_ctx {
     bool fused = true;  // one particle kernel per step when no box holds two particles (LBELL_FUSED=0: two kernels)
     hipStream_t nstream = nullptr;
     hipEvent_t evK = nullptr, evP = nullptr, evStart = nullptr;
+    // graph replay of whole groups of steps (0 = off); one cached executable
+    // per buffer parity, keyed by what the captured launch arguments depend on
+    int graph_steps = 0;
+    struct GraphSlot {
+        hipGraphExec_t exec = nullptr;
+        int np = -1, variant = -1, steps = 0;
+    } graph[2];
     std::string err;
 
     template <typename T>
@@ -167,6 +175,28 @@ struct lb_ctx {
 };
 
 namespace {
+
+// Collide-stream variants the tuner chooses from (the index is the variant
+// number of the ABI).  Row-wave kinds need a single box with nx = 64, 128 or
+// 256; the near-set schedule needs kinds 0-2.
+struct K1Shape {
+    int kind;      // 0 generic tiles, 1 row-wave, 2 row-wave with non-temporal stores
+    int spt;       // tiles per block (generic)
+    bool xcd;      // XCD-chunked block order (generic)
+    bool persist;  // grid of a few blocks per CU walking the tiles (generic)
+};
+constexpr K1Shape K1_SHAPES[] = {
+    {0, 1, false, false}, {1, 1, false, false}, {2, 1, false, false}, {0, 1, true, false},
+    {0, 2, false, false}, {0, 2, true, false},  {0, 1, true, true},   {0, 2, true, true},
+};
+constexpr int K1_NSHAPES = (int)(sizeof(K1_SHAPES) / sizeof(K1_SHAPES[0]));
+
+bool k1_applicable(const lb_ctx* ctx, int v) {
+    if (v < 0 || v >= K1_NSHAPES) return false;
+    if (K1_SHAPES[v].kind != 0 && ctx->rows_k == 0) return false;
+    if (ctx->overlap && v > 2) return false;
+    return true;
+}
 
 lb_status fail(lb_ctx* c, lb_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -417,9 +447,22 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
         ctx->rows_k = boxes[0].nx / 64;
         ctx->k1_variant = 1;
     }
-    if (const char* v = std::getenv("LBELL_K1_VARIANT")) ctx->k1_variant = std::atoi(v);
     if (const char* v = std::getenv("LBELL_OVERLAP")) ctx->overlap = std::atoi(v) != 0;
     if (const char* v = std::getenv("LBELL_FUSED")) ctx->fused = std::atoi(v) != 0;
+    if (const char* v = std::getenv("LBELL_K1_VARIANT")) {
+        if (!k1_applicable(ctx, std::atoi(v))) {
+            std::fprintf(stderr, "lb_init: LBELL_K1_VARIANT=%s does not apply to these boxes\n", v);
+            delete ctx;
+            return LB_EINVAL;
+        }
+        ctx->k1_variant = std::atoi(v);
+    }
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            ctx->n_cu = ncu;
+    }
     {
         hipError_t e2 = hipStreamCreateWithFlags(&ctx->nstream, hipStreamNonBlocking);
         if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&ctx->evK, hipEventDisableTiming);
@@ -549,7 +592,11 @@ LaunchCS collide_args(lb_ctx* ctx, int variant) {
     cs.fout = ctx->fbuf(ctx->cur ^ 1);
     cs.kp = ctx->kp;
     cs.walls = ctx->any_walls;
-    cs.variant = ctx->rows_k > 0 ? variant : 0;
+    const K1Shape& sh = K1_SHAPES[k1_applicable(ctx, variant) ? variant : 0];
+    cs.variant = sh.kind;
+    cs.spt = sh.spt;
+    cs.xcd = sh.xcd;
+    cs.grid = sh.persist ? 8 * ctx->n_cu : 0;
     cs.rows_k = ctx->rows_k;
     cs.rows_ny = ctx->hbox[0].ny;
     cs.rows_nz = ctx->hbox[0].nz;
@@ -565,7 +612,7 @@ NearSet near_set(lb_ctx* ctx, long long t) {
     ns.list = ctx->at<int>(ctx->L.near_list) + (size_t)slot * ctx->L.near_blocks;
     ns.count = ctx->at<int>(ctx->L.near_count) + slot;
     ns.epoch = (uint32_t)(t + 1);
-    ns.rows_geom = (ctx->rows_k > 0 && ctx->k1_variant != 0) ? 1 : 0;
+    ns.rows_geom = (ctx->rows_k > 0 && K1_SHAPES[ctx->k1_variant].kind != 0) ? 1 : 0;
     ns.margin = NEAR_MARGIN;
     return ns;
 }
@@ -573,15 +620,17 @@ NearSet near_set(lb_ctx* ctx, long long t) {
 // Upper bound of the near-set size, the launch size of the near part.
 int near_grid(lb_ctx* ctx) {
     const int R = 2 * (int)std::ceil(ctx->cfg.max_semi_axis) + 6 + 2 * NEAR_MARGIN;
-    const long long per = ctx->rows_k > 0 && ctx->k1_variant != 0 ? (long long)R * (R / 4 + 2)
+    const long long per = ctx->rows_k > 0 && K1_SHAPES[ctx->k1_variant].kind != 0 ? (long long)R * (R / 4 + 2)
                                                                   : (long long)R * R * (R / TILE + 2);
     return (int)std::min<long long>(ctx->L.near_blocks, per * std::max(ctx->np, 1));
 }
 
-lb_status launch_collide(lb_ctx* ctx) {
+lb_status launch_collide(lb_ctx* ctx, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
     LaunchCS cs = collide_args(ctx, ctx->k1_variant);
-    cs.next_count = ctx->np > 0 ? near_set(ctx, ctx->step + 1).count : nullptr;
-    HIPC(launch_collide_stream(cs, ctx->stream));
+    cs.ev_start = t0;
+    cs.ev_stop = t1;
+    cs.next_count = ctx->overlap && ctx->np > 0 ? near_set(ctx, ctx->step + 1).count : nullptr;
+    HIPC(launch_collide_stream(cs, st));
     ctx->cur ^= 1;
     return LB_OK;
 }
@@ -598,7 +647,7 @@ bool one_particle_per_box(lb_ctx* ctx) {
 lb_status launch_particles(lb_ctx* ctx, hipStream_t st) {
     if (ctx->np == 0) return LB_OK;
     LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
-    a.near = near_set(ctx, ctx->step + 1);
+    if (ctx->overlap) a.near = near_set(ctx, ctx->step + 1);  // only the two-stream schedule reads it
     if (ctx->fused && one_particle_per_box(ctx)) {
         // a box with one particle has no other writer, so solve and remap
         // can share a work-group
@@ -616,6 +665,7 @@ lb_status launch_particles(lb_ctx* ctx, hipStream_t st) {
 // Both slots' tags are cleared first: a tag left from another step count (a
 // checkpoint load can move the counter back) must never match a new epoch.
 lb_status near_rebuild(lb_ctx* ctx) {
+    if (!ctx->overlap) return LB_OK;
     LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
     a.near = near_set(ctx, ctx->step);
     HIPC(hipMemsetAsync(ctx->arena + ctx->L.near_flags, 0, sizeof(uint32_t) * 2 * ctx->L.near_blocks, ctx->stream));
@@ -654,7 +704,60 @@ lb_status step_overlapped(lb_ctx* ctx) {
     return LB_OK;
 }
 
+void graph_drop(lb_ctx* ctx) {
+    for (auto& g : ctx->graph) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g = lb_ctx::GraphSlot{};
+    }
+}
+
+// One replay of a group of graph_steps steps; captures the group first if
+// the cached executable does not match the current launch arguments.
+lb_status step_graph(lb_ctx* ctx) {
+    lb_ctx::GraphSlot& g = ctx->graph[ctx->cur];
+    if (!g.exec || g.np != ctx->np || g.variant != ctx->k1_variant || g.steps != ctx->graph_steps) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g = lb_ctx::GraphSlot{};
+        const int cur0 = ctx->cur;
+        const long long step0 = ctx->step;
+        HIPC(hipStreamBeginCapture(ctx->nstream, hipStreamCaptureModeThreadLocal));
+        lb_status s = LB_OK;
+        for (int k = 0; k < ctx->graph_steps && s == LB_OK; ++k) {
+            s = launch_collide(ctx, ctx->nstream);
+            if (s == LB_OK) s = launch_particles(ctx, ctx->nstream);
+            ctx->step++;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->nstream, &graph);
+        ctx->cur = cur0;
+        ctx->step = step0;
+        if (s != LB_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return s;
+        }
+        HIPC(ec);
+        const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        HIPC(ei);
+        g.np = ctx->np;
+        g.variant = ctx->k1_variant;
+        g.steps = ctx->graph_steps;
+    }
+    HIPC(hipGraphLaunch(g.exec, ctx->stream));
+    ctx->cur ^= (ctx->graph_steps & 1);
+    ctx->step += ctx->graph_steps;
+    return LB_OK;
+}
+
 }  // namespace
+
+lb_status lb_set_graph(lb_ctx* ctx, int steps) {
+    if (!ctx || steps < 0) return LB_EINVAL;
+    if (steps > 0 && ctx->overlap) return fail(ctx, LB_ESTATE, "graph replay is not available with two streams");
+    graph_drop(ctx);
+    ctx->graph_steps = steps;
+    return LB_OK;
+}
 
 lb_status lb_step(lb_ctx* ctx, int n) {
     if (!ctx || n < 0) return LB_EINVAL;
@@ -665,8 +768,15 @@ lb_status lb_step(lb_ctx* ctx, int n) {
         HIPC(hipStreamWaitEvent(ctx->nstream, ctx->evStart, 0));
         HIPC(hipEventRecord(ctx->evP, ctx->stream));
     }
-    for (int k = 0; k < n; ++k) {
-        lb_status s = ov ? step_overlapped(ctx) : launch_collide(ctx);
+    int k = 0;
+    if (!ov && ctx->graph_steps > 0) {
+        for (; k + ctx->graph_steps <= n; k += ctx->graph_steps) {
+            lb_status s = step_graph(ctx);
+            if (s != LB_OK) return s;
+        }
+    }
+    for (; k < n; ++k) {
+        lb_status s = ov ? step_overlapped(ctx) : launch_collide(ctx, ctx->stream);
         if (s == LB_OK && !ov) s = launch_particles(ctx, ctx->stream);
         if (s != LB_OK) return s;
         ctx->step++;
@@ -677,23 +787,24 @@ lb_status lb_step(lb_ctx* ctx, int n) {
 
 lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_particle) {
     if (!ctx || n < 0) return LB_EINVAL;
-    std::vector<hipEvent_t> ev((size_t)3 * n);
+    // collide-stream: events bound to the kernel's own start and end; particle
+    // phase: events on the stream around its launches
+    std::vector<hipEvent_t> ev((size_t)4 * n);
     for (auto& e : ev) HIPC(hipEventCreate(&e));
     lb_status s = LB_OK;
     for (int k = 0; k < n && s == LB_OK; ++k) {
-        HIPC(hipEventRecord(ev[3 * k], ctx->stream));
-        s = launch_collide(ctx);
-        HIPC(hipEventRecord(ev[3 * k + 1], ctx->stream));
+        s = launch_collide(ctx, ctx->stream, ev[4 * k], ev[4 * k + 1]);
+        HIPC(hipEventRecord(ev[4 * k + 2], ctx->stream));
         if (s == LB_OK) s = launch_particles(ctx, ctx->stream);
-        HIPC(hipEventRecord(ev[3 * k + 2], ctx->stream));
+        HIPC(hipEventRecord(ev[4 * k + 3], ctx->stream));
         ctx->step++;
     }
     HIPC(hipStreamSynchronize(ctx->stream));
     double c = 0, p = 0;
     for (int k = 0; k < n; ++k) {
         float a = 0, b = 0;
-        HIPC(hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]));
-        HIPC(hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]));
+        HIPC(hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]));
+        HIPC(hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]));
         c += a;
         p += b;
     }
@@ -705,35 +816,51 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
 
 lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best) {
     if (!ctx || reps <= 0) return LB_EINVAL;
-    // The collide-stream kernel maps the current buffer to the other one and
-    // nothing else, so repeating it leaves the simulation state untouched.
-    const int nvar = ctx->rows_k > 0 ? 3 : 1;
-    hipEvent_t e0, e1;
-    HIPC(hipEventCreate(&e0));
-    HIPC(hipEventCreate(&e1));
-    int best = 0;
+    // Every variant is timed inside real time steps (collide-stream, then the
+    // particle phase), so each launch reads the buffer the previous step
+    // wrote, as in production; timing a kernel against the same input again
+    // and again would let the last-level cache serve part of it.  The events
+    // take the kernel's own start and end.  All variants compute
+    // bit-identical results, so the steps taken here are ordinary steps of
+    // the simulation.
+    std::vector<hipEvent_t> ev((size_t)2 * reps);
+    for (auto& e : ev) HIPC(hipEventCreate(&e));
+    const int keep = ctx->k1_variant;
+    int best = keep;
     double tbest = 1e300;
-    for (int v = 0; v < nvar; ++v) {
-        const LaunchCS cs = collide_args(ctx, v);
-        HIPC(launch_collide_stream(cs, ctx->stream));  // warm-up
-        HIPC(hipEventRecord(e0, ctx->stream));
-        for (int r = 0; r < reps; ++r) HIPC(launch_collide_stream(cs, ctx->stream));
-        HIPC(hipEventRecord(e1, ctx->stream));
-        HIPC(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPC(hipEventElapsedTime(&ms, e0, e1));
-        if (ms / reps < tbest) {
-            tbest = ms / reps;
+    lb_status s = LB_OK;
+    for (int v = 0; v < K1_NSHAPES && s == LB_OK; ++v) {
+        if (!k1_applicable(ctx, v)) continue;
+        const bool kind_changed = K1_SHAPES[v].kind != K1_SHAPES[ctx->k1_variant].kind;
+        ctx->k1_variant = v;
+        if (kind_changed && (s = near_rebuild(ctx)) != LB_OK) break;
+        for (int r = -1; r < reps && s == LB_OK; ++r) {  // r = -1: warm-up step
+            s = r >= 0 ? launch_collide(ctx, ctx->stream, ev[2 * r], ev[2 * r + 1]) : launch_collide(ctx, ctx->stream);
+            if (s == LB_OK) s = launch_particles(ctx, ctx->stream);
+            ctx->step++;
+        }
+        if (s != LB_OK) break;
+        HIPC(hipStreamSynchronize(ctx->stream));
+        double t = 0;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+            t += ms;
+        }
+        t /= reps;
+        if (t < tbest) {
+            tbest = t;
             best = v;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    const bool changed = ctx->k1_variant != best;
+    for (auto& e : ev) hipEventDestroy(e);
+    if (s != LB_OK) return s;
+    const bool kind_changed = K1_SHAPES[best].kind != K1_SHAPES[ctx->k1_variant].kind;
     ctx->k1_variant = best;
     if (variant) *variant = best;
     if (ms_best) *ms_best = tbest;
-    return changed ? near_rebuild(ctx) : LB_OK;
+    if (kind_changed) return near_rebuild(ctx);
+    return flags_status(ctx);
 }
 
 lb_status lb_bandwidth_probe(void* dst, const void* src, size_t bytes, void* hip_stream, int reps, double* gbs) {
@@ -1009,6 +1136,7 @@ lb_status lb_destroy(lb_ctx* ctx) {
     }
     for (hipEvent_t e : {ctx->evK, ctx->evP, ctx->evStart})
         if (e) hipEventDestroy(e);
+    graph_drop(ctx);
     delete ctx;
     return LB_OK;
 }

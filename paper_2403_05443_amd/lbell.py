@@ -56,6 +56,7 @@ SIGNATURES = {
     "lb_profile_step": (C.c_int, [_VP, C.c_int, _D, _D]),
     "lb_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), _D]),
     "lb_bandwidth_probe": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_int, _D]),
+    "lb_set_graph": (C.c_int, [_VP, C.c_int]),
     "lb_sync": (C.c_int, [_VP]),
     "lb_get_force_torque": (C.c_int, [_VP, C.c_int, _D, _D]),
     "lb_get_particle": (C.c_int, [_VP, C.c_int, _D, _D, _D, _D]),
@@ -229,10 +230,15 @@ class Lattice:
         return a[0], b[0]
 
     def autotune(self, reps=20):
-        """Pick the fastest collide-stream variant; returns (variant, ms per launch)."""
+        """Pick the fastest collide-stream variant, timed inside real steps (the
+        simulation advances by those steps); returns (variant, ms per launch)."""
         v, ms = C.c_int(0), np.zeros(1)
         self._chk(self.lib.lb_autotune(self.ctx, int(reps), C.byref(v), _p(ms)))
         return v.value, ms[0]
+
+    def set_graph(self, steps):
+        """Run lb_step in HIP graphs of `steps` steps (0: plain launches)."""
+        self._chk(self.lib.lb_set_graph(self.ctx, int(steps)))
 
     def sync(self):
         self._chk(self.lib.lb_sync(self.ctx))

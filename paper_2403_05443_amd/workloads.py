@@ -136,3 +136,33 @@ def c3(r=3, seed_index=1, storage="fp32"):
                     [Particle((31.5, 63.5, 31.5), (3.0 * r, 3.0, 3.0), q)],
                     "bgk", 0.8, storage, 0, velocity_scale=0.01, max_semi_axis=12.0,
                     notes={"shear_rate": 0.02 / 126.0})
+
+
+def c4(storage="fp16", nboxes=256, seed_index=0):
+    """Ensemble of independent periodic cubic boxes, one spheroid each.
+
+    Edge L uniform on the integers 32..64; aspect ratio r uniform in [1, 5]
+    and semi-minor axis b uniform in [2, 4], redrawn until L - 2a >= 8
+    (a = r b); body axes (a, b, b); orientation uniform on S^3; centre at the
+    box centre plus a uniform sub-lattice offset in [-0.5, 0.5)^3; force of
+    magnitude uniform in [1e-5, 1e-4] and torque of magnitude uniform in
+    [1e-4, 1e-3], both in uniformly random directions.  TRT, Lambda = 3/16,
+    tau+ = 1 (nu = 1/6), counter-force on."""
+    g = SplitMix64(SEED0 + 3 + 1000 * seed_index)
+    boxes, parts = [], []
+    for i in range(nboxes):
+        L = 32 + int(g.uniform() * 33)
+        while True:
+            r = g.uniform(1.0, 5.0)
+            b = g.uniform(2.0, 4.0)
+            if L - 2.0 * r * b >= 8.0:
+                break
+        q = g.unit_quaternion()
+        c = tuple((L - 1) / 2.0 + g.uniform(-0.5, 0.5) for _ in range(3))
+        fm, tm = g.uniform(1e-5, 1e-4), g.uniform(1e-4, 1e-3)
+        fd, td = g.unit_vector(), g.unit_vector()
+        boxes.append(Box((L, L, L)))
+        parts.append(Particle(c, (r * b, b, b), q, force=tuple(fm * v for v in fd),
+                              torque=tuple(tm * v for v in td), box=i))
+    return Workload(f"c4_ensemble_{nboxes}", boxes, parts, "trt", 1.0, storage, 0, counterforce=True,
+                    velocity_scale=1e-3, max_semi_axis=20.0)
