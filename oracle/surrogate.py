@@ -1,0 +1,262 @@
+"""FP64 reference of the learned warm start: the MLP surrogate (forward,
+backward, Adam), its input features and output scaling, the Stokes start
+field, and the unbounded-fluid closed forms used as a control.
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``; never by the product
+path.  Plain numpy in float64, written from the definitions; it shares no
+code with the HIP library.
+
+Definitions (the paper has no learned part; the surrogate is specified by the
+task, and the readings are listed with the design notes):
+
+* network 8 -> 64 -> 64 -> 6, tanh hidden layers, linear output;
+  parameters flat, in the order W1[64][8], b1[64], W2[64][64], b2[64],
+  W3[6][64], b3[6] (5126 values);
+* loss: mean squared error over the n x 6 outputs;
+* Adam (Kingma & Ba 2015): beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected;
+* BF16 mode: the operands of every matrix product (inputs, weights, hidden
+  activations, back-propagated errors) are rounded to bfloat16 (round to
+  nearest even) at the points where the GPU kernels round them; sums, biases,
+  tanh and the error terms stay in full precision.
+"""
+import math
+
+import numpy as np
+
+N_IN, N_H, N_OUT = 8, 64, 6
+SHAPES = [("W1", (N_H, N_IN)), ("b1", (N_H,)), ("W2", (N_H, N_H)), ("b2", (N_H,)),
+          ("W3", (N_OUT, N_H)), ("b3", (N_OUT,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+# ------------------------------------------------------------------ bfloat16 --
+
+def bf16(x):
+    """Round float32 values of x to bfloat16 (nearest, ties to even); returns float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(f)
+    r = np.where(nan, u, r).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------- parameters --
+
+def unpack(p):
+    p = np.asarray(p, dtype=np.float64)
+    assert p.size == N_PARAMS
+    out, k = {}, 0
+    for name, s in SHAPES:
+        n = int(np.prod(s))
+        out[name] = p[k:k + n].reshape(s)
+        k += n
+    return out
+
+
+def pack(d):
+    return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name, _ in SHAPES])
+
+
+# -------------------------------------------------------------------- network --
+
+def forward(p, X, bf=False):
+    """Outputs (n, 6) and the cache of activations."""
+    P = unpack(p)
+    r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+    x = r(X)
+    W1, W2, W3 = r(P["W1"]), r(P["W2"]), r(P["W3"])
+    h1 = np.tanh(x @ W1.T + P["b1"])
+    h1r = r(h1)
+    h2 = np.tanh(h1r @ W2.T + P["b2"])
+    h2r = r(h2)
+    y = h2r @ W3.T + P["b3"]
+    return y, {"x": x, "h1": h1r, "h2": h2r, "W1": W1, "W2": W2, "W3": W3}
+
+
+def loss_grad(p, X, Y, bf=False):
+    """Mean squared error over all outputs and its gradient (flat, like p)."""
+    X, Y = np.asarray(X, dtype=np.float64), np.asarray(Y, dtype=np.float64)
+    n = X.shape[0]
+    r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+    y, c = forward(p, X, bf)
+    L = float(np.sum((y - Y) ** 2) / (n * N_OUT))
+    d3 = 2.0 * (y - Y) / (n * N_OUT)               # dL/dy
+    d3r = r(d3)
+    g = {"W3": d3r.T @ c["h2"], "b3": d3.sum(0)}
+    d2 = (d3r @ c["W3"]) * (1.0 - c["h2"] ** 2)     # dL/d(pre-activation of layer 2)
+    d2r = r(d2)
+    g["W2"], g["b2"] = d2r.T @ c["h1"], d2.sum(0)
+    d1 = (d2r @ c["W2"]) * (1.0 - c["h1"] ** 2)
+    d1r = r(d1)
+    g["W1"], g["b1"] = d1r.T @ c["x"], d1.sum(0)
+    return L, pack(g)
+
+
+def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update at step t (1-based); returns (p, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------------ features and scaling --
+
+def rotmat(q):
+    """Body -> lab rotation of the unit quaternion (scalar first)."""
+    q0, q1, q2, q3 = [float(v) for v in q]
+    return np.array([[1 - 2 * (q2 * q2 + q3 * q3), 2 * (q1 * q2 - q0 * q3), 2 * (q1 * q3 + q0 * q2)],
+                     [2 * (q1 * q2 + q0 * q3), 1 - 2 * (q1 * q1 + q3 * q3), 2 * (q2 * q3 - q0 * q1)],
+                     [2 * (q1 * q3 - q0 * q2), 2 * (q2 * q3 + q0 * q1), 1 - 2 * (q1 * q1 + q2 * q2)]])
+
+
+def req(axes):
+    """Radius of the sphere of equal volume."""
+    a, b, c = axes
+    return (a * b * c) ** (1.0 / 3.0)
+
+
+def features(axes, q, F, T, box):
+    """Input vector (ln r, a/L, F_body/s, T_body/(R s)), with r = a/sqrt(bc),
+    L = cube root of the box volume, R the equal-volume radius and
+    s = sqrt(|F|^2 + (|T|/R)^2); zero load gives zero load components."""
+    a, b, c = axes
+    R = req(axes)
+    L = (box[0] * box[1] * box[2]) ** (1.0 / 3.0)
+    Rm = rotmat(q)
+    Fb, Tb = Rm.T @ np.asarray(F, float), Rm.T @ np.asarray(T, float)
+    s = math.sqrt(Fb @ Fb + (Tb @ Tb) / (R * R))
+    x = np.zeros(8)
+    x[0] = math.log(a / math.sqrt(b * c))
+    x[1] = a / L
+    if s > 0:
+        x[2:5] = Fb / s
+        x[5:8] = Tb / (R * s)
+    return x, s
+
+
+def velocities(y, axes, q, F, T, nu, rho0=1.0):
+    """Lab-frame (U, Omega) from the network output y (normalised body-frame
+    response): U_body = y[0:3] s / (6 pi mu R), Omega_body = y[3:6] s / (8 pi mu R^2)."""
+    R = req(axes)
+    _, s = features(axes, q, F, T, (1, 1, 1))
+    mu = rho0 * nu
+    Rm = rotmat(q)
+    Ub = np.asarray(y[0:3], float) * s / (6 * math.pi * mu * R)
+    Wb = np.asarray(y[3:6], float) * s / (8 * math.pi * mu * R * R)
+    return Rm @ Ub, Rm @ Wb
+
+
+def targets(U, W, axes, q, F, T, nu, rho0=1.0):
+    """Inverse of velocities(): the normalised output for measured (U, Omega)."""
+    R = req(axes)
+    _, s = features(axes, q, F, T, (1, 1, 1))
+    mu = rho0 * nu
+    Rm = rotmat(q)
+    y = np.zeros(6)
+    y[0:3] = Rm.T @ np.asarray(U, float) * 6 * math.pi * mu * R / s
+    y[3:6] = Rm.T @ np.asarray(W, float) * 8 * math.pi * mu * R * R / s
+    return y
+
+
+# --------------------------------------------------------- Stokes start field --
+
+def equilibrium(rho, u):
+    """Second-order D3Q19 equilibria for velocities u (n, 3) -> (n, 19), in the
+    direction order rest, +-x, +-y, +-z, then (1,1,0), (-1,-1,0), (1,-1,0),
+    (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1),
+    (0,1,-1), (0,-1,1)."""
+    c = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1],
+                  [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=float)
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    u = np.atleast_2d(u)
+    cu = u @ c.T
+    uu = (u * u).sum(1, keepdims=True)
+    return rho * w * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
+
+
+def min_image(d, n):
+    d = np.array(d, dtype=float)
+    for k in range(3):
+        d[..., k] = np.where(d[..., k] >= n[k] / 2, d[..., k] - n[k], d[..., k])
+        d[..., k] = np.where(d[..., k] < -n[k] / 2, d[..., k] + n[k], d[..., k])
+    return d
+
+
+def stokes_velocity(d, U, W, R):
+    """Creeping flow around a sphere of radius R translating with U and
+    rotating with W, at offsets d (n, 3) from its centre: the Stokes solution
+    u = (3R/4r)(U + (U.e)e) + (R^3/4r^3)(U - 3(U.e)e) plus the rotlet
+    (R/r)^3 W x d outside, rigid motion U + W x d inside."""
+    d = np.atleast_2d(d)
+    r = np.linalg.norm(d, axis=1)[:, None]
+    U, W = np.asarray(U, float), np.asarray(W, float)
+    rigid = U + np.cross(W, d)
+    rs = np.maximum(r, 1e-300)
+    e = d / rs
+    Ue = (e @ U)[:, None]
+    out = (3 * R / (4 * rs)) * (U + Ue * e) + (R ** 3 / (4 * rs ** 3)) * (U - 3 * Ue * e) \
+        + (R / rs) ** 3 * np.cross(W, d)
+    return np.where(r >= R, out, rigid)
+
+
+def start_field(shape, owner, particles):
+    """Velocity of every node of a periodic box for the warm start.
+
+    particles: list of dicts (centre, axes, U, W, M).  Fluid nodes (owner 0)
+    take the sum over particles of the sphere field (equal-volume radius,
+    minimum-image offsets) minus the uniform velocity that makes the total
+    momentum (fluid at rho0 = 1 plus particles) zero; nodes of particle p take
+    its rigid motion U + W x d."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(float)
+    u = np.zeros((pos.shape[0], 3))
+    owner = np.asarray(owner).ravel()
+    fluid = owner == 0
+    P = np.zeros(3)
+    for k, p in enumerate(particles):
+        d = min_image(pos - np.asarray(p["centre"], float), shape)
+        f = stokes_velocity(d, p["U"], p["W"], req(p["axes"]))
+        u[fluid] += f[fluid]
+        mine = owner == k + 1
+        u[mine] = np.asarray(p["U"], float) + np.cross(np.asarray(p["W"], float), d[mine])
+        P += p["M"] * np.asarray(p["U"], float)
+    ubar = (u[fluid].sum(0) + P) / fluid.sum()
+    u[fluid] -= ubar
+    return u
+
+
+# ----------------------------------------------- unbounded-fluid closed forms --
+
+def kim_karrila(r):
+    """Resistance functions of a prolate spheroid with aspect ratio r >= 1
+    (Kim & Karrila, Microhydrodynamics, Table 3.4): X^A, Y^A (translation
+    along / across the axis, force 6 pi mu a X U) and X^C, Y^C (rotation
+    about / across the axis, torque 8 pi mu a^3 X Omega); all 1 for a sphere."""
+    if r < 1 + 1e-6:
+        return 1.0, 1.0, 1.0, 1.0
+    e = math.sqrt(1 - 1 / r ** 2)
+    Lg = math.log((1 + e) / (1 - e))
+    XA = 8 / 3 * e ** 3 / (-2 * e + (1 + e * e) * Lg)
+    YA = 16 / 3 * e ** 3 / (2 * e + (3 * e * e - 1) * Lg)
+    XC = 4 / 3 * e ** 3 * (1 - e * e) / (2 * e - (1 - e * e) * Lg)
+    YC = 4 / 3 * e ** 3 * (2 - e * e) / (-2 * e + (1 + e * e) * Lg)
+    return XA, YA, XC, YC
+
+
+def unbounded_velocities(axes, q, F, T, nu, rho0=1.0):
+    """Velocities of a prolate spheroid (a, b, b), a >= b, under (F, T) in an
+    unbounded fluid, from the resistance functions."""
+    a, b, _ = axes
+    XA, YA, XC, YC = kim_karrila(a / b)
+    mu = rho0 * nu
+    Rm = rotmat(q)
+    Fb, Tb = Rm.T @ np.asarray(F, float), Rm.T @ np.asarray(T, float)
+    Ub = np.array([Fb[0] / XA, Fb[1] / YA, Fb[2] / YA]) / (6 * math.pi * mu * a)
+    Wb = np.array([Tb[0] / XC, Tb[1] / YC, Tb[2] / YC]) / (8 * math.pi * mu * a ** 3)
+    return Rm @ Ub, Rm @ Wb

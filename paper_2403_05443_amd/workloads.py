@@ -166,3 +166,19 @@ def c4(storage="fp16", nboxes=256, seed_index=0):
                               torque=tuple(tm * v for v in td), box=i))
     return Workload(f"c4_ensemble_{nboxes}", boxes, parts, "trt", 1.0, storage, 0, counterforce=True,
                     velocity_scale=1e-3, max_semi_axis=20.0)
+
+
+MLP_LAYERS = ((64, 8), (64, 64), (6, 64))   # (fan_out, fan_in) of the surrogate's three layers
+
+
+def xavier_params(gen):
+    """Initial surrogate parameters, flat in the order W1, b1, W2, b2, W3, b3:
+    weights uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot & Bengio 2010),
+    drawn row by row from `gen` (a SplitMix64), biases zero."""
+    out = []
+    for fo, fi in MLP_LAYERS:
+        lim = math.sqrt(6.0 / (fi + fo))
+        out += [gen.uniform(-lim, lim) for _ in range(fo * fi)]
+        out += [0.0] * fo
+    import numpy as np
+    return np.array(out)

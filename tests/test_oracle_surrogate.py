@@ -1,0 +1,257 @@
+"""Pins of the surrogate reference (oracle/surrogate.py) against what fixes
+it independently of itself: finite differences and torch autograd for the
+network gradient, torch's bfloat16 conversion, Adam's closed-form first
+step, frame and scale invariances of the features, exact properties of the
+Stokes solution, and Perrin's independent formulas for the spheroid
+resistance functions."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+from paper_2403_05443_amd import workloads
+
+
+def _rand_params(seed, scale=0.5):
+    g = np.random.default_rng(seed)
+    return g.uniform(-scale, scale, S.N_PARAMS)
+
+
+def _rand_data(seed, n=13):
+    g = np.random.default_rng(seed)
+    return g.uniform(-1, 1, (n, 8)), g.uniform(-1, 1, (n, 6))
+
+
+def test_parameter_count():
+    assert S.N_PARAMS == 5126
+    p = np.arange(S.N_PARAMS, dtype=float)
+    assert np.array_equal(S.pack(S.unpack(p)), p)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(3)
+    x = np.concatenate([g.standard_normal(5000).astype(np.float32) * 10.0 ** g.integers(-8, 8, 5000),
+                        np.float32([1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -8, 0.0, -0.0, 65504.0])])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(S.bf16(x), ref)
+    # ties to even at 1: spacing 2^-7
+    assert S.bf16(np.float32(1 + 2 ** -8)) == 1.0
+    assert S.bf16(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
+
+
+def test_forward_matches_torch():
+    torch = pytest.importorskip("torch")
+    p, (X, Y) = _rand_params(1), _rand_data(2)
+    P = {k: torch.tensor(v) for k, v in S.unpack(p).items()}
+    Xt = torch.tensor(X)
+    h1 = torch.tanh(torch.nn.functional.linear(Xt, P["W1"], P["b1"]))
+    h2 = torch.tanh(torch.nn.functional.linear(h1, P["W2"], P["b2"]))
+    y = torch.nn.functional.linear(h2, P["W3"], P["b3"])
+    assert np.allclose(S.forward(p, X)[0], y.numpy(), rtol=0, atol=1e-14)
+
+
+def test_gradient_matches_autograd():
+    torch = pytest.importorskip("torch")
+    p, (X, Y) = _rand_params(4), _rand_data(5)
+    pt = torch.tensor(p, requires_grad=True)
+    sizes = [int(np.prod(s)) for _, s in S.SHAPES]
+    parts = torch.split(pt, sizes)
+    W1, b1, W2, b2, W3, b3 = [t.reshape(s) for t, (_, s) in zip(parts, S.SHAPES)]
+    Xt, Yt = torch.tensor(X), torch.tensor(Y)
+    h1 = torch.tanh(Xt @ W1.T + b1)
+    h2 = torch.tanh(h1 @ W2.T + b2)
+    L = ((h2 @ W3.T + b3 - Yt) ** 2).mean()
+    L.backward()
+    L0, g = S.loss_grad(p, X, Y)
+    assert abs(L0 - L.item()) < 1e-14
+    assert np.abs(g - pt.grad.numpy()).max() <= 1e-13 * np.abs(g).max()
+
+
+def test_gradient_central_differences():
+    """Every one of the 5126 partial derivatives against a central difference
+    with h = 1e-6: relative error below 1e-7 of the gradient's scale."""
+    p, (X, Y) = _rand_params(6), _rand_data(7, n=9)
+    _, g = S.loss_grad(p, X, Y)
+    h = 1e-6
+    fd = np.empty_like(p)
+    for k in range(S.N_PARAMS):
+        e = np.zeros_like(p)
+        e[k] = h
+        fd[k] = (S.loss_grad(p + e, X, Y)[0] - S.loss_grad(p - e, X, Y)[0]) / (2 * h)
+    assert np.abs(fd - g).max() <= 1e-7 * np.abs(g).max()
+
+
+def test_bf16_mode_is_close_to_exact():
+    """Rounding the product operands to bfloat16 (8 significant bits) moves
+    the loss and the gradient by no more than a few ulps of bfloat16."""
+    p, (X, Y) = _rand_params(8), _rand_data(9, n=64)
+    L, g = S.loss_grad(p, X, Y)
+    Lb, gb = S.loss_grad(p, X, Y, bf=True)
+    assert abs(Lb - L) < 3 * 2 ** -8 * L
+    assert np.abs(gb - g).max() < 6 * 2 ** -8 * np.abs(g).max()
+    assert not np.array_equal(gb, g)
+
+
+def test_bf16_mode_equals_exact_on_representable_network():
+    """With bfloat16-exact inputs and weights and a network whose hidden
+    activations are exactly 0 (zero first-layer weights and biases) the two
+    modes agree to rounding of the sums."""
+    p = S.unpack(S.bf16(_rand_params(10)))
+    p["W1"][:] = 0
+    p["b1"][:] = 0
+    p["W2"][:] = 0
+    p["b2"][:] = 0
+    q = S.pack(p)
+    X, Y = _rand_data(11)
+    X = S.bf16(X)
+    y0, _ = S.forward(q, X)
+    y1, _ = S.forward(q, X, bf=True)
+    assert np.allclose(y0, np.broadcast_to(p["b3"], y0.shape), atol=0)
+    assert np.array_equal(y0, y1)
+
+
+def test_adam_first_step_closed_form():
+    """From zero moments the first bias-corrected step is lr g / (|g| + eps)."""
+    g = np.array([3.0, -1e-3, 0.5, 0.0])
+    p = np.ones(4)
+    p1, m, v = S.adam(p, g, np.zeros(4), np.zeros(4), 1, 1e-3)
+    assert np.allclose(p1, p - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_fits_a_linear_map():
+    """Full-batch Adam on the network reduces the loss of a linear target by
+    two orders of magnitude."""
+    gen = workloads.SplitMix64(77)
+    p = workloads.xavier_params(gen)
+    g = np.random.default_rng(12)
+    X = g.uniform(-1, 1, (128, 8))
+    A = g.uniform(-0.5, 0.5, (8, 6))
+    Y = X @ A
+    m = v = np.zeros(S.N_PARAMS)
+    L0 = S.loss_grad(p, X, Y)[0]
+    for t in range(1, 601):
+        L, gr = S.loss_grad(p, X, Y)
+        p, m, v = S.adam(p, gr, m, v, t, 3e-3)
+    assert S.loss_grad(p, X, Y)[0] < 1e-2 * L0
+
+
+def test_xavier_bounds():
+    p = S.unpack(workloads.xavier_params(workloads.SplitMix64(5)))
+    for name, fi, fo in (("W1", 8, 64), ("W2", 64, 64), ("W3", 64, 6)):
+        lim = math.sqrt(6 / (fi + fo))
+        assert np.abs(p[name]).max() <= lim and np.abs(p[name]).max() > 0.9 * lim
+        assert abs(p[name].mean()) < 0.1 * lim
+    for b in ("b1", "b2", "b3"):
+        assert not p[b].any()
+
+
+def _rand_pose(g):
+    q = g.standard_normal(4)
+    return q / np.linalg.norm(q)
+
+
+def test_features_are_frame_and_scale_invariant():
+    g = np.random.default_rng(13)
+    axes, q = (6.0, 2.0, 2.0), _rand_pose(g)
+    F, T = g.standard_normal(3) * 1e-4, g.standard_normal(3) * 1e-3
+    x, s = S.features(axes, q, F, T, (40, 40, 40))
+    # rotate everything by Q: body-frame loads unchanged
+    Qq = _rand_pose(g)
+    Q = S.rotmat(Qq)
+    q2 = np.array([Qq[0] * q[0] - Qq[1:] @ q[1:], *(Qq[0] * q[1:] + q[0] * Qq[1:] + np.cross(Qq[1:], q[1:]))])
+    assert np.allclose(S.rotmat(q2), Q @ S.rotmat(q), atol=1e-14)
+    x2, s2 = S.features(axes, q2, Q @ F, Q @ T, (40, 40, 40))
+    assert np.allclose(x, x2, atol=1e-13) and abs(s - s2) < 1e-15
+    # Stokes linearity: loads scaled by lambda keep x and scale s
+    x3, s3 = S.features(axes, q, 7 * F, 7 * T, (40, 40, 40))
+    assert np.allclose(x, x3, atol=1e-14) and abs(s3 - 7 * s) < 1e-14
+    assert abs(np.linalg.norm(x[2:]) - 1) < 1e-14
+    assert x[0] == pytest.approx(math.log(3)) and x[1] == pytest.approx(6 / 40)
+
+
+def test_velocities_invert_targets():
+    g = np.random.default_rng(14)
+    axes, q = (5.0, 2.5, 2.0), _rand_pose(g)
+    F, T = g.standard_normal(3) * 1e-4, g.standard_normal(3) * 1e-3
+    U, W = g.standard_normal(3) * 1e-5, g.standard_normal(3) * 1e-6
+    y = S.targets(U, W, axes, q, F, T, 1 / 6)
+    U2, W2 = S.velocities(y, axes, q, F, T, 1 / 6)
+    assert np.allclose(U2, U, rtol=1e-13, atol=0) and np.allclose(W2, W, rtol=1e-13, atol=0)
+
+
+def test_sphere_targets_are_unit_mobility():
+    """A sphere in an unbounded fluid moves with U = F / 6 pi mu R and
+    Omega = T / 8 pi mu R^3: the normalised output equals the load inputs."""
+    g = np.random.default_rng(15)
+    axes, q = (3.0, 3.0, 3.0), _rand_pose(g)
+    F, T = g.standard_normal(3) * 1e-4, g.standard_normal(3) * 1e-3
+    U, W = S.unbounded_velocities(axes, q, F, T, 1 / 6)
+    x, _ = S.features(axes, q, F, T, (40, 40, 40))
+    assert np.allclose(S.targets(U, W, axes, q, F, T, 1 / 6), x[2:], atol=1e-13)
+
+
+def test_resistance_functions_match_perrin():
+    """Kim & Karrila's X^A, Y^A, X^C, Y^C against Perrin's friction
+    coefficients of a prolate spheroid (Perrin 1934), a separately published
+    form; and the sphere limit."""
+    for r in (1.05, 1.5, 3.0, 5.0):
+        a, b = r, 1.0
+        c = math.sqrt(a * a - b * b)
+        Sx = 2 / c * math.log((a + c) / b)
+        fpar = 16 * math.pi * (a * a - b * b) / ((2 * a * a - b * b) * Sx - 2 * a)
+        fperp = 32 * math.pi * (a * a - b * b) / ((2 * a * a - 3 * b * b) * Sx + 2 * a)
+        rax = 32 * math.pi / 3 * (a * a - b * b) * b * b / (2 * a - b * b * Sx)
+        rtr = 32 * math.pi / 3 * (a ** 4 - b ** 4) / ((2 * a * a - b * b) * Sx - 2 * a)
+        XA, YA, XC, YC = S.kim_karrila(r)
+        ref = (fpar / (6 * math.pi * a), fperp / (6 * math.pi * a), rax / (8 * math.pi * a ** 3),
+               rtr / (8 * math.pi * a ** 3))
+        assert np.allclose((XA, YA, XC, YC), ref, rtol=1e-9)
+    assert np.allclose(S.kim_karrila(1 + 1e-5), 1.0, atol=1e-4)
+    # the drift of the inclined r = 3 spheroid (Sec. III.B): 5.891 deg
+    XA, YA, _, _ = S.kim_karrila(3.0)
+    assert abs(45 - math.degrees(math.atan(XA / YA)) - 5.891) < 1e-3
+
+
+def test_stokes_field_exact_properties():
+    g = np.random.default_rng(16)
+    U, W, R = g.standard_normal(3), g.standard_normal(3), 2.7
+    # continuity with rigid motion on the sphere
+    e = g.standard_normal((50, 3))
+    e /= np.linalg.norm(e, axis=1)[:, None]
+    on = S.stokes_velocity(R * e * (1 + 1e-12), U, W, R)
+    assert np.allclose(on, U + np.cross(W, R * e), atol=1e-9)
+    # divergence free outside (central differences, h = 1e-4)
+    d = e * g.uniform(1.2 * R, 5 * R, (50, 1))
+    h = 1e-4
+    div = sum((S.stokes_velocity(d + h * np.eye(3)[k], U, W, R)[:, k]
+               - S.stokes_velocity(d - h * np.eye(3)[k], U, W, R)[:, k]) / (2 * h) for k in range(3))
+    assert np.abs(div).max() < 1e-7
+    # far field of pure translation: Stokeslet of force 6 pi mu R U, i.e. (3R/4r)(U + (U.e)e)
+    far = 1e5 * e
+    st = 0.75 * R / 1e5 * (U + (e @ U)[:, None] * e)
+    assert np.allclose(S.stokes_velocity(far, U, 0 * W, R), st, rtol=1e-8, atol=0)
+    # pure rotation: the rotlet, (R/r)^3 W x d at every distance outside
+    assert np.allclose(S.stokes_velocity(d, 0 * U, W, R),
+                       (R / np.linalg.norm(d, axis=1)[:, None]) ** 3 * np.cross(W, d), rtol=1e-13, atol=0)
+
+
+def test_start_field_has_zero_total_momentum():
+    shape = (20, 18, 22)
+    owner = np.zeros(np.prod(shape), dtype=np.uint16)
+    z, y, x = np.meshgrid(np.arange(22), np.arange(18), np.arange(20), indexing="ij")
+    inside = ((x - 9.3) / 4) ** 2 + ((y - 8.6) / 2) ** 2 + ((z - 10.2) / 2) ** 2 < 1
+    owner[inside.ravel()] = 1
+    p = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "U": (1e-3, -2e-4, 5e-4), "W": (1e-5, 2e-5, -3e-5),
+         "M": 4 / 3 * math.pi * 16}
+    u = S.start_field(shape, owner, [p])
+    tot = u[owner == 0].sum(0) + p["M"] * np.array(p["U"])
+    assert np.abs(tot).max() < 1e-15 * np.prod(shape)
+    # solid nodes move rigidly
+    pos = np.stack([x.ravel(), y.ravel(), z.ravel()], 1)[owner == 1]
+    rig = np.array(p["U"]) + np.cross(p["W"], pos - np.array(p["centre"]))
+    assert np.allclose(u[owner == 1], rig, atol=1e-18)
+    f = S.equilibrium(1.0, u)
+    assert np.allclose(f.sum(1), 1.0, atol=1e-15)
