@@ -262,6 +262,87 @@ lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value);
 /* Releases host resources of ctx (not the arena).  Synchronises. */
 lb_status lb_destroy(lb_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  The paper has no learned part: the surrogate and the
+ * warm start serve to reach the steady state of a run in fewer steps.  A
+ * small network maps a particle's shape, confinement and load to its steady
+ * velocities; a run then starts from those velocities and from the creeping
+ * flow around the particle instead of from rest.
+ *
+ * Network: 8 -> 64 -> 64 -> 6, tanh hidden layers, linear output; 5126 FP32
+ * parameters, flat in the order W1[64][8], b1[64], W2[64][64], b2[64],
+ * W3[6][64], b3[6].  Products run on the matrix cores with bfloat16 operands
+ * (inputs, weights, hidden activations, back-propagated errors) and FP32
+ * accumulation.  Loss: mean squared error over the n x 6 outputs.  Training:
+ * Adam (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master
+ * parameters.
+ *
+ * Inputs and outputs (all FP32, row-major, host memory owned by the caller):
+ * for a particle with semi-axes (a, b, c), orientation R(q), external load
+ * (F, T), equal-volume radius Req = (abc)^(1/3), load scale
+ * s = sqrt(|R^T F|^2 + |R^T T|^2 / Req^2) and box volume L^3,
+ *   x = (ln(a / sqrt(bc)), a / L, R^T F / s, R^T T / (Req s)),
+ *   y = (U_body 6 pi mu Req / s, Omega_body 8 pi mu Req^2 / s),  mu = rho0 nu.
+ * ------------------------------------------------------------------------ */
+typedef struct lbs lbs;
+
+/* Device bytes a surrogate needs to hold up to max_samples samples. */
+size_t lbs_arena_bytes(int max_samples);
+
+/* Creates a surrogate in a caller-owned device arena (256-byte aligned, kept
+ * alive until lbs_destroy) working on hip_stream.  Parameters start at zero:
+ * set them with lbs_set_params.  LB_ENOMEM if bytes is too small. */
+lb_status lbs_create(int max_samples, void* dev_arena, size_t bytes, void* hip_stream, lbs** out);
+
+/* Copies 5126 parameters in (and resets the Adam moments and step count) or
+ * out.  Synchronise. */
+lb_status lbs_set_params(lbs* s, const float* params);
+lb_status lbs_get_params(lbs* s, float* params);
+
+/* `epochs` passes over the n samples (X: n x 8, Y: n x 6) in their given
+ * order, in mini-batches of `batch` (the last one may be shorter), one Adam
+ * step of size lr per mini-batch.  *loss (may be NULL) receives the mean
+ * squared error of the last epoch accumulated over its mini-batches.
+ * LB_EINVAL for n < 1, n > max_samples, batch < 1 or epochs < 1.
+ * Synchronises. */
+lb_status lbs_train(lbs* s, const float* X, const float* Y, int n, int epochs, int batch, float lr,
+                    float* loss);
+
+/* Network outputs for n inputs (X: n x 8 -> Y: n x 6).  Synchronises. */
+lb_status lbs_predict(lbs* s, const float* X, int n, float* Y);
+
+/* Loss and its gradient with respect to the 5126 parameters over n samples
+ * (for gradient checks); grads and loss may be NULL.  Synchronises. */
+lb_status lbs_grad(lbs* s, const float* X, const float* Y, int n, float* grads, float* loss);
+
+/* Releases host resources of s (not the arena). */
+lb_status lbs_destroy(lbs* s);
+
+/* Warm start of every particle of the context: the surrogate predicts each
+ * particle's velocities from its current state and external load; they are
+ * set as the particles' velocities, and the fluid of every box is then
+ * started as lb_stokes_start does.  pred (may be NULL) receives the predicted
+ * lab-frame (U, Omega) of every particle, 6 doubles per particle id.  Needs
+ * np <= the surrogate's max_samples; LB_EINVAL for boxes with walls.
+ * Synchronises. */
+lb_status lb_warm_start(lb_ctx* ctx, lbs* s, double* pred);
+
+/* Starts the fluid of every box from the creeping flow of its particles at
+ * their current velocities: each fluid node gets the sum over the box's
+ * particles of the flow around a sphere of the particle's equal-volume radius
+ * translating with U and rotating with Omega (Stokes' solution and the
+ * rotlet, minimum-image offsets; rigid motion within that radius), minus the
+ * uniform velocity that makes the box's total momentum (fluid at rho0 plus
+ * particles) zero; nodes inside a particle move rigidly with it.  Every node
+ * is set to the second-order equilibrium at rho0 and its velocity (mass is
+ * unchanged).  LB_EINVAL if a box has walls.  Synchronises. */
+lb_status lb_stokes_start(lb_ctx* ctx);
+
+/* Bulk read-back of particles [first, first + count): x (unwrapped), q, U, W
+ * as 3, 4, 3, 3 doubles per particle (any pointer may be NULL).
+ * Synchronises. */
+lb_status lb_get_particles(lb_ctx* ctx, int first, int count, double* x, double* q, double* U, double* W);
+
 /* Static text for a status code. */
 const char* lb_status_str(lb_status s);
 

@@ -5,4 +5,4 @@ compute path is the HIP library ``liblbell.so`` behind the C ABI in
 ``include/lbell.h``; ``lbell`` is its Python binding.
 """
 from . import lbell  # noqa: F401
-from .lbell import Lattice, LBError, make_box  # noqa: F401
+from .lbell import Lattice, LBError, Surrogate, make_box  # noqa: F401

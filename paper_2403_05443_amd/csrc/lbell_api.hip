@@ -12,6 +12,7 @@
 #include "lbell.h"
 #include "lbell_dev.h"
 #include "lbell_launch.h"
+#include "lbs_internal.h"
 
 using namespace lbd;
 
@@ -26,7 +27,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
-           flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, total = 0;
+           flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, warm = 0, total = 0;
     int near_blocks = 0;  // collide-stream blocks that a near set can name (per slot)
     std::vector<long long> foff, stride, ooff;
     std::vector<int> tile0, ntiles;
@@ -124,6 +125,9 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     L.near_flags = take(sizeof(uint32_t) * 2 * L.near_blocks);
     L.near_list = take(sizeof(int) * 2 * L.near_blocks);
     L.near_count = take(sizeof(int) * 4);
+    // warm start: per-tile partial sums (4), per-box mean velocity (3), per
+    // particle load scale (1) and prediction (6)
+    L.warm = take(sizeof(double) * ((size_t)4 * tiles + 3 * (size_t)nboxes + 7 * (size_t)L.max_particles));
     L.total = p;
     return L;
 }
@@ -1125,6 +1129,70 @@ lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value) {
                      ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
     return LB_OK;
+}
+
+lb_status lb_get_particles(lb_ctx* ctx, int first, int count, double* x, double* q, double* U, double* W) {
+    if (!ctx || first < 0 || count < 0 || first + count > ctx->np) return LB_EINVAL;
+    if (count == 0) return LB_OK;
+    std::vector<PartDev> P((size_t)count);
+    HIPC(hipMemcpyAsync(P.data(), ctx->at<PartDev>(ctx->L.parts) + first, sizeof(PartDev) * count,
+                        hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < count; ++i)
+        for (int k = 0; k < 4; ++k) {
+            if (k < 3) {
+                if (x) x[3 * i + k] = P[i].xu[k];
+                if (U) U[3 * i + k] = P[i].U[k];
+                if (W) W[3 * i + k] = P[i].W[k];
+            }
+            if (q) q[4 * i + k] = P[i].q[k];
+        }
+    return flags_status(ctx);
+}
+
+namespace {
+lb_status stokes_start(lb_ctx* ctx) {
+    for (const auto& b : ctx->boxes)
+        if (b.walls) return fail(ctx, LB_EINVAL, "the start field is defined for periodic boxes only");
+    double* warm = ctx->at<double>(ctx->L.warm);
+    HIPC(launch_stokes_start(ctx->at<BoxDesc>(ctx->L.boxes), (int)ctx->boxes.size(), ctx->at<int>(ctx->L.tile_box),
+                             ctx->L.total_tiles, ctx->at<uint16_t>(ctx->L.omap), ctx->at<PartDev>(ctx->L.parts),
+                             ctx->np, warm, warm + 4 * (size_t)ctx->L.total_tiles, ctx->fbuf(ctx->cur), ctx->kp,
+                             ctx->stream));
+    return LB_OK;
+}
+}  // namespace
+
+lb_status lb_stokes_start(lb_ctx* ctx) {
+    if (!ctx) return LB_EINVAL;
+    lb_status s = stokes_start(ctx);
+    if (s != LB_OK) return s;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return flags_status(ctx);
+}
+
+lb_status lb_warm_start(lb_ctx* ctx, lbs* sur, double* pred) {
+    if (!ctx || !sur) return LB_EINVAL;
+    if (ctx->np == 0) return LB_OK;
+    if (ctx->np > sur->max_n) return fail(ctx, LB_EINVAL, "more particles than the surrogate's sample capacity");
+    for (const auto& b : ctx->boxes)
+        if (b.walls) return fail(ctx, LB_EINVAL, "the warm start is defined for periodic boxes only");
+    // the surrogate's work goes on the context's stream, after the steps already queued there
+    double* warm = ctx->at<double>(ctx->L.warm);
+    double* sc = warm + 4 * (size_t)ctx->L.total_tiles + 3 * ctx->boxes.size();
+    double* pr = sc + ctx->L.max_particles;
+    PartDev* parts = ctx->at<PartDev>(ctx->L.parts);
+    HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, sur->X, sc, ctx->stream));
+    MlpArgs a{sur->P, sur->X, nullptr, sur->out, nullptr, nullptr, ctx->np, 0.f, 0};
+    HIPC(launch_mlp(a, ctx->stream));
+    const double mu = ctx->kp.rho0 * (1.0 / ctx->kp.omega - 0.5) / 3.0;
+    HIPC(launch_warm_apply(parts, ctx->np, sur->out, sc, mu, pr, ctx->stream));
+    lb_status s = stokes_start(ctx);
+    if (s != LB_OK) return s;
+    if (pred)
+        HIPC(hipMemcpyAsync(pred, pr, sizeof(double) * 6 * ctx->np, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return flags_status(ctx);
 }
 
 lb_status lb_destroy(lb_ctx* ctx) {

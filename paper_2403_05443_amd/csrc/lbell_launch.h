@@ -73,4 +73,46 @@ hipError_t launch_particle_step(const LaunchPart& a, hipStream_t st);  // solve 
 size_t particle_remap_lds_bytes(int lds_words);
 hipError_t launch_near_mark(const LaunchPart& a, hipStream_t st);
 
+// ---- warm-start surrogate: 8 -> 64 -> 64 -> 6 tanh MLP (k_mlp.hip) ----
+constexpr int MLP_IN = 8, MLP_H = 64, MLP_OUT = 6;
+// flat parameters: W1[64][8], b1[64], W2[64][64], b2[64], W3[6][64], b3[6]
+constexpr int MLP_OW1 = 0, MLP_OB1 = MLP_OW1 + MLP_H * MLP_IN, MLP_OW2 = MLP_OB1 + MLP_H,
+              MLP_OB2 = MLP_OW2 + MLP_H * MLP_H, MLP_OW3 = MLP_OB2 + MLP_H, MLP_OB3 = MLP_OW3 + MLP_OUT * MLP_H,
+              MLP_NP = MLP_OB3 + MLP_OUT;
+
+struct MlpArgs {
+    const float* P;   // FP32 parameters
+    const float* X;   // n x 8 inputs
+    const float* Y;   // n x 6 targets (mode 1)
+    float* out;       // n x 6 outputs (mode 0)
+    float* G;         // per-tile partial gradients, ceil(n / 16) x MLP_NP (mode 1)
+    float* Lpart;     // per-tile sums of squared errors (mode 1)
+    int n;
+    float scale;      // dL/dy = scale * (y - Y)
+    int mode;         // 0 forward, 1 forward + backward
+};
+struct MlpReduceArgs {
+    const float* G;
+    const float* Lpart;
+    int ntiles;
+    float* P;
+    float* M;
+    float* V;
+    float lr, c1, c2;  // Adam: step size, 1 / (1 - beta1^t), 1 / (1 - beta2^t)
+    float* gsum;       // mode 1: summed gradient
+    double* loss_acc;  // += sum of the tiles' squared errors (may be null)
+    int mode;          // 0 Adam update, 1 write the summed gradient
+};
+hipError_t launch_mlp(const MlpArgs& a, hipStream_t st);
+hipError_t launch_mlp_reduce(const MlpReduceArgs& a, hipStream_t st);
+
+// ---- warm start (k_warm.hip) ----
+hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, float* X, double* s,
+                                hipStream_t st);
+hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const double* s, double mu, double* pred,
+                             hipStream_t st);
+hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
+                               const uint16_t* omap, const PartDev* parts, int np, double* partial, double* ubar,
+                               void* f, const KParams& kp, hipStream_t st);
+
 }  // namespace lbd

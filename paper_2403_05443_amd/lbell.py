@@ -41,6 +41,7 @@ class Box(C.Structure):
 
 # every entry point of include/lbell.h with its argument types
 _D = C.POINTER(C.c_double)
+_F = C.POINTER(C.c_float)
 _VP = C.c_void_p
 SIGNATURES = {
     "lb_config_default": (C.c_int, [C.POINTER(Config)]),
@@ -72,6 +73,17 @@ SIGNATURES = {
     "lb_save": (C.c_int, [_VP, C.c_char_p]),
     "lb_load": (C.c_int, [_VP, C.c_char_p]),
     "lb_debug_poke": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_double]),
+    "lb_get_particles": (C.c_int, [_VP, C.c_int, C.c_int, _D, _D, _D, _D]),
+    "lb_stokes_start": (C.c_int, [_VP]),
+    "lb_warm_start": (C.c_int, [_VP, _VP, _D]),
+    "lbs_arena_bytes": (C.c_size_t, [C.c_int]),
+    "lbs_create": (C.c_int, [C.c_int, _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
+    "lbs_set_params": (C.c_int, [_VP, _F]),
+    "lbs_get_params": (C.c_int, [_VP, _F]),
+    "lbs_train": (C.c_int, [_VP, _F, _F, C.c_int, C.c_int, C.c_int, C.c_float, _F]),
+    "lbs_predict": (C.c_int, [_VP, _F, C.c_int, _F]),
+    "lbs_grad": (C.c_int, [_VP, _F, _F, C.c_int, _F, _F]),
+    "lbs_destroy": (C.c_int, [_VP]),
     "lb_destroy": (C.c_int, [_VP]),
     "lb_status_str": (C.c_char_p, [C.c_int]),
     "lb_last_error": (C.c_char_p, [_VP]),
@@ -314,3 +326,105 @@ class Lattice:
 
     def poke(self, box, site, direction, value):
         self._chk(self.lib.lb_debug_poke(self.ctx, int(box), int(site), int(direction), float(value)))
+
+    def particles(self, first=0, count=None):
+        """Bulk read-back: dict of arrays x (n,3), q (n,4), U (n,3), W (n,3)."""
+        n = self.np - first if count is None else int(count)
+        x, q, U, W = np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3)), np.zeros((n, 3))
+        self._chk(self.lib.lb_get_particles(self.ctx, int(first), n, _p(x), _p(q), _p(U), _p(W)))
+        return {"x": x, "q": q, "U": U, "W": W}
+
+    def stokes_start(self):
+        """Start the fluid from the creeping flow of the particles' current velocities."""
+        self._chk(self.lib.lb_stokes_start(self.ctx))
+
+    def warm_start(self, surrogate):
+        """Surrogate warm start of every particle; returns the predicted lab-frame
+        (U, Omega) per particle, shape (np, 6)."""
+        pred = np.zeros((max(self.np, 1), 6))
+        self._chk(self.lib.lb_warm_start(self.ctx, surrogate.handle, _p(pred)))
+        return pred[:self.np]
+
+
+def _fp(a):
+    return a.ctypes.data_as(_F)
+
+
+class Surrogate:
+    """The warm-start network on the GPU (8 -> 64 -> 64 -> 6, bfloat16 matrix
+    products); parameters, Adam state and data live in a torch-allocated arena."""
+
+    N_PARAMS = 5126
+
+    def __init__(self, max_samples=65536, params=None, device="cuda:0"):
+        import torch
+        self.lib = load()
+        self.max_samples = int(max_samples)
+        nbytes = self.lib.lbs_arena_bytes(self.max_samples)
+        if nbytes == 0:
+            raise LBError(-1, "invalid surrogate capacity")
+        self.device = torch.device(device)
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.arena.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = self.lib.lbs_create(self.max_samples, C.c_void_p(aligned), C.c_size_t(nbytes),
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise LBError(st, "lbs_create failed")
+        self.handle = h
+        if params is not None:
+            self.set_params(params)
+
+    def _chk(self, st, what):
+        if st != 0:
+            raise LBError(st, what)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(self.N_PARAMS)
+        self._chk(self.lib.lbs_set_params(self.handle, _fp(p)), "lbs_set_params")
+
+    def params(self):
+        p = np.zeros(self.N_PARAMS, dtype=np.float32)
+        self._chk(self.lib.lbs_get_params(self.handle, _fp(p)), "lbs_get_params")
+        return p
+
+    @staticmethod
+    def _xy(X, Y=None):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 8)
+        if Y is not None:
+            Y = np.ascontiguousarray(Y, dtype=np.float32).reshape(-1, 6)
+        return X, Y
+
+    def train(self, X, Y, epochs, batch=256, lr=1e-3):
+        """Adam over the samples in their given order; returns the last epoch's mean loss."""
+        X, Y = self._xy(X, Y)
+        loss = np.zeros(1, dtype=np.float32)
+        self._chk(self.lib.lbs_train(self.handle, _fp(X), _fp(Y), X.shape[0], int(epochs), int(batch),
+                                     float(lr), _fp(loss)), "lbs_train")
+        return float(loss[0])
+
+    def predict(self, X):
+        X, _ = self._xy(X)
+        Y = np.zeros((X.shape[0], 6), dtype=np.float32)
+        self._chk(self.lib.lbs_predict(self.handle, _fp(X), X.shape[0], _fp(Y)), "lbs_predict")
+        return Y
+
+    def grad(self, X, Y):
+        """(loss, gradient) of the mean squared error."""
+        X, Y = self._xy(X, Y)
+        g = np.zeros(self.N_PARAMS, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        self._chk(self.lib.lbs_grad(self.handle, _fp(X), _fp(Y), X.shape[0], _fp(g), _fp(loss)), "lbs_grad")
+        return float(loss[0]), g
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lbs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
