@@ -30,18 +30,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2403_05443_amd", "csrc", "k_stream.hip")
 
 
 def build_lattice(W, device="cuda:0"):
-    from paper_2403_05443_amd import Lattice, make_box
-    boxes = [make_box(*b.shape, walls=b.walls, wall_lo=b.wall_lo, wall_hi=b.wall_hi, init=b.init)
-             for b in W.boxes]
-    lat = Lattice(boxes, collision=W.collision, tau=W.tau, magic=W.magic, storage=W.storage,
-                  counterforce=W.counterforce, velocity_scale=W.velocity_scale,
-                  max_particles=max(1, len(W.particles)), max_semi_axis=W.max_semi_axis, device=device)
-    for p in W.particles:
-        pid = lat.add_ellipsoid(p.centre, p.axes, p.quat, box=p.box)
-        lat.set_external(pid, p.force, p.torque)
-        if p.squirmer != (0.0, 0.0):
-            lat.set_squirmer(pid, *p.squirmer)
-    return lat
+    from paper_2403_05443_amd.runner import build_lattice as build
+    return build(W, device)
 
 
 def traffic_record(src_sha, workload, storage, variant):
@@ -173,6 +163,44 @@ def measure(W, steps, warmup, graph_steps, variant=None, psteps=200):
     }
 
 
+def steps_to_steady(runs, eval_boxes):
+    """The second half of the metric: train the warm-start network on `runs`
+    256-box FP16 ensembles (alternately with and without torques; symmetry
+    augmentation, 80/20 split), then count the steps a held-out force-driven
+    FP16 ensemble needs to come within 0.5% of its steady velocity from a
+    plain start, a surrogate warm start and the closed-form control."""
+    from paper_2403_05443_amd import runner, workloads
+    import numpy as np
+    t0 = time.perf_counter()
+    Xs, Ys, steps = [], [], 0
+    for k in range(runs):
+        W = workloads.c4("fp16", 256, seed_index=10 + k, torque=(k % 2 == 0))
+        X, Y, n = runner.ensemble_samples(W, efolds=8)
+        Xs.append(X)
+        Ys.append(Y)
+        steps += n
+    t_data = time.perf_counter() - t0
+    Xa, Ya = runner.augment(np.concatenate(Xs), np.concatenate(Ys))
+    sur, info = runner.train_surrogate(Xa, Ya, epochs=300)
+    t_train = time.perf_counter() - t0 - t_data
+    We = workloads.c4("fp16", eval_boxes, seed_index=100, torque=False)
+    res = runner.compare_starts(We, sur)
+    t_eval = time.perf_counter() - t0 - t_data - t_train
+    m = res["median_steps"]
+    return {"eval_workload": We.name, "storage": "fp16", "boxes": res["boxes"], "steady_boxes": res["steady_boxes"],
+            "tol": res["tol"], "sample_every": res["every"],
+            "median_steps_plain": m["plain"], "median_steps_surrogate": m["surrogate"],
+            "median_steps_control": m["control"],
+            "surrogate_over_plain": round(res["surrogate_over_plain"], 4),
+            "control_over_plain": round(res["control_over_plain"], 4),
+            "median_prediction_error": round(res["median_prediction_error"], 5),
+            "fallback_rate": round(res["fallback_rate"], 4),
+            "training": {"ensembles": runs, "lb_steps_per_ensemble": steps // max(runs, 1),
+                         "samples": info["samples"], "loss_val": info["loss_val"],
+                         "val_target_variance": info["val_target_variance"]},
+            "seconds": {"data": round(t_data, 2), "train": round(t_train, 2), "eval": round(t_eval, 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +213,9 @@ def main():
                     help="collide-stream variant to use instead of the tuner's choice (see lb_autotune)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-box FP16 ensemble reported beside the main line (0: skip)")
+    ap.add_argument("--surrogate-runs", type=int, default=4,
+                    help="256-box FP16 ensembles run to train the warm-start network (0: skip steps to steady)")
+    ap.add_argument("--eval-boxes", type=int, default=64, help="held-out force-driven boxes for steps to steady")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-bytes", type=int, default=1 << 30,
@@ -246,6 +277,8 @@ def main():
                            "k1_achieved_gbs": round(e["achieved_gbs"], 1),
                            "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
                            "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
+    if args.surrogate_runs > 0:
+        out["steps_to_steady"] = steps_to_steady(args.surrogate_runs, args.eval_boxes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -236,7 +236,9 @@ lb_status lb_get_mask(lb_ctx* ctx, int box, uint16_t* owner);
  * Either pointer may be NULL.  Synchronises. */
 lb_status lb_get_fields(lb_ctx* ctx, int box, double* rho, double* u);
 
-/* Conserved mass of box: sum of rho over fluid nodes plus dm of its particles.
+/* Conserved mass of box: sum of rho over fluid nodes, rho0 for every node
+ * inside a particle (a node changing side carries rho0 with it), plus the
+ * pending excess mass dm of its particles.
  * Momentum: sum of rho*u over fluid nodes (particles not included).
  * Synchronises. */
 lb_status lb_get_mass(lb_ctx* ctx, int box, double* mass);
@@ -319,24 +321,36 @@ lb_status lbs_grad(lbs* s, const float* X, const float* Y, int n, float* grads, 
 lb_status lbs_destroy(lbs* s);
 
 /* Warm start of every particle of the context: the surrogate predicts each
- * particle's velocities from its current state and external load; they are
- * set as the particles' velocities, and the fluid of every box is then
- * started as lb_stokes_start does.  pred (may be NULL) receives the predicted
+ * particle's steady velocities from its current state and external load;
+ * they are set as the particles' velocities, and the fluid of every box is
+ * then started as lb_stokes_start does.  pred (may be NULL) receives the predicted
  * lab-frame (U, Omega) of every particle, 6 doubles per particle id.  Needs
  * np <= the surrogate's max_samples; LB_EINVAL for boxes with walls.
  * Synchronises. */
 lb_status lb_warm_start(lb_ctx* ctx, lbs* s, double* pred);
 
-/* Starts the fluid of every box from the creeping flow of its particles at
- * their current velocities: each fluid node gets the sum over the box's
- * particles of the flow around a sphere of the particle's equal-volume radius
- * translating with U and rotating with Omega (Stokes' solution and the
- * rotlet, minimum-image offsets; rigid motion within that radius), minus the
- * uniform velocity that makes the box's total momentum (fluid at rho0 plus
- * particles) zero; nodes inside a particle move rigidly with it.  Every node
- * is set to the second-order equilibrium at rho0 and its velocity (mass is
- * unchanged).  LB_EINVAL if a box has walls.  Synchronises. */
+/* Starts the fluid of every box from the creeping flow its particles'
+ * external loads drive.  Each node gets the sum over the box's particles of
+ * the free-space flow of a sphere of the particle's equal-volume radius R
+ * moving with F_ext / (6 pi mu R) and turning with T_ext / (8 pi mu R^3)
+ * (Stokes' solution and the rotlet at minimum-image offsets; rigid motion
+ * within R), whose Fourier modes |n_i| <= 2 of the box (fewer along an edge
+ * shorter than 5) are replaced by those of the periodic flow of the same
+ * loads (uniform surface traction on the sphere), so the box's slowest shear
+ * modes start at their steady values.  The fluid nodes then lose the uniform
+ * velocity that makes the box's total momentum (fluid at rho0 plus the
+ * particles' M U) zero; nodes inside a particle move rigidly with its
+ * current U, Omega.  Every node is set to the second-order equilibrium at
+ * rho0 and its velocity (mass is unchanged).  LB_EINVAL if a box has walls.
+ * Synchronises. */
 lb_status lb_stokes_start(lb_ctx* ctx);
+
+/* Training sample of every particle at its current state: the surrogate's
+ * inputs (X, 8 floats per particle id) and its normalised body-frame
+ * response at the particle's current velocities (Y, 6 floats per particle:
+ * the inverse of the output scaling above; zero for an unloaded particle).
+ * Synchronises. */
+lb_status lb_surrogate_sample(lb_ctx* ctx, float* X, float* Y);
 
 /* Bulk read-back of particles [first, first + count): x (unwrapped), q, U, W
  * as 3, 4, 3, 3 doubles per particle (any pointer may be NULL).

@@ -18,10 +18,13 @@
  *   R6  dI/dt uses Omega(t) (step 4 precedes the solve);
  *   R7  bounce-back uses U(t+1), Omega(t+1) and x_c(t) (step 6 precedes 7);
  *   R8  external force/torque enter the right-hand side of the solve;
- *   R9  covered node: its mass and momentum go to the particle; uncovered
- *       node: f = f_eq(rho0, U + Omega x r) and the particle pays for it; the
- *       mass difference dm is returned at the next bounce-back spread over the
- *       links as dm * w_b / sum_b w_b;
+ *   R9  a node that changes side carries the rest density rho0 with it (no
+ *       fluid inside the particle, Sec. II.B): a covered node's momentum and
+ *       its mass in excess of rho0 go to the particle; an uncovered node gets
+ *       f = f_eq(rho0, U + Omega x r), its momentum paid by the particle; the
+ *       excess mass dm is returned at the next bounce-back spread over the
+ *       links as dm * w_b / sum_b w_b.  Conserved: the box mass counting
+ *       every particle node at rho0 (or_get_mass);
  *   R10 optional counter-force: a uniform force density g = -sum F_ext / N on
  *       all matter of the box (N = non-wall nodes), so total momentum stays
  *       zero: every fluid node gets f* += w_i (c_i . g)/c_s^2 after collision
@@ -576,8 +579,7 @@ static int remap(or_sim* s, int apply) {
                 cross(p->W, r, wr);
                 for (i = 0; i < 3; i++) u[i] = p->U[i] + wr[i];
                 or_equilibrium(s->rho0, u, feq);
-                for (i = 0; i < NQ; i++) s->f[st * NQ + i] = feq[i];
-                p->dm -= s->rho0;
+                for (i = 0; i < NQ; i++) s->f[st * NQ + i] = feq[i];  /* mass rho0: no excess */
                 for (i = 0; i < 3; i++) u[i] *= s->rho0;
                 cross(r, u, L);
                 for (i = 0; i < 3; i++) {
@@ -586,7 +588,7 @@ static int remap(or_sim* s, int apply) {
                 }
             }
             if (m > 0) {
-                /* covered by particle m-1 (R9): mass and momentum to the particle */
+                /* covered by particle m-1 (R9): momentum and excess mass to the particle */
                 opart* p = &s->p[m - 1];
                 double r[3], mass = 0, P[3] = {0, 0, 0}, L[3];
                 for (i = 0; i < NQ; i++) {
@@ -598,7 +600,7 @@ static int remap(or_sim* s, int apply) {
                 }
                 rel(s, p->xc, x, y, z, r);
                 cross(r, P, L);
-                p->dm += mass;
+                p->dm += mass - s->rho0;
                 for (i = 0; i < 3; i++) {
                     p->Pp[i] += P[i];
                     p->Lp[i] += L[i];
@@ -951,9 +953,12 @@ static void nadd(nsum* a, double v) {
 double or_get_mass(const or_sim* s) {
     nsum m = {0.0, 0.0};
     int st, i, pid;
-    for (st = 0; st < s->n; st++)
+    for (st = 0; st < s->n; st++) {
         if (s->node[st] == 0)
             for (i = 0; i < NQ; i++) nadd(&m, s->f[st * NQ + i]);
+        else if (s->node[st] > 0)
+            nadd(&m, s->rho0); /* particle node counted at the rest density (R9) */
+    }
     for (pid = 0; pid < s->np; pid++) nadd(&m, s->p[pid].dm);
     return m.s + m.c;
 }

@@ -39,6 +39,7 @@ int     or_get_zeta(const or_sim* s, int id, double z[36]);
 int     or_get_links(const or_sim* s, int id, uint32_t* site, uint8_t* dir, int cap);
 void    or_get_mask(const or_sim* s, uint16_t* owner);
 void    or_get_fields(const or_sim* s, double* rho, double* u);
+/* box mass counting every particle node at rho0, plus pending excess (R9) */
 double  or_get_mass(const or_sim* s);
 void    or_get_momentum(const or_sim* s, double P[3]);
 long long or_get_step(const or_sim* s);

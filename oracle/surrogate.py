@@ -204,27 +204,89 @@ def stokes_velocity(d, U, W, R):
     return np.where(r >= R, out, rigid)
 
 
-def start_field(shape, owner, particles):
-    """Velocity of every node of a periodic box for the warm start.
+KMAX = 2  # Fourier modes |n_i| <= KMAX of the box carry the periodic correction
 
-    particles: list of dicts (centre, axes, U, W, M).  Fluid nodes (owner 0)
-    take the sum over particles of the sphere field (equal-volume radius,
-    minimum-image offsets) minus the uniform velocity that makes the total
-    momentum (fluid at rho0 = 1 plus particles) zero; nodes of particle p take
-    its rigid motion U + W x d."""
+
+def periodic_modes(k, F, T, R, mu, V):
+    """Fourier coefficients (1/V) u_hat(k) of the creeping flow driven by a
+    force F and a torque T spread over a sphere of radius R (uniform surface
+    traction), at wave vectors k (m, 3), none zero, for a periodic box of
+    volume V, centre at the origin:
+      u_hat = (I - k k / k^2) F sinc(kR) / (mu k^2) + i (k x T) [3 j1(kR) / (kR)] / (2 mu k^2)."""
+    k = np.atleast_2d(np.asarray(k, float))
+    F, T = np.asarray(F, float), np.asarray(T, float)
+    k2 = (k * k).sum(1)
+    x = np.sqrt(k2) * R
+    sinc = np.sin(x) / x
+    j1f = 3 * (np.sin(x) / x - np.cos(x)) / (x * x)   # 3 j1(x) / x, 1 at x -> 0
+    Pf = F[None, :] - k * ((k @ F) / k2)[:, None]
+    return (Pf * (sinc / (mu * k2))[:, None] + 1j * np.cross(k, T) * (j1f / (2 * mu * k2))[:, None]) / V
+
+
+def periodic_coefficients(shape, centre, F, T, R, mu):
+    """Low-mode content (|n_i| <= KMAX, n != 0; fewer along an axis shorter
+    than 2 KMAX + 1) of the periodic flow of a sphere at `centre`:
+    periodic_modes at k = 2 pi n / L times exp(-i k . x_c).  Returns (list of
+    n, complex array (len, 3))."""
+    L = np.asarray(shape, float)
+    K = [min(KMAX, (int(l) - 1) // 2) for l in shape]
+    ns = [(nx, ny, nz) for nz in range(-K[2], K[2] + 1) for ny in range(-K[1], K[1] + 1)
+          for nx in range(-K[0], K[0] + 1) if (nx, ny, nz) != (0, 0, 0)]
+    k = 2 * np.pi * np.array(ns, float) / L
+    c = periodic_modes(k, F, T, R, mu, float(np.prod(L)))
+    return ns, c * np.exp(-1j * (k @ np.asarray(centre, float)))[:, None]
+
+
+def free_field(shape, particles, mu):
+    """Sum over the particles of the free-space flow of a sphere (equal-volume
+    radius) driven by the particle's load, at minimum-image offsets: the
+    sphere moves with F / (6 pi mu R) and turns with T / (8 pi mu R^3)."""
     nx, ny, nz = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(float)
     u = np.zeros((pos.shape[0], 3))
+    for p in particles:
+        R = req(p["axes"])
+        d = min_image(pos - np.asarray(p["centre"], float), shape)
+        u += stokes_velocity(d, np.asarray(p["F"], float) / (6 * math.pi * mu * R),
+                             np.asarray(p["T"], float) / (8 * math.pi * mu * R ** 3), R)
+    return pos, u
+
+
+def start_field(shape, owner, particles, mu):
+    """Velocity of every node of a periodic box for the warm start.
+
+    particles: list of dicts (centre, axes, F, T: the external load, U, W:
+    the particle's velocities, M).  The fluid field is the free-space sphere
+    flow of every particle's load (free_field) whose Fourier modes
+    |n_i| <= KMAX are replaced by those of the periodic solution
+    (periodic_coefficients), so the slow modes of the box start at their
+    steady values; the DFT is over all nodes (numpy's FFT).  Fluid nodes
+    (owner 0) then lose the uniform velocity that makes the total momentum
+    (fluid at rho0 = 1 plus particles M U) zero; nodes of particle p move
+    rigidly with its U, W."""
+    nx, ny, nz = shape
+    pos, u = free_field(shape, particles, mu)
+    N = nx * ny * nz
+    grid = u.reshape(nz, ny, nx, 3)
+    S = np.fft.fftn(grid, axes=(0, 1, 2))            # sum_x u exp(-2 pi i n . x / L)
+    corr = np.zeros(3 * N, dtype=complex).reshape(N, 3)
+    for p in particles:
+        ns, c = periodic_coefficients(shape, p["centre"], p["F"], p["T"], req(p["axes"]), mu)
+        for n, cn in zip(ns, c):
+            corr += cn[None, :] * np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / np.asarray(shape, float))))[:, None]
+    ns, _ = periodic_coefficients(shape, (0, 0, 0), (0, 0, 0), (0, 0, 0), 1.0, 1.0)
+    for n in ns:
+        dft = S[n[2] % nz, n[1] % ny, n[0] % nx] / N
+        corr -= dft[None, :] * np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / np.asarray(shape, float))))[:, None]
+    u = u + corr.real
     owner = np.asarray(owner).ravel()
     fluid = owner == 0
     P = np.zeros(3)
     for k, p in enumerate(particles):
-        d = min_image(pos - np.asarray(p["centre"], float), shape)
-        f = stokes_velocity(d, p["U"], p["W"], req(p["axes"]))
-        u[fluid] += f[fluid]
         mine = owner == k + 1
-        u[mine] = np.asarray(p["U"], float) + np.cross(np.asarray(p["W"], float), d[mine])
+        d = min_image(pos[mine] - np.asarray(p["centre"], float), shape)
+        u[mine] = np.asarray(p["U"], float) + np.cross(np.asarray(p["W"], float), d)
         P += p["M"] * np.asarray(p["U"], float)
     ubar = (u[fluid].sum(0) + P) / fluid.sum()
     u[fluid] -= ubar

@@ -639,7 +639,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                         if (mode == 0) {
                             const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
                                                  minimg((double)gz - xc[2], nz)};
-                            if (in) {  // covered: its fluid mass and momentum go to the particle
+                            if (in) {  // covered: its momentum and its mass in excess of rho0 go to the particle
                                 double m = 0, pm[3] = {0, 0, 0};
                                 for (int j = 0; j < NQ; ++j) {
                                     int dir, slot;
@@ -651,7 +651,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                     pm[1] += rcy(j) * v;
                                     pm[2] += rcz(j) * v;
                                 }
-                                tacc[0] += rho0 + m;
+                                tacc[0] += m;
                                 tacc[1] += pm[0];
                                 tacc[2] += pm[1];
                                 tacc[3] += pm[2];
@@ -671,7 +671,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                     const double dev = (rw36(j) / 36.0) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
                                     S::st64(f + (long long)dir * st + slot, dev - add, scl);
                                 }
-                                tacc[0] -= rho0;
+                                // the new node holds rho0: no excess mass
                                 const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
                                 tacc[1] -= pu[0];
                                 tacc[2] -= pu[1];

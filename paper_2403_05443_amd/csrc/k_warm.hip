@@ -9,13 +9,18 @@
 // Outputs y are the body-frame velocities in units of the Stokes scales:
 //   U_b = y[0:3] s / (6 pi mu Req),  Omega_b = y[3:6] s / (8 pi mu Req^2).
 //
-// Start field (one thread per node): fluid nodes take the sum over the
-// box's particles of the flow around a sphere of radius Req translating with
-// U and rotating with Omega (Stokes' solution and the rotlet), at the
-// minimum-image offset, minus the uniform velocity that makes the box's total
-// momentum (fluid at rho0 plus particles) zero; nodes inside particle p move
-// rigidly with it.  Every node gets the second-order equilibrium at rho0 and
-// its velocity, written as pre-collision populations (slot (x - c_i, i)).
+// Start field: the creeping flow the particles' loads drive in the periodic
+// box.  Per node, the sum over the box's particles of the free-space flow
+// of a sphere of radius Req moving with F / (6 pi mu Req) and turning with
+// T / (8 pi mu Req^3) (Stokes' solution and the rotlet, minimum-image
+// offsets; rigid inside Req) -- whose Fourier modes |n_i| <= 2 are replaced
+// by those of the periodic solution of the same loads (uniform surface
+// traction on the sphere), so the box's slowest shear modes start at their
+// steady values; then the uniform velocity that makes the box's total
+// momentum (fluid at rho0 plus particles) zero is removed from the fluid
+// nodes, and nodes inside particle p move rigidly with its U, Omega.  Every
+// node gets the second-order equilibrium at rho0 and its velocity, written as
+// pre-collision populations (slot (x - c_i, i)).
 #include "lbell_dev.h"
 #include "lbell_launch.h"
 
@@ -81,6 +86,24 @@ __global__ void k_warm_apply(PartDev* __restrict__ parts, int np, const float* _
     }
 }
 
+// Normalised body-frame response of every particle at its current
+// velocities (the training target of the surrogate; inverse of k_warm_apply).
+__global__ void k_warm_targets(const PartDev* __restrict__ parts, int np, const double* __restrict__ s_in,
+                               double mu, float* __restrict__ Y) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const PartDev& P = parts[p];
+    double Rm[3][3];
+    body_to_lab(P.q, Rm);
+    const double R = eq_radius(P), s = s_in[p];
+    const double cu = s > 0 ? 6.0 * M_PI * mu * R / s : 0.0, cw = s > 0 ? 8.0 * M_PI * mu * R * R / s : 0.0;
+    float* y = Y + (long long)p * MLP_OUT;
+    for (int k = 0; k < 3; ++k) {
+        y[k] = (float)(cu * (Rm[0][k] * P.U[0] + Rm[1][k] * P.U[1] + Rm[2][k] * P.U[2]));
+        y[3 + k] = (float)(cw * (Rm[0][k] * P.W[0] + Rm[1][k] * P.W[1] + Rm[2][k] * P.W[2]));
+    }
+}
+
 // minimum-image offset of node (x, y, z) from the particle centre
 __device__ __forceinline__ void offset(const PartDev& P, const BoxDesc& B, int x, int y, int z, double d[3]) {
     const int n[3] = {B.nx, B.ny, B.nz};
@@ -93,11 +116,68 @@ __device__ __forceinline__ void offset(const PartDev& P, const BoxDesc& B, int x
     }
 }
 
-// Velocity of node (x, y, z) of box bi before the mean correction: rigid
-// motion inside a particle, else the sum of the particles' sphere fields.
-__device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const PartDev* __restrict__ parts, int np,
-                               int x, int y, int z, double u[3]) {
+constexpr int WK = 2;                  // modes |n_i| <= WK carry the periodic correction
+constexpr int WM = (2 * WK + 1) * (2 * WK + 1) * (2 * WK + 1);  // mode slots per box (index 62 = n = 0)
+
+__device__ __forceinline__ int wk_axis(int L) { return min(WK, (L - 1) / 2); }
+
+// Free-space flow at node (x, y, z) of box bi: the sum over the box's
+// particles of the flow of a load-driven sphere (fluid nodes and, for the
+// Fourier analysis, every node).
+__device__ void free_velocity(const BoxDesc& B, int bi, const PartDev* __restrict__ parts, int np, double mu, int x,
+                              int y, int z, double u[3]) {
     u[0] = u[1] = u[2] = 0.0;
+    for (int p = 0; p < np; ++p) {
+        const PartDev& P = parts[p];
+        if (P.box != bi) continue;
+        double d[3];
+        offset(P, B, x, y, z, d);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double R = eq_radius(P);
+        const double cu = 1.0 / (6.0 * M_PI * mu * R), cw = 1.0 / (8.0 * M_PI * mu * R * R * R);
+        const double U[3] = {P.Fext[0] * cu, P.Fext[1] * cu, P.Fext[2] * cu};
+        const double W[3] = {P.Text[0] * cw, P.Text[1] * cw, P.Text[2] * cw};
+        const double wx[3] = {W[1] * d[2] - W[2] * d[1], W[2] * d[0] - W[0] * d[2], W[0] * d[1] - W[1] * d[0]};
+        if (r < R) {  // inside the sphere: rigid motion
+            for (int k = 0; k < 3; ++k) u[k] += U[k] + wx[k];
+            continue;
+        }
+        const double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+        const double Ue = U[0] * e[0] + U[1] * e[1] + U[2] * e[2];
+        const double a1 = 0.75 * R / r, a3 = 0.25 * R * R * R / (r * r * r), rr = (R / r) * (R / r) * (R / r);
+        for (int k = 0; k < 3; ++k)
+            u[k] += a1 * (U[k] + Ue * e[k]) + a3 * (U[k] - 3.0 * Ue * e[k]) + rr * wx[k];
+    }
+}
+
+// Periodic correction Re sum_m c_m exp(i k_m . x) at node (x, y, z); c: the
+// box's WM x 3 complex coefficients (re, im), zero for unused slots.
+__device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x, int y, int z, double u[3]) {
+    const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
+    double ex[2 * WK + 1][2];
+    for (int n = -Kx; n <= Kx; ++n) sincospi(2.0 * n * x / B.nx, &ex[n + WK][1], &ex[n + WK][0]);
+    for (int nz = -Kz; nz <= Kz; ++nz) {
+        double sz, cz;
+        sincospi(2.0 * nz * z / B.nz, &sz, &cz);
+        for (int ny = -Ky; ny <= Ky; ++ny) {
+            double sy, cy;
+            sincospi(2.0 * ny * y / B.ny, &sy, &cy);
+            const double pr = cy * cz - sy * sz, pi = sy * cz + cy * sz;  // exp(i (ky y + kz z))
+            for (int nx = -Kx; nx <= Kx; ++nx) {
+                const double er = ex[nx + WK][0] * pr - ex[nx + WK][1] * pi;
+                const double ei = ex[nx + WK][0] * pi + ex[nx + WK][1] * pr;
+                const int m = (nx + WK) + (2 * WK + 1) * ((ny + WK) + (2 * WK + 1) * (nz + WK));
+                const double* cm = c + 6 * m;
+                for (int k = 0; k < 3; ++k) u[k] += cm[2 * k] * er - cm[2 * k + 1] * ei;
+            }
+        }
+    }
+}
+
+// Velocity of node (x, y, z) of box bi before the mean correction: rigid
+// motion inside a particle, else the corrected load-driven flow.
+__device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const PartDev* __restrict__ parts, int np,
+                               double mu, const double* __restrict__ coef, int x, int y, int z, double u[3]) {
     if (owner != 0) {
         const PartDev& P = parts[owner - 1];
         double d[3];
@@ -107,24 +187,108 @@ __device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const P
         u[2] = P.U[2] + P.W[0] * d[1] - P.W[1] * d[0];
         return;
     }
+    free_velocity(B, bi, parts, np, mu, x, y, z, u);
+    correction(B, coef + (long long)bi * WM * 6, x, y, z, u);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Discrete Fourier sums S_m = sum_x u_free(x) exp(-i k_m . x) over every node
+// of a box, for the modes of one (ny, nz) pair (blockIdx.y) and all nx.
+__global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict__ boxes,
+                                                      const PartDev* __restrict__ parts, int np, double mu,
+                                                      double* __restrict__ S) {
+    __shared__ double red[4][2 * WK + 1][6];
+    const int bi = blockIdx.x, g = blockIdx.y;
+    const BoxDesc& B = boxes[bi];
+    const int ny_ = g % (2 * WK + 1) - WK, nz_ = g / (2 * WK + 1) - WK;
+    const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
+    if (abs(ny_) > Ky || abs(nz_) > Kz) return;  // uniform over the block
+    double acc[2 * WK + 1][6];
+#pragma unroll
+    for (int a = 0; a < 2 * WK + 1; ++a)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[a][k] = 0.0;
+    for (int s = threadIdx.x; s < B.n; s += blockDim.x) {
+        const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
+        double u[3];
+        free_velocity(B, bi, parts, np, mu, x, y, z, u);
+        double syz, cyz;
+        sincospi(2.0 * ((double)ny_ * y / B.ny + (double)nz_ * z / B.nz), &syz, &cyz);
+#pragma unroll
+        for (int nx = -WK; nx <= WK; ++nx) {  // fixed trip count: the accumulators stay in registers
+            if (nx < -Kx || nx > Kx) continue;
+            double sx, cx_;
+            sincospi(2.0 * nx * x / B.nx, &sx, &cx_);
+            // exp(-i theta) = cos theta - i sin theta, theta = kx x + ky y + kz z
+            const double c = cx_ * cyz - sx * syz, sn = sx * cyz + cx_ * syz;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                acc[nx + WK][2 * k] += u[k] * c;
+                acc[nx + WK][2 * k + 1] -= u[k] * sn;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 2 * WK + 1; ++a)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double v = wave_sum(acc[a][k]);
+            if (lane == 0) red[wv][a][k] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < (2 * WK + 1) * 6) {
+        const int a = threadIdx.x / 6, k = threadIdx.x % 6;
+        const double v = red[0][a][k] + red[1][a][k] + red[2][a][k] + red[3][a][k];
+        const int m = a + (2 * WK + 1) * ((ny_ + WK) + (2 * WK + 1) * (nz_ + WK));
+        S[((long long)bi * WM + m) * 6 + k] = v;
+    }
+}
+
+// Correction coefficients: one thread per (box, mode slot): the periodic
+// solution's coefficient of every particle of the box minus the free flow's
+// DFT coefficient S_m / N; zero for slots outside the box's mode set.
+__global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, const PartDev* __restrict__ parts,
+                              int np, double mu, const double* __restrict__ S, double* __restrict__ C) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nboxes * WM) return;
+    const int bi = id / WM, m = id % WM;
+    const BoxDesc& B = boxes[bi];
+    const int n[3] = {m % (2 * WK + 1) - WK, (m / (2 * WK + 1)) % (2 * WK + 1) - WK, m / ((2 * WK + 1) * (2 * WK + 1)) - WK};
+    const int L[3] = {B.nx, B.ny, B.nz};
+    double* c = C + (long long)id * 6;
+    bool use = !(n[0] == 0 && n[1] == 0 && n[2] == 0);
+    for (int a = 0; a < 3; ++a) use = use && abs(n[a]) <= wk_axis(L[a]);
+    for (int k = 0; k < 6; ++k) c[k] = 0.0;
+    if (!use) return;
+    const double V = (double)B.n;
+    double k[3];
+    for (int a = 0; a < 3; ++a) k[a] = 2.0 * M_PI * n[a] / L[a];
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     for (int p = 0; p < np; ++p) {
         const PartDev& P = parts[p];
         if (P.box != bi) continue;
-        double d[3];
-        offset(P, B, x, y, z, d);
-        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const double R = eq_radius(P);
-        const double wx[3] = {P.W[1] * d[2] - P.W[2] * d[1], P.W[2] * d[0] - P.W[0] * d[2],
-                              P.W[0] * d[1] - P.W[1] * d[0]};
-        if (r < R) {  // fluid node inside the equal-volume sphere: rigid motion
-            for (int k = 0; k < 3; ++k) u[k] += P.U[k] + wx[k];
-            continue;
+        const double R = eq_radius(P), xr = sqrt(k2) * R;
+        const double sinc = sin(xr) / xr, j1f = 3.0 * (sin(xr) / xr - cos(xr)) / (xr * xr);
+        const double kF = k[0] * P.Fext[0] + k[1] * P.Fext[1] + k[2] * P.Fext[2];
+        const double kxT[3] = {k[1] * P.Text[2] - k[2] * P.Text[1], k[2] * P.Text[0] - k[0] * P.Text[2],
+                               k[0] * P.Text[1] - k[1] * P.Text[0]};
+        double sp, cp;
+        sincos(-(k[0] * P.xc[0] + k[1] * P.xc[1] + k[2] * P.xc[2]), &sp, &cp);  // exp(-i k . x_c)
+        for (int a = 0; a < 3; ++a) {
+            const double re = (P.Fext[a] - k[a] * kF / k2) * sinc / (mu * k2) / V;  // real part of u_hat / V
+            const double im = kxT[a] * j1f / (2.0 * mu * k2) / V;                   // imaginary part
+            c[2 * a] += re * cp - im * sp;
+            c[2 * a + 1] += re * sp + im * cp;
         }
-        const double e[3] = {d[0] / r, d[1] / r, d[2] / r};
-        const double Ue = P.U[0] * e[0] + P.U[1] * e[1] + P.U[2] * e[2];
-        const double a1 = 0.75 * R / r, a3 = 0.25 * R * R * R / (r * r * r), rr = (R / r) * (R / r) * (R / r);
-        for (int k = 0; k < 3; ++k)
-            u[k] += a1 * (P.U[k] + Ue * e[k]) + a3 * (P.U[k] - 3.0 * Ue * e[k]) + rr * wx[k];
+    }
+    for (int a = 0; a < 3; ++a) {
+        c[2 * a] -= S[(long long)id * 6 + 2 * a] / V;
+        c[2 * a + 1] -= S[(long long)id * 6 + 2 * a + 1] / V;
     }
 }
 
@@ -132,7 +296,8 @@ __device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const P
 __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__ boxes,
                                                      const int* __restrict__ tile_box,
                                                      const uint16_t* __restrict__ omap,
-                                                     const PartDev* __restrict__ parts, int np,
+                                                     const PartDev* __restrict__ parts, int np, double mu,
+                                                     const double* __restrict__ coef,
                                                      double* __restrict__ partial) {
     __shared__ double red[4][TILE];
     const int tile = blockIdx.x, tid = threadIdx.x;
@@ -142,7 +307,7 @@ __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__
     double v[4] = {0, 0, 0, 0};
     if (s < B.n && omap[B.ooff + s] == 0) {
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
-        start_velocity(B, bi, 0, parts, np, x, y, z, v);
+        start_velocity(B, bi, 0, parts, np, mu, coef, x, y, z, v);
         v[3] = 1.0;
     }
     for (int k = 0; k < 4; ++k) red[k][tid] = v[k];
@@ -174,7 +339,8 @@ template <int ST>
 __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict__ boxes,
                                                        const int* __restrict__ tile_box,
                                                        const uint16_t* __restrict__ omap,
-                                                       const PartDev* __restrict__ parts, int np,
+                                                       const PartDev* __restrict__ parts, int np, double mu,
+                                                       const double* __restrict__ coef,
                                                        const double* __restrict__ ubar,
                                                        typename Store<ST>::T* __restrict__ f, KParams kp) {
     using S = Store<ST>;
@@ -188,7 +354,7 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
     double u[3];
-    start_velocity(B, bi, owner, parts, np, x, y, z, u);
+    start_velocity(B, bi, owner, parts, np, mu, coef, x, y, z, u);
     if (owner == 0)
         for (int k = 0; k < 3; ++k) u[k] -= ubar[3 * bi + k];
     const double rho0 = kp.rho0, uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -218,28 +384,45 @@ hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const doubl
     return hipGetLastError();
 }
 
+hipError_t launch_warm_targets(const PartDev* parts, int np, const double* s, double mu, float* Y, hipStream_t st) {
+    if (np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_warm_targets, dim3((np + 63) / 64), dim3(64), 0, st, parts, np, s, mu, Y);
+    return hipGetLastError();
+}
+
+size_t stokes_scratch_doubles(int nboxes, int ntiles) { return (size_t)nboxes * WM * 6 * 2 + (size_t)ntiles * 4 + 3 * (size_t)nboxes; }
+
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
-                               const uint16_t* omap, const PartDev* parts, int np, double* partial, double* ubar,
+                               const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
                                void* f, const KParams& kp, hipStream_t st) {
-    hipLaunchKernelGGL(k_stokes_sum, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap, parts, np, partial);
+    double* S = scratch;
+    double* C = S + (size_t)nboxes * WM * 6;
+    double* partial = C + (size_t)nboxes * WM * 6;
+    double* ubar = partial + (size_t)ntiles * 4;
+    hipLaunchKernelGGL(k_stokes_modes, dim3(nboxes, (2 * WK + 1) * (2 * WK + 1)), dim3(256), 0, st, boxes, parts, np,
+                       mu, S);
+    hipLaunchKernelGGL(k_stokes_coef, dim3((nboxes * WM + 127) / 128), dim3(128), 0, st, boxes, nboxes, parts, np, mu,
+                       S, C);
+    hipLaunchKernelGGL(k_stokes_sum, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap, parts, np, mu, C,
+                       partial);
     hipLaunchKernelGGL(k_stokes_mean, dim3((nboxes + 63) / 64), dim3(64), 0, st, boxes, nboxes, parts, np, partial,
                        kp.rho0, ubar);
     switch (kp.storage) {
         case ST_F64:
             hipLaunchKernelGGL((k_stokes_write<ST_F64>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, ubar, (double*)f, kp);
+                               parts, np, mu, C, ubar, (double*)f, kp);
             break;
         case ST_F32:
             hipLaunchKernelGGL((k_stokes_write<ST_F32>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, ubar, (float*)f, kp);
+                               parts, np, mu, C, ubar, (float*)f, kp);
             break;
         case ST_F16:
             hipLaunchKernelGGL((k_stokes_write<ST_F16>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, ubar, (typename Store<ST_F16>::T*)f, kp);
+                               parts, np, mu, C, ubar, (typename Store<ST_F16>::T*)f, kp);
             break;
         default:
             hipLaunchKernelGGL((k_stokes_write<ST_BF16>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, ubar, (typename Store<ST_BF16>::T*)f, kp);
+                               parts, np, mu, C, ubar, (typename Store<ST_BF16>::T*)f, kp);
     }
     return hipGetLastError();
 }

@@ -125,9 +125,9 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     L.near_flags = take(sizeof(uint32_t) * 2 * L.near_blocks);
     L.near_list = take(sizeof(int) * 2 * L.near_blocks);
     L.near_count = take(sizeof(int) * 4);
-    // warm start: per-tile partial sums (4), per-box mean velocity (3), per
-    // particle load scale (1) and prediction (6)
-    L.warm = take(sizeof(double) * ((size_t)4 * tiles + 3 * (size_t)nboxes + 7 * (size_t)L.max_particles));
+    // warm start: per particle load scale (1), prediction (6) and training
+    // sample (8 + 6 floats = 7 doubles); then the start field's scratch
+    L.warm = take(sizeof(double) * (14 * (size_t)L.max_particles + stokes_scratch_doubles(nboxes, tiles)));
     L.total = p;
     return L;
 }
@@ -997,7 +997,10 @@ lb_status lb_get_mass(lb_ctx* ctx, int box, double* mass) {
     double m[6];
     lb_status s = moments(ctx, box, m);
     if (s != LB_OK) return s;
-    double tot = m[0] * ctx->cfg.rho0 + m[1];
+    // every non-wall node counted at rho0 (particle nodes carry rho0 through
+    // their transitions), plus the fluid's excess and the pending excess
+    const BoxDesc& B = ctx->hbox[box];
+    double tot = (double)(B.n - B.n_wall) * ctx->cfg.rho0 + m[1];
     for (int p = 0; p < ctx->np; ++p)
         if (ctx->hpart[p].box == box) {
             double dm = 0;
@@ -1151,13 +1154,15 @@ lb_status lb_get_particles(lb_ctx* ctx, int first, int count, double* x, double*
 }
 
 namespace {
+double viscosity(const lb_ctx* ctx) { return (1.0 / ctx->kp.omega - 0.5) / 3.0; }
+
 lb_status stokes_start(lb_ctx* ctx) {
     for (const auto& b : ctx->boxes)
         if (b.walls) return fail(ctx, LB_EINVAL, "the start field is defined for periodic boxes only");
-    double* warm = ctx->at<double>(ctx->L.warm);
+    double* scratch = ctx->at<double>(ctx->L.warm) + 14 * (size_t)ctx->L.max_particles;
     HIPC(launch_stokes_start(ctx->at<BoxDesc>(ctx->L.boxes), (int)ctx->boxes.size(), ctx->at<int>(ctx->L.tile_box),
                              ctx->L.total_tiles, ctx->at<uint16_t>(ctx->L.omap), ctx->at<PartDev>(ctx->L.parts),
-                             ctx->np, warm, warm + 4 * (size_t)ctx->L.total_tiles, ctx->fbuf(ctx->cur), ctx->kp,
+                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, ctx->fbuf(ctx->cur), ctx->kp,
                              ctx->stream));
     return LB_OK;
 }
@@ -1178,19 +1183,34 @@ lb_status lb_warm_start(lb_ctx* ctx, lbs* sur, double* pred) {
     for (const auto& b : ctx->boxes)
         if (b.walls) return fail(ctx, LB_EINVAL, "the warm start is defined for periodic boxes only");
     // the surrogate's work goes on the context's stream, after the steps already queued there
-    double* warm = ctx->at<double>(ctx->L.warm);
-    double* sc = warm + 4 * (size_t)ctx->L.total_tiles + 3 * ctx->boxes.size();
+    double* sc = ctx->at<double>(ctx->L.warm);
     double* pr = sc + ctx->L.max_particles;
     PartDev* parts = ctx->at<PartDev>(ctx->L.parts);
     HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, sur->X, sc, ctx->stream));
     MlpArgs a{sur->P, sur->X, nullptr, sur->out, nullptr, nullptr, ctx->np, 0.f, 0};
     HIPC(launch_mlp(a, ctx->stream));
-    const double mu = ctx->kp.rho0 * (1.0 / ctx->kp.omega - 0.5) / 3.0;
+    const double mu = ctx->kp.rho0 * viscosity(ctx);
     HIPC(launch_warm_apply(parts, ctx->np, sur->out, sc, mu, pr, ctx->stream));
     lb_status s = stokes_start(ctx);
     if (s != LB_OK) return s;
     if (pred)
         HIPC(hipMemcpyAsync(pred, pr, sizeof(double) * 6 * ctx->np, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return flags_status(ctx);
+}
+
+lb_status lb_surrogate_sample(lb_ctx* ctx, float* X, float* Y) {
+    if (!ctx || !X || !Y) return LB_EINVAL;
+    if (ctx->np == 0) return LB_OK;
+    double* sc = ctx->at<double>(ctx->L.warm);
+    float* xy = reinterpret_cast<float*>(sc + 7 * (size_t)ctx->L.max_particles);  // after the scales and predictions
+    const PartDev* parts = ctx->at<PartDev>(ctx->L.parts);
+    const double mu = ctx->kp.rho0 * viscosity(ctx);
+    HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, xy, sc, ctx->stream));
+    HIPC(launch_warm_targets(parts, ctx->np, sc, mu, xy + (size_t)MLP_IN * ctx->np, ctx->stream));
+    HIPC(hipMemcpyAsync(X, xy, sizeof(float) * MLP_IN * ctx->np, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(Y, xy + (size_t)MLP_IN * ctx->np, sizeof(float) * MLP_OUT * ctx->np, hipMemcpyDeviceToHost,
+                        ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
     return flags_status(ctx);
 }

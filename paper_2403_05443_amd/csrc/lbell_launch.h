@@ -111,8 +111,10 @@ hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int 
                                 hipStream_t st);
 hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const double* s, double mu, double* pred,
                              hipStream_t st);
+hipError_t launch_warm_targets(const PartDev* parts, int np, const double* s, double mu, float* Y, hipStream_t st);
+size_t stokes_scratch_doubles(int nboxes, int ntiles);  // scratch of launch_stokes_start
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
-                               const uint16_t* omap, const PartDev* parts, int np, double* partial, double* ubar,
+                               const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
                                void* f, const KParams& kp, hipStream_t st);
 
 }  // namespace lbd

@@ -76,6 +76,7 @@ SIGNATURES = {
     "lb_get_particles": (C.c_int, [_VP, C.c_int, C.c_int, _D, _D, _D, _D]),
     "lb_stokes_start": (C.c_int, [_VP]),
     "lb_warm_start": (C.c_int, [_VP, _VP, _D]),
+    "lb_surrogate_sample": (C.c_int, [_VP, _F, _F]),
     "lbs_arena_bytes": (C.c_size_t, [C.c_int]),
     "lbs_create": (C.c_int, [C.c_int, _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
     "lbs_set_params": (C.c_int, [_VP, _F]),
@@ -348,6 +349,17 @@ class Lattice:
 
 def _fp(a):
     return a.ctypes.data_as(_F)
+
+
+def _lattice_sample(self):
+    """(X, Y): surrogate inputs and normalised responses of every particle now."""
+    X = np.zeros((max(self.np, 1), 8), dtype=np.float32)
+    Y = np.zeros((max(self.np, 1), 6), dtype=np.float32)
+    self._chk(self.lib.lb_surrogate_sample(self.ctx, _fp(X), _fp(Y)))
+    return X[:self.np], Y[:self.np]
+
+
+Lattice.surrogate_sample = _lattice_sample
 
 
 class Surrogate:

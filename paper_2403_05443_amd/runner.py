@@ -1,0 +1,224 @@
+"""Runs built on the library: lattices from workload descriptions, training
+data for the warm-start surrogate from batched ensembles, its training, and
+the comparison of the steps a run needs to reach its steady state from a
+plain start (fluid at rest), from the surrogate's warm start, and from a
+warm start with the unbounded-fluid closed forms (the control, the same
+start without the network).
+
+Every step of the method runs in the HIP library; this module only drives
+it (launch sizes, step counts, book-keeping of the sampled velocities) and
+shapes the training data.
+"""
+import math
+
+import numpy as np
+
+from . import lbell, workloads
+
+
+def build_lattice(W, device="cuda:0"):
+    """A Lattice holding workload W (boxes, particles, loads, squirmers)."""
+    boxes = [lbell.make_box(*b.shape, walls=b.walls, wall_lo=b.wall_lo, wall_hi=b.wall_hi, init=b.init)
+             for b in W.boxes]
+    lat = lbell.Lattice(boxes, collision=W.collision, tau=W.tau, magic=W.magic, storage=W.storage,
+                        counterforce=W.counterforce, velocity_scale=W.velocity_scale,
+                        max_particles=max(1, len(W.particles)), max_semi_axis=W.max_semi_axis, device=device)
+    for p in W.particles:
+        pid = lat.add_ellipsoid(p.centre, p.axes, p.quat, box=p.box)
+        lat.set_external(pid, p.force, p.torque)
+        if p.squirmer != (0.0, 0.0):
+            lat.set_squirmer(pid, *p.squirmer)
+    return lat
+
+
+def viscosity(W):
+    return (W.tau - 0.5) / 3.0
+
+
+def slow_time(L, nu):
+    """e-folding time of the slowest shear mode of a periodic box of edge L."""
+    return L * L / (4 * math.pi ** 2 * nu)
+
+
+def box_edge(W, i):
+    nx, ny, nz = W.boxes[W.particles[i].box].shape
+    return (nx * ny * nz) ** (1.0 / 3.0)
+
+
+# ------------------------------------------------------------ training data --
+
+def ensemble_samples(W, efolds=8.0, graph=50):
+    """Runs the ensemble W for `efolds` slow times of its largest box and
+    returns the surrogate's inputs and normalised responses of every particle
+    at the end, (X (n, 8), Y (n, 6))."""
+    lat = build_lattice(W)
+    nu = viscosity(W)
+    steps = int(math.ceil(efolds * max(slow_time(box_edge(W, i), nu) for i in range(len(W.particles)))))
+    lat.set_graph(graph)
+    lat.step(steps)
+    X, Y = lat.surrogate_sample()
+    del lat
+    return X.astype(np.float64), Y.astype(np.float64), steps
+
+
+def augment(X, Y, nrot=8, flip=True):
+    """Copies of the samples under the symmetries of a spheroid with b = c:
+    rotations about its axis (body x) by 2 pi k / nrot and, with flip, the
+    half-turn about body z that swaps its ends.  Loads and responses rotate
+    together (forces, torques and both velocities transform alike under
+    proper rotations); the shape inputs are unchanged."""
+    out_x, out_y = [], []
+    mats = []
+    for k in range(nrot):
+        c, s = math.cos(2 * math.pi * k / nrot), math.sin(2 * math.pi * k / nrot)
+        Q = np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+        mats.append(Q)
+        if flip:
+            mats.append(np.diag([-1.0, -1.0, 1.0]) @ Q)
+    for Q in mats:
+        x, y = X.copy(), Y.copy()
+        x[:, 2:5], x[:, 5:8] = X[:, 2:5] @ Q.T, X[:, 5:8] @ Q.T
+        y[:, 0:3], y[:, 3:6] = Y[:, 0:3] @ Q.T, Y[:, 3:6] @ Q.T
+        out_x.append(x)
+        out_y.append(y)
+    return np.concatenate(out_x), np.concatenate(out_y)
+
+
+def shuffle(X, Y, seed):
+    """Fisher-Yates permutation drawn from the project generator."""
+    g = workloads.SplitMix64(seed)
+    idx = np.arange(len(X))
+    for i in range(len(idx) - 1, 0, -1):
+        j = int(g.next_u64() % (i + 1))
+        idx[i], idx[j] = idx[j], idx[i]
+    return X[idx], Y[idx]
+
+
+def train_surrogate(X, Y, seed=2403054430, epochs=300, batch=256, lr=1e-3, val_frac=0.2):
+    """Xavier initialisation, seeded shuffle, 80/20 split, Adam on the GPU.
+    Returns (surrogate, info)."""
+    X, Y = shuffle(X, Y, seed)
+    nval = int(round(val_frac * len(X)))
+    Xv, Yv, Xt, Yt = X[:nval], Y[:nval], X[nval:], Y[nval:]
+    sur = lbell.Surrogate(max_samples=max(len(X), 64), params=workloads.xavier_params(workloads.SplitMix64(seed)))
+    L0 = sur.grad(Xt, Yt)[0]
+    Lt = sur.train(Xt, Yt, epochs=epochs, batch=batch, lr=lr)
+    Lv = sur.grad(Xv, Yv)[0] if nval else float("nan")
+    var = float(np.mean((Yv - Yv.mean(0)) ** 2)) if nval else float("nan")
+    return sur, {"samples": len(X), "train": len(Xt), "val": nval, "loss_init": L0, "loss_train": Lt,
+                 "loss_val": Lv, "val_target_variance": var}
+
+
+# ---------------------------------------------------- closed-form control --
+
+def resistance(r):
+    """X^A, Y^A, X^C, Y^C of a prolate spheroid of aspect ratio r (Kim &
+    Karrila, Microhydrodynamics, Table 3.4); 1 for a sphere."""
+    if r < 1 + 1e-6:
+        return 1.0, 1.0, 1.0, 1.0
+    e = math.sqrt(1 - 1 / (r * r))
+    lg = math.log((1 + e) / (1 - e))
+    return (8 / 3 * e ** 3 / (-2 * e + (1 + e * e) * lg), 16 / 3 * e ** 3 / (2 * e + (3 * e * e - 1) * lg),
+            4 / 3 * e ** 3 * (1 - e * e) / (2 * e - (1 - e * e) * lg),
+            4 / 3 * e ** 3 * (2 - e * e) / (-2 * e + (1 + e * e) * lg))
+
+
+def _rot(q):
+    q0, q1, q2, q3 = q
+    return np.array([[1 - 2 * (q2 * q2 + q3 * q3), 2 * (q1 * q2 - q0 * q3), 2 * (q1 * q3 + q0 * q2)],
+                     [2 * (q1 * q2 + q0 * q3), 1 - 2 * (q1 * q1 + q3 * q3), 2 * (q2 * q3 - q0 * q1)],
+                     [2 * (q1 * q3 - q0 * q2), 2 * (q2 * q3 + q0 * q1), 1 - 2 * (q1 * q1 + q2 * q2)]])
+
+
+def unbounded_velocities(p, nu):
+    """Velocities of particle p (a, b, b) under its load in an unbounded
+    fluid at rest (no periodic images)."""
+    a, b, _ = p.axes
+    XA, YA, XC, YC = resistance(a / b)
+    R = _rot(p.quat)
+    Fb, Tb = R.T @ np.asarray(p.force, float), R.T @ np.asarray(p.torque, float)
+    Ub = np.array([Fb[0] / XA, Fb[1] / YA, Fb[2] / YA]) / (6 * math.pi * nu * a)
+    Wb = np.array([Tb[0] / XC, Tb[1] / YC, Tb[2] / YC]) / (8 * math.pi * nu * a ** 3)
+    return R @ Ub, R @ Wb
+
+
+# ------------------------------------------------------- steps to steady --
+
+def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25):
+    """Velocities U of every particle every `every` steps from one of three
+    starts: 'plain' (rest), 'surrogate' (lb_warm_start), 'control' (closed
+    forms + Stokes start field).  Returns (times, U (nt, np, 3), pred)."""
+    lat = build_lattice(W)
+    pred = None
+    if start == "surrogate":
+        pred = lat.warm_start(surrogate)
+    elif start == "control":
+        nu = viscosity(W)
+        pred = np.zeros((len(W.particles), 6))
+        for i, p in enumerate(W.particles):
+            U, Wv = unbounded_velocities(p, nu)
+            lat.set_velocity(i, U, Wv)
+            pred[i] = np.concatenate([U, Wv])
+        lat.stokes_start()
+    lat.set_graph(graph)
+    times, Us = [], []
+    t = 0
+    while t < steps:
+        lat.step(every)
+        t += every
+        times.append(t)
+        Us.append(lat.particles()["U"].copy())
+    del lat
+    return np.array(times), np.array(Us), pred
+
+
+def steps_to_tolerance(times, U, Uinf, tol=0.005):
+    """Per particle: the first sampled step after which |U(t) - U_inf| <=
+    tol |U_inf| holds until the end (inf if it never settles)."""
+    dev = np.linalg.norm(U - Uinf[None], axis=2) / np.linalg.norm(Uinf, axis=1)[None]
+    out = np.full(U.shape[1], np.inf)
+    for i in range(U.shape[1]):
+        bad = np.nonzero(dev[:, i] > tol)[0]
+        if len(bad) == 0:
+            out[i] = times[0]
+        elif bad[-1] < len(times) - 1:
+            out[i] = times[bad[-1] + 1]
+    return out
+
+
+def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005):
+    """Steps to a tol-accurate steady velocity for each particle of the
+    force-driven ensemble W from the three starts.  The steady velocity is
+    the end of the plain run; a box counts only if that run changed by less
+    than 0.05% over its last slow time.  Fallback: a warm-started box whose
+    velocity after W0 = ceil(2 a^2 / nu) steps is more than tol away from the
+    prediction is marked to be run plainly (its sample goes back to
+    training)."""
+    nu = viscosity(W)
+    steps = int(math.ceil(efolds * max(slow_time(box_edge(W, i), nu) for i in range(len(W.particles)))))
+    steps = (steps + every - 1) // every * every
+    tp, Up, _ = trajectory(W, "plain", steps=steps, every=every)
+    ts, Us, pred = trajectory(W, "surrogate", surrogate, steps=steps, every=every)
+    tc, Uc, _ = trajectory(W, "control", steps=steps, every=every)
+    Uinf = Up[-1]
+    ok = np.ones(len(W.particles), dtype=bool)
+    fallback = np.zeros(len(W.particles), dtype=bool)
+    for i, p in enumerate(W.particles):
+        lag = int(round(slow_time(box_edge(W, i), nu) / every))
+        ok[i] = np.linalg.norm(Up[-1, i] - Up[-1 - lag, i]) < 5e-4 * np.linalg.norm(Uinf[i])
+        w0 = int(math.ceil(2 * p.axes[0] ** 2 / nu))
+        k = min(len(ts) - 1, max(0, int(math.ceil(w0 / every)) - 1))
+        fallback[i] = np.linalg.norm(Us[k, i] - pred[i, :3]) > tol * np.linalg.norm(pred[i, :3])
+    n = {"plain": steps_to_tolerance(tp, Up, Uinf, tol), "surrogate": steps_to_tolerance(ts, Us, Uinf, tol),
+         "control": steps_to_tolerance(tc, Uc, Uinf, tol)}
+    err0 = {"surrogate": np.linalg.norm(Us[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1),
+            "control": np.linalg.norm(Uc[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)}
+    pred_err = np.linalg.norm(pred[:, :3] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)
+    med = {k: float(np.median(v[ok])) for k, v in n.items()}
+    return {"boxes": int(len(W.particles)), "steady_boxes": int(ok.sum()), "steps": steps, "every": every,
+            "tol": tol, "median_steps": med,
+            "surrogate_over_plain": med["surrogate"] / med["plain"],
+            "control_over_plain": med["control"] / med["plain"],
+            "median_prediction_error": float(np.median(pred_err[ok])),
+            "median_error_after_first_sample": {k: float(np.median(v[ok])) for k, v in err0.items()},
+            "fallback_rate": float(fallback[ok].mean()), "per_box": n, "steady": ok}

@@ -138,7 +138,7 @@ def c3(r=3, seed_index=1, storage="fp32"):
                     notes={"shear_rate": 0.02 / 126.0})
 
 
-def c4(storage="fp16", nboxes=256, seed_index=0):
+def c4(storage="fp16", nboxes=256, seed_index=0, torque=True):
     """Ensemble of independent periodic cubic boxes, one spheroid each.
 
     Edge L uniform on the integers 32..64; aspect ratio r uniform in [1, 5]
@@ -146,8 +146,9 @@ def c4(storage="fp16", nboxes=256, seed_index=0):
     (a = r b); body axes (a, b, b); orientation uniform on S^3; centre at the
     box centre plus a uniform sub-lattice offset in [-0.5, 0.5)^3; force of
     magnitude uniform in [1e-5, 1e-4] and torque of magnitude uniform in
-    [1e-4, 1e-3], both in uniformly random directions.  TRT, Lambda = 3/16,
-    tau+ = 1 (nu = 1/6), counter-force on."""
+    [1e-4, 1e-3], both in uniformly random directions (torque=False keeps
+    the same draws and zeroes the torques: force-driven boxes reach a true
+    steady state).  TRT, Lambda = 3/16, tau+ = 1 (nu = 1/6), counter-force on."""
     g = SplitMix64(SEED0 + 3 + 1000 * seed_index)
     boxes, parts = [], []
     for i in range(nboxes):
@@ -163,8 +164,9 @@ def c4(storage="fp16", nboxes=256, seed_index=0):
         fd, td = g.unit_vector(), g.unit_vector()
         boxes.append(Box((L, L, L)))
         parts.append(Particle(c, (r * b, b, b), q, force=tuple(fm * v for v in fd),
-                              torque=tuple(tm * v for v in td), box=i))
-    return Workload(f"c4_ensemble_{nboxes}", boxes, parts, "trt", 1.0, storage, 0, counterforce=True,
+                              torque=tuple(tm * v for v in td) if torque else (0.0, 0.0, 0.0), box=i))
+    name = f"c4_ensemble_{nboxes}" + (f"_s{seed_index}" if seed_index else "") + ("" if torque else "_force")
+    return Workload(name, boxes, parts, "trt", 1.0, storage, 0, counterforce=True,
                     velocity_scale=1e-3, max_semi_axis=20.0)
 
 

@@ -148,7 +148,7 @@ def _sample_boxes(W, k=3):
 
 
 def _single(lb, W, i):
-    from bench import build_lattice
+    from paper_2403_05443_amd.runner import build_lattice
     from paper_2403_05443_amd import workloads
     Wi = workloads.Workload(W.name, [W.boxes[i]], [W.particles[i]], W.collision, W.tau, W.storage, 0,
                             magic=W.magic, counterforce=W.counterforce, velocity_scale=W.velocity_scale,
@@ -161,7 +161,7 @@ def test_full_ensemble_fp16_matches_single_boxes(lb):
     """The 256-box FP16 ensemble (edges 32-64, one spheroid each) in one
     launch per phase, graph-replayed, tuner-chosen tile shape: sampled boxes
     match the same box run alone bit for bit, and every box stays finite."""
-    from bench import build_lattice
+    from paper_2403_05443_amd.runner import build_lattice
     from paper_2403_05443_amd import workloads
     W = workloads.c4("fp16")
     g = build_lattice(W)
@@ -187,7 +187,7 @@ def test_full_ensemble_fp64_matches_oracle(lb):
     """The same 256-box ensemble with FP64 storage, 30 steps: sampled boxes
     against the oracle at the FP64 bar."""
     import oracle
-    from bench import build_lattice
+    from paper_2403_05443_amd.runner import build_lattice
     from paper_2403_05443_amd import workloads
     W = workloads.c4("fp64")
     g = build_lattice(W)

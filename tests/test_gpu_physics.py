@@ -40,7 +40,7 @@ def body_axis(q):
 
 
 def build(lb, W):
-    from bench import build_lattice
+    from paper_2403_05443_amd.runner import build_lattice
     return build_lattice(W)
 
 

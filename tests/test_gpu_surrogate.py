@@ -151,9 +151,9 @@ def test_warm_start_prediction_matches_reference(lb):
         assert np.allclose(pr, np.concatenate([U2, W2]), rtol=1e-5, atol=0)
 
 
-def _oracle_start(o, shape, parts):
+def _oracle_start(o, shape, parts, mu):
     """Oracle state started from the reference start field."""
-    u = S.start_field(shape, o.mask(), parts)
+    u = S.start_field(shape, o.mask(), parts, mu)
     o.set_f(S.equilibrium(1.0, u))
     return u
 
@@ -171,8 +171,9 @@ def test_stokes_start_field_matches_reference(lb):
         o = oracle.OracleSim(boxes[b], "trt", 0.8, counterforce=True)
         po = o.add_ellipsoid(c, a, q)
         assert np.array_equal(o.mask() != 0, g.mask(b) != 0)
-        part = {"centre": o.particle(po)["x"], "axes": a, "U": vel[pid][0], "W": vel[pid][1], "M": o.aux(po)["M"]}
-        u = S.start_field(boxes[b], o.mask(), [part])
+        part = {"centre": o.particle(po)["x"], "axes": a, "F": F, "T": T, "U": vel[pid][0], "W": vel[pid][1],
+                "M": o.aux(po)["M"]}
+        u = S.start_field(boxes[b], o.mask(), [part], (0.8 - 0.5) / 3)
         rho, ug = g.fields(b)
         fl = o.mask() == 0
         err = np.abs(ug[fl] - u[fl]).max() / np.abs(u[fl]).max()
@@ -203,10 +204,14 @@ def test_warm_started_trajectory_matches_oracle(lb):
     po = o.add_ellipsoid(c, a, q)
     o.set_external(po, F, T)
     o.set_velocity(po, U, W)
-    _oracle_start(o, shape, [{"centre": c, "axes": a, "U": U, "W": W, "M": o.aux(po)["M"]}])
+    _oracle_start(o, shape, [{"centre": c, "axes": a, "F": F, "T": T, "U": U, "W": W, "M": o.aux(po)["M"]}],
+                  (0.8 - 0.5) / 3)
     rho, ug = g.fields()
     _, uo = o.fields()
-    assert np.abs(ug - uo).max() < 1e-12 * np.abs(uo).max()
+    # the low-mode correction is a sum of 124 modes whose coefficients come
+    # from a direct DFT on the GPU and numpy's FFT in the reference: rounding
+    # ~ sqrt(N) eps per coefficient, N = 26 880 nodes
+    assert np.abs(ug - uo).max() < 1e-11 * np.abs(uo).max()
     g.step(60)
     o.step(60)
     A, B = g.particle(pg), o.particle(po)
@@ -228,3 +233,29 @@ def test_warm_start_rejects_walls(lb):
         g.warm_start(s)
     with pytest.raises(lb.LBError):
         g.stokes_start()
+
+
+def test_surrogate_warm_start_reaches_steady_state_sooner(lb):
+    """The network trained on the library's own ensemble runs (two 128-box
+    ensembles, one with torques, symmetry-augmented) warm-starts a held-out
+    force-driven 32-box ensemble: the median number of steps to a velocity
+    within 0.5% of the steady one is below both the plain start's and the
+    closed-form control's (the same start without the network)."""
+    from paper_2403_05443_amd import runner, workloads
+    Xs, Ys = [], []
+    for k in range(2):
+        W = workloads.c4("fp16", 128, seed_index=20 + k, torque=(k == 0))
+        X, Y, _ = runner.ensemble_samples(W, efolds=8)
+        Xs.append(X)
+        Ys.append(Y)
+    Xa, Ya = runner.augment(np.concatenate(Xs), np.concatenate(Ys))
+    sur, info = runner.train_surrogate(Xa, Ya, epochs=150)
+    print("training", info)
+    assert info["loss_val"] < 0.01 * info["val_target_variance"]
+    res = runner.compare_starts(workloads.c4("fp32", 32, seed_index=200, torque=False), sur)
+    res.pop("per_box")
+    res.pop("steady")
+    print(res)
+    m = res["median_steps"]
+    assert res["steady_boxes"] >= 24
+    assert m["surrogate"] < m["plain"] and m["surrogate"] < m["control"]

@@ -244,9 +244,9 @@ def test_start_field_has_zero_total_momentum():
     z, y, x = np.meshgrid(np.arange(22), np.arange(18), np.arange(20), indexing="ij")
     inside = ((x - 9.3) / 4) ** 2 + ((y - 8.6) / 2) ** 2 + ((z - 10.2) / 2) ** 2 < 1
     owner[inside.ravel()] = 1
-    p = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "U": (1e-3, -2e-4, 5e-4), "W": (1e-5, 2e-5, -3e-5),
-         "M": 4 / 3 * math.pi * 16}
-    u = S.start_field(shape, owner, [p])
+    p = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "F": (1e-4, -2e-5, 3e-5), "T": (0, 1e-4, 2e-4),
+         "U": (1e-3, -2e-4, 5e-4), "W": (1e-5, 2e-5, -3e-5), "M": 4 / 3 * math.pi * 16}
+    u = S.start_field(shape, owner, [p], 1 / 6)
     tot = u[owner == 0].sum(0) + p["M"] * np.array(p["U"])
     assert np.abs(tot).max() < 1e-15 * np.prod(shape)
     # solid nodes move rigidly
@@ -255,3 +255,65 @@ def test_start_field_has_zero_total_momentum():
     assert np.allclose(u[owner == 1], rig, atol=1e-18)
     f = S.equilibrium(1.0, u)
     assert np.allclose(f.sum(1), 1.0, atol=1e-15)
+
+
+def _ball(N):
+    n = np.arange(-N, N + 1)
+    X, Y, Z = np.meshgrid(n, n, n, indexing="ij")
+    v = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(float)
+    r = np.linalg.norm(v, axis=1)
+    return v[(r > 0) & (r <= N)]
+
+
+def test_periodic_modes_reproduce_hasimoto():
+    """Summed over all wave vectors (a ball |n| <= 48 plus the isotropic
+    continuum estimate of the rest, 1 / (6 pi^2 mu R^2 k_max) per unit force)
+    and averaged over the sphere (one more sinc(kR)), the periodic modes give
+    the velocity of a simple-cubic array of spheres under a force, which
+    Hasimoto's expansion fixes: U / U_Stokes = 1 - 2.837297 x + 4.19 x^3,
+    x = R/L.  The sphere model (uniform traction) may differ at O(x^3)."""
+    n = _ball(48)
+    k = 2 * np.pi * n
+    kk = np.sqrt((k * k).sum(1))
+    for x in (0.03, 0.05, 0.1, 0.15):
+        u = S.periodic_modes(k, (1.0, 0, 0), (0, 0, 0), x, 1.0, 1.0)
+        U = (u[:, 0].real * np.sin(kk * x) / (kk * x)).sum() + 1 / (6 * math.pi ** 2 * x * x * 2 * math.pi * 48)
+        ratio = U * 6 * math.pi * x
+        assert abs(ratio - (1 - 2.837297 * x + 4.19 * x ** 3)) < 2e-3, (x, ratio)
+
+
+def test_periodic_modes_rotlet_near_field():
+    """Near a small sphere turned by a torque, the summed periodic modes give
+    the free-space rotlet T x d / (8 pi mu r^3) up to the images' O(1/V)
+    correction."""
+    n = _ball(48)
+    k = 2 * np.pi * n
+    R, T = 0.05, np.array([0.0, 0.0, 1.0])
+    u = S.periodic_modes(k, (0, 0, 0), T, R, 1.0, 1.0)
+    for d in (np.array([0.12, 0.03, 0.0]), np.array([0.1, -0.05, 0.04])):
+        v = (u * np.exp(1j * (k @ d))[:, None]).sum(0).real
+        ref = np.cross(T, d) / (8 * math.pi * np.linalg.norm(d) ** 3)
+        assert np.abs(v - ref).max() < 0.25 * np.linalg.norm(np.cross(T, d)) + 0.01 * np.linalg.norm(ref)
+
+
+def test_start_field_low_modes_are_periodic():
+    """The start field's modes |n_i| <= 2 equal the periodic solution's and
+    the rest equal the free field's (before the momentum shift, on a box with
+    no particle nodes)."""
+    shape, mu = (20, 18, 22), 1 / 6
+    part = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "F": (1e-4, -2e-5, 3e-5), "T": (0, 1e-4, 2e-4),
+            "U": (0, 0, 0), "W": (0, 0, 0), "M": 0.0}
+    owner = np.zeros(np.prod(shape), dtype=np.uint16)
+    u = S.start_field(shape, owner, [part], mu)
+    _, uf = S.free_field(shape, [part], mu)
+    N = np.prod(shape)
+    A = np.fft.fftn(u.reshape(22, 18, 20, 3), axes=(0, 1, 2)) / N
+    B = np.fft.fftn(uf.reshape(22, 18, 20, 3), axes=(0, 1, 2)) / N
+    ns, c = S.periodic_coefficients(shape, part["centre"], part["F"], part["T"], S.req(part["axes"]), mu)
+    for n, cn in zip(ns, c):
+        assert np.allclose(A[n[2] % 22, n[1] % 18, n[0] % 20], cn, rtol=0, atol=1e-12 * np.abs(c).max())
+    mask = np.ones((22, 18, 20), bool)
+    for n in ns + [(0, 0, 0)]:
+        mask[n[2] % 22, n[1] % 18, n[0] % 20] = False
+    assert np.allclose(A[mask], B[mask], rtol=0, atol=1e-12 * np.abs(B).max())
+    assert np.abs(A[0, 0, 0]).max() < 1e-15
