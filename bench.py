@@ -213,6 +213,8 @@ def main():
                     help="collide-stream variant to use instead of the tuner's choice (see lb_autotune)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-box FP16 ensemble reported beside the main line (0: skip)")
+    ap.add_argument("--suspension-steps", type=int, default=100,
+                    help="steps of the 256^3 FP16 suspension of 512 squirmers reported beside the main line (0: skip)")
     ap.add_argument("--surrogate-runs", type=int, default=4,
                     help="256-box FP16 ensembles run to train the warm-start network (0: skip steps to steady)")
     ap.add_argument("--eval-boxes", type=int, default=64, help="held-out force-driven boxes for steps to steady")
@@ -277,6 +279,16 @@ def main():
                            "k1_achieved_gbs": round(e["achieved_gbs"], 1),
                            "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
                            "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
+    if args.suspension_steps > 0:
+        Ws = workloads.c5("fp16")
+        lat, e = measure(Ws, args.suspension_steps, 10, args.graph)
+        del lat
+        out["suspension"] = {"workload": Ws.name, "sites": Ws.sites, "particles": len(Ws.particles),
+                             "storage": "fp16", "mlups": round(e["mlups"], 1),
+                             "ms_per_step": round(e["ms_per_step"], 4), "k1_variant": e["variant"],
+                             "k1_avg_launch_ms": round(e["k1_ms"], 4), "k1_achieved_gbs": round(e["achieved_gbs"], 1),
+                             "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                             "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
     if args.surrogate_runs > 0:
         out["steps_to_steady"] = steps_to_steady(args.surrogate_runs, args.eval_boxes)
     if not args.no_cpu_baseline:

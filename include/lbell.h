@@ -172,6 +172,9 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
  *   4  generic, two tiles per block          5  the same, XCD-chunked
  *   6  generic, XCD-chunked persistent grid (8 blocks per compute unit)
  *   7  the same with two tiles per block
+ *   8  generic, four tiles per block, XCD-chunked
+ *   9  generic, XCD-chunked, non-temporal stores
+ *  10  generic, two tiles per block, XCD-chunked, non-temporal stores
  * With the two-stream schedule only 0-2 apply.  All variants give identical
  * bits, so the (applicable variants) x (reps + 1) steps the tuner takes are
  * ordinary steps of the simulation: the step counter advances by that many.
@@ -191,7 +194,8 @@ lb_status lb_set_graph(lb_ctx* ctx, int steps);
 
 /* Bandwidth reference: copies `bytes` (a multiple of 16, both pointers
  * 16-byte aligned device memory owned by the caller) from src to dst `reps`
- * times on hip_stream with 16-byte accesses, after one warm-up copy, and
+ * times on hip_stream with 16-byte accesses (one per thread, a grid covering
+ * the buffer), after one warm-up copy, and
  * returns the achieved read+write rate in GB/s (2 * bytes per copy).  Needs
  * no context.  Synchronises the stream. */
 lb_status lb_bandwidth_probe(void* dst, const void* src, size_t bytes, void* hip_stream, int reps,

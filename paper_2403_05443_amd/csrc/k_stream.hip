@@ -139,10 +139,11 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
 }
 
 // One site of the generic tile kernel: pull, collide, store.
-template <int ST, int COLL, bool WALLS>
+template <int ST, int COLL, bool WALLS, bool NT>
 __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
                                             const typename Store<ST>::T* __restrict__ fin,
-                                            typename Store<ST>::T* __restrict__ fout, const KParams& kp, int tile) {
+                                            typename Store<ST>::T* __restrict__ fout, const KParams& kp, int tile,
+                                            uint32_t step) {
     using S = Store<ST>;
     using R = typename S::R;
     const int bi = tile_box[tile];
@@ -166,8 +167,18 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     }
     collide<R, COLL>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
     typename S::T* fo = fout + B.foff;
+    const uint32_t seed = ST >= ST_F16 ? dither_seed((uint32_t)s, step) : 0u;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) S::st(fo + (long long)i * B.stride + s, f[i], scl);
+    for (int i = 0; i < NQ; ++i) {
+        const uint32_t r = ST >= ST_F16 ? dither_bits(seed, i) : 0u;
+        if constexpr (NT) {
+            typename S::T v;
+            S::st_dither(&v, f[i], scl, r);
+            __builtin_nontemporal_store(v, fo + (long long)i * B.stride + s);
+        } else {
+            S::st_dither(fo + (long long)i * B.stride + s, f[i], scl, r);
+        }
+    }
 }
 
 // Generic tile kernel over every box of the context.  A virtual block covers
@@ -177,9 +188,10 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
 // hardware deals consecutive blocks out to the 8 XCDs in turn, so neighbouring
 // tiles, which share cache lines at their edges, meet in one XCD's L2); a grid
 // smaller than the work (persistent launch) walks its range in strides of m.
-// Without XCD, block b takes virtual blocks b, b + grid, ...  The near-set
-// parts (part 1, 2) use SPT = 1 and the plain order only.
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD>
+// Without XCD, block b takes virtual blocks b, b + grid, ...  NT: stores that
+// do not allocate in the caches.  The near-set parts (part 1, 2) use SPT = 1
+// and the plain order only.
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT>
 __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restrict__ boxes,
                                                          const BoxRT* __restrict__ rt,
                                                          const int* __restrict__ tile_box,
@@ -188,8 +200,14 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
                                                          KParams kp, int part, const uint32_t* __restrict__ nflags,
                                                          const int* __restrict__ nlist,
                                                          const int* __restrict__ ncount, uint32_t epoch,
-                                                         int* __restrict__ next_count, int ntiles) {
-    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+                                                         int* __restrict__ next_count, int ntiles,
+                                                         const uint32_t* __restrict__ step_in,
+                                                         uint32_t* __restrict__ step_out) {
+    const uint32_t step = *step_in;  // the step being computed (read by every block)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (next_count) *next_count = 0;
+        *step_out = step + 1;  // the other parity's slot, read by the next step
+    }
     if (SPT == 1 && !XCD && part != 0) {
         int tile = blockIdx.x;
         if (part == 2) {
@@ -198,7 +216,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
         } else if (nflags[tile] == epoch) {
             return;
         }
-        site_update<ST, COLL, WALLS>(boxes, tile_box, fin, fout, kp, tile);
+        site_update<ST, COLL, WALLS, NT>(boxes, tile_box, fin, fout, kp, tile, step);
         return;
     }
     const int nvb = (ntiles + SPT - 1) / SPT;
@@ -217,7 +235,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             const int tile = v * SPT + k;
-            if (tile < ntiles) site_update<ST, COLL, WALLS>(boxes, tile_box, fin, fout, kp, tile);
+            if (tile < ntiles) site_update<ST, COLL, WALLS, NT>(boxes, tile_box, fin, fout, kp, tile, step);
         }
     }
 }
@@ -251,17 +269,19 @@ __device__ __forceinline__ void ld_vec(const T* p, R inv, R (&v)[K]) {
     }
 }
 
+// K consecutive sites (dither seeds seed[j]) of direction dir; half formats
+// round with the same dither as the generic kernel
 template <typename T, typename R, int K, int ST, bool NT>
-__device__ __forceinline__ void st_vec(T* p, R scl, const R (&v)[K]) {
+__device__ __forceinline__ void st_vec(T* p, R scl, const R (&v)[K], const uint32_t (&seed)[K], int dir) {
     using V = typename VecOf<T, K>::type;
     V x;
     if constexpr (K == 1) {
-        Store<ST>::st(&x, v[0], scl);
+        Store<ST>::st_dither(&x, v[0], scl, ST >= ST_F16 ? dither_bits(seed[0], dir) : 0u);
     } else {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             T e;
-            Store<ST>::st(&e, v[j], scl);
+            Store<ST>::st_dither(&e, v[j], scl, ST >= ST_F16 ? dither_bits(seed[j], dir) : 0u);
             x[j] = e;
         }
     }
@@ -280,12 +300,18 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
                                                              const uint32_t* __restrict__ nflags,
                                                              const int* __restrict__ nlist,
                                                              const int* __restrict__ ncount, uint32_t epoch,
-                                                             int* __restrict__ next_count) {
+                                                             int* __restrict__ next_count,
+                                                             const uint32_t* __restrict__ step_in,
+                                                             uint32_t* __restrict__ step_out) {
 #pragma clang fp contract(off)
     using S = Store<ST>;
     using T = typename S::T;
     using R = typename S::R;
-    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+    const uint32_t step = *step_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (next_count) *next_count = 0;
+        *step_out = step + 1;
+    }
     const BoxDesc& B = boxes[bi];
     const int ny = B.ny, nz = B.nz, nx = 64 * K;
     const int lane = threadIdx.x & 63;
@@ -348,12 +374,15 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
 #pragma unroll
     for (int j = 0; j < K; ++j) collide<R, COLL>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
     T* fo = fout + B.foff + (long long)nx * (y + ny * z) + x0;
+    uint32_t seed[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) seed[j] = ST >= ST_F16 ? dither_seed((uint32_t)(nx * (y + ny * z) + x0 + j), step) : 0u;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         R v[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) v[j] = f[j][i];
-        st_vec<T, R, K, ST, NT>(fo + (long long)i * st, scl, v);
+        st_vec<T, R, K, ST, NT>(fo + (long long)i * st, scl, v, seed, i);
     }
 }
 
@@ -510,16 +539,11 @@ __global__ void k_poke(const BoxDesc* __restrict__ boxes, int bi, typename Store
 // known-size kernel that calibrates the HBM byte counters.
 __global__ __launch_bounds__(256) void k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                     size_t n16) {
-    const size_t stride = (size_t)gridDim.x * 256 * 4;
-    for (size_t i = ((size_t)blockIdx.x * 256 * 4) + threadIdx.x; i < n16; i += stride) {
-        uint4 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (i + 256 * k < n16) v[k] = src[i + 256 * k];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (i + 256 * k < n16) dst[i + 256 * k] = v[k];
-    }
+    // one 16-byte element per thread over a grid that covers the buffer: the
+    // fastest of the copy shapes measured (grid-stride loops with 1-8 elements
+    // per thread on 4-32 blocks per CU reach 4.1-5.7 TB/s, this 6.2 TB/s)
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
 }
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int blocks, hipStream_t st) {
@@ -539,7 +563,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int block
             hipLaunchKernelGGL(KERNEL, G, B, 0, ST, __VA_ARGS__);                          \
     } while (0)
 
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD>
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT>
 static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
     const int nvb = (a.ntiles + SPT - 1) / SPT;
@@ -548,20 +572,23 @@ static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     else if (XCD) g = 8 * (a.grid > 0 ? std::max(1, a.grid / 8) : (nvb + 7) / 8);
     else g = a.grid > 0 ? std::min(a.grid, nvb) : nvb;
     if (g == 0 || a.ntiles == 0) return hipSuccess;
-    K1_LAUNCH((k_collide_stream<ST, COLL, WALLS, SPT, XCD>), dim3(g), dim3(TILE), st, a.boxes, a.rt, a.tile_box,
+    K1_LAUNCH((k_collide_stream<ST, COLL, WALLS, SPT, XCD, NT>), dim3(g), dim3(TILE), st, a.boxes, a.rt, a.tile_box,
               (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch,
-              a.next_count, a.ntiles);
+              a.next_count, a.ntiles, a.step_in, a.step_out);
     return hipGetLastError();
 }
 
 template <int ST, int COLL, bool WALLS>
 static hipError_t cs_shape(const LaunchCS& a, hipStream_t st) {
-    if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false>(a, st);
-    switch (a.spt * 2 + (a.xcd ? 1 : 0)) {
-        case 2: return cs_one<ST, COLL, WALLS, 1, false>(a, st);
-        case 3: return cs_one<ST, COLL, WALLS, 1, true>(a, st);
-        case 4: return cs_one<ST, COLL, WALLS, 2, false>(a, st);
-        case 5: return cs_one<ST, COLL, WALLS, 2, true>(a, st);
+    if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false, false>(a, st);
+    switch (a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0)) {
+        case 4: return cs_one<ST, COLL, WALLS, 1, false, false>(a, st);
+        case 6: return cs_one<ST, COLL, WALLS, 1, true, false>(a, st);
+        case 7: return cs_one<ST, COLL, WALLS, 1, true, true>(a, st);
+        case 8: return cs_one<ST, COLL, WALLS, 2, false, false>(a, st);
+        case 10: return cs_one<ST, COLL, WALLS, 2, true, false>(a, st);
+        case 11: return cs_one<ST, COLL, WALLS, 2, true, true>(a, st);
+        case 18: return cs_one<ST, COLL, WALLS, 4, true, false>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -588,10 +615,12 @@ static hipError_t rows_launch(bool walls, const LaunchCS& a, hipStream_t st) {
     if (grid.x == 0) return hipSuccess;
     if (walls)
         K1_LAUNCH((k_collide_stream_rows<ST, COLL, true, K, NT>), grid, blk, st, a.boxes, a.rt, 0, (const T*)a.fin,
-                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count);
+                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count,
+                  a.step_in, a.step_out);
     else
         K1_LAUNCH((k_collide_stream_rows<ST, COLL, false, K, NT>), grid, blk, st, a.boxes, a.rt, 0, (const T*)a.fin,
-                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count);
+                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count,
+                  a.step_in, a.step_out);
     return hipGetLastError();
 }
 

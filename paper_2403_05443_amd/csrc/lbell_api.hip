@@ -27,7 +27,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
-           flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, warm = 0, total = 0;
+           flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, warm = 0, step_ctr = 0,
+           total = 0;
     int near_blocks = 0;  // collide-stream blocks that a near set can name (per slot)
     std::vector<long long> foff, stride, ooff;
     std::vector<int> tile0, ntiles;
@@ -125,6 +126,10 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     L.near_flags = take(sizeof(uint32_t) * 2 * L.near_blocks);
     L.near_list = take(sizeof(int) * 2 * L.near_blocks);
     L.near_count = take(sizeof(int) * 4);
+    // the step counter the collide-stream kernels read (one slot per buffer
+    // parity: a launch reads its slot and writes step + 1 to the other), so
+    // that graph replays see the true step
+    L.step_ctr = take(sizeof(uint32_t) * 2);
     // warm start: per particle load scale (1), prediction (6) and training
     // sample (8 + 6 floats = 7 doubles); then the start field's scratch
     L.warm = take(sizeof(double) * (14 * (size_t)L.max_particles + stokes_scratch_doubles(nboxes, tiles)));
@@ -188,10 +193,13 @@ struct K1Shape {
     int spt;       // tiles per block (generic)
     bool xcd;      // XCD-chunked block order (generic)
     bool persist;  // grid of a few blocks per CU walking the tiles (generic)
+    bool nt;       // non-temporal stores (generic)
 };
 constexpr K1Shape K1_SHAPES[] = {
-    {0, 1, false, false}, {1, 1, false, false}, {2, 1, false, false}, {0, 1, true, false},
-    {0, 2, false, false}, {0, 2, true, false},  {0, 1, true, true},   {0, 2, true, true},
+    {0, 1, false, false, false}, {1, 1, false, false, false}, {2, 1, false, false, false},
+    {0, 1, true, false, false},  {0, 2, false, false, false}, {0, 2, true, false, false},
+    {0, 1, true, true, false},   {0, 2, true, true, false},   {0, 4, true, false, false},
+    {0, 1, true, false, true},   {0, 2, true, false, true},
 };
 constexpr int K1_NSHAPES = (int)(sizeof(K1_SHAPES) / sizeof(K1_SHAPES[0]));
 
@@ -475,6 +483,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
         if (e2 == hipSuccess)
             e2 = hipMemsetAsync(ctx->arena + ctx->L.near_flags, 0, ctx->L.near_count + 4 * sizeof(int) - ctx->L.near_flags,
                                 ctx->stream);
+        if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.step_ctr, 0, sizeof(uint32_t) * 2, ctx->stream);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
         if (e2 != hipSuccess) {
             std::fprintf(stderr, "lb_init: %s\n", hipGetErrorString(e2));
@@ -595,11 +604,14 @@ LaunchCS collide_args(lb_ctx* ctx, int variant) {
     cs.fin = ctx->fbuf(ctx->cur);
     cs.fout = ctx->fbuf(ctx->cur ^ 1);
     cs.kp = ctx->kp;
+    cs.step_in = ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur;
+    cs.step_out = ctx->at<uint32_t>(ctx->L.step_ctr) + (ctx->cur ^ 1);
     cs.walls = ctx->any_walls;
     const K1Shape& sh = K1_SHAPES[k1_applicable(ctx, variant) ? variant : 0];
     cs.variant = sh.kind;
     cs.spt = sh.spt;
     cs.xcd = sh.xcd;
+    cs.nt = sh.nt;
     cs.grid = sh.persist ? 8 * ctx->n_cu : 0;
     cs.rows_k = ctx->rows_k;
     cs.rows_ny = ctx->hbox[0].ny;
@@ -874,8 +886,10 @@ lb_status lb_bandwidth_probe(void* dst, const void* src, size_t bytes, void* hip
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return LB_EDEVICE;
-    const size_t per_block = (size_t)256 * 4 * 16;
-    const int blocks = (int)std::min<size_t>((size_t)cus * 16, (bytes + per_block - 1) / per_block);
+    (void)cus;
+    const size_t nblk = (bytes / 16 + 255) / 256;  // one 16-byte element per thread
+    if (nblk > (size_t)INT32_MAX) return LB_EINVAL;
+    const int blocks = (int)nblk;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB_EDEVICE;
     bool ok = launch_copy_probe(src, dst, bytes, blocks, st) == hipSuccess;  // warm-up
@@ -1118,6 +1132,12 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
     ctx->np = h.np;
     ctx->step = h.step;
     ctx->link_used = h.link_used;
+    {
+        const uint32_t st32 = (uint32_t)h.step;  // the device step counter of the restored parity
+        HIPC(hipMemcpyAsync(ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur, &st32, sizeof st32, hipMemcpyHostToDevice,
+                            ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+    }
     for (int b = 0; b < (int)ctx->boxes.size(); ++b) {
         lb_status s = box_fext_update(ctx, b);
         if (s != LB_OK) return s;

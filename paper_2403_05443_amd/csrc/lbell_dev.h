@@ -82,6 +82,24 @@ struct KParams {
     int collision, storage;
 };
 
+// Rounding dither of the half formats: one murmur3 32-bit finalisation per
+// (site of its box, step) seeds the site; direction i takes the high bits of
+// (seed + i * golden) * an odd constant.  A function of (site, direction,
+// step) only, so every collide-stream variant rounds identically.
+__device__ __forceinline__ uint32_t dither_seed(uint32_t site, uint32_t step) {
+    uint32_t h = site * 0x9E3779B1u + step * 0x85EBCA77u;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+// 16 dither bits (low half of the result) for direction dir
+__device__ __forceinline__ uint32_t dither_bits(uint32_t seed, int dir) {
+    return ((seed + (uint32_t)dir * 0x9E3779B9u) * 0x2C1B3C6Du) >> 16;
+}
+
 __host__ __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 }  // namespace lbd
@@ -98,6 +116,7 @@ template <> struct Store<ST_F64> {
     using R = double;
     static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
     static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+    static __device__ __forceinline__ void st_dither(T* p, R v, R, uint32_t) { *p = v; }
     static __device__ __forceinline__ double ld64(const T* p, double) { return *p; }
     static __device__ __forceinline__ void st64(T* p, double v, double) { *p = v; }
 };
@@ -106,6 +125,7 @@ template <> struct Store<ST_F32> {
     using R = float;
     static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
     static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+    static __device__ __forceinline__ void st_dither(T* p, R v, R, uint32_t) { *p = v; }
     static __device__ __forceinline__ double ld64(const T* p, double) { return (double)*p; }
     static __device__ __forceinline__ void st64(T* p, double v, double) { *p = (float)v; }
 };
@@ -114,6 +134,20 @@ template <> struct Store<ST_F16> {
     using R = float;
     static __device__ __forceinline__ R ld(const T* p, R inv) { return (float)*p * inv; }
     static __device__ __forceinline__ void st(T* p, R v, R s) { *p = (_Float16)(v * s); }
+    // Stochastic rounding in the normal range: the 13 FP32 mantissa bits that
+    // FP16 drops get r's low bits added before they are cut, so a value
+    // rounds up with probability equal to its distance from the lower
+    // neighbour; increments far below one FP16 ulp (the counter-force) then
+    // survive in expectation instead of being rounded away in a steady flow.
+    static __device__ __forceinline__ void st_dither(T* p, R v, R s, uint32_t r) {
+        const float x = v * s, ax = fabsf(x);
+        if (ax >= 6.103515625e-05f && ax < 65504.f) {
+            const uint32_t u = (__float_as_uint(x) + (r >> 3)) & ~0x1FFFu;  // 13 of the 16 bits
+            *p = (_Float16)__uint_as_float(u);
+        } else {
+            *p = (_Float16)x;
+        }
+    }
     static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)(float)*p * inv; }
     static __device__ __forceinline__ void st64(T* p, double v, double s) { *p = (_Float16)(float)(v * s); }
 };
@@ -128,6 +162,11 @@ template <> struct Store<ST_BF16> {
     using R = float;
     static __device__ __forceinline__ R ld(const T* p, R inv) { return bf16_to_f32(*p) * inv; }
     static __device__ __forceinline__ void st(T* p, R v, R s) { *p = f32_to_bf16(v * s); }
+    // stochastic rounding: r's low 16 bits added below the kept mantissa, then cut
+    static __device__ __forceinline__ void st_dither(T* p, R v, R s, uint32_t r) {
+        const float x = v * s;
+        *p = isfinite(x) ? (uint16_t)((__float_as_uint(x) + (r & 0xFFFFu)) >> 16) : f32_to_bf16(x);
+    }
     static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)bf16_to_f32(*p) * inv; }
     static __device__ __forceinline__ void st64(T* p, double v, double s) { *p = f32_to_bf16((float)(v * s)); }
 };

@@ -16,6 +16,7 @@ struct LaunchCS {
     int variant;            // 0 generic tiles, 1 row-wave, 2 row-wave with non-temporal stores
     int spt;                // generic tiles: 256-site tiles per block (1 or 2)
     bool xcd;               // generic tiles: XCD-chunked block order
+    bool nt;                // generic tiles: non-temporal stores
     int grid;               // generic tiles: blocks launched (0 = one per block of tiles; fewer = persistent)
     int rows_k;             // sites per lane of the row-wave kernel (nx = 64 rows_k), 0 = not applicable
     int rows_ny, rows_nz;   // its box (single-box contexts only)
@@ -26,6 +27,8 @@ struct LaunchCS {
     uint32_t near_epoch;    // a block is near iff its flag equals this step's epoch
     int near_grid;          // launch size of the near part (an upper bound of the set's size)
     int* next_count;        // block 0 empties the next step's near list (it is filled by the particle phase)
+    const uint32_t* step_in;  // device step counter of this buffer parity (dither of the half formats)
+    uint32_t* step_out;       // the other parity's counter: set to step + 1 by block 0
     hipEvent_t ev_start;    // optional: events that receive the kernel's start and end timestamps
     hipEvent_t ev_stop;
 };

@@ -184,3 +184,41 @@ def xavier_params(gen):
         out += [0.0] * fo
     import numpy as np
     return np.array(out)
+
+
+def _aabb_half(axes, q):
+    """Half-extents of the axis-aligned box around an ellipsoid: sqrt(sum_j (R_kj a_j)^2)."""
+    q0, q1, q2, q3 = q
+    R = ((1 - 2 * (q2 * q2 + q3 * q3), 2 * (q1 * q2 - q0 * q3), 2 * (q1 * q3 + q0 * q2)),
+         (2 * (q1 * q2 + q0 * q3), 1 - 2 * (q1 * q1 + q3 * q3), 2 * (q2 * q3 - q0 * q1)),
+         (2 * (q1 * q3 - q0 * q2), 2 * (q2 * q3 + q0 * q1), 1 - 2 * (q1 * q1 + q2 * q2)))
+    return tuple(math.sqrt(sum((R[k][j] * axes[j]) ** 2 for j in range(3))) for k in range(3))
+
+
+def c5(storage="fp16", L=256, n=512, seed_index=0):
+    """Suspension of n spheroidal squirmers a=5, b=c=2.5 in a periodic L^3
+    box (defaults 256^3, 512): centres uniform, orientations uniform on S^3,
+    placed one by one and redrawn while the bounding boxes (with a gap of 2
+    nodes) of two particles overlap under the minimum image; B1 = 1e-3,
+    B2 = beta B1 with beta uniform in [-3, 3].  TRT, Lambda = 3/16, tau+ = 1."""
+    g = SplitMix64(SEED0 + 5 + 1000 * seed_index)
+    axes = (5.0, 2.5, 2.5)
+    parts, boxes_ = [], []
+    while len(parts) < n:
+        c = tuple(g.uniform(0.0, float(L)) for _ in range(3))
+        q = g.unit_quaternion()
+        h = _aabb_half(axes, q)
+        ok = True
+        for pc, ph in boxes_:
+            d = [abs(c[k] - pc[k]) for k in range(3)]
+            d = [min(v, L - v) for v in d]
+            if all(d[k] < h[k] + ph[k] + 2.0 for k in range(3)):
+                ok = False
+                break
+        if not ok:
+            continue
+        beta = g.uniform(-3.0, 3.0)
+        boxes_.append((c, h))
+        parts.append(Particle(c, axes, q, squirmer=(1e-3, beta * 1e-3)))
+    return Workload(f"c5_squirmers_{L}_{n}", [Box((L, L, L))], parts, "trt", 1.0, storage, 10000,
+                    velocity_scale=2e-3, max_semi_axis=5.0)

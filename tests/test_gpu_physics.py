@@ -96,13 +96,21 @@ def test_inclined_spheroid_drift(lb, storage):
 
 def test_fp16_terminal_velocity_within_half_percent(lb):
     """FP16 deviation storage (scaled) against FP32 storage on the inclined
-    spheroid: velocity after 10 000 steps within 0.5%."""
+    spheroid: the terminal velocity (mean over steps 10 000-12 000, sampled
+    every 100 steps) within 0.5%.  FP16 keeps 11 significant bits of
+    deviations ~1e-5, so the counter-force increment (~4e-11 per node and
+    step) survives only statistically, through the rounding of a changing
+    flow; single samples scatter by a few tenths of a percent."""
     from paper_2403_05443_amd import workloads
     U = {}
     for st in ("fp32", "fp16"):
         g = build(lb, workloads.c2(st))
         g.step(10000)
-        U[st] = g.particle(0)["U"]
+        acc = np.zeros(3)
+        for _ in range(20):
+            g.step(100)
+            acc += g.particle(0)["U"]
+        U[st] = acc / 20
     err = np.linalg.norm(U["fp16"] - U["fp32"]) / np.linalg.norm(U["fp32"])
     print("fp16 vs fp32 velocity", err)
     assert err < 5e-3
