@@ -167,6 +167,8 @@ struct lb_ctx {
     // queue behind the streaming kernel; LBELL_OVERLAP=1 turns it on)
     bool overlap = false;
     bool fused = true;  // one particle kernel per step when no box holds two particles (LBELL_FUSED=0: two kernels)
+    int opb_np = -1;    // particle count for which opb was computed
+    bool opb = true;    // no box holds two particles
     hipStream_t nstream = nullptr;
     hipEvent_t evK = nullptr, evP = nullptr, evStart = nullptr;
     // graph replay of whole groups of steps (0 = off); one cached executable
@@ -654,10 +656,14 @@ lb_status launch_collide(lb_ctx* ctx, hipStream_t st, hipEvent_t t0 = nullptr, h
 // Particle phase of the step whose collide-stream output is the current
 // buffer; also builds the near set of the next step from x(t + 1).
 bool one_particle_per_box(lb_ctx* ctx) {
-    std::vector<int> cnt(ctx->boxes.size(), 0);
-    for (int p = 0; p < ctx->np; ++p)
-        if (++cnt[ctx->hpart[p].box] > 1) return false;
-    return true;
+    if (ctx->opb_np != ctx->np) {  // recomputed when the particle count changes
+        std::vector<int> cnt(ctx->boxes.size(), 0);
+        ctx->opb = true;
+        for (int p = 0; p < ctx->np; ++p)
+            if (++cnt[ctx->hpart[p].box] > 1) ctx->opb = false;
+        ctx->opb_np = ctx->np;
+    }
+    return ctx->opb;
 }
 
 lb_status launch_particles(lb_ctx* ctx, hipStream_t st) {
