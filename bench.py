@@ -181,7 +181,7 @@ def steps_to_steady(runs, eval_boxes):
         steps += n
     t_data = time.perf_counter() - t0
     Xa, Ya = runner.augment(np.concatenate(Xs), np.concatenate(Ys))
-    sur, info = runner.train_surrogate(Xa, Ya, epochs=300)
+    sur, info = runner.train_surrogate(Xa, Ya)
     t_train = time.perf_counter() - t0 - t_data
     We = workloads.c4("fp16", eval_boxes, seed_index=100, torque=False)
     res = runner.compare_starts(We, sur)

@@ -94,15 +94,20 @@ def shuffle(X, Y, seed):
     return X[idx], Y[idx]
 
 
-def train_surrogate(X, Y, seed=2403054430, epochs=300, batch=256, lr=1e-3, val_frac=0.2):
-    """Xavier initialisation, seeded shuffle, 80/20 split, Adam on the GPU.
-    Returns (surrogate, info)."""
+def train_surrogate(X, Y, seed=2403054430, epochs=1000, batch=256, lr=3e-3, lr_end=3e-5, stages=10, val_frac=0.2):
+    """Xavier initialisation, seeded shuffle, 80/20 split, Adam on the GPU with
+    the step size lowered geometrically from lr to lr_end over `stages`
+    equal parts of the epochs (the moments carry over).  Returns
+    (surrogate, info)."""
     X, Y = shuffle(X, Y, seed)
     nval = int(round(val_frac * len(X)))
     Xv, Yv, Xt, Yt = X[:nval], Y[:nval], X[nval:], Y[nval:]
     sur = lbell.Surrogate(max_samples=max(len(X), 64), params=workloads.xavier_params(workloads.SplitMix64(seed)))
     L0 = sur.grad(Xt, Yt)[0]
-    Lt = sur.train(Xt, Yt, epochs=epochs, batch=batch, lr=lr)
+    per = max(1, epochs // stages)
+    for k in range(stages):
+        step = lr * (lr_end / lr) ** (k / max(stages - 1, 1))
+        Lt = sur.train(Xt, Yt, epochs=per, batch=batch, lr=step)
     Lv = sur.grad(Xv, Yv)[0] if nval else float("nan")
     var = float(np.mean((Yv - Yv.mean(0)) ** 2)) if nval else float("nan")
     return sur, {"samples": len(X), "train": len(Xt), "val": nval, "loss_init": L0, "loss_train": Lt,

@@ -249,7 +249,7 @@ def test_surrogate_warm_start_reaches_steady_state_sooner(lb):
         Xs.append(X)
         Ys.append(Y)
     Xa, Ya = runner.augment(np.concatenate(Xs), np.concatenate(Ys))
-    sur, info = runner.train_surrogate(Xa, Ya, epochs=150)
+    sur, info = runner.train_surrogate(Xa, Ya, epochs=300)
     print("training", info)
     assert info["loss_val"] < 0.01 * info["val_target_variance"]
     res = runner.compare_starts(workloads.c4("fp32", 32, seed_index=200, torque=False), sur)
