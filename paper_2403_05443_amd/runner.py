@@ -219,11 +219,12 @@ def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005):
     err0 = {"surrogate": np.linalg.norm(Us[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1),
             "control": np.linalg.norm(Uc[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)}
     pred_err = np.linalg.norm(pred[:, :3] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)
-    med = {k: float(np.median(v[ok])) for k, v in n.items()}
+    med = {k: float(np.median(v[ok])) if ok.any() else float("nan") for k, v in n.items()}
     return {"boxes": int(len(W.particles)), "steady_boxes": int(ok.sum()), "steps": steps, "every": every,
             "tol": tol, "median_steps": med,
             "surrogate_over_plain": med["surrogate"] / med["plain"],
             "control_over_plain": med["control"] / med["plain"],
-            "median_prediction_error": float(np.median(pred_err[ok])),
-            "median_error_after_first_sample": {k: float(np.median(v[ok])) for k, v in err0.items()},
-            "fallback_rate": float(fallback[ok].mean()), "per_box": n, "steady": ok}
+            "median_prediction_error": float(np.median(pred_err[ok])) if ok.any() else float("nan"),
+            "median_error_after_first_sample": {k: float(np.median(v[ok])) if ok.any() else float("nan")
+                                                for k, v in err0.items()},
+            "fallback_rate": float(fallback[ok].mean()) if ok.any() else float("nan"), "per_box": n, "steady": ok}

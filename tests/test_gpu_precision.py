@@ -1,0 +1,60 @@
+"""Precision report: the error of each storage format against the FP64
+oracle on the same run (the 32^3 settling spheroid with a seeded
+orientation and a torque, 500 steps), for velocity, angular velocity,
+force, torque and mass.  Bounds: FP64 1e-9 and FP32 1e-5 (the parity bars);
+the half formats keep 11 (FP16) or 8 (BF16) significant bits of the scaled
+deviations, rounded stochastically: 2e-3 for FP16 and 2e-2 for BF16 on the
+velocities and loads of this transient run."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+BOUNDS = {"fp64": 1e-9, "fp32": 1e-5, "fp16": 2e-3, "bf16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    from paper_2403_05443_amd import lbell
+    lbell.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lbell
+
+
+@pytest.fixture(scope="module")
+def reference():
+    import oracle
+    from paper_2403_05443_amd import workloads
+    W = workloads.c1r()
+    p = W.particles[0]
+    o = oracle.OracleSim(W.boxes[0].shape, W.collision, W.tau, counterforce=True)
+    po = o.add_ellipsoid(p.centre, p.axes, p.quat)
+    o.set_external(po, p.force, p.torque)
+    m0 = o.mass()
+    o.step(500)
+    F, T = o.force_torque(po)
+    return {"state": o.particle(po), "F": F, "T": T, "dm": o.mass() / m0 - 1}
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "bf16"])
+def test_precision_against_oracle(lb, reference, storage):
+    from paper_2403_05443_amd import runner, workloads
+    W = workloads.c1r(storage)
+    g = runner.build_lattice(W)
+    m0 = g.mass(0)
+    g.step(500)
+    A = g.particle(0)
+    F, T = g.force_torque(0)
+    B = reference["state"]
+    a = W.particles[0].axes[0]
+    nU, nF = np.linalg.norm(B["U"]), np.linalg.norm(reference["F"])
+    err = {"U": np.abs(A["U"] - B["U"]).max() / nU,
+           "W": np.abs(A["W"] - B["W"]).max() / max(np.linalg.norm(B["W"]), nU / a),
+           "F": np.abs(F - reference["F"]).max() / nF,
+           "T": np.abs(T - reference["T"]).max() / max(np.linalg.norm(reference["T"]), nF * a),
+           "mass": abs((g.mass(0) / m0 - 1) - reference["dm"])}
+    print(storage, {k: float(f"{v:.2e}") for k, v in err.items()})
+    for k in ("U", "W", "F", "T"):
+        assert err[k] < BOUNDS[storage], (k, err)
+    assert err["mass"] < {"fp64": 1e-13, "fp32": 1e-11, "fp16": 1e-7, "bf16": 1e-6}[storage]
