@@ -327,6 +327,38 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         fbv[k] = l < nl ? S::ld64(f + (long long)b * st + s, inv) : 0.0;
     }
 
+    // steps 4-5, matrix part, built while the link loads are in flight: one
+    // lane per entry of [M + zFU, zFW; zTU, I' + dI/dt + zTW], with
+    // I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x (W = Omega(t)); lanes
+    // 36-38 store I' Omega(t) for the right-hand side
+    const double M = P.M;
+    const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
+    if (tid < 39) {
+        const double Ib0 = P.Ib[0], Ib1 = P.Ib[1], Ib2 = P.Ib[2];
+        auto Il = [&](int i, int j) {
+            return Rm[i][0] * Ib0 * Rm[j][0] + Rm[i][1] * Ib1 * Rm[j][1] + Rm[i][2] * Ib2 * Rm[j][2];
+        };
+        auto Wx = [&](int i, int j) {
+            return i == j ? 0.0 : (i == 0 ? (j == 1 ? -W0[2] : W0[1]) : (i == 1 ? (j == 0 ? W0[2] : -W0[0])
+                                                                         : (j == 0 ? -W0[1] : W0[0])));
+        };
+        if (tid < 36) {
+            const int i = tid / 6, j = tid % 6;
+            double v = P.zeta[tid];
+            if (i == j && i < 3) v += M;
+            if (i >= 3 && j >= 3) {
+                const int ii = i - 3, jj = j - 3;
+                double d = 0;
+                for (int k = 0; k < 3; ++k) d += Wx(ii, k) * Il(k, jj) - Il(ii, k) * Wx(k, jj);
+                v += Il(ii, jj) + d;
+            }
+            A[i][j] = v;
+        } else {
+            const int ii = tid - 36;
+            A[3 + ii][6] = Il(ii, 0) * W0[0] + Il(ii, 1) * W0[1] + Il(ii, 2) * W0[2];
+        }
+    }
+
     // step 3: velocity-independent force and torque (+ slip part)
     double acc[12];
 #pragma unroll
@@ -366,52 +398,23 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
     block_reduce<12>(acc, red);
 
-    // steps 4-5: one lane per entry of [M + zFU, zFW; zTU, I' + dI/dt + zTW | rhs], with
-    // I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x (W = Omega(t))
-    const double M = P.M;
-    const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
-    if (tid < 42) {
-        const double Ib0 = P.Ib[0], Ib1 = P.Ib[1], Ib2 = P.Ib[2];
-        auto Il = [&](int i, int j) {
-            return Rm[i][0] * Ib0 * Rm[j][0] + Rm[i][1] * Ib1 * Rm[j][1] + Rm[i][2] * Ib2 * Rm[j][2];
-        };
-        auto Wx = [&](int i, int j) {
-            return i == j ? 0.0 : (i == 0 ? (j == 1 ? -W0[2] : W0[1]) : (i == 1 ? (j == 0 ? W0[2] : -W0[0])
-                                                                         : (j == 0 ? -W0[1] : W0[0])));
-        };
-        if (tid < 36) {
-            const int i = tid / 6, j = tid % 6;
-            double v = P.zeta[tid];
-            if (i == j && i < 3) v += M;
-            if (i >= 3 && j >= 3) {
-                const int ii = i - 3, jj = j - 3;
-                double d = 0;
-                for (int k = 0; k < 3; ++k) d += Wx(ii, k) * Il(k, jj) - Il(ii, k) * Wx(k, jj);
-                v += Il(ii, jj) + d;
-            }
-            A[i][j] = v;
-        } else {
-            const int i = tid - 36;
-            if (i < 3) {
-                // counter-force density on the particle's own nodes (box-wide g = -sum F_ext / N)
-                const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
-                A[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
-            } else {
-                const int ii = i - 3;
-                A[i][6] = (Il(ii, 0) * W0[0] + Il(ii, 1) * W0[1] + Il(ii, 2) * W0[2]) + acc[3 + ii] + acc[9 + ii] +
-                          P.Text[ii] + P.Lp[ii];
-            }
-        }
-    }
     __syncthreads();
     if (tid == 0) {
-        // Gaussian elimination with partial pivoting in registers (every
-        // index is a compile-time constant; row swaps are selects)
+        // right-hand side [M U + F0' ; I' Omega + T0'] (counter-force density
+        // g = -sum F_ext / N on the particle's own nodes, transition impulses)
         double R[6][7];
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) R[i][c] = A[i][c];
+            for (int c = 0; c < 6; ++c) R[i][c] = A[i][c];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
+            R[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
+            R[3 + i][6] = A[3 + i][6] + acc[3 + i] + acc[9 + i] + P.Text[i] + P.Lp[i];
+        }
+        // Gaussian elimination with partial pivoting in registers (every
+        // index is a compile-time constant; row swaps are selects)
         bool ok = true;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -449,7 +452,6 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             for (int c = r + 1; c < 6; ++c) sum -= R[r][c] * sol[c];
             sol[r] = sum / R[r][r];
         }
-        {
         bool bad = !ok;
         for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
         {  // surface speed |U| + |Omega| max(a,b,c) must stay below half a node per step
@@ -462,59 +464,69 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             atomicOr(a.flags, (int)F_NONFINITE);
             for (int k = 0; k < 6; ++k) sol[k] = k < 3 ? U0[k] : W0[k - 3];
         }
-        // hydrodynamic force and torque over the step (eqs. Fsplit, Tsplit)
-        for (int i = 0; i < 3; ++i) {
-            double zf = 0, zt = 0;
-            for (int j = 0; j < 6; ++j) {
-                zf += P.zeta[6 * i + j] * sol[j];
-                zt += P.zeta[6 * (3 + i) + j] * sol[j];
-            }
-            Pg->F[i] = acc[i] + acc[6 + i] + P.Pp[i] - zf;
-            Pg->T[i] = acc[3 + i] + acc[9 + i] + P.Lp[i] - zt;
-            Pg->Pp[i] = 0.0;
-            Pg->Lp[i] = 0.0;
-        }
         for (int k = 0; k < 6; ++k) bc[k] = sol[k];
         bc[6] = P.wsum > 0.0 ? P.dm / P.wsum : 0.0;
-        // step 7 (its inputs are fixed now; the links below use x_c(t), q(t) from registers)
-        double Wm[3];
-        for (int i = 0; i < 3; ++i) {
+    }
+    __syncthreads();
+
+    // step 7 and the hydrodynamic force/torque, one piece per lane of the last
+    // wave, while the other waves start the bounce-back (which uses x_c(t),
+    // q(t) from registers and U(t+1), Omega(t+1) from bc)
+    if (tid >= PBLOCK - 64) {
+        const int k = tid - (PBLOCK - 64);
+        if (k < 6) {  // F, T over the step (eqs. Fsplit, Tsplit)
+            const int i = k % 3;
+            double z = 0;
+            for (int j = 0; j < 6; ++j) z += P.zeta[6 * k + j] * bc[j];
+            // each lane clears, after reading it, the pending impulse it used
+            // (another lane's LDS write would race with this read)
+            if (k < 3) {
+                Pg->F[i] = acc[i] + acc[6 + i] + P.Pp[i] - z;
+                Pg->Pp[i] = 0.0;
+                if (keep_lds) P.Pp[i] = 0.0;
+            } else {
+                Pg->T[i] = acc[3 + i] + acc[9 + i] + P.Lp[i] - z;
+                Pg->Lp[i] = 0.0;
+                if (keep_lds) P.Lp[i] = 0.0;
+            }
+        } else if (k < 9) {  // position (eq. posupdate), wrapped into the box
+            const int i = k - 6;
             const int n3 = i == 0 ? nx : (i == 1 ? ny : nz);
-            const double dx = 0.5 * (sol[i] + U0[i]);
+            const double dx = 0.5 * (bc[i] + U0[i]);
             double xn = xc[i] + dx;
             if (xn >= n3) xn -= n3;
             if (xn < 0.0) xn += n3;
+            const double xu = P.xu[i] + dx;
             Pg->xc[i] = xn;
-            Pg->xu[i] = P.xu[i] + dx;
-            Pg->U[i] = sol[i];
-            Pg->W[i] = sol[3 + i];
-            Wm[i] = 0.5 * (W0[i] + sol[3 + i]);
-        }
-        const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
-        if (nrm != 0.0) {
-            const double c = cos(0.5 * nrm), sn = sin(0.5 * nrm);
-            const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
-            Pg->q[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
-            Pg->q[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
-            Pg->q[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
-            Pg->q[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
-        }
-        Pg->dm = 0.0;
-        if (keep_lds) {  // the remap that follows in the same work-group reads the new state here
-            for (int i = 0; i < 3; ++i) {
-                P.xc[i] = Pg->xc[i];
-                P.xu[i] = Pg->xu[i];
-                P.U[i] = sol[i];
-                P.W[i] = sol[3 + i];
-                P.Pp[i] = 0.0;
-                P.Lp[i] = 0.0;
+            Pg->xu[i] = xu;
+            Pg->U[i] = bc[i];
+            Pg->W[i] = bc[3 + i];
+            if (keep_lds) {
+                P.xc[i] = xn;
+                P.xu[i] = xu;
+                P.U[i] = bc[i];
+                P.W[i] = bc[3 + i];
             }
-            for (int k = 0; k < 4; ++k) P.q[k] = Pg->q[k];
-            P.dm = 0.0;
-        }
+        } else if (k == 9) {  // orientation (eqs. qnplus0, qnplus1) with the mean angular velocity
+            const double Wm[3] = {0.5 * (W0[0] + bc[3]), 0.5 * (W0[1] + bc[4]), 0.5 * (W0[2] + bc[5])};
+            const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
+            double qn[4] = {q[0], q[1], q[2], q[3]};
+            if (nrm != 0.0) {
+                const double c = cos(0.5 * nrm), sn = sin(0.5 * nrm);
+                const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
+                qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
+                qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
+                qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
+                qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+            }
+            for (int j = 0; j < 4; ++j) Pg->q[j] = qn[j];
+            if (keep_lds)
+                for (int j = 0; j < 4; ++j) P.q[j] = qn[j];
+        } else if (k == 10) {
+            Pg->dm = 0.0;
+            if (keep_lds) P.dm = 0.0;
         }
     }
-    __syncthreads();
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step
     const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / 36.0;
