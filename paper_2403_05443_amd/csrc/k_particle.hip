@@ -223,6 +223,37 @@ struct ZAcc {
 };
 
 
+// Entry (i, j) of zeta (eqs. drag1-drag4) for the particle's link set at
+// its current centre, from the moments stored when the set was enumerated:
+// every link offset is r = rho - d with d = xu - xref, so with D the matrix
+// of d x . the blocks are zeta_FU = k Z0, zeta_FW = k (Z1 - Z0 D^T) and
+// zeta_TW = k (Z2 - Z1^T D^T - D Z1 + D Z0 D^T), k = rho0 / 6 (36 w = 6 w / c_s^2).
+// Both (i, j) and (j, i) evaluate the upper-triangle entry, so the matrix
+// stays exactly symmetric.
+__device__ __forceinline__ double zeta_entry(const PartDev& P, int i, int j, double rho0) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    auto ut = [](int a, int b) {  // upper-triangle index of the symmetric 3x3 (a, b)
+        const int l = a < b ? a : b, h = a < b ? b : a;
+        return l == 0 ? h : (l == 1 ? 2 + h : 5);
+    };
+    if (hi < 3) return rho0 * (double)P.zm0[ut(lo, hi)] / 6.0;
+    const double d[3] = {P.xu[0] - P.xref[0], P.xu[1] - P.xref[1], P.xu[2] - P.xref[2]};
+    const double D[3][3] = {{0.0, -d[2], d[1]}, {d[2], 0.0, -d[0]}, {-d[1], d[0], 0.0}};
+    double v;
+    if (lo < 3) {
+        const int jj = hi - 3;
+        v = P.zm1[3 * lo + jj];
+        for (int b = 0; b < 3; ++b) v -= (double)P.zm0[ut(lo, b)] * D[jj][b];
+    } else {
+        const int ii = lo - 3, jj = hi - 3;
+        v = P.zm2[ut(ii, jj)];
+        for (int b = 0; b < 3; ++b) v -= P.zm1[3 * b + ii] * D[jj][b] + D[ii][b] * P.zm1[3 * b + jj];
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) v += D[ii][b] * (double)P.zm0[ut(b, c)] * D[jj][c];
+    }
+    return rho0 * v / 6.0;
+}
+
 // Remap window of a particle: axis-aligned bounding box of the ellipsoid plus
 // two nodes (the whole axis when that is at least the box edge).
 __device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc& B, int lo[3], int wn[3],
@@ -717,22 +748,20 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         return;
     }
 
+    if (mode == 0 && !changed) {
+        // no node changed state: the link set, the solid count and the link
+        // weights stay, no mass or momentum moved; only zeta follows the centre
+        if (tid < 36) Pg->zeta[tid] = zeta_entry(P, tid / 6, tid % 6, rho0);
+        if (a.near.flags) mark_near(a.near, B, lo, wn);
+        return;
+    }
+
     ZAcc z;
     z.clear();
     int running = 0;
     const int lcap = P.lcap;
     uint32_t* L = a.links + P.lbase;
-    if (mode == 0 && !changed) {
-        // no node changed state, so the link set is unchanged: only the drag
-        // matrices move with the centre
-        running = P.nlinks;
-        for (int l = tid; l < running; l += PBLOCK) {
-            const uint32_t cd = L[l];
-            const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
-            const int x = s % nx, t = s / nx, y = t % ny, zz = t / ny;
-            z.add(b, x, y, zz, xc, nx, ny, nz);
-        }
-    } else {
+    {
         // pass 2: boundary links (fluid x, x + c_b solid here), staged in LDS
         // and written in (window index, direction) order
         for (int base = 0; base < nsites; base += PBLOCK) {
@@ -847,6 +876,12 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         const int ns = itot(7);
         if (ns != P.n_solid) atomicAdd(&a.rt[bi].n_solid, ns - P.n_solid);
         Pg->n_solid = ns;
+    } else if (tid >= 45 && tid < 69) {  // the moments of the new link set about this centre
+        const int k = tid - 45;
+        if (k < 6) Pg->zm0[k] = itot(k);
+        else if (k < 15) Pg->zm1[k - 6] = red[7 + (k - 6)][0];
+        else if (k < 21) Pg->zm2[k - 15] = red[16 + (k - 15)][0];
+        else Pg->xref[k - 21] = P.xu[k - 21];
     }
     if (mode == 0 && a.near.flags) mark_near(a.near, B, lo, wn);
 }

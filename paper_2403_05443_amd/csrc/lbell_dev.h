@@ -68,10 +68,16 @@ struct PartDev {
     double Fext[3], Text[3];
     double B1, B2;        // squirmer modes
     double zeta[36];      // [F;T] x [U;W] drag matrix of the current links
+    // moments of the current link set about the unwrapped centre xref at
+    // which it was enumerated (rho = link midpoint - xref, weights 36 w):
+    // zm1 = sum c (rho x c)^T (3x3), zm2 = sum (rho x c)(rho x c)^T (upper
+    // triangle); with zm0 = sum c c^T they give zeta at any later centre
+    double zm1[9], zm2[6], xref[3];
     double dm, Pp[3], Lp[3];  // pending mass / momentum / angular momentum of transitions
     double F[3], T[3];    // hydrodynamic force and torque of the last step
     double wsum;          // sum of w_b over the current links
     int box, nlinks, lcap, n_solid;
+    int zm0[6];           // sum 36 w c c^T (upper triangle), exact
     long long lbase;      // offset of this particle's links in the pool
 };
 
