@@ -33,6 +33,23 @@ __device__ __forceinline__ int rcz(int b) { return (int)((CZP >> (2 * b)) & 3ull
 __device__ __forceinline__ int rw36(int b) { return b == 0 ? 12 : (b <= 6 ? 2 : 1); }
 __device__ __forceinline__ int ropp(int b) { return b == 0 ? 0 : ((b & 1) ? b + 1 : b - 1); }
 
+// q = floor(i / w) and r = i - q w for 0 <= i < 2^31, w >= 1, given
+// rw = 1.0 / w: the FP64 product is within 2^-21 of i / w, so its truncation
+// is q or one off, and one correction either way makes it exact.  Cheaper
+// than an integer division by a value known only at run time.
+__device__ __forceinline__ int divmod(int i, int w, double rw, int& r) {
+    int q = (int)((double)i * rw);
+    r = i - q * w;
+    if (r >= w) {
+        ++q;
+        r -= w;
+    } else if (r < 0) {
+        --q;
+        r += w;
+    }
+    return q;
+}
+
 __device__ __forceinline__ double minimg(double d, int n) {
     if (d >= 0.5 * n) d -= n;
     else if (d < -0.5 * n) d += n;
@@ -338,6 +355,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     const int nl = P.nlinks;
     const uint32_t* L = a.links + P.lbase;
     const double inv = a.kp.inv_scale, scl = a.kp.scale, rho0 = a.kp.rho0;
+    const double rnx = 1.0 / nx, rny = 1.0 / ny;
     double Rm[3][3];
     rotmat(q, Rm);
     const double e[3] = {Rm[0][0], Rm[1][0], Rm[2][0]};
@@ -396,7 +414,8 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
     auto accumulate = [&](uint32_t cd, double fb) {
         const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
-        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        int x, y;
+        const int z = divmod(divmod(s, nx, rnx, x), ny, rny, y);
         const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b);
         const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
                              minimg(((double)z + 0.5 * c2) - xc[2], nz)};
@@ -433,55 +452,57 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     if (tid == 0) {
         // right-hand side [M U + F0' ; I' Omega + T0'] (counter-force density
         // g = -sum F_ext / N on the particle's own nodes, transition impulses)
-        double R[6][7];
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) R[i][c] = A[i][c];
+        double rhs[6];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
-            R[i][6] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
-            R[3 + i][6] = A[3 + i][6] + acc[3 + i] + acc[9 + i] + P.Text[i] + P.Lp[i];
+            rhs[i] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
+            rhs[3 + i] = A[3 + i][6] + acc[3 + i] + acc[9 + i] + P.Text[i] + P.Lp[i];
         }
-        // Gaussian elimination with partial pivoting in registers (every
-        // index is a compile-time constant; row swaps are selects)
+        // The matrix is symmetric (zeta is, I' is, and so is the commutator
+        // of [Omega]x with I'), so the elimination runs as A = L D L^T on the
+        // lower triangle, in registers, with one reciprocal per pivot.
+        double Lw[6][6], dv[6], di[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) Lw[i][j] = A[i][j];
         bool ok = true;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            int pv = k;
-            double best = fabs(R[k][k]);
+        for (int j = 0; j < 6; ++j) {
+            double v[6];
 #pragma unroll
-            for (int r = k + 1; r < 6; ++r)
-                if (fabs(R[r][k]) > best) {
-                    best = fabs(R[r][k]);
-                    pv = r;
-                }
-            ok = ok && best > 1e-300;
+            for (int k = 0; k < j; ++k) v[k] = Lw[j][k] * dv[k];
+            double d = Lw[j][j];
 #pragma unroll
-            for (int r = k + 1; r < 6; ++r) {
-                const bool sw = pv == r;
+            for (int k = 0; k < j; ++k) d -= Lw[j][k] * v[k];
+            dv[j] = d;
+            ok = ok && fabs(d) > 1e-300;
+            di[j] = 1.0 / d;
 #pragma unroll
-                for (int c = k; c < 7; ++c) {
-                    const double t = R[k][c];
-                    R[k][c] = sw ? R[r][c] : t;
-                    R[r][c] = sw ? t : R[r][c];
-                }
-            }
+            for (int i = j + 1; i < 6; ++i) {
+                double t = Lw[i][j];
 #pragma unroll
-            for (int r = k + 1; r < 6; ++r) {
-                const double m = R[r][k] / R[k][k];
-#pragma unroll
-                for (int c = k; c < 7; ++c) R[r][c] -= m * R[k][c];
+                for (int k = 0; k < j; ++k) t -= Lw[i][k] * v[k];
+                Lw[i][j] = t * di[j];
             }
         }
         double sol[6];
 #pragma unroll
-        for (int r = 5; r >= 0; --r) {
-            double sum = R[r][6];
+        for (int i = 0; i < 6; ++i) {
+            double t = rhs[i];
 #pragma unroll
-            for (int c = r + 1; c < 6; ++c) sum -= R[r][c] * sol[c];
-            sol[r] = sum / R[r][r];
+            for (int k = 0; k < i; ++k) t -= Lw[i][k] * sol[k];
+            sol[i] = t;
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sol[i] *= di[i];
+#pragma unroll
+        for (int i = 5; i >= 0; --i) {
+            double t = sol[i];
+#pragma unroll
+            for (int k = i + 1; k < 6; ++k) t -= Lw[k][i] * sol[k];
+            sol[i] = t;
         }
         bool bad = !ok;
         for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
@@ -563,7 +584,8 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / 36.0;
     auto bounce = [&](uint32_t cd, double fb) {
         const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
-        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        int x, y;
+        const int z = divmod(divmod(s, nx, rnx, x), ny, rny, y);
         const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b);
         const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
                              minimg(((double)z + 0.5 * c2) - xc[2], nz)};
@@ -635,6 +657,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     bool whole[3];
     particle_window(P, B, lo, wn, whole);
     const int nsites = wn[0] * wn[1] * wn[2];
+    const double rw0 = 1.0 / wn[0], rw1 = 1.0 / wn[1];
     if (((nsites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32) > a.lds_words) {
         if (tid == 0) atomicOr(a.flags, (int)F_WINDOW);
         return;
@@ -644,16 +667,17 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
     int nsol = 0;
     bool changed = false;
-    for (int base = 0; base < nsites; base += PBLOCK * KREG) {
-        uint16_t own[KREG];
-        int sidx[KREG], gxyz[KREG][3];
+    for (int base = 0; base < nsites; base += PBLOCK * KSCAN) {
+        uint16_t own[KSCAN];
+        int sidx[KSCAN], gxyz[KSCAN][3];
 #pragma unroll
-        for (int k = 0; k < KREG; ++k) {  // issue the node-map loads of the whole group first
+        for (int k = 0; k < KSCAN; ++k) {  // issue the node-map loads of the whole group first
             const int i = base + k * PBLOCK + tid;
             sidx[k] = -1;
             own[k] = 0;
             if (i < nsites) {
-                const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
+                int wx, wy;
+                const int wz = divmod(divmod(i, wn[0], rw0, wx), wn[1], rw1, wy);
                 gxyz[k][0] = wrap(lo[0] + wx, nx);
                 gxyz[k][1] = wrap(lo[1] + wy, ny);
                 gxyz[k][2] = wrap(lo[2] + wz, nz);
@@ -662,7 +686,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             }
         }
 #pragma unroll
-        for (int k = 0; k < KREG; ++k) {
+        for (int k = 0; k < KSCAN; ++k) {
             if (base + k * PBLOCK >= nsites) break;  // uniform over the block
             bool in = false;
             const int s = sidx[k];
@@ -769,7 +793,8 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             uint32_t lm = 0;
             int s = 0, gx = 0, gy = 0, gz = 0;
             if (i < nsites && !((bits[i >> 5] >> (i & 31)) & 1u)) {
-                const int wx = i % wn[0], tt = i / wn[0], wy = tt % wn[1], wz = tt / wn[1];
+                int wx, wy;
+                const int wz = divmod(divmod(i, wn[0], rw0, wx), wn[1], rw1, wy);
                 gx = wrap(lo[0] + wx, nx);
                 gy = wrap(lo[1] + wy, ny);
                 gz = wrap(lo[2] + wz, nz);
