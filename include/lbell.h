@@ -143,7 +143,10 @@ lb_status lb_set_external(lb_ctx* ctx, int id, const double F[3], const double T
  * x axis.  Requires b == c.  B1 = B2 = 0 switches it off. */
 lb_status lb_set_squirmer(lb_ctx* ctx, int id, double B1, double B2);
 
-/* Overwrites the particle's translational and angular velocity (lab frame). */
+/* Overwrites the particle's translational and angular velocity (lab frame).
+ * LB_EINVAL unless |U| + |W| max(a, b, c) <= 0.5 (the surface-speed limit
+ * that every solved velocity obeys: a boundary point moves less than half a
+ * node per step, which the remap window relies on). */
 lb_status lb_set_velocity(lb_ctx* ctx, int id, const double U[3], const double W[3]);
 
 /* Particle density (default rho0); rescales M and the body inertia. */
@@ -326,8 +329,9 @@ lb_status lbs_destroy(lbs* s);
 
 /* Warm start of every particle of the context: the surrogate predicts each
  * particle's steady velocities from its current state and external load;
- * they are set as the particles' velocities, and the fluid of every box is
- * then started as lb_stokes_start does.  pred (may be NULL) receives the predicted
+ * they are set as the particles' velocities (a prediction above the
+ * surface-speed limit of lb_set_velocity is scaled down to it), and the fluid
+ * of every box is then started as lb_stokes_start does.  pred (may be NULL) receives the predicted
  * lab-frame (U, Omega) of every particle, 6 doubles per particle id.  Needs
  * np <= the surrogate's max_samples; LB_EINVAL for boxes with walls.
  * Synchronises. */

@@ -272,7 +272,13 @@ __device__ __forceinline__ double zeta_entry(const PartDev& P, int i, int j, dou
 }
 
 // Remap window of a particle: axis-aligned bounding box of the ellipsoid plus
-// two nodes (the whole axis when that is at least the box edge).
+// one node (the whole axis when that is at least the box edge).  It holds
+//  - every node inside at t+1: such a node lies beyond x_c - h (h the box
+//    half-extent, padded by 1e-9 against the rounding of the inside test),
+//  - their fluid neighbours (one node further), and
+//  - every node inside at t: a boundary point moves at most half a node per
+//    step (the solve keeps |U| + |Omega| max(a,b,c) <= 0.5 and the update
+//    uses the mean of two such velocities), so within the same one node.
 __device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc& B, int lo[3], int wn[3],
                                                 bool whole[3]) {
     double Rm[3][3];
@@ -282,8 +288,8 @@ __device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc&
         const double h = sqrt((Rm[k][0] * P.axes[0]) * (Rm[k][0] * P.axes[0]) +
                               (Rm[k][1] * P.axes[1]) * (Rm[k][1] * P.axes[1]) +
                               (Rm[k][2] * P.axes[2]) * (Rm[k][2] * P.axes[2]));
-        lo[k] = (int)floor(P.xc[k] - h) - 2;
-        wn[k] = (int)floor(P.xc[k] + h) + 2 - lo[k] + 1;
+        lo[k] = (int)floor(P.xc[k] - h - 1e-9) - 1;
+        wn[k] = (int)floor(P.xc[k] + h + 1e-9) + 1 - lo[k] + 1;
         whole[k] = wn[k] >= n3[k];
         if (whole[k]) {
             lo[k] = 0;

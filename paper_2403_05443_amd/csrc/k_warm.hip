@@ -77,7 +77,19 @@ __global__ void k_warm_apply(PartDev* __restrict__ parts, int np, const float* _
     const double R = eq_radius(P), s = s_in[p];
     const double cu = s / (6.0 * M_PI * mu * R), cw = s / (8.0 * M_PI * mu * R * R);
     const float* y = Y + (long long)p * MLP_OUT;
-    const double Ub[3] = {y[0] * cu, y[1] * cu, y[2] * cu}, Wb[3] = {y[3] * cw, y[4] * cw, y[5] * cw};
+    double Ub[3] = {y[0] * cu, y[1] * cu, y[2] * cu}, Wb[3] = {y[3] * cw, y[4] * cw, y[5] * cw};
+    {  // a prediction above the surface-speed limit of the solve is scaled down to it
+        const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
+        const double sp = sqrt(Ub[0] * Ub[0] + Ub[1] * Ub[1] + Ub[2] * Ub[2]) +
+                          sqrt(Wb[0] * Wb[0] + Wb[1] * Wb[1] + Wb[2] * Wb[2]) * amax;
+        if (!(sp <= 0.5)) {
+            const double f = sp > 0.5 && sp <= 1e300 ? 0.5 / sp : 0.0;  // a non-finite prediction becomes rest
+            for (int k = 0; k < 3; ++k) {
+                Ub[k] = f == 0.0 ? 0.0 : Ub[k] * f;
+                Wb[k] = f == 0.0 ? 0.0 : Wb[k] * f;
+            }
+        }
+    }
     for (int k = 0; k < 3; ++k) {
         P.U[k] = Rm[k][0] * Ub[0] + Rm[k][1] * Ub[1] + Rm[k][2] * Ub[2];
         P.W[k] = Rm[k][0] * Wb[0] + Rm[k][1] * Wb[1] + Rm[k][2] * Wb[2];

@@ -578,6 +578,13 @@ lb_status lb_set_velocity(lb_ctx* ctx, int id, const double U[3], const double W
     lb_status s = check_id(ctx, id);
     if (s != LB_OK) return s;
     if (!U || !W) return LB_EINVAL;
+    {
+        const double* ax = ctx->hpart[id].axes;
+        const double amax = std::max(ax[0], std::max(ax[1], ax[2]));
+        const double sp = std::sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) +
+                          std::sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]) * amax;
+        if (!(sp <= 0.5)) return fail(ctx, LB_EINVAL, "velocity above the surface-speed limit");
+    }
     s = write_part_field(ctx, id, offsetof(PartDev, U), U, 3);
     if (s != LB_OK) return s;
     return write_part_field(ctx, id, offsetof(PartDev, W), W, 3);
