@@ -240,21 +240,21 @@ struct ZAcc {
 };
 
 
-// Entry (i, j) of zeta (eqs. drag1-drag4) for the particle's link set at
-// its current centre, from the moments stored when the set was enumerated:
+// Entry (i, j) of zeta (eqs. drag1-drag4) for the particle's link set with
+// its centre at xu (unwrapped), from the moments stored when the set was enumerated:
 // every link offset is r = rho - d with d = xu - xref, so with D the matrix
 // of d x . the blocks are zeta_FU = k Z0, zeta_FW = k (Z1 - Z0 D^T) and
 // zeta_TW = k (Z2 - Z1^T D^T - D Z1 + D Z0 D^T), k = rho0 / 6 (36 w = 6 w / c_s^2).
 // Both (i, j) and (j, i) evaluate the upper-triangle entry, so the matrix
 // stays exactly symmetric.
-__device__ __forceinline__ double zeta_entry(const PartDev& P, int i, int j, double rho0) {
+__device__ __forceinline__ double zeta_entry(const PartDev& P, const double xu[3], int i, int j, double rho0) {
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     auto ut = [](int a, int b) {  // upper-triangle index of the symmetric 3x3 (a, b)
         const int l = a < b ? a : b, h = a < b ? b : a;
         return l == 0 ? h : (l == 1 ? 2 + h : 5);
     };
     if (hi < 3) return rho0 * (double)P.zm0[ut(lo, hi)] / 6.0;
-    const double d[3] = {P.xu[0] - P.xref[0], P.xu[1] - P.xref[1], P.xu[2] - P.xref[2]};
+    const double d[3] = {xu[0] - P.xref[0], xu[1] - P.xref[1], xu[2] - P.xref[2]};
     const double D[3][3] = {{0.0, -d[2], d[1]}, {d[2], 0.0, -d[0]}, {-d[1], d[0], 0.0}};
     double v;
     if (lo < 3) {
@@ -414,10 +414,11 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         }
     }
 
-    // step 3: velocity-independent force and torque (+ slip part)
-    double acc[12];
+    // step 3: velocity-independent force and torque, slip part included (the
+    // two only ever enter summed)
+    double acc[6];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 6; ++k) acc[k] = 0.0;
     auto accumulate = [&](uint32_t cd, double fb) {
         const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
         int x, y;
@@ -437,12 +438,12 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             double us[3];
             squirmer_slip(ax, bx, e, B1, B2, r, us);
             const double kuc = (rw36(b) / 6.0) * rho0 * (us[0] * c0 + us[1] * c1 + us[2] * c2);
-            acc[6] -= kuc * c0;
-            acc[7] -= kuc * c1;
-            acc[8] -= kuc * c2;
-            acc[9] -= kuc * rc0;
-            acc[10] -= kuc * rc1;
-            acc[11] -= kuc * rc2;
+            acc[0] -= kuc * c0;
+            acc[1] -= kuc * c1;
+            acc[2] -= kuc * c2;
+            acc[3] -= kuc * rc0;
+            acc[4] -= kuc * rc1;
+            acc[5] -= kuc * rc2;
         }
     };
 #pragma unroll
@@ -452,7 +453,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         const uint32_t cd = L[l];
         accumulate(cd, S::ld64(f + (long long)(cd >> SITE_BITS) * st + (int)(cd & SITE_MASK), inv));
     }
-    block_reduce<12>(acc, red);
+    block_reduce<6>(acc, red);
 
     __syncthreads();
     if (tid == 0) {
@@ -462,8 +463,8 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
-            rhs[i] = M * U0[i] + acc[i] + acc[6 + i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
-            rhs[3 + i] = A[3 + i][6] + acc[3 + i] + acc[9 + i] + P.Text[i] + P.Lp[i];
+            rhs[i] = M * U0[i] + acc[i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
+            rhs[3 + i] = A[3 + i][6] + acc[3 + i] + P.Text[i] + P.Lp[i];
         }
         // The matrix is symmetric (zeta is, I' is, and so is the commutator
         // of [Omega]x with I'), so the elimination runs as A = L D L^T on the
@@ -539,11 +540,11 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             // each lane clears, after reading it, the pending impulse it used
             // (another lane's LDS write would race with this read)
             if (k < 3) {
-                Pg->F[i] = acc[i] + acc[6 + i] + P.Pp[i] - z;
+                Pg->F[i] = acc[i] + P.Pp[i] - z;
                 Pg->Pp[i] = 0.0;
                 if (keep_lds) P.Pp[i] = 0.0;
             } else {
-                Pg->T[i] = acc[3 + i] + acc[9 + i] + P.Lp[i] - z;
+                Pg->T[i] = acc[3 + i] + P.Lp[i] - z;
                 Pg->Lp[i] = 0.0;
                 if (keep_lds) P.Lp[i] = 0.0;
             }
@@ -584,6 +585,13 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             Pg->dm = 0.0;
             if (keep_lds) P.dm = 0.0;
         }
+    } else if (tid >= PBLOCK - 128 && tid < PBLOCK - 128 + 36) {
+        // zeta at x(t+1) for the current link set, from its moments; the
+        // remap replaces it only if some node changes side
+        const int e = tid - (PBLOCK - 128);
+        double xu[3];
+        for (int i = 0; i < 3; ++i) xu[i] = P.xu[i] + 0.5 * (bc[i] + U0[i]);
+        Pg->zeta[e] = zeta_entry(P, xu, e / 6, e % 6, rho0);
     }
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step
@@ -780,8 +788,8 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
 
     if (mode == 0 && !changed) {
         // no node changed state: the link set, the solid count and the link
-        // weights stay, no mass or momentum moved; only zeta follows the centre
-        if (tid < 36) Pg->zeta[tid] = zeta_entry(P, tid / 6, tid % 6, rho0);
+        // weights stay, no mass or momentum moved, and the solve has already
+        // evaluated zeta of this link set at the new centre
         if (a.near.flags) mark_near(a.near, B, lo, wn);
         return;
     }
