@@ -340,10 +340,52 @@ struct SolveShm {
     double A[6][7];  // the 6x6 system, eliminated by thread 0
 };
 
+// The links of one thread (l = tid + k PBLOCK, k < KREG): codes and stored
+// post-collision populations, held in registers from the force reduction to
+// the bounce-back.
+template <typename T>
+struct LinkRegs {
+    uint32_t code[KREG];
+    T raw[KREG];
+};
+
+// Stages the particle record in LDS (one 8-byte word per thread) and loads
+// this thread's links, all from the global record: the record load and the
+// code loads go out together, then the population loads, and those stay in
+// flight across the LDS write and the barrier.  A lane without a link reads
+// element 0 of the box (always valid) and never uses it, so no load sits in
+// a branch, where its use, and a wait for it, would follow at once.
+template <int ST>
+__device__ __forceinline__ void load_particle(const LaunchPart& a, int p, PartDev* Pl,
+                                              LinkRegs<typename Store<ST>::T>& lr) {
+    using T = typename Store<ST>::T;
+    const PartDev* Pg = a.parts + p;
+    constexpr int NW = (int)(sizeof(PartDev) / 8);
+    static_assert(sizeof(PartDev) % 8 == 0 && NW <= PBLOCK, "one 8-byte word of the record per thread");
+    const int tid = threadIdx.x;
+    const unsigned long long sv = tid < NW ? reinterpret_cast<const unsigned long long*>(Pg)[tid] : 0ull;
+    const int nl = Pg->nlinks;
+    const BoxDesc& B = a.boxes[Pg->box];
+    const uint32_t* L = a.links + Pg->lbase;
+    const T* f = (const T*)a.f + B.foff;
+    const long long st = B.stride;
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) {
+        const int l = tid + k * PBLOCK;
+        lr.code[k] = l < nl ? L[l] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < KREG; ++k)
+        lr.raw[k] = f[(long long)(lr.code[k] >> SITE_BITS) * st + (int)(lr.code[k] & SITE_MASK)];
+    if (tid < NW) reinterpret_cast<unsigned long long*>(Pl)[tid] = sv;
+    __syncthreads();
+}
+
 // Steps 3-7 for particle p whose record is staged in LDS (P).  The new state
 // goes to global memory; with keep_lds the LDS copy is updated as well.
 template <int ST>
-__device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev& P, SolveShm& sh, bool keep_lds) {
+__device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev& P, SolveShm& sh,
+                                            const LinkRegs<typename Store<ST>::T>& lr, bool keep_lds) {
     using S = Store<ST>;
     using T = typename S::T;
     double (*red)[PWAVES] = sh.red;
@@ -354,7 +396,9 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     T* f = (T*)a.f + B.foff;
     const long long st = B.stride;
     const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
-    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
+    // the state at t in registers: with keep_lds the LDS record is
+    // overwritten with the state at t+1 while other lanes still need these
+    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]}, xu0[3] = {P.xu[0], P.xu[1], P.xu[2]};
     const double q[4] = {P.q[0], P.q[1], P.q[2], P.q[3]};
     const double B1 = P.B1, B2 = P.B2, ax = P.axes[0], bx = P.axes[1];
     const bool sq = B1 != 0.0 || B2 != 0.0;
@@ -366,21 +410,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     rotmat(q, Rm);
     const double e[3] = {Rm[0][0], Rm[1][0], Rm[2][0]};
 
-    // links of this thread: codes and post-collision populations stay in
-    // registers from the force reduction to the bounce-back
-    uint32_t code[KREG];
-    double fbv[KREG];
-#pragma unroll
-    for (int k = 0; k < KREG; ++k) {
-        const int l = tid + k * PBLOCK;
-        code[k] = l < nl ? L[l] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < KREG; ++k) {
-        const int l = tid + k * PBLOCK;
-        const int s = (int)(code[k] & SITE_MASK), b = (int)(code[k] >> SITE_BITS);
-        fbv[k] = l < nl ? S::ld64(f + (long long)b * st + s, inv) : 0.0;
-    }
+    const uint32_t* code = lr.code;
 
     // steps 4-5, matrix part, built while the link loads are in flight: one
     // lane per entry of [M + zFU, zFW; zTU, I' + dI/dt + zTW], with
@@ -446,6 +476,9 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             acc[5] -= kuc * rc2;
         }
     };
+    double fbv[KREG];
+#pragma unroll
+    for (int k = 0; k < KREG; ++k) fbv[k] = S::cv64(lr.raw[k], inv);
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
         if (tid + k * PBLOCK < nl) accumulate(code[k], fbv[k]);
@@ -528,9 +561,11 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
     __syncthreads();
 
-    // step 7 and the hydrodynamic force/torque, one piece per lane of the last
-    // wave, while the other waves start the bounce-back (which uses x_c(t),
-    // q(t) from registers and U(t+1), Omega(t+1) from bc)
+    // step 7, the hydrodynamic force/torque and zeta at x(t+1), one piece per
+    // lane, spread over the upper four waves (one per SIMD), while all waves
+    // do the bounce-back (which uses x_c(t), q(t) from registers and U(t+1),
+    // Omega(t+1) from bc).  No lane reads an LDS field another lane writes here.
+    static_assert(PBLOCK >= 256, "the state update uses four waves");
     if (tid >= PBLOCK - 64) {
         const int k = tid - (PBLOCK - 64);
         if (k < 6) {  // F, T over the step (eqs. Fsplit, Tsplit)
@@ -538,7 +573,6 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             double z = 0;
             for (int j = 0; j < 6; ++j) z += P.zeta[6 * k + j] * bc[j];
             // each lane clears, after reading it, the pending impulse it used
-            // (another lane's LDS write would race with this read)
             if (k < 3) {
                 Pg->F[i] = acc[i] + P.Pp[i] - z;
                 Pg->Pp[i] = 0.0;
@@ -548,50 +582,51 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
                 Pg->Lp[i] = 0.0;
                 if (keep_lds) P.Lp[i] = 0.0;
             }
-        } else if (k < 9) {  // position (eq. posupdate), wrapped into the box
-            const int i = k - 6;
-            const int n3 = i == 0 ? nx : (i == 1 ? ny : nz);
-            const double dx = 0.5 * (bc[i] + U0[i]);
-            double xn = xc[i] + dx;
-            if (xn >= n3) xn -= n3;
-            if (xn < 0.0) xn += n3;
-            const double xu = P.xu[i] + dx;
-            Pg->xc[i] = xn;
-            Pg->xu[i] = xu;
-            Pg->U[i] = bc[i];
-            Pg->W[i] = bc[3 + i];
-            if (keep_lds) {
-                P.xc[i] = xn;
-                P.xu[i] = xu;
-                P.U[i] = bc[i];
-                P.W[i] = bc[3 + i];
-            }
-        } else if (k == 9) {  // orientation (eqs. qnplus0, qnplus1) with the mean angular velocity
-            const double Wm[3] = {0.5 * (W0[0] + bc[3]), 0.5 * (W0[1] + bc[4]), 0.5 * (W0[2] + bc[5])};
-            const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
-            double qn[4] = {q[0], q[1], q[2], q[3]};
-            if (nrm != 0.0) {
-                const double c = cos(0.5 * nrm), sn = sin(0.5 * nrm);
-                const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
-                qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
-                qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
-                qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
-                qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
-            }
-            for (int j = 0; j < 4; ++j) Pg->q[j] = qn[j];
-            if (keep_lds)
-                for (int j = 0; j < 4; ++j) P.q[j] = qn[j];
-        } else if (k == 10) {
+        } else if (k == 6) {
             Pg->dm = 0.0;
             if (keep_lds) P.dm = 0.0;
         }
     } else if (tid >= PBLOCK - 128 && tid < PBLOCK - 128 + 36) {
-        // zeta at x(t+1) for the current link set, from its moments; the
-        // remap replaces it only if some node changes side
+        // zeta of the current link set at x(t+1), from its moments; the remap
+        // replaces it only if some node changes side
         const int e = tid - (PBLOCK - 128);
         double xu[3];
-        for (int i = 0; i < 3; ++i) xu[i] = P.xu[i] + 0.5 * (bc[i] + U0[i]);
+        for (int i = 0; i < 3; ++i) xu[i] = xu0[i] + 0.5 * (bc[i] + U0[i]);
         Pg->zeta[e] = zeta_entry(P, xu, e / 6, e % 6, rho0);
+    } else if (tid >= PBLOCK - 192 && tid < PBLOCK - 192 + 3) {  // position (eq. posupdate), wrapped into the box
+        const int i = tid - (PBLOCK - 192);
+        const int n3 = i == 0 ? nx : (i == 1 ? ny : nz);
+        const double dx = 0.5 * (bc[i] + U0[i]);
+        double xn = xc[i] + dx;
+        if (xn >= n3) xn -= n3;
+        if (xn < 0.0) xn += n3;
+        const double xu = xu0[i] + dx;
+        Pg->xc[i] = xn;
+        Pg->xu[i] = xu;
+        Pg->U[i] = bc[i];
+        Pg->W[i] = bc[3 + i];
+        if (keep_lds) {
+            P.xc[i] = xn;
+            P.xu[i] = xu;
+            P.U[i] = bc[i];
+            P.W[i] = bc[3 + i];
+        }
+    } else if (tid == PBLOCK - 256) {  // orientation (eqs. qnplus0, qnplus1) with the mean angular velocity
+        const double Wm[3] = {0.5 * (W0[0] + bc[3]), 0.5 * (W0[1] + bc[4]), 0.5 * (W0[2] + bc[5])};
+        const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
+        double qn[4] = {q[0], q[1], q[2], q[3]};
+        if (nrm != 0.0) {
+            double sn, c;
+            sincos(0.5 * nrm, &sn, &c);
+            const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
+            qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
+            qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
+            qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
+            qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+        }
+        for (int j = 0; j < 4; ++j) Pg->q[j] = qn[j];
+        if (keep_lds)
+            for (int j = 0; j < 4; ++j) P.q[j] = qn[j];
     }
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step
@@ -631,8 +666,9 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
     __shared__ PartDev P;
     __shared__ SolveShm sh;
     const int p = a.first + (int)blockIdx.x;
-    stage_particle(a.parts + p, &P);
-    solve_phase<ST>(a, p, P, sh, false);
+    LinkRegs<typename Store<ST>::T> lr;
+    load_particle<ST>(a, p, &P, lr);
+    solve_phase<ST>(a, p, P, sh, lr, false);
 }
 
 struct RemapShm {
@@ -947,8 +983,9 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
         RemapShm r;
     } sh;
     const int p = a.first + (int)blockIdx.x;
-    stage_particle(a.parts + p, &P);
-    solve_phase<ST>(a, p, P, sh.s, true);
+    LinkRegs<typename Store<ST>::T> lr;
+    load_particle<ST>(a, p, &P, lr);
+    solve_phase<ST>(a, p, P, sh.s, lr, true);
     __syncthreads();  // bounce-back writes before the covered-node reads of the remap
     remap_phase<ST>(a, p, P, sh.r, smem);
 }

@@ -125,6 +125,7 @@ template <> struct Store<ST_F64> {
     static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
     static __device__ __forceinline__ void st_dither(T* p, R v, R, uint32_t) { *p = v; }
     static __device__ __forceinline__ double ld64(const T* p, double) { return *p; }
+    static __device__ __forceinline__ double cv64(T v, double) { return v; }
     static __device__ __forceinline__ void st64(T* p, double v, double) { *p = v; }
 };
 template <> struct Store<ST_F32> {
@@ -134,6 +135,7 @@ template <> struct Store<ST_F32> {
     static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
     static __device__ __forceinline__ void st_dither(T* p, R v, R, uint32_t) { *p = v; }
     static __device__ __forceinline__ double ld64(const T* p, double) { return (double)*p; }
+    static __device__ __forceinline__ double cv64(T v, double) { return (double)v; }
     static __device__ __forceinline__ void st64(T* p, double v, double) { *p = (float)v; }
 };
 template <> struct Store<ST_F16> {
@@ -156,6 +158,7 @@ template <> struct Store<ST_F16> {
         }
     }
     static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)(float)*p * inv; }
+    static __device__ __forceinline__ double cv64(T v, double inv) { return (double)(float)v * inv; }
     static __device__ __forceinline__ void st64(T* p, double v, double s) { *p = (_Float16)(float)(v * s); }
 };
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -175,6 +178,7 @@ template <> struct Store<ST_BF16> {
         *p = isfinite(x) ? (uint16_t)((__float_as_uint(x) + (r & 0xFFFFu)) >> 16) : f32_to_bf16(x);
     }
     static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)bf16_to_f32(*p) * inv; }
+    static __device__ __forceinline__ double cv64(T v, double inv) { return (double)bf16_to_f32(v) * inv; }
     static __device__ __forceinline__ void st64(T* p, double v, double s) { *p = f32_to_bf16((float)(v * s)); }
 };
 
