@@ -184,20 +184,30 @@ __device__ __forceinline__ void stage_particle(const PartDev* P, PartDev* S) {
 
 // Where node (x,y,z) keeps its pre-collision population i in the pull
 // layout, and what the collide kernel adds when it reads it (wall rows).
-__device__ __forceinline__ void pre_slot(const BoxDesc& B, double rho0, int i, int x, int y, int z, int& dir,
+__device__ __forceinline__ void pre_slot(int cv, const BoxDesc& B, double rho0, int i, int x, int y, int z, int& dir,
                                          int& slot, double& add) {
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int sy = wrap(y - rcy(i), ny);
     if (B.walls && rcy(i) != 0 && (sy == 0 || sy == ny - 1)) {
+        // off a wall: the node's own f*_opp(i) of the last step plus the wall term
         const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
-        dir = ropp(i);
-        slot = x + nx * (y + ny * z);
+        post_slot(cv, ropp(i), x, y, z, nx, ny, nz, dir, slot);
         add = (rw36(i) / 6.0) * rho0 * (rcx(i) * uw[0] + rcy(i) * uw[1] + rcz(i) * uw[2]);
     } else {
-        dir = i;
-        slot = wrap(x - rcx(i), nx) + nx * (sy + ny * wrap(z - rcz(i), nz));
+        pre_slot_open(cv, i, x, y, z, nx, ny, nz, dir, slot);
         add = 0.0;
     }
+}
+
+// Element offset (in the box's block) of f*_b at fluid site s: where the
+// population a link reads lives in convention cv.
+__device__ __forceinline__ long long link_post(int cv, const BoxDesc& B, int b, int s, double rnx, double rny) {
+    if (cv == CV_PULL) return (long long)b * B.stride + s;
+    if (cv == CV_EVEN) return (long long)ropp(b) * B.stride + s;
+    int x, y;
+    const int z = divmod(divmod(s, B.nx, rnx, x), B.ny, rny, y);
+    return (long long)b * B.stride +
+           (wrap(x + rcx(b), B.nx) + B.nx * (wrap(y + rcy(b), B.ny) + B.ny * wrap(z + rcz(b), B.nz)));
 }
 
 // Per-thread partial sums of eqs. drag1-drag4 (36 w_b as integers 2 / 1).
@@ -368,7 +378,8 @@ __device__ __forceinline__ void load_particle(const LaunchPart& a, int p, PartDe
     const BoxDesc& B = a.boxes[Pg->box];
     const uint32_t* L = a.links + Pg->lbase;
     const T* f = (const T*)a.f + B.foff;
-    const long long st = B.stride;
+    const int cv = a.kp.conv;
+    const double rnx = 1.0 / B.nx, rny = 1.0 / B.ny;
 #pragma unroll
     for (int k = 0; k < KREG; ++k) {
         const int l = tid + k * PBLOCK;
@@ -376,7 +387,7 @@ __device__ __forceinline__ void load_particle(const LaunchPart& a, int p, PartDe
     }
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
-        lr.raw[k] = f[(long long)(lr.code[k] >> SITE_BITS) * st + (int)(lr.code[k] & SITE_MASK)];
+        lr.raw[k] = f[link_post(cv, B, (int)(lr.code[k] >> SITE_BITS), (int)(lr.code[k] & SITE_MASK), rnx, rny)];
     if (tid < NW) reinterpret_cast<unsigned long long*>(Pl)[tid] = sv;
     __syncthreads();
 }
@@ -484,7 +495,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         if (tid + k * PBLOCK < nl) accumulate(code[k], fbv[k]);
     for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
         const uint32_t cd = L[l];
-        accumulate(cd, S::ld64(f + (long long)(cd >> SITE_BITS) * st + (int)(cd & SITE_MASK), inv));
+        accumulate(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv));
     }
     block_reduce<6>(acc, red);
 
@@ -649,15 +660,18 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         }
         const int w36 = rw36(b);
         const double val = fb - (w36 / 6.0) * rho0 * (ub[0] * c0 + ub[1] * c1 + ub[2] * c2) + dmw * w36;
-        const int dst = wrap(x + c0, nx) + nx * (wrap(y + c1, ny) + ny * wrap(z + c2, nz));
-        S::st64(f + (long long)ropp(b) * st + dst, val, scl);
+        // the slot of f_opp(b)(x) the fluid node reads next (it comes from the
+        // solid node, never off a wall)
+        int pd, ps;
+        pre_slot_open(a.kp.conv, ropp(b), x, y, z, nx, ny, nz, pd, ps);
+        S::st64(f + (long long)pd * st + ps, val, scl);
     };
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
         if (tid + k * PBLOCK < nl) bounce(code[k], fbv[k]);
     for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
         const uint32_t cd = L[l];
-        bounce(cd, S::ld64(f + (long long)(cd >> SITE_BITS) * st + (int)(cd & SITE_MASK), inv));
+        bounce(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv));
     }
 }
 
@@ -761,7 +775,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                 for (int j = 0; j < NQ; ++j) {
                                     int dir, slot;
                                     double add;
-                                    pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
+                                    pre_slot(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
                                     const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
                                     m += v;
                                     pm[0] += rcx(j) * v;
@@ -783,7 +797,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                 for (int j = 0; j < NQ; ++j) {
                                     int dir, slot;
                                     double add;
-                                    pre_slot(B, rho0, j, gx, gy, gz, dir, slot, add);
+                                    pre_slot(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
                                     const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
                                     const double dev = (rw36(j) / 36.0) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
                                     S::st64(f + (long long)dir * st + slot, dev - add, scl);

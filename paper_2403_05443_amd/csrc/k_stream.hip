@@ -1,16 +1,19 @@
-// k_stream.hip - fused collide + stream (pull) over all boxes, plus the
-// per-site initialisation and read-out kernels that see the lattice exactly
-// as the collide kernel does.
+// k_stream.hip - fused collide + stream over all boxes, plus the per-site
+// initialisation and read-out kernels that see the lattice exactly as the
+// collide kernel does.
 //
-// Storage: structure of arrays per box, f[dir * stride + site], ping-pong
-// buffers.  The value stored at (site, i) after a step is the post-collision
-// population f*_i(site), i.e. the pre-collision population that site + c_i
-// pulls at the next step (Sec. II.A: f_i(x + c_i, t + 1) = f*_i(x, t)).
-// Link bounce-back on particles (Sec. II.B) writes the reflected value into
-// the slot of the solid node that the fluid node pulls from, so this kernel
-// needs no node map.  Moving walls (Sec. III.C set-up) are handled here: a
-// pull from a wall row is replaced by the reflected own population plus the
-// moving-boundary term of eq. fb.
+// Storage: structure of arrays per box, f[dir * stride + site], in one of
+// the conventions CV_PULL (ping-pong buffers: the value at (site, i) after a
+// step is the post-collision population f*_i(site), the pre-collision
+// population that site + c_i pulls at the next step, Sec. II.A:
+// f_i(x + c_i, t + 1) = f*_i(x, t)) or CV_EVEN / CV_ODD (one buffer updated in
+// place, alternating an even step that works on each node's own slots and an
+// odd step that gathers from and scatters to the neighbours).  Link
+// bounce-back on particles (Sec. II.B) writes the reflected value into the
+// slot the fluid node reads next, so these kernels need no node map.  Moving
+// walls (Sec. III.C set-up) are handled here: a population that would come
+// out of a wall row is replaced by the node's own reflected population plus
+// the moving-boundary term of eq. fb.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -26,8 +29,10 @@ struct Pull {
     using T = typename S::T;
     using R = typename S::R;
 
-    // Pre-collision populations of fluid site (x,y,z) as deviations.
-    static __device__ __forceinline__ void pull(const BoxDesc& B, const T* __restrict__ fi, int s,
+    // Pre-collision populations of fluid site (x,y,z) as deviations, from
+    // storage in convention CIN.
+    template <int CIN>
+    static __device__ __forceinline__ void pull(const BoxDesc& B, const T* fi, int s,
                                                 int x, int y, int z, R inv_scale, R rho0,
                                                 bool walls, R (&f)[NQ]) {
 #pragma clang fp contract(off)
@@ -42,16 +47,29 @@ struct Pull {
             const int sx = cx(i) == 1 ? xs2 : (cx(i) == -1 ? xs0 : x);
             const int sy = cy(i) == 1 ? ys2 : (cy(i) == -1 ? ys0 : y);
             const int sz = cz(i) == 1 ? zs2 : (cz(i) == -1 ? zs0 : z);
+            const int src = sx + nx * (sy + ny * sz);
             if (walls && cy(i) != 0 && (sy == 0 || sy == ny - 1)) {
+                // f*_opp(i)(x) of the last step: its own opposite slot (pull),
+                // its own slot i (even), the wall-row slot it was scattered to (odd)
                 const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
                 const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
-                f[i] = S::ld(fi + (long long)opp(i) * st + s, inv_scale) +
-                       (R)(6.0 * wgt(i)) * rho0 * cu;
+                const long long off = CIN == CV_PULL ? (long long)opp(i) * st + s
+                                    : (CIN == CV_EVEN ? (long long)i * st + s : (long long)opp(i) * st + src);
+                f[i] = S::ld(fi + off, inv_scale) + (R)(6.0 * wgt(i)) * rho0 * cu;
             } else {
-                const int src = sx + nx * (sy + ny * sz);
-                f[i] = S::ld(fi + (long long)i * st + src, inv_scale);
+                const long long off = CIN == CV_PULL ? (long long)i * st + src
+                                    : (CIN == CV_EVEN ? (long long)opp(i) * st + src : (long long)i * st + s);
+                f[i] = S::ld(fi + off, inv_scale);
             }
         }
+    }
+
+    // The same in the convention held in a run-time value (read-out kernels).
+    static __device__ __forceinline__ void pull_cv(int cv, const BoxDesc& B, const T* fi, int s, int x, int y,
+                                                   int z, R inv_scale, R rho0, bool walls, R (&f)[NQ]) {
+        if (cv == CV_ODD) pull<CV_ODD>(B, fi, s, x, y, z, inv_scale, rho0, walls, f);
+        else if (cv == CV_EVEN) pull<CV_EVEN>(B, fi, s, x, y, z, inv_scale, rho0, walls, f);
+        else pull<CV_PULL>(B, fi, s, x, y, z, inv_scale, rho0, walls, f);
     }
 };
 
@@ -138,12 +156,12 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
     }
 }
 
-// One site of the generic tile kernel: pull, collide, store.
-template <int ST, int COLL, bool WALLS, bool NT>
+// One site of the generic tile kernel: read the pre-collision populations
+// (convention CIN), collide, store the post-collision ones (convention COUT).
+template <int ST, int COLL, bool WALLS, bool NT, int CIN, int COUT>
 __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
-                                            const typename Store<ST>::T* __restrict__ fin,
-                                            typename Store<ST>::T* __restrict__ fout, const KParams& kp, int tile,
-                                            uint32_t step) {
+                                            const typename Store<ST>::T* fin, typename Store<ST>::T* fout,
+                                            const KParams& kp, int tile, uint32_t step) {
     using S = Store<ST>;
     using R = typename S::R;
     const int bi = tile_box[tile];
@@ -156,7 +174,7 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     if (walls && (y == 0 || y == ny - 1)) return;
     const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
     R f[NQ];
-    Pull<ST>::pull(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
+    Pull<ST>::template pull<CIN>(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
     R g0 = 0, g1 = 0, g2 = 0;
     const bool cf = B.counterforce != 0;
     if (cf) {  // uniform force density on all matter of the box (fluid and particles)
@@ -167,16 +185,30 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     }
     collide<R, COLL>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
     typename S::T* fo = fout + B.foff;
+    // the dither is a function of (node, direction, step) in every convention
     const uint32_t seed = ST >= ST_F16 ? dither_seed((uint32_t)s, step) : 0u;
+    const int nz = B.nz;
+    const int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    const int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+    const int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const uint32_t r = ST >= ST_F16 ? dither_bits(seed, i) : 0u;
+        long long off;
+        if (COUT == CV_ODD) {  // scattered to the node it streams to
+            const int dx = cx(i) == 1 ? xp : (cx(i) == -1 ? xm : x);
+            const int dy = cy(i) == 1 ? yp : (cy(i) == -1 ? ym : y);
+            const int dz = cz(i) == 1 ? zp : (cz(i) == -1 ? zm : z);
+            off = (long long)i * B.stride + (dx + nx * (dy + ny * dz));
+        } else {
+            off = (long long)(COUT == CV_EVEN ? opp(i) : i) * B.stride + s;
+        }
         if constexpr (NT) {
             typename S::T v;
             S::st_dither(&v, f[i], scl, r);
-            __builtin_nontemporal_store(v, fo + (long long)i * B.stride + s);
+            __builtin_nontemporal_store(v, fo + off);
         } else {
-            S::st_dither(fo + (long long)i * B.stride + s, f[i], scl, r);
+            S::st_dither(fo + off, f[i], scl, r);
         }
     }
 }
@@ -216,7 +248,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
         } else if (nflags[tile] == epoch) {
             return;
         }
-        site_update<ST, COLL, WALLS, NT>(boxes, tile_box, fin, fout, kp, tile, step);
+        site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL>(boxes, tile_box, fin, fout, kp, tile, step);
         return;
     }
     const int nvb = (ntiles + SPT - 1) / SPT;
@@ -235,8 +267,64 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             const int tile = v * SPT + k;
-            if (tile < ntiles) site_update<ST, COLL, WALLS, NT>(boxes, tile_box, fin, fout, kp, tile, step);
+            if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL>(boxes, tile_box, fin, fout, kp, tile, step);
         }
+    }
+}
+
+// In-place step over one buffer: CIN = CV_ODD runs the even step (each node
+// reads and rewrites its own slots), CIN = CV_EVEN the odd step (gather from
+// and scatter to the neighbours).  Every slot is read and written by one
+// thread only, so no block depends on another.  Block order as the generic
+// kernel's; wall rows are not updated.
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int CIN>
+__global__ __launch_bounds__(TILE) void k_collide_stream_aa(const BoxDesc* __restrict__ boxes,
+                                                            const int* __restrict__ tile_box,
+                                                            typename Store<ST>::T* __restrict__ f, KParams kp,
+                                                            int ntiles, const uint32_t* __restrict__ step_in,
+                                                            uint32_t* __restrict__ step_out) {
+    constexpr int COUT = CIN == CV_ODD ? CV_EVEN : CV_ODD;
+    const uint32_t step = *step_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *step_out = step + 1;
+    const int nvb = (ntiles + SPT - 1) / SPT;
+    int v, vend, vstep;
+    if (XCD) {
+        const int m = (int)gridDim.x >> 3, chunk = (nvb + 7) >> 3, k = (int)(blockIdx.x & 7);
+        v = k * chunk + (int)(blockIdx.x >> 3);
+        vend = min(nvb, (k + 1) * chunk);
+        vstep = m;
+    } else {
+        v = blockIdx.x;
+        vend = nvb;
+        vstep = gridDim.x;
+    }
+    for (; v < vend; v += vstep) {
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int tile = v * SPT + k;
+            if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CIN, COUT>(boxes, tile_box, f, f, kp, tile, step);
+        }
+    }
+}
+
+// Moves every population from its slot in convention cs (buffer src) to its
+// slot in convention cd (buffer dst), wall and particle nodes included: a
+// permutation of the slots (post_slot is one-to-one per direction), exact.
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_relayout(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
+                                                   const T* __restrict__ src, T* __restrict__ dst, int cs, int cd) {
+    const int tile = blockIdx.x;
+    const BoxDesc& B = boxes[tile_box[tile]];
+    const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
+    if (s >= B.n) return;
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        int ds, ss, dd, sd;
+        post_slot(cs, i, x, y, z, nx, ny, nz, ds, ss);
+        post_slot(cd, i, x, y, z, nx, ny, nz, dd, sd);
+        dst[B.foff + (long long)dd * B.stride + sd] = src[B.foff + (long long)ds * B.stride + ss];
     }
 }
 
@@ -461,7 +549,7 @@ __global__ __launch_bounds__(TILE) void k_fields(const BoxDesc* __restrict__ box
         const int nx = B.nx, ny = B.ny;
         const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
         R f[NQ];
-        Pull<ST>::pull(B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        Pull<ST>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
         double d = 0, j[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
@@ -498,7 +586,7 @@ __global__ __launch_bounds__(TILE) void k_moments(const BoxDesc* __restrict__ bo
         const int nx = B.nx, ny = B.ny;
         const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
         R f[NQ];
-        Pull<ST>::pull(B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        Pull<ST>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
         v[0] = 1.0;
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
@@ -530,8 +618,9 @@ __global__ void k_poke(const BoxDesc* __restrict__ boxes, int bi, typename Store
     const BoxDesc& B = boxes[bi];
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
-    int slot = wrap(x - cx(dir), nx) + nx * (wrap(y - cy(dir), ny) + ny * wrap(z - cz(dir), nz));
-    Store<ST>::st64(f + B.foff + (long long)dir * B.stride + slot, val, kp.scale);
+    int d, slot;
+    pre_slot_open(kp.conv, dir, x, y, z, nx, ny, nz, d, slot);
+    Store<ST>::st64(f + B.foff + (long long)d * B.stride + slot, val, kp.scale);
 }
 
 // Plain device copy with 16-byte accesses, four per thread per iteration:
@@ -578,8 +667,34 @@ static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT>
+static hipError_t aa_one(const LaunchCS& a, hipStream_t st) {
+    using T = typename Store<ST>::T;
+    const int nvb = (a.ntiles + SPT - 1) / SPT;
+    const int g = XCD ? 8 * ((nvb + 7) / 8) : nvb;
+    if (a.ntiles == 0) return hipSuccess;
+    if (a.kp.conv == CV_ODD)
+        K1_LAUNCH((k_collide_stream_aa<ST, COLL, WALLS, SPT, XCD, NT, CV_ODD>), dim3(g), dim3(TILE), st, a.boxes,
+                  a.tile_box, (T*)a.fout, a.kp, a.ntiles, a.step_in, a.step_out);
+    else if (a.kp.conv == CV_EVEN)
+        K1_LAUNCH((k_collide_stream_aa<ST, COLL, WALLS, SPT, XCD, NT, CV_EVEN>), dim3(g), dim3(TILE), st, a.boxes,
+                  a.tile_box, (T*)a.fout, a.kp, a.ntiles, a.step_in, a.step_out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int ST, int COLL, bool WALLS>
 static hipError_t cs_shape(const LaunchCS& a, hipStream_t st) {
+    if (a.aa) {
+        switch (a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0)) {
+            case 4: return aa_one<ST, COLL, WALLS, 1, false, false>(a, st);
+            case 6: return aa_one<ST, COLL, WALLS, 1, true, false>(a, st);
+            case 7: return aa_one<ST, COLL, WALLS, 1, true, true>(a, st);
+            case 10: return aa_one<ST, COLL, WALLS, 2, true, false>(a, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false, false>(a, st);
     switch (a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0)) {
         case 4: return cs_one<ST, COLL, WALLS, 1, false, false>(a, st);
@@ -644,6 +759,7 @@ static hipError_t rows_coll(const LaunchCS& a, hipStream_t st) {
 }
 
 hipError_t launch_collide_stream(const LaunchCS& a, hipStream_t st) {
+    if (a.aa && (a.fin != a.fout || a.part != 0 || a.variant != 0)) return hipErrorInvalidValue;
     if (a.variant != 0 && a.rows_k > 0) {
         switch (a.kp.storage) {
             case ST_F64: return rows_coll<ST_F64>(a, st);
@@ -697,6 +813,22 @@ hipError_t launch_moments(const BoxDesc* boxes, int bi, int n, const uint16_t* o
         hipLaunchKernelGGL((k_moments<SS>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin,
                            partial, kp);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(const BoxDesc* boxes, const int* tile_box, int ntiles, const void* src, void* dst, int cs,
+                           int cd, int storage, hipStream_t st) {
+    if (src == dst) return hipErrorInvalidValue;
+    const int es = storage_bytes(storage);
+    if (es == 8)
+        hipLaunchKernelGGL((k_relayout<unsigned long long>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                           (const unsigned long long*)src, (unsigned long long*)dst, cs, cd);
+    else if (es == 4)
+        hipLaunchKernelGGL((k_relayout<uint32_t>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                           (const uint32_t*)src, (uint32_t*)dst, cs, cd);
+    else
+        hipLaunchKernelGGL((k_relayout<uint16_t>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                           (const uint16_t*)src, (uint16_t*)dst, cs, cd);
     return hipGetLastError();
 }
 

@@ -375,10 +375,10 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     for (int i = 0; i < NQ; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
         const double dev = wgt(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        // node (x, y, z) pulls f_i from slot (x - c_i, i)
-        const int xs = wrap(x - cx(i), nx), ys = wrap(y - cy(i), ny), zs = wrap(z - cz(i), nz);
-        const long long slot = xs + (long long)nx * (ys + (long long)ny * zs);
-        S::st64(fb + (long long)i * B.stride + slot, dev, kp.scale);
+        // the slot node (x, y, z) reads f_i from at the next step (no walls here)
+        int d, slot;
+        pre_slot_open(kp.conv, i, x, y, z, nx, ny, nz, d, slot);
+        S::st64(fb + (long long)d * B.stride + slot, dev, kp.scale);
     }
 }
 

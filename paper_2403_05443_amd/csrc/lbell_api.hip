@@ -155,7 +155,14 @@ struct lb_ctx {
     std::vector<PartHost> hpart;
     int np = 0;
     long long link_used = 0;
-    int cur = 0;  // buffer holding the current state: 0 -> f0, 1 -> f1
+    // Population storage.  Pull variants: ping-pong buffers, cur = buffer
+    // holding the current state (0 -> f0, 1 -> f1).  In-place variants (aa):
+    // buffer aa_buf only, cur = parity of the state (0: after an odd step,
+    // convention CV_ODD; 1: after an even step, CV_EVEN).  cur also selects
+    // the device step counter slot and the cached graph.
+    int cur = 0;
+    bool aa = false;
+    int aa_buf = 0;
     long long step = 0;
     KParams kp{};
     bool any_walls = false;
@@ -182,26 +189,36 @@ struct lb_ctx {
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
-    void* fbuf(int which) { return arena + (which ? L.f1 : L.f0); }
+    void* fbuf(int which) { return arena + ((aa ? aa_buf : which) ? L.f1 : L.f0); }
+    // every change of cur goes through here so the convention in kp follows
+    void set_cur(int c) {
+        cur = c;
+        kp.conv = aa ? (c ? CV_EVEN : CV_ODD) : CV_PULL;
+    }
 };
 
 namespace {
 
 // Collide-stream variants the tuner chooses from (the index is the variant
 // number of the ABI).  Row-wave kinds need a single box with nx = 64, 128 or
-// 256; the near-set schedule needs kinds 0-2.
+// 256; the near-set schedule needs kinds 0-2.  Variants 11-14 update one
+// buffer in place (even / odd steps): half the population memory, so a
+// lattice whose two buffers overflow the last-level cache may fit with one.
 struct K1Shape {
     int kind;      // 0 generic tiles, 1 row-wave, 2 row-wave with non-temporal stores
     int spt;       // tiles per block (generic)
     bool xcd;      // XCD-chunked block order (generic)
     bool persist;  // grid of a few blocks per CU walking the tiles (generic)
     bool nt;       // non-temporal stores (generic)
+    bool aa;       // in place (generic)
 };
 constexpr K1Shape K1_SHAPES[] = {
-    {0, 1, false, false, false}, {1, 1, false, false, false}, {2, 1, false, false, false},
-    {0, 1, true, false, false},  {0, 2, false, false, false}, {0, 2, true, false, false},
-    {0, 1, true, true, false},   {0, 2, true, true, false},   {0, 4, true, false, false},
-    {0, 1, true, false, true},   {0, 2, true, false, true},
+    {0, 1, false, false, false, false}, {1, 1, false, false, false, false}, {2, 1, false, false, false, false},
+    {0, 1, true, false, false, false},  {0, 2, false, false, false, false}, {0, 2, true, false, false, false},
+    {0, 1, true, true, false, false},   {0, 2, true, true, false, false},   {0, 4, true, false, false, false},
+    {0, 1, true, false, true, false},   {0, 2, true, false, true, false},
+    {0, 1, false, false, false, true},  {0, 1, true, false, false, true},   {0, 2, true, false, false, true},
+    {0, 1, true, false, true, true},
 };
 constexpr int K1_NSHAPES = (int)(sizeof(K1_SHAPES) / sizeof(K1_SHAPES[0]));
 
@@ -354,6 +371,10 @@ size_t lb_arena_bytes(const lb_config* cfg, int nboxes, const lb_box* boxes) {
     return make_layout(cfg, nboxes, boxes).total;
 }
 
+namespace {
+lb_status switch_layout(lb_ctx* ctx, bool to_aa);
+}  // namespace
+
 lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* dev_arena, size_t arena_bytes,
                   void* hip_stream, lb_ctx** out) {
     if (!out) return LB_EINVAL;
@@ -493,6 +514,11 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
             return LB_EDEVICE;
         }
     }
+    if (K1_SHAPES[ctx->k1_variant].aa && switch_layout(ctx, true) != LB_OK) {
+        std::fprintf(stderr, "lb_init: %s\n", ctx->err.c_str());
+        lb_destroy(ctx);
+        return LB_EDEVICE;
+    }
     *out = ctx;
     return LB_OK;
 }
@@ -611,13 +637,14 @@ LaunchCS collide_args(lb_ctx* ctx, int variant) {
     cs.tile_box = ctx->at<int>(ctx->L.tile_box);
     cs.ntiles = ctx->L.total_tiles;
     cs.fin = ctx->fbuf(ctx->cur);
-    cs.fout = ctx->fbuf(ctx->cur ^ 1);
+    cs.fout = ctx->fbuf(ctx->cur ^ 1);  // the same buffer in place
     cs.kp = ctx->kp;
     cs.step_in = ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur;
     cs.step_out = ctx->at<uint32_t>(ctx->L.step_ctr) + (ctx->cur ^ 1);
     cs.walls = ctx->any_walls;
     const K1Shape& sh = K1_SHAPES[k1_applicable(ctx, variant) ? variant : 0];
     cs.variant = sh.kind;
+    cs.aa = sh.aa;
     cs.spt = sh.spt;
     cs.xcd = sh.xcd;
     cs.nt = sh.nt;
@@ -656,7 +683,7 @@ lb_status launch_collide(lb_ctx* ctx, hipStream_t st, hipEvent_t t0 = nullptr, h
     cs.ev_stop = t1;
     cs.next_count = ctx->overlap && ctx->np > 0 ? near_set(ctx, ctx->step + 1).count : nullptr;
     HIPC(launch_collide_stream(cs, st));
-    ctx->cur ^= 1;
+    ctx->set_cur(ctx->cur ^ 1);
     return LB_OK;
 }
 
@@ -726,7 +753,7 @@ lb_status step_overlapped(lb_ctx* ctx) {
     HIPC(hipEventRecord(ctx->evK, ctx->stream));
     HIPC(launch_collide_stream(far, ctx->stream));
     HIPC(hipStreamWaitEvent(ctx->nstream, ctx->evK, 0));
-    ctx->cur ^= 1;
+    ctx->set_cur(ctx->cur ^ 1);
     lb_status s = launch_particles(ctx, ctx->nstream);
     if (s != LB_OK) return s;
     HIPC(hipEventRecord(ctx->evP, ctx->nstream));
@@ -738,6 +765,38 @@ void graph_drop(lb_ctx* ctx) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         g = lb_ctx::GraphSlot{};
     }
+}
+
+// Moves the populations between the two-buffer pull layout and the in-place
+// layout (to_aa).  Every slot is permuted exactly, nothing is recomputed, so
+// the run continues bit for bit.  The state lands in the other buffer; the
+// device step counter moves to the slot of the new cur.
+lb_status switch_layout(lb_ctx* ctx, bool to_aa) {
+    if (ctx->aa == to_aa) return LB_OK;
+    graph_drop(ctx);
+    const int src_buf = ctx->aa ? ctx->aa_buf : ctx->cur, dst_buf = src_buf ^ 1;
+    HIPC(launch_relayout(ctx->at<BoxDesc>(ctx->L.boxes), ctx->at<int>(ctx->L.tile_box), ctx->L.total_tiles,
+                         ctx->arena + (src_buf ? ctx->L.f1 : ctx->L.f0), ctx->arena + (dst_buf ? ctx->L.f1 : ctx->L.f0),
+                         ctx->kp.conv, to_aa ? CV_EVEN : CV_PULL, ctx->cfg.storage, ctx->stream));
+    ctx->aa = to_aa;
+    ctx->aa_buf = dst_buf;
+    const int c = to_aa ? 1 : dst_buf;
+    const uint32_t st32 = (uint32_t)ctx->step;
+    HIPC(hipMemcpyAsync(ctx->at<uint32_t>(ctx->L.step_ctr) + c, &st32, sizeof st32, hipMemcpyHostToDevice,
+                        ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->set_cur(c);
+    return LB_OK;
+}
+
+// Makes v the collide-stream variant: the population layout follows it, and
+// the near set is rebuilt when the block geometry changes.
+lb_status use_variant(lb_ctx* ctx, int v) {
+    const bool kind_changed = K1_SHAPES[v].kind != K1_SHAPES[ctx->k1_variant].kind;
+    lb_status s = switch_layout(ctx, K1_SHAPES[v].aa);
+    if (s != LB_OK) return s;
+    ctx->k1_variant = v;
+    return kind_changed ? near_rebuild(ctx) : LB_OK;
 }
 
 // One replay of a group of graph_steps steps; captures the group first if
@@ -758,7 +817,7 @@ lb_status step_graph(lb_ctx* ctx) {
         }
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(ctx->nstream, &graph);
-        ctx->cur = cur0;
+        ctx->set_cur(cur0);
         ctx->step = step0;
         if (s != LB_OK) {
             if (graph) hipGraphDestroy(graph);
@@ -773,7 +832,7 @@ lb_status step_graph(lb_ctx* ctx) {
         g.steps = ctx->graph_steps;
     }
     HIPC(hipGraphLaunch(g.exec, ctx->stream));
-    ctx->cur ^= (ctx->graph_steps & 1);
+    ctx->set_cur(ctx->cur ^ (ctx->graph_steps & 1));
     ctx->step += ctx->graph_steps;
     return LB_OK;
 }
@@ -860,9 +919,7 @@ lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best) {
     lb_status s = LB_OK;
     for (int v = 0; v < K1_NSHAPES && s == LB_OK; ++v) {
         if (!k1_applicable(ctx, v)) continue;
-        const bool kind_changed = K1_SHAPES[v].kind != K1_SHAPES[ctx->k1_variant].kind;
-        ctx->k1_variant = v;
-        if (kind_changed && (s = near_rebuild(ctx)) != LB_OK) break;
+        if ((s = use_variant(ctx, v)) != LB_OK) break;
         for (int r = -1; r < reps && s == LB_OK; ++r) {  // r = -1: warm-up step
             s = r >= 0 ? launch_collide(ctx, ctx->stream, ev[2 * r], ev[2 * r + 1]) : launch_collide(ctx, ctx->stream);
             if (s == LB_OK) s = launch_particles(ctx, ctx->stream);
@@ -884,11 +941,9 @@ lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best) {
     }
     for (auto& e : ev) hipEventDestroy(e);
     if (s != LB_OK) return s;
-    const bool kind_changed = K1_SHAPES[best].kind != K1_SHAPES[ctx->k1_variant].kind;
-    ctx->k1_variant = best;
+    if ((s = use_variant(ctx, best)) != LB_OK) return s;
     if (variant) *variant = best;
     if (ms_best) *ms_best = tbest;
-    if (kind_changed) return near_rebuild(ctx);
     return flags_status(ctx);
 }
 
@@ -1079,7 +1134,8 @@ lb_status lb_save(lb_ctx* ctx, const char* path) {
     if (!fp) return fail(ctx, LB_EIO, "cannot open checkpoint for writing");
     CkptHeader h{};
     std::memcpy(h.magic, "LBELLCK1", 8);
-    h.version = 1;
+    h.version = 2;
+    h.pad = ctx->aa ? 1 : 0;  // populations in the in-place layout (cur = parity)
     h.nboxes = (int)ctx->boxes.size();
     h.storage = ctx->cfg.storage;
     h.np = ctx->np;
@@ -1133,7 +1189,10 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
         if (bytes && std::fread(buf.data(), 1, bytes, fp) != bytes) ok = false;
         if (ok && hipMemcpy(dptr, buf.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
     };
-    ctx->cur = h.cur;
+    graph_drop(ctx);
+    ctx->aa = h.pad != 0;
+    ctx->aa_buf = 0;
+    ctx->set_cur(h.cur);
     load(ctx->fbuf(ctx->cur), (size_t)h.pop_elems * es);
     load(ctx->at<char>(ctx->L.omap), (size_t)h.omap_elems * sizeof(uint16_t));
     load(ctx->at<char>(ctx->L.rt), sizeof(BoxRT) * ctx->boxes.size());
@@ -1155,6 +1214,9 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
         lb_status s = box_fext_update(ctx, b);
         if (s != LB_OK) return s;
     }
+    // the checkpoint's layout, converted to the one this context's variant uses
+    lb_status s = switch_layout(ctx, K1_SHAPES[ctx->k1_variant].aa);
+    if (s != LB_OK) return s;
     return near_rebuild(ctx);
 }
 

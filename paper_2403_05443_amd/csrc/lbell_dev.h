@@ -87,7 +87,47 @@ struct KParams {
     double scale, inv_scale;  // half formats: stored = scale * deviation
     double rho0;
     int collision, storage;
+    int conv, pad;            // storage convention of the current populations (CV_*)
 };
+
+// Storage conventions of the population array.  The post-collision
+// population f*_i(x) of node x is held in slot (direction plane, site)
+//   CV_PULL  (i, x)          two buffers; a step pulls from x - c_i of one and
+//                            writes the other
+//   CV_EVEN  (opp(i), x)     one buffer, after an in-place even step
+//   CV_ODD   (i, x + c_i)    one buffer, after an in-place odd step
+// An in-place even step reads each node's own slots and writes them back
+// (CV_ODD -> CV_EVEN); an odd step gathers from and scatters to the
+// neighbours (CV_EVEN -> CV_ODD).  Either way every slot is read and written
+// by one node only.  The pre-collision f_i(x) a node reads at the next step
+// is f*_i(x - c_i): slot (i, x - c_i), (opp(i), x - c_i) or (i, x).
+constexpr int CV_PULL = 0, CV_EVEN = 1, CV_ODD = 2;
+
+__host__ __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Slot of f*_i at node (x, y, z) of an nx x ny x nz box.
+__host__ __device__ inline void post_slot(int cv, int i, int x, int y, int z, int nx, int ny, int nz, int& dir,
+                                          int& site) {
+    if (cv == CV_ODD) {
+        dir = i;
+        site = wrap(x + cx(i), nx) + nx * (wrap(y + cy(i), ny) + ny * wrap(z + cz(i), nz));
+    } else {
+        dir = cv == CV_EVEN ? opp(i) : i;
+        site = x + nx * (y + ny * z);
+    }
+}
+
+// Slot of the pre-collision f_i of node (x, y, z) (no wall in between).
+__host__ __device__ inline void pre_slot_open(int cv, int i, int x, int y, int z, int nx, int ny, int nz, int& dir,
+                                              int& site) {
+    if (cv == CV_ODD) {
+        dir = i;
+        site = x + nx * (y + ny * z);
+    } else {
+        dir = cv == CV_EVEN ? opp(i) : i;
+        site = wrap(x - cx(i), nx) + nx * (wrap(y - cy(i), ny) + ny * wrap(z - cz(i), nz));
+    }
+}
 
 // Rounding dither of the half formats: one murmur3 32-bit finalisation per
 // (site of its box, step) seeds the site; direction i takes the high bits of
@@ -106,8 +146,6 @@ __device__ __forceinline__ uint32_t dither_seed(uint32_t site, uint32_t step) {
 __device__ __forceinline__ uint32_t dither_bits(uint32_t seed, int dir) {
     return ((seed + (uint32_t)dir * 0x9E3779B9u) * 0x2C1B3C6Du) >> 16;
 }
-
-__host__ __device__ inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 }  // namespace lbd
 

@@ -14,6 +14,7 @@ struct LaunchCS {
     KParams kp;
     bool walls;
     int variant;            // 0 generic tiles, 1 row-wave, 2 row-wave with non-temporal stores
+    bool aa;                // generic tiles in place on fin (== fout); kp.conv says even or odd step
     int spt;                // generic tiles: 256-site tiles per block (1 or 2)
     bool xcd;               // generic tiles: XCD-chunked block order
     bool nt;                // generic tiles: non-temporal stores
@@ -52,6 +53,10 @@ hipError_t launch_fields(const BoxDesc* boxes, int bi, const uint16_t* omap, con
 hipError_t launch_moments(const BoxDesc* boxes, int bi, int n, const uint16_t* omap, const void* fin,
                           double* partial, const KParams& kp, hipStream_t st);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
+// Copies every population from its slot in convention cs (src) to its slot in
+// convention cd (dst); src and dst are distinct buffers of the same layout.
+hipError_t launch_relayout(const BoxDesc* boxes, const int* tile_box, int ntiles, const void* src, void* dst, int cs,
+                           int cd, int storage, hipStream_t st);
 hipError_t launch_poke(const BoxDesc* boxes, int bi, void* f, int s, int dir, double val, const KParams& kp,
                        hipStream_t st);
 
