@@ -96,9 +96,10 @@ def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes, variant):
         names = [k for k, _ in rows if "collide_stream" in k]
         if not probe or not names:
             raise SystemExit(f"no copy-probe / collide-stream dispatches under {d}")
-        # the variant the tuner kept is the one launched in the timed steps: the most frequent
-        kname = max(set(names), key=names.count)
-        k1 = [v for k, v in rows if k == kname]
+        # the counter runs force one variant, so every collide-stream dispatch
+        # is of it (an in-place variant alternates its even and odd kernel)
+        kname = " + ".join(sorted(set(names)))
+        k1 = [v for k, v in rows if "collide_stream" in k]
         probe_kib = sorted(probe)[len(probe) // 2]
         scale = probe_bytes / (probe_kib * 1024.0)
         res[name] = {"kernel": kname, "launches": len(k1),

@@ -114,7 +114,9 @@ size_t lb_arena_bytes(const lb_config* cfg, int nboxes, const lb_box* boxes);
  * and kept alive until lb_destroy.  hip_stream: the hipStream_t all work is
  * enqueued on (NULL = the default stream).  Populations are initialised to
  * f_eq(rho0, u0) with u0 = 0, or the wall-driven Couette profile (init = 1),
- * including its first-order non-equilibrium part.  Synchronises the stream. */
+ * including its first-order non-equilibrium part.  The environment variable
+ * LBELL_K1_VARIANT picks the initial collide-stream variant (see
+ * lb_autotune).  Synchronises the stream. */
 lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes,
                   void* dev_arena, size_t arena_bytes, void* hip_stream,
                   lb_ctx** out);
@@ -178,6 +180,13 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
  *   8  generic, four tiles per block, XCD-chunked
  *   9  generic, XCD-chunked, non-temporal stores
  *  10  generic, two tiles per block, XCD-chunked, non-temporal stores
+ *  11  in place: one population buffer, alternating an even step (each
+ *      node reads and rewrites its own slots) and an odd step (gather from
+ *      and scatter to the neighbours); half the population memory
+ *  12  in place, XCD-chunked     13  in place, two tiles per block, XCD-chunked
+ *  14  in place, XCD-chunked, non-temporal stores
+ * Moving between the two-buffer variants (0-10) and the in-place ones
+ * (11-14) permutes the stored populations into the other layout exactly.
  * With the two-stream schedule only 0-2 apply.  All variants give identical
  * bits, so the (applicable variants) x (reps + 1) steps the tuner takes are
  * ordinary steps of the simulation: the step counter advances by that many.
@@ -259,7 +268,9 @@ lb_status lb_get_step(lb_ctx* ctx, long long* step);
 
 /* Checkpoint: every population, node map, link list and particle record plus
  * the step counter, to a binary file; lb_load restores it into a context made
- * with the same configuration and boxes.  LB_EIO on file errors, LB_EINVAL on
+ * with the same configuration and boxes (in either population layout: the
+ * file records its own, and the load converts to the one the context's
+ * collide-stream variant uses).  LB_EIO on file errors, LB_EINVAL on
  * a mismatching file.  Synchronise. */
 lb_status lb_save(lb_ctx* ctx, const char* path);
 lb_status lb_load(lb_ctx* ctx, const char* path);
