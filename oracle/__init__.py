@@ -53,6 +53,11 @@ def lib():
         L.or_create.restype = vp
         L.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                 C.c_int, _D, _D, C.c_int, C.c_int]
+        L.or_create_q.restype = vp
+        L.or_create_q.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                  C.c_int, _D, _D, C.c_int, C.c_int, C.c_int]
+        L.or_equilibrium_q.argtypes = [C.c_int, C.c_double, _D, _D]
+        L.or_lattice_q.argtypes = [C.c_int, C.POINTER(C.c_int), _D]
         L.or_destroy.argtypes = [vp]
         L.or_add_ellipsoid.argtypes = [vp, _D, _D, _D]
         for name in ("or_set_external", "or_set_velocity"):
@@ -93,17 +98,18 @@ def lib():
 
 # ----------------------------- single pieces --------------------------------
 
-def lattice():
-    c = np.zeros(57, dtype=np.int32)
-    w = np.zeros(19)
-    lib().or_lattice(c.ctypes.data_as(C.POINTER(C.c_int)), _ptr(w))
-    return c.reshape(19, 3), w
+def lattice(q=19):
+    """Velocities (q, 3) and weights of the D3Q19 (q = 19) or D3Q27 set."""
+    c = np.zeros(3 * q, dtype=np.int32)
+    w = np.zeros(q)
+    lib().or_lattice_q(int(q), c.ctypes.data_as(C.POINTER(C.c_int)), _ptr(w))
+    return c.reshape(q, 3), w
 
 
-def equilibrium(rho, u):
+def equilibrium(rho, u, q=19):
     u = _arr(u)
-    out = np.zeros(19)
-    lib().or_equilibrium(float(rho), _ptr(u), _ptr(out))
+    out = np.zeros(q)
+    lib().or_equilibrium_q(int(q), float(rho), _ptr(u), _ptr(out))
     return out
 
 
@@ -156,14 +162,17 @@ class OracleSim:
     """One periodic (or wall-bounded) box stepped by the FP64 oracle."""
 
     def __init__(self, shape, collision="bgk", tau=1.0, magic=3.0 / 16.0, walls=False,
-                 wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), init="rest", counterforce=False):
+                 wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), init="rest", counterforce=False, lattice=19):
         self.shape = tuple(int(v) for v in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
+        self.q = int(lattice)
         ulo, uhi = _arr(wall_lo), _arr(wall_hi)
-        self._h = lib().or_create(self.shape[0], self.shape[1], self.shape[2],
-                                  COLLISIONS[collision], float(tau), float(magic),
-                                  int(bool(walls)), _ptr(ulo), _ptr(uhi),
-                                  {"rest": 0, "couette": 1}[init], int(bool(counterforce)))
+        self._h = lib().or_create_q(self.shape[0], self.shape[1], self.shape[2],
+                                    COLLISIONS[collision], float(tau), float(magic),
+                                    int(bool(walls)), _ptr(ulo), _ptr(uhi),
+                                    {"rest": 0, "couette": 1}[init], int(bool(counterforce)), self.q)
+        if not self._h:
+            raise ValueError(f"lattice must be 19 or 27, got {lattice}")
         self.np = 0
 
     def __del__(self):
@@ -254,12 +263,12 @@ class OracleSim:
         return lib().or_overlap_count(self._h)
 
     def get_f(self):
-        f = np.zeros(self.n * 19)
+        f = np.zeros(self.n * self.q)
         lib().or_get_f(self._h, _ptr(f))
-        return f.reshape(self.n, 19)
+        return f.reshape(self.n, self.q)
 
     def set_f(self, f):
-        f = _arr(f).reshape(self.n * 19)
+        f = _arr(f).reshape(self.n * self.q)
         lib().or_set_f(self._h, _ptr(f))
 
     def stream_only(self):
@@ -267,6 +276,6 @@ class OracleSim:
 
     def collide_node(self, f):
         f = _arr(f)
-        out = np.zeros(19)
+        out = np.zeros(self.q)
         lib().or_collide_node(self._h, _ptr(f), _ptr(out))
         return out

@@ -38,32 +38,46 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NQ 19
+#define NQMAX 27
 #define CS2 (1.0 / 3.0)
 
-/* Sec. II.A: D3Q19 velocity set (textbook, reading R2) */
-static const int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-static const int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-static const int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-static const double WT[NQ] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
-                              1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
-                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
-                              1.0 / 36};
+/* Sec. II.A: velocity sets (textbook, reading R2).  D3Q19: rest, the six
+   axis vectors, the twelve edge vectors; D3Q27 adds the eight corner
+   vectors (appended, each followed by its opposite). */
+static const int CX[NQMAX] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                              1, -1, 1, -1, 1, -1, -1, 1};
+static const int CY[NQMAX] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                              1, -1, 1, -1, -1, 1, 1, -1};
+static const int CZ[NQMAX] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                              1, -1, -1, 1, 1, -1, 1, -1};
+/* weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216 */
+static const double WT19[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                1.0 / 36};
+static const double WT27[27] = {8.0 / 27,  2.0 / 27,  2.0 / 27,  2.0 / 27,  2.0 / 27,  2.0 / 27,
+                                2.0 / 27,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,
+                                1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,  1.0 / 54,
+                                1.0 / 54,  1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216, 1.0 / 216,
+                                1.0 / 216, 1.0 / 216, 1.0 / 216};
 
+static const double* weights_of(int lattice) { return lattice == 27 ? WT27 : WT19; }
+
+/* index of -c_i, found once by search over the velocity table (the D3Q19
+   part of the table is closed under negation, so one table serves both) */
 static int opposite_search(int i) {
     int j;
-    for (j = 0; j < NQ; j++)
+    for (j = 0; j < NQMAX; j++)
         if (CX[j] == -CX[i] && CY[j] == -CY[i] && CZ[j] == -CZ[i]) return j;
     return -1;
 }
 
-/* index of -c_i, found once by search over the velocity table */
-static int OPPT[NQ];
+static int OPPT[NQMAX];
 static int opp_ready = 0;
 static int opposite(int i) {
     if (!opp_ready) {
         int j;
-        for (j = 0; j < NQ; j++) OPPT[j] = opposite_search(j);
+        for (j = 0; j < NQMAX; j++) OPPT[j] = opposite_search(j);
         opp_ready = 1;
     }
     return OPPT[i];
@@ -85,12 +99,14 @@ typedef struct {
 
 struct or_sim {
     int nx, ny, nz, n;
+    int q;              /* lattice: 19 or 27 velocities */
+    const double* wt;   /* its weights                  */
     int coll;
     double tau, taum, rho0;
     int walls;
     double ulo[3], uhi[3];
     int counterforce;
-    double* f;   /* pre-collision f[site*19+i], meaningful on fluid nodes */
+    double* f;   /* pre-collision f[site*q+i], meaningful on fluid nodes */
     double* fs;  /* post-collision                                       */
     int* node;   /* 0 fluid, p+1 solid of particle p, -1 wall            */
     int np, pcap;
@@ -117,19 +133,25 @@ static void cross(const double a[3], const double b[3], double r[3]) {
 
 /* ---------------- Sec. II.A: equilibrium and collision ------------------- */
 
-void or_equilibrium(double rho, const double u[3], double feq[19]) {
+static void equilibrium(int q, const double* wt, double rho, const double u[3], double* feq) {
     int i;
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    for (i = 0; i < NQ; i++) {
+    for (i = 0; i < q; i++) {
         double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
-        feq[i] = rho * WT[i] * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+        feq[i] = rho * wt[i] * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
     }
 }
 
-static void moments(const double f[19], double* rho, double u[3]) {
+void or_equilibrium(double rho, const double u[3], double feq[19]) { equilibrium(19, WT19, rho, u, feq); }
+
+void or_equilibrium_q(int lattice, double rho, const double u[3], double* feq) {
+    equilibrium(lattice, weights_of(lattice), rho, u, feq);
+}
+
+static void moments(int q, const double* f, double* rho, double u[3]) {
     int i;
     double r = 0, j[3] = {0, 0, 0};
-    for (i = 0; i < NQ; i++) {
+    for (i = 0; i < q; i++) {
         r += f[i];
         j[0] += f[i] * CX[i];
         j[1] += f[i] * CY[i];
@@ -141,17 +163,17 @@ static void moments(const double f[19], double* rho, double u[3]) {
     u[2] = j[2] / r;
 }
 
-void or_collide_node(const or_sim* s, const double f[19], double out[19]) {
-    double rho, u[3], feq[NQ];
+void or_collide_node(const or_sim* s, const double* f, double* out) {
+    double rho, u[3], feq[NQMAX];
     int i;
-    moments(f, &rho, u);
-    or_equilibrium(rho, u, feq);
+    moments(s->q, f, &rho, u);
+    equilibrium(s->q, s->wt, rho, u, feq);
     if (s->coll == 0) {
         /* BGK, reading R1 */
-        for (i = 0; i < NQ; i++) out[i] = f[i] - (f[i] - feq[i]) / s->tau;
+        for (i = 0; i < s->q; i++) out[i] = f[i] - (f[i] - feq[i]) / s->tau;
     } else if (s->coll == 1) {
         /* two-relaxation-time: symmetric part with tau+, antisymmetric with tau- */
-        for (i = 0; i < NQ; i++) {
+        for (i = 0; i < s->q; i++) {
             int o = opposite(i);
             double fp = 0.5 * (f[i] + f[o]), fm = 0.5 * (f[i] - f[o]);
             double ep = 0.5 * (feq[i] + feq[o]), em = 0.5 * (feq[i] - feq[o]);
@@ -162,7 +184,7 @@ void or_collide_node(const or_sim* s, const double f[19], double out[19]) {
            ghost modes set to equilibrium (zero): Hermite reconstruction */
         double P[3][3] = {{0}}, Pneq[3][3], c[3];
         int a, b;
-        for (i = 0; i < NQ; i++) {
+        for (i = 0; i < s->q; i++) {
             c[0] = CX[i]; c[1] = CY[i]; c[2] = CZ[i];
             for (a = 0; a < 3; a++)
                 for (b = 0; b < 3; b++) P[a][b] += f[i] * c[a] * c[b];
@@ -170,7 +192,7 @@ void or_collide_node(const or_sim* s, const double f[19], double out[19]) {
         for (a = 0; a < 3; a++)
             for (b = 0; b < 3; b++)
                 Pneq[a][b] = P[a][b] - rho * CS2 * (a == b) - rho * u[a] * u[b];
-        for (i = 0; i < NQ; i++) {
+        for (i = 0; i < s->q; i++) {
             double cu, qp = 0;
             c[0] = CX[i]; c[1] = CY[i]; c[2] = CZ[i];
             cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
@@ -179,7 +201,7 @@ void or_collide_node(const or_sim* s, const double f[19], double out[19]) {
                     double Qab = c[a] * c[b] - CS2 * (a == b);
                     qp += Qab * (rho * u[a] * u[b] + (1.0 - 1.0 / s->tau) * Pneq[a][b]);
                 }
-            out[i] = WT[i] * (rho + rho * cu / CS2 + qp / (2.0 * CS2 * CS2));
+            out[i] = s->wt[i] * (rho + rho * cu / CS2 + qp / (2.0 * CS2 * CS2));
         }
     }
 }
@@ -380,15 +402,18 @@ void or_squirmer_slip(const double axes[3], const double q[4], double B1, double
     for (k = 0; k < 3; k++) us[k] = -B1 * se * s[k] - B2 * zeta * se * s[k];
 }
 
-void or_lattice(int c[57], double w[19]) {
+void or_lattice_q(int lattice, int* c, double* w) {
     int i;
-    for (i = 0; i < NQ; i++) {
+    const double* wt = weights_of(lattice);
+    for (i = 0; i < lattice; i++) {
         c[3 * i] = CX[i];
         c[3 * i + 1] = CY[i];
         c[3 * i + 2] = CZ[i];
-        w[i] = WT[i];
+        w[i] = wt[i];
     }
 }
+
+void or_lattice(int c[57], double w[19]) { or_lattice_q(19, c, w); }
 
 /* ------------------------------- set-up ---------------------------------- */
 
@@ -398,10 +423,10 @@ static void init_fluid(or_sim* s, int init) {
         for (y = 0; y < s->ny; y++)
             for (x = 0; x < s->nx; x++) {
                 int st = site_of(s, x, y, z);
-                double u[3] = {0, 0, 0}, feq[NQ], g[3] = {0, 0, 0};
+                double u[3] = {0, 0, 0}, feq[NQMAX], g[3] = {0, 0, 0};
                 if (s->walls && (y == 0 || y == s->ny - 1)) {
                     s->node[st] = -1;
-                    for (i = 0; i < NQ; i++) s->f[st * NQ + i] = 0.0;
+                    for (i = 0; i < s->q; i++) s->f[st * s->q + i] = 0.0;
                     continue;
                 }
                 s->node[st] = 0;
@@ -414,23 +439,27 @@ static void init_fluid(or_sim* s, int init) {
                         u[k] = s->ulo[k] + g[k] * (y - 0.5);
                     }
                 }
-                or_equilibrium(s->rho0, u, feq);
-                for (i = 0; i < NQ; i++) {
+                equilibrium(s->q, s->wt, s->rho0, u, feq);
+                for (i = 0; i < s->q; i++) {
                     /* first-order Chapman-Enskog part: -tau w_i rho0 Q_i:grad u / c_s^2 */
                     double taus = s->tau;
                     double qg = CY[i] * (CX[i] * g[0] + CZ[i] * g[2]);
-                    s->f[st * NQ + i] = feq[i] - taus * WT[i] * s->rho0 * qg / CS2;
+                    s->f[st * s->q + i] = feq[i] - taus * s->wt[i] * s->rho0 * qg / CS2;
                 }
             }
 }
 
-or_sim* or_create(int nx, int ny, int nz, int collision, double tau, double magic,
-                  int walls, const double ulo[3], const double uhi[3], int init,
-                  int counterforce) {
-    or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
+or_sim* or_create_q(int nx, int ny, int nz, int collision, double tau, double magic,
+                    int walls, const double ulo[3], const double uhi[3], int init,
+                    int counterforce, int lattice) {
+    or_sim* s;
     int k;
+    if (lattice != 19 && lattice != 27) return NULL;
+    s = (or_sim*)calloc(1, sizeof(or_sim));
     if (!s) return NULL;
     (void)opposite(0);
+    s->q = lattice;
+    s->wt = weights_of(lattice);
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->n = nx * ny * nz;
     s->coll = collision;
@@ -443,13 +472,19 @@ or_sim* or_create(int nx, int ny, int nz, int collision, double tau, double magi
         s->uhi[k] = uhi ? uhi[k] : 0.0;
     }
     s->counterforce = counterforce;
-    s->f = (double*)calloc((size_t)s->n * NQ, sizeof(double));
-    s->fs = (double*)calloc((size_t)s->n * NQ, sizeof(double));
+    s->f = (double*)calloc((size_t)s->n * s->q, sizeof(double));
+    s->fs = (double*)calloc((size_t)s->n * s->q, sizeof(double));
     s->node = (int*)calloc((size_t)s->n, sizeof(int));
     s->pcap = 16;
     s->p = (opart*)calloc((size_t)s->pcap, sizeof(opart));
     init_fluid(s, init);
     return s;
+}
+
+or_sim* or_create(int nx, int ny, int nz, int collision, double tau, double magic,
+                  int walls, const double ulo[3], const double uhi[3], int init,
+                  int counterforce) {
+    return or_create_q(nx, ny, nz, collision, tau, magic, walls, ulo, uhi, init, counterforce, 19);
 }
 
 void or_destroy(or_sim* s) {
@@ -507,7 +542,7 @@ static void build_links_and_zeta(or_sim* s, int pid) {
                 int z = ((lo[2] + dz) % s->nz + s->nz) % s->nz;
                 int st = site_of(s, x, y, z);
                 if (s->node[st] != 0) continue;
-                for (b = 1; b < NQ; b++) {
+                for (b = 1; b < s->q; b++) {
                     int nb = site_of(s, wrapi(x + CX[b], s->nx), wrapi(y + CY[b], s->ny),
                                      wrapi(z + CZ[b], s->nz));
                     if (s->node[nb] != pid + 1) continue;
@@ -529,13 +564,13 @@ static void build_links_and_zeta(or_sim* s, int pid) {
         int i, j;
         rel(s, p->xc, x + 0.5 * cb[0], y + 0.5 * cb[1], z + 0.5 * cb[2], r);
         cross(r, cb, rc);
-        p->wsum += WT[bl];
+        p->wsum += s->wt[bl];
         for (i = 0; i < 3; i++)
             for (j = 0; j < 3; j++) {
-                p->zeta[6 * i + j] += K * WT[bl] * cb[i] * cb[j];               /* zeta_FU */
-                p->zeta[6 * i + 3 + j] += K * WT[bl] * cb[i] * rc[j];           /* zeta_FW */
-                p->zeta[6 * (3 + i) + j] += K * WT[bl] * rc[i] * cb[j];         /* zeta_TU */
-                p->zeta[6 * (3 + i) + 3 + j] += K * WT[bl] * rc[i] * rc[j];     /* zeta_TW */
+                p->zeta[6 * i + j] += K * s->wt[bl] * cb[i] * cb[j];               /* zeta_FU */
+                p->zeta[6 * i + 3 + j] += K * s->wt[bl] * cb[i] * rc[j];           /* zeta_FW */
+                p->zeta[6 * (3 + i) + j] += K * s->wt[bl] * rc[i] * cb[j];         /* zeta_TU */
+                p->zeta[6 * (3 + i) + 3 + j] += K * s->wt[bl] * rc[i] * rc[j];     /* zeta_TW */
             }
     }
 }
@@ -574,12 +609,12 @@ static int remap(or_sim* s, int apply) {
             if (o > 0) {
                 /* uncovered by particle o-1 (R9): f = f_eq(rho0, U + W x r) */
                 opart* p = &s->p[o - 1];
-                double r[3], wr[3], u[3], feq[NQ], L[3];
+                double r[3], wr[3], u[3], feq[NQMAX], L[3];
                 rel(s, p->xc, x, y, z, r);
                 cross(p->W, r, wr);
                 for (i = 0; i < 3; i++) u[i] = p->U[i] + wr[i];
-                or_equilibrium(s->rho0, u, feq);
-                for (i = 0; i < NQ; i++) s->f[st * NQ + i] = feq[i];  /* mass rho0: no excess */
+                equilibrium(s->q, s->wt, s->rho0, u, feq);
+                for (i = 0; i < s->q; i++) s->f[st * s->q + i] = feq[i];  /* mass rho0: no excess */
                 for (i = 0; i < 3; i++) u[i] *= s->rho0;
                 cross(r, u, L);
                 for (i = 0; i < 3; i++) {
@@ -591,8 +626,8 @@ static int remap(or_sim* s, int apply) {
                 /* covered by particle m-1 (R9): momentum and excess mass to the particle */
                 opart* p = &s->p[m - 1];
                 double r[3], mass = 0, P[3] = {0, 0, 0}, L[3];
-                for (i = 0; i < NQ; i++) {
-                    double fi = s->f[st * NQ + i];
+                for (i = 0; i < s->q; i++) {
+                    double fi = s->f[st * s->q + i];
                     mass += fi;
                     P[0] += fi * CX[i];
                     P[1] += fi * CY[i];
@@ -716,9 +751,9 @@ static int step_once(or_sim* s) {
     for (st = 0; st < s->n; st++) {
         int i;
         if (s->node[st] != 0) continue;
-        or_collide_node(s, &s->f[st * NQ], &s->fs[st * NQ]);
-        for (i = 0; i < NQ; i++)
-            s->fs[st * NQ + i] += WT[i] * s->rho0 * (CX[i] * g[0] + CY[i] * g[1] + CZ[i] * g[2]) / CS2;
+        or_collide_node(s, &s->f[st * s->q], &s->fs[st * s->q]);
+        for (i = 0; i < s->q; i++)
+            s->fs[st * s->q + i] += s->wt[i] * s->rho0 * (CX[i] * g[0] + CY[i] * g[1] + CZ[i] * g[2]) / CS2;
     }
 
     /* step 2: streaming between fluid nodes; links into solid/wall nodes skipped */
@@ -726,10 +761,10 @@ static int step_once(or_sim* s) {
     for (st = 0; st < s->n; st++) {
         int x = st % s->nx, y = (st / s->nx) % s->ny, z = st / (s->nx * s->ny), i;
         if (s->node[st] != 0) continue;
-        for (i = 0; i < NQ; i++) {
+        for (i = 0; i < s->q; i++) {
             int src = site_of(s, wrapi(x - CX[i], s->nx), wrapi(y - CY[i], s->ny),
                               wrapi(z - CZ[i], s->nz));
-            if (s->node[src] == 0) s->f[st * NQ + i] = s->fs[src * NQ + i];
+            if (s->node[src] == 0) s->f[st * s->q + i] = s->fs[src * s->q + i];
         }
     }
 
@@ -746,7 +781,7 @@ static int step_once(or_sim* s) {
         for (l = 0; l < p->nlinks; l++) {
             int stl = p->lsite[l], b = p->ldir[l];
             int x = stl % s->nx, y = (stl / s->nx) % s->ny, z = stl / (s->nx * s->ny);
-            double cb[3] = {CX[b], CY[b], CZ[b]}, r[3], rc[3], fb = s->fs[stl * NQ + b];
+            double cb[3] = {CX[b], CY[b], CZ[b]}, r[3], rc[3], fb = s->fs[stl * s->q + b];
             rel(s, p->xc, x + 0.5 * cb[0], y + 0.5 * cb[1], z + 0.5 * cb[2], r);
             cross(r, cb, rc);
             for (k = 0; k < 3; k++) {
@@ -758,8 +793,8 @@ static int step_once(or_sim* s) {
                 or_squirmer_slip(p->axes, p->q, p->B1, p->B2, r, us);
                 uc = us[0] * cb[0] + us[1] * cb[1] + us[2] * cb[2];
                 for (k = 0; k < 3; k++) {
-                    Fs[k] -= K * WT[b] * uc * cb[k];
-                    Ts[k] -= K * WT[b] * uc * rc[k];
+                    Fs[k] -= K * s->wt[b] * uc * cb[k];
+                    Ts[k] -= K * s->wt[b] * uc * rc[k];
                 }
             }
         }
@@ -816,8 +851,8 @@ static int step_once(or_sim* s) {
                     for (k = 0; k < 3; k++) ub[k] += us[k];
                 }
                 uc = ub[0] * cb[0] + ub[1] * cb[1] + ub[2] * cb[2];
-                s->f[stl * NQ + bo] = s->fs[stl * NQ + b] - 2.0 * WT[b] * s->rho0 * uc / CS2 +
-                                      (p->wsum > 0 ? p->dm * WT[b] / p->wsum : 0.0);
+                s->f[stl * s->q + bo] = s->fs[stl * s->q + b] - 2.0 * s->wt[b] * s->rho0 * uc / CS2 +
+                                      (p->wsum > 0 ? p->dm * s->wt[b] / p->wsum : 0.0);
             }
             p->dm = 0.0;
             /* step 7: eq. posupdate and eqs. qnplus0/qnplus1 */
@@ -840,7 +875,7 @@ static int step_once(or_sim* s) {
         for (st = 0; st < s->n; st++) {
             int x = st % s->nx, y = (st / s->nx) % s->ny, z = st / (s->nx * s->ny), b;
             if (s->node[st] != 0) continue;
-            for (b = 1; b < NQ; b++) {
+            for (b = 1; b < s->q; b++) {
                 int yy = y + CY[b];
                 const double* uw;
                 double uc;
@@ -848,7 +883,7 @@ static int step_once(or_sim* s) {
                 (void)x; (void)z;
                 uw = yy == 0 ? s->ulo : s->uhi;
                 uc = uw[0] * CX[b] + uw[1] * CY[b] + uw[2] * CZ[b];
-                s->f[st * NQ + opposite(b)] = s->fs[st * NQ + b] - 2.0 * WT[b] * s->rho0 * uc / CS2;
+                s->f[st * s->q + opposite(b)] = s->fs[st * s->q + b] - 2.0 * s->wt[b] * s->rho0 * uc / CS2;
             }
         }
     }
@@ -930,7 +965,7 @@ void or_get_fields(const or_sim* s, double* rho, double* u) {
     int st;
     for (st = 0; st < s->n; st++) {
         double r = 0, v[3] = {0, 0, 0};
-        if (s->node[st] == 0) moments(&s->f[st * NQ], &r, v);
+        if (s->node[st] == 0) moments(s->q, &s->f[st * s->q], &r, v);
         if (rho) rho[st] = r;
         if (u) {
             u[3 * st] = v[0];
@@ -955,7 +990,7 @@ double or_get_mass(const or_sim* s) {
     int st, i, pid;
     for (st = 0; st < s->n; st++) {
         if (s->node[st] == 0)
-            for (i = 0; i < NQ; i++) nadd(&m, s->f[st * NQ + i]);
+            for (i = 0; i < s->q; i++) nadd(&m, s->f[st * s->q + i]);
         else if (s->node[st] > 0)
             nadd(&m, s->rho0); /* particle node counted at the rest density (R9) */
     }
@@ -968,8 +1003,8 @@ void or_get_momentum(const or_sim* s, double P[3]) {
     int st, i;
     for (st = 0; st < s->n; st++)
         if (s->node[st] == 0)
-            for (i = 0; i < NQ; i++) {
-                double fi = s->f[st * NQ + i];
+            for (i = 0; i < s->q; i++) {
+                double fi = s->f[st * s->q + i];
                 nadd(&a[0], fi * CX[i]);
                 nadd(&a[1], fi * CY[i]);
                 nadd(&a[2], fi * CZ[i]);
@@ -980,18 +1015,18 @@ void or_get_momentum(const or_sim* s, double P[3]) {
 long long or_get_step(const or_sim* s) { return s->step; }
 int or_overlap_count(const or_sim* s) { return s->overlaps; }
 
-void or_get_f(const or_sim* s, double* out) { memcpy(out, s->f, sizeof(double) * (size_t)s->n * NQ); }
-void or_set_f(or_sim* s, const double* in) { memcpy(s->f, in, sizeof(double) * (size_t)s->n * NQ); }
+void or_get_f(const or_sim* s, double* out) { memcpy(out, s->f, sizeof(double) * (size_t)s->n * s->q); }
+void or_set_f(or_sim* s, const double* in) { memcpy(s->f, in, sizeof(double) * (size_t)s->n * s->q); }
 
 void or_stream_only(or_sim* s) {
     int st;
-    memcpy(s->fs, s->f, sizeof(double) * (size_t)s->n * NQ);
+    memcpy(s->fs, s->f, sizeof(double) * (size_t)s->n * s->q);
     for (st = 0; st < s->n; st++) {
         int x = st % s->nx, y = (st / s->nx) % s->ny, z = st / (s->nx * s->ny), i;
-        for (i = 0; i < NQ; i++) {
+        for (i = 0; i < s->q; i++) {
             int src = site_of(s, wrapi(x - CX[i], s->nx), wrapi(y - CY[i], s->ny),
                               wrapi(z - CZ[i], s->nz));
-            s->f[st * NQ + i] = s->fs[src * NQ + i];
+            s->f[st * s->q + i] = s->fs[src * s->q + i];
         }
     }
 }

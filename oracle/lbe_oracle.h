@@ -7,8 +7,8 @@
  * baseline leg of the benchmark, never from the product path.  It shares no
  * source, header, table or helper with the HIP library.
  *
- * Storage: full populations f_i (not deviations), one AoS array of 19 doubles
- * per node, explicit separate collision and streaming loops, the node map as
+ * Storage: full populations f_i (not deviations), one AoS array of q doubles
+ * per node (q = 19 for D3Q19, 27 for D3Q27), explicit separate collision and streaming loops, the node map as
  * an int per site (0 fluid, p+1 solid node of particle p, -1 wall).
  */
 #ifndef LBE_ORACLE_H
@@ -21,6 +21,11 @@ typedef struct or_sim or_sim;
 or_sim* or_create(int nx, int ny, int nz, int collision, double tau, double magic,
                   int walls, const double ulo[3], const double uhi[3], int init,
                   int counterforce);
+/* the same on the D3Q19 (lattice = 19) or D3Q27 (27) velocity set; NULL
+   for any other lattice */
+or_sim* or_create_q(int nx, int ny, int nz, int collision, double tau, double magic,
+                    int walls, const double ulo[3], const double uhi[3], int init,
+                    int counterforce, int lattice);
 void    or_destroy(or_sim* s);
 int     or_add_ellipsoid(or_sim* s, const double centre[3], const double axes[3],
                          const double quat[4]);
@@ -45,12 +50,13 @@ void    or_get_momentum(const or_sim* s, double P[3]);
 long long or_get_step(const or_sim* s);
 int     or_overlap_count(const or_sim* s);
 
-/* raw access for pins: pre-collision populations f[site*19 + i] */
+/* raw access for pins: pre-collision populations f[site*q + i] */
 void    or_get_f(const or_sim* s, double* out);
 void    or_set_f(or_sim* s, const double* in);
 /* pins on single pieces of the method */
 void    or_equilibrium(double rho, const double u[3], double feq[19]);
-void    or_collide_node(const or_sim* s, const double f[19], double out[19]);
+void    or_equilibrium_q(int lattice, double rho, const double u[3], double* feq);
+void    or_collide_node(const or_sim* s, const double* f, double* out);
 void    or_stream_only(or_sim* s);   /* post-collision := f, then stream, no links */
 int     or_inside(int nx, int ny, int nz, const double xc[3], const double axes[3],
                   const double q[4], int x, int y, int z);
@@ -62,4 +68,5 @@ void    or_quat_update(const double q[4], const double Wmean[3], double out[4]);
 void    or_squirmer_slip(const double axes[3], const double q[4], double B1, double B2,
                          const double d[3], double us[3]);
 void    or_lattice(int c[57], double w[19]);
+void    or_lattice_q(int lattice, int* c, double* w);
 #endif
