@@ -20,7 +20,11 @@
  *      6:(0,0,-1) 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0) 11:(1,0,1)
  *      12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1) 16:(0,-1,-1)
  *      17:(0,1,-1) 18:(0,-1,1); the opposite of an odd i is i+1.
- *      Weights 1/3 (rest), 1/18 (axis), 1/36 (diagonal).
+ *      Weights 1/3 (rest), 1/18 (axis), 1/36 (diagonal).  D3Q27 continues
+ *      19:(1,1,1) 20:(-1,-1,-1) 21:(1,1,-1) 22:(-1,-1,1) 23:(1,-1,1)
+ *      24:(-1,1,-1) 25:(-1,1,1) 26:(1,-1,-1), weights 8/27 (rest), 2/27
+ *      (axis), 1/54 (edge), 1/216 (corner).  Link codes and the direction
+ *      arguments below use these indices.
  *  - Nodes sit at integer coordinates 0..n-1; site index = x + nx*(y + ny*z).
  *  - Quaternions are Hamilton, scalar first, rotating body to lab
  *    (s_lab = q s_body q^-1, Sec. II.D); Omega is in the lab frame.
@@ -72,7 +76,9 @@ typedef int lb_status;
 #define LB_BF16 3
 
 typedef struct lb_config {
-    int    lattice;         /* must be 19                                              */
+    int    lattice;         /* 19 (D3Q19, default) or 27 (D3Q27: the eight corner
+                               vectors appended as directions 19-26, each followed by
+                               its opposite; Sec. III.A, Fig. 3d)                      */
     int    collision;       /* LB_BGK, LB_TRT or LB_REG                                */
     double tau;             /* relaxation time (TRT: tau+), nu = (tau - 1/2)/3, > 1/2  */
     double magic;           /* TRT Lambda; default 3/16                                */

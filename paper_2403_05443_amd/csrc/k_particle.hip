@@ -22,7 +22,7 @@ namespace lbd {
 
 __host__ __device__ constexpr unsigned long long pack_dir(int axis) {
     unsigned long long v = 0;
-    for (int i = 0; i < NQ; ++i)
+    for (int i = 0; i < NQMAX; ++i)
         v |= (unsigned long long)((axis == 0 ? cx(i) : (axis == 1 ? cy(i) : cz(i))) + 1) << (2 * i);
     return v;
 }
@@ -30,7 +30,12 @@ constexpr unsigned long long CXP = pack_dir(0), CYP = pack_dir(1), CZP = pack_di
 __device__ __forceinline__ int rcx(int b) { return (int)((CXP >> (2 * b)) & 3ull) - 1; }
 __device__ __forceinline__ int rcy(int b) { return (int)((CYP >> (2 * b)) & 3ull) - 1; }
 __device__ __forceinline__ int rcz(int b) { return (int)((CZP >> (2 * b)) & 3ull) - 1; }
-__device__ __forceinline__ int rw36(int b) { return b == 0 ? 12 : (b <= 6 ? 2 : 1); }
+// the weight of direction b in exact integer form (W w_b, W = WSCALE<Q>), and
+// 6 / W: the factor of eq. fb's moving-boundary term 2 w rho0 (u.c) / c_s^2
+template <int Q>
+__device__ __forceinline__ int rw(int b) { return wint<Q>(b); }
+template <int Q>
+constexpr double W6 = (double)(WSCALE<Q> / 6);
 __device__ __forceinline__ int ropp(int b) { return b == 0 ? 0 : ((b & 1) ? b + 1 : b - 1); }
 
 // q = floor(i / w) and r = i - q w for 0 <= i < 2^31, w >= 1, given
@@ -184,6 +189,7 @@ __device__ __forceinline__ void stage_particle(const PartDev* P, PartDev* S) {
 
 // Where node (x,y,z) keeps its pre-collision population i in the pull
 // layout, and what the collide kernel adds when it reads it (wall rows).
+template <int Q>
 __device__ __forceinline__ void pre_slot(int cv, const BoxDesc& B, double rho0, int i, int x, int y, int z, int& dir,
                                          int& slot, double& add) {
     const int nx = B.nx, ny = B.ny, nz = B.nz;
@@ -192,7 +198,7 @@ __device__ __forceinline__ void pre_slot(int cv, const BoxDesc& B, double rho0, 
         // off a wall: the node's own f*_opp(i) of the last step plus the wall term
         const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
         post_slot(cv, ropp(i), x, y, z, nx, ny, nz, dir, slot);
-        add = (rw36(i) / 6.0) * rho0 * (rcx(i) * uw[0] + rcy(i) * uw[1] + rcz(i) * uw[2]);
+        add = (rw<Q>(i) / W6<Q>) * rho0 * (rcx(i) * uw[0] + rcy(i) * uw[1] + rcz(i) * uw[2]);
     } else {
         pre_slot_open(cv, i, x, y, z, nx, ny, nz, dir, slot);
         add = 0.0;
@@ -211,6 +217,7 @@ __device__ __forceinline__ long long link_post(int cv, const BoxDesc& B, int b, 
 }
 
 // Per-thread partial sums of eqs. drag1-drag4 (36 w_b as integers 2 / 1).
+template <int Q>
 struct ZAcc {
     int cnt6[6];
     int w36s;
@@ -223,7 +230,7 @@ struct ZAcc {
         for (int k = 0; k < 6; ++k) ztw[k] = 0.0;
     }
     __device__ __forceinline__ void add(int b, int gx, int gy, int gz, const double xc[3], int nx, int ny, int nz) {
-        const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b), w36 = rw36(b);
+        const int c0 = rcx(b), c1 = rcy(b), c2 = rcz(b), w36 = rw<Q>(b);
         const double r0 = minimg(((double)gx + 0.5 * c0) - xc[0], nx);
         const double r1 = minimg(((double)gy + 0.5 * c1) - xc[1], ny);
         const double r2 = minimg(((double)gz + 0.5 * c2) - xc[2], nz);
@@ -257,13 +264,14 @@ struct ZAcc {
 // zeta_TW = k (Z2 - Z1^T D^T - D Z1 + D Z0 D^T), k = rho0 / 6 (36 w = 6 w / c_s^2).
 // Both (i, j) and (j, i) evaluate the upper-triangle entry, so the matrix
 // stays exactly symmetric.
+template <int Q>
 __device__ __forceinline__ double zeta_entry(const PartDev& P, const double xu[3], int i, int j, double rho0) {
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     auto ut = [](int a, int b) {  // upper-triangle index of the symmetric 3x3 (a, b)
         const int l = a < b ? a : b, h = a < b ? b : a;
         return l == 0 ? h : (l == 1 ? 2 + h : 5);
     };
-    if (hi < 3) return rho0 * (double)P.zm0[ut(lo, hi)] / 6.0;
+    if (hi < 3) return rho0 * (double)P.zm0[ut(lo, hi)] / W6<Q>;
     const double d[3] = {xu[0] - P.xref[0], xu[1] - P.xref[1], xu[2] - P.xref[2]};
     const double D[3][3] = {{0.0, -d[2], d[1]}, {d[2], 0.0, -d[0]}, {-d[1], d[0], 0.0}};
     double v;
@@ -278,7 +286,7 @@ __device__ __forceinline__ double zeta_entry(const PartDev& P, const double xu[3
         for (int b = 0; b < 3; ++b)
             for (int c = 0; c < 3; ++c) v += D[ii][b] * (double)P.zm0[ut(b, c)] * D[jj][c];
     }
-    return rho0 * v / 6.0;
+    return rho0 * v / W6<Q>;
 }
 
 // Remap window of a particle: axis-aligned bounding box of the ellipsoid plus
@@ -365,7 +373,7 @@ struct LinkRegs {
 // flight across the LDS write and the barrier.  A lane without a link reads
 // element 0 of the box (always valid) and never uses it, so no load sits in
 // a branch, where its use, and a wait for it, would follow at once.
-template <int ST>
+template <int ST, int Q>
 __device__ __forceinline__ void load_particle(const LaunchPart& a, int p, PartDev* Pl,
                                               LinkRegs<typename Store<ST>::T>& lr) {
     using T = typename Store<ST>::T;
@@ -394,7 +402,7 @@ __device__ __forceinline__ void load_particle(const LaunchPart& a, int p, PartDe
 
 // Steps 3-7 for particle p whose record is staged in LDS (P).  The new state
 // goes to global memory; with keep_lds the LDS copy is updated as well.
-template <int ST>
+template <int ST, int Q>
 __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev& P, SolveShm& sh,
                                             const LinkRegs<typename Store<ST>::T>& lr, bool keep_lds) {
     using S = Store<ST>;
@@ -478,7 +486,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         if (sq) {
             double us[3];
             squirmer_slip(ax, bx, e, B1, B2, r, us);
-            const double kuc = (rw36(b) / 6.0) * rho0 * (us[0] * c0 + us[1] * c1 + us[2] * c2);
+            const double kuc = (rw<Q>(b) / W6<Q>) * rho0 * (us[0] * c0 + us[1] * c1 + us[2] * c2);
             acc[0] -= kuc * c0;
             acc[1] -= kuc * c1;
             acc[2] -= kuc * c2;
@@ -603,7 +611,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         const int e = tid - (PBLOCK - 128);
         double xu[3];
         for (int i = 0; i < 3; ++i) xu[i] = xu0[i] + 0.5 * (bc[i] + U0[i]);
-        Pg->zeta[e] = zeta_entry(P, xu, e / 6, e % 6, rho0);
+        Pg->zeta[e] = zeta_entry<Q>(P, xu, e / 6, e % 6, rho0);
     } else if (tid >= PBLOCK - 192 && tid < PBLOCK - 192 + 3) {  // position (eq. posupdate), wrapped into the box
         const int i = tid - (PBLOCK - 192);
         const int n3 = i == 0 ? nx : (i == 1 ? ny : nz);
@@ -641,7 +649,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step
-    const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / 36.0;
+    const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / (double)WSCALE<Q>;
     auto bounce = [&](uint32_t cd, double fb) {
         const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
         int x, y;
@@ -658,8 +666,8 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             ub[1] += us[1];
             ub[2] += us[2];
         }
-        const int w36 = rw36(b);
-        const double val = fb - (w36 / 6.0) * rho0 * (ub[0] * c0 + ub[1] * c1 + ub[2] * c2) + dmw * w36;
+        const int w36 = rw<Q>(b);
+        const double val = fb - (w36 / W6<Q>) * rho0 * (ub[0] * c0 + ub[1] * c1 + ub[2] * c2) + dmw * w36;
         // the slot of f_opp(b)(x) the fluid node reads next (it comes from the
         // solid node, never off a wall)
         int pd, ps;
@@ -675,14 +683,14 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
 }
 
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
     __shared__ PartDev P;
     __shared__ SolveShm sh;
     const int p = a.first + (int)blockIdx.x;
     LinkRegs<typename Store<ST>::T> lr;
-    load_particle<ST>(a, p, &P, lr);
-    solve_phase<ST>(a, p, P, sh, lr, false);
+    load_particle<ST, Q>(a, p, &P, lr);
+    solve_phase<ST, Q>(a, p, P, sh, lr, false);
 }
 
 struct RemapShm {
@@ -692,7 +700,7 @@ struct RemapShm {
 };
 
 // Steps 8-9 for particle p with its (new) state staged in LDS (P).
-template <int ST>
+template <int ST, int Q>
 __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const PartDev& P, RemapShm& sh, uint32_t* smem) {
     using S = Store<ST>;
     using T = typename S::T;
@@ -772,10 +780,10 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                                  minimg((double)gz - xc[2], nz)};
                             if (in) {  // covered: its momentum and its mass in excess of rho0 go to the particle
                                 double m = 0, pm[3] = {0, 0, 0};
-                                for (int j = 0; j < NQ; ++j) {
+                                for (int j = 0; j < Q; ++j) {
                                     int dir, slot;
                                     double add;
-                                    pre_slot(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
+                                    pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
                                     const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
                                     m += v;
                                     pm[0] += rcx(j) * v;
@@ -794,12 +802,12 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                                      U[1] + (W[2] * r[0] - W[0] * r[2]),
                                                      U[2] + (W[0] * r[1] - W[1] * r[0])};
                                 const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-                                for (int j = 0; j < NQ; ++j) {
+                                for (int j = 0; j < Q; ++j) {
                                     int dir, slot;
                                     double add;
-                                    pre_slot(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
+                                    pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
                                     const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
-                                    const double dev = (rw36(j) / 36.0) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                                    const double dev = (rw<Q>(j) / (double)WSCALE<Q>) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
                                     S::st64(f + (long long)dir * st + slot, dev - add, scl);
                                 }
                                 // the new node holds rho0: no excess mass
@@ -844,7 +852,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         return;
     }
 
-    ZAcc z;
+    ZAcc<Q> z;
     z.clear();
     int running = 0;
     const int lcap = P.lcap;
@@ -865,7 +873,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                 s = gx + nx * (gy + ny * gz);
                 if (om[s] == 0) {
 #pragma unroll
-                    for (int b = 1; b < NQ; ++b) {
+                    for (int b = 1; b < Q; ++b) {
                         int nwx = wx + cx(b), nwy = wy + cy(b), nwz = wz + cz(b);
                         if (whole[0]) nwx = wrap(nwx, wn[0]);
                         else if (nwx < 0 || nwx >= wn[0]) continue;
@@ -942,18 +950,18 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         double z;
         if (i < 3 && j < 3) {
             const int lo_ = i < j ? i : j, hi_ = i < j ? j : i;  // upper-triangle index of (i, j)
-            z = rho0 * itot(lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5)) / 6.0;
+            z = rho0 * itot(lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5)) / W6<Q>;
         } else if (i < 3) {
-            z = rho0 * red[7 + 3 * i + (j - 3)][0] / 6.0;
+            z = rho0 * red[7 + 3 * i + (j - 3)][0] / W6<Q>;
         } else if (j < 3) {
-            z = rho0 * red[7 + 3 * j + (i - 3)][0] / 6.0;
+            z = rho0 * red[7 + 3 * j + (i - 3)][0] / W6<Q>;
         } else {
             const int ii = i - 3, jj = j - 3, lo_ = ii < jj ? ii : jj, hi_ = ii < jj ? jj : ii;
-            z = rho0 * red[16 + (lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5))][0] / 6.0;
+            z = rho0 * red[16 + (lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5))][0] / W6<Q>;
         }
         Pg->zeta[tid] = z;
     } else if (tid == 36) {
-        Pg->wsum = itot(6) / 36.0;
+        Pg->wsum = itot(6) / (double)WSCALE<Q>;
         Pg->nlinks = running < lcap ? running : lcap;
     } else if (tid >= 37 && tid < 44 && mode == 0) {
         const int k = tid - 37;  // dm, Pp[3], Lp[3]
@@ -975,20 +983,20 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     if (mode == 0 && a.near.flags) mark_near(a.near, B, lo, wn);
 }
 
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
     extern __shared__ uint32_t smem[];
     __shared__ PartDev P;
     __shared__ RemapShm sh;
     const int p = a.first + (int)blockIdx.x;
     stage_particle(a.parts + p, &P);
-    remap_phase<ST>(a, p, P, sh, smem);
+    remap_phase<ST, Q>(a, p, P, sh, smem);
 }
 
 // Steps 3-9 in one work-group, for boxes that hold one particle: the record
 // is staged once, and the remap reads the bounce-back writes of its own
 // work-group (no other particle writes this box).
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
     extern __shared__ uint32_t smem[];
     __shared__ PartDev P;
@@ -998,10 +1006,10 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
     } sh;
     const int p = a.first + (int)blockIdx.x;
     LinkRegs<typename Store<ST>::T> lr;
-    load_particle<ST>(a, p, &P, lr);
-    solve_phase<ST>(a, p, P, sh.s, lr, true);
+    load_particle<ST, Q>(a, p, &P, lr);
+    solve_phase<ST, Q>(a, p, P, sh.s, lr, true);
     __syncthreads();  // bounce-back writes before the covered-node reads of the remap
-    remap_phase<ST>(a, p, P, sh.r, smem);
+    remap_phase<ST, Q>(a, p, P, sh.r, smem);
 }
 
 // Near set from the particles' current positions (set-up and re-tuning).
@@ -1026,44 +1034,59 @@ hipError_t launch_near_mark(const LaunchPart& a, hipStream_t st) {
 
 size_t particle_remap_lds_bytes(int lds_words) { return (size_t)(lds_words + STAGE) * sizeof(uint32_t); }
 
-hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st) {
-    if (a.count <= 0) return hipSuccess;
+template <int Q>
+static hipError_t solve_q(const LaunchPart& a, hipStream_t st) {
     switch (a.kp.storage) {
-        case ST_F64: hipLaunchKernelGGL(k_particle_solve<ST_F64>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
-        case ST_F32: hipLaunchKernelGGL(k_particle_solve<ST_F32>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
-        case ST_F16: hipLaunchKernelGGL(k_particle_solve<ST_F16>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_particle_solve<ST_BF16>, dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        case ST_F64: hipLaunchKernelGGL((k_particle_solve<ST_F64, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        case ST_F32: hipLaunchKernelGGL((k_particle_solve<ST_F32, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        case ST_F16: hipLaunchKernelGGL((k_particle_solve<ST_F16, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_particle_solve<ST_BF16, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
     }
     return hipGetLastError();
 }
 
-template <int ST>
+hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    return a.kp.q == 27 ? solve_q<27>(a, st) : solve_q<19>(a, st);
+}
+
+template <int ST, int Q>
 static hipError_t remap_one(const LaunchPart& a, hipStream_t st) {
     const size_t lds = particle_remap_lds_bytes(a.lds_words);
-    hipLaunchKernelGGL(k_particle_remap<ST>, dim3(a.count), dim3(PBLOCK), lds, st, a);
+    hipLaunchKernelGGL((k_particle_remap<ST, Q>), dim3(a.count), dim3(PBLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int Q>
+static hipError_t step_q(const LaunchPart& a, hipStream_t st) {
+    const size_t lds = particle_remap_lds_bytes(a.lds_words);
+    switch (a.kp.storage) {
+        case ST_F64: hipLaunchKernelGGL((k_particle_step<ST_F64, Q>), dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        case ST_F32: hipLaunchKernelGGL((k_particle_step<ST_F32, Q>), dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        case ST_F16: hipLaunchKernelGGL((k_particle_step<ST_F16, Q>), dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        default: hipLaunchKernelGGL((k_particle_step<ST_BF16, Q>), dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_particle_step(const LaunchPart& a, hipStream_t st) {
     if (a.count <= 0) return hipSuccess;
-    const size_t lds = particle_remap_lds_bytes(a.lds_words);
+    return a.kp.q == 27 ? step_q<27>(a, st) : step_q<19>(a, st);
+}
+
+template <int Q>
+static hipError_t remap_q(const LaunchPart& a, hipStream_t st) {
     switch (a.kp.storage) {
-        case ST_F64: hipLaunchKernelGGL(k_particle_step<ST_F64>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
-        case ST_F32: hipLaunchKernelGGL(k_particle_step<ST_F32>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
-        case ST_F16: hipLaunchKernelGGL(k_particle_step<ST_F16>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
-        default: hipLaunchKernelGGL(k_particle_step<ST_BF16>, dim3(a.count), dim3(PBLOCK), lds, st, a); break;
+        case ST_F64: return remap_one<ST_F64, Q>(a, st);
+        case ST_F32: return remap_one<ST_F32, Q>(a, st);
+        case ST_F16: return remap_one<ST_F16, Q>(a, st);
+        default: return remap_one<ST_BF16, Q>(a, st);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_particle_remap(const LaunchPart& a, hipStream_t st) {
     if (a.count <= 0) return hipSuccess;
-    switch (a.kp.storage) {
-        case ST_F64: return remap_one<ST_F64>(a, st);
-        case ST_F32: return remap_one<ST_F32>(a, st);
-        case ST_F16: return remap_one<ST_F16>(a, st);
-        default: return remap_one<ST_BF16>(a, st);
-    }
+    return a.kp.q == 27 ? remap_q<27>(a, st) : remap_q<19>(a, st);
 }
 
 }  // namespace lbd

@@ -23,7 +23,7 @@
 
 namespace lbd {
 
-template <int ST>
+template <int ST, int Q>
 struct Pull {
     using S = Store<ST>;
     using T = typename S::T;
@@ -34,7 +34,7 @@ struct Pull {
     template <int CIN>
     static __device__ __forceinline__ void pull(const BoxDesc& B, const T* fi, int s,
                                                 int x, int y, int z, R inv_scale, R rho0,
-                                                bool walls, R (&f)[NQ]) {
+                                                bool walls, R (&f)[Q]) {
 #pragma clang fp contract(off)
         const int nx = B.nx, ny = B.ny, nz = B.nz;
         const long long st = B.stride;
@@ -42,7 +42,7 @@ struct Pull {
         const int ys0 = y == ny - 1 ? 0 : y + 1, ys2 = y == 0 ? ny - 1 : y - 1;
         const int zs0 = z == nz - 1 ? 0 : z + 1, zs2 = z == 0 ? nz - 1 : z - 1;
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < Q; ++i) {
             // source node x - c_i
             const int sx = cx(i) == 1 ? xs2 : (cx(i) == -1 ? xs0 : x);
             const int sy = cy(i) == 1 ? ys2 : (cy(i) == -1 ? ys0 : y);
@@ -55,7 +55,7 @@ struct Pull {
                 const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
                 const long long off = CIN == CV_PULL ? (long long)opp(i) * st + s
                                     : (CIN == CV_EVEN ? (long long)i * st + s : (long long)opp(i) * st + src);
-                f[i] = S::ld(fi + off, inv_scale) + (R)(6.0 * wgt(i)) * rho0 * cu;
+                f[i] = S::ld(fi + off, inv_scale) + (R)(6.0 * wgt<Q>(i)) * rho0 * cu;
             } else {
                 const long long off = CIN == CV_PULL ? (long long)i * st + src
                                     : (CIN == CV_EVEN ? (long long)opp(i) * st + src : (long long)i * st + s);
@@ -66,7 +66,7 @@ struct Pull {
 
     // The same in the convention held in a run-time value (read-out kernels).
     static __device__ __forceinline__ void pull_cv(int cv, const BoxDesc& B, const T* fi, int s, int x, int y,
-                                                   int z, R inv_scale, R rho0, bool walls, R (&f)[NQ]) {
+                                                   int z, R inv_scale, R rho0, bool walls, R (&f)[Q]) {
         if (cv == CV_ODD) pull<CV_ODD>(B, fi, s, x, y, z, inv_scale, rho0, walls, f);
         else if (cv == CV_EVEN) pull<CV_EVEN>(B, fi, s, x, y, z, inv_scale, rho0, walls, f);
         else pull<CV_PULL>(B, fi, s, x, y, z, inv_scale, rho0, walls, f);
@@ -78,12 +78,12 @@ struct Pull {
 // collide-stream variant then rounds identically, so results never depend on
 // which variant the tuner picked (the kernel is bandwidth-bound; the extra
 // multiply-adds cost nothing measurable).
-template <typename R, int COLL>
-__device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf, R g0, R g1, R g2) {
+template <typename R, int COLL, int Q>
+__device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf, R g0, R g1, R g2) {
 #pragma clang fp contract(off)
     R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
         drho += f[i];
         if (cx(i)) jx += cx(i) * f[i];
         if (cy(i)) jy += cy(i) * f[i];
@@ -95,22 +95,22 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
     const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
     if (COLL == 0) {  // BGK
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < Q; ++i) {
             const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
-            const R feq = R(wgt(i)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - usq));
+            const R feq = R(wgt<Q>(i)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - usq));
             f[i] = f[i] - om * (f[i] - feq);
         }
     } else if (COLL == 1) {  // TRT
         {
-            const R feq = R(wgt(0)) * (drho - rho * usq);
+            const R feq = R(wgt<Q>(0)) * (drho - rho * usq);
             f[0] = f[0] - om * (f[0] - feq);
         }
 #pragma unroll
-        for (int i = 1; i < NQ; i += 2) {
+        for (int i = 1; i < Q; i += 2) {
             const int o = i + 1;
             const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
-            const R ep = R(wgt(i)) * (drho + rho * (R(4.5) * cu * cu - usq));
-            const R em = R(wgt(i)) * rho * R(3) * cu;
+            const R ep = R(wgt<Q>(i)) * (drho + rho * (R(4.5) * cu * cu - usq));
+            const R em = R(wgt<Q>(i)) * rho * R(3) * cu;
             const R fp = R(0.5) * (f[i] + f[o]), fm = R(0.5) * (f[i] - f[o]);
             const R a = om * (fp - ep), b = omm * (fm - em);
             f[i] = f[i] - a - b;
@@ -119,7 +119,7 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
     } else {  // hydrodynamic modes relaxed with tau, ghost modes to equilibrium
         R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
-        for (int i = 1; i < NQ; ++i) {
+        for (int i = 1; i < Q; ++i) {
             if (cx(i)) pxx += f[i];
             if (cy(i)) pyy += f[i];
             if (cz(i)) pzz += f[i];
@@ -137,7 +137,7 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
         const R xyz = rho * uy * uz + k1 * (pyz - rho * uy * uz);
         const R tr3 = (xxx + xyy + xzz) * R(1.0 / 3.0);
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < Q; ++i) {
             const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
             R cxc = 0;
             if (cx(i)) cxc += xxx;
@@ -146,19 +146,19 @@ __device__ __forceinline__ void collide(R (&f)[NQ], R rho0, R om, R omm, bool cf
             if (cx(i) && cy(i)) cxc += R(2 * cx(i) * cy(i)) * xxy;
             if (cx(i) && cz(i)) cxc += R(2 * cx(i) * cz(i)) * xxz;
             if (cy(i) && cz(i)) cxc += R(2 * cy(i) * cz(i)) * xyz;
-            f[i] = R(wgt(i)) * (drho + R(3) * rho * cu + R(4.5) * (cxc - tr3));
+            f[i] = R(wgt<Q>(i)) * (drho + R(3) * rho * cu + R(4.5) * (cxc - tr3));
         }
     }
     if (cf) {  // uniform counter-force, w_i (c_i . g) / c_s^2
 #pragma unroll
-        for (int i = 1; i < NQ; ++i)
-            f[i] += R(3.0 * wgt(i)) * rho0 * (R(cx(i)) * g0 + R(cy(i)) * g1 + R(cz(i)) * g2);
+        for (int i = 1; i < Q; ++i)
+            f[i] += R(3.0 * wgt<Q>(i)) * rho0 * (R(cx(i)) * g0 + R(cy(i)) * g1 + R(cz(i)) * g2);
     }
 }
 
 // One site of the generic tile kernel: read the pre-collision populations
 // (convention CIN), collide, store the post-collision ones (convention COUT).
-template <int ST, int COLL, bool WALLS, bool NT, int CIN, int COUT>
+template <int ST, int COLL, bool WALLS, bool NT, int CIN, int COUT, int Q>
 __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
                                             const typename Store<ST>::T* fin, typename Store<ST>::T* fout,
                                             const KParams& kp, int tile, uint32_t step) {
@@ -173,8 +173,8 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     const bool walls = WALLS && B.walls;
     if (walls && (y == 0 || y == ny - 1)) return;
     const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
-    R f[NQ];
-    Pull<ST>::template pull<CIN>(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
+    R f[Q];
+    Pull<ST, Q>::template pull<CIN>(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
     R g0 = 0, g1 = 0, g2 = 0;
     const bool cf = B.counterforce != 0;
     if (cf) {  // uniform force density on all matter of the box (fluid and particles)
@@ -183,7 +183,7 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
         g1 = (R)(-B.fext[1] / nall);
         g2 = (R)(-B.fext[2] / nall);
     }
-    collide<R, COLL>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
+    collide<R, COLL, Q>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
     typename S::T* fo = fout + B.foff;
     // the dither is a function of (node, direction, step) in every convention
     const uint32_t seed = ST >= ST_F16 ? dither_seed((uint32_t)s, step) : 0u;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     const int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
     const int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
         const uint32_t r = ST >= ST_F16 ? dither_bits(seed, i) : 0u;
         long long off;
         if (COUT == CV_ODD) {  // scattered to the node it streams to
@@ -223,7 +223,7 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
 // Without XCD, block b takes virtual blocks b, b + grid, ...  NT: stores that
 // do not allocate in the caches.  The near-set parts (part 1, 2) use SPT = 1
 // and the plain order only.
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT>
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int Q>
 __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restrict__ boxes,
                                                          const BoxRT* __restrict__ rt,
                                                          const int* __restrict__ tile_box,
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
         } else if (nflags[tile] == epoch) {
             return;
         }
-        site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL>(boxes, tile_box, fin, fout, kp, tile, step);
+        site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL, Q>(boxes, tile_box, fin, fout, kp, tile, step);
         return;
     }
     const int nvb = (ntiles + SPT - 1) / SPT;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             const int tile = v * SPT + k;
-            if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL>(boxes, tile_box, fin, fout, kp, tile, step);
+            if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL, Q>(boxes, tile_box, fin, fout, kp, tile, step);
         }
     }
 }
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
 // and scatter to the neighbours).  Every slot is read and written by one
 // thread only, so no block depends on another.  Block order as the generic
 // kernel's; wall rows are not updated.
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int CIN>
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int CIN, int Q>
 __global__ __launch_bounds__(TILE) void k_collide_stream_aa(const BoxDesc* __restrict__ boxes,
                                                             const int* __restrict__ tile_box,
                                                             typename Store<ST>::T* __restrict__ f, KParams kp,
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream_aa(const BoxDesc* __res
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             const int tile = v * SPT + k;
-            if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CIN, COUT>(boxes, tile_box, f, f, kp, tile, step);
+            if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CIN, COUT, Q>(boxes, tile_box, f, f, kp, tile, step);
         }
     }
 }
@@ -312,7 +312,8 @@ __global__ __launch_bounds__(TILE) void k_collide_stream_aa(const BoxDesc* __res
 // permutation of the slots (post_slot is one-to-one per direction), exact.
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_relayout(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
-                                                   const T* __restrict__ src, T* __restrict__ dst, int cs, int cd) {
+                                                   const T* __restrict__ src, T* __restrict__ dst, int cs, int cd,
+                                                   int q) {
     const int tile = blockIdx.x;
     const BoxDesc& B = boxes[tile_box[tile]];
     const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(TILE) void k_relayout(const BoxDesc* __restrict__ b
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < q; ++i) {
         int ds, ss, dd, sd;
         post_slot(cs, i, x, y, z, nx, ny, nz, ds, ss);
         post_slot(cd, i, x, y, z, nx, ny, nz, dd, sd);
@@ -379,7 +380,7 @@ __device__ __forceinline__ void st_vec(T* p, R scl, const R (&v)[K], const uint3
         *reinterpret_cast<V*>(p) = x;
 }
 
-template <int ST, int COLL, bool WALLS, int K, bool NT>
+template <int ST, int COLL, bool WALLS, int K, bool NT, int Q>
 __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __restrict__ boxes,
                                                              const BoxRT* __restrict__ rt, int bi,
                                                              const typename Store<ST>::T* __restrict__ fin,
@@ -422,9 +423,9 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
     const int x0 = K * lane;
     const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
     const int up = (lane + 63) & 63, dn = (lane + 1) & 63;
-    R f[K][NQ];
+    R f[K][Q];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
         const int sy = cy(i) == 1 ? ym : (cy(i) == -1 ? yp : y);
         const int sz = cz(i) == 1 ? zm : (cz(i) == -1 ? zp : z);
         R v[K];
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
             const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
             ld_vec<T, R, K, ST>(fi + (long long)opp(i) * st + (long long)nx * (y + ny * z) + x0, inv, v);
 #pragma unroll
-            for (int j = 0; j < K; ++j) f[j][i] = v[j] + (R)(6.0 * wgt(i)) * rho0 * cu;
+            for (int j = 0; j < K; ++j) f[j][i] = v[j] + (R)(6.0 * wgt<Q>(i)) * rho0 * cu;
             continue;
         }
         ld_vec<T, R, K, ST>(fi + (long long)i * st + (long long)nx * (sy + ny * sz) + x0, inv, v);
@@ -460,13 +461,13 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
         g2 = (R)(-B.fext[2] / nall);
     }
 #pragma unroll
-    for (int j = 0; j < K; ++j) collide<R, COLL>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
+    for (int j = 0; j < K; ++j) collide<R, COLL, Q>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
     T* fo = fout + B.foff + (long long)nx * (y + ny * z) + x0;
     uint32_t seed[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) seed[j] = ST >= ST_F16 ? dither_seed((uint32_t)(nx * (y + ny * z) + x0 + j), step) : 0u;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
         R v[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) v[j] = f[j][i];
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
 // Initial state: every slot holds the pre-collision population its reader
 // pulls at the first step, f_eq(rho0, u0) plus the first-order
 // non-equilibrium part of the Couette profile (zero at rest).
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(TILE) void k_init(const BoxDesc* __restrict__ boxes,
                                                const int* __restrict__ tile_box,
                                                typename Store<ST>::T* __restrict__ f0,
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(TILE) void k_init(const BoxDesc* __restrict__ boxes
         for (int k = 0; k < 3; ++k) gr[k] = (B.wall_hi[k] - B.wall_lo[k]) / H;
     const double tau = 1.0 / kp.omega, rho0 = kp.rho0;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
         // reader of slot (s, i) is node s + c_i
         int yd = y + cy(i);
         double val = 0.0;
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(TILE) void k_init(const BoxDesc* __restrict__ boxes
             const double cu = cx(j) * u[0] + cy(j) * u[1] + cz(j) * u[2];
             const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
             const double qg = cy(j) * (cx(j) * gr[0] + cz(j) * gr[2]);
-            return wgt(j) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) - tau * wgt(j) * rho0 * 3.0 * qg;
+            return wgt<Q>(j) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu) - tau * wgt<Q>(j) * rho0 * 3.0 * qg;
         };
         if (!wall_here) {
             if (B.walls && (yd == 0 || yd == ny - 1)) {
@@ -518,7 +519,7 @@ __global__ __launch_bounds__(TILE) void k_init(const BoxDesc* __restrict__ boxes
                 const int o = opp(i);
                 const double* uw = yd == 0 ? B.wall_lo : B.wall_hi;
                 const double cu = cx(o) * uw[0] + cy(o) * uw[1] + cz(o) * uw[2];
-                val = dev(o, y) - 6.0 * wgt(o) * rho0 * cu;
+                val = dev(o, y) - 6.0 * wgt<Q>(o) * rho0 * cu;
             } else {
                 val = dev(i, wrap(yd, ny));
             }
@@ -533,7 +534,7 @@ __global__ __launch_bounds__(TILE) void k_init(const BoxDesc* __restrict__ boxes
 
 // Pre-collision density / velocity of fluid sites of one box, for a chunk of
 // sites [s0, s0 + count): out[4*k] = rho, out[4*k+1..3] = u (zeros elsewhere).
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(TILE) void k_fields(const BoxDesc* __restrict__ boxes, int bi,
                                                  const uint16_t* __restrict__ omap,
                                                  const typename Store<ST>::T* __restrict__ fin,
@@ -548,11 +549,11 @@ __global__ __launch_bounds__(TILE) void k_fields(const BoxDesc* __restrict__ box
     if (omap[B.ooff + s] == 0) {
         const int nx = B.nx, ny = B.ny;
         const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
-        R f[NQ];
-        Pull<ST>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        R f[Q];
+        Pull<ST, Q>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
         double d = 0, j[3] = {0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < Q; ++i) {
             d += (double)f[i];
             j[0] += cx(i) * (double)f[i];
             j[1] += cy(i) * (double)f[i];
@@ -573,7 +574,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // Per-block sums over fluid sites: [count, sum(d rho), j_x, j_y, j_z, non-finite].
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(TILE) void k_moments(const BoxDesc* __restrict__ boxes, int bi,
                                                   const uint16_t* __restrict__ omap,
                                                   const typename Store<ST>::T* __restrict__ fin,
@@ -585,11 +586,11 @@ __global__ __launch_bounds__(TILE) void k_moments(const BoxDesc* __restrict__ bo
     if (s < B.n && omap[B.ooff + s] == 0) {
         const int nx = B.nx, ny = B.ny;
         const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
-        R f[NQ];
-        Pull<ST>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        R f[Q];
+        Pull<ST, Q>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
         v[0] = 1.0;
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
+        for (int i = 0; i < Q; ++i) {
             const double fi = (double)f[i];
             if (!isfinite(fi)) v[5] += 1.0;
             v[1] += fi;
@@ -652,7 +653,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int block
             hipLaunchKernelGGL(KERNEL, G, B, 0, ST, __VA_ARGS__);                          \
     } while (0)
 
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT>
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int Q>
 static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
     const int nvb = (a.ntiles + SPT - 1) / SPT;
@@ -661,67 +662,87 @@ static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     else if (XCD) g = 8 * (a.grid > 0 ? std::max(1, a.grid / 8) : (nvb + 7) / 8);
     else g = a.grid > 0 ? std::min(a.grid, nvb) : nvb;
     if (g == 0 || a.ntiles == 0) return hipSuccess;
-    K1_LAUNCH((k_collide_stream<ST, COLL, WALLS, SPT, XCD, NT>), dim3(g), dim3(TILE), st, a.boxes, a.rt, a.tile_box,
-              (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch,
-              a.next_count, a.ntiles, a.step_in, a.step_out);
+    K1_LAUNCH((k_collide_stream<ST, COLL, WALLS, SPT, XCD, NT, Q>), dim3(g), dim3(TILE), st, a.boxes, a.rt,
+              a.tile_box, (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count,
+              a.near_epoch, a.next_count, a.ntiles, a.step_in, a.step_out);
     return hipGetLastError();
 }
 
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT>
+template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int Q>
 static hipError_t aa_one(const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
     const int nvb = (a.ntiles + SPT - 1) / SPT;
     const int g = XCD ? 8 * ((nvb + 7) / 8) : nvb;
     if (a.ntiles == 0) return hipSuccess;
     if (a.kp.conv == CV_ODD)
-        K1_LAUNCH((k_collide_stream_aa<ST, COLL, WALLS, SPT, XCD, NT, CV_ODD>), dim3(g), dim3(TILE), st, a.boxes,
+        K1_LAUNCH((k_collide_stream_aa<ST, COLL, WALLS, SPT, XCD, NT, CV_ODD, Q>), dim3(g), dim3(TILE), st, a.boxes,
                   a.tile_box, (T*)a.fout, a.kp, a.ntiles, a.step_in, a.step_out);
     else if (a.kp.conv == CV_EVEN)
-        K1_LAUNCH((k_collide_stream_aa<ST, COLL, WALLS, SPT, XCD, NT, CV_EVEN>), dim3(g), dim3(TILE), st, a.boxes,
+        K1_LAUNCH((k_collide_stream_aa<ST, COLL, WALLS, SPT, XCD, NT, CV_EVEN, Q>), dim3(g), dim3(TILE), st, a.boxes,
                   a.tile_box, (T*)a.fout, a.kp, a.ntiles, a.step_in, a.step_out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-template <int ST, int COLL, bool WALLS>
+// D3Q27 takes the one-tile-per-block shapes only (plain or XCD-chunked, pull
+// or in place); the tuner offers no other.
+template <int ST, int COLL, bool WALLS, int Q>
 static hipError_t cs_shape(const LaunchCS& a, hipStream_t st) {
-    if (a.aa) {
-        switch (a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0)) {
-            case 4: return aa_one<ST, COLL, WALLS, 1, false, false>(a, st);
-            case 6: return aa_one<ST, COLL, WALLS, 1, true, false>(a, st);
-            case 7: return aa_one<ST, COLL, WALLS, 1, true, true>(a, st);
-            case 10: return aa_one<ST, COLL, WALLS, 2, true, false>(a, st);
+    const int key = a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0);
+    if constexpr (Q == 27) {
+        if (a.part != 0) return hipErrorInvalidValue;
+        switch (key) {
+            case 4: return a.aa ? aa_one<ST, COLL, WALLS, 1, false, false, Q>(a, st)
+                                : cs_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
+            case 6: return a.aa ? aa_one<ST, COLL, WALLS, 1, true, false, Q>(a, st)
+                                : cs_one<ST, COLL, WALLS, 1, true, false, Q>(a, st);
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (a.aa) {
+            switch (key) {
+                case 4: return aa_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
+                case 6: return aa_one<ST, COLL, WALLS, 1, true, false, Q>(a, st);
+                case 7: return aa_one<ST, COLL, WALLS, 1, true, true, Q>(a, st);
+                case 10: return aa_one<ST, COLL, WALLS, 2, true, false, Q>(a, st);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
+        switch (key) {
+            case 4: return cs_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
+            case 6: return cs_one<ST, COLL, WALLS, 1, true, false, Q>(a, st);
+            case 7: return cs_one<ST, COLL, WALLS, 1, true, true, Q>(a, st);
+            case 8: return cs_one<ST, COLL, WALLS, 2, false, false, Q>(a, st);
+            case 10: return cs_one<ST, COLL, WALLS, 2, true, false, Q>(a, st);
+            case 11: return cs_one<ST, COLL, WALLS, 2, true, true, Q>(a, st);
+            case 18: return cs_one<ST, COLL, WALLS, 4, true, false, Q>(a, st);
             default: return hipErrorInvalidValue;
         }
     }
-    if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false, false>(a, st);
-    switch (a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0)) {
-        case 4: return cs_one<ST, COLL, WALLS, 1, false, false>(a, st);
-        case 6: return cs_one<ST, COLL, WALLS, 1, true, false>(a, st);
-        case 7: return cs_one<ST, COLL, WALLS, 1, true, true>(a, st);
-        case 8: return cs_one<ST, COLL, WALLS, 2, false, false>(a, st);
-        case 10: return cs_one<ST, COLL, WALLS, 2, true, false>(a, st);
-        case 11: return cs_one<ST, COLL, WALLS, 2, true, true>(a, st);
-        case 18: return cs_one<ST, COLL, WALLS, 4, true, false>(a, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
-template <int ST, int COLL>
+template <int ST, int COLL, int Q>
 static hipError_t cs_walls(bool walls, const LaunchCS& a, hipStream_t st) {
-    return walls ? cs_shape<ST, COLL, true>(a, st) : cs_shape<ST, COLL, false>(a, st);
+    return walls ? cs_shape<ST, COLL, true, Q>(a, st) : cs_shape<ST, COLL, false, Q>(a, st);
+}
+
+template <int ST, int Q>
+static hipError_t cs_coll(const LaunchCS& a, hipStream_t st) {
+    switch (a.kp.collision) {
+        case 0: return cs_walls<ST, 0, Q>(a.walls, a, st);
+        case 1: return cs_walls<ST, 1, Q>(a.walls, a, st);
+        default: return cs_walls<ST, 2, Q>(a.walls, a, st);
+    }
 }
 
 template <int ST>
-static hipError_t cs_coll(const LaunchCS& a, hipStream_t st) {
-    switch (a.kp.collision) {
-        case 0: return cs_walls<ST, 0>(a.walls, a, st);
-        case 1: return cs_walls<ST, 1>(a.walls, a, st);
-        default: return cs_walls<ST, 2>(a.walls, a, st);
-    }
+static hipError_t cs_lat(const LaunchCS& a, hipStream_t st) {
+    return a.kp.q == 27 ? cs_coll<ST, 27>(a, st) : cs_coll<ST, 19>(a, st);
 }
 
+// row-wave kernel: D3Q19 only
 template <int ST, int COLL, int K, bool NT>
 static hipError_t rows_launch(bool walls, const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
@@ -729,13 +750,13 @@ static hipError_t rows_launch(bool walls, const LaunchCS& a, hipStream_t st) {
     dim3 grid(a.part == 2 ? a.near_grid : (rows + 3) / 4), blk(256);
     if (grid.x == 0) return hipSuccess;
     if (walls)
-        K1_LAUNCH((k_collide_stream_rows<ST, COLL, true, K, NT>), grid, blk, st, a.boxes, a.rt, 0, (const T*)a.fin,
-                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count,
-                  a.step_in, a.step_out);
+        K1_LAUNCH((k_collide_stream_rows<ST, COLL, true, K, NT, 19>), grid, blk, st, a.boxes, a.rt, 0,
+                  (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch,
+                  a.next_count, a.step_in, a.step_out);
     else
-        K1_LAUNCH((k_collide_stream_rows<ST, COLL, false, K, NT>), grid, blk, st, a.boxes, a.rt, 0, (const T*)a.fin,
-                  (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch, a.next_count,
-                  a.step_in, a.step_out);
+        K1_LAUNCH((k_collide_stream_rows<ST, COLL, false, K, NT, 19>), grid, blk, st, a.boxes, a.rt, 0,
+                  (const T*)a.fin, (T*)a.fout, a.kp, a.part, a.near_flags, a.near_list, a.near_count, a.near_epoch,
+                  a.next_count, a.step_in, a.step_out);
     return hipGetLastError();
 }
 
@@ -760,7 +781,9 @@ static hipError_t rows_coll(const LaunchCS& a, hipStream_t st) {
 
 hipError_t launch_collide_stream(const LaunchCS& a, hipStream_t st) {
     if (a.aa && (a.fin != a.fout || a.part != 0 || a.variant != 0)) return hipErrorInvalidValue;
+    if (a.kp.q != 19 && a.kp.q != 27) return hipErrorInvalidValue;
     if (a.variant != 0 && a.rows_k > 0) {
+        if (a.kp.q != 19) return hipErrorInvalidValue;
         switch (a.kp.storage) {
             case ST_F64: return rows_coll<ST_F64>(a, st);
             case ST_F32: return rows_coll<ST_F32>(a, st);
@@ -769,10 +792,10 @@ hipError_t launch_collide_stream(const LaunchCS& a, hipStream_t st) {
         }
     }
     switch (a.kp.storage) {
-        case ST_F64: return cs_coll<ST_F64>(a, st);
-        case ST_F32: return cs_coll<ST_F32>(a, st);
-        case ST_F16: return cs_coll<ST_F16>(a, st);
-        default: return cs_coll<ST_BF16>(a, st);
+        case ST_F64: return cs_lat<ST_F64>(a, st);
+        case ST_F32: return cs_lat<ST_F32>(a, st);
+        case ST_F16: return cs_lat<ST_F16>(a, st);
+        default: return cs_lat<ST_BF16>(a, st);
     }
 }
 
@@ -788,8 +811,12 @@ hipError_t launch_init(const BoxDesc* boxes, const int* tile_box, int ntiles, vo
                        const int* box_init, const KParams& kp, hipStream_t st) {
     LB_DISPATCH_ST(kp.storage, {
         using T = typename Store<SS>::T;
-        hipLaunchKernelGGL((k_init<SS>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, (T*)f0, (T*)f1,
-                           box_init, kp);
+        if (kp.q == 27)
+            hipLaunchKernelGGL((k_init<SS, 27>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, (T*)f0, (T*)f1,
+                               box_init, kp);
+        else
+            hipLaunchKernelGGL((k_init<SS, 19>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, (T*)f0, (T*)f1,
+                               box_init, kp);
     });
     return hipGetLastError();
 }
@@ -799,8 +826,12 @@ hipError_t launch_fields(const BoxDesc* boxes, int bi, const uint16_t* omap, con
     const int nb = (count + TILE - 1) / TILE;
     LB_DISPATCH_ST(kp.storage, {
         using T = typename Store<SS>::T;
-        hipLaunchKernelGGL((k_fields<SS>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin, s0,
-                           count, out, kp);
+        if (kp.q == 27)
+            hipLaunchKernelGGL((k_fields<SS, 27>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin, s0,
+                               count, out, kp);
+        else
+            hipLaunchKernelGGL((k_fields<SS, 19>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin, s0,
+                               count, out, kp);
     });
     return hipGetLastError();
 }
@@ -810,25 +841,29 @@ hipError_t launch_moments(const BoxDesc* boxes, int bi, int n, const uint16_t* o
     const int nb = (n + TILE - 1) / TILE;
     LB_DISPATCH_ST(kp.storage, {
         using T = typename Store<SS>::T;
-        hipLaunchKernelGGL((k_moments<SS>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin,
-                           partial, kp);
+        if (kp.q == 27)
+            hipLaunchKernelGGL((k_moments<SS, 27>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin,
+                               partial, kp);
+        else
+            hipLaunchKernelGGL((k_moments<SS, 19>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin,
+                               partial, kp);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_relayout(const BoxDesc* boxes, const int* tile_box, int ntiles, const void* src, void* dst, int cs,
-                           int cd, int storage, hipStream_t st) {
+                           int cd, int storage, int q, hipStream_t st) {
     if (src == dst) return hipErrorInvalidValue;
     const int es = storage_bytes(storage);
     if (es == 8)
         hipLaunchKernelGGL((k_relayout<unsigned long long>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                           (const unsigned long long*)src, (unsigned long long*)dst, cs, cd);
+                           (const unsigned long long*)src, (unsigned long long*)dst, cs, cd, q);
     else if (es == 4)
         hipLaunchKernelGGL((k_relayout<uint32_t>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                           (const uint32_t*)src, (uint32_t*)dst, cs, cd);
+                           (const uint32_t*)src, (uint32_t*)dst, cs, cd, q);
     else
         hipLaunchKernelGGL((k_relayout<uint16_t>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                           (const uint16_t*)src, (uint16_t*)dst, cs, cd);
+                           (const uint16_t*)src, (uint16_t*)dst, cs, cd, q);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@
 // nodes, and nodes inside particle p move rigidly with its U, Omega.  Every
 // node gets the second-order equilibrium at rho0 and its velocity, written as
 // pre-collision populations (slot (x - c_i, i)).
+#include <type_traits>
+
 #include "lbell_dev.h"
 #include "lbell_launch.h"
 
@@ -347,7 +349,7 @@ __global__ void k_stokes_mean(const BoxDesc* __restrict__ boxes, int nboxes, con
     for (int k = 0; k < 3; ++k) ubar[3 * b + k] = S[3] > 0 ? S[k] / S[3] : 0.0;
 }
 
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict__ boxes,
                                                        const int* __restrict__ tile_box,
                                                        const uint16_t* __restrict__ omap,
@@ -372,9 +374,9 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     const double rho0 = kp.rho0, uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     typename S::T* fb = f + B.foff;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-        const double dev = wgt(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const double dev = wgt<Q>(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         // the slot node (x, y, z) reads f_i from at the next step (no walls here)
         int d, slot;
         pre_slot_open(kp.conv, i, x, y, z, nx, ny, nz, d, slot);
@@ -419,23 +421,28 @@ hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile
                        partial);
     hipLaunchKernelGGL(k_stokes_mean, dim3((nboxes + 63) / 64), dim3(64), 0, st, boxes, nboxes, parts, np, partial,
                        kp.rho0, ubar);
-    switch (kp.storage) {
-        case ST_F64:
-            hipLaunchKernelGGL((k_stokes_write<ST_F64>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, mu, C, ubar, (double*)f, kp);
-            break;
-        case ST_F32:
-            hipLaunchKernelGGL((k_stokes_write<ST_F32>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, mu, C, ubar, (float*)f, kp);
-            break;
-        case ST_F16:
-            hipLaunchKernelGGL((k_stokes_write<ST_F16>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, mu, C, ubar, (typename Store<ST_F16>::T*)f, kp);
-            break;
-        default:
-            hipLaunchKernelGGL((k_stokes_write<ST_BF16>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
-                               parts, np, mu, C, ubar, (typename Store<ST_BF16>::T*)f, kp);
-    }
+    auto write = [&](auto q) {
+        constexpr int Q = decltype(q)::value;
+        switch (kp.storage) {
+            case ST_F64:
+                hipLaunchKernelGGL((k_stokes_write<ST_F64, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                                   omap, parts, np, mu, C, ubar, (double*)f, kp);
+                break;
+            case ST_F32:
+                hipLaunchKernelGGL((k_stokes_write<ST_F32, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                                   omap, parts, np, mu, C, ubar, (float*)f, kp);
+                break;
+            case ST_F16:
+                hipLaunchKernelGGL((k_stokes_write<ST_F16, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                                   omap, parts, np, mu, C, ubar, (typename Store<ST_F16>::T*)f, kp);
+                break;
+            default:
+                hipLaunchKernelGGL((k_stokes_write<ST_BF16, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
+                                   omap, parts, np, mu, C, ubar, (typename Store<ST_BF16>::T*)f, kp);
+        }
+    };
+    if (kp.q == 27) write(std::integral_constant<int, 27>{});
+    else write(std::integral_constant<int, 19>{});
     return hipGetLastError();
 }
 

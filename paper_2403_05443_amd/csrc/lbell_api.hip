@@ -37,10 +37,11 @@ struct Layout {
     size_t scratch_bytes = 0;
 };
 
-long long link_cap_for(double amax) {
-    // 16 links per unit of the circumscribed sphere's area plus a floor: the
-    // discrete surface carries about 5.5 links per unit area
-    return (long long)(16.0 * 4.0 * M_PI * amax * amax) + 1024;
+long long link_cap_for(double amax, int q) {
+    // 16 (D3Q19) or 24 (D3Q27) links per unit of the circumscribed sphere's
+    // area plus a floor: the discrete surface carries about 5.5 (D3Q19) or
+    // 9 (D3Q27) links per unit area
+    return (long long)((q == 27 ? 24.0 : 16.0) * 4.0 * M_PI * amax * amax) + 1024;
 }
 
 int lds_words_for(double amax) {
@@ -56,7 +57,7 @@ bool valid_cfg(const lb_config* c, int nboxes, const lb_box* boxes, std::string*
         return false;
     };
     if (!c || !boxes || nboxes <= 0) return bad("null config / boxes or nboxes <= 0");
-    if (c->lattice != 19) return bad("only the D3Q19 lattice is implemented");
+    if (c->lattice != 19 && c->lattice != 27) return bad("lattice must be 19 (D3Q19) or 27 (D3Q27)");
     if (c->collision < 0 || c->collision > 2) return bad("unknown collision");
     if (!(c->tau > 0.5)) return bad("tau must exceed 1/2");
     if (c->collision == LB_TRT && !(c->magic > 0)) return bad("TRT needs magic > 0");
@@ -89,7 +90,7 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
         const long long stride = (long long)align_up((size_t)n, 64) + 64;
         L.foff.push_back(off);
         L.stride.push_back(stride);
-        off += (long long)align_up((size_t)(NQ * stride), 128);
+        off += (long long)align_up((size_t)(c->lattice * stride), 128);
         L.ooff.push_back(ooff);
         ooff += (long long)align_up((size_t)n, 128);
         const int nt = (int)((n + TILE - 1) / TILE);
@@ -102,7 +103,7 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     L.omap_elems = ooff;
     L.total_tiles = tiles;
     L.max_particles = c->max_particles > 0 ? c->max_particles : nboxes;
-    L.link_pool = (long long)L.max_particles * link_cap_for(c->max_semi_axis);
+    L.link_pool = (long long)L.max_particles * link_cap_for(c->max_semi_axis, c->lattice);
     L.lds_words = lds_words_for(c->max_semi_axis);
     L.scratch_bytes = std::max(maxpart, (size_t)FIELDS_CHUNK * 4 * sizeof(double));
     size_t p = 0;
@@ -224,6 +225,8 @@ constexpr int K1_NSHAPES = (int)(sizeof(K1_SHAPES) / sizeof(K1_SHAPES[0]));
 
 bool k1_applicable(const lb_ctx* ctx, int v) {
     if (v < 0 || v >= K1_NSHAPES) return false;
+    // D3Q27: one tile per block, plain or XCD-chunked, pull or in place
+    if (ctx->cfg.lattice == 27 && v != 0 && v != 3 && v != 11 && v != 12) return false;
     if (K1_SHAPES[v].kind != 0 && ctx->rows_k == 0) return false;
     if (ctx->overlap && v > 2) return false;
     return true;
@@ -403,6 +406,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
     kp.rho0 = cfg->rho0;
     kp.collision = cfg->collision;
     kp.storage = cfg->storage;
+    kp.q = cfg->lattice;
     int e = 0;
     if (cfg->storage == LB_FP16 || cfg->storage == LB_BF16) {
         e = cfg->scale_log2;
@@ -478,7 +482,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
     }
     // collide-stream variant: the row-wave kernel needs a single box whose x
     // edge is 64, 128 or 256 sites
-    if (nboxes == 1 && (boxes[0].nx == 64 || boxes[0].nx == 128 || boxes[0].nx == 256)) {
+    if (nboxes == 1 && cfg->lattice == 19 && (boxes[0].nx == 64 || boxes[0].nx == 128 || boxes[0].nx == 256)) {
         ctx->rows_k = boxes[0].nx / 64;
         ctx->k1_variant = 1;
     }
@@ -537,7 +541,7 @@ lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const d
     if (amax > ctx->cfg.max_semi_axis) return fail(ctx, LB_EINVAL, "semi-axis above cfg.max_semi_axis");
     const double nq = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
     if (!(std::fabs(nq - 1.0) <= 1e-6)) return fail(ctx, LB_EINVAL, "quaternion is not unit");
-    const long long cap = link_cap_for(amax);
+    const long long cap = link_cap_for(amax, ctx->cfg.lattice);
     if (ctx->link_used + cap > ctx->L.link_pool) return fail(ctx, LB_ENOMEM, "link pool exhausted");
     PartDev P;
     std::memset(&P, 0, sizeof P);
@@ -777,7 +781,7 @@ lb_status switch_layout(lb_ctx* ctx, bool to_aa) {
     const int src_buf = ctx->aa ? ctx->aa_buf : ctx->cur, dst_buf = src_buf ^ 1;
     HIPC(launch_relayout(ctx->at<BoxDesc>(ctx->L.boxes), ctx->at<int>(ctx->L.tile_box), ctx->L.total_tiles,
                          ctx->arena + (src_buf ? ctx->L.f1 : ctx->L.f0), ctx->arena + (dst_buf ? ctx->L.f1 : ctx->L.f0),
-                         ctx->kp.conv, to_aa ? CV_EVEN : CV_PULL, ctx->cfg.storage, ctx->stream));
+                         ctx->kp.conv, to_aa ? CV_EVEN : CV_PULL, ctx->cfg.storage, ctx->cfg.lattice, ctx->stream));
     ctx->aa = to_aa;
     ctx->aa_buf = dst_buf;
     const int c = to_aa ? 1 : dst_buf;
@@ -1221,7 +1225,7 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
 }
 
 lb_status lb_debug_poke(lb_ctx* ctx, int box, int site, int dir, double value) {
-    if (!ctx || box < 0 || box >= (int)ctx->boxes.size() || dir < 0 || dir >= NQ) return LB_EINVAL;
+    if (!ctx || box < 0 || box >= (int)ctx->boxes.size() || dir < 0 || dir >= ctx->cfg.lattice) return LB_EINVAL;
     if (site < 0 || site >= ctx->hbox[box].n) return LB_EINVAL;
     HIPC(launch_poke(ctx->at<BoxDesc>(ctx->L.boxes), box, ctx->fbuf(ctx->cur), site, dir, value, ctx->kp,
                      ctx->stream));

@@ -6,7 +6,7 @@
 
 namespace lbd {
 
-constexpr int NQ = 19;
+constexpr int NQMAX = 27;        // velocities of the largest set (D3Q27)
 constexpr int TILE = 256;        // sites per K1 work-group
 constexpr int PBLOCK = 512;      // threads per particle work-group
 constexpr int PWAVES = PBLOCK / 64;
@@ -16,23 +16,42 @@ constexpr int STAGE = 4096;      // link codes staged in LDS per copy-out round
 constexpr int SITE_BITS = 27;    // link code: site | dir << 27
 constexpr uint32_t SITE_MASK = (1u << SITE_BITS) - 1u;
 
-// D3Q19, order fixed by the ABI: rest, 6 axis, 12 diagonal; opposite of odd i is i+1.
+// Velocity sets, order fixed by the ABI (link codes carry it): rest, 6 axis,
+// 12 edge vectors (D3Q19, Q = 19); D3Q27 (Q = 27) appends the 8 corners
+// (1,1,1), (1,1,-1), (1,-1,1), (-1,1,1), each followed by its opposite.  The
+// opposite of odd i is i + 1, so one table serves both sets.
+__host__ __device__ constexpr int corner(int i, int flip) {  // component of corner i >= 19
+    return ((i & 1) ? 1 : -1) * (((i - 19) >> 1) == flip ? -1 : 1);
+}
 __host__ __device__ constexpr int cx(int i) {
-    return i == 1 || i == 7 || i == 9 || i == 11 || i == 13 ? 1
-         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 ? -1 : 0);
+    return i >= 19 ? corner(i, 3)
+         : (i == 1 || i == 7 || i == 9 || i == 11 || i == 13 ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 ? -1 : 0));
 }
 __host__ __device__ constexpr int cy(int i) {
-    return i == 3 || i == 7 || i == 10 || i == 15 || i == 17 ? 1
-         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 ? -1 : 0);
+    return i >= 19 ? corner(i, 2)
+         : (i == 3 || i == 7 || i == 10 || i == 15 || i == 17 ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 ? -1 : 0));
 }
 __host__ __device__ constexpr int cz(int i) {
-    return i == 5 || i == 11 || i == 14 || i == 15 || i == 18 ? 1
-         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0);
+    return i >= 19 ? corner(i, 1)
+         : (i == 5 || i == 11 || i == 14 || i == 15 || i == 18 ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0));
 }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
-// 36 * w_i as an integer (12, 2, 1): link weights in exact integer form
-__host__ __device__ constexpr int w36(int i) { return i == 0 ? 12 : (i <= 6 ? 2 : 1); }
+// weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216
+template <int Q>
+__host__ __device__ constexpr double wgt(int i) {
+    return Q == 27 ? (i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0)))
+                   : (i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0));
+}
+// W w_i as an exact integer: W = 36 for D3Q19 (12, 2, 1), 216 for D3Q27 (64, 16, 4, 1)
+template <int Q>
+constexpr int WSCALE = Q == 27 ? 216 : 36;
+template <int Q>
+__host__ __device__ constexpr int wint(int i) {
+    return Q == 27 ? (i == 0 ? 64 : (i <= 6 ? 16 : (i <= 18 ? 4 : 1))) : (i == 0 ? 12 : (i <= 6 ? 2 : 1));
+}
 
 enum Flags : int {
     F_OVERLAP = 1,      // a node claimed by two particles or a particle and a wall
@@ -87,7 +106,8 @@ struct KParams {
     double scale, inv_scale;  // half formats: stored = scale * deviation
     double rho0;
     int collision, storage;
-    int conv, pad;            // storage convention of the current populations (CV_*)
+    int conv;                 // storage convention of the current populations (CV_*)
+    int q;                    // velocity set: 19 or 27
 };
 
 // Storage conventions of the population array.  The post-collision

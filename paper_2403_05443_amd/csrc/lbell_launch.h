@@ -56,7 +56,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int block
 // Copies every population from its slot in convention cs (src) to its slot in
 // convention cd (dst); src and dst are distinct buffers of the same layout.
 hipError_t launch_relayout(const BoxDesc* boxes, const int* tile_box, int ntiles, const void* src, void* dst, int cs,
-                           int cd, int storage, hipStream_t st);
+                           int cd, int storage, int q, hipStream_t st);
 hipError_t launch_poke(const BoxDesc* boxes, int bi, void* f, int s, int dir, double val, const KParams& kp,
                        hipStream_t st);
 

@@ -156,7 +156,7 @@ class Lattice:
 
     def __init__(self, boxes, collision="bgk", tau=1.0, magic=3.0 / 16.0, storage="fp32",
                  scale_log2=0, velocity_scale=1e-3, counterforce=False, max_particles=0,
-                 max_semi_axis=8.0, device="cuda:0"):
+                 max_semi_axis=8.0, lattice=19, device="cuda:0"):
         import torch
         self.lib = load()
         self.torch = torch
@@ -171,6 +171,7 @@ class Lattice:
         cfg.counterforce = int(bool(counterforce))
         cfg.max_particles = int(max_particles)
         cfg.max_semi_axis = float(max_semi_axis)
+        cfg.lattice = int(lattice)
         self.cfg = cfg
         bl = [b if isinstance(b, Box) else make_box(*b) for b in boxes]
         self.nboxes = len(bl)

@@ -22,7 +22,8 @@ def build_lattice(W, device="cuda:0"):
              for b in W.boxes]
     lat = lbell.Lattice(boxes, collision=W.collision, tau=W.tau, magic=W.magic, storage=W.storage,
                         counterforce=W.counterforce, velocity_scale=W.velocity_scale,
-                        max_particles=max(1, len(W.particles)), max_semi_axis=W.max_semi_axis, device=device)
+                        max_particles=max(1, len(W.particles)), max_semi_axis=W.max_semi_axis,
+                        lattice=W.lattice, device=device)
     for p in W.particles:
         pid = lat.add_ellipsoid(p.centre, p.axes, p.quat, box=p.box)
         lat.set_external(pid, p.force, p.torque)

@@ -85,6 +85,7 @@ class Workload:
     velocity_scale: float = 1e-3
     max_semi_axis: float = 8.0
     notes: dict = field(default_factory=dict)
+    lattice: int = 19
 
     @property
     def sites(self):
@@ -114,16 +115,16 @@ def c1r(storage="fp64"):
                     "bgk", 1.0, storage, 500, counterforce=True, velocity_scale=2e-5)
 
 
-def c2(storage="fp32", L=128):
+def c2(storage="fp32", L=128, lattice=19):
     """L^3 periodic (128 by default), TRT Lambda=3/16 with tau+ = 0.8
     (nu = 0.1), spheroid a=6, b=c=2, long axis at 45 deg to a force 5e-4
-    along z, 20 000 steps."""
+    along z, 20 000 steps; D3Q19, or D3Q27 with lattice=27."""
     # body x -> (sin 45, 0, cos 45): rotation about y by +45 deg maps x -> (cos, 0, -sin)
     q = quat_axis_angle((0.0, 1.0, 0.0), -math.pi / 4)
     c = (L - 1) / 2.0
-    return Workload(f"c2_inclined_{L}", [Box((L, L, L))],
+    return Workload(f"c2_inclined_{L}" + ("_d3q27" if lattice == 27 else ""), [Box((L, L, L))],
                     [Particle((c, c, c), (6.0, 2.0, 2.0), q, force=(0.0, 0.0, 5e-4))],
-                    "trt", 0.8, storage, 20000, counterforce=True, velocity_scale=1e-4)
+                    "trt", 0.8, storage, 20000, counterforce=True, velocity_scale=1e-4, lattice=lattice)
 
 
 def c3(r=3, seed_index=1, storage="fp32"):

@@ -62,7 +62,7 @@ def test_arena_bytes(lib):
     assert lib.lb_arena_bytes(C.byref(_cfg(lib)), 2, two) > 2 * 19 * 4 * (32 ** 3 + 40 * 36 * 44)
 
 
-@pytest.mark.parametrize("field,value", [("tau", 0.5), ("lattice", 27), ("collision", 5), ("storage", 9),
+@pytest.mark.parametrize("field,value", [("tau", 0.5), ("lattice", 15), ("collision", 5), ("storage", 9),
                                          ("rho0", 1.1), ("max_semi_axis", 200.0)])
 def test_invalid_config_sizes_to_zero(lib, field, value):
     from paper_2403_05443_amd.lbell import Box, make_box
