@@ -83,12 +83,12 @@ def _pmc_rows(d):
     return out
 
 
-def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes, variant):
+def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes, variant, lattice=19):
     """HBM bytes per collide-stream launch from FETCH_SIZE and WRITE_SIZE (KiB
     per dispatch), each scaled by what the same counter reads for the copy
     probe of known size."""
     from paper_2403_05443_amd import workloads
-    W = workloads.c2(storage, size)
+    W = workloads.c2(storage, size, lattice=lattice)
     res = {}
     for name, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _pmc_rows(d)
@@ -116,7 +116,7 @@ def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes, variant):
     rec["kernel"] = "k_collide_stream / k_collide_stream_rows"
     rec.setdefault("entries", {})[f"{W.name}/{storage}/v{variant}"] = {
         "fetch": res["fetch"], "write": res["write"],
-        "algorithmic_bytes_per_launch": 38 * BYTES[storage] * W.sites,
+        "algorithmic_bytes_per_launch": 2 * W.lattice * BYTES[storage] * W.sites,
         "traffic_bytes_per_launch": round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]),
     }
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
@@ -156,7 +156,7 @@ def measure(W, steps, warmup, graph_steps, variant=None, psteps=200):
     n = min(steps, psteps)
     ms_c, ms_p = lat.profile_step(n)
     k1 = ms_c / n
-    alg = 38 * BYTES[W.storage] * W.sites
+    alg = 2 * W.lattice * BYTES[W.storage] * W.sites  # Q reads + Q writes per site
     return lat, {
         "mlups": W.sites * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps, "wall_s": wall,
         "variant": variant, "k1_ms": k1, "alg_bytes": alg, "achieved_gbs": alg / (k1 / 1e3) / 1e9,
@@ -209,11 +209,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="fp32", choices=sorted(BYTES))
     ap.add_argument("--size", type=int, default=128, help="box edge of the inclined-spheroid workload")
+    ap.add_argument("--lattice", type=int, default=19, choices=(19, 27),
+                    help="velocity set of the main line (the metric is quoted on D3Q19)")
     ap.add_argument("--graph", type=int, default=50, help="steps per HIP graph replay (0: plain launches)")
     ap.add_argument("--variant", type=int, default=None,
                     help="collide-stream variant to use instead of the tuner's choice (see lb_autotune)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-box FP16 ensemble reported beside the main line (0: skip)")
+    ap.add_argument("--d3q27-steps", type=int, default=500,
+                    help="steps of the same spheroid workload on the D3Q27 lattice (0: skip)")
     ap.add_argument("--suspension-steps", type=int, default=100,
                     help="steps of the 256^3 FP16 suspension of 512 squirmers reported beside the main line (0: skip)")
     ap.add_argument("--surrogate-runs", type=int, default=4,
@@ -231,7 +235,7 @@ def main():
         if args.variant is None:
             raise SystemExit("--summarize-pmc needs the --variant the counter runs used")
         summarize_pmc(*args.summarize_pmc, storage=args.storage, size=args.size, probe_bytes=args.probe_bytes,
-                      variant=args.variant)
+                      variant=args.variant, lattice=args.lattice)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -241,7 +245,7 @@ def main():
     from paper_2403_05443_amd import workloads
     from paper_2403_05443_amd import lbell
     lbell.load()
-    W = workloads.c2(args.storage, args.size)
+    W = workloads.c2(args.storage, args.size, lattice=args.lattice)
     copy_gbs = lbell.bandwidth_probe(args.probe_bytes, reps=5)
     lat, m = measure(W, args.steps, args.warmup, args.graph, variant=args.variant)
     del lat
@@ -260,7 +264,7 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": W.name, "sites": W.sites, "storage": args.storage, "collision": "trt",
+        "config": {"workload": W.name, "sites": W.sites, "lattice": f"D3Q{W.lattice}", "storage": args.storage, "collision": "trt",
                    "tau_plus": W.tau, "lambda": W.magic, "particles": len(W.particles),
                    "graph_steps": args.graph, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
@@ -280,6 +284,17 @@ def main():
                            "k1_achieved_gbs": round(e["achieved_gbs"], 1),
                            "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
                            "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
+    if args.d3q27_steps > 0:
+        Wq = workloads.c2(args.storage, args.size, lattice=27)
+        lat, e = measure(Wq, args.d3q27_steps, 50, args.graph)
+        del lat
+        out["d3q27"] = {"workload": Wq.name, "sites": Wq.sites, "storage": args.storage,
+                        "mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 5),
+                        "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 5),
+                        "k1_bytes_per_launch": e["alg_bytes"], "k1_achieved_gbs": round(e["achieved_gbs"], 1),
+                        "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        "k1_traffic": traffic_record(src_sha, Wq.name, args.storage, e["variant"]),
+                        "phase_ms_per_step": {k: round(v, 5) for k, v in e["phase_ms"].items()}}
     if args.suspension_steps > 0:
         Ws = workloads.c5("fp16")
         lat, e = measure(Ws, args.suspension_steps, 10, args.graph)
