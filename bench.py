@@ -216,6 +216,9 @@ def main():
                     help="collide-stream variant to use instead of the tuner's choice (see lb_autotune)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-box FP16 ensemble reported beside the main line (0: skip)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run the domain-size (32^3-512^3) and resolution studies of the settling spheroid "
+                         "instead of the benchmark and print their results as one JSON line")
     ap.add_argument("--d3q27-steps", type=int, default=500,
                     help="steps of the same spheroid workload on the D3Q27 lattice (0: skip)")
     ap.add_argument("--suspension-steps", type=int, default=100,
@@ -245,6 +248,16 @@ def main():
     from paper_2403_05443_amd import workloads
     from paper_2403_05443_amd import lbell
     lbell.load()
+    if args.sweep_only:
+        from paper_2403_05443_amd import runner
+        t0 = time.perf_counter()
+        out = {"kind": "settling spheroid studies (Sec. III.A, Figs. 4 and 9)", "data": "synthetic",
+               "domain": runner.domain_sweep([32, 64, 128, 256, 512], a=7.5, b=2.5, nu=0.1, storage="fp32"),
+               "resolution": runner.resolution_sweep([2.0, 2.5, 3.0, 4.0], r=3.0),
+               "sphere_array": {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)}}
+        out["seconds"] = round(time.perf_counter() - t0, 1)
+        print(json.dumps(out), flush=True)
+        return
     W = workloads.c2(args.storage, args.size, lattice=args.lattice)
     copy_gbs = lbell.bandwidth_probe(args.probe_bytes, reps=5)
     lat, m = measure(W, args.steps, args.warmup, args.graph, variant=args.variant)

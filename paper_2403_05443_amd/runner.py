@@ -148,6 +148,113 @@ def unbounded_velocities(p, nu):
     return R @ Ub, R @ Wb
 
 
+# --------------------------------------------- domain size and resolution --
+
+def settling_run(W, transient, graph=50, tune=True, sample=50, travel=1.0):
+    """Settling velocity of the single particle of workload W, started from
+    the closed-form control (unbounded velocities and the periodic Stokes
+    start field).  After `transient` steps, U is sampled every `sample` steps
+    over two windows in each of which the particle travels about `travel`
+    lattice spacings: as the particle moves, nodes change side and the
+    velocity jumps by a fraction of a percent (the discrete-shape error of
+    the method), so only a mean over such a window is a settled value.
+    Returns the mean over the last window, its relative change from the
+    window before (drift), the relative spread of the samples in it, and
+    the site updates per second of the last window (graph replay, sampling
+    included)."""
+    import time
+    import torch
+    nu = viscosity(W)
+    p = W.particles[0]
+    lat = build_lattice(W)
+    if tune:
+        lat.autotune(2)  # ordinary steps; the start below replaces fluid and particle velocities
+    U0, W0 = unbounded_velocities(p, nu)
+    force = np.asarray(p.force, float)
+    e = force / np.linalg.norm(force)
+    Uc = float(np.asarray(U0, float) @ e)
+    every = int(math.ceil(travel / abs(Uc) / sample)) * sample
+    lat.set_velocity(0, U0, W0)
+    lat.stokes_start()
+    lat.set_graph(graph if sample % graph == 0 else sample)
+    lat.step(transient)
+
+    def window():
+        us = []
+        for _ in range(every // sample):
+            lat.step(sample)
+            us.append(lat.particles()["U"][0].copy())
+        return np.array(us)
+    Ua = window().mean(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wb = window()
+    dt = time.perf_counter() - t0
+    del lat
+    Ub = wb.mean(0)
+    U = float(Ub @ e)
+    return {"L": W.boxes[0].shape[0], "U": U, "U_closed": Uc, "error": U / Uc - 1,
+            "drift": float(np.linalg.norm(Ub - Ua) / np.linalg.norm(Ub)),
+            "spread": float((wb @ e).std() / abs(U)), "steps": transient + 2 * every,
+            "mlups": W.sites * every / dt / 1e6}
+
+
+def domain_sweep(lengths, a=7.5, b=2.5, nu=0.1, force=2e-3, storage="fp32", transient=None, lattice=19,
+                 orientations=("end-on", "broadside")):
+    """Settling velocity against box edge L for both orientations (Fig. 4),
+    and for each orientation the fit U(L) = U_inf (1 - k / L) over the boxes
+    of edge >= 8a (the leading periodic-image correction), U_inf against the
+    closed form of eq. settlingvel."""
+    transient = transient or int(4 * a * a / nu)
+    out = {}
+    for orient in orientations:
+        rows = [settling_run(workloads.settling(L, a, b, orient, nu, force, storage, lattice), transient)
+                for L in lengths]
+        big = [r for r in rows if r["L"] >= 8 * a] or rows
+        x = np.array([1.0 / r["L"] for r in big])
+        y = np.array([r["U"] for r in big])
+        A = np.vstack([np.ones_like(x), x]).T
+        c0, c1 = np.linalg.lstsq(A, y, rcond=None)[0]
+        out[orient] = {"runs": rows, "U_inf_fit": float(c0), "k_fit": float(-c1 / c0),
+                       "U_closed": rows[0]["U_closed"], "fit_error": float(c0 / rows[0]["U_closed"] - 1)}
+    return out
+
+
+def resolution_sweep(bs, r=3.0, l_over_b=(32, 64), nu=0.1, force=2e-3, storage="fp32",
+                     orientations=("end-on", "broadside"), travel=2.0):
+    """Settling velocity against resolution (Fig. 9): semi-axes (r b, b, b)
+    for b in bs at the same force (so the same Reynolds number
+    F / (6 pi mu nu)), each in two boxes of edge l_over_b * b; the 1/L law
+    through the two removes the periodic images, and the extrapolated
+    velocity, normalized by that of a sphere of radius b (F / (6 pi mu b)),
+    is compared with the closed form of eq. settlingvel."""
+    out = {}
+    for orient in orientations:
+        rows = []
+        for bb in bs:
+            runs = [settling_run(workloads.settling(int(round(m * bb)), r * bb, bb, orient, nu, force, storage),
+                                 int(4 * (r * bb) ** 2 / nu), travel=travel) for m in l_over_b]
+            (L1, U1), (L2, U2) = [(q["L"], q["U"]) for q in runs]
+            U_inf = (U2 * L2 - U1 * L1) / (L2 - L1)  # U = U_inf (1 - k / L) through both
+            norm = force / (6 * math.pi * nu * bb)
+            rows.append({"b": bb, "L": [L1, L2], "U": [U1, U2], "U_inf": U_inf, "U_norm": U_inf / norm,
+                         "U_closed_norm": runs[0]["U_closed"] / norm, "error": U_inf / runs[0]["U_closed"] - 1,
+                         "drift": max(q["drift"] for q in runs), "spread": max(q["spread"] for q in runs)})
+        out[orient] = rows
+    return out
+
+
+def sphere_array_run(L, R=4.0, force=2e-3, steps=None):
+    """A sphere of radius R in a periodic L^3 box (BGK, tau = 1, nu = 1/6)
+    under a force: a simple-cubic array of spheres, whose velocity
+    Hasimoto's expansion gives exactly for small R / L."""
+    nu = 1.0 / 6.0
+    W = workloads.settling(L, R, R, "end-on", nu, force, "fp64")
+    W.collision = "bgk"
+    W.tau = 1.0
+    return settling_run(W, steps or int(16 * R * R / nu))
+
+
 # ------------------------------------------------------- steps to steady --
 
 def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25):
