@@ -254,7 +254,8 @@ def main():
         out = {"kind": "settling spheroid studies (Sec. III.A, Figs. 4 and 9)", "data": "synthetic",
                "domain": runner.domain_sweep([32, 64, 128, 256, 512], a=7.5, b=2.5, nu=0.1, storage="fp32"),
                "resolution": runner.resolution_sweep([2.0, 2.5, 3.0, 4.0], r=3.0),
-               "sphere_array": {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)}}
+               "sphere_array": {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)},
+               "jeffery_domain": [runner.jeffery_half_period(L) for L in (26, 32, 40, 48, 64)]}
         out["seconds"] = round(time.perf_counter() - t0, 1)
         print(json.dumps(out), flush=True)
         return

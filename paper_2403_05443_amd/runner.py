@@ -244,6 +244,36 @@ def resolution_sweep(bs, r=3.0, l_over_b=(32, 64), nu=0.1, force=2e-3, storage="
     return out
 
 
+def jeffery_half_period(L, a=6.0, b=2.0, rate=2e-4, nu=0.1, storage="fp32", chunk=250):
+    """Steps the long axis of a spheroid in the flow-gradient plane of an L^3
+    wall-bounded shear cell takes to turn by pi (half a Jeffery orbit,
+    eq. jeffery; closed form pi (r + 1/r) / rate for r = a / b), with
+    linear interpolation of the crossing."""
+    W = workloads.jeffery_box(L, a, b, rate, nu, storage)
+    lat = build_lattice(W)
+    lat.autotune(2)
+    lat.set_graph(50 if chunk % 50 == 0 else chunk)
+    r = a / b
+    T_half = math.pi * (r + 1 / r) / rate
+    phi, last, t = 0.0, 0.0, 0
+    while True:
+        lat.step(chunk)
+        t += chunk
+        q = lat.particles()["q"][0]
+        ex, ey = 1 - 2 * (q[2] ** 2 + q[3] ** 2), 2 * (q[1] * q[2] + q[0] * q[3])  # body x axis in the lab
+        ang = math.atan2(ey, ex)
+        d = (ang - last + math.pi) % (2 * math.pi) - math.pi
+        prev, phi, last = phi, phi + d, ang
+        if abs(phi) >= math.pi:
+            t_cross = t - chunk + (math.pi - abs(prev)) / (abs(phi) - abs(prev)) * chunk
+            break
+        if t > 3 * T_half:
+            t_cross = float("nan")
+            break
+    del lat
+    return {"L": L, "half_period": t_cross, "closed_form": T_half, "ratio": t_cross / T_half}
+
+
 def sphere_array_run(L, R=4.0, force=2e-3, steps=None):
     """A sphere of radius R in a periodic L^3 box (BGK, tau = 1, nu = 1/6)
     under a force: a simple-cubic array of spheres, whose velocity

@@ -141,6 +141,19 @@ def settling(L, a=7.5, b=2.5, orientation="end-on", nu=0.1, force=1e-3, storage=
                     max_semi_axis=max(8.0, a), lattice=lattice, notes={"nu": nu, "orientation": orientation})
 
 
+def jeffery_box(L, a=6.0, b=2.0, rate=2e-4, nu=0.1, storage="fp32"):
+    """A prolate spheroid (a, b, b) at the centre of an L^3 box between walls
+    y = 0 and y = L-1 moving at -/+U along x, U chosen for the shear rate
+    `rate` between the half-way planes (Sec. III.C, Fig. 6c), started in the
+    flow-gradient plane along the flow (body x = lab x); Couette start."""
+    U = rate * (L - 2) / 2.0
+    c = (L - 1) / 2.0
+    return Workload(f"jeffery_L{L}_a{a:g}_b{b:g}",
+                    [Box((L, L, L), walls=True, wall_lo=(-U, 0, 0), wall_hi=(U, 0, 0), init="couette")],
+                    [Particle((c, c, c), (a, b, b), (1.0, 0.0, 0.0, 0.0))], "trt", 3 * nu + 0.5, storage, 0,
+                    velocity_scale=2 * U, max_semi_axis=max(8.0, a), notes={"shear_rate": rate, "nu": nu})
+
+
 def c3(r=3, seed_index=1, storage="fp32"):
     """64 x 128 x 64 between walls y=0 and y=127 moving at -/+0.01 along x,
     BGK tau=0.8, neutrally buoyant spheroid b=c=3, a=3r, seeded orientation."""

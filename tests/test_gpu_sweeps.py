@@ -21,6 +21,10 @@ such a window moves by < 0.5% from one window to the next).
   as nodes change side, the paper's error bars) shrinks as b grows.  The
   mean error itself is not monotonic in b at these sizes (measured end-on
   -1.6, +0.8, -2.0, -1.7% for b = 2, 2.5, 3, 4).
+* Jeffery orbits against box size (Fig. 6c): a spheroid r = 3 in the
+  flow-gradient plane of wall-bounded cubes 26^3-64^3 at one shear rate
+  turns slower than eq. jeffery in the small cubes (walls and images) and
+  approaches it as the cube grows.
 """
 import numpy as np
 import pytest
@@ -76,3 +80,13 @@ def test_spheroid_resolution(lb):
         assert all(abs(r["error"]) < 0.035 for r in rows)
         assert rows[1]["spread"] < rows[0]["spread"]
         assert max(r["drift"] for r in rows) < 1e-2
+
+
+def test_jeffery_orbit_domain_size(lb):
+    from paper_2403_05443_amd import runner
+    rows = [runner.jeffery_half_period(L) for L in (26, 40, 64)]
+    ratios = [r["ratio"] for r in rows]
+    print("half period / closed form", [(r["L"], round(r["ratio"], 4)) for r in rows])
+    assert all(x > 1.0 for x in ratios)
+    assert ratios[0] > ratios[1] > ratios[2]
+    assert ratios[2] < 1.08
