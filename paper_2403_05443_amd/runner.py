@@ -129,6 +129,33 @@ def resistance(r):
             4 / 3 * e ** 3 * (2 - e * e) / (-2 * e + (1 + e * e) * lg))
 
 
+def ellipsoid_resistance(axes, mu, n=200):
+    """Translational and rotational resistance of an ellipsoid with
+    semi-axes (a1, a2, a3) about its body axes in an unbounded fluid
+    (Oberbeck's integrals, as in Jeffery 1922): with
+    D(l) = sqrt((a1^2 + l)(a2^2 + l)(a3^2 + l)), chi = int_0^inf dl / D and
+    alpha_i = int_0^inf dl / ((a_i^2 + l) D), translation along axis i costs
+    16 pi mu / (chi + a_i^2 alpha_i) and rotation about it
+    16 pi mu (a_j^2 + a_k^2) / (3 (a_j^2 alpha_j + a_k^2 alpha_k)).  The
+    integrals are taken by Gauss-Legendre quadrature after
+    l = s^2 (1 - u^2) / u^2 (s = the largest semi-axis), which maps [0, inf)
+    to (0, 1] with smooth integrands (dl / D tends to 2 du / s at u = 0)."""
+    a2 = np.asarray(axes, float) ** 2
+    sc = a2.max()
+    x, w = np.polynomial.legendre.leggauss(n)
+    u = 0.5 * (x + 1.0)
+    wt = 0.5 * w
+    lam = sc * (1.0 - u * u) / (u * u)
+    jac = 2.0 * sc / u ** 3
+    D = np.sqrt((a2[0] + lam) * (a2[1] + lam) * (a2[2] + lam))
+    chi = np.sum(wt * jac / D)
+    alpha = np.array([np.sum(wt * jac / ((a2[i] + lam) * D)) for i in range(3)])
+    trans = 16 * math.pi * mu / (chi + a2 * alpha)
+    rot = np.array([16 * math.pi * mu * (a2[j] + a2[k]) / (3 * (a2[j] * alpha[j] + a2[k] * alpha[k]))
+                    for j, k in ((1, 2), (0, 2), (0, 1))])
+    return trans, rot
+
+
 def _rot(q):
     q0, q1, q2, q3 = q
     return np.array([[1 - 2 * (q2 * q2 + q3 * q3), 2 * (q1 * q2 - q0 * q3), 2 * (q1 * q3 + q0 * q2)],
@@ -137,14 +164,20 @@ def _rot(q):
 
 
 def unbounded_velocities(p, nu):
-    """Velocities of particle p (a, b, b) under its load in an unbounded
-    fluid at rest (no periodic images)."""
-    a, b, _ = p.axes
-    XA, YA, XC, YC = resistance(a / b)
+    """Velocities of particle p under its load in an unbounded fluid at rest
+    (no periodic images): the Kim-Karrila closed forms for a prolate
+    spheroid (a, b, b), a >= b, Oberbeck's integrals for any other
+    ellipsoid (rho0 = 1, so mu = nu)."""
+    a, b, c = p.axes
     R = _rot(p.quat)
     Fb, Tb = R.T @ np.asarray(p.force, float), R.T @ np.asarray(p.torque, float)
-    Ub = np.array([Fb[0] / XA, Fb[1] / YA, Fb[2] / YA]) / (6 * math.pi * nu * a)
-    Wb = np.array([Tb[0] / XC, Tb[1] / YC, Tb[2] / YC]) / (8 * math.pi * nu * a ** 3)
+    if b == c and a >= b:
+        XA, YA, XC, YC = resistance(a / b)
+        Ub = np.array([Fb[0] / XA, Fb[1] / YA, Fb[2] / YA]) / (6 * math.pi * nu * a)
+        Wb = np.array([Tb[0] / XC, Tb[1] / YC, Tb[2] / YC]) / (8 * math.pi * nu * a ** 3)
+    else:
+        trans, rot = ellipsoid_resistance(p.axes, nu)
+        Ub, Wb = Fb / trans, Tb / rot
     return R @ Ub, R @ Wb
 
 
@@ -200,17 +233,18 @@ def settling_run(W, transient, graph=50, tune=True, sample=50, travel=1.0):
 
 
 def domain_sweep(lengths, a=7.5, b=2.5, nu=0.1, force=2e-3, storage="fp32", transient=None, lattice=19,
-                 orientations=("end-on", "broadside")):
+                 orientations=("end-on", "broadside"), c=None):
     """Settling velocity against box edge L for both orientations (Fig. 4),
     and for each orientation the fit U(L) = U_inf (1 - k / L) over the boxes
     of edge >= 8a (the leading periodic-image correction), U_inf against the
     closed form of eq. settlingvel."""
-    transient = transient or int(4 * a * a / nu)
+    amax = max(a, b, c or 0.0)
+    transient = transient or int(4 * amax * amax / nu)
     out = {}
     for orient in orientations:
-        rows = [settling_run(workloads.settling(L, a, b, orient, nu, force, storage, lattice), transient)
+        rows = [settling_run(workloads.settling(L, a, b, orient, nu, force, storage, lattice, c), transient)
                 for L in lengths]
-        big = [r for r in rows if r["L"] >= 8 * a] or rows
+        big = [r for r in rows if r["L"] >= 8 * amax] or rows
         x = np.array([1.0 / r["L"] for r in big])
         y = np.array([r["U"] for r in big])
         A = np.vstack([np.ones_like(x), x]).T

@@ -127,18 +127,20 @@ def c2(storage="fp32", L=128, lattice=19):
                     "trt", 0.8, storage, 20000, counterforce=True, velocity_scale=1e-4, lattice=lattice)
 
 
-def settling(L, a=7.5, b=2.5, orientation="end-on", nu=0.1, force=1e-3, storage="fp32", lattice=19):
-    """A prolate spheroid (a, b, b) settling under a force at the centre of a
-    periodic L^3 box (Sec. III.A, Figs. 3-4 and 9): body x axis along the
-    lab x axis, the force along x (end-on, long axis parallel to the force)
-    or along y (broadside); TRT with tau = 3 nu + 1/2, counter-force on."""
-    c = (L - 1) / 2.0
+def settling(L, a=7.5, b=2.5, orientation="end-on", nu=0.1, force=1e-3, storage="fp32", lattice=19, c=None):
+    """An ellipsoid (a, b, c) (c = b by default: a spheroid) settling under a
+    force at the centre of a periodic L^3 box (Sec. III.A, Figs. 3-4 and 9):
+    body x axis along the lab x axis, the force along x ("end-on": along the
+    a axis) or along y ("broadside"); TRT with tau = 3 nu + 1/2,
+    counter-force on."""
+    c_ax = b if c is None else c
+    c0 = (L - 1) / 2.0
     F = (force, 0.0, 0.0) if orientation == "end-on" else (0.0, force, 0.0)
-    u_est = force / (6 * math.pi * nu * b)
-    return Workload(f"settling_{orientation}_L{L}_a{a:g}_b{b:g}", [Box((L, L, L))],
-                    [Particle((c, c, c), (a, b, b), (1.0, 0.0, 0.0, 0.0), force=F)],
+    u_est = force / (6 * math.pi * nu * min(a, b, c_ax))
+    return Workload(f"settling_{orientation}_L{L}_a{a:g}_b{b:g}_c{c_ax:g}", [Box((L, L, L))],
+                    [Particle((c0, c0, c0), (a, b, c_ax), (1.0, 0.0, 0.0, 0.0), force=F)],
                     "trt", 3 * nu + 0.5, storage, 0, counterforce=True, velocity_scale=2 * u_est,
-                    max_semi_axis=max(8.0, a), lattice=lattice, notes={"nu": nu, "orientation": orientation})
+                    max_semi_axis=max(8.0, a, b, c_ax), lattice=lattice, notes={"nu": nu, "orientation": orientation})
 
 
 def jeffery_box(L, a=6.0, b=2.0, rate=2e-4, nu=0.1, storage="fp32"):

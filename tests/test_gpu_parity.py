@@ -163,14 +163,17 @@ def test_config1_trajectory(lb, storage, tol):
     assert abs(g.mass() / o.mass() - 1) < (1e-13 if storage == "fp64" else 1e-11)
 
 
+@pytest.mark.parametrize("axes", [(6, 2, 2), (2, 5, 5), (6, 4, 2)], ids=["prolate", "oblate", "triaxial"])
 @pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
-def test_random_pose_trajectory(lb, storage, tol):
-    """Random orientation with force and torque: rotation, dI/dt, quaternion."""
+def test_random_pose_trajectory(lb, storage, tol, axes):
+    """Random orientation with force and torque: rotation, dI/dt, quaternion;
+    prolate, oblate and triaxial ellipsoids (the method is not restricted to
+    prolate spheroids, Sec. IV)."""
     rng = np.random.default_rng(2403054431)
     q = rand_q(rng)
     g, o = pair(lb, (32, 28, 30), "trt", 0.8, storage, counterforce=True)
     c = (15.2, 13.7, 14.9)
-    pg, po = g.add_ellipsoid(c, (6, 2, 2), q), o.add_ellipsoid(c, (6, 2, 2), q)
+    pg, po = g.add_ellipsoid(c, axes, q), o.add_ellipsoid(c, axes, q)
     F, T = (1e-4, -2e-4, 5e-5), (2e-3, 1e-3, -1e-3)
     g.set_external(pg, F, T)
     o.set_external(po, F, T)
@@ -178,7 +181,7 @@ def test_random_pose_trajectory(lb, storage, tol):
     for _ in range(3):
         g.step(100)
         o.step(100)
-        compare_particles(g, o, pg, po, tol, x0, a=6.0)
+        compare_particles(g, o, pg, po, tol, x0, a=max(axes))
 
 
 @pytest.mark.parametrize("coll,tau", [("bgk", 1.0), ("trt", 0.8), ("reg", 0.7)])
