@@ -58,6 +58,7 @@ def lib():
                                   C.c_int, _D, _D, C.c_int, C.c_int, C.c_int]
         L.or_equilibrium_q.argtypes = [C.c_int, C.c_double, _D, _D]
         L.or_lattice_q.argtypes = [C.c_int, C.POINTER(C.c_int), _D]
+        L.or_set_rotation.argtypes = [vp, C.c_int]
         L.or_destroy.argtypes = [vp]
         L.or_add_ellipsoid.argtypes = [vp, _D, _D, _D]
         for name in ("or_set_external", "or_set_velocity"):
@@ -162,7 +163,8 @@ class OracleSim:
     """One periodic (or wall-bounded) box stepped by the FP64 oracle."""
 
     def __init__(self, shape, collision="bgk", tau=1.0, magic=3.0 / 16.0, walls=False,
-                 wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), init="rest", counterforce=False, lattice=19):
+                 wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), init="rest", counterforce=False, lattice=19,
+                 rotation=0):
         self.shape = tuple(int(v) for v in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
         self.q = int(lattice)
@@ -173,6 +175,8 @@ class OracleSim:
                                     {"rest": 0, "couette": 1}[init], int(bool(counterforce)), self.q)
         if not self._h:
             raise ValueError(f"lattice must be 19 or 27, got {lattice}")
+        if lib().or_set_rotation(self._h, int(rotation)) != 0:
+            raise ValueError(f"rotation must be 0, 1 or 2, got {rotation}")
         self.np = 0
 
     def __del__(self):

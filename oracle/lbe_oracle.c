@@ -92,6 +92,7 @@ typedef struct {
     double dm, Pp[3], Lp[3];  /* pending transition book-keeping (R9)       */
     double F[3], T[3];        /* hydrodynamic force / torque of last step   */
     double wsum;              /* sum of w_b over the links                  */
+    double qprev[4];          /* orientation one step before (finite-difference dI/dt) */
     int nlinks, lcap;
     int* lsite;
     int* ldir;
@@ -106,6 +107,8 @@ struct or_sim {
     int walls;
     double ulo[3], uhi[3];
     int counterforce;
+    int rotation;        /* 0 eq. Irotdiff with I(t); 1 finite-difference dI/dt;
+                            2 predictor-corrector for I(t + dt) (reading R21) */
     double* f;   /* pre-collision f[site*q+i], meaningful on fluid nodes */
     double* fs;  /* post-collision                                       */
     int* node;   /* 0 fluid, p+1 solid of particle p, -1 wall            */
@@ -487,6 +490,12 @@ or_sim* or_create(int nx, int ny, int nz, int collision, double tau, double magi
     return or_create_q(nx, ny, nz, collision, tau, magic, walls, ulo, uhi, init, counterforce, 19);
 }
 
+int or_set_rotation(or_sim* s, int mode) {
+    if (mode < 0 || mode > 2) return -1;
+    s->rotation = mode;
+    return 0;
+}
+
 void or_destroy(or_sim* s) {
     int k;
     if (!s) return;
@@ -670,6 +679,7 @@ int or_add_ellipsoid(or_sim* s, const double centre[3], const double axes[3], co
     memset(p, 0, sizeof *p);
     nq = sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
     for (k = 0; k < 4; k++) p->q[k] = quat[k] / nq;
+    for (k = 0; k < 4; k++) p->qprev[k] = p->q[k];
     for (k = 0; k < 3; k++) {
         double c = centre[k];
         if (c >= n3[k]) c -= n3[k] * floor(c / n3[k]);
@@ -798,9 +808,16 @@ static int step_once(or_sim* s) {
                 }
             }
         }
-        /* step 4: lab-frame inertia and its rate (eqs. Irot, Irotdiff), R6 */
+        /* step 4: lab-frame inertia and its rate (eqs. Irot, Irotdiff), R6;
+           or the finite difference (I(t) - I(t - dt)) / dt of Sec. II.D */
         or_inertia_lab(p->q, p->Ib, Il);
-        or_inertia_dot(p->q, p->Ib, p->W, Id);
+        if (s->rotation == 1) {
+            double Ip[9];
+            or_inertia_lab(p->qprev, p->Ib, Ip);
+            for (k = 0; k < 9; k++) Id[k] = Il[k] - Ip[k];
+        } else {
+            or_inertia_dot(p->q, p->Ib, p->W, Id);
+        }
         /* step 5: eqs. Fdiscrete, Tdiscrete (dt = 1) as one 6x6 system */
         for (i = 0; i < 6; i++)
             for (j = 0; j < 6; j++) A[6 * i + j] = p->zeta[6 * i + j];
@@ -814,6 +831,20 @@ static int step_once(or_sim* s) {
             rhs[3 + i] = Iw[i] + T0[i] + Ts[i] + p->Text[i] + p->Lp[i];
         }
         if (or_solve6(A, rhs, sol) != 0) return -6;
+        if (s->rotation == 2) {
+            /* R21: the solve above predicts Omega(t + dt); the orientation it
+               gives (eqs. qnplus0/1 with the mean angular velocity) yields
+               I(t + dt), and the rotational rows are solved again as the
+               discrete balance I(t + dt) Omega(t + dt) - I(t) Omega(t) = dt T
+               (the same right-hand side) */
+            double Wm[3], qs[4], Is[9];
+            for (i = 0; i < 3; i++) Wm[i] = 0.5 * (p->W[i] + sol[3 + i]);
+            or_quat_update(p->q, Wm, qs);
+            or_inertia_lab(qs, p->Ib, Is);
+            for (i = 0; i < 3; i++)
+                for (j = 0; j < 3; j++) A[6 * (3 + i) + 3 + j] = p->zeta[6 * (3 + i) + 3 + j] + Is[3 * i + j];
+            if (or_solve6(A, rhs, sol) != 0) return -6;
+        }
         for (i = 0; i < 3; i++) {
             double zf = 0, zt = 0;
             for (j = 0; j < 6; j++) {
@@ -866,6 +897,7 @@ static int step_once(or_sim* s) {
                 Wm[i] = 0.5 * (Wold[i] + p->W[i]);
             }
             or_quat_update(p->q, Wm, qn);
+            memcpy(p->qprev, p->q, sizeof qn);
             memcpy(p->q, qn, sizeof qn);
         }
     }

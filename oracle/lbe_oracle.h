@@ -26,6 +26,13 @@ or_sim* or_create(int nx, int ny, int nz, int collision, double tau, double magi
 or_sim* or_create_q(int nx, int ny, int nz, int collision, double tau, double magic,
                     int walls, const double ulo[3], const double uhi[3], int init,
                     int counterforce, int lattice);
+/* treatment of the inertia in the rotational equation (Sec. II.D): 0 the
+   analytic dI/dt of eq. Irotdiff with I(t) (default); 1 dI/dt as the finite
+   difference (I(t) - I(t - dt)) / dt; 2 predictor-corrector for I(t + dt):
+   the solve with mode 0 predicts Omega(t + dt), the orientation it gives
+   yields I(t + dt), and the rotational rows are solved again as
+   I(t + dt) Omega(t + dt) - I(t) Omega(t) = dt T.  -1 for another mode. */
+int     or_set_rotation(or_sim* s, int mode);
 void    or_destroy(or_sim* s);
 int     or_add_ellipsoid(or_sim* s, const double centre[3], const double axes[3],
                          const double quat[4]);
