@@ -75,6 +75,23 @@ typedef int lb_status;
 #define LB_FP16 2
 #define LB_BF16 3
 
+/* Rotational update (Sec. II.D, eq. Tdiscrete).  The implicit step solves
+ * (I + dI) Omega(t+1) - I Omega(t) = T + T_ext for Omega(t+1), I = I(t) the
+ * lab-frame inertia; the modes differ in dI:
+ *   LB_ROT_ANALYTIC  dI = [Omega(t)]x I - I [Omega(t)]x, the analytic rate
+ *   LB_ROT_FD        dI = I(t) - I(t-1), the backward difference over the
+ *                    orientations of the last two steps (I(t-1) = I(t) on
+ *                    the step after a particle is added)
+ *   LB_ROT_PC        predictor-corrector: the analytic solve predicts
+ *                    Omega(t+1), whose mean with Omega(t) rotates q(t) to q*;
+ *                    the rotational rows are solved again with I + dI
+ *                    replaced by I(q*), the same right-hand side.
+ * All three agree for a sphere; the paper found no difference between the
+ * first two. */
+#define LB_ROT_ANALYTIC 0
+#define LB_ROT_FD       1
+#define LB_ROT_PC       2
+
 typedef struct lb_config {
     int    lattice;         /* 19 (D3Q19, default) or 27 (D3Q27: the eight corner
                                vectors appended as directions 19-26, each followed by
@@ -93,6 +110,8 @@ typedef struct lb_config {
                                momentum stays zero (default 0)                        */
     int    max_particles;   /* particle capacity over all boxes (default 1 per box)    */
     double max_semi_axis;   /* largest semi-axis any particle may have (default 8)     */
+    int    rotation;        /* inertia term of the rotational update (Sec. II.D):
+                               LB_ROT_ANALYTIC (default), LB_ROT_FD or LB_ROT_PC        */
 } lb_config;
 
 typedef struct lb_box {

@@ -75,6 +75,66 @@ __device__ __forceinline__ void rotmat(const double q[4], double R[3][3]) {
     R[2][2] = 1 - 2 * (q1 * q1 + q2 * q2);
 }
 
+// q(t+1) = exp(Wm / 2) q(t) (eqs. qnplus0, qnplus1): rotation by |Wm| about
+// Wm / |Wm|, Wm the mean angular velocity over the step.
+__device__ __forceinline__ void quat_advance(const double q[4], const double Wm[3], double qn[4]) {
+    const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
+    for (int j = 0; j < 4; ++j) qn[j] = q[j];
+    if (nrm != 0.0) {
+        double sn, c;
+        sincos(0.5 * nrm, &sn, &c);
+        const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
+        qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
+        qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
+        qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
+        qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+    }
+}
+
+// Symmetric 6x6 solve A x = rhs as A = L D L^T, A in the lower triangle of
+// Lw (overwritten by L below the diagonal), one reciprocal per pivot.
+// Returns false on a zero pivot.
+__device__ __forceinline__ bool ldlt_solve6(double Lw[6][6], double dv[6], double di[6], const double rhs[6],
+                                            double sol[6]) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double v[6];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v[k] = Lw[j][k] * dv[k];
+        double d = Lw[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= Lw[j][k] * v[k];
+        dv[j] = d;
+        ok = ok && fabs(d) > 1e-300;
+        di[j] = 1.0 / d;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double t = Lw[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= Lw[i][k] * v[k];
+            Lw[i][j] = t * di[j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double t = rhs[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) t -= Lw[i][k] * sol[k];
+        sol[i] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sol[i] *= di[i];
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double t = sol[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) t -= Lw[k][i] * sol[k];
+        sol[i] = t;
+    }
+    return ok;
+}
+
 // Solid test of eq. ellipsoidsurface.  Body coordinates come from eq.
 // vectrotn with q^-1; the operation order is fixed and contraction is off so
 // the decision is reproducible bit for bit by any IEEE FP64 evaluation of the
@@ -400,6 +460,27 @@ __device__ __forceinline__ void load_particle(const LaunchPart& a, int p, PartDe
     __syncthreads();
 }
 
+// Takes a solution of the 6x6 system as U(t+1), Omega(t+1) (bc[0..5], with
+// the transition mass per unit link weight in bc[6]), unless a pivot
+// vanished, it is not finite, or the surface speed |U| + |Omega| max(a,b,c)
+// reaches half a node per step: then the velocities are kept and the
+// non-finite flag raised.
+__device__ __forceinline__ void accept_solution(const LaunchPart& a, const PartDev& P, bool ok, double sol[6],
+                                                const double U0[3], const double W0[3], double* bc) {
+    bool bad = !ok;
+    for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
+    const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
+    const double sp = sqrt(sol[0] * sol[0] + sol[1] * sol[1] + sol[2] * sol[2]) +
+                      sqrt(sol[3] * sol[3] + sol[4] * sol[4] + sol[5] * sol[5]) * amax;
+    bad = bad || !(sp <= 0.5);
+    if (bad) {
+        atomicOr(a.flags, (int)F_NONFINITE);
+        for (int k = 0; k < 6; ++k) sol[k] = k < 3 ? U0[k] : W0[k - 3];
+    }
+    for (int k = 0; k < 6; ++k) bc[k] = sol[k];
+    bc[6] = P.wsum > 0.0 ? P.dm / P.wsum : 0.0;
+}
+
 // Steps 3-7 for particle p whose record is staged in LDS (P).  The new state
 // goes to global memory; with keep_lds the LDS copy is updated as well.
 template <int ST, int Q>
@@ -433,8 +514,9 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
 
     // steps 4-5, matrix part, built while the link loads are in flight: one
     // lane per entry of [M + zFU, zFW; zTU, I' + dI/dt + zTW], with
-    // I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x (W = Omega(t)); lanes
-    // 36-38 store I' Omega(t) for the right-hand side
+    // I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x (W = Omega(t)), or
+    // with the backward difference I'(t) - I'(t-1); lanes 36-38 store
+    // I' Omega(t) for the right-hand side
     const double M = P.M;
     const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
     if (tid < 39) {
@@ -453,7 +535,14 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             if (i >= 3 && j >= 3) {
                 const int ii = i - 3, jj = j - 3;
                 double d = 0;
-                for (int k = 0; k < 3; ++k) d += Wx(ii, k) * Il(k, jj) - Il(ii, k) * Wx(k, jj);
+                if (a.kp.rot == 1) {
+                    double Rp[3][3];
+                    rotmat(P.qprev, Rp);
+                    d = Il(ii, jj) - (Rp[ii][0] * Ib0 * Rp[jj][0] + Rp[ii][1] * Ib1 * Rp[jj][1] +
+                                      Rp[ii][2] * Ib2 * Rp[jj][2]);
+                } else {
+                    for (int k = 0; k < 3; ++k) d += Wx(ii, k) * Il(k, jj) - Il(ii, k) * Wx(k, jj);
+                }
                 v += Il(ii, jj) + d;
             }
             A[i][j] = v;
@@ -518,65 +607,50 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             rhs[i] = M * U0[i] + acc[i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
             rhs[3 + i] = A[3 + i][6] + acc[3 + i] + P.Text[i] + P.Lp[i];
         }
-        // The matrix is symmetric (zeta is, I' is, and so is the commutator
-        // of [Omega]x with I'), so the elimination runs as A = L D L^T on the
-        // lower triangle, in registers, with one reciprocal per pivot.
-        double Lw[6][6], dv[6], di[6];
+        // The matrix is symmetric (zeta is, I' is, and so are the commutator
+        // of [Omega]x with I' and a difference of two inertias), so the
+        // elimination runs as A = L D L^T on the lower triangle, in registers.
+        double Lw[6][6], dv[6], di[6], sol[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
             for (int j = 0; j <= i; ++j) Lw[i][j] = A[i][j];
-        bool ok = true;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            double v[6];
-#pragma unroll
-            for (int k = 0; k < j; ++k) v[k] = Lw[j][k] * dv[k];
-            double d = Lw[j][j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) d -= Lw[j][k] * v[k];
-            dv[j] = d;
-            ok = ok && fabs(d) > 1e-300;
-            di[j] = 1.0 / d;
-#pragma unroll
-            for (int i = j + 1; i < 6; ++i) {
-                double t = Lw[i][j];
-#pragma unroll
-                for (int k = 0; k < j; ++k) t -= Lw[i][k] * v[k];
-                Lw[i][j] = t * di[j];
+        const bool ok = ldlt_solve6(Lw, dv, di, rhs, sol);
+        if (a.kp.rot == 2) {  // the prediction, checked after the corrector
+            for (int i = 0; i < 6; ++i) {
+                A[i][6] = rhs[i];
+                bc[i] = sol[i];
             }
+        } else {
+            accept_solution(a, P, ok, sol, U0, W0, bc);
         }
-        double sol[6];
+    }
+    if (a.kp.rot == 2) {
+        // predictor-corrector: the predicted Omega(t+1) rotates q(t) to q*
+        // with the mean angular velocity, and the system is solved again with
+        // the rotational block zTW + I'(q*) and the same right-hand side
+        // (a separate phase, so its registers do not add to the first solve's)
+        __syncthreads();
+        if (tid == 0) {
+            const double Wm[3] = {0.5 * (W0[0] + bc[3]), 0.5 * (W0[1] + bc[4]), 0.5 * (W0[2] + bc[5])};
+            double qs[4], Rs[3][3], Lw[6][6], dv[6], di[6], rhs[6], sol[6];
+            quat_advance(q, Wm, qs);
+            rotmat(qs, Rs);
+            const double Ib0 = P.Ib[0], Ib1 = P.Ib[1], Ib2 = P.Ib[2];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            double t = rhs[i];
+            for (int i = 0; i < 6; ++i) {
+                rhs[i] = A[i][6];
 #pragma unroll
-            for (int k = 0; k < i; ++k) t -= Lw[i][k] * sol[k];
-            sol[i] = t;
+                for (int j = 0; j <= i; ++j)
+                    Lw[i][j] = i >= 3 && j >= 3
+                                   ? P.zeta[6 * i + j] + (Rs[i - 3][0] * Ib0 * Rs[j - 3][0] +
+                                                          Rs[i - 3][1] * Ib1 * Rs[j - 3][1] +
+                                                          Rs[i - 3][2] * Ib2 * Rs[j - 3][2])
+                                   : A[i][j];
+            }
+            const bool ok = ldlt_solve6(Lw, dv, di, rhs, sol);
+            accept_solution(a, P, ok, sol, U0, W0, bc);
         }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) sol[i] *= di[i];
-#pragma unroll
-        for (int i = 5; i >= 0; --i) {
-            double t = sol[i];
-#pragma unroll
-            for (int k = i + 1; k < 6; ++k) t -= Lw[k][i] * sol[k];
-            sol[i] = t;
-        }
-        bool bad = !ok;
-        for (int k = 0; k < 6; ++k) bad = bad || !isfinite(sol[k]);
-        {  // surface speed |U| + |Omega| max(a,b,c) must stay below half a node per step
-            const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
-            const double sp = sqrt(sol[0] * sol[0] + sol[1] * sol[1] + sol[2] * sol[2]) +
-                              sqrt(sol[3] * sol[3] + sol[4] * sol[4] + sol[5] * sol[5]) * amax;
-            bad = bad || !(sp <= 0.5);
-        }
-        if (bad) {
-            atomicOr(a.flags, (int)F_NONFINITE);
-            for (int k = 0; k < 6; ++k) sol[k] = k < 3 ? U0[k] : W0[k - 3];
-        }
-        for (int k = 0; k < 6; ++k) bc[k] = sol[k];
-        bc[6] = P.wsum > 0.0 ? P.dm / P.wsum : 0.0;
     }
     __syncthreads();
 
@@ -632,20 +706,17 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         }
     } else if (tid == PBLOCK - 256) {  // orientation (eqs. qnplus0, qnplus1) with the mean angular velocity
         const double Wm[3] = {0.5 * (W0[0] + bc[3]), 0.5 * (W0[1] + bc[4]), 0.5 * (W0[2] + bc[5])};
-        const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
-        double qn[4] = {q[0], q[1], q[2], q[3]};
-        if (nrm != 0.0) {
-            double sn, c;
-            sincos(0.5 * nrm, &sn, &c);
-            const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
-            qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
-            qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
-            qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
-            qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+        double qn[4];
+        quat_advance(q, Wm, qn);
+        for (int j = 0; j < 4; ++j) {
+            Pg->q[j] = qn[j];
+            Pg->qprev[j] = q[j];
         }
-        for (int j = 0; j < 4; ++j) Pg->q[j] = qn[j];
         if (keep_lds)
-            for (int j = 0; j < 4; ++j) P.q[j] = qn[j];
+            for (int j = 0; j < 4; ++j) {
+                P.q[j] = qn[j];
+                P.qprev[j] = q[j];
+            }
     }
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step

@@ -64,6 +64,7 @@ bool valid_cfg(const lb_config* c, int nboxes, const lb_box* boxes, std::string*
     if (c->storage < 0 || c->storage > 3) return bad("unknown storage");
     if (c->rho0 != 1.0) return bad("rho0 must be 1");
     if (!(c->max_semi_axis > 0)) return bad("max_semi_axis must be positive");
+    if (c->rotation < 0 || c->rotation > 2) return bad("rotation must be LB_ROT_ANALYTIC, LB_ROT_FD or LB_ROT_PC");
     if (lds_words_for(c->max_semi_axis) > MAX_LDS_WORDS) return bad("max_semi_axis too large for the remap window");
     for (int b = 0; b < nboxes; ++b) {
         const lb_box& B = boxes[b];
@@ -366,6 +367,7 @@ lb_status lb_config_default(lb_config* cfg) {
     cfg->counterforce = 0;
     cfg->max_particles = 0;
     cfg->max_semi_axis = 8.0;
+    cfg->rotation = LB_ROT_ANALYTIC;
     return LB_OK;
 }
 
@@ -407,6 +409,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
     kp.collision = cfg->collision;
     kp.storage = cfg->storage;
     kp.q = cfg->lattice;
+    kp.rot = cfg->rotation;
     int e = 0;
     if (cfg->storage == LB_FP16 || cfg->storage == LB_BF16) {
         e = cfg->scale_log2;
@@ -546,7 +549,7 @@ lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const d
     PartDev P;
     std::memset(&P, 0, sizeof P);
     const int n3[3] = {B.nx, B.ny, B.nz};
-    for (int k = 0; k < 4; ++k) P.q[k] = quat[k] / nq;
+    for (int k = 0; k < 4; ++k) P.q[k] = P.qprev[k] = quat[k] / nq;
     for (int k = 0; k < 3; ++k) {
         double c = centre[k];
         if (c >= n3[k]) c -= n3[k] * std::floor(c / n3[k]);

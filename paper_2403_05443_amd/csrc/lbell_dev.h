@@ -81,6 +81,7 @@ struct PartDev {
     double xc[3];         // centre, wrapped into the box
     double xu[3];         // centre, unwrapped
     double q[4];          // orientation (scalar first, body -> lab)
+    double qprev[4];      // orientation one step earlier (q on the first step)
     double U[3], W[3];    // velocity, angular velocity (lab)
     double axes[3];       // semi-axes a, b, c along body x, y, z
     double ia2[3];        // 1 / axis^2, computed on the host
@@ -108,6 +109,7 @@ struct KParams {
     int collision, storage;
     int conv;                 // storage convention of the current populations (CV_*)
     int q;                    // velocity set: 19 or 27
+    int rot;                  // inertia term of the rotational update (LB_ROT_*)
 };
 
 // Storage conventions of the population array.  The post-collision

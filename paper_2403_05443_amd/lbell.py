@@ -16,6 +16,9 @@ BGK, TRT, REG = 0, 1, 2
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 COLLISION = {"bgk": BGK, "trt": TRT, "reg": REG}
 STORAGE = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+# inertia term of the rotational update (Sec. II.D): analytic rate, backward
+# difference, predictor-corrector
+ROTATION = {"analytic": 0, "fd": 1, "pc": 2}
 
 STATUS = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", -4: "LB_ESTATE",
           -5: "LB_EOVERLAP", -6: "LB_ENONFINITE", -7: "LB_ERANGE", -8: "LB_EIO"}
@@ -31,7 +34,7 @@ class Config(C.Structure):
     _fields_ = [("lattice", C.c_int), ("collision", C.c_int), ("tau", C.c_double),
                 ("magic", C.c_double), ("storage", C.c_int), ("scale_log2", C.c_int),
                 ("velocity_scale", C.c_double), ("rho0", C.c_double), ("counterforce", C.c_int),
-                ("max_particles", C.c_int), ("max_semi_axis", C.c_double)]
+                ("max_particles", C.c_int), ("max_semi_axis", C.c_double), ("rotation", C.c_int)]
 
 
 class Box(C.Structure):
@@ -156,7 +159,7 @@ class Lattice:
 
     def __init__(self, boxes, collision="bgk", tau=1.0, magic=3.0 / 16.0, storage="fp32",
                  scale_log2=0, velocity_scale=1e-3, counterforce=False, max_particles=0,
-                 max_semi_axis=8.0, lattice=19, device="cuda:0"):
+                 max_semi_axis=8.0, lattice=19, rotation="analytic", device="cuda:0"):
         import torch
         self.lib = load()
         self.torch = torch
@@ -172,6 +175,7 @@ class Lattice:
         cfg.max_particles = int(max_particles)
         cfg.max_semi_axis = float(max_semi_axis)
         cfg.lattice = int(lattice)
+        cfg.rotation = ROTATION[rotation] if isinstance(rotation, str) else int(rotation)
         self.cfg = cfg
         bl = [b if isinstance(b, Box) else make_box(*b) for b in boxes]
         self.nboxes = len(bl)

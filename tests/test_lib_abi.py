@@ -37,6 +37,7 @@ def test_config_default(lib):
     cfg = Config()
     assert lib.lb_config_default(C.byref(cfg)) == 0
     assert cfg.lattice == 19 and cfg.collision == 0 and cfg.tau == 1.0
+    assert cfg.rotation == 0
     assert abs(cfg.magic - 3 / 16) < 1e-15 and cfg.rho0 == 1.0 and cfg.storage == 1
 
 
@@ -63,7 +64,8 @@ def test_arena_bytes(lib):
 
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("lattice", 15), ("collision", 5), ("storage", 9),
-                                         ("rho0", 1.1), ("max_semi_axis", 200.0)])
+                                         ("rho0", 1.1), ("max_semi_axis", 200.0), ("rotation", 3),
+                                         ("rotation", -1)])
 def test_invalid_config_sizes_to_zero(lib, field, value):
     from paper_2403_05443_amd.lbell import Box, make_box
     b = (Box * 1)(make_box(32, 32, 32))
