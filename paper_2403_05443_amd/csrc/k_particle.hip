@@ -139,7 +139,7 @@ __device__ __forceinline__ bool ldlt_solve6(double Lw[6][6], double dv[6], doubl
 // vectrotn with q^-1; the operation order is fixed and contraction is off so
 // the decision is reproducible bit for bit by any IEEE FP64 evaluation of the
 // same expression.
-__device__ __forceinline__ bool inside_test(const double xc[3], const double q[4], const double ia2[3],
+__device__ __forceinline__ double quad_form(const double xc[3], const double q[4], const double ia2[3],
                                             int x, int y, int z, int nx, int ny, int nz) {
 #pragma clang fp contract(off)
     const double d0 = minimg((double)x - xc[0], nx);
@@ -154,8 +154,7 @@ __device__ __forceinline__ bool inside_test(const double xc[3], const double q[4
     const double u = (a0 * d0 + (2.0 * ps) * p1) + (2.0 * q0) * c0;
     const double v = (a0 * d1 + (2.0 * ps) * p2) + (2.0 * q0) * c1;
     const double w = (a0 * d2 + (2.0 * ps) * p3) + (2.0 * q0) * c2;
-    const double Q = ((u * u) * ia2[0] + (v * v) * ia2[1]) + (w * w) * ia2[2];
-    return Q < 1.0;
+    return ((u * u) * ia2[0] + (v * v) * ia2[1]) + (w * w) * ia2[2];
 }
 
 // Spheroidal squirmer slip (eq. squirmer) at lab offset d from the centre;
@@ -207,6 +206,10 @@ __device__ __forceinline__ double wsum64(double v) {
     v += dpp_d<0x143, 0xc>(v);
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
                             __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+__device__ __forceinline__ double wmin64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
 }
 __device__ __forceinline__ int wsumi(int v) {
     v += dpp_i<0x111, 0xf>(v);
@@ -766,9 +769,39 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
 
 struct RemapShm {
     double red[22][PWAVES];
+    double mred[PWAVES];
     int wtot[PWAVES];
     int ired[8][PWAVES];
 };
+
+// Whether the window must be tested again.  At its last test every node of
+// the window had |sqrt(Q) - 1| >= smargin / min(a, b, c).  Since then the
+// centre moved by dx and the body turned by an angle th: a node x of that
+// window then has its body coordinates moved by at most dx + 2 sin(th/2)
+// |x - x_c|, which is at most dx + 2 sin(th/2) srho, and sqrt(Q) by at most
+// that over min(a, b, c); while that stays below the margin no node of the
+// window changed side.  A node outside that window was more than one node
+// from the body, and no body point moved by half a node.  Rounding of Q
+// (~1e-15) is covered by the 1e-9 allowance.
+__device__ __forceinline__ bool scan_needed(const PartDev& P) {
+    if (!(P.smargin > 0.0)) return true;
+    double dx2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double d = P.xu[k] - P.sref[k];
+        dx2 += d * d;
+    }
+    const double dx = sqrt(dx2);
+    // vector part of q conj(qref): its length is sin(th/2)
+    const double q0 = P.q[0], r0 = P.qref[0];
+    const double v[3] = {P.q[1], P.q[2], P.q[3]}, w[3] = {P.qref[1], P.qref[2], P.qref[3]};
+    const double s0 = r0 * v[0] - q0 * w[0] - (v[1] * w[2] - v[2] * w[1]);
+    const double s1 = r0 * v[1] - q0 * w[1] - (v[2] * w[0] - v[0] * w[2]);
+    const double s2 = r0 * v[2] - q0 * w[2] - (v[0] * w[1] - v[1] * w[0]);
+    const double sh = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+    const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
+    const double dwin = dx + 2.0 * sh * P.srho, dbody = dx + 2.0 * sh * amax;
+    return !(dwin * (1.0 + 1e-12) + 1e-9 < P.smargin && dbody < 0.5);
+}
 
 // Steps 8-9 for particle p with its (new) state staged in LDS (P).
 template <int ST, int Q>
@@ -805,9 +838,16 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         if (tid == 0) atomicOr(a.flags, (int)F_WINDOW);
         return;
     }
+    if (mode == 0 && !scan_needed(P)) {
+        // no node can have changed side since the last scan: as the fast
+        // path below, without testing the window
+        if (a.near.flags) mark_near(a.near, B, lo, wn);
+        return;
+    }
 
     // pass 1: solid test, node-map update, covered / uncovered nodes
     double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double mloc = 1.0;  // lower bound of |sqrt(Q) - 1| over this thread's nodes
     int nsol = 0;
     bool changed = false;
     for (int base = 0; base < nsites; base += PBLOCK * KSCAN) {
@@ -838,7 +878,10 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                 if (mode == 2) {
                     if (own[k] == me) om[s] = 0;
                 } else {
-                    in = inside_test(xc, q, ia2, gx, gy, gz, nx, ny, nz);
+                    const double Qv = quad_form(xc, q, ia2, gx, gy, gz, nx, ny, nz);
+                    in = Qv < 1.0;
+                    // sqrt(Q) <= (Q + 1) / 2, so |sqrt(Q) - 1| = |Q - 1| / (sqrt(Q) + 1) >= 2 |Q - 1| / (Q + 3)
+                    mloc = fmin(mloc, 2.0 * fabs(Qv - 1.0) / (Qv + 3.0));
                     if (in && own[k] != 0 && own[k] != me) {
                         atomicOr(a.flags, (int)F_OVERLAP);
                         in = false;
@@ -904,7 +947,36 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             }
         }
     }
+    if (mode != 2) {
+        const double wm = wmin64(mloc);
+        if (lane == 0) sh.mred[wv] = wm;
+    }
     changed = __syncthreads_or(changed);
+
+    if (mode != 2 && tid < 9) {
+        // the reference of the skip test: this pose, and the margin in
+        // distance units (sqrt(Q) is 1 / min(a, b, c)-Lipschitz in the body
+        // coordinates), shaded down for rounding
+        if (tid == 0) {
+            double m = sh.mred[0];
+            for (int w = 1; w < PWAVES; ++w) m = fmin(m, sh.mred[w]);
+            const double amin = fmin(P.axes[0], fmin(P.axes[1], P.axes[2]));
+            Pg->smargin = m * amin * (1.0 - 1e-12);
+        } else if (tid < 4) {
+            Pg->sref[tid - 1] = P.xu[tid - 1];
+        } else if (tid < 8) {
+            Pg->qref[tid - 4] = P.q[tid - 4];
+        } else {
+            // largest |x - x_c| over the window's nodes
+            const int n3[3] = {nx, ny, nz};
+            double r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double e = whole[k] ? 0.5 * n3[k] : fmax(xc[k] - lo[k], (double)(lo[k] + wn[k] - 1) - xc[k]);
+                r2 += e * e;
+            }
+            Pg->srho = sqrt(r2);
+        }
+    }
 
     if (mode == 2) {
         if (tid == 0) {

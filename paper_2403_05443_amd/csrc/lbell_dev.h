@@ -94,6 +94,10 @@ struct PartDev {
     // zm1 = sum c (rho x c)^T (3x3), zm2 = sum (rho x c)(rho x c)^T (upper
     // triangle); with zm0 = sum c c^T they give zeta at any later centre
     double zm1[9], zm2[6], xref[3];
+    // pose at the last test of the window (unwrapped centre, orientation),
+    // the smallest distance-like margin of its nodes to the surface and the
+    // largest distance of its nodes from the centre (remap skip test)
+    double sref[3], qref[4], smargin, srho;
     double dm, Pp[3], Lp[3];  // pending mass / momentum / angular momentum of transitions
     double F[3], T[3];    // hydrodynamic force and torque of the last step
     double wsum;          // sum of w_b over the current links
