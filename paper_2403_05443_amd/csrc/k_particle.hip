@@ -20,16 +20,9 @@
 
 namespace lbd {
 
-__host__ __device__ constexpr unsigned long long pack_dir(int axis) {
-    unsigned long long v = 0;
-    for (int i = 0; i < NQMAX; ++i)
-        v |= (unsigned long long)((axis == 0 ? cx(i) : (axis == 1 ? cy(i) : cz(i))) + 1) << (2 * i);
-    return v;
-}
-constexpr unsigned long long CXP = pack_dir(0), CYP = pack_dir(1), CZP = pack_dir(2);
-__device__ __forceinline__ int rcx(int b) { return (int)((CXP >> (2 * b)) & 3ull) - 1; }
-__device__ __forceinline__ int rcy(int b) { return (int)((CYP >> (2 * b)) & 3ull) - 1; }
-__device__ __forceinline__ int rcz(int b) { return (int)((CZP >> (2 * b)) & 3ull) - 1; }
+__device__ __forceinline__ int rcx(int b) { return cx(b); }
+__device__ __forceinline__ int rcy(int b) { return cy(b); }
+__device__ __forceinline__ int rcz(int b) { return cz(b); }
 // the weight of direction b in exact integer form (W w_b, W = WSCALE<Q>), and
 // 6 / W: the factor of eq. fb's moving-boundary term 2 w rho0 (u.c) / c_s^2
 template <int Q>
@@ -76,19 +69,31 @@ __device__ __forceinline__ void rotmat(const double q[4], double R[3][3]) {
 }
 
 // q(t+1) = exp(Wm / 2) q(t) (eqs. qnplus0, qnplus1): rotation by |Wm| about
-// Wm / |Wm|, Wm the mean angular velocity over the step.
+// Wm / |Wm|, Wm the mean angular velocity over the step.  With h = |Wm| / 2
+// the rotation quaternion is (cos h, (sin h / h) Wm / 2); both are even in h,
+// so for h <= 1/4 (every admissible step of a particle with max(a,b,c) >= 1)
+// their Taylor series in h^2 up to h^14 give them to rounding (the first
+// omitted terms are below 1e-19), without a square root, a division or a
+// trigonometric call.
 __device__ __forceinline__ void quat_advance(const double q[4], const double Wm[3], double qn[4]) {
-    const double nrm = sqrt(Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
-    for (int j = 0; j < 4; ++j) qn[j] = q[j];
-    if (nrm != 0.0) {
-        double sn, c;
-        sincos(0.5 * nrm, &sn, &c);
-        const double t0 = c, t1 = sn * Wm[0] / nrm, t2 = sn * Wm[1] / nrm, t3 = sn * Wm[2] / nrm;
-        qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
-        qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
-        qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
-        qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
+    const double h2 = 0.25 * (Wm[0] * Wm[0] + Wm[1] * Wm[1] + Wm[2] * Wm[2]);
+    double c, s;  // cos h and sin(h) / h
+    if (h2 <= 0.0625) {
+        c = 1.0 + h2 * (-1.0 / 2 + h2 * (1.0 / 24 + h2 * (-1.0 / 720 + h2 * (1.0 / 40320 + h2 * (-1.0 / 3628800 +
+            h2 * (1.0 / 479001600 + h2 * (-1.0 / 87178291200.0)))))));
+        s = 1.0 + h2 * (-1.0 / 6 + h2 * (1.0 / 120 + h2 * (-1.0 / 5040 + h2 * (1.0 / 362880 + h2 * (-1.0 / 39916800 +
+            h2 * (1.0 / 6227020800.0 + h2 * (-1.0 / 1307674368000.0)))))));
+    } else {
+        const double h = sqrt(h2);
+        double sn;
+        sincos(h, &sn, &c);
+        s = sn / h;
     }
+    const double t0 = c, t1 = 0.5 * s * Wm[0], t2 = 0.5 * s * Wm[1], t3 = 0.5 * s * Wm[2];
+    qn[0] = t0 * q[0] - t1 * q[1] - t2 * q[2] - t3 * q[3];
+    qn[1] = t0 * q[1] + t1 * q[0] + t2 * q[3] - t3 * q[2];
+    qn[2] = t0 * q[2] - t1 * q[3] + t2 * q[0] + t3 * q[1];
+    qn[3] = t0 * q[3] + t1 * q[2] - t2 * q[1] + t3 * q[0];
 }
 
 // Symmetric 6x6 solve A x = rhs as A = L D L^T, A in the lower triangle of
@@ -221,6 +226,14 @@ __device__ __forceinline__ int wsumi(int v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Barrier ordering LDS accesses only: global stores issued before it may
+// still be in flight after it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Deterministic block reduction of N doubles; every thread gets the sums.
 template <int N>
 __device__ __forceinline__ void block_reduce(double (&v)[N], double (*red)[PWAVES]) {
@@ -327,29 +340,54 @@ struct ZAcc {
 // zeta_TW = k (Z2 - Z1^T D^T - D Z1 + D Z0 D^T), k = rho0 / 6 (36 w = 6 w / c_s^2).
 // Both (i, j) and (j, i) evaluate the upper-triangle entry, so the matrix
 // stays exactly symmetric.
+__device__ __forceinline__ int ut3(int a, int b) {  // upper-triangle index of the symmetric 3x3 (a, b)
+    const int l = a < b ? a : b, h = a < b ? b : a;
+    return l == 0 ? h : (l == 1 ? 2 + h : 5);
+}
+// Row j of [d]x (the cross-product matrix of d), for a j known at run time.
+__device__ __forceinline__ void cross_row(const double d[3], int j, double r[3]) {
+    r[0] = j == 0 ? 0.0 : (j == 1 ? d[2] : -d[1]);
+    r[1] = j == 0 ? -d[2] : (j == 1 ? 0.0 : d[0]);
+    r[2] = j == 0 ? d[1] : (j == 1 ? -d[0] : 0.0);
+}
+
+// zeta of the current link set (eqs. drag1-drag4) at the centre x_u, from
+// the moments of the set about x_ref, d = x_u - x_ref.  Lane k < 21 of a
+// group: k < 6 an upper entry of zFU (integer sum), k < 15 an entry of zFW
+// (zTU = zFW^T), else an upper entry of zTW; each is written to Z[6 i + j]
+// and its transposed place.
 template <int Q>
-__device__ __forceinline__ double zeta_entry(const PartDev& P, const double xu[3], int i, int j, double rho0) {
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    auto ut = [](int a, int b) {  // upper-triangle index of the symmetric 3x3 (a, b)
-        const int l = a < b ? a : b, h = a < b ? b : a;
-        return l == 0 ? h : (l == 1 ? 2 + h : 5);
-    };
-    if (hi < 3) return rho0 * (double)P.zm0[ut(lo, hi)] / W6<Q>;
-    const double d[3] = {xu[0] - P.xref[0], xu[1] - P.xref[1], xu[2] - P.xref[2]};
-    const double D[3][3] = {{0.0, -d[2], d[1]}, {d[2], 0.0, -d[0]}, {-d[1], d[0], 0.0}};
+__device__ __forceinline__ void zeta_lanes(const PartDev& P, int k, double rho0, double* Z) {
+    const double d[3] = {P.xu[0] - P.xref[0], P.xu[1] - P.xref[1], P.xu[2] - P.xref[2]};
+    int i, j;
     double v;
-    if (lo < 3) {
-        const int jj = hi - 3;
-        v = P.zm1[3 * lo + jj];
-        for (int b = 0; b < 3; ++b) v -= (double)P.zm0[ut(lo, b)] * D[jj][b];
+    if (k < 6) {
+        i = k < 3 ? 0 : (k < 5 ? 1 : 2);
+        j = k < 3 ? k : (k < 5 ? k - 2 : 2);
+        v = (double)P.zm0[k];
+    } else if (k < 15) {
+        const int ii = (k - 6) / 3, jj = (k - 6) % 3;
+        double D[3];
+        cross_row(d, jj, D);
+        v = P.zm1[3 * ii + jj];
+        for (int b = 0; b < 3; ++b) v -= (double)P.zm0[ut3(ii, b)] * D[b];
+        i = ii;
+        j = 3 + jj;
     } else {
-        const int ii = lo - 3, jj = hi - 3;
-        v = P.zm2[ut(ii, jj)];
-        for (int b = 0; b < 3; ++b) v -= P.zm1[3 * b + ii] * D[jj][b] + D[ii][b] * P.zm1[3 * b + jj];
+        const int u = k - 15, ii = u < 3 ? 0 : (u < 5 ? 1 : 2), jj = u < 3 ? u : (u < 5 ? u - 2 : 2);
+        double Di[3], Dj[3];
+        cross_row(d, ii, Di);
+        cross_row(d, jj, Dj);
+        v = P.zm2[u];
+        for (int b = 0; b < 3; ++b) v -= P.zm1[3 * b + ii] * Dj[b] + Di[b] * P.zm1[3 * b + jj];
         for (int b = 0; b < 3; ++b)
-            for (int c = 0; c < 3; ++c) v += D[ii][b] * (double)P.zm0[ut(b, c)] * D[jj][c];
+            for (int c = 0; c < 3; ++c) v += Di[b] * (double)P.zm0[ut3(b, c)] * Dj[c];
+        i = 3 + ii;
+        j = 3 + jj;
     }
-    return rho0 * v / W6<Q>;
+    v = rho0 * v / W6<Q>;
+    Z[6 * i + j] = v;
+    Z[6 * j + i] = v;
 }
 
 // Remap window of a particle: axis-aligned bounding box of the ellipsoid plus
@@ -418,7 +456,10 @@ __device__ void mark_near(const NearSet& ns, const BoxDesc& B, const int wlo[3],
 struct SolveShm {
     double red[12][PWAVES];
     double bc[8];
-    double A[6][7];  // the 6x6 system, eliminated by thread 0
+    double Z[36];     // zeta of the current links at x(t)
+    double Iblk[9];   // I' + dI/dt
+    double IW[3];     // I' Omega(t)
+    double rhs[6];    // right-hand side, kept for the predictor-corrector
 };
 
 // The links of one thread (l = tid + k PBLOCK, k < KREG): codes and stored
@@ -493,7 +534,6 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     using T = typename S::T;
     double (*red)[PWAVES] = sh.red;
     double* bc = sh.bc;
-    double (*A)[7] = sh.A;
     PartDev* Pg = a.parts + p;
     const BoxDesc& B = a.boxes[P.box];
     T* f = (T*)a.f + B.foff;
@@ -515,43 +555,50 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
 
     const uint32_t* code = lr.code;
 
-    // steps 4-5, matrix part, built while the link loads are in flight: one
-    // lane per entry of [M + zFU, zFW; zTU, I' + dI/dt + zTW], with
-    // I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x (W = Omega(t)), or
-    // with the backward difference I'(t) - I'(t-1); lanes 36-38 store
-    // I' Omega(t) for the right-hand side
+    // steps 4-5, matrix part, built by the last two waves while the link
+    // loads are in flight: zeta of the current link set at x(t) from its
+    // moments (three groups of lanes: the zFU, zFW and zTW blocks, each entry
+    // also written to its transposed place), and, in one lane, the inertia
+    // block I' + dI/dt with I' = R diag(I) R^T and dI/dt = [W]x I' - I' [W]x
+    // (W = Omega(t)) or the backward difference I'(t) - I'(t-1), and I' Omega(t)
     const double M = P.M;
     const double U0[3] = {P.U[0], P.U[1], P.U[2]}, W0[3] = {P.W[0], P.W[1], P.W[2]};
-    if (tid < 39) {
-        const double Ib0 = P.Ib[0], Ib1 = P.Ib[1], Ib2 = P.Ib[2];
-        auto Il = [&](int i, int j) {
-            return Rm[i][0] * Ib0 * Rm[j][0] + Rm[i][1] * Ib1 * Rm[j][1] + Rm[i][2] * Ib2 * Rm[j][2];
-        };
-        auto Wx = [&](int i, int j) {
-            return i == j ? 0.0 : (i == 0 ? (j == 1 ? -W0[2] : W0[1]) : (i == 1 ? (j == 0 ? W0[2] : -W0[0])
-                                                                         : (j == 0 ? -W0[1] : W0[0])));
-        };
-        if (tid < 36) {
-            const int i = tid / 6, j = tid % 6;
-            double v = P.zeta[tid];
-            if (i == j && i < 3) v += M;
-            if (i >= 3 && j >= 3) {
-                const int ii = i - 3, jj = j - 3;
-                double d = 0;
-                if (a.kp.rot == 1) {
-                    double Rp[3][3];
-                    rotmat(P.qprev, Rp);
-                    d = Il(ii, jj) - (Rp[ii][0] * Ib0 * Rp[jj][0] + Rp[ii][1] * Ib1 * Rp[jj][1] +
-                                      Rp[ii][2] * Ib2 * Rp[jj][2]);
-                } else {
-                    for (int k = 0; k < 3; ++k) d += Wx(ii, k) * Il(k, jj) - Il(ii, k) * Wx(k, jj);
-                }
-                v += Il(ii, jj) + d;
-            }
-            A[i][j] = v;
+    if (tid >= PBLOCK - 64 && tid < PBLOCK - 64 + 21) {
+        zeta_lanes<Q>(P, tid - (PBLOCK - 64), rho0, sh.Z);
+    } else if (tid == PBLOCK - 128) {
+        const double Ib[3] = {P.Ib[0], P.Ib[1], P.Ib[2]};
+        double Il[3][3], Id[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Il[i][j] = Rm[i][0] * Ib[0] * Rm[j][0] + Rm[i][1] * Ib[1] * Rm[j][1] + Rm[i][2] * Ib[2] * Rm[j][2];
+        if (a.kp.rot == 1) {
+            double Rp[3][3];
+            rotmat(P.qprev, Rp);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Id[i][j] = Il[i][j] - (Rp[i][0] * Ib[0] * Rp[j][0] + Rp[i][1] * Ib[1] * Rp[j][1] +
+                                           Rp[i][2] * Ib[2] * Rp[j][2]);
         } else {
-            const int ii = tid - 36;
-            A[3 + ii][6] = Il(ii, 0) * W0[0] + Il(ii, 1) * W0[1] + Il(ii, 2) * W0[2];
+            const double Wx[3][3] = {{0.0, -W0[2], W0[1]}, {W0[2], 0.0, -W0[0]}, {-W0[1], W0[0], 0.0}};
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double d = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) d += Wx[i][k] * Il[k][j] - Il[i][k] * Wx[k][j];
+                    Id[i][j] = d;
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sh.Iblk[3 * i + j] = Il[i][j] + Id[i][j];
+            sh.IW[i] = Il[i][0] * W0[0] + Il[i][1] * W0[1] + Il[i][2] * W0[2];
         }
     }
 
@@ -608,20 +655,23 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         for (int i = 0; i < 3; ++i) {
             const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
             rhs[i] = M * U0[i] + acc[i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
-            rhs[3 + i] = A[3 + i][6] + acc[3 + i] + P.Text[i] + P.Lp[i];
+            rhs[3 + i] = sh.IW[i] + acc[3 + i] + P.Text[i] + P.Lp[i];
         }
-        // The matrix is symmetric (zeta is, I' is, and so are the commutator
-        // of [Omega]x with I' and a difference of two inertias), so the
-        // elimination runs as A = L D L^T on the lower triangle, in registers.
+        // [M + zFU, zFW; zTU, I' + dI/dt + zTW].  The matrix is symmetric
+        // (zeta is, I' is, and so are the commutator of [Omega]x with I' and a
+        // difference of two inertias), so the elimination runs as A = L D L^T
+        // on the lower triangle, in registers.
         double Lw[6][6], dv[6], di[6], sol[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
-            for (int j = 0; j <= i; ++j) Lw[i][j] = A[i][j];
+            for (int j = 0; j <= i; ++j)
+                Lw[i][j] = sh.Z[6 * i + j] + (i >= 3 ? (j >= 3 ? sh.Iblk[3 * (i - 3) + j - 3] : 0.0)
+                                                     : (i == j ? M : 0.0));
         const bool ok = ldlt_solve6(Lw, dv, di, rhs, sol);
         if (a.kp.rot == 2) {  // the prediction, checked after the corrector
             for (int i = 0; i < 6; ++i) {
-                A[i][6] = rhs[i];
+                sh.rhs[i] = rhs[i];
                 bc[i] = sol[i];
             }
         } else {
@@ -642,14 +692,14 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             const double Ib0 = P.Ib[0], Ib1 = P.Ib[1], Ib2 = P.Ib[2];
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
-                rhs[i] = A[i][6];
+                rhs[i] = sh.rhs[i];
 #pragma unroll
                 for (int j = 0; j <= i; ++j)
-                    Lw[i][j] = i >= 3 && j >= 3
-                                   ? P.zeta[6 * i + j] + (Rs[i - 3][0] * Ib0 * Rs[j - 3][0] +
-                                                          Rs[i - 3][1] * Ib1 * Rs[j - 3][1] +
-                                                          Rs[i - 3][2] * Ib2 * Rs[j - 3][2])
-                                   : A[i][j];
+                    Lw[i][j] = sh.Z[6 * i + j] + (i >= 3 ? (j >= 3 ? Rs[i - 3][0] * Ib0 * Rs[j - 3][0] +
+                                                                         Rs[i - 3][1] * Ib1 * Rs[j - 3][1] +
+                                                                         Rs[i - 3][2] * Ib2 * Rs[j - 3][2]
+                                                                   : 0.0)
+                                                         : (i == j ? M : 0.0));
             }
             const bool ok = ldlt_solve6(Lw, dv, di, rhs, sol);
             accept_solution(a, P, ok, sol, U0, W0, bc);
@@ -657,17 +707,19 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
     __syncthreads();
 
-    // step 7, the hydrodynamic force/torque and zeta at x(t+1), one piece per
-    // lane, spread over the upper four waves (one per SIMD), while all waves
-    // do the bounce-back (which uses x_c(t), q(t) from registers and U(t+1),
-    // Omega(t+1) from bc).  No lane reads an LDS field another lane writes here.
+    // step 7, the hydrodynamic force/torque, position and orientation, spread
+    // over three of the upper four waves (one per SIMD), while all waves do
+    // the bounce-back (which uses x_c(t), q(t) from registers and U(t+1),
+    // Omega(t+1) from bc).  No lane reads an LDS field another lane writes
+    // here.  zeta at x(t+1) is evaluated from the link moments when the next
+    // step starts.
     static_assert(PBLOCK >= 256, "the state update uses four waves");
     if (tid >= PBLOCK - 64) {
         const int k = tid - (PBLOCK - 64);
         if (k < 6) {  // F, T over the step (eqs. Fsplit, Tsplit)
             const int i = k % 3;
             double z = 0;
-            for (int j = 0; j < 6; ++j) z += P.zeta[6 * k + j] * bc[j];
+            for (int j = 0; j < 6; ++j) z += sh.Z[6 * k + j] * bc[j];
             // each lane clears, after reading it, the pending impulse it used
             if (k < 3) {
                 Pg->F[i] = acc[i] + P.Pp[i] - z;
@@ -682,13 +734,6 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             Pg->dm = 0.0;
             if (keep_lds) P.dm = 0.0;
         }
-    } else if (tid >= PBLOCK - 128 && tid < PBLOCK - 128 + 36) {
-        // zeta of the current link set at x(t+1), from its moments; the remap
-        // replaces it only if some node changes side
-        const int e = tid - (PBLOCK - 128);
-        double xu[3];
-        for (int i = 0; i < 3; ++i) xu[i] = xu0[i] + 0.5 * (bc[i] + U0[i]);
-        Pg->zeta[e] = zeta_entry<Q>(P, xu, e / 6, e % 6, rho0);
     } else if (tid >= PBLOCK - 192 && tid < PBLOCK - 192 + 3) {  // position (eq. posupdate), wrapped into the box
         const int i = tid - (PBLOCK - 192);
         const int n3 = i == 0 ? nx : (i == 1 ? ny : nz);
@@ -804,8 +849,11 @@ __device__ __forceinline__ bool scan_needed(const PartDev& P) {
 }
 
 // Steps 8-9 for particle p with its (new) state staged in LDS (P).
+// stores_done: the bounce-back stores of the step are complete (a kernel
+// boundary lies between); otherwise the window test waits for them first.
 template <int ST, int Q>
-__device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const PartDev& P, RemapShm& sh, uint32_t* smem) {
+__device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const PartDev& P, RemapShm& sh, uint32_t* smem,
+                                            bool stores_done) {
     using S = Store<ST>;
     using T = typename S::T;
     uint32_t* bits = smem;
@@ -844,6 +892,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         if (a.near.flags) mark_near(a.near, B, lo, wn);
         return;
     }
+    if (!stores_done) __syncthreads();  // the bounce-back writes before the covered-node reads
 
     // pass 1: solid test, node-map update, covered / uncovered nodes
     double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1081,29 +1130,15 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         if (lane == 0) ired[k][wv] = sm;
     }
     __syncthreads();
-    // one lane per output: zeta_FU = (2 rho0 / c_s^2) sum w c c = rho0 (integer sum of 36 w c c) / 6,
-    // the other blocks from the FP64 sums
+    // one lane per output: the integer sums, the moments of the new link set
+    // about this centre (zeta follows from them, eqs. drag1-drag4, when the
+    // next step starts), the transition totals and the solid count
     auto itot = [&](int k) {
         int t = 0;
         for (int w = 0; w < PWAVES; ++w) t += ired[k][w];
         return t;
     };
-    if (tid < 36) {
-        const int i = tid / 6, j = tid % 6;
-        double z;
-        if (i < 3 && j < 3) {
-            const int lo_ = i < j ? i : j, hi_ = i < j ? j : i;  // upper-triangle index of (i, j)
-            z = rho0 * itot(lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5)) / W6<Q>;
-        } else if (i < 3) {
-            z = rho0 * red[7 + 3 * i + (j - 3)][0] / W6<Q>;
-        } else if (j < 3) {
-            z = rho0 * red[7 + 3 * j + (i - 3)][0] / W6<Q>;
-        } else {
-            const int ii = i - 3, jj = j - 3, lo_ = ii < jj ? ii : jj, hi_ = ii < jj ? jj : ii;
-            z = rho0 * red[16 + (lo_ == 0 ? hi_ : (lo_ == 1 ? 2 + hi_ : 5))][0] / W6<Q>;
-        }
-        Pg->zeta[tid] = z;
-    } else if (tid == 36) {
+    if (tid == 36) {
         Pg->wsum = itot(6) / (double)WSCALE<Q>;
         Pg->nlinks = running < lcap ? running : lcap;
     } else if (tid >= 37 && tid < 44 && mode == 0) {
@@ -1133,7 +1168,7 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_remap(LaunchPart a) {
     __shared__ RemapShm sh;
     const int p = a.first + (int)blockIdx.x;
     stage_particle(a.parts + p, &P);
-    remap_phase<ST, Q>(a, p, P, sh, smem);
+    remap_phase<ST, Q>(a, p, P, sh, smem, true);
 }
 
 // Steps 3-9 in one work-group, for boxes that hold one particle: the record
@@ -1151,8 +1186,10 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
     LinkRegs<typename Store<ST>::T> lr;
     load_particle<ST, Q>(a, p, &P, lr);
     solve_phase<ST, Q>(a, p, P, sh.s, lr, true);
-    __syncthreads();  // bounce-back writes before the covered-node reads of the remap
-    remap_phase<ST, Q>(a, p, P, sh.r, smem);
+    // the new state in LDS before the remap; the bounce-back stores may still
+    // be in flight (the remap waits for them only if it tests the window)
+    lds_barrier();
+    remap_phase<ST, Q>(a, p, P, sh.r, smem, false);
 }
 
 // Near set from the particles' current positions (set-up and re-tuning).

@@ -23,21 +23,35 @@ constexpr uint32_t SITE_MASK = (1u << SITE_BITS) - 1u;
 __host__ __device__ constexpr int corner(int i, int flip) {  // component of corner i >= 19
     return ((i & 1) ? 1 : -1) * (((i - 19) >> 1) == flip ? -1 : 1);
 }
-__host__ __device__ constexpr int cx(int i) {
+__host__ __device__ constexpr int cx_def(int i) {
     return i >= 19 ? corner(i, 3)
          : (i == 1 || i == 7 || i == 9 || i == 11 || i == 13 ? 1
          : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 ? -1 : 0));
 }
-__host__ __device__ constexpr int cy(int i) {
+__host__ __device__ constexpr int cy_def(int i) {
     return i >= 19 ? corner(i, 2)
          : (i == 3 || i == 7 || i == 10 || i == 15 || i == 17 ? 1
          : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 ? -1 : 0));
 }
-__host__ __device__ constexpr int cz(int i) {
+__host__ __device__ constexpr int cz_def(int i) {
     return i >= 19 ? corner(i, 1)
          : (i == 5 || i == 11 || i == 14 || i == 15 || i == 18 ? 1
          : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0));
 }
+// The same components packed two bits per direction (c + 1), so that a
+// direction known only at run time costs a shift and a mask rather than a
+// chain of compares (which diverges across a wave's lanes).
+template <int AXIS>
+__host__ __device__ constexpr unsigned long long pack_c() {
+    unsigned long long v = 0;
+    for (int i = 0; i < 27; ++i)
+        v |= (unsigned long long)((AXIS == 0 ? cx_def(i) : (AXIS == 1 ? cy_def(i) : cz_def(i))) + 1) << (2 * i);
+    return v;
+}
+constexpr unsigned long long CX_PACK = pack_c<0>(), CY_PACK = pack_c<1>(), CZ_PACK = pack_c<2>();
+__host__ __device__ constexpr int cx(int i) { return (int)((CX_PACK >> (2 * i)) & 3ull) - 1; }
+__host__ __device__ constexpr int cy(int i) { return (int)((CY_PACK >> (2 * i)) & 3ull) - 1; }
+__host__ __device__ constexpr int cz(int i) { return (int)((CZ_PACK >> (2 * i)) & 3ull) - 1; }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 // weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216
 template <int Q>
@@ -88,11 +102,11 @@ struct PartDev {
     double M, Ib[3];      // mass and body inertia
     double Fext[3], Text[3];
     double B1, B2;        // squirmer modes
-    double zeta[36];      // [F;T] x [U;W] drag matrix of the current links
     // moments of the current link set about the unwrapped centre xref at
-    // which it was enumerated (rho = link midpoint - xref, weights 36 w):
+    // which it was enumerated (rho = link midpoint - xref, weights W w):
     // zm1 = sum c (rho x c)^T (3x3), zm2 = sum (rho x c)(rho x c)^T (upper
-    // triangle); with zm0 = sum c c^T they give zeta at any later centre
+    // triangle); with zm0 = sum c c^T they give the [F;T] x [U;W] drag
+    // matrix zeta at any later centre
     double zm1[9], zm2[6], xref[3];
     // pose at the last test of the window (unwrapped centre, orientation),
     // the smallest distance-like margin of its nodes to the surface and the
