@@ -603,11 +603,20 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
 
     // step 3: velocity-independent force and torque, slip part included (the
-    // two only ever enter summed)
+    // two only ever enter summed).  For the links held in registers (k >= 0)
+    // the same pass keeps what the bounce-back needs apart from U(t+1) and
+    // Omega(t+1): the slot it writes, r x c, the weight factor and the
+    // velocity-independent part of the value (eq. fb: the post-collision
+    // population, the transition mass share, the slip term), so that the
+    // bounce-back after the solve is a six-term dot product and a store.
     double acc[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = 0.0;
-    auto accumulate = [&](uint32_t cd, double fb) {
+    const double dmw = (P.wsum > 0.0 ? P.dm / P.wsum : 0.0) / (double)WSCALE<Q>;
+    double bb_base[KREG], bb_kw[KREG], bb_rc[KREG][3];
+    long long bb_slot[KREG];
+    int bb_b[KREG];
+    auto accumulate = [&](uint32_t cd, double fb, int k) {
         const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
         int x, y;
         const int z = divmod(divmod(s, nx, rnx, x), ny, rny, y);
@@ -622,10 +631,12 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         acc[3] += fb2 * rc0;
         acc[4] += fb2 * rc1;
         acc[5] += fb2 * rc2;
+        const double kw = (rw<Q>(b) / W6<Q>) * rho0;
+        double kuc = 0.0;
         if (sq) {
             double us[3];
             squirmer_slip(ax, bx, e, B1, B2, r, us);
-            const double kuc = (rw<Q>(b) / W6<Q>) * rho0 * (us[0] * c0 + us[1] * c1 + us[2] * c2);
+            kuc = kw * (us[0] * c0 + us[1] * c1 + us[2] * c2);
             acc[0] -= kuc * c0;
             acc[1] -= kuc * c1;
             acc[2] -= kuc * c2;
@@ -633,16 +644,28 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
             acc[4] -= kuc * rc1;
             acc[5] -= kuc * rc2;
         }
+        if (k >= 0) {
+            int pd, ps;  // the slot of f_opp(b)(x) the fluid node reads next
+            pre_slot_open(a.kp.conv, ropp(b), x, y, z, nx, ny, nz, pd, ps);
+            bb_slot[k] = (long long)pd * st + ps;
+            bb_base[k] = (fb + dmw * rw<Q>(b)) - kuc;
+            bb_kw[k] = kw;
+            bb_rc[k][0] = rc0;
+            bb_rc[k][1] = rc1;
+            bb_rc[k][2] = rc2;
+            bb_b[k] = b;
+        }
     };
     double fbv[KREG];
 #pragma unroll
     for (int k = 0; k < KREG; ++k) fbv[k] = S::cv64(lr.raw[k], inv);
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
-        if (tid + k * PBLOCK < nl) accumulate(code[k], fbv[k]);
+        if (tid + k * PBLOCK < nl) accumulate(code[k], fbv[k], k);
     for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
         const uint32_t cd = L[l];
-        accumulate(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv));
+        accumulate(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv),
+                   -1);
     }
     block_reduce<6>(acc, red);
 
@@ -768,7 +791,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
 
     // step 6: bounce-back into the solid slot the fluid node pulls next step
-    const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]}, dmw = bc[6] / (double)WSCALE<Q>;
+    const double Un[3] = {bc[0], bc[1], bc[2]}, Wn[3] = {bc[3], bc[4], bc[5]};
     auto bounce = [&](uint32_t cd, double fb) {
         const int s = (int)(cd & SITE_MASK), b = (int)(cd >> SITE_BITS);
         int x, y;
@@ -795,7 +818,13 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     };
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
-        if (tid + k * PBLOCK < nl) bounce(code[k], fbv[k]);
+        if (tid + k * PBLOCK < nl) {
+            // u_b . c = U . c + Omega . (r x c)
+            const int b = bb_b[k];
+            const double uc = (Un[0] * rcx(b) + Un[1] * rcy(b) + Un[2] * rcz(b)) +
+                              (Wn[0] * bb_rc[k][0] + Wn[1] * bb_rc[k][1] + Wn[2] * bb_rc[k][2]);
+            S::st64(f + bb_slot[k], bb_base[k] - bb_kw[k] * uc, scl);
+        }
     for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
         const uint32_t cd = L[l];
         bounce(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv));
