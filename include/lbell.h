@@ -296,7 +296,8 @@ lb_status lb_get_step(lb_ctx* ctx, long long* step);
  * with the same configuration and boxes (in either population layout: the
  * file records its own, and the load converts to the one the context's
  * collide-stream variant uses).  LB_EIO on file errors, LB_EINVAL on
- * a mismatching file.  Synchronise. */
+ * a mismatching file (another configuration, or a file format version other
+ * than this library's, currently 3).  Synchronise. */
 lb_status lb_save(lb_ctx* ctx, const char* path);
 lb_status lb_load(lb_ctx* ctx, const char* path);
 

@@ -1126,9 +1126,12 @@ lb_status lb_get_step(lb_ctx* ctx, long long* step) {
 }
 
 namespace {
+// 3: the particle record carries the previous orientation and the remap
+// skip reference, and no drag matrix (rebuilt from the link moments)
+constexpr int CKPT_VERSION = 3;
 struct CkptHeader {
     char magic[8];
-    int version, nboxes, storage, np, cur, pad;
+    int version, nboxes, storage, np, cur, pad;  // version: CKPT_VERSION
     long long step, pop_elems, omap_elems, link_used;
     size_t part_bytes;
 };
@@ -1141,7 +1144,7 @@ lb_status lb_save(lb_ctx* ctx, const char* path) {
     if (!fp) return fail(ctx, LB_EIO, "cannot open checkpoint for writing");
     CkptHeader h{};
     std::memcpy(h.magic, "LBELLCK1", 8);
-    h.version = 2;
+    h.version = CKPT_VERSION;
     h.pad = ctx->aa ? 1 : 0;  // populations in the in-place layout (cur = parity)
     h.nboxes = (int)ctx->boxes.size();
     h.storage = ctx->cfg.storage;
@@ -1181,7 +1184,8 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
         std::fclose(fp);
         return fail(ctx, LB_EIO, "not a checkpoint");
     }
-    if (h.nboxes != (int)ctx->boxes.size() || h.storage != ctx->cfg.storage || h.pop_elems != ctx->L.pop_elems ||
+    if (h.version != CKPT_VERSION || h.nboxes != (int)ctx->boxes.size() || h.storage != ctx->cfg.storage ||
+        h.pop_elems != ctx->L.pop_elems ||
         h.omap_elems != ctx->L.omap_elems || h.np > ctx->L.max_particles || h.link_used > ctx->L.link_pool ||
         h.part_bytes != sizeof(PartDev)) {
         std::fclose(fp);
