@@ -332,6 +332,28 @@ def test_checkpoint_roundtrip_bitwise(lb):
     assert np.array_equal(a.fields()[1], b.fields()[1])
 
 
+def test_checkpoint_of_another_version_is_rejected(lb):
+    """The header's format version (the int after the 8-byte magic) must be
+    this library's; a file claiming another is refused with LB_EINVAL and the
+    context keeps running."""
+    import struct
+    g, _ = pair(lb, (20, 18, 22), "trt", 0.8, "fp32", counterforce=True)
+    p = g.add_ellipsoid((9.3, 8.7, 10.1), (5.0, 2.5, 2.0), (1, 0, 0, 0))
+    g.step(5)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        g.save(path)
+        raw = bytearray(open(path, "rb").read())
+        (ver,) = struct.unpack_from("<i", raw, 8)
+        struct.pack_into("<i", raw, 8, ver - 1)
+        open(path, "wb").write(bytes(raw))
+        with pytest.raises(lb.LBError) as e:
+            g.load(path)
+        assert lb.STATUS[e.value.status] == "LB_EINVAL"
+    g.step(5)
+    assert g.step_count() == 10 and np.isfinite(g.particle(p)["U"]).all()
+
+
 def test_nonfinite_watchdog(lb):
     g, _ = pair(lb, (16, 16, 16), "bgk", 1.0, "fp32")
     assert g.nonfinite() == 0
