@@ -170,9 +170,10 @@ __host__ __device__ inline void pre_slot_open(int cv, int i, int x, int y, int z
 }
 
 // Rounding dither of the half formats: one murmur3 32-bit finalisation per
-// (site of its box, step) seeds the site; direction i takes the high bits of
-// (seed + i * golden) * an odd constant.  A function of (site, direction,
-// step) only, so every collide-stream variant rounds identically.
+// (site of its box, step) seeds the site; direction i takes
+// (seed + i * golden) * an odd constant, whose high bits are the random ones.
+// A function of (site, direction, step) only, so every collide-stream
+// variant rounds identically.
 __device__ __forceinline__ uint32_t dither_seed(uint32_t site, uint32_t step) {
     uint32_t h = site * 0x9E3779B1u + step * 0x85EBCA77u;
     h ^= h >> 16;
@@ -182,9 +183,9 @@ __device__ __forceinline__ uint32_t dither_seed(uint32_t site, uint32_t step) {
     h ^= h >> 16;
     return h;
 }
-// 16 dither bits (low half of the result) for direction dir
+// the dither word of direction dir (random in its high 16 bits)
 __device__ __forceinline__ uint32_t dither_bits(uint32_t seed, int dir) {
-    return ((seed + (uint32_t)dir * 0x9E3779B9u) * 0x2C1B3C6Du) >> 16;
+    return (seed + (uint32_t)dir * 0x9E3779B9u) * 0x2C1B3C6Du;
 }
 
 }  // namespace lbd
@@ -221,19 +222,20 @@ template <> struct Store<ST_F16> {
     using R = float;
     static __device__ __forceinline__ R ld(const T* p, R inv) { return (float)*p * inv; }
     static __device__ __forceinline__ void st(T* p, R v, R s) { *p = (_Float16)(v * s); }
-    // Stochastic rounding in the normal range: the 13 FP32 mantissa bits that
-    // FP16 drops get r's low bits added before they are cut, so a value
-    // rounds up with probability equal to its distance from the lower
-    // neighbour; increments far below one FP16 ulp (the counter-force) then
-    // survive in expectation instead of being rounded away in a steady flow.
+    // Stochastic rounding: a value rounds up with probability equal to its
+    // distance from the lower FP16 neighbour (over one ulp), so increments far
+    // below one FP16 ulp (the counter-force) survive in expectation instead
+    // of being rounded away in a steady flow.  The conversion instruction
+    // does it in one step, normal and subnormal range alike, drawing on the
+    // high bits of r (checked: unbiased to the sampling noise over 2^20 draws,
+    // and the low 16 bits of r alone have no effect); a value rounded up past
+    // the largest finite half becomes infinite, which the non-finite watchdog
+    // reports.
     static __device__ __forceinline__ void st_dither(T* p, R v, R s, uint32_t r) {
-        const float x = v * s, ax = fabsf(x);
-        if (ax >= 6.103515625e-05f && ax < 65504.f) {
-            const uint32_t u = (__float_as_uint(x) + (r >> 3)) & ~0x1FFFu;  // 13 of the 16 bits
-            *p = (_Float16)__uint_as_float(u);
-        } else {
-            *p = (_Float16)x;
-        }
+        typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+        half2_t o = {(_Float16)0.0f, (_Float16)0.0f};
+        o = __builtin_amdgcn_cvt_sr_f16_f32(o, v * s, r, false);
+        *p = o[0];
     }
     static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)(float)*p * inv; }
     static __device__ __forceinline__ double cv64(T v, double inv) { return (double)(float)v * inv; }
@@ -250,10 +252,11 @@ template <> struct Store<ST_BF16> {
     using R = float;
     static __device__ __forceinline__ R ld(const T* p, R inv) { return bf16_to_f32(*p) * inv; }
     static __device__ __forceinline__ void st(T* p, R v, R s) { *p = f32_to_bf16(v * s); }
-    // stochastic rounding: r's low 16 bits added below the kept mantissa, then cut
+    // stochastic rounding: r's high 16 bits added below the kept mantissa,
+    // then cut
     static __device__ __forceinline__ void st_dither(T* p, R v, R s, uint32_t r) {
         const float x = v * s;
-        *p = isfinite(x) ? (uint16_t)((__float_as_uint(x) + (r & 0xFFFFu)) >> 16) : f32_to_bf16(x);
+        *p = isfinite(x) ? (uint16_t)((__float_as_uint(x) + (r >> 16)) >> 16) : f32_to_bf16(x);
     }
     static __device__ __forceinline__ double ld64(const T* p, double inv) { return (double)bf16_to_f32(*p) * inv; }
     static __device__ __forceinline__ double cv64(T v, double inv) { return (double)bf16_to_f32(v) * inv; }
