@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="run the domain-size (32^3-512^3) and resolution studies of the settling spheroid "
                          "instead of the benchmark and print their results as one JSON line")
+    ap.add_argument("--half-steps", type=int, default=500,
+                    help="steps of the same workload with FP16 storage (0: skip; only with --storage fp32)")
     ap.add_argument("--d3q27-steps", type=int, default=500,
                     help="steps of the same spheroid workload on the D3Q27 lattice (0: skip)")
     ap.add_argument("--suspension-steps", type=int, default=100,
@@ -298,6 +300,17 @@ def main():
                            "k1_achieved_gbs": round(e["achieved_gbs"], 1),
                            "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
                            "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
+    if args.half_steps > 0 and args.storage == "fp32":
+        # the same inclined spheroid with FP16 deviation storage (FP32 collide)
+        Wh = workloads.c2("fp16", args.size, lattice=args.lattice)
+        lat, e = measure(Wh, args.half_steps, 50, args.graph)
+        del lat
+        out["fp16"] = {"workload": Wh.name, "sites": Wh.sites, "storage": "fp16",
+                       "mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 5),
+                       "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 5),
+                       "k1_bytes_per_launch": e["alg_bytes"], "k1_achieved_gbs": round(e["achieved_gbs"], 1),
+                       "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                       "phase_ms_per_step": {k: round(v, 5) for k, v in e["phase_ms"].items()}}
     if args.d3q27_steps > 0:
         Wq = workloads.c2(args.storage, args.size, lattice=27)
         lat, e = measure(Wq, args.d3q27_steps, 50, args.graph)
