@@ -310,6 +310,7 @@ def main():
                        "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 5),
                        "k1_bytes_per_launch": e["alg_bytes"], "k1_achieved_gbs": round(e["achieved_gbs"], 1),
                        "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                       "k1_traffic": traffic_record(src_sha, Wh.name, "fp16", e["variant"]),
                        "phase_ms_per_step": {k: round(v, 5) for k, v in e["phase_ms"].items()}}
     if args.d3q27_steps > 0:
         Wq = workloads.c2(args.storage, args.size, lattice=27)
