@@ -73,11 +73,44 @@ struct Pull {
     }
 };
 
+// c_i . v with the zero components of c_i left out and the unit ones taken
+// as a sign: under IEEE rules 0 * v (v might be infinite) and 1 * v are not
+// folded away by the compiler, and they were most of the collision's
+// instructions.  The value equals the plain dot product (up to the sign of a
+// zero result).  i is a compile-time constant after unrolling, so every
+// branch here folds.
+template <typename R>
+__device__ __forceinline__ R dotc(int i, R vx, R vy, R vz) {
+    R s = R(0);
+    bool any = false;
+    if (cx(i) != 0) {
+        s = cx(i) > 0 ? vx : -vx;
+        any = true;
+    }
+    if (cy(i) != 0) {
+        const R t = cy(i) > 0 ? vy : -vy;
+        s = any ? s + t : t;
+        any = true;
+    }
+    if (cz(i) != 0) {
+        const R t = cz(i) > 0 ? vz : -vz;
+        s = any ? s + t : t;
+    }
+    return s;
+}
+
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// 1 / x: the hardware reciprocal in FP32 (1 ulp; every variant uses it), the
+// correctly rounded quotient in FP64
+__device__ __forceinline__ float rcpr(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcpr(double x) { return 1.0 / x; }
+
 // Collision on deviations d_i = f_i - w_i rho0 (algebraically identical to
-// the full-population forms of Sec. II.A).  FP contraction is off: every
-// collide-stream variant then rounds identically, so results never depend on
-// which variant the tuner picked (the kernel is bandwidth-bound; the extra
-// multiply-adds cost nothing measurable).
+// the full-population forms of Sec. II.A).  FP contraction is off and the
+// fused multiply-adds are written out: every collide-stream variant then
+// rounds identically, so results never depend on which variant the tuner
+// picked.
 template <typename R, int COLL, int Q>
 __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf, R g0, R g1, R g2) {
 #pragma clang fp contract(off)
@@ -90,31 +123,43 @@ __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf,
         if (cz(i)) jz += cz(i) * f[i];
     }
     const R rho = rho0 + drho;
-    const R ir = R(1) / rho;
+    const R ir = rcpr(rho);
     const R ux = jx * ir, uy = jy * ir, uz = jz * ir;
-    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
-    if (COLL == 0) {  // BGK
+    const R usq = R(1.5) * fmar(ux, ux, fmar(uy, uy, uz * uz));
+    // w rho and w drho per weight class (the rest, the axes, the edges, the
+    // corners); i is a compile-time constant after unrolling
+    auto wcls = [](int i) { return i == 0 ? 0 : (i <= 6 ? 1 : (i <= 18 ? 2 : 3)); };
+    R wr[4], wd[4], w3r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int rep = k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? 7 : 19));
+        wr[k] = R(wgt<Q>(rep)) * rho;
+        wd[k] = R(wgt<Q>(rep)) * drho;
+        w3r[k] = R(3) * wr[k];
+    }
+    if (COLL == 0) {  // BGK: f_eq = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2))
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
-            const R feq = R(wgt<Q>(i)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - usq));
-            f[i] = f[i] - om * (f[i] - feq);
+            const R cu = dotc<R>(i, ux, uy, uz);
+            const R feq = fmar(wr[wcls(i)], fmar(cu, fmar(R(4.5), cu, R(3)), -usq), wd[wcls(i)]);
+            f[i] = fmar(-om, f[i] - feq, f[i]);
         }
     } else if (COLL == 1) {  // TRT
-        {
-            const R feq = R(wgt<Q>(0)) * (drho - rho * usq);
-            f[0] = f[0] - om * (f[0] - feq);
-        }
+        f[0] = fmar(-om, f[0] - fmar(-wr[0], usq, wd[0]), f[0]);
 #pragma unroll
         for (int i = 1; i < Q; i += 2) {
-            const int o = i + 1;
-            const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
-            const R ep = R(wgt<Q>(i)) * (drho + rho * (R(4.5) * cu * cu - usq));
-            const R em = R(wgt<Q>(i)) * rho * R(3) * cu;
-            const R fp = R(0.5) * (f[i] + f[o]), fm = R(0.5) * (f[i] - f[o]);
-            const R a = om * (fp - ep), b = omm * (fm - em);
-            f[i] = f[i] - a - b;
-            f[o] = f[o] - a + b;
+            // symmetric and antisymmetric parts of the pair (i, opp(i)) and
+            // of its equilibrium: e+ = w (drho + rho (4.5 cu^2 - 1.5 u^2)),
+            // e- = 3 w rho cu; a = om+ (f+ - e+), b = om- (f- - e-)
+            const int o = i + 1, k = wcls(i);
+            const R cu = dotc<R>(i, ux, uy, uz);
+            const R ep = fmar(wr[k], fmar(R(4.5) * cu, cu, -usq), wd[k]);
+            const R em = w3r[k] * cu;
+            const R s = f[i] + f[o], d = f[i] - f[o];
+            const R a = fmar(R(0.5) * om, s, -(om * ep));
+            const R b = fmar(R(0.5) * omm, d, -(omm * em));
+            f[i] = f[i] - (a + b);
+            f[o] = f[o] - (a - b);
         }
     } else {  // hydrodynamic modes relaxed with tau, ghost modes to equilibrium
         R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
@@ -138,7 +183,7 @@ __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf,
         const R tr3 = (xxx + xyy + xzz) * R(1.0 / 3.0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
+            const R cu = dotc<R>(i, ux, uy, uz);
             R cxc = 0;
             if (cx(i)) cxc += xxx;
             if (cy(i)) cxc += xyy;
@@ -149,10 +194,13 @@ __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf,
             f[i] = R(wgt<Q>(i)) * (drho + R(3) * rho * cu + R(4.5) * (cxc - tr3));
         }
     }
-    if (cf) {  // uniform counter-force, w_i (c_i . g) / c_s^2
+    if (cf) {  // uniform counter-force, w_i (c_i . g) / c_s^2 (opposite for opp(i))
 #pragma unroll
-        for (int i = 1; i < Q; ++i)
-            f[i] += R(3.0 * wgt<Q>(i)) * rho0 * (R(cx(i)) * g0 + R(cy(i)) * g1 + R(cz(i)) * g2);
+        for (int i = 1; i < Q; i += 2) {
+            const R t = R(3.0 * wgt<Q>(i)) * rho0 * dotc<R>(i, g0, g1, g2);
+            f[i] += t;
+            f[i + 1] -= t;
+        }
     }
 }
 

@@ -170,10 +170,12 @@ __host__ __device__ inline void pre_slot_open(int cv, int i, int x, int y, int z
 }
 
 // Rounding dither of the half formats: one murmur3 32-bit finalisation per
-// (site of its box, step) seeds the site; direction i takes
-// (seed + i * golden) * an odd constant, whose high bits are the random ones.
-// A function of (site, direction, step) only, so every collide-stream
-// variant rounds identically.
+// (site of its box, step) seeds the site; the direction pair (2k-1, 2k) shares
+// p = (seed + k * golden) * an odd constant: the first takes its high 16
+// bits, the second its low 16 bits (uniform too: the low half of the product
+// is a bijection of the seed's uniform low half) moved up, the conversions
+// drawing on the high bits.  A function of (site, direction, step) only, so
+// every collide-stream variant rounds identically.
 __device__ __forceinline__ uint32_t dither_seed(uint32_t site, uint32_t step) {
     uint32_t h = site * 0x9E3779B1u + step * 0x85EBCA77u;
     h ^= h >> 16;
@@ -183,9 +185,11 @@ __device__ __forceinline__ uint32_t dither_seed(uint32_t site, uint32_t step) {
     h ^= h >> 16;
     return h;
 }
-// the dither word of direction dir (random in its high 16 bits)
+// the dither word of direction dir (random in its high 16 bits); dir is a
+// compile-time constant in the kernels, so a pair's product is formed once
 __device__ __forceinline__ uint32_t dither_bits(uint32_t seed, int dir) {
-    return (seed + (uint32_t)dir * 0x9E3779B9u) * 0x2C1B3C6Du;
+    const uint32_t p = (seed + (uint32_t)((dir + 1) >> 1) * 0x9E3779B9u) * 0x2C1B3C6Du;
+    return (dir & 1) ? p : (p << 16);
 }
 
 }  // namespace lbd
