@@ -31,10 +31,12 @@ struct Pull {
 
     // Pre-collision populations of fluid site (x,y,z) as deviations, from
     // storage in convention CIN.
+    // wsc: the scale of the result (1 for deviations; the storage scale when
+    // inv_scale is 1 and the stored values are taken as they are)
     template <int CIN>
     static __device__ __forceinline__ void pull(const BoxDesc& B, const T* fi, int s,
                                                 int x, int y, int z, R inv_scale, R rho0,
-                                                bool walls, R (&f)[Q]) {
+                                                bool walls, R (&f)[Q], R wsc = R(1)) {
 #pragma clang fp contract(off)
         const int nx = B.nx, ny = B.ny, nz = B.nz;
         const long long st = B.stride;
@@ -55,7 +57,7 @@ struct Pull {
                 const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
                 const long long off = CIN == CV_PULL ? (long long)opp(i) * st + s
                                     : (CIN == CV_EVEN ? (long long)i * st + s : (long long)opp(i) * st + src);
-                f[i] = S::ld(fi + off, inv_scale) + (R)(6.0 * wgt<Q>(i)) * rho0 * cu;
+                f[i] = S::ld(fi + off, inv_scale) + (R)(6.0 * wgt<Q>(i)) * rho0 * cu * wsc;
             } else {
                 const long long off = CIN == CV_PULL ? (long long)i * st + src
                                     : (CIN == CV_EVEN ? (long long)opp(i) * st + src : (long long)i * st + s);
@@ -111,9 +113,26 @@ __device__ __forceinline__ double rcpr(double x) { return 1.0 / x; }
 // fused multiply-adds are written out: every collide-stream variant then
 // rounds identically, so results never depend on which variant the tuner
 // picked.
-template <typename R, int COLL, int Q>
-__device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf, R g0, R g1, R g2) {
+// SCALED (the half formats): f holds the stored, scaled deviations
+// sc (f_i - w_i rho0) and the result is scaled the same way, so that loads
+// and stores need no multiply per population; the density and velocity are
+// formed unscaled (isc = 1 / sc), and w rho and the counter-force term carry
+// the scale.  sc is a power of two, so every product and sum here is the
+// unscaled one times sc exactly: the results are those of scaling at the
+// loads and stores, bit for bit.  The regularised collision unscales and
+// rescales instead.
+template <typename R, int COLL, int Q, bool SCALED = false>
+__device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf, R g0, R g1, R g2, R sc = R(1),
+                                        R isc = R(1)) {
 #pragma clang fp contract(off)
+    if constexpr (SCALED && COLL == 2) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] *= isc;
+        collide<R, COLL, Q, false>(f, rho0, om, omm, cf, g0, g1, g2);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] *= sc;
+        return;
+    }
     R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -122,9 +141,11 @@ __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf,
         if (cy(i)) jy += cy(i) * f[i];
         if (cz(i)) jz += cz(i) * f[i];
     }
-    const R rho = rho0 + drho;
-    const R ir = rcpr(rho);
+    // drho, j are scaled like f when SCALED; rho and u are not
+    const R rho = SCALED ? rho0 + drho * isc : rho0 + drho;
+    const R ir = SCALED ? isc * rcpr(rho) : rcpr(rho);
     const R ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const R rs = SCALED ? rho * sc : rho;  // w rs: the scaled w rho
     const R usq = R(1.5) * fmar(ux, ux, fmar(uy, uy, uz * uz));
     // w rho and w drho per weight class (the rest, the axes, the edges, the
     // corners); i is a compile-time constant after unrolling
@@ -133,7 +154,7 @@ __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf,
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int rep = k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? 7 : 19));
-        wr[k] = R(wgt<Q>(rep)) * rho;
+        wr[k] = R(wgt<Q>(rep)) * rs;
         wd[k] = R(wgt<Q>(rep)) * drho;
         w3r[k] = R(3) * wr[k];
     }
@@ -195,9 +216,10 @@ __device__ __forceinline__ void collide(R (&f)[Q], R rho0, R om, R omm, bool cf,
         }
     }
     if (cf) {  // uniform counter-force, w_i (c_i . g) / c_s^2 (opposite for opp(i))
+        const R r0 = SCALED ? rho0 * sc : rho0;
 #pragma unroll
         for (int i = 1; i < Q; i += 2) {
-            const R t = R(3.0 * wgt<Q>(i)) * rho0 * dotc<R>(i, g0, g1, g2);
+            const R t = R(3.0 * wgt<Q>(i)) * r0 * dotc<R>(i, g0, g1, g2);
             f[i] += t;
             f[i + 1] -= t;
         }
@@ -220,9 +242,11 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
     const bool walls = WALLS && B.walls;
     if (walls && (y == 0 || y == ny - 1)) return;
+    // the half formats collide on the scaled values as stored (see collide)
+    constexpr bool SC = ST >= ST_F16;
     const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
     R f[Q];
-    Pull<ST, Q>::template pull<CIN>(B, fin + B.foff, s, x, y, z, inv, rho0, walls, f);
+    Pull<ST, Q>::template pull<CIN>(B, fin + B.foff, s, x, y, z, SC ? R(1) : inv, rho0, walls, f, SC ? scl : R(1));
     R g0 = 0, g1 = 0, g2 = 0;
     const bool cf = B.counterforce != 0;
     if (cf) {  // uniform force density on all matter of the box (fluid and particles)
@@ -231,7 +255,7 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
         g1 = (R)(-B.fext[1] / nall);
         g2 = (R)(-B.fext[2] / nall);
     }
-    collide<R, COLL, Q>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
+    collide<R, COLL, Q, SC>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2, scl, inv);
     typename S::T* fo = fout + B.foff;
     // the dither is a function of (node, direction, step) in every convention
     const uint32_t seed = ST >= ST_F16 ? dither_seed((uint32_t)s, step) : 0u;
@@ -253,10 +277,10 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
         }
         if constexpr (NT) {
             typename S::T v;
-            S::st_dither(&v, f[i], scl, r);
+            S::st_dither(&v, f[i], SC ? R(1) : scl, r);
             __builtin_nontemporal_store(v, fo + off);
         } else {
-            S::st_dither(fo + off, f[i], scl, r);
+            S::st_dither(fo + off, f[i], SC ? R(1) : scl, r);
         }
     }
 }
@@ -469,7 +493,10 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
     const long long st = B.stride;
     const T* fi = fin + B.foff;
     const int x0 = K * lane;
+    // the half formats collide on the scaled values as stored (see collide)
+    constexpr bool SC = ST >= ST_F16;
     const R inv = (R)kp.inv_scale, scl = (R)kp.scale, rho0 = (R)kp.rho0;
+    const R ldi = SC ? R(1) : inv, sts = SC ? R(1) : scl, wsc = SC ? scl : R(1);
     const int up = (lane + 63) & 63, dn = (lane + 1) & 63;
     R f[K][Q];
 #pragma unroll
@@ -480,12 +507,12 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
         if (walls && cy(i) != 0 && (sy == 0 || sy == ny - 1)) {
             const double* uw = sy == 0 ? B.wall_lo : B.wall_hi;
             const R cu = (R)(cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
-            ld_vec<T, R, K, ST>(fi + (long long)opp(i) * st + (long long)nx * (y + ny * z) + x0, inv, v);
+            ld_vec<T, R, K, ST>(fi + (long long)opp(i) * st + (long long)nx * (y + ny * z) + x0, ldi, v);
 #pragma unroll
-            for (int j = 0; j < K; ++j) f[j][i] = v[j] + (R)(6.0 * wgt<Q>(i)) * rho0 * cu;
+            for (int j = 0; j < K; ++j) f[j][i] = v[j] + (R)(6.0 * wgt<Q>(i)) * rho0 * cu * wsc;
             continue;
         }
-        ld_vec<T, R, K, ST>(fi + (long long)i * st + (long long)nx * (sy + ny * sz) + x0, inv, v);
+        ld_vec<T, R, K, ST>(fi + (long long)i * st + (long long)nx * (sy + ny * sz) + x0, ldi, v);
         if (cx(i) == 1) {  // source x - 1
             const R carry = __shfl(v[K - 1], up);
 #pragma unroll
@@ -509,7 +536,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
         g2 = (R)(-B.fext[2] / nall);
     }
 #pragma unroll
-    for (int j = 0; j < K; ++j) collide<R, COLL, Q>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2);
+    for (int j = 0; j < K; ++j) collide<R, COLL, Q, SC>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2, scl, inv);
     T* fo = fout + B.foff + (long long)nx * (y + ny * z) + x0;
     uint32_t seed[K];
 #pragma unroll
@@ -519,7 +546,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
         R v[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) v[j] = f[j][i];
-        st_vec<T, R, K, ST, NT>(fo + (long long)i * st, scl, v, seed, i);
+        st_vec<T, R, K, ST, NT>(fo + (long long)i * st, sts, v, seed, i);
     }
 }
 
