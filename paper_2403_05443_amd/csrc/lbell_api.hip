@@ -927,7 +927,9 @@ lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best) {
     for (int v = 0; v < K1_NSHAPES && s == LB_OK; ++v) {
         if (!k1_applicable(ctx, v)) continue;
         if ((s = use_variant(ctx, v)) != LB_OK) break;
-        for (int r = -1; r < reps && s == LB_OK; ++r) {  // r = -1: warm-up step
+        // two untimed steps first: after a layout switch the first step finds
+        // the populations out of the last-level cache
+        for (int r = -2; r < reps && s == LB_OK; ++r) {
             s = r >= 0 ? launch_collide(ctx, ctx->stream, ev[2 * r], ev[2 * r + 1]) : launch_collide(ctx, ctx->stream);
             if (s == LB_OK) s = launch_particles(ctx, ctx->stream);
             ctx->step++;
