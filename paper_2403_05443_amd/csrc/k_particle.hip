@@ -140,10 +140,11 @@ __device__ __forceinline__ bool ldlt_solve6(double Lw[6][6], double dv[6], doubl
     return ok;
 }
 
-// Solid test of eq. ellipsoidsurface.  Body coordinates come from eq.
-// vectrotn with q^-1; the operation order is fixed and contraction is off so
-// the decision is reproducible bit for bit by any IEEE FP64 evaluation of the
-// same expression.
+// The quadratic form Q of eq. ellipsoidsurface at node (x, y, z); the node is
+// solid iff Q < 1.  Body coordinates come from eq. vectrotn with q^-1; the
+// operation order is fixed and contraction is off so the decision is
+// reproducible bit for bit by any IEEE FP64 evaluation of the same
+// expression.
 __device__ __forceinline__ double quad_form(const double xc[3], const double q[4], const double ia2[3],
                                             int x, int y, int z, int nx, int ny, int nz) {
 #pragma clang fp contract(off)
