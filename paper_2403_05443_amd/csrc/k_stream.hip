@@ -239,7 +239,8 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
     if (s >= B.n) return;
     const int nx = B.nx, ny = B.ny;
-    const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+    int x, y;
+    const int z = div_magic(div_magic(s, nx, B.mnx, B.lnx, x), ny, B.mny, B.lny, y);
     const bool walls = WALLS && B.walls;
     if (walls && (y == 0 || y == ny - 1)) return;
     // the half formats collide on the scaled values as stored (see collide)

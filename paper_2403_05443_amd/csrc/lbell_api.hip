@@ -439,6 +439,8 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
         D.tile0 = ctx->L.tile0[b];
         D.ntiles = ctx->L.ntiles[b];
         D.counterforce = cfg->counterforce;
+        magic_div(X.nx, D.mnx, D.lnx);
+        magic_div(X.ny, D.mny, D.lny);
         for (int k = 0; k < 3; ++k) {
             D.wall_lo[k] = X.wall_lo[k];
             D.wall_hi[k] = X.wall_hi[k];

@@ -84,7 +84,25 @@ struct BoxDesc {
     int counterforce, pad0;
     double wall_lo[3], wall_hi[3];
     double fext[3];       // sum of external forces on this machine's particles
+    uint32_t mnx, mny;    // site -> (x, y, z) by multiplication: see magic_div
+    int lnx, lny;
 };
+
+// Division of 0 <= n < 2^27 (a site index, SITE_BITS) by d >= 1 as one
+// multiply and shift: m = ceil(2^L / d) with L = 27 + ceil(log2 d) (m < 2^29).
+// Exact: n / d differs from n m / 2^L by n (m d - 2^L) / (d 2^L), and
+// n (m d - 2^L) < 2^27 d <= 2^L keeps it below the gap to the next integer.
+inline void magic_div(int d, uint32_t& m, int& L) {
+    int c = 0;
+    while ((1ll << c) < d) ++c;
+    L = SITE_BITS + c;
+    m = (uint32_t)(((1ull << L) + (unsigned long long)d - 1) / (unsigned long long)d);
+}
+__device__ __forceinline__ int div_magic(int n, int d, uint32_t m, int L, int& r) {
+    const int q = (int)(((unsigned long long)(uint32_t)n * m) >> L);
+    r = n - q * d;
+    return q;
+}
 
 struct BoxRT {            // mutated by kernels
     int n_solid;
