@@ -677,7 +677,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         double rhs[6];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const double gcf = B.counterforce ? -B.fext[i] / (double)(B.n - B.n_wall) : 0.0;
+            const double gcf = B.gcf[i];  // -fext / (n - n_wall) with the counter-force, else 0
             rhs[i] = M * U0[i] + acc[i] + P.Fext[i] + P.n_solid * gcf + P.Pp[i];
             rhs[3 + i] = sh.IW[i] + acc[3 + i] + P.Text[i] + P.Lp[i];
         }

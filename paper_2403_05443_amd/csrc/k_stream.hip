@@ -251,10 +251,9 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
     R g0 = 0, g1 = 0, g2 = 0;
     const bool cf = B.counterforce != 0;
     if (cf) {  // uniform force density on all matter of the box (fluid and particles)
-        const double nall = (double)(B.n - B.n_wall);
-        g0 = (R)(-B.fext[0] / nall);
-        g1 = (R)(-B.fext[1] / nall);
-        g2 = (R)(-B.fext[2] / nall);
+        g0 = (R)B.gcf[0];
+        g1 = (R)B.gcf[1];
+        g2 = (R)B.gcf[2];
     }
     collide<R, COLL, Q, SC>(f, rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2, scl, inv);
     typename S::T* fo = fout + B.foff;
@@ -531,10 +530,9 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(const BoxDesc* __re
     R g0 = 0, g1 = 0, g2 = 0;
     const bool cf = B.counterforce != 0;
     if (cf) {  // uniform force density on all matter of the box (fluid and particles)
-        const double nall = (double)(B.n - B.n_wall);
-        g0 = (R)(-B.fext[0] / nall);
-        g1 = (R)(-B.fext[1] / nall);
-        g2 = (R)(-B.fext[2] / nall);
+        g0 = (R)B.gcf[0];
+        g1 = (R)B.gcf[1];
+        g2 = (R)B.gcf[2];
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) collide<R, COLL, Q, SC>(f[j], rho0, (R)kp.omega, (R)kp.omega_m, cf, g0, g1, g2, scl, inv);

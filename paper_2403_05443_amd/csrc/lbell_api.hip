@@ -321,7 +321,13 @@ lb_status box_fext_update(lb_ctx* ctx, int b) {
     for (int p = 0; p < ctx->np; ++p)
         if (ctx->hpart[p].box == b)
             for (int k = 0; k < 3; ++k) s[k] += ctx->hpart[p].Fext[k];
-    for (int k = 0; k < 3; ++k) ctx->hbox[b].fext[k] = s[k];
+    BoxDesc& D = ctx->hbox[b];
+    for (int k = 0; k < 3; ++k) {
+        D.fext[k] = s[k];
+        // the uniform force density of the counter-force (the expression the
+        // kernels used to evaluate per site)
+        D.gcf[k] = D.counterforce ? -D.fext[k] / (double)(D.n - D.n_wall) : 0.0;
+    }
     return upload_box(ctx, b);
 }
 

@@ -84,6 +84,7 @@ struct BoxDesc {
     int counterforce, pad0;
     double wall_lo[3], wall_hi[3];
     double fext[3];       // sum of external forces on this machine's particles
+    double gcf[3];        // counter-force density -fext / (n - n_wall), or 0
     uint32_t mnx, mny;    // site -> (x, y, z) by multiplication: see magic_div
     int lnx, lny;
 };
