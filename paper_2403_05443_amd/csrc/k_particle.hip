@@ -973,6 +973,8 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
                                                  minimg((double)gz - xc[2], nz)};
                             if (in) {  // covered: its momentum and its mass in excess of rho0 go to the particle
                                 double m = 0, pm[3] = {0, 0, 0};
+                                // unrolled, so that the Q loads are in flight together
+#pragma unroll
                                 for (int j = 0; j < Q; ++j) {
                                     int dir, slot;
                                     double add;
