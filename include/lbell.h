@@ -213,9 +213,10 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
  * Moving between the two-buffer variants (0-10) and the in-place ones
  * (11-14) permutes the stored populations into the other layout exactly.
  * With the two-stream schedule only 0-2 apply.  All variants give identical
- * bits, so the (applicable variants) x (reps + 2) steps the tuner takes (two
- * untimed, reps timed per variant) are ordinary steps of the simulation: the
- * step counter advances by that many.
+ * bits, so the 2 x (applicable variants) x (reps + 2) steps the tuner takes
+ * (two sweeps over the variants; in each, two untimed and reps timed steps
+ * per variant, and a variant counts with the smaller of its two means) are
+ * ordinary steps of the simulation: the step counter advances by that many.
  * *variant and *ms_best (milliseconds per collide-stream launch, HIP events
  * around each launch) may be NULL.  Synchronises. */
 lb_status lb_autotune(lb_ctx* ctx, int reps, int* variant, double* ms_best);

@@ -96,7 +96,7 @@ def test_tuner_covers_generic_shapes(lb):
     v, ms = g.autotune(3)
     assert v in GENERIC and ms > 0
     taken = g.step_count() - t0
-    assert taken == len(GENERIC) * 5      # two warm-up + 3 timed steps per variant
+    assert taken == 2 * len(GENERIC) * 5  # two sweeps of two warm-up + 3 timed steps per variant
     h.step(taken)
     g.step(10)
     h.step(10)
