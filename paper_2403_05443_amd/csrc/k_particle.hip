@@ -842,11 +842,14 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
     solve_phase<ST, Q>(a, p, P, sh, lr, false);
 }
 
+constexpr int P2B = 8;  // windows of up to P2B chunks of PBLOCK nodes take the batched link pass
+
 struct RemapShm {
     double red[22][PWAVES];
     double mred[PWAVES];
     int wtot[PWAVES];
     int ired[8][PWAVES];
+    int wchunk[P2B][PWAVES];  // links per wave and chunk (batched link pass)
 };
 
 // Whether the window must be tested again.  At its last test every node of
@@ -1081,7 +1084,120 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     int running = 0;
     const int lcap = P.lcap;
     uint32_t* L = a.links + P.lbase;
-    {
+    // the link mask of window node i: bit b set when i is fluid and i + c_b
+    // is solid here (the node map is read only where bits[] says fluid)
+    auto link_mask = [&](int i, uint16_t own, int& s, int& gx, int& gy, int& gz) -> uint32_t {
+        uint32_t lm = 0;
+        int wx, wy;
+        const int wz = divmod(divmod(i, wn[0], rw0, wx), wn[1], rw1, wy);
+        gx = wrap(lo[0] + wx, nx);
+        gy = wrap(lo[1] + wy, ny);
+        gz = wrap(lo[2] + wz, nz);
+        s = gx + nx * (gy + ny * gz);
+        if (own == 0) {
+#pragma unroll
+            for (int b = 1; b < Q; ++b) {
+                int nwx = wx + cx(b), nwy = wy + cy(b), nwz = wz + cz(b);
+                if (whole[0]) nwx = wrap(nwx, wn[0]);
+                else if (nwx < 0 || nwx >= wn[0]) continue;
+                if (whole[1]) nwy = wrap(nwy, wn[1]);
+                else if (nwy < 0 || nwy >= wn[1]) continue;
+                if (whole[2]) nwz = wrap(nwz, wn[2]);
+                else if (nwz < 0 || nwz >= wn[2]) continue;
+                const int ni = nwx + wn[0] * (nwy + wn[1] * nwz);
+                if ((bits[ni >> 5] >> (ni & 31)) & 1u) lm |= 1u << b;
+            }
+        }
+        return lm;
+    };
+    const int nch = (nsites + PBLOCK - 1) / PBLOCK;
+    if (nch <= P2B) {
+        // pass 2, small windows: every chunk's masks first (the node-map
+        // loads of all chunks in flight together), one block scan over all
+        // chunks, one staged copy-out; same order and same sums as below
+        uint32_t lmv[P2B];
+        int sv[P2B], offv[P2B];
+        uint16_t ownv[P2B];
+#pragma unroll
+        for (int c = 0; c < P2B; ++c) {
+            const int i = c * PBLOCK + tid;
+            ownv[c] = 1;  // not fluid
+            if (i < nsites && !((bits[i >> 5] >> (i & 31)) & 1u)) {
+                int wx, wy;
+                const int wz = divmod(divmod(i, wn[0], rw0, wx), wn[1], rw1, wy);
+                ownv[c] = om[wrap(lo[0] + wx, nx) + nx * (wrap(lo[1] + wy, ny) + ny * wrap(lo[2] + wz, nz))];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < P2B; ++c) {
+            lmv[c] = 0;
+            sv[c] = 0;
+            offv[c] = 0;
+            if (c < nch) {  // uniform over the block
+                const int i = c * PBLOCK + tid;
+                int gx = 0, gy = 0, gz = 0;
+                if (i < nsites) lmv[c] = link_mask(i, ownv[c], sv[c], gx, gy, gz);
+                uint32_t mm = lmv[c];
+                while (mm) {
+                    const int b = __ffs(mm) - 1;
+                    mm &= mm - 1;
+                    z.add(b, gx, gy, gz, xc, nx, ny, nz);
+                }
+                const int cnt = __popc(lmv[c]);
+                int incl = cnt;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int nb = __shfl_up(incl, o);
+                    if (lane >= o) incl += nb;
+                }
+                offv[c] = incl - cnt;
+                if (lane == 63) sh.wchunk[c][wv] = incl;
+            }
+        }
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int c = 0; c < P2B; ++c) {
+            if (c < nch) {
+                int before = 0, all = 0;
+                for (int w = 0; w < PWAVES; ++w) {
+                    const int t = sh.wchunk[c][w];
+                    if (w < wv) before += t;
+                    all += t;
+                }
+                offv[c] += total + before;
+                total += all;
+            }
+        }
+        if (total <= STAGE) {
+#pragma unroll
+            for (int c = 0; c < P2B; ++c) {
+                uint32_t m2 = lmv[c];
+                int idx = offv[c];
+                while (m2) {
+                    const int b = __ffs(m2) - 1;
+                    m2 &= m2 - 1;
+                    stage[idx++] = (uint32_t)sv[c] | ((uint32_t)b << SITE_BITS);
+                }
+            }
+            __syncthreads();
+            for (int j = tid; j < total; j += PBLOCK)
+                if (j < lcap) L[j] = stage[j];
+        } else {  // more links than the stage holds: each thread writes its own
+#pragma unroll
+            for (int c = 0; c < P2B; ++c) {
+                uint32_t m2 = lmv[c];
+                int idx = offv[c];
+                while (m2) {
+                    const int b = __ffs(m2) - 1;
+                    m2 &= m2 - 1;
+                    if (idx < lcap) L[idx] = (uint32_t)sv[c] | ((uint32_t)b << SITE_BITS);
+                    ++idx;
+                }
+            }
+        }
+        running = total;
+        if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
+    } else {
         // pass 2: boundary links (fluid x, x + c_b solid here), staged in LDS
         // and written in (window index, direction) order
         for (int base = 0; base < nsites; base += PBLOCK) {
@@ -1091,24 +1207,8 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             if (i < nsites && !((bits[i >> 5] >> (i & 31)) & 1u)) {
                 int wx, wy;
                 const int wz = divmod(divmod(i, wn[0], rw0, wx), wn[1], rw1, wy);
-                gx = wrap(lo[0] + wx, nx);
-                gy = wrap(lo[1] + wy, ny);
-                gz = wrap(lo[2] + wz, nz);
-                s = gx + nx * (gy + ny * gz);
-                if (om[s] == 0) {
-#pragma unroll
-                    for (int b = 1; b < Q; ++b) {
-                        int nwx = wx + cx(b), nwy = wy + cy(b), nwz = wz + cz(b);
-                        if (whole[0]) nwx = wrap(nwx, wn[0]);
-                        else if (nwx < 0 || nwx >= wn[0]) continue;
-                        if (whole[1]) nwy = wrap(nwy, wn[1]);
-                        else if (nwy < 0 || nwy >= wn[1]) continue;
-                        if (whole[2]) nwz = wrap(nwz, wn[2]);
-                        else if (nwz < 0 || nwz >= wn[2]) continue;
-                        const int ni = nwx + wn[0] * (nwy + wn[1] * nwz);
-                        if ((bits[ni >> 5] >> (ni & 31)) & 1u) lm |= 1u << b;
-                    }
-                }
+                const uint16_t own = om[wrap(lo[0] + wx, nx) + nx * (wrap(lo[1] + wy, ny) + ny * wrap(lo[2] + wz, nz))];
+                lm = link_mask(i, own, s, gx, gy, gz);
             }
             const int cnt = __popc(lm);
             int incl = cnt;
