@@ -1,0 +1,76 @@
+"""Consistency of the committed measurement record (CPU only): the bench line
+in profiles/ keeps the bench.py output contract, its roofline figures follow
+from one another, its traffic figure is the counter record's for the kernel
+source it was taken on, and the kernel trace summary's average for the
+collide-stream kernel agrees with the bench line's own events."""
+import hashlib
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROF = os.path.join(ROOT, "profiles")
+BENCH = os.path.join(PROF, "bench_c2_inclined_128_fp32.json")
+TRAFFIC = os.path.join(PROF, "collide_stream_traffic.json")
+TRACE = os.path.join(PROF, "trace_c2_128_fp32_fp16_d3q27_c4_ensemble_fp16_c5_suspension_fp16.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2403_05443_amd", "csrc", "k_stream.hip")
+
+# the in-place FP32 D3Q19 shapes as their template instantiations appear in a
+# kernel trace, {p} the even (1) or odd (2) step
+INPLACE_FP32_Q19 = {11: "k_collide_stream_aa<1, 1, false, 1, false, false, {p}, 19>",
+                    12: "k_collide_stream_aa<1, 1, false, 1, true, false, {p}, 19>"}
+
+
+def _bench():
+    return json.loads(open(BENCH).read().strip().splitlines()[-1])
+
+
+def test_bench_line_contract():
+    d = _bench()
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["higher_is_better"] is True and d["value"] > 0
+    assert d["config"]["workload"] == "c2_inclined_128"
+    r = d["roofline"]
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], abs=1e-3)
+    # achieved = algorithmic bytes per launch over the measured launch duration
+    assert r["achieved"] == pytest.approx(r["bytes_per_launch"] / (r["avg_launch_ms"] * 1e-3) / 1e9, rel=2e-3)
+    # 2 x 19 FP32 populations per site, read once and written once
+    assert r["bytes_per_launch"] == 2 * 19 * 4 * d["config"]["sites"]
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["sample"]
+
+
+def test_traffic_matches_counter_record():
+    d = _bench()
+    r = d["roofline"]
+    rec = json.load(open(TRAFFIC))
+    ent = rec["entries"].get(f"c2_inclined_128/fp32/v{r['variant']}")
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec["source_sha256"] == sha and ent is not None:
+        assert r["traffic"] == ent["traffic_bytes_per_launch"]
+        # no wasted re-reads: within 1 % of the algorithmic bytes
+        assert abs(r["traffic"] / r["bytes_per_launch"] - 1) < 0.01
+    else:
+        # counters taken on another kernel source are not reported
+        assert r["traffic"] is None
+
+
+def test_trace_agrees_with_bench_events():
+    d = _bench()
+    r = d["roofline"]
+    pattern = INPLACE_FP32_Q19.get(r["variant"])
+    if pattern is None:
+        pytest.skip(f"variant {r['variant']} has no trace name here")
+    avg = {}
+    for line in open(TRACE):
+        m = re.match(r"\| `([^`]+)` \| (\d+) \| ([0-9.]+) \|", line)
+        if m:
+            avg[m.group(1)] = float(m.group(3))
+    us = [avg[pattern.format(p=p)] for p in (1, 2)]
+    # the trace's mean over the even and odd launches, against the bench's events
+    assert sum(us) / 2 == pytest.approx(r["avg_launch_ms"] * 1e3, rel=0.03)
