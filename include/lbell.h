@@ -108,7 +108,8 @@ typedef struct lb_config {
                                nodes of the box) on all matter: every fluid node, and
                                every particle by its solid-node count, so that total
                                momentum stays zero (default 0)                        */
-    int    max_particles;   /* particle capacity over all boxes (default 1 per box)    */
+    int    max_particles;   /* particle capacity over all boxes (default 1 per box);
+                               at most 65534 (the node map holds id + 1 in 16 bits)    */
     double max_semi_axis;   /* largest semi-axis any particle may have (default 8)     */
     int    rotation;        /* inertia term of the rotational update (Sec. II.D):
                                LB_ROT_ANALYTIC (default), LB_ROT_FD or LB_ROT_PC        */
@@ -264,8 +265,8 @@ lb_status lb_get_particle_aux(lb_ctx* ctx, int id, double* M, double* dm,
                               double P[3], double L[3], int* nlinks);
 
 /* Boundary links (x, b) of particle id: x fluid, x + c_b solid (Sec. II.B).
- * site[k] is the site index of x, dir[k] is b (1..18).  Order: deterministic,
- * not sorted.  If cap < the number of links, nothing is copied, *n is set and
+ * site[k] is the site index of x, dir[k] is b (1..18 on D3Q19, 1..26 on
+ * D3Q27).  Order: deterministic, not sorted.  If cap < the number of links, nothing is copied, *n is set and
  * LB_ERANGE returned.  Synchronises. */
 lb_status lb_get_links(lb_ctx* ctx, int id, uint32_t* site, uint8_t* dir,
                        int cap, int* n);

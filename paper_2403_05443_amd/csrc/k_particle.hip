@@ -625,7 +625,11 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         const double r[3] = {minimg(((double)x + 0.5 * c0) - xc[0], nx), minimg(((double)y + 0.5 * c1) - xc[1], ny),
                              minimg(((double)z + 0.5 * c2) - xc[2], nz)};
         const double rc0 = r[1] * c2 - r[2] * c1, rc1 = r[2] * c0 - r[0] * c2, rc2 = r[0] * c1 - r[1] * c0;
-        const double fb2 = 2.0 * fb;
+        // eqs. F0, T0 sum the full population f_b = deviation + w_b rho0: the
+        // w_b rho0 part cancels over a closed link set, but not where this
+        // particle's solid touches another solid or a wall (its links there
+        // are missing, and the rest pressure on the exposed side remains)
+        const double fb2 = 2.0 * (fb + (rw<Q>(b) / (double)WSCALE<Q>) * rho0);
         acc[0] += fb2 * c0;
         acc[1] += fb2 * c1;
         acc[2] += fb2 * c2;
@@ -832,20 +836,10 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
     }
 }
 
-template <int ST, int Q>
-__global__ __launch_bounds__(PBLOCK) void k_particle_solve(LaunchPart a) {
-    __shared__ PartDev P;
-    __shared__ SolveShm sh;
-    const int p = a.first + (int)blockIdx.x;
-    LinkRegs<typename Store<ST>::T> lr;
-    load_particle<ST, Q>(a, p, &P, lr);
-    solve_phase<ST, Q>(a, p, P, sh, lr, false);
-}
-
 constexpr int P2B = 8;  // windows of up to P2B chunks of PBLOCK nodes take the batched link pass
 
 struct RemapShm {
-    double red[22][PWAVES];
+    double red[15][PWAVES];
     double mred[PWAVES];
     int wtot[PWAVES];
     int ired[8][PWAVES];
@@ -881,22 +875,129 @@ __device__ __forceinline__ bool scan_needed(const PartDev& P) {
     return !(dwin * (1.0 + 1e-12) + 1e-9 < P.smargin && dbody < 0.5);
 }
 
-// Steps 8-9 for particle p with its (new) state staged in LDS (P).
-// stores_done: the bounce-back stores of the step are complete (a kernel
-// boundary lies between); otherwise the window test waits for them first.
+// The remap window of a particle with the reciprocals its index arithmetic
+// uses.
+struct Win {
+    int lo[3], wn[3];
+    bool whole[3];
+    int nsites;
+    double rw0, rw1;
+};
+
+// False (and the window flag raised) when the window's bitmask exceeds the
+// LDS budget.
+__device__ __forceinline__ bool window_of(const LaunchPart& a, const PartDev& P, const BoxDesc& B, Win& w) {
+    particle_window(P, B, w.lo, w.wn, w.whole);
+    w.nsites = w.wn[0] * w.wn[1] * w.wn[2];
+    w.rw0 = 1.0 / w.wn[0];
+    w.rw1 = 1.0 / w.wn[1];
+    if (((w.nsites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32) > a.lds_words) {
+        if (threadIdx.x == 0) atomicOr(a.flags, (int)F_WINDOW);
+        return false;
+    }
+    return true;
+}
+
+// Box coordinates of window node i.
+__device__ __forceinline__ void win_node(const Win& w, const BoxDesc& B, int i, int& gx, int& gy, int& gz) {
+    int wx, wy;
+    const int wz = divmod(divmod(i, w.wn[0], w.rw0, wx), w.wn[1], w.rw1, wy);
+    gx = wrap(w.lo[0] + wx, B.nx);
+    gy = wrap(w.lo[1] + wy, B.ny);
+    gz = wrap(w.lo[2] + wz, B.nz);
+}
+
+// Node-map updates that several particles' work-groups may make at once in
+// one 32-bit word (two sites): a box's map starts at an even element, so
+// site s lies in word s >> 1.  A claim succeeds only on a free (fluid) node.
+__device__ __forceinline__ bool claim_node(uint16_t* om, int s, uint16_t me) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(om) + (s >> 1);
+    const int sh = (s & 1) * 16;
+    uint32_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (true) {
+        if ((cur >> sh) & 0xFFFFu) return false;
+        const uint32_t prev = atomicCAS(w, cur, cur | ((uint32_t)me << sh));
+        if (prev == cur) return true;
+        cur = prev;
+    }
+}
+__device__ __forceinline__ void release_node(uint16_t* om, int s) {
+    atomicAnd(reinterpret_cast<uint32_t*>(om) + (s >> 1), ~(0xFFFFu << ((s & 1) * 16)));
+}
+
+// Marks the cell (8^3 nodes) of a node whose owner changes at this step.
+__device__ __forceinline__ void stamp_cell(const LaunchPart& a, const BoxDesc& B, int gx, int gy, int gz,
+                                           uint32_t ep) {
+    a.stamps[B.coff + (gx >> 3) + B.cnx * ((gy >> 3) + B.cny * (gz >> 3))] = ep;
+}
+
+// Whether some node of the window changed owner at this step (a cell of the
+// window carries this step's stamp): then links of this particle may have
+// appeared or vanished although none of its own nodes changed.  Block-uniform.
+__device__ bool window_stamped(const LaunchPart& a, const BoxDesc& B, const Win& w, uint32_t ep) {
+    // per axis up to two runs of coordinates (the window may wrap), as cells
+    int c0[3][2], c1[3][2], nr[3], cnt[3];
+    const int n3[3] = {B.nx, B.ny, B.nz};
+    for (int k = 0; k < 3; ++k) {
+        int s0 = w.lo[k], e0 = w.lo[k] + w.wn[k], s1 = 0, e1 = 0;
+        if (w.whole[k]) {
+            s0 = 0;
+            e0 = n3[k];
+        } else if (s0 < 0) {
+            s1 = 0;
+            e1 = e0;
+            s0 += n3[k];
+            e0 = n3[k];
+        } else if (e0 > n3[k]) {
+            s1 = 0;
+            e1 = e0 - n3[k];
+            e0 = n3[k];
+        }
+        c0[k][0] = s0 >> 3;
+        c1[k][0] = (e0 - 1) >> 3;
+        nr[k] = e1 > s1 ? 2 : 1;
+        c0[k][1] = s1 >> 3;
+        c1[k][1] = e1 > s1 ? (e1 - 1) >> 3 : -1;
+        cnt[k] = (c1[k][0] - c0[k][0] + 1) + (nr[k] == 2 ? c1[k][1] - c0[k][1] + 1 : 0);
+    }
+    auto cell = [&](int k, int j) {
+        const int n0 = c1[k][0] - c0[k][0] + 1;
+        return j < n0 ? c0[k][0] + j : c0[k][1] + (j - n0);
+    };
+    bool hit = false;
+    const int total = cnt[0] * cnt[1] * cnt[2];
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int jx = t % cnt[0], jy = (t / cnt[0]) % cnt[1], jz = t / (cnt[0] * cnt[1]);
+        const int c = cell(0, jx) + B.cnx * (cell(1, jy) + B.cny * cell(2, jz));
+        hit = hit || a.stamps[B.coff + c] == ep;
+    }
+    return __syncthreads_or(hit) != 0;
+}
+
+// Pass 1 of the remap over the window: the solid test of eq. ellipsoidsurface
+// at the particle's new pose.
+//  mode 0 (step): a node of this particle no longer inside is uncovered: it
+//    gets f = f_eq(rho0, U + W x r) and its momentum is paid by the particle
+//    (reading R9); a node inside that is not yet this particle's is a
+//    candidate, claimed afterwards by claim_pass (so that, with several
+//    particles in a box, every release is done before any claim);
+//  mode 1 (add): every node inside is a candidate, no book-keeping;
+//  mode 2 (remove): every node of this particle is released.
+// bits (LDS; may be null): this particle's nodes after the step.  cand: the
+// candidate bits (LDS, or this particle's global area).  With ep != 0 the
+// cells of released and candidate nodes are stamped.  Also records the skip
+// test's reference (pose, margin, window radius), and with mode 0 the pending
+// mass / momentum / angular momentum and the solid count.  Returns bit 0 set
+// when some node was released or is a candidate, bit 1 when some node is a
+// candidate; block-uniform.
 template <int ST, int Q>
-__device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const PartDev& P, RemapShm& sh, uint32_t* smem,
-                                            bool stores_done) {
+__device__ int scan_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w, uint32_t* bits,
+                         uint32_t* cand, RemapShm& sh, uint32_t ep) {
     using S = Store<ST>;
     using T = typename S::T;
-    uint32_t* bits = smem;
-    uint32_t* stage = smem + a.lds_words;
     double (*red)[PWAVES] = sh.red;
-    int* wtot = sh.wtot;
     int (*ired)[PWAVES] = sh.ired;
     PartDev* Pg = a.parts + p;
-    const int bi = P.box;
-    const BoxDesc& B = a.boxes[bi];
     T* f = (T*)a.f + B.foff;
     uint16_t* om = a.omap + B.ooff;
     const long long st = B.stride;
@@ -908,30 +1009,13 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     const double q[4] = {P.q[0], P.q[1], P.q[2], P.q[3]};
     const double ia2[3] = {P.ia2[0], P.ia2[1], P.ia2[2]};
     const double U[3] = {P.U[0], P.U[1], P.U[2]}, W[3] = {P.W[0], P.W[1], P.W[2]};
-    const double inv = a.kp.inv_scale, scl = a.kp.scale, rho0 = a.kp.rho0;
+    const double scl = a.kp.scale, rho0 = a.kp.rho0;
+    const int nsites = w.nsites;
 
-    int lo[3], wn[3];
-    bool whole[3];
-    particle_window(P, B, lo, wn, whole);
-    const int nsites = wn[0] * wn[1] * wn[2];
-    const double rw0 = 1.0 / wn[0], rw1 = 1.0 / wn[1];
-    if (((nsites + PBLOCK - 1) / PBLOCK) * (PBLOCK / 32) > a.lds_words) {
-        if (tid == 0) atomicOr(a.flags, (int)F_WINDOW);
-        return;
-    }
-    if (mode == 0 && !scan_needed(P)) {
-        // no node can have changed side since the last scan: as the fast
-        // path below, without testing the window
-        if (a.near.flags) mark_near(a.near, B, lo, wn);
-        return;
-    }
-    if (!stores_done) __syncthreads();  // the bounce-back writes before the covered-node reads
-
-    // pass 1: solid test, node-map update, covered / uncovered nodes
     double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
     double mloc = 1.0;  // lower bound of |sqrt(Q) - 1| over this thread's nodes
     int nsol = 0;
-    bool changed = false;
+    bool released = false, candidate = false;
     for (int base = 0; base < nsites; base += PBLOCK * KSCAN) {
         uint16_t own[KSCAN];
         int sidx[KSCAN], gxyz[KSCAN][3];
@@ -941,11 +1025,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             sidx[k] = -1;
             own[k] = 0;
             if (i < nsites) {
-                int wx, wy;
-                const int wz = divmod(divmod(i, wn[0], rw0, wx), wn[1], rw1, wy);
-                gxyz[k][0] = wrap(lo[0] + wx, nx);
-                gxyz[k][1] = wrap(lo[1] + wy, ny);
-                gxyz[k][2] = wrap(lo[2] + wz, nz);
+                win_node(w, B, i, gxyz[k][0], gxyz[k][1], gxyz[k][2]);
                 sidx[k] = gxyz[k][0] + nx * (gxyz[k][1] + ny * gxyz[k][2]);
                 own[k] = om[sidx[k]];
             }
@@ -953,81 +1033,73 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
 #pragma unroll
         for (int k = 0; k < KSCAN; ++k) {
             if (base + k * PBLOCK >= nsites) break;  // uniform over the block
-            bool in = false;
+            bool in = false, cd = false;
             const int s = sidx[k];
             if (s >= 0) {
                 const int gx = gxyz[k][0], gy = gxyz[k][1], gz = gxyz[k][2];
                 if (mode == 2) {
-                    if (own[k] == me) om[s] = 0;
+                    if (own[k] == me) {
+                        release_node(om, s);
+                        released = true;
+                    }
                 } else {
                     const double Qv = quad_form(xc, q, ia2, gx, gy, gz, nx, ny, nz);
                     in = Qv < 1.0;
                     // sqrt(Q) <= (Q + 1) / 2, so |sqrt(Q) - 1| = |Q - 1| / (sqrt(Q) + 1) >= 2 |Q - 1| / (Q + 3)
                     mloc = fmin(mloc, 2.0 * fabs(Qv - 1.0) / (Qv + 3.0));
-                    if (in && own[k] != 0 && own[k] != me) {
+                    if (in && own[k] == 0xFFFFu) {  // a wall node
                         atomicOr(a.flags, (int)F_OVERLAP);
                         in = false;
                     }
-                    const bool old = own[k] == me;
-                    if (in != old) {
-                        changed = true;
+                    if (in && own[k] != me) {
+                        cd = true;
+                        candidate = true;
+                        if (ep) stamp_cell(a, B, gx, gy, gz, ep);
+                    } else if (!in && own[k] == me) {
+                        released = true;
+                        if (ep) stamp_cell(a, B, gx, gy, gz, ep);
                         if (mode == 0) {
+                            // uncovered: f = f_eq(rho0, U + W x r), paid by the particle
                             const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
                                                  minimg((double)gz - xc[2], nz)};
-                            if (in) {  // covered: its momentum and its mass in excess of rho0 go to the particle
-                                double m = 0, pm[3] = {0, 0, 0};
-                                // unrolled, so that the Q loads are in flight together
-#pragma unroll
-                                for (int j = 0; j < Q; ++j) {
-                                    int dir, slot;
-                                    double add;
-                                    pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
-                                    const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
-                                    m += v;
-                                    pm[0] += rcx(j) * v;
-                                    pm[1] += rcy(j) * v;
-                                    pm[2] += rcz(j) * v;
-                                }
-                                tacc[0] += m;
-                                tacc[1] += pm[0];
-                                tacc[2] += pm[1];
-                                tacc[3] += pm[2];
-                                tacc[4] += r[1] * pm[2] - r[2] * pm[1];
-                                tacc[5] += r[2] * pm[0] - r[0] * pm[2];
-                                tacc[6] += r[0] * pm[1] - r[1] * pm[0];
-                            } else {  // uncovered: f = f_eq(rho0, U + W x r), paid by the particle
-                                const double u[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]),
-                                                     U[1] + (W[2] * r[0] - W[0] * r[2]),
-                                                     U[2] + (W[0] * r[1] - W[1] * r[0])};
-                                const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-                                for (int j = 0; j < Q; ++j) {
-                                    int dir, slot;
-                                    double add;
-                                    pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
-                                    const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
-                                    const double dev = (rw<Q>(j) / (double)WSCALE<Q>) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-                                    S::st64(f + (long long)dir * st + slot, dev - add, scl);
-                                }
-                                // the new node holds rho0: no excess mass
-                                const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
-                                tacc[1] -= pu[0];
-                                tacc[2] -= pu[1];
-                                tacc[3] -= pu[2];
-                                tacc[4] -= r[1] * pu[2] - r[2] * pu[1];
-                                tacc[5] -= r[2] * pu[0] - r[0] * pu[2];
-                                tacc[6] -= r[0] * pu[1] - r[1] * pu[0];
+                            const double u[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]),
+                                                 U[1] + (W[2] * r[0] - W[0] * r[2]),
+                                                 U[2] + (W[0] * r[1] - W[1] * r[0])};
+                            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                            for (int j = 0; j < Q; ++j) {
+                                int dir, slot;
+                                double add;
+                                pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
+                                const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
+                                const double dev = (rw<Q>(j) / (double)WSCALE<Q>) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                                S::st64(f + (long long)dir * st + slot, dev - add, scl);
                             }
+                            // the new node holds rho0: no excess mass
+                            const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
+                            tacc[1] -= pu[0];
+                            tacc[2] -= pu[1];
+                            tacc[3] -= pu[2];
+                            tacc[4] -= r[1] * pu[2] - r[2] * pu[1];
+                            tacc[5] -= r[2] * pu[0] - r[0] * pu[2];
+                            tacc[6] -= r[0] * pu[1] - r[1] * pu[0];
                         }
-                        om[s] = in ? me : (uint16_t)0;
+                        release_node(om, s);
                     }
                     nsol += in ? 1 : 0;
                 }
             }
-            const unsigned long long m = __ballot(in);
+            const int w0 = (base + k * PBLOCK + wv * 64) >> 5;
+            const unsigned long long cm = __ballot(cd);
             if (lane == 0) {
-                const int w0 = (base + k * PBLOCK + wv * 64) >> 5;
-                bits[w0] = (uint32_t)m;
-                bits[w0 + 1] = (uint32_t)(m >> 32);
+                cand[w0] = (uint32_t)cm;
+                cand[w0 + 1] = (uint32_t)(cm >> 32);
+            }
+            if (bits) {
+                const unsigned long long m = __ballot(in);
+                if (lane == 0) {
+                    bits[w0] = (uint32_t)m;
+                    bits[w0 + 1] = (uint32_t)(m >> 32);
+                }
             }
         }
     }
@@ -1035,7 +1107,8 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         const double wm = wmin64(mloc);
         if (lane == 0) sh.mred[wv] = wm;
     }
-    changed = __syncthreads_or(changed);
+    const bool anycand = __syncthreads_or(candidate) != 0;
+    const bool changed = anycand || __syncthreads_or(released) != 0;
 
     if (mode != 2 && tid < 9) {
         // the reference of the skip test: this pose, and the margin in
@@ -1043,7 +1116,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         // coordinates), shaded down for rounding
         if (tid == 0) {
             double m = sh.mred[0];
-            for (int w = 1; w < PWAVES; ++w) m = fmin(m, sh.mred[w]);
+            for (int v = 1; v < PWAVES; ++v) m = fmin(m, sh.mred[v]);
             const double amin = fmin(P.axes[0], fmin(P.axes[1], P.axes[2]));
             Pg->smargin = m * amin * (1.0 - 1e-12);
         } else if (tid < 4) {
@@ -1055,29 +1128,164 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             const int n3[3] = {nx, ny, nz};
             double r2 = 0.0;
             for (int k = 0; k < 3; ++k) {
-                const double e = whole[k] ? 0.5 * n3[k] : fmax(xc[k] - lo[k], (double)(lo[k] + wn[k] - 1) - xc[k]);
+                const double e = w.whole[k] ? 0.5 * n3[k]
+                                            : fmax(xc[k] - w.lo[k], (double)(w.lo[k] + w.wn[k] - 1) - xc[k]);
                 r2 += e * e;
             }
             Pg->srho = sqrt(r2);
         }
     }
-
-    if (mode == 2) {
-        if (tid == 0) {
-            atomicAdd(&a.rt[bi].n_solid, -P.n_solid);
-            Pg->n_solid = 0;
-            Pg->nlinks = 0;
+    if (changed) {
+        // solid count and (mode 0) the uncovered nodes' book-keeping
+        if (mode == 0) block_reduce<7>(tacc, red);
+        const int sm = wsumi(nsol);
+        if (lane == 0) ired[7][wv] = sm;
+        __syncthreads();
+        // one lane per output; each reads and rewrites only its own field of
+        // the LDS copy, which the claims then start from
+        if (tid == 44) {
+            int ns = 0;
+            for (int v = 0; v < PWAVES; ++v) ns += ired[7][v];
+            if (ns != P.n_solid) atomicAdd(&a.rt[P.box].n_solid, ns - P.n_solid);
+            Pg->n_solid = ns;
+            P.n_solid = ns;
+        } else if (mode == 0 && tid >= 37 && tid < 44) {
+            const int k = tid - 37;  // dm, Pp[3], Lp[3]
+            double* fld = k == 0 ? &P.dm : (k < 4 ? &P.Pp[k - 1] : &P.Lp[k - 4]);
+            double* gfld = k == 0 ? &Pg->dm : (k < 4 ? &Pg->Pp[k - 1] : &Pg->Lp[k - 4]);
+            const double nv = *fld + tacc[k];
+            *gfld = nv;
+            *fld = nv;
         }
-        return;
+        __syncthreads();
     }
+    return (changed ? 1 : 0) | (anycand ? 2 : 0);
+}
 
-    if (mode == 0 && !changed) {
-        // no node changed state: the link set, the solid count and the link
-        // weights stay, no mass or momentum moved, and the solve has already
-        // evaluated zeta of this link set at the new centre
-        if (a.near.flags) mark_near(a.near, B, lo, wn);
+// Claims the candidate nodes of pass 1 (cand: bits over the window, in LDS or
+// global memory).  Bit words are dealt to the threads in one fixed way, so
+// the sums below do not depend on where the bits are held.  A node another
+// particle or a wall holds is an overlap.  Mode 0: a covered node's momentum
+// and its mass in excess of rho0 go to the particle, its angular momentum
+// about x_c(t+1) (reading R9); the populations it holds are read after every
+// bounce-back and release of the step.
+template <int ST, int Q>
+__device__ void claim_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w,
+                           const uint32_t* cand, RemapShm& sh) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    const T* f = (const T*)a.f + B.foff;
+    uint16_t* om = a.omap + B.ooff;
+    PartDev* Pg = a.parts + p;
+    const long long st = B.stride;
+    const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
+    const uint16_t me = (uint16_t)(p + 1);
+    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
+    const double inv = a.kp.inv_scale, rho0 = a.kp.rho0;
+    double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int nw = (w.nsites + 31) >> 5;
+    for (int wd = tid; wd < nw; wd += PBLOCK) {
+        uint32_t m = cand[wd];
+        while (m) {
+            const int i = 32 * wd + (__ffs(m) - 1);
+            m &= m - 1;
+            int gx, gy, gz;
+            win_node(w, B, i, gx, gy, gz);
+            const int s = gx + nx * (gy + ny * gz);
+            if (!claim_node(om, s, me)) {
+                atomicOr(a.flags, (int)F_OVERLAP);
+                continue;
+            }
+            if (a.mode != 0) continue;
+            const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
+                                 minimg((double)gz - xc[2], nz)};
+            double mm = 0, pm[3] = {0, 0, 0};
+            // unrolled, so that the Q loads are in flight together
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                int dir, slot;
+                double add;
+                pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
+                const double v = S::ld64(f + (long long)dir * st + slot, inv) + add;
+                mm += v;
+                pm[0] += rcx(j) * v;
+                pm[1] += rcy(j) * v;
+                pm[2] += rcz(j) * v;
+            }
+            tacc[0] += mm;
+            tacc[1] += pm[0];
+            tacc[2] += pm[1];
+            tacc[3] += pm[2];
+            tacc[4] += r[1] * pm[2] - r[2] * pm[1];
+            tacc[5] += r[2] * pm[0] - r[0] * pm[2];
+            tacc[6] += r[0] * pm[1] - r[1] * pm[0];
+        }
+    }
+    if (a.mode != 0) {
+        __syncthreads();
         return;
     }
+    block_reduce<7>(tacc, sh.red);
+    if (tid >= 37 && tid < 44) {
+        const int k = tid - 37;  // dm, Pp[3], Lp[3], added to the uncovered nodes' sums of pass 1
+        if (k == 0) Pg->dm = P.dm + tacc[0];
+        else if (k < 4) Pg->Pp[k - 1] = P.Pp[k - 1] + tacc[k];
+        else Pg->Lp[k - 4] = P.Lp[k - 4] + tacc[k];
+    }
+    __syncthreads();
+}
+
+// This particle's nodes over the window, as window bits, from the node map.
+__device__ void bits_from_map(const LaunchPart& a, int p, const BoxDesc& B, const Win& w, uint32_t* bits) {
+    const uint16_t* om = a.omap + B.ooff;
+    const uint16_t me = (uint16_t)(p + 1);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int base = 0; base < w.nsites; base += PBLOCK * KSCAN) {
+        bool in[KSCAN];
+#pragma unroll
+        for (int k = 0; k < KSCAN; ++k) {
+            const int i = base + k * PBLOCK + tid;
+            in[k] = false;
+            if (i < w.nsites) {
+                int gx, gy, gz;
+                win_node(w, B, i, gx, gy, gz);
+                in[k] = om[gx + B.nx * (gy + B.ny * gz)] == me;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KSCAN; ++k) {
+            if (base + k * PBLOCK >= w.nsites) break;  // uniform over the block
+            const unsigned long long m = __ballot(in[k]);
+            if (lane == 0) {
+                const int w0 = (base + k * PBLOCK + wv * 64) >> 5;
+                bits[w0] = (uint32_t)m;
+                bits[w0 + 1] = (uint32_t)(m >> 32);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Pass 2: the boundary links (fluid x, x + c_b solid of this particle; bits
+// holds this particle's nodes over the window), staged in LDS and written in
+// (window index, direction) order, and their moments, from which zeta of
+// eqs. drag1-drag4 is evaluated when the next step starts.
+template <int Q>
+__device__ void link_pass(const LaunchPart& a, int p, const PartDev& P, const BoxDesc& B, const Win& w,
+                          const uint32_t* bits, uint32_t* stage, RemapShm& sh) {
+    double (*red)[PWAVES] = sh.red;
+    int* wtot = sh.wtot;
+    int (*ired)[PWAVES] = sh.ired;
+    PartDev* Pg = a.parts + p;
+    const uint16_t* om = a.omap + B.ooff;
+    const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
+    const int nsites = w.nsites;
+    const int* lo = w.lo;
+    const int* wn = w.wn;
+    const bool* whole = w.whole;
+    const double rw0 = w.rw0, rw1 = w.rw1;
 
     ZAcc<Q> z;
     z.clear();
@@ -1085,7 +1293,8 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     const int lcap = P.lcap;
     uint32_t* L = a.links + P.lbase;
     // the link mask of window node i: bit b set when i is fluid and i + c_b
-    // is solid here (the node map is read only where bits[] says fluid)
+    // is solid here (the node map is read only where bits[] says not this
+    // particle's)
     auto link_mask = [&](int i, uint16_t own, int& s, int& gx, int& gy, int& gz) -> uint32_t {
         uint32_t lm = 0;
         int wx, wy;
@@ -1112,9 +1321,9 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
     };
     const int nch = (nsites + PBLOCK - 1) / PBLOCK;
     if (nch <= P2B) {
-        // pass 2, small windows: every chunk's masks first (the node-map
-        // loads of all chunks in flight together), one block scan over all
-        // chunks, one staged copy-out; same order and same sums as below
+        // small windows: every chunk's masks first (the node-map loads of all
+        // chunks in flight together), one block scan over all chunks, one
+        // staged copy-out; same order and same sums as below
         uint32_t lmv[P2B];
         int sv[P2B], offv[P2B];
         uint16_t ownv[P2B];
@@ -1159,9 +1368,9 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
         for (int c = 0; c < P2B; ++c) {
             if (c < nch) {
                 int before = 0, all = 0;
-                for (int w = 0; w < PWAVES; ++w) {
-                    const int t = sh.wchunk[c][w];
-                    if (w < wv) before += t;
+                for (int v = 0; v < PWAVES; ++v) {
+                    const int t = sh.wchunk[c][v];
+                    if (v < wv) before += t;
                     all += t;
                 }
                 offv[c] += total + before;
@@ -1196,10 +1405,7 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             }
         }
         running = total;
-        if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
     } else {
-        // pass 2: boundary links (fluid x, x + c_b solid here), staged in LDS
-        // and written in (window index, direction) order
         for (int base = 0; base < nsites; base += PBLOCK) {
             const int i = base + tid;
             uint32_t lm = 0;
@@ -1219,9 +1425,9 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             if (lane == 63) wtot[wv] = incl;
             __syncthreads();
             int off = incl - cnt, total = 0;
-            for (int w = 0; w < PWAVES; ++w) {
-                if (w < wv) off += wtot[w];
-                total += wtot[w];
+            for (int v = 0; v < PWAVES; ++v) {
+                if (v < wv) off += wtot[v];
+                total += wtot[v];
             }
             uint32_t mm = lm;
             while (mm) {
@@ -1248,49 +1454,77 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, const Pa
             }
             running += total;
         }
-        if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
     }
+    if (running > lcap && tid == 0) atomicOr(a.flags, (int)F_LINKS);
 
-    double all[22];
-    for (int k = 0; k < 7; ++k) all[k] = tacc[k];
-    for (int k = 0; k < 9; ++k) all[7 + k] = z.zfw[k];
-    for (int k = 0; k < 6; ++k) all[16 + k] = z.ztw[k];
-    block_reduce<22>(all, red);
-    const int iv[8] = {z.cnt6[0], z.cnt6[1], z.cnt6[2], z.cnt6[3], z.cnt6[4], z.cnt6[5], z.w36s, nsol};
-    for (int k = 0; k < 8; ++k) {
+    double all[15];
+    for (int k = 0; k < 9; ++k) all[k] = z.zfw[k];
+    for (int k = 0; k < 6; ++k) all[9 + k] = z.ztw[k];
+    block_reduce<15>(all, red);
+    const int iv[7] = {z.cnt6[0], z.cnt6[1], z.cnt6[2], z.cnt6[3], z.cnt6[4], z.cnt6[5], z.w36s};
+    for (int k = 0; k < 7; ++k) {
         const int sm = wsumi(iv[k]);
         if (lane == 0) ired[k][wv] = sm;
     }
     __syncthreads();
-    // one lane per output: the integer sums, the moments of the new link set
-    // about this centre (zeta follows from them, eqs. drag1-drag4, when the
-    // next step starts), the transition totals and the solid count
+    // one lane per output: the integer sums and the moments of the new link
+    // set about this centre
     auto itot = [&](int k) {
         int t = 0;
-        for (int w = 0; w < PWAVES; ++w) t += ired[k][w];
+        for (int v = 0; v < PWAVES; ++v) t += ired[k][v];
         return t;
     };
     if (tid == 36) {
         Pg->wsum = itot(6) / (double)WSCALE<Q>;
         Pg->nlinks = running < lcap ? running : lcap;
-    } else if (tid >= 37 && tid < 44 && mode == 0) {
-        const int k = tid - 37;  // dm, Pp[3], Lp[3]
-        const double v = red[k][0];  // the block totals stay in LDS after the reduction
-        if (k == 0) Pg->dm = P.dm + v;
-        else if (k < 4) Pg->Pp[k - 1] = P.Pp[k - 1] + v;
-        else Pg->Lp[k - 4] = P.Lp[k - 4] + v;
-    } else if (tid == 44) {
-        const int ns = itot(7);
-        if (ns != P.n_solid) atomicAdd(&a.rt[bi].n_solid, ns - P.n_solid);
-        Pg->n_solid = ns;
-    } else if (tid >= 45 && tid < 69) {  // the moments of the new link set about this centre
+    } else if (tid >= 45 && tid < 69) {
         const int k = tid - 45;
         if (k < 6) Pg->zm0[k] = itot(k);
-        else if (k < 15) Pg->zm1[k - 6] = red[7 + (k - 6)][0];
-        else if (k < 21) Pg->zm2[k - 15] = red[16 + (k - 15)][0];
+        else if (k < 15) Pg->zm1[k - 6] = red[k - 6][0];  // the block totals stay in LDS after the reduction
+        else if (k < 21) Pg->zm2[k - 15] = red[9 + (k - 15)][0];
         else Pg->xref[k - 21] = P.xu[k - 21];
     }
-    if (mode == 0 && a.near.flags) mark_near(a.near, B, lo, wn);
+}
+
+// Steps 8-9 for particle p with its (new) state staged in LDS (P), in one
+// work-group: scan, claims, links.  Only for a particle alone in its box
+// (mode 0), or for adding / removing one particle at set-up (modes 1, 2),
+// since the claims and the links here follow the scan without waiting for
+// other work-groups.  stores_done: the bounce-back stores of the step are
+// complete (a kernel boundary lies between); otherwise the claims wait for
+// them first.
+template <int ST, int Q>
+__device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, PartDev& P, RemapShm& sh, uint32_t* smem,
+                                            bool stores_done) {
+    uint32_t* bits = smem;
+    uint32_t* stage = smem + a.lds_words;
+    uint32_t* cand = stage;  // the candidate bits are consumed before the links are staged
+    const BoxDesc& B = a.boxes[P.box];
+    Win w;
+    if (!window_of(a, P, B, w)) return;
+    const int mode = a.mode;
+    if (mode == 0 && !scan_needed(P)) {
+        // no node can have changed side since the last scan
+        if (a.near.flags) mark_near(a.near, B, w.lo, w.wn);
+        return;
+    }
+    const int res = scan_pass<ST, Q>(a, p, P, B, w, bits, cand, sh, 0u);
+    if (mode == 2) {
+        if (threadIdx.x == 0) a.parts[p].nlinks = 0;
+        return;
+    }
+    if (mode == 0 && !(res & 1)) {
+        // no node changed side: the link set and the link weights stay, no
+        // mass or momentum moved
+        if (a.near.flags) mark_near(a.near, B, w.lo, w.wn);
+        return;
+    }
+    if (res & 2) {
+        if (!stores_done) __syncthreads();  // the bounce-back writes before the covered-node reads
+        claim_pass<ST, Q>(a, p, P, B, w, cand, sh);
+    }
+    link_pass<Q>(a, p, P, B, w, bits, stage, sh);
+    if (mode == 0 && a.near.flags) mark_near(a.near, B, w.lo, w.wn);
 }
 
 template <int ST, int Q>
@@ -1319,9 +1553,78 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
     load_particle<ST, Q>(a, p, &P, lr);
     solve_phase<ST, Q>(a, p, P, sh.s, lr, true);
     // the new state in LDS before the remap; the bounce-back stores may still
-    // be in flight (the remap waits for them only if it tests the window)
+    // be in flight (the remap waits for them only before its claims)
     lds_barrier();
     remap_phase<ST, Q>(a, p, P, sh.r, smem, false);
+}
+
+// Boxes with several particles take three kernels per step, so that every
+// particle's node-map update is complete before any particle claims a node,
+// and every claim before any link list is rebuilt (the order of the paper's
+// Appendix A: the whole node map at t+1, then links and drag matrices).
+//
+// 1. Steps 3-7 and pass 1 of the remap: releases, claim candidates (kept in
+//    this particle's area of a.cand), stamps of the cells where owners change.
+template <int ST, int Q>
+__global__ __launch_bounds__(PBLOCK) void k_particle_solve_map(LaunchPart a) {
+    __shared__ PartDev P;
+    __shared__ union {
+        SolveShm s;
+        RemapShm r;
+    } sh;
+    const int p = a.first + (int)blockIdx.x;
+    LinkRegs<typename Store<ST>::T> lr;
+    load_particle<ST, Q>(a, p, &P, lr);
+    solve_phase<ST, Q>(a, p, P, sh.s, lr, true);
+    lds_barrier();
+    PartDev* Pg = a.parts + p;
+    const BoxDesc& B = a.boxes[P.box];
+    Win w;
+    int res = 0;
+    if (window_of(a, P, B, w) && scan_needed(P))
+        res = scan_pass<ST, Q>(a, p, P, B, w, nullptr, a.cand + (size_t)p * a.lds_words, sh.r, *a.epoch);
+    if (threadIdx.x == 0) {
+        Pg->nchg = res & 1;
+        Pg->ncand = (res >> 1) & 1;
+    }
+}
+
+// 2. Claims of the candidates, after every particle's releases.
+template <int ST, int Q>
+__global__ __launch_bounds__(PBLOCK) void k_particle_claim(LaunchPart a) {
+    __shared__ PartDev P;
+    __shared__ RemapShm sh;
+    const int p = a.first + (int)blockIdx.x;
+    if (a.parts[p].ncand == 0) return;
+    stage_particle(a.parts + p, &P);
+    const BoxDesc& B = a.boxes[P.box];
+    Win w;
+    if (!window_of(a, P, B, w)) return;
+    claim_pass<ST, Q>(a, p, P, B, w, a.cand + (size_t)p * a.lds_words, sh);
+}
+
+// 3. Links and their moments, from the complete node map, for a particle whose
+//    own nodes changed or in whose window another particle's did.  With
+//    a.force_box >= 0 (after a particle was added to that box at set-up):
+//    every particle of that box, and nothing else.
+template <int Q>
+__global__ __launch_bounds__(PBLOCK) void k_particle_links(LaunchPart a) {
+    extern __shared__ uint32_t smem[];
+    __shared__ PartDev P;
+    __shared__ RemapShm sh;
+    const int p = a.first + (int)blockIdx.x;
+    if (a.force_box >= 0 && a.parts[p].box != a.force_box) return;
+    stage_particle(a.parts + p, &P);
+    const BoxDesc& B = a.boxes[P.box];
+    Win w;
+    if (!window_of(a, P, B, w)) return;
+    const bool rebuild = a.force_box >= 0 || P.nchg != 0 || window_stamped(a, B, w, *a.epoch);
+    if (rebuild) {
+        uint32_t* bits = smem;
+        bits_from_map(a, p, B, w, bits);
+        link_pass<Q>(a, p, P, B, w, bits, smem + a.lds_words, sh);
+    }
+    if (a.force_box < 0 && a.near.flags) mark_near(a.near, B, w.lo, w.wn);
 }
 
 // Near set from the particles' current positions (set-up and re-tuning).
@@ -1344,22 +1647,54 @@ hipError_t launch_near_mark(const LaunchPart& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-size_t particle_remap_lds_bytes(int lds_words) { return (size_t)(lds_words + STAGE) * sizeof(uint32_t); }
+// The bitmask of the window, and the link stage, which the candidate bits of
+// the single-work-group remap share (they are consumed before links are
+// staged).
+size_t particle_remap_lds_bytes(int lds_words) {
+    return (size_t)(lds_words + (lds_words > STAGE ? lds_words : STAGE)) * sizeof(uint32_t);
+}
 
-template <int Q>
-static hipError_t solve_q(const LaunchPart& a, hipStream_t st) {
+template <int ST, int Q>
+struct SolveMapK {
+    static void go(const LaunchPart& a, hipStream_t st) {
+        hipLaunchKernelGGL((k_particle_solve_map<ST, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a);
+    }
+};
+template <int ST, int Q>
+struct ClaimK {
+    static void go(const LaunchPart& a, hipStream_t st) {
+        hipLaunchKernelGGL((k_particle_claim<ST, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a);
+    }
+};
+template <template <int, int> class K, int Q>
+static hipError_t by_storage(const LaunchPart& a, hipStream_t st) {
     switch (a.kp.storage) {
-        case ST_F64: hipLaunchKernelGGL((k_particle_solve<ST_F64, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
-        case ST_F32: hipLaunchKernelGGL((k_particle_solve<ST_F32, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
-        case ST_F16: hipLaunchKernelGGL((k_particle_solve<ST_F16, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_particle_solve<ST_BF16, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a); break;
+        case ST_F64: K<ST_F64, Q>::go(a, st); break;
+        case ST_F32: K<ST_F32, Q>::go(a, st); break;
+        case ST_F16: K<ST_F16, Q>::go(a, st); break;
+        default: K<ST_BF16, Q>::go(a, st); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st) {
+hipError_t launch_particle_solve_map(const LaunchPart& a, hipStream_t st) {
     if (a.count <= 0) return hipSuccess;
-    return a.kp.q == 27 ? solve_q<27>(a, st) : solve_q<19>(a, st);
+    return a.kp.q == 27 ? by_storage<SolveMapK, 27>(a, st) : by_storage<SolveMapK, 19>(a, st);
+}
+
+hipError_t launch_particle_claim(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    return a.kp.q == 27 ? by_storage<ClaimK, 27>(a, st) : by_storage<ClaimK, 19>(a, st);
+}
+
+hipError_t launch_particle_links(const LaunchPart& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    const size_t lds = particle_remap_lds_bytes(a.lds_words);
+    if (a.kp.q == 27)
+        hipLaunchKernelGGL((k_particle_links<27>), dim3(a.count), dim3(PBLOCK), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_particle_links<19>), dim3(a.count), dim3(PBLOCK), lds, st, a);
+    return hipGetLastError();
 }
 
 template <int ST, int Q>

@@ -20,7 +20,10 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int FIELDS_CHUNK = 1 << 18;  // sites per read-back chunk
-constexpr int MAX_LDS_WORDS = 10240;   // window bitmask budget (40 KB; with the 16 KB stage < 64 KB)
+// window bitmask budget: 28 KB, twice (the bitmask and the candidate bits,
+// which share the 16 KB link stage when smaller) under the 64 KB of LDS a
+// work-group may hold
+constexpr int MAX_LDS_WORDS = 7168;
 constexpr int NEAR_MARGIN = 2;         // nodes of the near set beyond each particle window
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -28,9 +31,10 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
            flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, warm = 0, step_ctr = 0,
-           total = 0;
+           stamps = 0, cand = 0, total = 0;
+    long long cells = 0;  // owner-change stamp cells over all boxes
     int near_blocks = 0;  // collide-stream blocks that a near set can name (per slot)
-    std::vector<long long> foff, stride, ooff;
+    std::vector<long long> foff, stride, ooff, coff;
     std::vector<int> tile0, ntiles;
     long long pop_elems = 0, omap_elems = 0, link_pool = 0;
     int total_tiles = 0, max_particles = 0, lds_words = 0;
@@ -64,6 +68,8 @@ bool valid_cfg(const lb_config* c, int nboxes, const lb_box* boxes, std::string*
     if (c->storage < 0 || c->storage > 3) return bad("unknown storage");
     if (c->rho0 != 1.0) return bad("rho0 must be 1");
     if (!(c->max_semi_axis > 0)) return bad("max_semi_axis must be positive");
+    // the node map holds id + 1 in 16 bits, 0xFFFF marking walls
+    if (c->max_particles < 0 || c->max_particles > 65534) return bad("max_particles must be in 0..65534");
     if (c->rotation < 0 || c->rotation > 2) return bad("rotation must be LB_ROT_ANALYTIC, LB_ROT_FD or LB_ROT_PC");
     if (lds_words_for(c->max_semi_axis) > MAX_LDS_WORDS) return bad("max_semi_axis too large for the remap window");
     for (int b = 0; b < nboxes; ++b) {
@@ -99,6 +105,8 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
         L.ntiles.push_back(nt);
         tiles += nt;
         maxpart = std::max(maxpart, (size_t)((n + TILE - 1) / TILE) * 6 * sizeof(double));
+        L.coff.push_back(L.cells);
+        L.cells += (long long)((boxes[b].nx + 7) / 8) * ((boxes[b].ny + 7) / 8) * ((boxes[b].nz + 7) / 8);
     }
     L.pop_elems = off;
     L.omap_elems = ooff;
@@ -135,6 +143,10 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     // warm start: per particle load scale (1), prediction (6) and training
     // sample (8 + 6 floats = 7 doubles); then the start field's scratch
     L.warm = take(sizeof(double) * (14 * (size_t)L.max_particles + stokes_scratch_doubles(nboxes, tiles)));
+    // boxes with several particles: owner-change stamps per cell of 8^3
+    // nodes, and each particle's remap claim candidates (one window bitmask)
+    L.stamps = take(sizeof(uint32_t) * (size_t)L.cells);
+    L.cand = take(sizeof(uint32_t) * (size_t)L.max_particles * L.lds_words);
     L.total = p;
     return L;
 }
@@ -277,6 +289,12 @@ LaunchPart part_launch(lb_ctx* ctx, int first, int count, int mode) {
     a.kp = ctx->kp;
     a.lds_words = ctx->L.lds_words;
     a.mode = mode;
+    a.stamps = ctx->at<uint32_t>(ctx->L.stamps);
+    // after the collide launch of a step, the counter slot of the current
+    // parity holds step + 1: unique to the step, also in graph replays
+    a.epoch = ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur;
+    a.cand = ctx->at<uint32_t>(ctx->L.cand);
+    a.force_box = -1;
     return a;
 }
 
@@ -447,6 +465,9 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
         D.counterforce = cfg->counterforce;
         magic_div(X.nx, D.mnx, D.lnx);
         magic_div(X.ny, D.mny, D.lny);
+        D.coff = ctx->L.coff[b];
+        D.cnx = (X.nx + 7) / 8;
+        D.cny = (X.ny + 7) / 8;
         for (int k = 0; k < 3; ++k) {
             D.wall_lo[k] = X.wall_lo[k];
             D.wall_hi[k] = X.wall_hi[k];
@@ -522,6 +543,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
             e2 = hipMemsetAsync(ctx->arena + ctx->L.near_flags, 0, ctx->L.near_count + 4 * sizeof(int) - ctx->L.near_flags,
                                 ctx->stream);
         if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.step_ctr, 0, sizeof(uint32_t) * 2, ctx->stream);
+        if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.stamps, 0, sizeof(uint32_t) * ctx->L.cells, ctx->stream);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
         if (e2 != hipSuccess) {
             std::fprintf(stderr, "lb_init: %s\n", hipGetErrorString(e2));
@@ -587,6 +609,17 @@ lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const d
     for (int k = 0; k < 3; ++k) h.axes[k] = semi_axes[k];
     ctx->np++;
     if (id) *id = pid;
+    bool shared = false;
+    for (int p = 0; p < pid; ++p) shared = shared || ctx->hpart[p].box == box;
+    if (shared) {
+        // the new nodes may have been fluid neighbours of another particle of
+        // the box: every particle there rebuilds its links from the node map
+        LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
+        a.force_box = box;
+        HIPC(launch_particle_links(a, ctx->stream));
+        s = flags_status(ctx);
+        if (s != LB_OK) return s;
+    }
     return near_rebuild(ctx);
 }
 
@@ -724,10 +757,12 @@ lb_status launch_particles(lb_ctx* ctx, hipStream_t st) {
         // can share a work-group
         HIPC(launch_particle_step(a, st));
     } else {
-        // the kernel boundary orders every particle's bounce-back before any
-        // particle's covered-node reads
-        HIPC(launch_particle_solve(a, st));
-        HIPC(launch_particle_remap(a, st));
+        // kernel boundaries order, over all particles: every bounce-back and
+        // release before any claim (and its covered-node reads), every claim
+        // before any link rebuild
+        HIPC(launch_particle_solve_map(a, st));
+        HIPC(launch_particle_claim(a, st));
+        HIPC(launch_particle_links(a, st));
     }
     return LB_OK;
 }
@@ -1146,8 +1181,9 @@ lb_status lb_get_step(lb_ctx* ctx, long long* step) {
 
 namespace {
 // 3: the particle record carries the previous orientation and the remap
-// skip reference, and no drag matrix (rebuilt from the link moments)
-constexpr int CKPT_VERSION = 3;
+// skip reference, and no drag matrix (rebuilt from the link moments);
+// 4: and the remap change flags of boxes with several particles
+constexpr int CKPT_VERSION = 4;
 struct CkptHeader {
     char magic[8];
     int version, nboxes, storage, np, cur, pad;  // version: CKPT_VERSION
@@ -1232,8 +1268,11 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
     std::fclose(fp);
     if (!ok) return fail(ctx, LB_EIO, "checkpoint read failed");
     ctx->np = h.np;
+    ctx->opb_np = -1;  // which boxes hold several particles is recomputed
     ctx->step = h.step;
     ctx->link_used = h.link_used;
+    // stamps of the steps after the checkpoint must not match an epoch again
+    HIPC(hipMemsetAsync(ctx->arena + ctx->L.stamps, 0, sizeof(uint32_t) * ctx->L.cells, ctx->stream));
     {
         const uint32_t st32 = (uint32_t)h.step;  // the device step counter of the restored parity
         HIPC(hipMemcpyAsync(ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur, &st32, sizeof st32, hipMemcpyHostToDevice,

@@ -87,6 +87,8 @@ struct BoxDesc {
     double gcf[3];        // counter-force density -fext / (n - n_wall), or 0
     uint32_t mnx, mny;    // site -> (x, y, z) by multiplication: see magic_div
     int lnx, lny;
+    long long coff;       // offset of the box's cells (8^3 nodes each) in the owner-change stamps
+    int cnx, cny;         // cells along x and y
 };
 
 // Division of 0 <= n < 2^27 (a site index, SITE_BITS) by d >= 1 as one
@@ -136,6 +138,9 @@ struct PartDev {
     double wsum;          // sum of w_b over the current links
     int box, nlinks, lcap, n_solid;
     int zm0[6];           // sum 36 w c c^T (upper triangle), exact
+    // set by the remap scan of the step in boxes with several particles:
+    // some node changed side / some node is a claim candidate
+    int nchg, ncand;
     long long lbase;      // offset of this particle's links in the pool
 };
 

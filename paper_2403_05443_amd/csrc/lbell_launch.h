@@ -73,11 +73,19 @@ struct LaunchPart {
     int lds_words;    // 32-bit words of the remap window bitmask
     int mode;         // remap: 0 step, 1 add (no transitions), 2 remove
     NearSet near;     // set of the next step: the preceding collide launch empties it, remap (mode 0) fills it
+    // boxes with several particles (solve_map, claim, links):
+    uint32_t* stamps;        // per cell of 8^3 nodes: the epoch of the last step an owner changed there
+    const uint32_t* epoch;   // this step's epoch (the device step counter after the collide launch)
+    uint32_t* cand;          // claim candidates, lds_words bit words per particle
+    int force_box;           // links: >= 0 rebuild every particle of this box (set-up), else -1
 };
 
-hipError_t launch_particle_solve(const LaunchPart& a, hipStream_t st);
 hipError_t launch_particle_remap(const LaunchPart& a, hipStream_t st);
 hipError_t launch_particle_step(const LaunchPart& a, hipStream_t st);  // solve + remap, one particle per box
+// boxes with several particles: the three kernels of a step, in this order
+hipError_t launch_particle_solve_map(const LaunchPart& a, hipStream_t st);
+hipError_t launch_particle_claim(const LaunchPart& a, hipStream_t st);
+hipError_t launch_particle_links(const LaunchPart& a, hipStream_t st);
 size_t particle_remap_lds_bytes(int lds_words);
 hipError_t launch_near_mark(const LaunchPart& a, hipStream_t st);
 

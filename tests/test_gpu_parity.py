@@ -275,6 +275,57 @@ def test_two_particles(lb):
     assert np.array_equal(g.mask(), o.mask())
 
 
+@pytest.mark.parametrize("variant", ["0", "12"], ids=["pull", "in-place"])
+def test_two_particles_closing_to_one_node_gap(lb, variant):
+    """Two particles pulled towards each other until a single fluid node
+    separates them (the oracle reports an overlap at step 330; the run stops
+    at 318).  When one of them covers or uncovers a node beside the other, the
+    other's link list changes although none of its own nodes did: the node map
+    of step t+1 is complete before any link list is rebuilt (Appendix A,
+    steps 8-9).  Masks and link lists equal the oracle's bit for bit after
+    every step; such link changes happen (counted on the oracle, so a remap
+    that kept stale links would fail here); trajectories within the FP64 bar."""
+    os.environ["LBELL_K1_VARIANT"] = variant
+    try:
+        g, o = pair(lb, (40, 20, 22), "bgk", 0.9, "fp64")
+    finally:
+        del os.environ["LBELL_K1_VARIANT"]
+    specs = [((14.6, 9.6, 10.8), (5.0, 3.0, 2.5), (0.95, 0.1, 0.2, 0.2), 1.0),
+             ((24.5, 10.2, 11.1), (4.5, 3.5, 2.5), (0.9, -0.2, 0.1, 0.35), -1.0)]
+    ids = []
+    for c, ax, q, sgn in specs:
+        q = np.array(q) / np.linalg.norm(q)
+        pg, po = g.add_ellipsoid(c, ax, q), o.add_ellipsoid(c, ax, q)
+        for s, p in ((g, pg), (o, po)):
+            s.set_external(p, (0.06 * sgn, 5e-4 * sgn, 0.0), (0.0, 0.0, 2e-3 * sgn))
+        ids.append((pg, po, snapshot(o, po)))
+    (ga, oa, _), (gb, ob, _) = ids
+
+    def linkset(sim, p):
+        return sorted_links(*sim.links(p))
+
+    m_prev = o.mask()
+    prev = [linkset(o, oa), linkset(o, ob)]
+    foreign = 0
+    for step in range(318):
+        g.step(1)
+        o.step(1)
+        m = o.mask()
+        assert np.array_equal(g.mask(), m), step
+        cur = [linkset(o, oa), linkset(o, ob)]
+        for k, (pg, po) in enumerate(((ga, oa), (gb, ob))):
+            assert np.array_equal(linkset(g, pg), cur[k]), (step, k)
+            own_changed = ((m_prev == po + 1) != (m == po + 1)).any()
+            if not own_changed and not np.array_equal(cur[k], prev[k]):
+                foreign += 1
+        m_prev, prev = m, cur
+    assert o.overlaps() == 0
+    print("link lists changed by the other particle:", foreign)
+    assert foreign >= 3
+    for pg, po, x0 in ids:
+        compare_particles(g, o, pg, po, 1e-9, x0, a=5.0)
+
+
 # ----------------------------------------------------------------- batching --
 
 def test_batch_matches_single_boxes_bitwise(lb):
