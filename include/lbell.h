@@ -367,6 +367,24 @@ lb_status lbs_grad(lbs* s, const float* X, const float* Y, int n, float* grads, 
 /* Releases host resources of s (not the arena). */
 lb_status lbs_destroy(lbs* s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the loss
+ * and gradient of lbs_grad, computed by the same kernels in the same order,
+ * with no surrogate object, no arena and no allocation of any kind.  All
+ * pointers are device memory owned by the caller: params (5126 floats, the
+ * order above), X (n x 8), Y (n x 6), grads (5126 floats, written), loss (one
+ * float, written; may be NULL).  Work is enqueued on hip_stream (a stream of
+ * the current device) and the call returns without waiting.  The per-tile
+ * partial gradients live in a fixed device array of the library (5.3 MB,
+ * one per device, kept until the process ends): n above
+ * LBS_NOALLOC_MAX_SAMPLES is rejected with LB_EINVAL, as are NULL pointers
+ * and n < 1.  Every call on a device shares that array, so calls that overlap
+ * on one device (other streams, other host threads) race; order them on one
+ * stream. */
+#define LBS_NOALLOC_MAX_SAMPLES 4096
+lb_status lbs_grad_noalloc(const float* params, const float* X, const float* Y, int n, float* grads, float* loss,
+                           void* hip_stream);
+
 /* Warm start of every particle of the context: the surrogate predicts each
  * particle's steady velocities from its current state and external load;
  * they are set as the particles' velocities (a prediction above the

@@ -230,13 +230,14 @@ __global__ __launch_bounds__(64 * MLP_WAVES) void k_mlp(MlpArgs a) {
 // One thread per parameter: sum of the tiles' partial gradients in tile
 // order; mode 0 applies Adam (c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t)),
 // mode 1 writes the sum to gsum.  Thread 0 also adds the tiles' squared
-// errors to *loss_acc.
+// errors to *loss_acc, or writes their sum over loss_div to *loss_out.
 __global__ __launch_bounds__(256) void k_mlp_reduce(MlpReduceArgs a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && a.loss_acc) {
+    if (p == 0 && (a.loss_acc || a.loss_out)) {
         double s = 0.0;
         for (int t = 0; t < a.ntiles; ++t) s += (double)a.Lpart[t];
-        *a.loss_acc += s;
+        if (a.loss_acc) *a.loss_acc += s;
+        if (a.loss_out) *a.loss_out = (float)(s / a.loss_div);
     }
     if (p >= MLP_NP) return;
     float gsum = 0.f;

@@ -117,6 +117,8 @@ struct MlpReduceArgs {
     float lr, c1, c2;  // Adam: step size, 1 / (1 - beta1^t), 1 / (1 - beta2^t)
     float* gsum;       // mode 1: summed gradient
     double* loss_acc;  // += sum of the tiles' squared errors (may be null)
+    float* loss_out;   // or: = that sum / loss_div (may be null)
+    double loss_div;
     int mode;          // 0 Adam update, 1 write the summed gradient
 };
 hipError_t launch_mlp(const MlpArgs& a, hipStream_t st);

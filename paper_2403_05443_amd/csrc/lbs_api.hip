@@ -3,6 +3,7 @@
 // arithmetic step runs in the kernels of k_mlp.hip.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lbell.h"
@@ -47,6 +48,31 @@ lb_status hipc(lbs* s, hipError_t e, const char* what) {
         lb_status _s = hipc(s, (expr), #expr);            \
         if (_s != LB_OK) return _s;                       \
     } while (0)
+
+// Scratch of lbs_grad_noalloc: the per-tile partial gradients and squared
+// errors of up to LBS_NOALLOC_MAX_SAMPLES samples (16 samples per tile),
+// 5.3 MB, one copy on every device the library runs on, held until the
+// process ends.  Its address is taken once per device with that device
+// current; host code uses that address only, never the array's name.
+constexpr int NOALLOC_TILES = (LBS_NOALLOC_MAX_SAMPLES + 15) / 16;
+static __device__ __align__(256) float scratch[(size_t)NOALLOC_TILES * MLP_NP + NOALLOC_TILES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+lb_status noalloc_scratch(float** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LB_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LB_EDEVICE;
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
 
 lb_status upload(lbs* s, const float* X, const float* Y, int n) {
     HC(hipMemcpyAsync(s->X, X, sizeof(float) * MLP_IN * (size_t)n, hipMemcpyHostToDevice, s->stream));
@@ -176,6 +202,31 @@ lb_status lbs_grad(lbs* s, const float* X, const float* Y, int n, float* grads, 
     HC(hipMemcpyAsync(&acc, s->loss_acc, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HC(hipStreamSynchronize(s->stream));
     if (loss) *loss = (float)(acc / (6.0 * n));
+    return LB_OK;
+}
+
+lb_status lbs_grad_noalloc(const float* params, const float* X, const float* Y, int n, float* grads, float* loss,
+                           void* hip_stream) {
+    if (!params || !X || !Y || !grads || n < 1 || n > LBS_NOALLOC_MAX_SAMPLES) return LB_EINVAL;
+    float* sc = nullptr;
+    const lb_status st = noalloc_scratch(&sc);
+    if (st != LB_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    float* G = sc;
+    float* Lpart = sc + (size_t)NOALLOC_TILES * MLP_NP;
+    // the same kernels and sums as lbs_grad; every tile the sums read is
+    // written first, so nothing in the scratch needs clearing
+    MlpArgs a{params, X, Y, nullptr, G, Lpart, n, (float)(2.0 / (6.0 * n)), 1};
+    if (launch_mlp(a, stream) != hipSuccess) return LB_EDEVICE;
+    MlpReduceArgs r{};
+    r.G = G;
+    r.Lpart = Lpart;
+    r.ntiles = (n + 15) / 16;
+    r.gsum = grads;
+    r.loss_out = loss;
+    r.loss_div = 6.0 * n;
+    r.mode = 1;
+    if (launch_mlp_reduce(r, stream) != hipSuccess) return LB_EDEVICE;
     return LB_OK;
 }
 

@@ -87,6 +87,7 @@ SIGNATURES = {
     "lbs_train": (C.c_int, [_VP, _F, _F, C.c_int, C.c_int, C.c_int, C.c_float, _F]),
     "lbs_predict": (C.c_int, [_VP, _F, C.c_int, _F]),
     "lbs_grad": (C.c_int, [_VP, _F, _F, C.c_int, _F, _F]),
+    "lbs_grad_noalloc": (C.c_int, [_VP, _VP, _VP, C.c_int, _VP, _VP, _VP]),
     "lbs_destroy": (C.c_int, [_VP]),
     "lb_destroy": (C.c_int, [_VP]),
     "lb_status_str": (C.c_char_p, [C.c_int]),

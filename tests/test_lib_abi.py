@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "lbell.h")
 def declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbs?_[a-z_0-9]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
