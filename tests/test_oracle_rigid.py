@@ -138,3 +138,52 @@ def test_squirmer_slip_is_tangential(orc):
         us = orc.squirmer_slip([a, b, b], q, 1e-3, 5e-4, R @ v)
         assert abs((R @ nrm) @ us) < 1e-15
         assert np.linalg.norm(us) > 0
+
+
+def test_squirmer_spheroidal_coordinate_on_the_surface(orc):
+    """Eq. squirmer on a prolate spheroid (a, b, b), eps > 0, B1 = 0: the slip
+    is -B2 zeta (s . e) s with zeta = z / a on the surface (the foci sit at
+    +-a eps on the axis, and on the ellipse the focal distances differ by
+    2 eps z) and s the unit meridian tangent, built here from the ellipse
+    parametrisation (z, rho) = (a cos t, b sin t), d/dt = (-a sin t, b cos t).
+    A wrong focal factor in zeta changes the B2 mode by tens of percent."""
+    rng = np.random.default_rng(11)
+    for a, b in ((5.0, 2.5), (6.0, 2.0), (3.0, 2.9)):
+        q = rand_q(rng)
+        R = rot(q)
+        for _ in range(25):
+            t = rng.uniform(0.05, np.pi - 0.05)
+            phi = rng.uniform(0, 2 * np.pi)
+            z, rho = a * np.cos(t), b * np.sin(t)
+            perp = np.array([0.0, np.cos(phi), np.sin(phi)])  # body frame, e = body x
+            x_body = np.array([z, 0, 0]) + rho * perp
+            s = np.array([-a * np.sin(t), 0, 0]) + b * np.cos(t) * perp
+            s /= np.linalg.norm(s)
+            for B1, B2 in ((0.0, 1e-3), (7e-4, -2e-3)):
+                expect = R @ (-(B1 + B2 * z / a) * s[0] * s)
+                got = orc.squirmer_slip([a, b, b], q, B1, B2, R @ x_body)
+                assert np.allclose(got, expect, rtol=1e-12, atol=1e-17), (a, b, t, B1, B2)
+
+
+def test_squirmer_spheroidal_coordinate_off_the_surface(orc):
+    """Off the surface zeta is the angular prolate spheroidal coordinate of
+    the point, cos(v) in z = f cosh(u) cos(v), rho = f sinh(u) sin(v) with
+    f = a eps: with l = cosh^2 u and h = cos^2 v, l h = (z/f)^2 and
+    l + h = 1 + (z/f)^2 + (rho/f)^2, so h is the smaller root of a quadratic
+    (an algebraic route, not the focal-distance formula of the paper); s is
+    the surface tangent at the point's axial coordinate (clamped to [-a, a],
+    reading R11)."""
+    rng = np.random.default_rng(12)
+    a, b = 5.0, 2.5
+    f = a * np.sqrt(1 - (b / a) ** 2)
+    for _ in range(40):
+        z, rho = rng.uniform(-a, a), rng.uniform(0.3, 2 * b)
+        Z2, R2 = (z / f) ** 2, (rho / f) ** 2
+        ssum = 1 + Z2 + R2
+        h = (ssum - np.sqrt(ssum * ssum - 4 * Z2)) / 2
+        zeta = np.sign(z) * np.sqrt(h)
+        ct = z / a
+        s = np.array([-a * np.sqrt(1 - ct * ct), b * ct, 0.0])
+        s /= np.linalg.norm(s)
+        got = orc.squirmer_slip([a, b, b], [1, 0, 0, 0], 0.0, 1e-3, [z, rho, 0.0])
+        assert np.allclose(got, -1e-3 * zeta * s[0] * s, rtol=1e-11, atol=1e-18), (z, rho)
