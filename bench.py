@@ -219,6 +219,9 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="run the domain-size (32^3-512^3) and resolution studies of the settling spheroid "
                          "instead of the benchmark and print their results as one JSON line")
+    ap.add_argument("--studies", default="domain,resolution,sphere_array,jeffery_domain",
+                    help="with --sweep-only: comma-separated studies to run (domain, resolution, sphere_array, "
+                         "jeffery_domain, drift_superposition)")
     ap.add_argument("--half-steps", type=int, default=500,
                     help="steps of the same workload with FP16 storage (0: skip; only with --storage fp32)")
     ap.add_argument("--d3q27-steps", type=int, default=500,
@@ -253,11 +256,16 @@ def main():
     if args.sweep_only:
         from paper_2403_05443_amd import runner
         t0 = time.perf_counter()
-        out = {"kind": "settling spheroid studies (Sec. III.A, Figs. 4 and 9)", "data": "synthetic",
-               "domain": runner.domain_sweep([32, 64, 128, 256, 512], a=7.5, b=2.5, nu=0.1, storage="fp32"),
-               "resolution": runner.resolution_sweep([2.0, 2.5, 3.0, 4.0], r=3.0),
-               "sphere_array": {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)},
-               "jeffery_domain": [runner.jeffery_half_period(L) for L in (26, 32, 40, 48, 64)]}
+        studies = {
+            "domain": lambda: runner.domain_sweep([32, 64, 128, 256, 512], a=7.5, b=2.5, nu=0.1, storage="fp32"),
+            "resolution": lambda: runner.resolution_sweep([2.0, 2.5, 3.0, 4.0], r=3.0),
+            "sphere_array": lambda: {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)},
+            "jeffery_domain": lambda: [runner.jeffery_half_period(L) for L in (26, 32, 40, 48, 64)],
+            "drift_superposition": lambda: runner.drift_superposition(bs=(2.0, 3.0, 4.0)),
+        }
+        out = {"kind": "settling spheroid studies (Sec. III.A-C, Figs. 4 and 9)", "data": "synthetic"}
+        for name in args.studies.split(","):
+            out[name] = studies[name]()
         out["seconds"] = round(time.perf_counter() - t0, 1)
         print(json.dumps(out), flush=True)
         return

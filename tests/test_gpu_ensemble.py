@@ -185,25 +185,36 @@ def test_full_ensemble_fp16_matches_single_boxes(lb):
 
 
 def test_full_ensemble_fp64_matches_oracle(lb):
-    """The same 256-box ensemble with FP64 storage, 30 steps: sampled boxes
-    against the oracle at the FP64 bar."""
+    """The same 256-box ensemble with FP64 storage, 60 steps: the smallest
+    box, the largest box and the box of the longest particle (a = 18 in a
+    45^3 box, the largest remap window) against the oracle at the FP64 bar."""
     import oracle
     from paper_2403_05443_amd.runner import build_lattice
     from paper_2403_05443_amd import workloads
     W = workloads.c4("fp64")
     g = build_lattice(W)
-    g.step(30)
-    for i in _sample_boxes(W, 2):
+    g.step(60)
+    boxes = _sample_boxes(W)
+    assert len(boxes) == 3 and max(W.particles[i].axes[0] for i in boxes) > 17.9
+    for i in boxes:
         p, b = W.particles[i], W.boxes[i]
         o = oracle.OracleSim(b.shape, W.collision, W.tau, magic=W.magic, counterforce=True)
         po = o.add_ellipsoid(p.centre, p.axes, p.quat)
         o.set_external(po, p.force, p.torque)
-        o.step(30)
+        o.step(60)
         A, B = g.particle(i), o.particle(po)
         Fg, Tg = g.force_torque(i)
         Fo, To = o.force_torque(po)
         a = p.axes[0]
-        nU, nF = np.linalg.norm(B["U"]), np.linalg.norm(Fo)
+        # natural velocity scale: the larger of |U| and the Stokes speed of the
+        # load, |F_ext| / (6 pi mu a).  A heavy particle started from rest
+        # (a = 18: M ~ 1000) moves at |U| ~ 3e-7 after 60 steps, a few percent
+        # of that scale, and the oracle's full populations (rounding ~6e-17
+        # near 1/3) resolve flow deviations of ~|U| / 6 only to ~1e-9
+        # relative there: the bar stays 1e-9 of the velocity scale
+        mu = (W.tau - 0.5) / 3.0
+        Us = np.linalg.norm(p.force) / (6 * np.pi * mu * a)
+        nU, nF = max(np.linalg.norm(B["U"]), Us), np.linalg.norm(Fo)
         errs = {"U": np.abs(A["U"] - B["U"]).max() / nU,
                 "W": np.abs(A["W"] - B["W"]).max() / max(np.linalg.norm(B["W"]), nU / a),
                 "F": np.abs(Fg - Fo).max() / nF,

@@ -326,6 +326,29 @@ def test_two_particles_closing_to_one_node_gap(lb, variant):
         compare_particles(g, o, pg, po, 1e-9, x0, a=5.0)
 
 
+@pytest.mark.parametrize("axis", [0, 2], ids=["axial", "transverse"])
+def test_torque_driven_spin(lb, axis):
+    """A torque-driven r = 2 spheroid spinning up about / across its axis
+    (the run the oracle's rotational-resistance pin checks against X^C and
+    Y^C), 400 steps in 32^3: the GPU at the FP64 bar."""
+    g, o = pair(lb, (32, 32, 32), "bgk", 1.0, "fp64")
+    T = [0.0, 0.0, 0.0]
+    T[axis] = 1e-3
+    pg = g.add_ellipsoid((15.63, 15.29, 15.57), (6.0, 3.0, 3.0), (1, 0, 0, 0))
+    po = o.add_ellipsoid((15.63, 15.29, 15.57), (6.0, 3.0, 3.0), (1, 0, 0, 0))
+    g.set_external(pg, (0, 0, 0), T)
+    o.set_external(po, (0, 0, 0), T)
+    g.step(400)
+    o.step(400)
+    A, B = g.particle(pg), o.particle(po)
+    nW = np.linalg.norm(B["W"])
+    assert nW > 1e-6
+    assert np.abs(A["W"] - B["W"]).max() / nW < 1e-9
+    Tg = g.force_torque(pg)[1]
+    To = o.force_torque(po)[1]
+    assert np.abs(Tg - To).max() / np.linalg.norm(To) < 1e-9
+
+
 # ----------------------------------------------------------------- batching --
 
 def test_batch_matches_single_boxes_bitwise(lb):

@@ -59,37 +59,24 @@ def test_inclined_spheroid_drift(lb, storage):
     """128^3, a=6, b=c=2 at alpha = 45 deg to a force 5e-4, 20 000 steps.
 
     (i) Against the unbounded closed form (Oberbeck coefficients, eq. drift:
-    delta = 5.891 deg for r = 3): periodic images at L/a ~ 21 and the b = 2
-    resolution: tolerance 0.75 deg.
-    (ii) As in Sec. III.B, the drift predicted from the end-on and broadside
-    speeds measured in the same box, tan(alpha - delta) = (U_perp/U_par)
-    tan(alpha), is checked against the same closed form and tolerance.  (At
-    b = 2 the 45-degree staircase of the cross-section differs from the
-    axis-aligned one, so the two LB estimates differ by ~0.9 deg; finer
-    resolution closes the gap, Sec. III.E.)
-    (iii) The orientation stays within 1 deg (no rotation in Stokes flow)."""
+    delta = 5.891 deg for r = 3): tolerance 0.6 deg (periodic images at
+    L/a ~ 21, resolution b = 2).
+    (ii) The orientation stays within 1 deg (no rotation in Stokes flow,
+    Sec. III.B).
+    The drift predicted from end-on and broadside runs (the linear
+    superposition of Sec. III.B) is studied against resolution in
+    test_drift_superposition_converges_with_resolution."""
     from paper_2403_05443_amd import workloads
     W = workloads.c2(storage)
     q0 = np.array(W.particles[0].quat)
     v, p = _settle(lb, W)
     F = np.array(W.particles[0].force)
     delta = math.degrees(math.acos(v @ F / (np.linalg.norm(v) * np.linalg.norm(F))))
-    # aligned runs in the same box: end-on (axis along F) and broadside
-    U = {}
-    for name, q in (("par", workloads.quat_axis_angle((0, 1, 0), -math.pi / 2)), ("perp", (1.0, 0, 0, 0))):
-        Wa = workloads.c2(storage)
-        Wa.particles[0].quat = q
-        va, _ = _settle(lb, Wa)
-        U[name] = va @ F / np.linalg.norm(F)
-    alpha = math.radians(45)
-    sup = 45 - math.degrees(math.atan(U["perp"] / U["par"] * math.tan(alpha)))
     Cp, Cn = oberbeck(3.0)
-    pred = 45 - math.degrees(math.atan(Cp / Cn * math.tan(alpha)))
-    print(f"{storage}: drift {delta:.3f} deg, from aligned runs {sup:.3f} deg, closed form {pred:.3f} deg; "
-          f"U_par {U['par']:.4e} U_perp {U['perp']:.4e}")
+    pred = 45 - math.degrees(math.atan(Cp / Cn * math.tan(math.radians(45))))
+    print(f"{storage}: drift {delta:.3f} deg, closed form {pred:.3f} deg")
     assert abs(pred - 5.891) < 1e-3
-    assert abs(delta - pred) < 0.75
-    assert abs(sup - pred) < 0.75
+    assert abs(delta - pred) < 0.6
     e0, e1 = body_axis(q0), body_axis(p["q"])
     assert math.degrees(math.acos(min(1.0, abs(e0 @ e1)))) < 1.0
 
@@ -126,22 +113,16 @@ def jeffery_rhs(e, beta, rate):
     return Om @ e + beta * (Ee - e * (e @ Ee))
 
 
-def test_jeffery_orbit_period(lb):
-    """Spheroid r = 3 (a=9, b=c=3) between walls moving at -/+0.01 (shear
-    rate 0.02/126): the azimuth of the long axis about the vorticity axis
-    advances by 2 pi in T = 2 pi (r + 1/r) / rate = 131 947 steps.  Walls at
-    H/(2a) = 7 slow the rotation (Sec. III.C sees domain-size effects up to
-    64^3): tolerance 8%."""
-    from paper_2403_05443_amd import workloads
-    W = workloads.c3(r=3, seed_index=1, storage="fp32")
+def _jeffery_period(lb, W, r, chunk=500):
+    """Steps the azimuth of the long axis about the vorticity axis (z) takes to
+    advance by 2 pi, linearly interpolated within the sampling chunk."""
     g = build(lb, W)
+    g.set_graph(50)
     rate = W.notes["shear_rate"]
-    r = 3.0
     T = 2 * math.pi * (r + 1 / r) / rate
     phi, last, t = 0.0, None, 0
-    chunk = 500
-    times, phis = [], []
-    while t < 1.3 * T:
+    prev = 0.0
+    while t < 1.5 * T:
         g.step(chunk)
         t += chunk
         e = body_axis(g.particle(0)["q"])
@@ -149,17 +130,38 @@ def test_jeffery_orbit_period(lb):
         if last is not None:
             d = a - last
             d = (d + math.pi) % (2 * math.pi) - math.pi
-            phi += d
+            prev, phi = phi, phi + d
+            if abs(phi) >= 2 * math.pi:
+                return t - chunk + (2 * math.pi - abs(prev)) / (abs(phi) - abs(prev)) * chunk, T
         last = a
-        times.append(t)
-        phis.append(phi)
-    phis = np.abs(np.array(phis))
-    k = int(np.searchsorted(phis, 2 * math.pi))
-    assert k < len(phis), "orbit not completed"
-    # linear interpolation of the crossing
-    t_cross = times[k - 1] + (2 * math.pi - phis[k - 1]) / (phis[k] - phis[k - 1]) * chunk
-    print(f"Jeffery period {t_cross:.0f} steps, closed form {T:.0f}")
-    assert abs(t_cross / T - 1) < 0.08
+    return float("nan"), T
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_jeffery_orbit_period(lb, r, storage):
+    """Config 3: spheroid b = c = 3, a = 3r, seeded orientation, between walls
+    y = 0, 127 moving at -/+0.01 (shear rate 0.02/126): the azimuth of the long
+    axis about the vorticity axis advances by 2 pi in T = 2 pi (r + 1/r) /
+    rate (eq. jeffery) = 98 960 / 131 947 / 168 232 steps for r = 2 / 3 / 4.
+    Tolerance 5 % (wall confinement, Sec. III.C)."""
+    from paper_2403_05443_amd import workloads
+    W = workloads.c3(r=r, seed_index=1, storage=storage)
+    t, T = _jeffery_period(lb, W, r)
+    print(f"r={r} {storage}: Jeffery period {t:.0f} steps, closed form {T:.0f}, ratio {t / T:.4f}")
+    assert abs(t / T - 1) < 0.05
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_jeffery_orbit_period_other_orientations(lb, r, seed):
+    """The same for two more seeded orientations (FP32): the period does not
+    depend on the orbit (eq. jeffery)."""
+    from paper_2403_05443_amd import workloads
+    W = workloads.c3(r=r, seed_index=seed, storage="fp32")
+    t, T = _jeffery_period(lb, W, r)
+    print(f"r={r} seed {seed}: Jeffery period {t:.0f} steps, closed form {T:.0f}, ratio {t / T:.4f}")
+    assert abs(t / T - 1) < 0.05
 
 
 @pytest.mark.parametrize("B2", [0.0, 5e-3])
@@ -168,7 +170,7 @@ def test_squirmer_speed(lb, B2):
     (e^-2 - 1) arcoth(1/e)) = 0.8264 B1 along its axis, independent of B2.
     A force-free swimmer's periodic images decay as 1/L^3; at L=64 and with
     first-order bounce-back at b=2.5 the paper reports deviations of a few
-    percent (Sec. III.D): tolerance 6%."""
+    percent (Sec. III.D): tolerance 5%."""
     L = 64
     g = lb.Lattice([(L, L, L)], collision="trt", tau=1.0, storage="fp32", velocity_scale=2e-3)
     q = np.array([0.9, 0.2, -0.3, 0.25])
@@ -183,7 +185,7 @@ def test_squirmer_speed(lb, B2):
     along = p["U"] @ e
     print(f"B2={B2}: U.e {along:.6e}, closed form {Us:.6e}, ratio {along / Us:.4f}")
     assert abs(Us / 1e-3 - 0.82644) < 1e-4
-    assert abs(along / Us - 1) < 0.06
+    assert abs(along / Us - 1) < 0.05
     assert np.linalg.norm(p["U"] - along * e) < 0.05 * abs(along)
 
 
@@ -222,3 +224,50 @@ def test_sphere_drag_hasimoto_sizes(lb):
         radii.append(a)
     assert all(abs(a / R - 1) < 0.05 for a in radii)
     assert max(radii) / min(radii) - 1 < 0.02
+
+
+@pytest.mark.parametrize("axis,coef", [(0, 0.20166928), (2, 0.37623218)], ids=["axial", "transverse"])
+def test_torque_driven_spin_resistance(lb, axis, coef):
+    """A torque-driven r = 2 spheroid (a = 6, b = c = 3) spinning about (X^C)
+    and across (Y^C) its axis (Sec. II.C, eqs. T0 and drag4) in periodic
+    boxes L = 32, 48, 64: the rotlet's periodic images decay as (a/L)^3, so
+    Omega(L) = Omega_inf (1 + k / L^3) is fitted through the three and
+    Omega_inf compared with T / (8 pi mu a^3 X^C) (Kim & Karrila Table 3.4):
+    within 5 %."""
+    mu = (1.0 - 0.5) / 3
+    Ws = []
+    for L in (32, 48, 64):
+        g = lb.Lattice([(L, L, L)], collision="bgk", tau=1.0, storage="fp64")
+        c = (L - 1) / 2.0
+        pid = g.add_ellipsoid((c + 0.13, c - 0.21, c + 0.07), (6.0, 3.0, 3.0), (1, 0, 0, 0))
+        T = np.zeros(3)
+        T[axis] = 1e-3
+        g.set_external(pid, (0, 0, 0), T)
+        g.set_graph(50)
+        g.step(3000)
+        Ws.append(g.particle(pid)["W"][axis])
+    x = np.array([1 / 32 ** 3, 1 / 48 ** 3, 1 / 64 ** 3])
+    k1, k0 = np.polyfit(x, np.array(Ws), 1)
+    closed = 1e-3 / (8 * math.pi * mu * 6.0 ** 3 * coef)
+    print(f"spin {axis}: Omega(L) {Ws}, extrapolated {k0:.6e}, closed {closed:.6e}, ratio {k0 / closed:.4f}")
+    assert abs(k0 / closed - 1) < 0.05
+
+
+def test_drift_superposition_converges_with_resolution(lb):
+    """Sec. III.B predicts the drift of an inclined spheroid from the settling
+    speeds of its end-on and broadside orientations (linear superposition of
+    Stokes flow).  a = 3b at b = 2 (box 128^3) and b = 3 (192^3), alpha =
+    45 deg, the same speed ~1e-4: at b = 2 the 45-degree staircase of the
+    cross-section makes the inclined particle's resistance differ from the
+    mix of the axis-aligned ones (measured gap 14 %); at b = 3 the predicted
+    and measured drifts agree within 2 % (measured 0.5 %; 0.8 % at b = 4 in
+    a 256^3 box), both within 0.3 deg of the closed form 5.891 deg."""
+    from paper_2403_05443_amd import runner
+    rows = runner.drift_superposition(bs=(2.0, 3.0))
+    for r in rows:
+        print(f"b={r['b']}: measured {r['delta_measured']:.3f} deg, superposition {r['delta_superposition']:.3f} deg, "
+              f"gap {r['gap']:+.4f}, closed {r['delta_closed']:.3f}")
+    g2, g3 = abs(rows[0]["gap"]), abs(rows[1]["gap"])
+    assert g3 < 0.02 and g3 < g2
+    assert abs(rows[1]["delta_measured"] - rows[1]["delta_closed"]) < 0.3
+    assert abs(rows[1]["delta_superposition"] - rows[1]["delta_closed"]) < 0.3
