@@ -4,10 +4,16 @@ MI355X, in million lattice-site updates per second (MLUPS), with the
 collide-stream kernel's fraction of the HBM roofline and the FP64 CPU oracle
 timed on the host beside it.
 
-Default workload: the inclined sedimenting spheroid, 128^3 periodic box,
-D3Q19 TRT (Lambda = 3/16, tau+ = 0.8), spheroid a=6, b=c=2 at 45 deg to a
-5e-4 force, counter-force on, FP32 population storage.  Inputs are resident in
-device memory before the timed region starts.
+Headline workload: the batched ensemble of 256 independent periodic boxes
+(edges 32-64, 29.5 M sites, one spheroid each), D3Q19 TRT (Lambda = 3/16,
+tau+ = 1), FP16 storage of the scaled deviations with FP32 collision,
+counter-force on: its 2.24 GB of population traffic per step is far beyond
+the 256 MB last-level cache, so the roofline figure is an HBM figure.  Legs
+beside it: the 256^3 suspension of 512 squirmers in FP16 and FP32 (HBM-sized),
+its 6,400-squirmer variant (5 % volume fraction), and the 128^3 inclined
+spheroid in FP32, FP16 and D3Q27, whose in-place population buffer fits the
+last-level cache (labelled cache_resident).  Inputs are resident in device
+memory before the timed region starts.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 is refused.
 """
@@ -49,27 +55,119 @@ def traffic_record(src_sha, workload, storage, variant):
     return ent.get("traffic_bytes_per_launch")
 
 
+MALL_BYTES = 256 * 2 ** 20   # the last-level (Infinity) cache of the MI355X
+
+
+def workload_by_name(name, storage):
+    """The synthetic workloads bench.py measures, by name."""
+    from paper_2403_05443_amd import workloads
+    table = {
+        "c4_ensemble_256": lambda: workloads.c4(storage),
+        "c2_inclined_128": lambda: workloads.c2(storage, 128),
+        "c2_inclined_128_d3q27": lambda: workloads.c2(storage, 128, lattice=27),
+        "c5_squirmers_256_512": lambda: workloads.c5(storage),
+        "c5_squirmers_256_6400": lambda: workloads.c5(storage, n=6400),
+    }
+    if name not in table:
+        raise SystemExit(f"unknown workload {name}; one of {sorted(table)}")
+    return table[name]()
+
+
+# legs reported beside the headline: workload, storage, timed steps, warm-up steps
+LEGS = {
+    "suspension_fp16": ("c5_squirmers_256_512", "fp16", 100, 10),
+    "suspension_fp32": ("c5_squirmers_256_512", "fp32", 100, 10),
+    "suspension_6400_fp16": ("c5_squirmers_256_6400", "fp16", 50, 10),
+    "inclined_128_fp32": ("c2_inclined_128", "fp32", 1000, 50),
+    "inclined_128_fp16": ("c2_inclined_128", "fp16", 1000, 50),
+    "inclined_128_d3q27_fp32": ("c2_inclined_128_d3q27", "fp32", 500, 50),
+}
+
+
+def _omp():
+    """libgomp of this process (the oracle is built with OpenMP), or None."""
+    import ctypes
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
 def cpu_baseline(W, seconds):
-    """The oracle as it stands, on the same workload, for a bounded number of
-    steps on the host cores."""
+    """The oracle as it stands on a bounded sample of workload W, on every
+    host core OpenMP gives it: box after box (each with its particles), a few
+    steps each, until `seconds` of stepping are spent; MLUPS over the steps
+    taken."""
     import oracle
-    b = W.boxes[0]
-    o = oracle.OracleSim(b.shape, W.collision, W.tau, magic=W.magic, walls=b.walls, wall_lo=b.wall_lo,
-                         wall_hi=b.wall_hi, init=b.init, counterforce=W.counterforce)
-    for p in W.particles:
-        pid = o.add_ellipsoid(p.centre, p.axes, p.quat)
-        o.set_external(pid, p.force, p.torque)
-    t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    n = max(1, int(seconds / max(one, 1e-6)))
-    t0 = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(W.sites * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{W.name}: {n} oracle steps of the {b.shape[0]}x{b.shape[1]}x{b.shape[2]} box "
-                      f"({dt:.1f} s)"}
+    omp = _omp()
+    cores = omp.omp_get_max_threads() if omp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    steps_per_box = 10 if len(W.boxes) > 1 else 0
+    done, spent, nb = 0, 0.0, 0
+    for bi, b in enumerate(W.boxes):
+        o = oracle.OracleSim(b.shape, W.collision, W.tau, magic=W.magic, walls=b.walls, wall_lo=b.wall_lo,
+                             wall_hi=b.wall_hi, init=b.init, counterforce=W.counterforce)
+        for p in W.particles:
+            if p.box == bi:
+                pid = o.add_ellipsoid(p.centre, p.axes, p.quat)
+                o.set_external(pid, p.force, p.torque)
+        n3 = b.shape[0] * b.shape[1] * b.shape[2]
+        n = steps_per_box
+        if n == 0:  # a single box: size the run from one timed step
+            t0 = time.perf_counter()
+            o.step(1)
+            n = max(1, int(seconds / max(time.perf_counter() - t0, 1e-6)))
+        t0 = time.perf_counter()
+        o.step(n)
+        spent += time.perf_counter() - t0
+        done += n3 * n
+        nb += 1
+        del o
+        if spent >= seconds:
+            break
+    sample = (f"{W.name}: the first {nb} of its {len(W.boxes)} boxes, {steps_per_box} oracle steps each"
+              if len(W.boxes) > 1 else f"{W.name}: {done // (W.boxes[0].shape[0] ** 3)} oracle steps")
+    return {"value": round(done / spent / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{sample} ({spent:.1f} s of stepping)"}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_reference():
+    """The oracle on the host, one thread and all threads, on 64^3 and 128^3
+    periodic boxes holding a static sphere of radius 4 (BGK tau = 1), with
+    the CPU model: the single-thread and all-core figures beside the GPU's."""
+    import oracle
+    omp = _omp()
+    allc = omp.omp_get_max_threads() if omp else 1
+    out = {"cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(), "threads_all": allc, "kind": "oracle",
+           "workload": "periodic box, static sphere R = 4, BGK tau = 1, FP64, D3Q19"}
+    plan = {1: {64: 20, 128: 5}, allc: {64: 100, 128: 40}}
+    for threads, sizes in plan.items():
+        if omp:
+            omp.omp_set_num_threads(threads)
+        key = "single_thread" if threads == 1 else "all_threads"
+        out[key] = {}
+        for L, n in sizes.items():
+            o = oracle.OracleSim((L, L, L), "bgk", 1.0)
+            o.add_ellipsoid((L / 2 - 0.3, L / 2 - 0.2, L / 2 - 0.1), (4.0, 4.0, 4.0), (1, 0, 0, 0))
+            o.step(1)
+            t0 = time.perf_counter()
+            o.step(n)
+            dt = time.perf_counter() - t0
+            out[key][f"{L}^3"] = {"mlups": round(L ** 3 * n / dt / 1e6, 3), "steps": n}
+            del o
+    if omp:
+        omp.omp_set_num_threads(allc)
+    return out
 
 
 def _pmc_rows(d):
@@ -83,12 +181,11 @@ def _pmc_rows(d):
     return out
 
 
-def summarize_pmc(fetch_dir, write_dir, storage, size, probe_bytes, variant, lattice=19):
+def summarize_pmc(fetch_dir, write_dir, workload, storage, probe_bytes, variant):
     """HBM bytes per collide-stream launch from FETCH_SIZE and WRITE_SIZE (KiB
     per dispatch), each scaled by what the same counter reads for the copy
     probe of known size."""
-    from paper_2403_05443_amd import workloads
-    W = workloads.c2(storage, size, lattice=lattice)
+    W = workload_by_name(workload, storage)
     res = {}
     for name, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _pmc_rows(d)
@@ -157,11 +254,32 @@ def measure(W, steps, warmup, graph_steps, variant=None, psteps=200):
     ms_c, ms_p = lat.profile_step(n)
     k1 = ms_c / n
     alg = 2 * W.lattice * BYTES[W.storage] * W.sites  # Q reads + Q writes per site
+    # population memory a step touches: one buffer in place (variants 11-14), two otherwise
+    ws = W.lattice * BYTES[W.storage] * W.sites * (1 if variant >= 11 else 2)
     return lat, {
         "mlups": W.sites * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps, "wall_s": wall,
         "variant": variant, "k1_ms": k1, "alg_bytes": alg, "achieved_gbs": alg / (k1 / 1e3) / 1e9,
-        "phase_ms": {"collide_stream": ms_c / n, "particle": ms_p / n},
+        "phase_ms": {"collide_stream": ms_c / n, "particle": ms_p / n}, "working_set": ws,
     }
+
+
+def roofline_mlups(W):
+    """Site updates per second (millions) at 8 TB/s with 2 Q s bytes per site."""
+    return HBM_PEAK_GBS * 1e9 / (2 * W.lattice * BYTES[W.storage]) / 1e6
+
+
+def leg_record(W, m, src_sha, steps):
+    """One measured workload beside the headline."""
+    return {"workload": W.name, "boxes": len(W.boxes), "sites": W.sites, "particles": len(W.particles),
+            "lattice": f"D3Q{W.lattice}", "storage": W.storage, "steps": steps,
+            "mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
+            "frac_of_roofline_mlups": round(m["mlups"] / roofline_mlups(W), 4),
+            "k1_variant": m["variant"], "k1_avg_launch_ms": round(m["k1_ms"], 5),
+            "k1_bytes_per_launch": m["alg_bytes"], "k1_achieved_gbs": round(m["achieved_gbs"], 1),
+            "k1_frac": round(m["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "k1_traffic": traffic_record(src_sha, W.name, W.storage, m["variant"]),
+            "working_set_bytes": m["working_set"], "cache_resident": m["working_set"] <= MALL_BYTES,
+            "phase_ms_per_step": {k: round(v, 5) for k, v in m["phase_ms"].items()}}
 
 
 def steps_to_steady(runs, eval_boxes):
@@ -207,27 +325,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", default="fp32", choices=sorted(BYTES))
-    ap.add_argument("--size", type=int, default=128, help="box edge of the inclined-spheroid workload")
-    ap.add_argument("--lattice", type=int, default=19, choices=(19, 27),
-                    help="velocity set of the main line (the metric is quoted on D3Q19)")
+    ap.add_argument("--workload", default="c4_ensemble_256",
+                    help="headline workload (c4_ensemble_256, c5_squirmers_256_512, c5_squirmers_256_6400, "
+                         "c2_inclined_128, c2_inclined_128_d3q27)")
+    ap.add_argument("--storage", default="fp16", choices=sorted(BYTES))
     ap.add_argument("--graph", type=int, default=50, help="steps per HIP graph replay (0: plain launches)")
     ap.add_argument("--variant", type=int, default=None,
-                    help="collide-stream variant to use instead of the tuner's choice (see lb_autotune)")
-    ap.add_argument("--ensemble-steps", type=int, default=200,
-                    help="steps of the 256-box FP16 ensemble reported beside the main line (0: skip)")
+                    help="collide-stream variant of the headline instead of the tuner's choice (see lb_autotune)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs measured beside the headline ('none' for none): " + ", ".join(LEGS))
     ap.add_argument("--sweep-only", action="store_true",
                     help="run the domain-size (32^3-512^3) and resolution studies of the settling spheroid "
                          "instead of the benchmark and print their results as one JSON line")
     ap.add_argument("--studies", default="domain,resolution,sphere_array,jeffery_domain",
                     help="with --sweep-only: comma-separated studies to run (domain, resolution, sphere_array, "
                          "jeffery_domain, drift_superposition)")
-    ap.add_argument("--half-steps", type=int, default=500,
-                    help="steps of the same workload with FP16 storage (0: skip; only with --storage fp32)")
-    ap.add_argument("--d3q27-steps", type=int, default=500,
-                    help="steps of the same spheroid workload on the D3Q27 lattice (0: skip)")
-    ap.add_argument("--suspension-steps", type=int, default=100,
-                    help="steps of the 256^3 FP16 suspension of 512 squirmers reported beside the main line (0: skip)")
     ap.add_argument("--surrogate-runs", type=int, default=4,
                     help="256-box FP16 ensembles run to train the warm-start network (0: skip steps to steady)")
     ap.add_argument("--eval-boxes", type=int, default=64, help="held-out force-driven boxes for steps to steady")
@@ -242,15 +354,14 @@ def main():
     if args.summarize_pmc:
         if args.variant is None:
             raise SystemExit("--summarize-pmc needs the --variant the counter runs used")
-        summarize_pmc(*args.summarize_pmc, storage=args.storage, size=args.size, probe_bytes=args.probe_bytes,
-                      variant=args.variant, lattice=args.lattice)
+        summarize_pmc(*args.summarize_pmc, workload=args.workload, storage=args.storage,
+                      probe_bytes=args.probe_bytes, variant=args.variant)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
-    from paper_2403_05443_amd import workloads
     from paper_2403_05443_amd import lbell
     lbell.load()
     if args.sweep_only:
@@ -269,12 +380,13 @@ def main():
         out["seconds"] = round(time.perf_counter() - t0, 1)
         print(json.dumps(out), flush=True)
         return
-    W = workloads.c2(args.storage, args.size, lattice=args.lattice)
+    W = workload_by_name(args.workload, args.storage)
     copy_gbs = lbell.bandwidth_probe(args.probe_bytes, reps=5)
     lat, m = measure(W, args.steps, args.warmup, args.graph, variant=args.variant)
     del lat
     src_sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     traffic = traffic_record(src_sha, W.name, args.storage, m["variant"])
+    rm = roofline_mlups(W)
     out = {
         "metric": METRIC,
         "value": round(m["mlups"], 1),
@@ -288,63 +400,32 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": W.name, "sites": W.sites, "lattice": f"D3Q{W.lattice}", "storage": args.storage, "collision": "trt",
-                   "tau_plus": W.tau, "lambda": W.magic, "particles": len(W.particles),
-                   "graph_steps": args.graph, "parallelism": "1 GPU"},
+        "config": {"workload": W.name, "boxes": len(W.boxes), "sites": W.sites, "particles": len(W.particles),
+                   "lattice": f"D3Q{W.lattice}", "storage": args.storage, "collision": W.collision,
+                   "tau_plus": W.tau, "lambda": W.magic, "graph_steps": args.graph, "parallelism": "1 GPU"},
+        "roofline_mlups": round(rm, 1),
+        "frac_of_roofline_mlups": round(m["mlups"] / rm, 4),
         "roofline": {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(m["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_collide_stream", "variant": m["variant"], "bytes_per_launch": m["alg_bytes"],
-                     "avg_launch_ms": round(m["k1_ms"], 5), "copy_probe_gbs": round(copy_gbs, 1)},
+                     "avg_launch_ms": round(m["k1_ms"], 5), "copy_probe_gbs": round(copy_gbs, 1),
+                     "working_set_bytes": m["working_set"], "cache_resident": m["working_set"] <= MALL_BYTES},
         "phase_ms_per_step": {k: round(v, 5) for k, v in m["phase_ms"].items()},
         "wall_s": round(m["wall_s"], 3),
+        "legs": {},
     }
-    if args.ensemble_steps > 0:
-        We = workloads.c4("fp16")
-        lat, e = measure(We, args.ensemble_steps, 20, args.graph)
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    for name in legs:
+        wname, storage, steps, warm = LEGS[name]
+        Wl = workload_by_name(wname, storage)
+        lat, e = measure(Wl, steps, warm, args.graph)
         del lat
-        out["ensemble"] = {"workload": We.name, "boxes": len(We.boxes), "sites": We.sites, "storage": "fp16",
-                           "mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 4),
-                           "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 4),
-                           "k1_achieved_gbs": round(e["achieved_gbs"], 1),
-                           "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                           "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
-    if args.half_steps > 0 and args.storage == "fp32":
-        # the same inclined spheroid with FP16 deviation storage (FP32 collide)
-        Wh = workloads.c2("fp16", args.size, lattice=args.lattice)
-        lat, e = measure(Wh, args.half_steps, 50, args.graph)
-        del lat
-        out["fp16"] = {"workload": Wh.name, "sites": Wh.sites, "storage": "fp16",
-                       "mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 5),
-                       "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 5),
-                       "k1_bytes_per_launch": e["alg_bytes"], "k1_achieved_gbs": round(e["achieved_gbs"], 1),
-                       "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                       "k1_traffic": traffic_record(src_sha, Wh.name, "fp16", e["variant"]),
-                       "phase_ms_per_step": {k: round(v, 5) for k, v in e["phase_ms"].items()}}
-    if args.d3q27_steps > 0:
-        Wq = workloads.c2(args.storage, args.size, lattice=27)
-        lat, e = measure(Wq, args.d3q27_steps, 50, args.graph)
-        del lat
-        out["d3q27"] = {"workload": Wq.name, "sites": Wq.sites, "storage": args.storage,
-                        "mlups": round(e["mlups"], 1), "ms_per_step": round(e["ms_per_step"], 5),
-                        "k1_variant": e["variant"], "k1_avg_launch_ms": round(e["k1_ms"], 5),
-                        "k1_bytes_per_launch": e["alg_bytes"], "k1_achieved_gbs": round(e["achieved_gbs"], 1),
-                        "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                        "k1_traffic": traffic_record(src_sha, Wq.name, args.storage, e["variant"]),
-                        "phase_ms_per_step": {k: round(v, 5) for k, v in e["phase_ms"].items()}}
-    if args.suspension_steps > 0:
-        Ws = workloads.c5("fp16")
-        lat, e = measure(Ws, args.suspension_steps, 10, args.graph)
-        del lat
-        out["suspension"] = {"workload": Ws.name, "sites": Ws.sites, "particles": len(Ws.particles),
-                             "storage": "fp16", "mlups": round(e["mlups"], 1),
-                             "ms_per_step": round(e["ms_per_step"], 4), "k1_variant": e["variant"],
-                             "k1_avg_launch_ms": round(e["k1_ms"], 4), "k1_achieved_gbs": round(e["achieved_gbs"], 1),
-                             "k1_frac": round(e["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                             "phase_ms_per_step": {k: round(v, 4) for k, v in e["phase_ms"].items()}}
+        out["legs"][name] = leg_record(Wl, e, src_sha, steps)
     if args.surrogate_runs > 0:
         out["steps_to_steady"] = steps_to_steady(args.surrogate_runs, args.eval_boxes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+        out["cpu_reference"] = cpu_reference()
     print(json.dumps(out), flush=True)
 
 

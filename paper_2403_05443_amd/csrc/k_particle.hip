@@ -29,6 +29,10 @@ template <int Q>
 __device__ __forceinline__ int rw(int b) { return wint<Q>(b); }
 template <int Q>
 constexpr double W6 = (double)(WSCALE<Q> / 6);
+// 1 / W: a link weight is w_b = rw(b) * WINV exactly, since rw(b) is a power
+// of two for every direction a link can take (2, 1; 16, 4, 1)
+template <int Q>
+constexpr double WINV = 1.0 / WSCALE<Q>;
 __device__ __forceinline__ int ropp(int b) { return b == 0 ? 0 : ((b & 1) ? b + 1 : b - 1); }
 
 // q = floor(i / w) and r = i - q w for 0 <= i < 2^31, w >= 1, given
@@ -420,7 +424,7 @@ __device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc&
 
 // Adds every collide-stream block touching the particle's window grown by
 // the set's margin to the near set (block-cooperative).
-__device__ void mark_near(const NearSet& ns, const BoxDesc& B, const int wlo[3], const int wwn[3]) {
+__device__ __forceinline__ void mark_near(const NearSet& ns, const BoxDesc& B, const int wlo[3], const int wwn[3]) {
     const int n3[3] = {B.nx, B.ny, B.nz};
     int lo[3], wn[3];
     for (int k = 0; k < 3; ++k) {
@@ -629,7 +633,7 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
         // w_b rho0 part cancels over a closed link set, but not where this
         // particle's solid touches another solid or a wall (its links there
         // are missing, and the rest pressure on the exposed side remains)
-        const double fb2 = 2.0 * (fb + (rw<Q>(b) / (double)WSCALE<Q>) * rho0);
+        const double fb2 = 2.0 * (fb + (rw<Q>(b) * WINV<Q>) * rho0);
         acc[0] += fb2 * c0;
         acc[1] += fb2 * c1;
         acc[2] += fb2 * c2;
@@ -934,7 +938,7 @@ __device__ __forceinline__ void stamp_cell(const LaunchPart& a, const BoxDesc& B
 // Whether some node of the window changed owner at this step (a cell of the
 // window carries this step's stamp): then links of this particle may have
 // appeared or vanished although none of its own nodes changed.  Block-uniform.
-__device__ bool window_stamped(const LaunchPart& a, const BoxDesc& B, const Win& w, uint32_t ep) {
+__device__ __forceinline__ bool window_stamped(const LaunchPart& a, const BoxDesc& B, const Win& w, uint32_t ep) {
     // per axis up to two runs of coordinates (the window may wrap), as cells
     int c0[3][2], c1[3][2], nr[3], cnt[3];
     const int n3[3] = {B.nx, B.ny, B.nz};
@@ -991,7 +995,7 @@ __device__ bool window_stamped(const LaunchPart& a, const BoxDesc& B, const Win&
 // when some node was released or is a candidate, bit 1 when some node is a
 // candidate; block-uniform.
 template <int ST, int Q>
-__device__ int scan_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w, uint32_t* bits,
+__device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w, uint32_t* bits,
                          uint32_t* cand, RemapShm& sh, uint32_t ep) {
     using S = Store<ST>;
     using T = typename S::T;
@@ -1163,14 +1167,15 @@ __device__ int scan_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& 
 }
 
 // Claims the candidate nodes of pass 1 (cand: bits over the window, in LDS or
-// global memory).  Bit words are dealt to the threads in one fixed way, so
-// the sums below do not depend on where the bits are held.  A node another
-// particle or a wall holds is an overlap.  Mode 0: a covered node's momentum
+// global memory).  Window node i is claimed by thread i mod PBLOCK, as in
+// pass 1 (neighbouring surface nodes, which change side together, go to
+// different threads), so the sums below do not depend on where the bits
+// are held.  A node another particle or a wall holds is an overlap.  Mode 0: a covered node's momentum
 // and its mass in excess of rho0 go to the particle, its angular momentum
 // about x_c(t+1) (reading R9); the populations it holds are read after every
 // bounce-back and release of the step.
 template <int ST, int Q>
-__device__ void claim_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w,
+__device__ __forceinline__ void claim_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w,
                            const uint32_t* cand, RemapShm& sh) {
     using S = Store<ST>;
     using T = typename S::T;
@@ -1183,12 +1188,11 @@ __device__ void claim_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc
     const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
     const double inv = a.kp.inv_scale, rho0 = a.kp.rho0;
     double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int nw = (w.nsites + 31) >> 5;
-    for (int wd = tid; wd < nw; wd += PBLOCK) {
-        uint32_t m = cand[wd];
-        while (m) {
-            const int i = 32 * wd + (__ffs(m) - 1);
-            m &= m - 1;
+    for (int base = 0; base < w.nsites; base += PBLOCK) {
+        const int i = base + tid;
+        // a wave reads two bit words, each shared by 32 lanes
+        if (i >= w.nsites || !((cand[i >> 5] >> (i & 31)) & 1u)) continue;
+        {
             int gx, gy, gz;
             win_node(w, B, i, gx, gy, gz);
             const int s = gx + nx * (gy + ny * gz);
@@ -1236,7 +1240,7 @@ __device__ void claim_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc
 }
 
 // This particle's nodes over the window, as window bits, from the node map.
-__device__ void bits_from_map(const LaunchPart& a, int p, const BoxDesc& B, const Win& w, uint32_t* bits) {
+__device__ __forceinline__ void bits_from_map(const LaunchPart& a, int p, const BoxDesc& B, const Win& w, uint32_t* bits) {
     const uint16_t* om = a.omap + B.ooff;
     const uint16_t me = (uint16_t)(p + 1);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1271,7 +1275,7 @@ __device__ void bits_from_map(const LaunchPart& a, int p, const BoxDesc& B, cons
 // (window index, direction) order, and their moments, from which zeta of
 // eqs. drag1-drag4 is evaluated when the next step starts.
 template <int Q>
-__device__ void link_pass(const LaunchPart& a, int p, const PartDev& P, const BoxDesc& B, const Win& w,
+__device__ __forceinline__ void link_pass(const LaunchPart& a, int p, const PartDev& P, const BoxDesc& B, const Win& w,
                           const uint32_t* bits, uint32_t* stage, RemapShm& sh) {
     double (*red)[PWAVES] = sh.red;
     int* wtot = sh.wtot;
@@ -1508,7 +1512,10 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, PartDev&
         if (a.near.flags) mark_near(a.near, B, w.lo, w.wn);
         return;
     }
-    const int res = scan_pass<ST, Q>(a, p, P, B, w, bits, cand, sh, 0u);
+    // an added particle stamps the cells it claims (with the set-up epoch),
+    // so that only the particles whose window meets its nodes rebuild links
+    const uint32_t ep = (mode == 1 && a.epoch) ? *a.epoch : 0u;
+    const int res = scan_pass<ST, Q>(a, p, P, B, w, bits, cand, sh, ep);
     if (mode == 2) {
         if (threadIdx.x == 0) a.parts[p].nlinks = 0;
         return;
@@ -1604,9 +1611,11 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_claim(LaunchPart a) {
 }
 
 // 3. Links and their moments, from the complete node map, for a particle whose
-//    own nodes changed or in whose window another particle's did.  With
-//    a.force_box >= 0 (after a particle was added to that box at set-up):
-//    every particle of that box, and nothing else.
+//    own nodes changed or in whose window another particle's did (a cell of
+//    the window carries this step's stamp).  With a.force_box >= 0 (after a
+//    particle was added to that box at set-up, a.epoch then pointing at the
+//    add's own epoch): the particles of that box whose window meets the
+//    added particle's nodes.
 template <int Q>
 __global__ __launch_bounds__(PBLOCK) void k_particle_links(LaunchPart a) {
     extern __shared__ uint32_t smem[];
@@ -1618,7 +1627,7 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_links(LaunchPart a) {
     const BoxDesc& B = a.boxes[P.box];
     Win w;
     if (!window_of(a, P, B, w)) return;
-    const bool rebuild = a.force_box >= 0 || P.nchg != 0 || window_stamped(a, B, w, *a.epoch);
+    const bool rebuild = (a.force_box < 0 && P.nchg != 0) || window_stamped(a, B, w, *a.epoch);
     if (rebuild) {
         uint32_t* bits = smem;
         bits_from_map(a, p, B, w, bits);

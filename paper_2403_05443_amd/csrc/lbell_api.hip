@@ -138,8 +138,10 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     L.near_count = take(sizeof(int) * 4);
     // the step counter the collide-stream kernels read (one slot per buffer
     // parity: a launch reads its slot and writes step + 1 to the other), so
-    // that graph replays see the true step
-    L.step_ctr = take(sizeof(uint32_t) * 2);
+    // that graph replays see the true step; slot 2 holds the epoch of the
+    // particle being added (set-up epochs count down from 2^32 - 1, step
+    // epochs up from 1)
+    L.step_ctr = take(sizeof(uint32_t) * 4);
     // warm start: per particle load scale (1), prediction (6) and training
     // sample (8 + 6 floats = 7 doubles); then the start field's scratch
     L.warm = take(sizeof(double) * (14 * (size_t)L.max_particles + stokes_scratch_doubles(nboxes, tiles)));
@@ -178,6 +180,7 @@ struct lb_ctx {
     bool aa = false;
     int aa_buf = 0;
     long long step = 0;
+    uint32_t setup_epoch = 0xFFFFFFFFu;  // owner-change stamps of the next lb_add_ellipsoid
     KParams kp{};
     bool any_walls = false;
     int k1_variant = 0;  // collide-stream variant in use (index into K1_SHAPES)
@@ -542,7 +545,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
         if (e2 == hipSuccess)
             e2 = hipMemsetAsync(ctx->arena + ctx->L.near_flags, 0, ctx->L.near_count + 4 * sizeof(int) - ctx->L.near_flags,
                                 ctx->stream);
-        if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.step_ctr, 0, sizeof(uint32_t) * 2, ctx->stream);
+        if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.step_ctr, 0, sizeof(uint32_t) * 4, ctx->stream);
         if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.stamps, 0, sizeof(uint32_t) * ctx->L.cells, ctx->stream);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
         if (e2 != hipSuccess) {
@@ -594,8 +597,15 @@ lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const d
     P.lcap = (int)cap;
     P.lbase = ctx->link_used;
     const int pid = ctx->np;
+    uint32_t* ep_slot = ctx->at<uint32_t>(ctx->L.step_ctr) + 2;
+    const uint32_t ep = ctx->setup_epoch--;
+    HIPC(hipMemcpyAsync(ep_slot, &ep, sizeof ep, hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(ctx->at<PartDev>(ctx->L.parts) + pid, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(launch_particle_remap(part_launch(ctx, pid, 1, 1), ctx->stream));
+    {
+        LaunchPart a = part_launch(ctx, pid, 1, 1);
+        a.epoch = ep_slot;
+        HIPC(launch_particle_remap(a, ctx->stream));
+    }
     lb_status s = flags_status(ctx);
     if (s != LB_OK) {
         HIPC(launch_particle_remap(part_launch(ctx, pid, 1, 2), ctx->stream));
@@ -613,9 +623,11 @@ lb_status lb_add_ellipsoid(lb_ctx* ctx, int box, const double centre[3], const d
     for (int p = 0; p < pid; ++p) shared = shared || ctx->hpart[p].box == box;
     if (shared) {
         // the new nodes may have been fluid neighbours of another particle of
-        // the box: every particle there rebuilds its links from the node map
+        // the box: the particles there whose window meets a cell the add
+        // stamped rebuild their links from the node map
         LaunchPart a = part_launch(ctx, 0, ctx->np, 0);
         a.force_box = box;
+        a.epoch = ep_slot;
         HIPC(launch_particle_links(a, ctx->stream));
         s = flags_status(ctx);
         if (s != LB_OK) return s;

@@ -231,24 +231,24 @@ def c5(storage="fp16", L=256, n=512, seed_index=0):
     placed one by one and redrawn while the bounding boxes (with a gap of 2
     nodes) of two particles overlap under the minimum image; B1 = 1e-3,
     B2 = beta B1 with beta uniform in [-3, 3].  TRT, Lambda = 3/16, tau+ = 1."""
+    import numpy as np
     g = SplitMix64(SEED0 + 5 + 1000 * seed_index)
     axes = (5.0, 2.5, 2.5)
-    parts, boxes_ = [], []
+    parts = []
+    cs = np.zeros((n, 3))
+    hs = np.zeros((n, 3))
     while len(parts) < n:
         c = tuple(g.uniform(0.0, float(L)) for _ in range(3))
         q = g.unit_quaternion()
         h = _aabb_half(axes, q)
-        ok = True
-        for pc, ph in boxes_:
-            d = [abs(c[k] - pc[k]) for k in range(3)]
-            d = [min(v, L - v) for v in d]
-            if all(d[k] < h[k] + ph[k] + 2.0 for k in range(3)):
-                ok = False
-                break
-        if not ok:
-            continue
+        m = len(parts)
+        if m:
+            d = np.abs(np.asarray(c) - cs[:m])
+            d = np.minimum(d, L - d)
+            if np.any(np.all(d < np.asarray(h) + hs[:m] + 2.0, axis=1)):
+                continue
         beta = g.uniform(-3.0, 3.0)
-        boxes_.append((c, h))
+        cs[m], hs[m] = c, h
         parts.append(Particle(c, axes, q, squirmer=(1e-3, beta * 1e-3)))
     return Workload(f"c5_squirmers_{L}_{n}", [Box((L, L, L))], parts, "trt", 1.0, storage, 10000,
                     velocity_scale=2e-3, max_semi_axis=5.0)
