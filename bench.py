@@ -282,30 +282,28 @@ def leg_record(W, m, src_sha, steps):
             "phase_ms_per_step": {k: round(v, 5) for k, v in m["phase_ms"].items()}}
 
 
-def steps_to_steady(runs, eval_boxes):
+def steps_to_steady(runs, eval_boxes, monitor_tol=0.1, wrong_tol=0.02):
     """The second half of the metric: train the warm-start network on `runs`
     256-box FP16 ensembles (alternately with and without torques; symmetry
-    augmentation, 80/20 split), then count the steps a held-out force-driven
-    FP16 ensemble needs to come within 0.5% of its steady velocity from a
-    plain start, a surrogate warm start and the closed-form control."""
-    from paper_2403_05443_amd import runner, workloads
-    import numpy as np
+    and linearity augmentation, 80/20 split), then count the steps a held-out
+    force-driven FP16 ensemble needs to come within 0.5% of its steady
+    velocity from a plain start, a surrogate warm start watched by the device
+    monitor at monitor_tol, and the closed-form control.  A second surrogate
+    leg starts the same ensemble from the network with its parameters
+    doubled, watched at wrong_tol: its fallback rate and the steps to steady
+    of the boxes that fell back, counted from the warm start (the steps spent
+    before the fallback included)."""
+    from paper_2403_05443_amd import lbell, runner, workloads
     t0 = time.perf_counter()
-    Xs, Ys, steps = [], [], 0
-    for k in range(runs):
-        W = workloads.c4("fp16", 256, seed_index=10 + k, torque=(k % 2 == 0))
-        X, Y, n = runner.ensemble_samples(W, efolds=8)
-        Xs.append(X)
-        Ys.append(Y)
-        steps += n
-    t_data = time.perf_counter() - t0
-    Xa, Ya = runner.augment(np.concatenate(Xs), np.concatenate(Ys))
-    sur, info = runner.train_surrogate(Xa, Ya)
-    t_train = time.perf_counter() - t0 - t_data
+    sur, info = runner.train_warm_network(seeds=runs, boxes=256, epochs=1000, seed0=10)
+    t_train = time.perf_counter() - t0
     We = workloads.c4("fp16", eval_boxes, seed_index=100, torque=False)
-    res = runner.compare_starts(We, sur)
-    t_eval = time.perf_counter() - t0 - t_data - t_train
+    res = runner.compare_starts(We, sur, monitor_tol=monitor_tol)
+    wrong = lbell.Surrogate(max_samples=4096, params=2.0 * sur.params())
+    bad = runner.compare_starts(We, wrong, monitor_tol=wrong_tol)
+    t_eval = time.perf_counter() - t0 - t_train
     m = res["median_steps"]
+    rates = lambda r: {k: round(r[k + "_rate"], 4) for k in ("accepted", "fallback", "steady_miss")}  # noqa: E731
     return {"eval_workload": We.name, "storage": "fp16", "boxes": res["boxes"], "steady_boxes": res["steady_boxes"],
             "tol": res["tol"], "sample_every": res["every"],
             "median_steps_plain": m["plain"], "median_steps_surrogate": m["surrogate"],
@@ -313,11 +311,18 @@ def steps_to_steady(runs, eval_boxes):
             "surrogate_over_plain": round(res["surrogate_over_plain"], 4),
             "control_over_plain": round(res["control_over_plain"], 4),
             "median_prediction_error": round(res["median_prediction_error"], 5),
-            "fallback_rate": round(res["fallback_rate"], 4),
-            "training": {"ensembles": runs, "lb_steps_per_ensemble": steps // max(runs, 1),
+            "monitor": {"tol": monitor_tol, **rates(res), "queued_for_training": len(res["queued"])},
+            "wrong_network": {"params": "trained x 2", "monitor_tol": wrong_tol, **rates(bad),
+                              "median_prediction_error": round(bad["median_prediction_error"], 5),
+                              "median_steps_surrogate": bad["median_steps"]["surrogate"],
+                              "median_steps_fallback_boxes": bad["median_steps_fallback_boxes"],
+                              "median_steps_plain_same_boxes": bad["median_steps_plain_fallback_boxes"],
+                              "median_decision_step_fallback_boxes": bad["median_decision_step_fallback_boxes"],
+                              "queued_for_training": len(bad["queued"])},
+            "training": {"ensembles": runs, "lb_steps_per_ensemble": info["lb_steps_per_ensemble"],
                          "samples": info["samples"], "loss_val": info["loss_val"],
                          "val_target_variance": info["val_target_variance"]},
-            "seconds": {"data": round(t_data, 2), "train": round(t_train, 2), "eval": round(t_eval, 2)}}
+            "seconds": {"train": round(t_train, 2), "eval": round(t_eval, 2)}}
 
 
 def main():
@@ -409,6 +414,7 @@ def main():
                      "unit": "GB/s", "frac": round(m["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_collide_stream", "variant": m["variant"], "bytes_per_launch": m["alg_bytes"],
                      "avg_launch_ms": round(m["k1_ms"], 5), "copy_probe_gbs": round(copy_gbs, 1),
+                     "source_sha256": src_sha,
                      "working_set_bytes": m["working_set"], "cache_resident": m["working_set"] <= MALL_BYTES},
         "phase_ms_per_step": {k: round(v, 5) for k, v in m["phase_ms"].items()},
         "wall_s": round(m["wall_s"], 3),

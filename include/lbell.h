@@ -113,6 +113,8 @@ typedef struct lb_config {
     double max_semi_axis;   /* largest semi-axis any particle may have (default 8)     */
     int    rotation;        /* inertia term of the rotational update (Sec. II.D):
                                LB_ROT_ANALYTIC (default), LB_ROT_FD or LB_ROT_PC        */
+    int    monitor_period;  /* steps between the checks of warm-started boxes (see
+                               lb_warm_start); 0 = the default, 25                      */
 } lb_config;
 
 typedef struct lb_box {
@@ -385,15 +387,47 @@ lb_status lbs_destroy(lbs* s);
 lb_status lbs_grad_noalloc(const float* params, const float* X, const float* Y, int n, float* grads, float* loss,
                            void* hip_stream);
 
-/* Warm start of every particle of the context: the surrogate predicts each
- * particle's steady velocities from its current state and external load;
- * they are set as the particles' velocities (a prediction above the
- * surface-speed limit of lb_set_velocity is scaled down to it), and the fluid
- * of every box is then started as lb_stokes_start does.  pred (may be NULL) receives the predicted
- * lab-frame (U, Omega) of every particle, 6 doubles per particle id.  Needs
- * np <= the surrogate's max_samples; LB_EINVAL for boxes with walls.
+/* Warm start of the particles of box `box` (every box for box = -1): the
+ * surrogate predicts each particle's steady velocities from its current state
+ * and external load; they are set as the particles' velocities (a prediction
+ * above the surface-speed limit of lb_set_velocity is scaled down to it), and
+ * the fluid of the box is then started as lb_stokes_start does.  pred (may be
+ * NULL) receives the predicted lab-frame (U, Omega) of every particle, 6
+ * doubles per particle id (only those of the box are meaningful).
+ *
+ * With tol > 0 the box is then watched on the device, every
+ * cfg.monitor_period steps of lb_step.  W0 = max over the box's particles of
+ * ceil(2 a^2 / nu) (a the largest semi-axis) is the time in which a particle
+ * sheds the error of its start.  The first check at least W0 / 4 steps after
+ * the warm start records the box's flow energy (the sum of |j|^2 over its
+ * fluid nodes, j the momentum density) and its particles' velocities
+ * V = (U, a Omega); the first check at least W0 steps after it compares with
+ * them (the residuals: the relative changes since then) and with the
+ * prediction, and decides the box:
+ *   LB_WARM_ACCEPTED     every particle within tol of its prediction;
+ *   LB_WARM_FALLBACK     a particle misses by more than tol while a residual
+ *                        still exceeds tol: the surrogate's start has failed,
+ *                        and the box falls back to the plain method: its fluid
+ *                        and particles are reset to rest and the run goes on
+ *                        from there (the steps so far are spent);
+ *   LB_WARM_STEADY_MISS  a particle misses but both residuals are below tol:
+ *                        the run is steady away from the prediction; it is
+ *                        kept, and its sample (lb_surrogate_sample) belongs in
+ *                        the training data.
+ * tol <= 0 leaves the box unwatched.  Needs np <= the surrogate's
+ * max_samples; LB_EINVAL for boxes with walls or box out of range.
  * Synchronises. */
-lb_status lb_warm_start(lb_ctx* ctx, lbs* s, double* pred);
+#define LB_WARM_OFF         0
+#define LB_WARM_PENDING     1
+#define LB_WARM_ACCEPTED    2
+#define LB_WARM_FALLBACK    3
+#define LB_WARM_STEADY_MISS 4
+lb_status lb_warm_start(lb_ctx* ctx, int box, lbs* s, double tol, double* pred);
+
+/* State of the warm-start monitor of every box (host arrays of nboxes
+ * entries, either may be NULL): status (LB_WARM_*) and the step at which it
+ * was decided (-1 while pending or unwatched).  Synchronises. */
+lb_status lb_warm_status(lb_ctx* ctx, int* status, long long* decided_step);
 
 /* Starts the fluid of every box from the creeping flow its particles'
  * external loads drive.  Each node gets the sum over the box's particles of

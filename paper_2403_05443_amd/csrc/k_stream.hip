@@ -687,6 +687,51 @@ __global__ __launch_bounds__(TILE) void k_moments(const BoxDesc* __restrict__ bo
     }
 }
 
+// Flow energy per tile for the warm-start monitor: the sum over the tile's
+// fluid sites of |j|^2, j = sum_i (f_i - w_i rho0) c_i the momentum density,
+// for boxes whose monitor is pending (0 elsewhere).
+template <int ST, int Q>
+__global__ __launch_bounds__(TILE) void k_box_energy(const BoxDesc* __restrict__ boxes,
+                                                     const int* __restrict__ tile_box,
+                                                     const uint16_t* __restrict__ omap,
+                                                     const typename Store<ST>::T* __restrict__ fin,
+                                                     const BoxMon* __restrict__ mon, double* __restrict__ partial,
+                                                     KParams kp) {
+    using R = typename Store<ST>::R;
+    const int tile = blockIdx.x;
+    const int bi = tile_box[tile];
+    if (mon[bi].status != MON_PENDING) {  // uniform over the block
+        if (threadIdx.x == 0) partial[tile] = 0.0;
+        return;
+    }
+    const BoxDesc& B = boxes[bi];
+    const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
+    double e = 0.0;
+    if (s < B.n && omap[B.ooff + s] == 0) {
+        const int nx = B.nx, ny = B.ny;
+        const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+        R f[Q];
+        Pull<ST, Q>::pull_cv(kp.conv, B, fin + B.foff, s, x, y, z, (R)kp.inv_scale, (R)kp.rho0, B.walls != 0, f);
+        double j[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            j[0] += cx(i) * (double)f[i];
+            j[1] += cy(i) * (double)f[i];
+            j[2] += cz(i) * (double)f[i];
+        }
+        e = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+    }
+    __shared__ double red[TILE / 64];
+    const double w = wave_sum_d(e);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0;
+        for (int k = 0; k < TILE / 64; ++k) a += red[k];
+        partial[tile] = a;
+    }
+}
+
 template <int ST>
 __global__ void k_poke(const BoxDesc* __restrict__ boxes, int bi, typename Store<ST>::T* __restrict__ f,
                        int s, int dir, double val, KParams kp) {
@@ -921,6 +966,20 @@ hipError_t launch_moments(const BoxDesc* boxes, int bi, int n, const uint16_t* o
         else
             hipLaunchKernelGGL((k_moments<SS, 19>), dim3(nb), dim3(TILE), 0, st, boxes, bi, omap, (const T*)fin,
                                partial, kp);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_box_energy(const BoxDesc* boxes, const int* tile_box, int ntiles, const uint16_t* omap,
+                             const void* fin, const BoxMon* mon, double* partial, const KParams& kp, hipStream_t st) {
+    LB_DISPATCH_ST(kp.storage, {
+        using T = typename Store<SS>::T;
+        if (kp.q == 27)
+            hipLaunchKernelGGL((k_box_energy<SS, 27>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
+                               (const T*)fin, mon, partial, kp);
+        else
+            hipLaunchKernelGGL((k_box_energy<SS, 19>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap,
+                               (const T*)fin, mon, partial, kp);
     });
     return hipGetLastError();
 }

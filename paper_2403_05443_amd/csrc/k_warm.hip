@@ -70,10 +70,11 @@ __global__ void k_warm_features(const BoxDesc* __restrict__ boxes, const PartDev
 }
 
 __global__ void k_warm_apply(PartDev* __restrict__ parts, int np, const float* __restrict__ Y,
-                             const double* __restrict__ s_in, double mu, double* __restrict__ pred) {
+                             const double* __restrict__ s_in, double mu, double* __restrict__ pred, int only_box) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     PartDev& P = parts[p];
+    if (only_box >= 0 && P.box != only_box) return;
     double Rm[3][3];
     body_to_lab(P.q, Rm);
     const double R = eq_radius(P), s = s_in[p];
@@ -356,10 +357,12 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
                                                        const PartDev* __restrict__ parts, int np, double mu,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ ubar,
-                                                       typename Store<ST>::T* __restrict__ f, KParams kp) {
+                                                       typename Store<ST>::T* __restrict__ f, KParams kp,
+                                                       int only_box) {
     using S = Store<ST>;
     const int tile = blockIdx.x;
     const int bi = tile_box[tile];
+    if (only_box >= 0 && bi != only_box) return;
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
     if (s >= B.n) return;
@@ -384,6 +387,151 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fallback monitor of warm-started boxes, one work-group per box, run every
+// monitor period.  W0, the viscous time 2 a^2 / nu of the box's largest
+// particle (a its largest semi-axis), is the time in which a particle sheds
+// the error of its start.  The first check at least Wref = W0 / 4 steps after
+// the warm start takes the reference: the flow energy E = sum |j|^2 over the
+// box's fluid and every particle's V = (U, a Omega).  The first check at
+// least W0 steps after it decides from the residuals (the relative changes
+// since the reference: |E - E_ref| / (2 E), E being quadratic in the velocity,
+// and the largest |V - V_ref| / |V| over the box's particles) and the
+// prediction:
+//   every particle within tol of its prediction   accepted;
+//   a miss while a residual exceeds tol (the run moves away from the
+//     prediction)   fallback: the box restarts from the plain start (fluid and
+//     particles at rest, pending transition book-keeping dropped), its steps
+//     so far spent;
+//   a miss with both residuals below tol (the run has settled elsewhere)
+//     kept, its sample to be added to the training data.
+__global__ __launch_bounds__(256) void k_warm_monitor(const BoxDesc* __restrict__ boxes, BoxMon* __restrict__ mon,
+                                                      const double* __restrict__ partial, PartDev* __restrict__ parts,
+                                                      int np, const double* __restrict__ pred,
+                                                      double* __restrict__ vref, long long step) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    BoxMon& M = mon[b];
+    __shared__ double red[3][4];
+    __shared__ int phase;  // 0 nothing, 1 take the reference, 2 decide
+    __shared__ int decide;
+    if (M.status != MON_PENDING) {
+        if (tid == 0) M.reset = 0;
+        return;
+    }
+    if (tid == 0) {
+        const long long age = step - M.t0;
+        phase = M.t_ref < 0 ? (age >= M.Wref ? 1 : 0) : (age >= M.W0 && step > M.t_ref ? 2 : 0);
+        M.reset = 0;
+    }
+    __syncthreads();
+    if (phase == 0) return;  // uniform over the block
+    const BoxDesc& B = boxes[b];
+    // the box's flow energy, tile partials summed in a fixed order
+    double e = 0.0;
+    for (int t = B.tile0 + tid; t < B.tile0 + B.ntiles; t += blockDim.x) e += partial[t];
+    // the box's particles: the largest relative change since the reference,
+    // and whether any misses its prediction
+    double dv = 0.0, miss = 0.0;
+    for (int p = tid; p < np; p += blockDim.x) {
+        const PartDev& P = parts[p];
+        if (P.box != b) continue;
+        const double a = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
+        const double V[6] = {P.U[0], P.U[1], P.U[2], a * P.W[0], a * P.W[1], a * P.W[2]};
+        double* vr = vref + 6 * (long long)p;
+        const double* pr = pred + 6 * (long long)p;
+        if (phase == 1) {
+            for (int k = 0; k < 6; ++k) vr[k] = V[k];
+            continue;
+        }
+        double d2 = 0, v2 = 0, m2 = 0, p2 = 0;
+        for (int k = 0; k < 6; ++k) {
+            const double pk = k < 3 ? pr[k] : a * pr[k];
+            d2 += (V[k] - vr[k]) * (V[k] - vr[k]);
+            v2 += V[k] * V[k];
+            m2 += (V[k] - pk) * (V[k] - pk);
+            p2 += pk * pk;
+        }
+        dv = fmax(dv, v2 > 0 ? sqrt(d2 / v2) : 0.0);
+        if (m2 > M.tol * M.tol * p2) miss = 1.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o);
+        dv = fmax(dv, __shfl_xor(dv, o));
+        miss = fmax(miss, __shfl_xor(miss, o));
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = e;
+        red[1][tid >> 6] = dv;
+        red[2][tid >> 6] = miss;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double E = 0, DV = 0, MISS = 0;
+        for (int k = 0; k < 4; ++k) {
+            E += red[0][k];
+            DV = fmax(DV, red[1][k]);
+            MISS = fmax(MISS, red[2][k]);
+        }
+        int dec = 0;
+        if (phase == 1) {
+            M.E_ref = E;
+            M.t_ref = step;
+        } else {
+            M.res_flow = E > 0 ? 0.5 * fabs(E - M.E_ref) / E : 0.0;
+            M.res_part = DV;
+            const bool conv = M.res_flow < M.tol && M.res_part < M.tol;
+            dec = MISS == 0.0 ? MON_ACCEPTED : (conv ? MON_STEADY_MISS : MON_FALLBACK);
+            M.status = dec;
+            M.t_decided = step;
+        }
+        M.reset = dec == MON_FALLBACK ? 1 : 0;
+        decide = dec;
+    }
+    __syncthreads();
+    if (decide != MON_FALLBACK) return;
+    for (int p = tid; p < np; p += blockDim.x) {  // the box's particles to rest
+        PartDev& P = parts[p];
+        if (P.box != b) continue;
+        for (int k = 0; k < 3; ++k) {
+            P.U[k] = P.W[k] = 0.0;
+            P.Pp[k] = P.Lp[k] = 0.0;
+        }
+        P.dm = 0.0;
+    }
+}
+
+// Every population slot of a box whose check fell back is set to rest
+// (deviation 0 in every storage format and layout).
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_box_reset(const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
+                                                    const BoxMon* __restrict__ mon, T* __restrict__ f, int q) {
+    const int tile = blockIdx.x;
+    const int bi = tile_box[tile];
+    if (!mon[bi].reset) return;
+    const BoxDesc& B = boxes[bi];
+    const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
+    if (s >= B.n) return;
+    for (int i = 0; i < q; ++i) f[B.foff + (long long)i * B.stride + s] = T(0);
+}
+
+hipError_t launch_warm_monitor(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles, BoxMon* mon,
+                               const double* partial, PartDev* parts, int np, const double* pred, double* vref,
+                               long long step, void* f, int storage, int q, hipStream_t st) {
+    hipLaunchKernelGGL(k_warm_monitor, dim3(nboxes), dim3(256), 0, st, boxes, mon, partial, parts, np, pred, vref,
+                       step);
+    const int es = storage_bytes(storage);
+    if (es == 8)
+        hipLaunchKernelGGL((k_box_reset<unsigned long long>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, mon,
+                           (unsigned long long*)f, q);
+    else if (es == 4)
+        hipLaunchKernelGGL((k_box_reset<uint32_t>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, mon,
+                           (uint32_t*)f, q);
+    else
+        hipLaunchKernelGGL((k_box_reset<uint16_t>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, mon,
+                           (uint16_t*)f, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, float* X, double* s,
                                 hipStream_t st) {
     if (np <= 0) return hipSuccess;
@@ -392,9 +540,9 @@ hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int 
 }
 
 hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const double* s, double mu, double* pred,
-                             hipStream_t st) {
+                             int only_box, hipStream_t st) {
     if (np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_warm_apply, dim3((np + 63) / 64), dim3(64), 0, st, parts, np, Y, s, mu, pred);
+    hipLaunchKernelGGL(k_warm_apply, dim3((np + 63) / 64), dim3(64), 0, st, parts, np, Y, s, mu, pred, only_box);
     return hipGetLastError();
 }
 
@@ -408,7 +556,7 @@ size_t stokes_scratch_doubles(int nboxes, int ntiles) { return (size_t)nboxes * 
 
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
                                const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
-                               void* f, const KParams& kp, hipStream_t st) {
+                               void* f, const KParams& kp, int only_box, hipStream_t st) {
     double* S = scratch;
     double* C = S + (size_t)nboxes * WM * 6;
     double* partial = C + (size_t)nboxes * WM * 6;
@@ -426,19 +574,19 @@ hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile
         switch (kp.storage) {
             case ST_F64:
                 hipLaunchKernelGGL((k_stokes_write<ST_F64, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (double*)f, kp);
+                                   omap, parts, np, mu, C, ubar, (double*)f, kp, only_box);
                 break;
             case ST_F32:
                 hipLaunchKernelGGL((k_stokes_write<ST_F32, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (float*)f, kp);
+                                   omap, parts, np, mu, C, ubar, (float*)f, kp, only_box);
                 break;
             case ST_F16:
                 hipLaunchKernelGGL((k_stokes_write<ST_F16, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (typename Store<ST_F16>::T*)f, kp);
+                                   omap, parts, np, mu, C, ubar, (typename Store<ST_F16>::T*)f, kp, only_box);
                 break;
             default:
                 hipLaunchKernelGGL((k_stokes_write<ST_BF16, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (typename Store<ST_BF16>::T*)f, kp);
+                                   omap, parts, np, mu, C, ubar, (typename Store<ST_BF16>::T*)f, kp, only_box);
         }
     };
     if (kp.q == 27) write(std::integral_constant<int, 27>{});

@@ -31,7 +31,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
            flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, warm = 0, step_ctr = 0,
-           stamps = 0, cand = 0, total = 0;
+           stamps = 0, cand = 0, mon = 0, total = 0;
     long long cells = 0;  // owner-change stamp cells over all boxes
     int near_blocks = 0;  // collide-stream blocks that a near set can name (per slot)
     std::vector<long long> foff, stride, ooff, coff;
@@ -71,6 +71,7 @@ bool valid_cfg(const lb_config* c, int nboxes, const lb_box* boxes, std::string*
     // the node map holds id + 1 in 16 bits, 0xFFFF marking walls
     if (c->max_particles < 0 || c->max_particles > 65534) return bad("max_particles must be in 0..65534");
     if (c->rotation < 0 || c->rotation > 2) return bad("rotation must be LB_ROT_ANALYTIC, LB_ROT_FD or LB_ROT_PC");
+    if (c->monitor_period < 0) return bad("monitor_period must be >= 0");
     if (lds_words_for(c->max_semi_axis) > MAX_LDS_WORDS) return bad("max_semi_axis too large for the remap window");
     for (int b = 0; b < nboxes; ++b) {
         const lb_box& B = boxes[b];
@@ -149,6 +150,9 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     // nodes, and each particle's remap claim candidates (one window bitmask)
     L.stamps = take(sizeof(uint32_t) * (size_t)L.cells);
     L.cand = take(sizeof(uint32_t) * (size_t)L.max_particles * L.lds_words);
+    // warm-start monitor: a record per box, each particle's velocity at the
+    // last check (6 doubles), a flow-energy partial per tile
+    L.mon = take(sizeof(BoxMon) * nboxes + sizeof(double) * (6 * (size_t)L.max_particles + tiles));
     L.total = p;
     return L;
 }
@@ -202,6 +206,10 @@ struct lb_ctx {
         hipGraphExec_t exec = nullptr;
         int np = -1, variant = -1, steps = 0;
     } graph[2];
+    // warm-start monitor: checks every monitor_period steps from mon_next
+    // while mon_active, until mon_until (every watched box decided by then)
+    bool mon_active = false;
+    long long mon_next = 0, mon_until = 0;
     std::string err;
 
     template <typename T>
@@ -395,6 +403,7 @@ lb_status lb_config_default(lb_config* cfg) {
     cfg->max_particles = 0;
     cfg->max_semi_axis = 8.0;
     cfg->rotation = LB_ROT_ANALYTIC;
+    cfg->monitor_period = 25;
     return LB_OK;
 }
 
@@ -547,6 +556,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
                                 ctx->stream);
         if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.step_ctr, 0, sizeof(uint32_t) * 4, ctx->stream);
         if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.stamps, 0, sizeof(uint32_t) * ctx->L.cells, ctx->stream);
+        if (e2 == hipSuccess) e2 = hipMemsetAsync(ctx->arena + ctx->L.mon, 0, sizeof(BoxMon) * nboxes, ctx->stream);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
         if (e2 != hipSuccess) {
             std::fprintf(stderr, "lb_init: %s\n", hipGetErrorString(e2));
@@ -909,6 +919,29 @@ lb_status lb_set_graph(lb_ctx* ctx, int steps) {
     return LB_OK;
 }
 
+namespace {
+int monitor_period(const lb_ctx* ctx) { return ctx->cfg.monitor_period > 0 ? ctx->cfg.monitor_period : 25; }
+
+// The warm-start check of every watched box, when one is due (after the
+// step or group of steps just enqueued); enqueued on the stream like a step.
+lb_status monitor_if_due(lb_ctx* ctx) {
+    if (!ctx->mon_active || ctx->step < ctx->mon_next) return LB_OK;
+    const int nb = (int)ctx->boxes.size();
+    BoxMon* mon = ctx->at<BoxMon>(ctx->L.mon);
+    double* vref = reinterpret_cast<double*>(mon + nb);
+    double* partial = vref + 6 * (size_t)ctx->L.max_particles;
+    const double* pred = ctx->at<double>(ctx->L.warm) + ctx->L.max_particles;
+    HIPC(launch_box_energy(ctx->at<BoxDesc>(ctx->L.boxes), ctx->at<int>(ctx->L.tile_box), ctx->L.total_tiles,
+                           ctx->at<uint16_t>(ctx->L.omap), ctx->fbuf(ctx->cur), mon, partial, ctx->kp, ctx->stream));
+    HIPC(launch_warm_monitor(ctx->at<BoxDesc>(ctx->L.boxes), nb, ctx->at<int>(ctx->L.tile_box), ctx->L.total_tiles,
+                             mon, partial, ctx->at<PartDev>(ctx->L.parts), ctx->np, pred, vref, ctx->step,
+                             ctx->fbuf(ctx->cur), ctx->cfg.storage, ctx->cfg.lattice, ctx->stream));
+    ctx->mon_next = ctx->step + monitor_period(ctx);
+    if (ctx->step > ctx->mon_until) ctx->mon_active = false;
+    return LB_OK;
+}
+}  // namespace
+
 lb_status lb_step(lb_ctx* ctx, int n) {
     if (!ctx || n < 0) return LB_EINVAL;
     if (n == 0) return LB_OK;
@@ -922,6 +955,7 @@ lb_status lb_step(lb_ctx* ctx, int n) {
     if (!ov && ctx->graph_steps > 0) {
         for (; k + ctx->graph_steps <= n; k += ctx->graph_steps) {
             lb_status s = step_graph(ctx);
+            if (s == LB_OK) s = monitor_if_due(ctx);
             if (s != LB_OK) return s;
         }
     }
@@ -930,6 +964,7 @@ lb_status lb_step(lb_ctx* ctx, int n) {
         if (s == LB_OK && !ov) s = launch_particles(ctx, ctx->stream);
         if (s != LB_OK) return s;
         ctx->step++;
+        if (!ov && (s = monitor_if_due(ctx)) != LB_OK) return s;
     }
     if (ov) HIPC(hipStreamWaitEvent(ctx->stream, ctx->evP, 0));  // join
     return LB_OK;
@@ -1283,8 +1318,11 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
     ctx->opb_np = -1;  // which boxes hold several particles is recomputed
     ctx->step = h.step;
     ctx->link_used = h.link_used;
-    // stamps of the steps after the checkpoint must not match an epoch again
+    // stamps of the steps after the checkpoint must not match an epoch again;
+    // the warm-start monitor is not part of a checkpoint
     HIPC(hipMemsetAsync(ctx->arena + ctx->L.stamps, 0, sizeof(uint32_t) * ctx->L.cells, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->arena + ctx->L.mon, 0, sizeof(BoxMon) * ctx->boxes.size(), ctx->stream));
+    ctx->mon_active = false;
     {
         const uint32_t st32 = (uint32_t)h.step;  // the device step counter of the restored parity
         HIPC(hipMemcpyAsync(ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur, &st32, sizeof st32, hipMemcpyHostToDevice,
@@ -1332,13 +1370,14 @@ lb_status lb_get_particles(lb_ctx* ctx, int first, int count, double* x, double*
 namespace {
 double viscosity(const lb_ctx* ctx) { return (1.0 / ctx->kp.omega - 0.5) / 3.0; }
 
-lb_status stokes_start(lb_ctx* ctx) {
-    for (const auto& b : ctx->boxes)
-        if (b.walls) return fail(ctx, LB_EINVAL, "the start field is defined for periodic boxes only");
+lb_status stokes_start(lb_ctx* ctx, int only_box = -1) {
+    for (size_t b = 0; b < ctx->boxes.size(); ++b)
+        if ((only_box < 0 || (int)b == only_box) && ctx->boxes[b].walls)
+            return fail(ctx, LB_EINVAL, "the start field is defined for periodic boxes only");
     double* scratch = ctx->at<double>(ctx->L.warm) + 14 * (size_t)ctx->L.max_particles;
     HIPC(launch_stokes_start(ctx->at<BoxDesc>(ctx->L.boxes), (int)ctx->boxes.size(), ctx->at<int>(ctx->L.tile_box),
                              ctx->L.total_tiles, ctx->at<uint16_t>(ctx->L.omap), ctx->at<PartDev>(ctx->L.parts),
-                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, ctx->fbuf(ctx->cur), ctx->kp,
+                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, ctx->fbuf(ctx->cur), ctx->kp, only_box,
                              ctx->stream));
     return LB_OK;
 }
@@ -1352,12 +1391,15 @@ lb_status lb_stokes_start(lb_ctx* ctx) {
     return flags_status(ctx);
 }
 
-lb_status lb_warm_start(lb_ctx* ctx, lbs* sur, double* pred) {
+lb_status lb_warm_start(lb_ctx* ctx, int box, lbs* sur, double tol, double* pred) {
     if (!ctx || !sur) return LB_EINVAL;
+    const int nb = (int)ctx->boxes.size();
+    if (box < -1 || box >= nb) return fail(ctx, LB_EINVAL, "no such box");
     if (ctx->np == 0) return LB_OK;
     if (ctx->np > sur->max_n) return fail(ctx, LB_EINVAL, "more particles than the surrogate's sample capacity");
-    for (const auto& b : ctx->boxes)
-        if (b.walls) return fail(ctx, LB_EINVAL, "the warm start is defined for periodic boxes only");
+    for (int b = 0; b < nb; ++b)
+        if ((box < 0 || b == box) && ctx->boxes[b].walls)
+            return fail(ctx, LB_EINVAL, "the warm start is defined for periodic boxes only");
     // the surrogate's work goes on the context's stream, after the steps already queued there
     double* sc = ctx->at<double>(ctx->L.warm);
     double* pr = sc + ctx->L.max_particles;
@@ -1365,14 +1407,62 @@ lb_status lb_warm_start(lb_ctx* ctx, lbs* sur, double* pred) {
     HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, sur->X, sc, ctx->stream));
     MlpArgs a{sur->P, sur->X, nullptr, sur->out, nullptr, nullptr, ctx->np, 0.f, 0};
     HIPC(launch_mlp(a, ctx->stream));
-    const double mu = ctx->kp.rho0 * viscosity(ctx);
-    HIPC(launch_warm_apply(parts, ctx->np, sur->out, sc, mu, pr, ctx->stream));
-    lb_status s = stokes_start(ctx);
+    const double nu = viscosity(ctx), mu = ctx->kp.rho0 * nu;
+    HIPC(launch_warm_apply(parts, ctx->np, sur->out, sc, mu, pr, box, ctx->stream));
+    lb_status s = stokes_start(ctx, box);
     if (s != LB_OK) return s;
+    // the monitor of the warm-started boxes
+    BoxMon* mon = ctx->at<BoxMon>(ctx->L.mon);
+    std::vector<BoxMon> hm((size_t)nb);
+    HIPC(hipMemcpyAsync(hm.data(), mon, sizeof(BoxMon) * nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    long long maxW0 = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (box >= 0 && b != box) continue;
+        BoxMon& M = hm[b];
+        std::memset(&M, 0, sizeof M);
+        // W0: the viscous time of the box's largest particle, 2 a^2 / nu
+        int W0 = -1;
+        for (int p = 0; p < ctx->np; ++p)
+            if (ctx->hpart[p].box == b) {
+                const double* ax = ctx->hpart[p].axes;
+                const double am = std::max(ax[0], std::max(ax[1], ax[2]));
+                W0 = std::max(W0, (int)std::ceil(2.0 * am * am / nu));
+            }
+        M.status = (tol > 0 && W0 >= 0) ? MON_PENDING : MON_OFF;
+        M.W0 = std::max(W0, 1);
+        M.Wref = M.W0 / 4;
+        M.tol = tol;
+        M.t0 = ctx->step;
+        M.t_ref = -1;
+        M.t_decided = -1;
+        if (M.status == MON_PENDING) maxW0 = std::max(maxW0, (long long)M.W0);
+    }
+    HIPC(hipMemcpyAsync(mon, hm.data(), sizeof(BoxMon) * nb, hipMemcpyHostToDevice, ctx->stream));
+    if (maxW0 > 0 || tol > 0) {
+        const long long until = ctx->step + maxW0 + 2 * monitor_period(ctx);
+        ctx->mon_until = ctx->mon_active ? std::max(ctx->mon_until, until) : until;
+        if (!ctx->mon_active) ctx->mon_next = ctx->step + monitor_period(ctx);
+        ctx->mon_active = tol > 0 || ctx->mon_active;
+    }
     if (pred)
         HIPC(hipMemcpyAsync(pred, pr, sizeof(double) * 6 * ctx->np, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
     return flags_status(ctx);
+}
+
+lb_status lb_warm_status(lb_ctx* ctx, int* status, long long* decided_step) {
+    if (!ctx) return LB_EINVAL;
+    const int nb = (int)ctx->boxes.size();
+    std::vector<BoxMon> hm((size_t)nb);
+    HIPC(hipMemcpyAsync(hm.data(), ctx->at<BoxMon>(ctx->L.mon), sizeof(BoxMon) * nb, hipMemcpyDeviceToHost,
+                        ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    for (int b = 0; b < nb; ++b) {
+        if (status) status[b] = hm[b].status;
+        if (decided_step) decided_step[b] = hm[b].t_decided;
+    }
+    return LB_OK;
 }
 
 lb_status lb_surrogate_sample(lb_ctx* ctx, float* X, float* Y) {

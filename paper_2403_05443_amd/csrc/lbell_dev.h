@@ -144,6 +144,28 @@ struct PartDev {
     long long lbase;      // offset of this particle's links in the pool
 };
 
+// Fallback monitor of a warm-started box (one record per box).
+enum MonStatus : int {
+    MON_OFF = 0,          // no warm start to watch
+    MON_PENDING = 1,      // warm-started, not decided yet
+    MON_ACCEPTED = 2,     // within tol of the prediction at the decision
+    MON_FALLBACK = 3,     // missed while the run was still evolving: reset to the plain start
+    MON_STEADY_MISS = 4,  // missed, but the run was already steady: kept, its sample queued for training
+};
+struct BoxMon {
+    double E_ref;          // flow energy sum |j|^2 at the reference check
+    double tol;            // relative tolerance of the prediction and of the residuals
+    double res_flow;       // residuals of the decision: relative changes since the reference
+    double res_part;
+    long long t0;          // step of the warm start
+    long long t_ref;       // step of the reference check (-1: not yet)
+    long long t_decided;   // step of the decision (-1 before it)
+    int W0;                // steps from the warm start before the decision
+    int Wref;              // steps from the warm start before the reference check
+    int status;            // MonStatus
+    int reset;             // set by the last check when it fell back
+};
+
 struct KParams {
     double omega, omega_m;    // 1/tau (TRT: 1/tau+), TRT 1/tau-
     double scale, inv_scale;  // half formats: stored = scale * deviation

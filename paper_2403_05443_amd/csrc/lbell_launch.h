@@ -128,11 +128,20 @@ hipError_t launch_mlp_reduce(const MlpReduceArgs& a, hipStream_t st);
 hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, float* X, double* s,
                                 hipStream_t st);
 hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const double* s, double mu, double* pred,
-                             hipStream_t st);
+                             int only_box, hipStream_t st);
 hipError_t launch_warm_targets(const PartDev* parts, int np, const double* s, double mu, float* Y, hipStream_t st);
 size_t stokes_scratch_doubles(int nboxes, int ntiles);  // scratch of launch_stokes_start
+// only_box >= 0: write that box only (every box otherwise)
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
                                const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
-                               void* f, const KParams& kp, hipStream_t st);
+                               void* f, const KParams& kp, int only_box, hipStream_t st);
+// ---- fallback monitor of warm-started boxes ----
+// per tile: sum over fluid sites of |j|^2 for boxes whose monitor is pending (k_stream.hip)
+hipError_t launch_box_energy(const BoxDesc* boxes, const int* tile_box, int ntiles, const uint16_t* omap,
+                             const void* fin, const BoxMon* mon, double* partial, const KParams& kp, hipStream_t st);
+// one work-group per box: residuals, decision, particle reset; then the populations of boxes that fell back
+hipError_t launch_warm_monitor(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles, BoxMon* mon,
+                               const double* partial, PartDev* parts, int np, const double* pred, double* vref,
+                               long long step, void* f, int storage, int q, hipStream_t st);
 
 }  // namespace lbd

@@ -34,7 +34,8 @@ class Config(C.Structure):
     _fields_ = [("lattice", C.c_int), ("collision", C.c_int), ("tau", C.c_double),
                 ("magic", C.c_double), ("storage", C.c_int), ("scale_log2", C.c_int),
                 ("velocity_scale", C.c_double), ("rho0", C.c_double), ("counterforce", C.c_int),
-                ("max_particles", C.c_int), ("max_semi_axis", C.c_double), ("rotation", C.c_int)]
+                ("max_particles", C.c_int), ("max_semi_axis", C.c_double), ("rotation", C.c_int),
+                ("monitor_period", C.c_int)]
 
 
 class Box(C.Structure):
@@ -78,7 +79,8 @@ SIGNATURES = {
     "lb_debug_poke": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_double]),
     "lb_get_particles": (C.c_int, [_VP, C.c_int, C.c_int, _D, _D, _D, _D]),
     "lb_stokes_start": (C.c_int, [_VP]),
-    "lb_warm_start": (C.c_int, [_VP, _VP, _D]),
+    "lb_warm_start": (C.c_int, [_VP, C.c_int, _VP, C.c_double, _D]),
+    "lb_warm_status": (C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
     "lb_surrogate_sample": (C.c_int, [_VP, _F, _F]),
     "lbs_arena_bytes": (C.c_size_t, [C.c_int]),
     "lbs_create": (C.c_int, [C.c_int, _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
@@ -160,7 +162,7 @@ class Lattice:
 
     def __init__(self, boxes, collision="bgk", tau=1.0, magic=3.0 / 16.0, storage="fp32",
                  scale_log2=0, velocity_scale=1e-3, counterforce=False, max_particles=0,
-                 max_semi_axis=8.0, lattice=19, rotation="analytic", device="cuda:0"):
+                 max_semi_axis=8.0, lattice=19, rotation="analytic", monitor_period=25, device="cuda:0"):
         import torch
         self.lib = load()
         self.torch = torch
@@ -177,6 +179,7 @@ class Lattice:
         cfg.max_semi_axis = float(max_semi_axis)
         cfg.lattice = int(lattice)
         cfg.rotation = ROTATION[rotation] if isinstance(rotation, str) else int(rotation)
+        cfg.monitor_period = int(monitor_period)
         self.cfg = cfg
         bl = [b if isinstance(b, Box) else make_box(*b) for b in boxes]
         self.nboxes = len(bl)
@@ -345,12 +348,24 @@ class Lattice:
         """Start the fluid from the creeping flow of the particles' current velocities."""
         self._chk(self.lib.lb_stokes_start(self.ctx))
 
-    def warm_start(self, surrogate):
-        """Surrogate warm start of every particle; returns the predicted lab-frame
-        (U, Omega) per particle, shape (np, 6)."""
+    def warm_start(self, surrogate, box=-1, tol=0.0):
+        """Surrogate warm start of the particles of `box` (-1: every box);
+        with tol > 0 the boxes are watched on the device and fall back to
+        the plain start when the prediction fails (lb_warm_start).  Returns
+        the predicted lab-frame (U, Omega) per particle, shape (np, 6)."""
         pred = np.zeros((max(self.np, 1), 6))
-        self._chk(self.lib.lb_warm_start(self.ctx, surrogate.handle, _p(pred)))
+        self._chk(self.lib.lb_warm_start(self.ctx, int(box), surrogate.handle, float(tol), _p(pred)))
         return pred[:self.np]
+
+    WARM_STATUS = {0: "off", 1: "pending", 2: "accepted", 3: "fallback", 4: "steady_miss"}
+
+    def warm_status(self):
+        """(status per box as LB_WARM_* codes, decision step per box)."""
+        st = np.zeros(self.nboxes, dtype=np.int32)
+        at = np.zeros(self.nboxes, dtype=np.int64)
+        self._chk(self.lib.lb_warm_status(self.ctx, st.ctypes.data_as(C.POINTER(C.c_int)),
+                                          at.ctypes.data_as(C.POINTER(C.c_longlong))))
+        return st, at
 
 
 def _fp(a):

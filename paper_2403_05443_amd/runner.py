@@ -62,12 +62,14 @@ def ensemble_samples(W, efolds=8.0, graph=50):
     return X.astype(np.float64), Y.astype(np.float64), steps
 
 
-def augment(X, Y, nrot=8, flip=True):
+def augment(X, Y, nrot=8, flip=True, negate=True):
     """Copies of the samples under the symmetries of a spheroid with b = c:
     rotations about its axis (body x) by 2 pi k / nrot and, with flip, the
     half-turn about body z that swaps its ends.  Loads and responses rotate
     together (forces, torques and both velocities transform alike under
-    proper rotations); the shape inputs are unchanged."""
+    proper rotations); the shape inputs are unchanged.  With negate, each
+    copy also with loads and responses reversed: Stokes flow is linear in
+    the load, and the normalised inputs and outputs are odd in it."""
     out_x, out_y = [], []
     mats = []
     for k in range(nrot):
@@ -77,11 +79,12 @@ def augment(X, Y, nrot=8, flip=True):
         if flip:
             mats.append(np.diag([-1.0, -1.0, 1.0]) @ Q)
     for Q in mats:
-        x, y = X.copy(), Y.copy()
-        x[:, 2:5], x[:, 5:8] = X[:, 2:5] @ Q.T, X[:, 5:8] @ Q.T
-        y[:, 0:3], y[:, 3:6] = Y[:, 0:3] @ Q.T, Y[:, 3:6] @ Q.T
-        out_x.append(x)
-        out_y.append(y)
+        for sg in ((1.0, -1.0) if negate else (1.0,)):
+            x, y = X.copy(), Y.copy()
+            x[:, 2:5], x[:, 5:8] = sg * (X[:, 2:5] @ Q.T), sg * (X[:, 5:8] @ Q.T)
+            y[:, 0:3], y[:, 3:6] = sg * (Y[:, 0:3] @ Q.T), sg * (Y[:, 3:6] @ Q.T)
+            out_x.append(x)
+            out_y.append(y)
     return np.concatenate(out_x), np.concatenate(out_y)
 
 
@@ -358,14 +361,19 @@ def sphere_array_run(L, R=4.0, force=2e-3, steps=None):
 
 # ------------------------------------------------------- steps to steady --
 
-def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25):
+def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25, tol=0.0):
     """Velocities U of every particle every `every` steps from one of three
-    starts: 'plain' (rest), 'surrogate' (lb_warm_start), 'control' (closed
-    forms + Stokes start field).  Returns (times, U (nt, np, 3), pred)."""
+    starts: 'plain' (rest), 'surrogate' (lb_warm_start; with tol > 0 its
+    boxes are watched on the device and fall back to the plain start when the
+    prediction fails), 'control' (closed forms + Stokes start field).  Returns
+    (times, U (nt, np, 3), pred, info) with info holding, for the surrogate
+    start, the device's decision per box and the samples (X, Y) of every
+    particle at the end of the run."""
     lat = build_lattice(W)
     pred = None
+    info = {}
     if start == "surrogate":
-        pred = lat.warm_start(surrogate)
+        pred = lat.warm_start(surrogate, tol=tol)
     elif start == "control":
         nu = viscosity(W)
         pred = np.zeros((len(W.particles), 6))
@@ -382,8 +390,11 @@ def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25)
         t += every
         times.append(t)
         Us.append(lat.particles()["U"].copy())
+    if start == "surrogate":
+        info["status"], info["decided"] = lat.warm_status()
+        info["samples"] = lat.surrogate_sample()
     del lat
-    return np.array(times), np.array(Us), pred
+    return np.array(times), np.array(Us), pred, info
 
 
 def steps_to_tolerance(times, U, Uinf, tol=0.005):
@@ -400,40 +411,98 @@ def steps_to_tolerance(times, U, Uinf, tol=0.005):
     return out
 
 
-def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005):
+def train_warm_network(seeds=4, boxes=128, epochs=600, seed0=20, storage="fp16"):
+    """The warm-start network trained on the library's own ensemble runs:
+    `seeds` force-driven ensembles of `boxes` boxes with config 4's
+    distributions (seeds seed0, seed0 + 1, ...; every other one with
+    torques), their steady samples augmented by the spheroid's symmetries and
+    the linearity of Stokes flow.  Returns (surrogate, info)."""
+    Xs, Ys, steps = [], [], 0
+    for k in range(seeds):
+        W = workloads.c4(storage, boxes, seed_index=seed0 + k, torque=(k % 2 == 0))
+        X, Y, n = ensemble_samples(W, efolds=8)
+        Xs.append(X)
+        Ys.append(Y)
+        steps += n
+    Xa, Ya = augment(np.concatenate(Xs), np.concatenate(Ys))
+    sur, info = train_surrogate(Xa, Ya, epochs=epochs)
+    info["lb_steps_per_ensemble"] = steps // max(seeds, 1)
+    return sur, info
+
+
+def watch_warm_start(W, surrogate, tol, every=25):
+    """Warm-start every box of W with the surrogate, watched at tol, and step
+    until every box is decided.  Returns (lattice, status per box, decision
+    step per box, predictions, the particles' velocities just after each
+    box's decision)."""
+    lat = build_lattice(W)
+    pred = lat.warm_start(surrogate, tol=tol)
+    lat.set_graph(every)
+    nb = len(W.boxes)
+    U_dec = np.full((len(W.particles), 6), np.nan)
+    decided = np.zeros(nb, dtype=bool)
+    t = 0
+    while not decided.all():
+        lat.step(every)
+        t += every
+        st, at = lat.warm_status()
+        new = (st >= 2) & ~decided
+        if new.any():
+            P = lat.particles()
+            for i, p in enumerate(W.particles):
+                if new[p.box]:
+                    U_dec[i] = np.concatenate([P["U"][i], P["W"][i]])
+            decided |= new
+        assert t < 10 ** 6, "the monitor decided no box"
+    st, at = lat.warm_status()
+    return lat, st, at, pred, U_dec
+
+
+def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0.1):
     """Steps to a tol-accurate steady velocity for each particle of the
     force-driven ensemble W from the three starts.  The steady velocity is
     the end of the plain run; a box counts only if that run changed by less
-    than 0.05% over its last slow time.  Fallback: a warm-started box whose
-    velocity after W0 = ceil(2 a^2 / nu) steps is more than tol away from the
-    prediction is marked to be run plainly (its sample goes back to
-    training)."""
+    than 0.05% over its last slow time.  The surrogate run is watched on the
+    device (lb_warm_start with monitor_tol): at W0 = ceil(2 a^2 / nu) steps a
+    box whose velocity missed the prediction while the run still moved falls
+    back to the plain start, and its steps count from the warm start; boxes
+    that missed, fell back or not, have their samples (at the end of the run)
+    queued for training."""
     nu = viscosity(W)
     steps = int(math.ceil(efolds * max(slow_time(box_edge(W, i), nu) for i in range(len(W.particles)))))
     steps = (steps + every - 1) // every * every
-    tp, Up, _ = trajectory(W, "plain", steps=steps, every=every)
-    ts, Us, pred = trajectory(W, "surrogate", surrogate, steps=steps, every=every)
-    tc, Uc, _ = trajectory(W, "control", steps=steps, every=every)
+    tp, Up, _, _ = trajectory(W, "plain", steps=steps, every=every)
+    ts, Us, pred, info = trajectory(W, "surrogate", surrogate, steps=steps, every=every, tol=monitor_tol)
+    tc, Uc, _, _ = trajectory(W, "control", steps=steps, every=every)
     Uinf = Up[-1]
     ok = np.ones(len(W.particles), dtype=bool)
-    fallback = np.zeros(len(W.particles), dtype=bool)
     for i, p in enumerate(W.particles):
         lag = int(round(slow_time(box_edge(W, i), nu) / every))
         ok[i] = np.linalg.norm(Up[-1, i] - Up[-1 - lag, i]) < 5e-4 * np.linalg.norm(Uinf[i])
-        w0 = int(math.ceil(2 * p.axes[0] ** 2 / nu))
-        k = min(len(ts) - 1, max(0, int(math.ceil(w0 / every)) - 1))
-        fallback[i] = np.linalg.norm(Us[k, i] - pred[i, :3]) > tol * np.linalg.norm(pred[i, :3])
+    status = np.array([info["status"][p.box] for p in W.particles])
     n = {"plain": steps_to_tolerance(tp, Up, Uinf, tol), "surrogate": steps_to_tolerance(ts, Us, Uinf, tol),
          "control": steps_to_tolerance(tc, Uc, Uinf, tol)}
     err0 = {"surrogate": np.linalg.norm(Us[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1),
             "control": np.linalg.norm(Uc[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)}
     pred_err = np.linalg.norm(pred[:, :3] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)
     med = {k: float(np.median(v[ok])) if ok.any() else float("nan") for k, v in n.items()}
+    rate = lambda code: float((status[ok] == code).mean()) if ok.any() else float("nan")  # noqa: E731
+    queued = np.nonzero(ok & ((status == 3) | (status == 4)))[0]
+    X, Y = info["samples"]
     return {"boxes": int(len(W.particles)), "steady_boxes": int(ok.sum()), "steps": steps, "every": every,
-            "tol": tol, "median_steps": med,
+            "tol": tol, "monitor_tol": monitor_tol, "median_steps": med,
             "surrogate_over_plain": med["surrogate"] / med["plain"],
             "control_over_plain": med["control"] / med["plain"],
             "median_prediction_error": float(np.median(pred_err[ok])) if ok.any() else float("nan"),
             "median_error_after_first_sample": {k: float(np.median(v[ok])) if ok.any() else float("nan")
                                                 for k, v in err0.items()},
-            "fallback_rate": float(fallback[ok].mean()) if ok.any() else float("nan"), "per_box": n, "steady": ok}
+            "accepted_rate": rate(2), "fallback_rate": rate(3), "steady_miss_rate": rate(4),
+            "median_steps_fallback_boxes": (float(np.median(n["surrogate"][ok & (status == 3)]))
+                                            if (ok & (status == 3)).any() else None),
+            "median_steps_plain_fallback_boxes": (float(np.median(n["plain"][ok & (status == 3)]))
+                                                  if (ok & (status == 3)).any() else None),
+            "median_decision_step_fallback_boxes": (float(np.median(np.array(
+                [info["decided"][p.box] for p in W.particles])[ok & (status == 3)]))
+                if (ok & (status == 3)).any() else None),
+            "queued": queued.tolist(), "queued_samples": (X[queued], Y[queued]),
+            "per_box": n, "steady": ok, "status": status}
