@@ -344,7 +344,7 @@ def main():
                          "instead of the benchmark and print their results as one JSON line")
     ap.add_argument("--studies", default="domain,resolution,sphere_array,jeffery_domain",
                     help="with --sweep-only: comma-separated studies to run (domain, resolution, sphere_array, "
-                         "jeffery_domain, drift_superposition)")
+                         "jeffery_domain, drift_superposition, squirmer_starts)")
     ap.add_argument("--surrogate-runs", type=int, default=4,
                     help="256-box FP16 ensembles run to train the warm-start network (0: skip steps to steady)")
     ap.add_argument("--eval-boxes", type=int, default=64, help="held-out force-driven boxes for steps to steady")
@@ -370,7 +370,7 @@ def main():
     from paper_2403_05443_amd import lbell
     lbell.load()
     if args.sweep_only:
-        from paper_2403_05443_amd import runner
+        from paper_2403_05443_amd import runner, workloads
         t0 = time.perf_counter()
         studies = {
             "domain": lambda: runner.domain_sweep([32, 64, 128, 256, 512], a=7.5, b=2.5, nu=0.1, storage="fp32"),
@@ -378,8 +378,12 @@ def main():
             "sphere_array": lambda: {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)},
             "jeffery_domain": lambda: [runner.jeffery_half_period(L) for L in (26, 32, 40, 48, 64)],
             "drift_superposition": lambda: runner.drift_superposition(bs=(2.0, 3.0, 4.0)),
+            "squirmer_starts": lambda: runner.squirmer_starts(
+                workloads.c5("fp16"), runner.train_warm_network(seeds=4, boxes=256, epochs=1000, seed0=10)[0],
+                log=lambda m: print(m, file=sys.stderr, flush=True)),
         }
-        out = {"kind": "settling spheroid studies (Sec. III.A-C, Figs. 4 and 9)", "data": "synthetic"}
+        out = {"kind": "studies of the settling spheroid (Sec. III.A-C, Figs. 4 and 9) and of the squirmer "
+                       "suspension's starts (Sec. III.D)", "data": "synthetic"}
         for name in args.studies.split(","):
             out[name] = studies[name]()
         out["seconds"] = round(time.perf_counter() - t0, 1)

@@ -331,9 +331,18 @@ lb_status lb_destroy(lb_ctx* ctx);
  * Inputs and outputs (all FP32, row-major, host memory owned by the caller):
  * for a particle with semi-axes (a, b, c), orientation R(q), external load
  * (F, T), equal-volume radius Req = (abc)^(1/3), load scale
- * s = sqrt(|R^T F|^2 + |R^T T|^2 / Req^2) and box volume L^3,
+ * s = sqrt(|R^T F|^2 + |R^T T|^2 / Req^2) and L^3 its box's volume per
+ * particle (the box's volume over its number of particles),
  *   x = (ln(a / sqrt(bc)), a / L, R^T F / s, R^T T / (Req s)),
  *   y = (U_body 6 pi mu Req / s, Omega_body 8 pi mu Req^2 / s),  mu = rho0 nu.
+ * A squirmer (lb_set_squirmer, B1 != 0) carries no load of its own: its body
+ * frame load gains the equivalent propulsive force F_eff along its axis,
+ * the drag of a prolate spheroid translating along its axis at the free
+ * swimming speed (Sec. III.D, eq. squirmervel),
+ *   F_eff = 6 pi mu a X^A(e) U_s,  U_s = B1 e^-1 (e^-1 - (e^-2 - 1) arcoth(1/e)),
+ *   X^A(e) = (8/3) e^3 / (-2 e + (1 + e^2) ln((1 + e) / (1 - e))),
+ * e = sqrt(1 - b c / a^2) (1 and 2 B1 / 3 for a sphere); the start field of
+ * the warm start stays that of the external loads alone.
  * ------------------------------------------------------------------------ */
 typedef struct lbs lbs;
 

@@ -119,15 +119,18 @@ def req(axes):
     return (a * b * c) ** (1.0 / 3.0)
 
 
-def features(axes, q, F, T, box):
+def features(axes, q, F, T, box, n_box=1, B1=0.0, mu=1.0):
     """Input vector (ln r, a/L, F_body/s, T_body/(R s)), with r = a/sqrt(bc),
-    L = cube root of the box volume, R the equal-volume radius and
-    s = sqrt(|F|^2 + (|T|/R)^2); zero load gives zero load components."""
+    L = cube root of the box volume per particle (n_box particles in the
+    box), R the equal-volume radius and s = sqrt(|F|^2 + (|T|/R)^2); zero
+    load gives zero load components.  A squirmer (B1 != 0) adds its
+    equivalent propulsive force (propulsive_force) along body x to F_body."""
     a, b, c = axes
     R = req(axes)
-    L = (box[0] * box[1] * box[2]) ** (1.0 / 3.0)
+    L = (box[0] * box[1] * box[2] / n_box) ** (1.0 / 3.0)
     Rm = rotmat(q)
     Fb, Tb = Rm.T @ np.asarray(F, float), Rm.T @ np.asarray(T, float)
+    Fb[0] += propulsive_force(axes, B1, mu)
     s = math.sqrt(Fb @ Fb + (Tb @ Tb) / (R * R))
     x = np.zeros(8)
     x[0] = math.log(a / math.sqrt(b * c))
@@ -138,23 +141,23 @@ def features(axes, q, F, T, box):
     return x, s
 
 
-def velocities(y, axes, q, F, T, nu, rho0=1.0):
+def velocities(y, axes, q, F, T, nu, rho0=1.0, B1=0.0):
     """Lab-frame (U, Omega) from the network output y (normalised body-frame
     response): U_body = y[0:3] s / (6 pi mu R), Omega_body = y[3:6] s / (8 pi mu R^2)."""
     R = req(axes)
-    _, s = features(axes, q, F, T, (1, 1, 1))
     mu = rho0 * nu
+    _, s = features(axes, q, F, T, (1, 1, 1), B1=B1, mu=mu)
     Rm = rotmat(q)
     Ub = np.asarray(y[0:3], float) * s / (6 * math.pi * mu * R)
     Wb = np.asarray(y[3:6], float) * s / (8 * math.pi * mu * R * R)
     return Rm @ Ub, Rm @ Wb
 
 
-def targets(U, W, axes, q, F, T, nu, rho0=1.0):
+def targets(U, W, axes, q, F, T, nu, rho0=1.0, B1=0.0):
     """Inverse of velocities(): the normalised output for measured (U, Omega)."""
     R = req(axes)
-    _, s = features(axes, q, F, T, (1, 1, 1))
     mu = rho0 * nu
+    _, s = features(axes, q, F, T, (1, 1, 1), B1=B1, mu=mu)
     Rm = rotmat(q)
     y = np.zeros(6)
     y[0:3] = Rm.T @ np.asarray(U, float) * 6 * math.pi * mu * R / s
@@ -309,6 +312,28 @@ def kim_karrila(r):
     XC = 4 / 3 * e ** 3 * (1 - e * e) / (2 * e - (1 - e * e) * Lg)
     YC = 4 / 3 * e ** 3 * (2 - e * e) / (-2 * e + (1 + e * e) * Lg)
     return XA, YA, XC, YC
+
+
+def squirmer_speed(r, B1):
+    """Free swimming speed of a prolate spheroidal squirmer of aspect ratio
+    r >= 1 with first slip mode B1 (Sec. III.D, eq. squirmervel; Keller & Wu
+    1977): U_s = B1 e^-1 (e^-1 - (e^-2 - 1) arcoth(1/e)), e the
+    eccentricity; 2 B1 / 3 for a sphere."""
+    if r < 1 + 1e-6:
+        return 2.0 * B1 / 3.0
+    e = math.sqrt(1 - 1 / r ** 2)
+    return B1 / e * (1 / e - (1 / e ** 2 - 1) * math.atanh(e))
+
+
+def propulsive_force(axes, B1, mu):
+    """Equivalent propulsive load of a squirmer with semi-axes (a, b, c),
+    a >= b = c: the drag 6 pi mu a X^A U_s of the spheroid translating along
+    its axis at its free swimming speed; 0 for B1 = 0."""
+    if B1 == 0.0:
+        return 0.0
+    a, b, c = axes
+    r = a / math.sqrt(b * c)
+    return 6 * math.pi * mu * a * kim_karrila(r)[0] * squirmer_speed(r, B1)
 
 
 def unbounded_velocities(axes, q, F, T, nu, rho0=1.0):

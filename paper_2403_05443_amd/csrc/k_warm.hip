@@ -5,9 +5,16 @@
 // Surrogate inputs (one thread per particle): with R(q) the body -> lab
 // rotation, F_b = R^T F_ext, T_b = R^T T_ext, the equal-volume radius
 // Req = (abc)^(1/3) and the load scale s = sqrt(|F_b|^2 + |T_b|^2 / Req^2):
-//   x = (ln(a / sqrt(bc)), a / L, F_b / s, T_b / (Req s)),  L = (nx ny nz)^(1/3).
+//   x = (ln(a / sqrt(bc)), a / L, F_b / s, T_b / (Req s)),
+// L = (nx ny nz / n)^(1/3), the box's volume per particle (n particles).
 // Outputs y are the body-frame velocities in units of the Stokes scales:
 //   U_b = y[0:3] s / (6 pi mu Req),  Omega_b = y[3:6] s / (8 pi mu Req^2).
+// A squirmer carries no load of its own; it enters with the equivalent
+// propulsive force along its axis (body x), the drag of a prolate spheroid
+// translating along its axis at the free swimming speed of eq. squirmervel:
+//   F_eff = 6 pi mu a X^A(e) U_s,  U_s = B1 e^-1 (e^-1 - (e^-2 - 1) arcoth(1/e)),
+// e = sqrt(1 - b^2 / a^2), X^A(e) = (8/3) e^3 / (-2 e + (1 + e^2) ln((1+e)/(1-e)))
+// (the sphere's limits 1 and 2 B1 / 3 for e -> 0), added to F_b.
 //
 // Start field: the creeping flow the particles' loads drive in the periodic
 // box.  Per node, the sum over the box's particles of the free-space flow
@@ -43,12 +50,30 @@ __device__ __forceinline__ void body_to_lab(const double q[4], double Rm[3][3]) 
 
 __device__ __forceinline__ double eq_radius(const PartDev& P) { return cbrt(P.axes[0] * P.axes[1] * P.axes[2]); }
 
+// Equivalent propulsive force of a squirmer along its body x axis (0 for a
+// passive particle); a prolate spheroid, b taken as sqrt(bc).  Below
+// e = 1e-3 the sphere's limits hold to 1e-6.
+__device__ double propulsive_force(const PartDev& P, double mu) {
+    if (P.B1 == 0.0) return 0.0;
+    const double a = P.axes[0], b = sqrt(P.axes[1] * P.axes[2]);
+    const double e = a > b ? sqrt(1.0 - (b / a) * (b / a)) : 0.0;
+    double XA = 1.0, Us = 2.0 * P.B1 / 3.0;
+    if (e >= 1e-3) {
+        const double lg = log((1.0 + e) / (1.0 - e));
+        XA = (8.0 / 3.0) * e * e * e / (-2.0 * e + (1.0 + e * e) * lg);
+        Us = P.B1 / e * (1.0 / e - (1.0 / (e * e) - 1.0) * 0.5 * lg);
+    }
+    return 6.0 * M_PI * mu * a * XA * Us;
+}
+
 __global__ void k_warm_features(const BoxDesc* __restrict__ boxes, const PartDev* __restrict__ parts, int np,
-                                float* __restrict__ X, double* __restrict__ s_out) {
+                                double mu, float* __restrict__ X, double* __restrict__ s_out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const PartDev& P = parts[p];
     const BoxDesc& B = boxes[P.box];
+    int nbox = 0;  // the box's particles (a one-off pass; np is at most 65534)
+    for (int k = 0; k < np; ++k) nbox += parts[k].box == P.box;
     double Rm[3][3];
     body_to_lab(P.q, Rm);
     double Fb[3], Tb[3];
@@ -56,12 +81,13 @@ __global__ void k_warm_features(const BoxDesc* __restrict__ boxes, const PartDev
         Fb[k] = Rm[0][k] * P.Fext[0] + Rm[1][k] * P.Fext[1] + Rm[2][k] * P.Fext[2];
         Tb[k] = Rm[0][k] * P.Text[0] + Rm[1][k] * P.Text[1] + Rm[2][k] * P.Text[2];
     }
+    Fb[0] += propulsive_force(P, mu);
     const double R = eq_radius(P);
     const double s = sqrt(Fb[0] * Fb[0] + Fb[1] * Fb[1] + Fb[2] * Fb[2] +
                           (Tb[0] * Tb[0] + Tb[1] * Tb[1] + Tb[2] * Tb[2]) / (R * R));
     float* x = X + (long long)p * MLP_IN;
     x[0] = (float)log(P.axes[0] / sqrt(P.axes[1] * P.axes[2]));
-    x[1] = (float)(P.axes[0] / cbrt((double)B.nx * B.ny * B.nz));
+    x[1] = (float)(P.axes[0] / cbrt((double)B.nx * B.ny * B.nz / nbox));
     for (int k = 0; k < 3; ++k) {
         x[2 + k] = s > 0 ? (float)(Fb[k] / s) : 0.f;
         x[5 + k] = s > 0 ? (float)(Tb[k] / (R * s)) : 0.f;
@@ -532,10 +558,10 @@ hipError_t launch_warm_monitor(const BoxDesc* boxes, int nboxes, const int* tile
     return hipGetLastError();
 }
 
-hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, float* X, double* s,
+hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, double mu, float* X, double* s,
                                 hipStream_t st) {
     if (np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_warm_features, dim3((np + 63) / 64), dim3(64), 0, st, boxes, parts, np, X, s);
+    hipLaunchKernelGGL(k_warm_features, dim3((np + 63) / 64), dim3(64), 0, st, boxes, parts, np, mu, X, s);
     return hipGetLastError();
 }
 

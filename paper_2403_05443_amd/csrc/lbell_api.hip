@@ -1404,10 +1404,10 @@ lb_status lb_warm_start(lb_ctx* ctx, int box, lbs* sur, double tol, double* pred
     double* sc = ctx->at<double>(ctx->L.warm);
     double* pr = sc + ctx->L.max_particles;
     PartDev* parts = ctx->at<PartDev>(ctx->L.parts);
-    HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, sur->X, sc, ctx->stream));
+    const double nu = viscosity(ctx), mu = ctx->kp.rho0 * nu;
+    HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, mu, sur->X, sc, ctx->stream));
     MlpArgs a{sur->P, sur->X, nullptr, sur->out, nullptr, nullptr, ctx->np, 0.f, 0};
     HIPC(launch_mlp(a, ctx->stream));
-    const double nu = viscosity(ctx), mu = ctx->kp.rho0 * nu;
     HIPC(launch_warm_apply(parts, ctx->np, sur->out, sc, mu, pr, box, ctx->stream));
     lb_status s = stokes_start(ctx, box);
     if (s != LB_OK) return s;
@@ -1472,7 +1472,7 @@ lb_status lb_surrogate_sample(lb_ctx* ctx, float* X, float* Y) {
     float* xy = reinterpret_cast<float*>(sc + 7 * (size_t)ctx->L.max_particles);  // after the scales and predictions
     const PartDev* parts = ctx->at<PartDev>(ctx->L.parts);
     const double mu = ctx->kp.rho0 * viscosity(ctx);
-    HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, xy, sc, ctx->stream));
+    HIPC(launch_warm_features(ctx->at<BoxDesc>(ctx->L.boxes), parts, ctx->np, mu, xy, sc, ctx->stream));
     HIPC(launch_warm_targets(parts, ctx->np, sc, mu, xy + (size_t)MLP_IN * ctx->np, ctx->stream));
     HIPC(hipMemcpyAsync(X, xy, sizeof(float) * MLP_IN * ctx->np, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipMemcpyAsync(Y, xy + (size_t)MLP_IN * ctx->np, sizeof(float) * MLP_OUT * ctx->np, hipMemcpyDeviceToHost,

@@ -125,7 +125,7 @@ hipError_t launch_mlp(const MlpArgs& a, hipStream_t st);
 hipError_t launch_mlp_reduce(const MlpReduceArgs& a, hipStream_t st);
 
 // ---- warm start (k_warm.hip) ----
-hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, float* X, double* s,
+hipError_t launch_warm_features(const BoxDesc* boxes, const PartDev* parts, int np, double mu, float* X, double* s,
                                 hipStream_t st);
 hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const double* s, double mu, double* pred,
                              int only_box, hipStream_t st);

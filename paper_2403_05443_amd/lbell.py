@@ -22,6 +22,7 @@ ROTATION = {"analytic": 0, "fd": 1, "pc": 2}
 
 STATUS = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EDEVICE", -4: "LB_ESTATE",
           -5: "LB_EOVERLAP", -6: "LB_ENONFINITE", -7: "LB_ERANGE", -8: "LB_EIO"}
+LB_EOVERLAP = -5
 
 
 class LBError(RuntimeError):

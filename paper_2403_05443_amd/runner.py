@@ -458,6 +458,107 @@ def watch_warm_start(W, surrogate, tol, every=25):
     return lat, st, at, pred, U_dec
 
 
+def _body_axis(q):
+    """Lab-frame body x axis of unit quaternions q (n, 4), scalar first."""
+    q0, q1, q2, q3 = np.asarray(q, float).T
+    return np.stack([1 - 2 * (q2 * q2 + q3 * q3), 2 * (q1 * q2 + q0 * q3), 2 * (q1 * q3 - q0 * q2)], -1)
+
+
+def squirmer_starts(W, surrogate, steps=10000, every=50, monitor_tol=0.1, contact=12.0, log=None):
+    """Starts of a squirmer suspension (config 5) compared through each
+    swimmer's speed along its own axis, s = U . e: plain (rest), the
+    surrogate warm start (its inputs the equivalent propulsive load of each
+    squirmer and the box's volume per particle), the same watched by the
+    device monitor at monitor_tol, and a control starting every squirmer at
+    the closed-form free swimming speed (eq. squirmervel).  The paper has no
+    inter-particle force: squirmers that come within `contact` of another
+    centre (2a + 2 for a = 5) in any run are left out, and the latched overlap
+    flags are counted.  s_inf is the plain run's mean over its last fifth;
+    reported per start: the median |s - s_inf| / s_inf at sampled steps, the
+    median first step at which it falls below 5% and 2%, and the fraction of
+    swimmers that stay within 0.5% / 2% from some step to the end."""
+    a = max(max(p.axes) for p in W.particles)
+    Us = {}
+    for i, p in enumerate(W.particles):
+        ax = p.axes
+        r = ax[0] / math.sqrt(ax[1] * ax[2])
+        e = math.sqrt(1 - 1 / r ** 2) if r > 1 + 1e-6 else 0.0
+        B1 = p.squirmer[0]
+        Us[i] = 2 * B1 / 3 if e < 1e-3 else B1 / e * (1 / e - (1 / e ** 2 - 1) * math.atanh(e))
+    runs, pos, info = {}, {}, {}
+    L = np.array(W.boxes[0].shape, float)
+    for start in ("plain", "surrogate", "surrogate_watched", "control"):
+        lat = build_lattice(W)
+        if start.startswith("surrogate"):
+            pred = lat.warm_start(surrogate, tol=monitor_tol if start == "surrogate_watched" else 0.0)
+            e0 = _body_axis([p.quat for p in W.particles])
+            info["prediction_over_closed_form"] = float(np.median(
+                (pred[:, :3] * e0).sum(1) / np.array([Us[i] for i in range(len(W.particles))])))
+        elif start == "control":
+            e0 = _body_axis([p.quat for p in W.particles])
+            for i in range(len(W.particles)):
+                lat.set_velocity(i, e0[i] * Us[i], np.zeros(3))
+            lat.stokes_start()
+        lat.set_graph(every)
+        S, X, flags = [], [], 0
+        for _ in range(steps // every):
+            try:
+                lat.step(every)
+            except lbell.LBError as err:
+                if err.status != lbell.LB_EOVERLAP:
+                    raise
+                flags += 1
+            try:
+                P = lat.particles()
+            except lbell.LBError as err:
+                if err.status != lbell.LB_EOVERLAP:
+                    raise
+                flags += 1
+                P = lat.particles()
+            S.append((P["U"] * _body_axis(P["q"])).sum(1))
+            X.append(P["x"].copy())
+        if start == "surrogate_watched":
+            st, at = lat.warm_status()
+            info["monitor"] = {"status": lbell.Lattice.WARM_STATUS[int(st[0])], "decided_step": int(at[0])}
+        info.setdefault("overlap_flags", {})[start] = flags
+        runs[start], pos[start] = np.array(S), np.array(X)
+        del lat
+        if log:
+            log(f"squirmer_starts: {start} run done ({steps} steps, {flags} overlap flags)")
+    times = np.arange(1, steps // every + 1) * every
+    close = np.zeros(len(W.particles), dtype=bool)
+    for Xs in pos.values():
+        for k in range(0, len(Xs), 4):
+            d = Xs[k][:, None, :] - Xs[k][None, :, :]
+            d -= L * np.round(d / L)
+            rr = np.sqrt((d * d).sum(-1)) + 1e9 * np.eye(len(W.particles))
+            close |= (rr < contact).any(1)
+    keep = ~close
+    tail = max(len(times) // 5, 1)
+    s_inf = runs["plain"][-tail:, keep].mean(0)
+    sp = runs["plain"][:, keep]
+    out = {"workload": W.name, "storage": W.storage, "steps": steps, "every": every, "monitor_tol": monitor_tol,
+           "swimmers": len(W.particles), "kept": int(keep.sum()), "left_out_contact": int(close.sum()),
+           "plain_speed_change_over_last_2000": float(np.median(np.abs(sp[-1] - sp[-1 - 2000 // every])
+                                                                / np.abs(sp[-1]))),
+           "plain_speed_over_closed_form": float(np.median(sp[-1] / np.array([Us[i] for i in np.nonzero(keep)[0]]))),
+           **info, "starts": {}}
+    marks = [k for k in (0, 1, 3, 5, 9, 19, 39, 99, len(times) - 1) if k < len(times)]
+    for start, s in runs.items():
+        dev = np.abs(s[:, keep] - s_inf[None]) / np.abs(s_inf)[None]
+        first = {}
+        for tol in (0.05, 0.02):
+            hit = dev <= tol
+            idx = np.where(hit.any(0), hit.argmax(0), -1)
+            first[str(tol)] = float(np.median(np.where(idx >= 0, times[np.maximum(idx, 0)], np.inf)))
+        stay = {}
+        for tol in (0.005, 0.02):
+            stay[str(tol)] = float(np.isfinite(steps_to_tolerance(times, s[:, keep, None], s_inf[:, None], tol)).mean())
+        out["starts"][start] = {"median_deviation": {int(times[k]): round(float(np.median(dev[k])), 4) for k in marks},
+                                "median_first_step_within": first, "fraction_settled_to_end": stay}
+    return out
+
+
 def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0.1):
     """Steps to a tol-accurate steady velocity for each particle of the
     force-driven ensemble W from the three starts.  The steady velocity is

@@ -151,6 +151,40 @@ def test_warm_start_prediction_matches_reference(lb):
         assert np.allclose(pr, np.concatenate([U2, W2]), rtol=1e-5, atol=0)
 
 
+def test_squirmer_features_match_reference(lb):
+    """Surrogate inputs and targets of a box shared by two squirmers and a
+    loaded passive spheroid (lb_surrogate_sample) against the reference: L
+    is the box's volume per particle and the squirmers carry their
+    equivalent propulsive load; FP32 rounding of O(1) values."""
+    g = lb.Lattice([(48, 40, 44)], collision="trt", tau=0.8, storage="fp32", max_particles=4)
+    nu = (0.8 - 0.5) / 3
+    rng = np.random.default_rng(31)
+    specs = [((11.3, 10.2, 12.4), (5.0, 2.5, 2.5), 1e-3, -2e-3, np.zeros(3), np.zeros(3)),
+             ((34.1, 27.5, 30.2), (3.0, 3.0, 3.0), -5e-4, 0.0, np.zeros(3), np.zeros(3)),
+             ((12.7, 29.9, 31.6), (6.0, 2.0, 2.0), 0.0, 0.0, np.array([1e-4, -2e-5, 3e-5]),
+              np.array([0.0, 2e-4, -1e-4]))]
+    ids, qs, vel = [], [], []
+    for c, a, B1, B2, F, T in specs:
+        q = rng.standard_normal(4)
+        q /= np.linalg.norm(q)
+        pid = g.add_ellipsoid(c, a, q)
+        if B1:
+            g.set_squirmer(pid, B1, B2)
+        g.set_external(pid, F, T)
+        U, W = rng.standard_normal(3) * 1e-4, rng.standard_normal(3) * 1e-5
+        g.set_velocity(pid, U, W)
+        ids.append(pid)
+        qs.append(q)
+        vel.append((U, W))
+    X, Y = g.surrogate_sample()
+    for (c, a, B1, B2, F, T), pid, q, (U, W) in zip(specs, ids, qs, vel):
+        x, _ = S.features(a, q, F, T, (48, 40, 44), n_box=3, B1=B1, mu=nu)
+        y = S.targets(U, W, a, q, F, T, nu, B1=B1)
+        print(pid, "x err", np.abs(X[pid] - x).max(), "y err", np.abs(Y[pid] - y).max() / np.abs(y).max())
+        assert np.abs(X[pid] - x).max() < 1e-6
+        assert np.abs(Y[pid] - y).max() < 1e-6 * np.abs(y).max()
+
+
 def _oracle_start(o, shape, parts, mu):
     """Oracle state started from the reference start field."""
     u = S.start_field(shape, o.mask(), parts, mu)

@@ -215,6 +215,42 @@ def test_resistance_functions_match_perrin():
     assert abs(45 - math.degrees(math.atan(XA / YA)) - 5.891) < 1e-3
 
 
+def test_squirmer_speed_limits_and_series():
+    """Eq. squirmervel pinned by what fixes it independently: the sphere's
+    2 B1 / 3, the needle limit B1, the small-eccentricity series
+    U_s / B1 = 2/3 + (2/15) e^2 + (2/35) e^4 + (2/63) e^6 + ... (from
+    arcoth(1/e) = atanh(e) = e + e^3/3 + e^5/5 + ...), and the growth with the
+    aspect ratio the paper's Fig. 8(a) shows; U_s is linear in B1."""
+    assert S.squirmer_speed(1.0, 3e-3) == pytest.approx(2e-3, rel=1e-15)
+    for e in (0.02, 0.05, 0.1):
+        r = 1 / math.sqrt(1 - e * e)
+        series = 2 / 3 + 2 / 15 * e ** 2 + 2 / 35 * e ** 4
+        assert abs(S.squirmer_speed(r, 1.0) - series) < 0.04 * e ** 6 + 1e-14 / e ** 2
+    assert abs(S.squirmer_speed(1e4, 1.0) - 1.0) < 1e-6
+    speeds = [S.squirmer_speed(r, 1.0) for r in (1.0, 1.5, 2.0, 3.0, 5.0)]
+    assert all(b > a for a, b in zip(speeds, speeds[1:]))
+    assert S.squirmer_speed(2.0, -2e-3) == pytest.approx(-2 * S.squirmer_speed(2.0, 1e-3), rel=1e-15)
+
+
+def test_squirmer_features_carry_the_propulsive_load():
+    """A force-free squirmer enters the surrogate with the Stokes drag of its
+    free swimming: for a sphere 6 pi mu R (2 B1 / 3) = 4 pi mu R B1 along its
+    axis, so that a unit-mobility output is a sphere swimming at 2 B1 / 3;
+    L is the box's volume per particle."""
+    g = np.random.default_rng(21)
+    q = _rand_pose(g)
+    mu, R, B1 = 1 / 6, 3.0, 1e-3
+    assert S.propulsive_force((R, R, R), B1, mu) == pytest.approx(4 * math.pi * mu * R * B1, rel=1e-14)
+    x, s = S.features((R, R, R), q, np.zeros(3), np.zeros(3), (64, 64, 64), n_box=8, B1=B1, mu=mu)
+    assert np.allclose(x[2:], [1, 0, 0, 0, 0, 0], atol=1e-15) and x[1] == pytest.approx(R / 32)
+    U, W = S.velocities(np.array([1.0, 0, 0, 0, 0, 0]), (R, R, R), q, np.zeros(3), np.zeros(3), mu, B1=B1)
+    assert np.allclose(U, S.rotmat(q)[:, 0] * 2 * B1 / 3, rtol=1e-13, atol=0) and not W.any()
+    # prolate r = 2: the closed forms give the free swimming speed back
+    axes = (5.0, 2.5, 2.5)
+    U, _ = S.unbounded_velocities(axes, q, S.rotmat(q)[:, 0] * S.propulsive_force(axes, B1, mu), np.zeros(3), mu)
+    assert np.allclose(U, S.rotmat(q)[:, 0] * S.squirmer_speed(2.0, B1), rtol=1e-13, atol=0)
+
+
 def test_stokes_field_exact_properties():
     g = np.random.default_rng(16)
     U, W, R = g.standard_normal(3), g.standard_normal(3), 2.7
