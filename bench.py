@@ -325,6 +325,11 @@ def steps_to_steady(runs, eval_boxes, monitor_tol=0.1, wrong_tol=0.02):
             "seconds": {"train": round(t_train, 2), "eval": round(t_eval, 2)}}
 
 
+def _progress(msg):
+    """One line on stderr per finished part of the run."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +398,7 @@ def main():
     copy_gbs = lbell.bandwidth_probe(args.probe_bytes, reps=5)
     lat, m = measure(W, args.steps, args.warmup, args.graph, variant=args.variant)
     del lat
+    _progress(f"headline {W.name}/{args.storage}: {m['mlups']:.1f} MLUPS, variant {m['variant']}")
     src_sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     traffic = traffic_record(src_sha, W.name, args.storage, m["variant"])
     rm = roofline_mlups(W)
@@ -431,10 +437,13 @@ def main():
         lat, e = measure(Wl, steps, warm, args.graph)
         del lat
         out["legs"][name] = leg_record(Wl, e, src_sha, steps)
+        _progress(f"leg {name}: {e['mlups']:.1f} MLUPS, variant {e['variant']}")
     if args.surrogate_runs > 0:
         out["steps_to_steady"] = steps_to_steady(args.surrogate_runs, args.eval_boxes)
+        _progress("steps to steady done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+        _progress("cpu baseline done")
         out["cpu_reference"] = cpu_reference()
     print(json.dumps(out), flush=True)
 

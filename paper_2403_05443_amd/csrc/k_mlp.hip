@@ -1,11 +1,15 @@
 // k_mlp.hip - the warm-start surrogate: an 8 -> 64 -> 64 -> 6 tanh MLP whose
-// forward and backward passes run on the gfx950 matrix cores
-// (v_mfma_f32_16x16x16_bf16: bfloat16 operands, FP32 accumulation), plus the
-// gradient reduction and the Adam update (Kingma & Ba 2015).
+// forward and backward passes run on the gfx950 matrix cores (bfloat16
+// operands, FP32 accumulation), plus the gradient reduction and the Adam
+// update (Kingma & Ba 2015).
 //
 // Work split: a wave owns a tile of 16 samples and carries it through all
 // three layers (and back); a work-group of four waves shares one bfloat16 copy
-// of the weights in LDS.  Every product is a sum of 16 x 16 x 16 tiles.
+// of the weights in LDS.  Products over the 64 hidden units (forward layers 2
+// and 3, the error back-propagated into layer 1) are sums of 16 x 16 x 32
+// tiles (v_mfma_f32_16x16x32_bf16); products over 16 (the padded inputs and
+// outputs, and the weight gradients over the tile's 16 samples) take the
+// 16 x 16 x 16 shape (v_mfma_f32_16x16x16_bf16).
 // Rounding points (mirrored by the FP64 reference): inputs, weights, hidden
 // activations and back-propagated errors are rounded to bfloat16 where they
 // enter a product; biases, tanh, error terms and all sums stay FP32.  Each
@@ -17,6 +21,7 @@
 namespace lbd {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MLP_WAVES = 4;  // tiles of 16 samples per work-group
@@ -41,6 +46,21 @@ __device__ __forceinline__ f32x4 mma16(FA A, FB B, f32x4 acc, int lane) {
         b[j] = (short)B(4 * g + j, r);
     }
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+}
+
+// The same for a K = 32 slice: lane l supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7; D as above.  A and B take the same K
+// order, so the sum pairs A[m][k] with B[k][n] whatever K order the unit uses.
+template <class FA, class FB>
+__device__ __forceinline__ f32x4 mma32(FA A, FB B, f32x4 acc, int lane) {
+    const int r = lane & 15, g = lane >> 4;
+    bf16x8 a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = __builtin_bit_cast(__bf16, (uint16_t)A(r, 8 * g + j));
+        b[j] = __builtin_bit_cast(__bf16, (uint16_t)B(8 * g + j, r));
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
 
 struct MlpShm {
@@ -100,9 +120,9 @@ __global__ __launch_bounds__(64 * MLP_WAVES) void k_mlp(MlpArgs a) {
     for (int ot = 0; ot < 4; ++ot) {
         f32x4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-            acc = mma16([&](int m, int k) { return W.h1[m][16 * kt + k]; },
-                        [&](int k, int n) { return sh.w2[16 * ot + n][16 * kt + k]; }, acc, lane);
+        for (int kt = 0; kt < 2; ++kt)
+            acc = mma32([&](int m, int k) { return W.h1[m][32 * kt + k]; },
+                        [&](int k, int n) { return sh.w2[16 * ot + n][32 * kt + k]; }, acc, lane);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             W.h2[4 * g + j][16 * ot + r] = to_bf16(tanhf(acc[j] + P[MLP_OB2 + 16 * ot + r]));
@@ -110,9 +130,9 @@ __global__ __launch_bounds__(64 * MLP_WAVES) void k_mlp(MlpArgs a) {
     __syncthreads();
     f32x4 y = {0, 0, 0, 0};
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt)
-        y = mma16([&](int m, int k) { return W.h2[m][16 * kt + k]; },
-                  [&](int k, int n) { return sh.w3[n][16 * kt + k]; }, y, lane);
+    for (int kt = 0; kt < 2; ++kt)
+        y = mma32([&](int m, int k) { return W.h2[m][32 * kt + k]; },
+                  [&](int k, int n) { return sh.w3[n][32 * kt + k]; }, y, lane);
     if (a.mode == 0) {
         if (r < MLP_OUT)
 #pragma unroll
@@ -197,9 +217,9 @@ __global__ __launch_bounds__(64 * MLP_WAVES) void k_mlp(MlpArgs a) {
     for (int kt = 0; kt < 4; ++kt) {
         f32x4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-            acc = mma16([&](int m, int o) { return W.d2[m][16 * ot + o]; },
-                        [&](int o, int k) { return sh.w2[16 * ot + o][16 * kt + k]; }, acc, lane);
+        for (int ot = 0; ot < 2; ++ot)
+            acc = mma32([&](int m, int o) { return W.d2[m][32 * ot + o]; },
+                        [&](int o, int k) { return sh.w2[32 * ot + o][16 * kt + k]; }, acc, lane);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int m = 4 * g + j, k = 16 * kt + r;
