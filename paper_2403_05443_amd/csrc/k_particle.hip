@@ -671,10 +671,22 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
 #pragma unroll
     for (int k = 0; k < KREG; ++k)
         if (tid + k * PBLOCK < nl) accumulate(code[k], fbv[k], k);
-    for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
-        const uint32_t cd = L[l];
-        accumulate(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv),
-                   -1);
+    // links past the registers (large particles): KOVF per thread per pass,
+    // their code loads issued together, then their population loads, then
+    // the sums in the same order as one at a time (a lane past the end reads
+    // element 0 of the box, always valid, and does not use it)
+    for (int l0 = tid + KREG * PBLOCK; l0 < nl; l0 += KOVF * PBLOCK) {
+        uint32_t cd[KOVF];
+        double fv[KOVF];
+#pragma unroll
+        for (int j = 0; j < KOVF; ++j) cd[j] = l0 + j * PBLOCK < nl ? L[l0 + j * PBLOCK] : 0u;
+#pragma unroll
+        for (int j = 0; j < KOVF; ++j)
+            fv[j] = S::ld64(f + link_post(a.kp.conv, B, (int)(cd[j] >> SITE_BITS), (int)(cd[j] & SITE_MASK), rnx, rny),
+                            inv);
+#pragma unroll
+        for (int j = 0; j < KOVF; ++j)
+            if (l0 + j * PBLOCK < nl) accumulate(cd[j], fv[j], -1);
     }
     block_reduce<6>(acc, red);
 
@@ -834,9 +846,21 @@ __device__ __forceinline__ void solve_phase(const LaunchPart& a, int p, PartDev&
                               (Wn[0] * bb_rc[k][0] + Wn[1] * bb_rc[k][1] + Wn[2] * bb_rc[k][2]);
             S::st64(f + bb_slot[k], bb_base[k] - bb_kw[k] * uc, scl);
         }
-    for (int l = tid + KREG * PBLOCK; l < nl; l += PBLOCK) {
-        const uint32_t cd = L[l];
-        bounce(cd, S::ld64(f + link_post(a.kp.conv, B, (int)(cd >> SITE_BITS), (int)(cd & SITE_MASK), rnx, rny), inv));
+    // the links past the registers, KOVF per thread per pass as in the force
+    // pass (a link's store never lands on another link's read slot: the
+    // store goes to a slot read from the solid side)
+    for (int l0 = tid + KREG * PBLOCK; l0 < nl; l0 += KOVF * PBLOCK) {
+        uint32_t cd[KOVF];
+        double fv[KOVF];
+#pragma unroll
+        for (int j = 0; j < KOVF; ++j) cd[j] = l0 + j * PBLOCK < nl ? L[l0 + j * PBLOCK] : 0u;
+#pragma unroll
+        for (int j = 0; j < KOVF; ++j)
+            fv[j] = S::ld64(f + link_post(a.kp.conv, B, (int)(cd[j] >> SITE_BITS), (int)(cd[j] & SITE_MASK), rnx, rny),
+                            inv);
+#pragma unroll
+        for (int j = 0; j < KOVF; ++j)
+            if (l0 + j * PBLOCK < nl) bounce(cd[j], fv[j]);
     }
 }
 

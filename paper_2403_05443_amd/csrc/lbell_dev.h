@@ -11,6 +11,7 @@ constexpr int TILE = 256;        // sites per K1 work-group
 constexpr int PBLOCK = 512;      // threads per particle work-group
 constexpr int PWAVES = PBLOCK / 64;
 constexpr int KREG = 2;          // links per thread held in registers across phases
+constexpr int KOVF = 4;          // links past those whose loads one thread issues together
 constexpr int KSCAN = 4;         // window sites per thread whose node-map loads the solid scan issues together
 constexpr int STAGE = 4096;      // link codes staged in LDS per copy-out round
 constexpr int SITE_BITS = 27;    // link code: site | dir << 27
