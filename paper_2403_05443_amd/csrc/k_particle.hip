@@ -408,6 +408,7 @@ __device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc&
     double Rm[3][3];
     rotmat(P.q, Rm);
     const int n3[3] = {B.nx, B.ny, B.nz};
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double h = sqrt((Rm[k][0] * P.axes[0]) * (Rm[k][0] * P.axes[0]) +
                               (Rm[k][1] * P.axes[1]) * (Rm[k][1] * P.axes[1]) +
@@ -427,6 +428,7 @@ __device__ __forceinline__ void particle_window(const PartDev& P, const BoxDesc&
 __device__ __forceinline__ void mark_near(const NearSet& ns, const BoxDesc& B, const int wlo[3], const int wwn[3]) {
     const int n3[3] = {B.nx, B.ny, B.nz};
     int lo[3], wn[3];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         lo[k] = wlo[k] - ns.margin;
         wn[k] = wwn[k] + 2 * ns.margin;
@@ -886,6 +888,7 @@ struct RemapShm {
 __device__ __forceinline__ bool scan_needed(const PartDev& P) {
     if (!(P.smargin > 0.0)) return true;
     double dx2 = 0.0;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double d = P.xu[k] - P.sref[k];
         dx2 += d * d;
@@ -901,6 +904,34 @@ __device__ __forceinline__ bool scan_needed(const PartDev& P) {
     const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
     const double dwin = dx + 2.0 * sh * P.srho, dbody = dx + 2.0 * sh * amax;
     return !(dwin * (1.0 + 1e-12) + 1e-9 < P.smargin && dbody < 0.5);
+}
+
+// Whether a rescan may test the narrow band of the last full scan only.
+// That scan recorded, over its window, every node whose margin was below
+// BAND_M (in lattice units; the margin bounds the distance to the surface
+// from below); every other node of the box was at least BAND_M from the
+// body (nodes outside that window more than one node).  While the body has
+// moved by less than BAND_M since (translation plus the rotation's chord over
+// that window's radius, shaded for rounding), no node outside the band can
+// have changed side.  d0 receives that displacement bound.
+__device__ __forceinline__ bool band_ok(const PartDev& P, double& d0) {
+    if (!P.bvalid) return false;
+    double dx2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double d = P.xu[k] - P.bref[k];
+        dx2 += d * d;
+    }
+    const double dx = sqrt(dx2);
+    const double q0 = P.q[0], r0 = P.bqref[0];
+    const double v[3] = {P.q[1], P.q[2], P.q[3]}, w[3] = {P.bqref[1], P.bqref[2], P.bqref[3]};
+    const double s0 = r0 * v[0] - q0 * w[0] - (v[1] * w[2] - v[2] * w[1]);
+    const double s1 = r0 * v[1] - q0 * w[1] - (v[2] * w[0] - v[0] * w[2]);
+    const double s2 = r0 * v[2] - q0 * w[2] - (v[0] * w[1] - v[1] * w[0]);
+    const double sh = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+    const double amax = fmax(P.axes[0], fmax(P.axes[1], P.axes[2]));
+    d0 = dx + 2.0 * sh * P.bsrho;
+    return d0 * (1.0 + 1e-12) + 1e-9 < BAND_M * (1.0 - 1e-12) && dx + 2.0 * sh * amax < 0.5;
 }
 
 // The remap window of a particle with the reciprocals its index arithmetic
@@ -966,6 +997,7 @@ __device__ __forceinline__ bool window_stamped(const LaunchPart& a, const BoxDes
     // per axis up to two runs of coordinates (the window may wrap), as cells
     int c0[3][2], c1[3][2], nr[3], cnt[3];
     const int n3[3] = {B.nx, B.ny, B.nz};
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         int s0 = w.lo[k], e0 = w.lo[k] + w.wn[k], s1 = 0, e1 = 0;
         if (w.whole[k]) {
@@ -1044,6 +1076,11 @@ __device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P,
     double mloc = 1.0;  // lower bound of |sqrt(Q) - 1| over this thread's nodes
     int nsol = 0;
     bool released = false, candidate = false;
+    // the narrow band of this scan (mode 0 and 1): window nodes whose margin
+    // is below BAND_M
+    const bool rec_band = a.use_band && mode != 2;
+    uint32_t* bandw = a.band + (size_t)p * a.lds_words;
+    const double band_q = BAND_M / fmin(P.axes[0], fmin(P.axes[1], P.axes[2]));
     for (int base = 0; base < nsites; base += PBLOCK * KSCAN) {
         uint16_t own[KSCAN];
         int sidx[KSCAN], gxyz[KSCAN][3];
@@ -1061,7 +1098,7 @@ __device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P,
 #pragma unroll
         for (int k = 0; k < KSCAN; ++k) {
             if (base + k * PBLOCK >= nsites) break;  // uniform over the block
-            bool in = false, cd = false;
+            bool in = false, cd = false, bnd = false;
             const int s = sidx[k];
             if (s >= 0) {
                 const int gx = gxyz[k][0], gy = gxyz[k][1], gz = gxyz[k][2];
@@ -1074,7 +1111,9 @@ __device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P,
                     const double Qv = quad_form(xc, q, ia2, gx, gy, gz, nx, ny, nz);
                     in = Qv < 1.0;
                     // sqrt(Q) <= (Q + 1) / 2, so |sqrt(Q) - 1| = |Q - 1| / (sqrt(Q) + 1) >= 2 |Q - 1| / (Q + 3)
-                    mloc = fmin(mloc, 2.0 * fabs(Qv - 1.0) / (Qv + 3.0));
+                    const double mq = 2.0 * fabs(Qv - 1.0) / (Qv + 3.0);
+                    mloc = fmin(mloc, mq);
+                    bnd = mq < band_q;
                     if (in && own[k] == 0xFFFFu) {  // a wall node
                         atomicOr(a.flags, (int)F_OVERLAP);
                         in = false;
@@ -1129,6 +1168,13 @@ __device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P,
                     bits[w0 + 1] = (uint32_t)(m >> 32);
                 }
             }
+            if (rec_band) {
+                const unsigned long long m = __ballot(bnd);
+                if (lane == 0) {
+                    bandw[w0] = (uint32_t)m;
+                    bandw[w0 + 1] = (uint32_t)(m >> 32);
+                }
+            }
         }
     }
     if (mode != 2) {
@@ -1155,14 +1201,28 @@ __device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P,
             // largest |x - x_c| over the window's nodes
             const int n3[3] = {nx, ny, nz};
             double r2 = 0.0;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double e = w.whole[k] ? 0.5 * n3[k]
                                             : fmax(xc[k] - w.lo[k], (double)(w.lo[k] + w.wn[k] - 1) - xc[k]);
                 r2 += e * e;
             }
             Pg->srho = sqrt(r2);
+            // the band's reference: this pose, this window and its radius
+            if (rec_band) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Pg->bref[k] = P.xu[k];
+                    Pg->blo[k] = w.lo[k];
+                    Pg->bwn[k] = w.wn[k];
+                }
+                for (int k = 0; k < 4; ++k) Pg->bqref[k] = P.q[k];
+                Pg->bsrho = sqrt(r2);
+            }
+            Pg->bvalid = rec_band ? 1 : 0;
         }
     }
+    if (mode == 2 && tid == 0) Pg->bvalid = 0;
     if (changed) {
         // solid count and (mode 0) the uncovered nodes' book-keeping
         if (mode == 0) block_reduce<7>(tacc, red);
@@ -1178,6 +1238,290 @@ __device__ __forceinline__ int scan_pass(const LaunchPart& a, int p, PartDev& P,
             Pg->n_solid = ns;
             P.n_solid = ns;
         } else if (mode == 0 && tid >= 37 && tid < 44) {
+            const int k = tid - 37;  // dm, Pp[3], Lp[3]
+            double* fld = k == 0 ? &P.dm : (k < 4 ? &P.Pp[k - 1] : &P.Lp[k - 4]);
+            double* gfld = k == 0 ? &Pg->dm : (k < 4 ? &Pg->Pp[k - 1] : &Pg->Lp[k - 4]);
+            const double nv = *fld + tacc[k];
+            *gfld = nv;
+            *fld = nv;
+        }
+        __syncthreads();
+    }
+    return (changed ? 1 : 0) | (anycand ? 2 : 0);
+}
+
+// This particle's nodes over the window, as window bits, from the node map.
+__device__ __forceinline__ void bits_from_map(const LaunchPart& a, int p, const BoxDesc& B, const Win& w, uint32_t* bits) {
+    const uint16_t* om = a.omap + B.ooff;
+    const uint16_t me = (uint16_t)(p + 1);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int base = 0; base < w.nsites; base += PBLOCK * KSCAN) {
+        bool in[KSCAN];
+#pragma unroll
+        for (int k = 0; k < KSCAN; ++k) {
+            const int i = base + k * PBLOCK + tid;
+            in[k] = false;
+            if (i < w.nsites) {
+                int gx, gy, gz;
+                win_node(w, B, i, gx, gy, gz);
+                in[k] = om[gx + B.nx * (gy + B.ny * gz)] == me;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KSCAN; ++k) {
+            if (base + k * PBLOCK >= w.nsites) break;  // uniform over the block
+            const unsigned long long m = __ballot(in[k]);
+            if (lane == 0) {
+                const int w0 = (base + k * PBLOCK + wv * 64) >> 5;
+                bits[w0] = (uint32_t)m;
+                bits[w0 + 1] = (uint32_t)(m >> 32);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// LDS words of the particle kernels' dynamic area (window bitmask and link
+// stage), which the band's list may fill.
+__host__ __device__ constexpr int band_list_cap(int lds_words) { return lds_words + (lds_words > STAGE ? lds_words : STAGE); }
+
+// The band's nodes (indices in the window of its full scan), in index
+// order, into list[0, nb) (LDS, cap entries): a block-wide prefix over the
+// band's bit words.  False, with nb the count, when they do not fit.
+__device__ __forceinline__ bool band_list(const uint32_t* bandw, int nwords, uint32_t* list, int cap,
+                                          RemapShm& sh, int& nb) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int per = (nwords + PBLOCK - 1) / PBLOCK;  // consecutive words per thread
+    int cnt = 0;
+    for (int j = 0; j < per; ++j) {
+        const int wi = tid * per + j;
+        if (wi < nwords) cnt += __popc(bandw[wi]);
+    }
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) sh.wtot[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int v = 0; v < PWAVES; ++v) {
+        const int t = sh.wtot[v];
+        if (v < wv) before += t;
+        total += t;
+    }
+    nb = total;
+    if (total > cap) {  // uniform over the block
+        __syncthreads();
+        return false;
+    }
+    int off = before + incl - cnt;
+    for (int j = 0; j < per; ++j) {
+        const int wi = tid * per + j;
+        if (wi < nwords) {
+            uint32_t m = bandw[wi];
+            while (m) {
+                const int bt = __ffs(m) - 1;
+                m &= m - 1;
+                list[off++] = (uint32_t)(wi * 32 + bt);
+            }
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// Pass 1 over the narrow band of the last full scan only (mode 0, when
+// band_ok holds; d0 its displacement bound).  Every node outside the band
+// keeps its side (band_ok), so the outcome equals scan_pass's: the same
+// releases and uncovered-node book-keeping, the same candidates (cand, over
+// the current window), the same solid count, and with bits (LDS; the fused
+// path) this particle's nodes after the step.  The band's nodes are first
+// tested without side effects (listed in index order in lst, cap entries of
+// LDS that the pass may overwrite, when they fit); only if some node changes
+// side are the candidate bits cleared, bits read from the node map (before
+// any change) and the changes made.  The skip test's reference becomes this
+// pose, with the margin of the band's nodes here and BAND_M - d0 for every
+// other node.  Returns as scan_pass.
+template <int ST, int Q>
+__device__ __forceinline__ int band_pass(const LaunchPart& a, int p, PartDev& P, const BoxDesc& B, const Win& w,
+                                         uint32_t* bits, uint32_t* cand, uint32_t* lst, int cap, RemapShm& sh,
+                                         uint32_t ep, double d0) {
+    using S = Store<ST>;
+    double (*red)[PWAVES] = sh.red;
+    int (*ired)[PWAVES] = sh.ired;
+    PartDev* Pg = a.parts + p;
+    auto* f = (typename S::T*)a.f + B.foff;
+    uint16_t* om = a.omap + B.ooff;
+    const long long st = B.stride;
+    const int nx = B.nx, ny = B.ny, nz = B.nz, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const uint16_t me = (uint16_t)(p + 1);
+    const double xc[3] = {P.xc[0], P.xc[1], P.xc[2]};
+    const double q[4] = {P.q[0], P.q[1], P.q[2], P.q[3]};
+    const double ia2[3] = {P.ia2[0], P.ia2[1], P.ia2[2]};
+    const double U[3] = {P.U[0], P.U[1], P.U[2]}, W[3] = {P.W[0], P.W[1], P.W[2]};
+    const double scl = a.kp.scale, rho0 = a.kp.rho0;
+    // the window of the full scan the band belongs to
+    Win w0;
+    w0.lo[0] = P.blo[0];
+    w0.lo[1] = P.blo[1];
+    w0.lo[2] = P.blo[2];
+    w0.wn[0] = P.bwn[0];
+    w0.wn[1] = P.bwn[1];
+    w0.wn[2] = P.bwn[2];
+    w0.whole[0] = w0.wn[0] >= nx;
+    w0.whole[1] = w0.wn[1] >= ny;
+    w0.whole[2] = w0.wn[2] >= nz;
+    w0.nsites = w0.wn[0] * w0.wn[1] * w0.wn[2];
+    w0.rw0 = 1.0 / w0.wn[0];
+    w0.rw1 = 1.0 / w0.wn[1];
+    const uint32_t* bandw = a.band + (size_t)p * a.lds_words;
+    const int bwords = (w0.nsites + 31) >> 5;
+    int nb = 0;
+    const bool listed = lst && band_list(bandw, bwords, lst, cap, sh, nb);
+
+    // visits the band's nodes that lie in the current window, the node-map
+    // loads of KSCAN nodes per thread in flight together: fn(gx, gy, gz, s, i1, own)
+    auto visit = [&](bool from_list, auto&& fn) {
+        const int n = from_list ? nb : w0.nsites;
+        for (int base = 0; base < n; base += PBLOCK * KSCAN) {
+            uint16_t own[KSCAN];
+            int sidx[KSCAN], widx[KSCAN], gxyz[KSCAN][3];
+#pragma unroll
+            for (int k = 0; k < KSCAN; ++k) {
+                const int j = base + k * PBLOCK + tid;
+                sidx[k] = -1;
+                widx[k] = -1;
+                own[k] = 0;
+                int i = -1;
+                if (j < n) i = from_list ? (int)lst[j] : (((bandw[j >> 5] >> (j & 31)) & 1u) ? j : -1);
+                if (i >= 0) {
+                    win_node(w0, B, i, gxyz[k][0], gxyz[k][1], gxyz[k][2]);
+                    // its index in the current window (a band node outside it is
+                    // more than a node from the body: it stays fluid)
+                    const int ox = w.whole[0] ? gxyz[k][0] : wrap(gxyz[k][0] - w.lo[0], nx);
+                    const int oy = w.whole[1] ? gxyz[k][1] : wrap(gxyz[k][1] - w.lo[1], ny);
+                    const int oz = w.whole[2] ? gxyz[k][2] : wrap(gxyz[k][2] - w.lo[2], nz);
+                    if (ox < w.wn[0] && oy < w.wn[1] && oz < w.wn[2]) {
+                        widx[k] = ox + w.wn[0] * (oy + w.wn[1] * oz);
+                        sidx[k] = gxyz[k][0] + nx * (gxyz[k][1] + ny * gxyz[k][2]);
+                        own[k] = om[sidx[k]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < KSCAN; ++k)
+                if (sidx[k] >= 0) fn(gxyz[k][0], gxyz[k][1], gxyz[k][2], sidx[k], widx[k], own[k]);
+        }
+    };
+
+    // test: the margins, and whether any node changes side
+    double mloc = 1.0;
+    bool chg = false;
+    visit(listed, [&](int gx, int gy, int gz, int s, int i1, uint16_t own) {
+        const double Qv = quad_form(xc, q, ia2, gx, gy, gz, nx, ny, nz);
+        mloc = fmin(mloc, 2.0 * fabs(Qv - 1.0) / (Qv + 3.0));
+        const bool in = Qv < 1.0;
+        chg = chg || (in ? own != me : own == me);
+    });
+    {
+        const double wm = wmin64(mloc);
+        if (lane == 0) sh.mred[wv] = wm;
+    }
+    const bool any = __syncthreads_or(chg) != 0;
+    if (tid < 9) {
+        if (tid == 0) {
+            double m = sh.mred[0];
+            for (int v = 1; v < PWAVES; ++v) m = fmin(m, sh.mred[v]);
+            const double amin = fmin(P.axes[0], fmin(P.axes[1], P.axes[2]));
+            Pg->smargin = fmin(m * amin, BAND_M - d0) * (1.0 - 1e-12);
+        } else if (tid < 4) {
+            Pg->sref[tid - 1] = P.xu[tid - 1];
+        } else if (tid < 8) {
+            Pg->qref[tid - 4] = P.q[tid - 4];
+        } else {
+            const int n3[3] = {nx, ny, nz};
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double e = w.whole[k] ? 0.5 * n3[k]
+                                            : fmax(xc[k] - w.lo[k], (double)(w.lo[k] + w.wn[k] - 1) - xc[k]);
+                r2 += e * e;
+            }
+            Pg->srho = sqrt(r2);
+        }
+    }
+    if (!any) return 0;
+
+    // some node changes side: candidate bits over the current window, this
+    // particle's nodes from the map before any change (fused path), then the
+    // changes, as scan_pass makes them
+    const int nwords = (w.nsites + 31) >> 5;
+    for (int j = tid; j < nwords; j += PBLOCK) cand[j] = 0u;
+    const bool relist = listed && !bits;  // bits overwrites the LDS the list is in
+    if (bits) bits_from_map(a, p, B, w, bits);  // ends with a barrier
+    else __syncthreads();
+    double tacc[7] = {0, 0, 0, 0, 0, 0, 0};
+    int dsol = 0;  // change of the solid count
+    bool released = false, candidate = false;
+    visit(relist, [&](int gx, int gy, int gz, int s, int i1, uint16_t own) {
+        const double Qv = quad_form(xc, q, ia2, gx, gy, gz, nx, ny, nz);
+        bool in = Qv < 1.0;
+        if (in && own == 0xFFFFu) {  // a wall node
+            atomicOr(a.flags, (int)F_OVERLAP);
+            in = false;
+        }
+        if (in && own != me) {
+            candidate = true;
+            atomicOr(&cand[i1 >> 5], 1u << (i1 & 31));
+            if (bits) atomicOr(&bits[i1 >> 5], 1u << (i1 & 31));
+            if (ep) stamp_cell(a, B, gx, gy, gz, ep);
+            ++dsol;
+        } else if (!in && own == me) {
+            released = true;
+            if (bits) atomicAnd(&bits[i1 >> 5], ~(1u << (i1 & 31)));
+            if (ep) stamp_cell(a, B, gx, gy, gz, ep);
+            --dsol;
+            // uncovered: f = f_eq(rho0, U + W x r), paid by the particle
+            const double r[3] = {minimg((double)gx - xc[0], nx), minimg((double)gy - xc[1], ny),
+                                 minimg((double)gz - xc[2], nz)};
+            const double u[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]), U[1] + (W[2] * r[0] - W[0] * r[2]),
+                                 U[2] + (W[0] * r[1] - W[1] * r[0])};
+            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            for (int j = 0; j < Q; ++j) {
+                int dir, slot;
+                double add;
+                pre_slot<Q>(a.kp.conv, B, rho0, j, gx, gy, gz, dir, slot, add);
+                const double cu = rcx(j) * u[0] + rcy(j) * u[1] + rcz(j) * u[2];
+                const double dev = (rw<Q>(j) / (double)WSCALE<Q>) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                S::st64(f + (long long)dir * st + slot, dev - add, scl);
+            }
+            const double pu[3] = {rho0 * u[0], rho0 * u[1], rho0 * u[2]};
+            tacc[1] -= pu[0];
+            tacc[2] -= pu[1];
+            tacc[3] -= pu[2];
+            tacc[4] -= r[1] * pu[2] - r[2] * pu[1];
+            tacc[5] -= r[2] * pu[0] - r[0] * pu[2];
+            tacc[6] -= r[0] * pu[1] - r[1] * pu[0];
+            release_node(om, s);
+        }
+    });
+    const bool anycand = __syncthreads_or(candidate) != 0;
+    const bool changed = anycand || __syncthreads_or(released) != 0;
+    if (changed) {
+        block_reduce<7>(tacc, red);
+        const int sm = wsumi(dsol);
+        if (lane == 0) ired[7][wv] = sm;
+        __syncthreads();
+        if (tid == 44) {
+            int ds = 0;
+            for (int v = 0; v < PWAVES; ++v) ds += ired[7][v];
+            const int ns = P.n_solid + ds;
+            if (ns != P.n_solid) atomicAdd(&a.rt[P.box].n_solid, ns - P.n_solid);
+            Pg->n_solid = ns;
+            P.n_solid = ns;
+        } else if (tid >= 37 && tid < 44) {
             const int k = tid - 37;  // dm, Pp[3], Lp[3]
             double* fld = k == 0 ? &P.dm : (k < 4 ? &P.Pp[k - 1] : &P.Lp[k - 4]);
             double* gfld = k == 0 ? &Pg->dm : (k < 4 ? &Pg->Pp[k - 1] : &Pg->Lp[k - 4]);
@@ -1263,36 +1607,6 @@ __device__ __forceinline__ void claim_pass(const LaunchPart& a, int p, PartDev& 
     __syncthreads();
 }
 
-// This particle's nodes over the window, as window bits, from the node map.
-__device__ __forceinline__ void bits_from_map(const LaunchPart& a, int p, const BoxDesc& B, const Win& w, uint32_t* bits) {
-    const uint16_t* om = a.omap + B.ooff;
-    const uint16_t me = (uint16_t)(p + 1);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int base = 0; base < w.nsites; base += PBLOCK * KSCAN) {
-        bool in[KSCAN];
-#pragma unroll
-        for (int k = 0; k < KSCAN; ++k) {
-            const int i = base + k * PBLOCK + tid;
-            in[k] = false;
-            if (i < w.nsites) {
-                int gx, gy, gz;
-                win_node(w, B, i, gx, gy, gz);
-                in[k] = om[gx + B.nx * (gy + B.ny * gz)] == me;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < KSCAN; ++k) {
-            if (base + k * PBLOCK >= w.nsites) break;  // uniform over the block
-            const unsigned long long m = __ballot(in[k]);
-            if (lane == 0) {
-                const int w0 = (base + k * PBLOCK + wv * 64) >> 5;
-                bits[w0] = (uint32_t)m;
-                bits[w0 + 1] = (uint32_t)(m >> 32);
-            }
-        }
-    }
-    __syncthreads();
-}
 
 // Pass 2: the boundary links (fluid x, x + c_b solid of this particle; bits
 // holds this particle's nodes over the window), staged in LDS and written in
@@ -1539,7 +1853,12 @@ __device__ __forceinline__ void remap_phase(const LaunchPart& a, int p, PartDev&
     // an added particle stamps the cells it claims (with the set-up epoch),
     // so that only the particles whose window meets its nodes rebuild links
     const uint32_t ep = (mode == 1 && a.epoch) ? *a.epoch : 0u;
-    const int res = scan_pass<ST, Q>(a, p, P, B, w, bits, cand, sh, ep);
+    double d0 = 0.0;
+    // the band's list may take the whole of this kernel's LDS (bits, stage)
+    // until a change needs the bits
+    const int res = (mode == 0 && a.use_band && band_ok(P, d0))
+                        ? band_pass<ST, Q>(a, p, P, B, w, bits, cand, smem, band_list_cap(a.lds_words), sh, 0u, d0)
+                        : scan_pass<ST, Q>(a, p, P, B, w, bits, cand, sh, ep);
     if (mode == 2) {
         if (threadIdx.x == 0) a.parts[p].nlinks = 0;
         return;
@@ -1598,6 +1917,7 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_step(LaunchPart a) {
 //    this particle's area of a.cand), stamps of the cells where owners change.
 template <int ST, int Q>
 __global__ __launch_bounds__(PBLOCK) void k_particle_solve_map(LaunchPart a) {
+    extern __shared__ uint32_t smem[];  // the band's list
     __shared__ PartDev P;
     __shared__ union {
         SolveShm s;
@@ -1612,8 +1932,13 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_solve_map(LaunchPart a) {
     const BoxDesc& B = a.boxes[P.box];
     Win w;
     int res = 0;
-    if (window_of(a, P, B, w) && scan_needed(P))
-        res = scan_pass<ST, Q>(a, p, P, B, w, nullptr, a.cand + (size_t)p * a.lds_words, sh.r, *a.epoch);
+    if (window_of(a, P, B, w) && scan_needed(P)) {
+        double d0 = 0.0;
+        uint32_t* cand = a.cand + (size_t)p * a.lds_words;
+        res = (a.use_band && band_ok(P, d0))
+                  ? band_pass<ST, Q>(a, p, P, B, w, nullptr, cand, smem, band_list_cap(a.lds_words), sh.r, *a.epoch, d0)
+                  : scan_pass<ST, Q>(a, p, P, B, w, nullptr, cand, sh.r, *a.epoch);
+    }
     if (threadIdx.x == 0) {
         Pg->nchg = res & 1;
         Pg->ncand = (res >> 1) & 1;
@@ -1690,7 +2015,8 @@ size_t particle_remap_lds_bytes(int lds_words) {
 template <int ST, int Q>
 struct SolveMapK {
     static void go(const LaunchPart& a, hipStream_t st) {
-        hipLaunchKernelGGL((k_particle_solve_map<ST, Q>), dim3(a.count), dim3(PBLOCK), 0, st, a);
+        hipLaunchKernelGGL((k_particle_solve_map<ST, Q>), dim3(a.count), dim3(PBLOCK),
+                           particle_remap_lds_bytes(a.lds_words), st, a);
     }
 };
 template <int ST, int Q>

@@ -31,7 +31,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t f0 = 0, f1 = 0, omap = 0, boxes = 0, rt = 0, tile_box = 0, box_init = 0, parts = 0, links = 0,
            flags = 0, scratch = 0, near_flags = 0, near_list = 0, near_count = 0, warm = 0, step_ctr = 0,
-           stamps = 0, cand = 0, mon = 0, total = 0;
+           stamps = 0, cand = 0, band = 0, mon = 0, total = 0;
     long long cells = 0;  // owner-change stamp cells over all boxes
     int near_blocks = 0;  // collide-stream blocks that a near set can name (per slot)
     std::vector<long long> foff, stride, ooff, coff;
@@ -150,6 +150,8 @@ Layout make_layout(const lb_config* c, int nboxes, const lb_box* boxes) {
     // nodes, and each particle's remap claim candidates (one window bitmask)
     L.stamps = take(sizeof(uint32_t) * (size_t)L.cells);
     L.cand = take(sizeof(uint32_t) * (size_t)L.max_particles * L.lds_words);
+    // the narrow band of each particle's last full remap scan (a window bitmask)
+    L.band = take(sizeof(uint32_t) * (size_t)L.max_particles * L.lds_words);
     // warm-start monitor: a record per box, each particle's velocity at the
     // last check (6 doubles), a flow-energy partial per tile
     L.mon = take(sizeof(BoxMon) * nboxes + sizeof(double) * (6 * (size_t)L.max_particles + tiles));
@@ -195,6 +197,7 @@ struct lb_ctx {
     // queue behind the streaming kernel; LBELL_OVERLAP=1 turns it on)
     bool overlap = false;
     bool fused = true;  // one particle kernel per step when no box holds two particles (LBELL_FUSED=0: two kernels)
+    bool use_band = true;  // remap rescans within the narrow band test only its nodes (LBELL_BAND=0: full scans)
     int opb_np = -1;    // particle count for which opb was computed
     bool opb = true;    // no box holds two particles
     hipStream_t nstream = nullptr;
@@ -306,6 +309,8 @@ LaunchPart part_launch(lb_ctx* ctx, int first, int count, int mode) {
     a.epoch = ctx->at<uint32_t>(ctx->L.step_ctr) + ctx->cur;
     a.cand = ctx->at<uint32_t>(ctx->L.cand);
     a.force_box = -1;
+    a.band = ctx->at<uint32_t>(ctx->L.band);
+    a.use_band = ctx->use_band ? 1 : 0;
     return a;
 }
 
@@ -532,6 +537,7 @@ lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes, void* d
     }
     if (const char* v = std::getenv("LBELL_OVERLAP")) ctx->overlap = std::atoi(v) != 0;
     if (const char* v = std::getenv("LBELL_FUSED")) ctx->fused = std::atoi(v) != 0;
+    if (const char* v = std::getenv("LBELL_BAND")) ctx->use_band = std::atoi(v) != 0;
     if (const char* v = std::getenv("LBELL_K1_VARIANT")) {
         if (!k1_applicable(ctx, std::atoi(v))) {
             std::fprintf(stderr, "lb_init: LBELL_K1_VARIANT=%s does not apply to these boxes\n", v);
@@ -1230,7 +1236,7 @@ namespace {
 // 3: the particle record carries the previous orientation and the remap
 // skip reference, and no drag matrix (rebuilt from the link moments);
 // 4: and the remap change flags of boxes with several particles
-constexpr int CKPT_VERSION = 4;
+constexpr int CKPT_VERSION = 5;
 struct CkptHeader {
     char magic[8];
     int version, nboxes, storage, np, cur, pad;  // version: CKPT_VERSION
@@ -1309,7 +1315,15 @@ lb_status lb_load(lb_ctx* ctx, const char* path) {
     load(ctx->fbuf(ctx->cur), (size_t)h.pop_elems * es);
     load(ctx->at<char>(ctx->L.omap), (size_t)h.omap_elems * sizeof(uint16_t));
     load(ctx->at<char>(ctx->L.rt), sizeof(BoxRT) * ctx->boxes.size());
-    load(ctx->at<char>(ctx->L.parts), sizeof(PartDev) * h.np);
+    {   // the particle records; their narrow bands are not part of a checkpoint
+        std::vector<PartDev> parts((size_t)h.np);
+        if (ok && h.np && std::fread(parts.data(), sizeof(PartDev), h.np, fp) != (size_t)h.np) ok = false;
+        for (auto& P : parts) P.bvalid = 0;
+        if (ok && h.np &&
+            hipMemcpy(ctx->at<PartDev>(ctx->L.parts), parts.data(), sizeof(PartDev) * h.np, hipMemcpyHostToDevice) !=
+                hipSuccess)
+            ok = false;
+    }
     load(ctx->at<char>(ctx->L.links), sizeof(uint32_t) * h.link_used);
     if (ok) ok = std::fread(ctx->hpart.data(), sizeof(PartHost), h.np, fp) == (size_t)h.np;
     std::fclose(fp);

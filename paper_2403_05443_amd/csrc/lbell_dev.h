@@ -12,6 +12,7 @@ constexpr int PBLOCK = 512;      // threads per particle work-group
 constexpr int PWAVES = PBLOCK / 64;
 constexpr int KREG = 2;          // links per thread held in registers across phases
 constexpr int KOVF = 4;          // links past those whose loads one thread issues together
+constexpr double BAND_M = 1.0;   // narrow band of the remap scan: nodes within this margin (lattice units)
 constexpr int KSCAN = 4;         // window sites per thread whose node-map loads the solid scan issues together
 constexpr int STAGE = 4096;      // link codes staged in LDS per copy-out round
 constexpr int SITE_BITS = 27;    // link code: site | dir << 27
@@ -134,6 +135,12 @@ struct PartDev {
     // the smallest distance-like margin of its nodes to the surface and the
     // largest distance of its nodes from the centre (remap skip test)
     double sref[3], qref[4], smargin, srho;
+    // narrow band of the last full test: the pose it was taken at, its
+    // window (origin, edges) and the largest distance of that window's nodes
+    // from the centre; the band itself (window nodes whose margin was below
+    // BAND_M) is a bitmask over that window in the band area
+    double bref[3], bqref[4], bsrho;
+    int blo[3], bwn[3], bvalid, bpad;
     double dm, Pp[3], Lp[3];  // pending mass / momentum / angular momentum of transitions
     double F[3], T[3];    // hydrodynamic force and torque of the last step
     double wsum;          // sum of w_b over the current links

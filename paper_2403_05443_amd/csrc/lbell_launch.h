@@ -78,6 +78,8 @@ struct LaunchPart {
     const uint32_t* epoch;   // this step's epoch (the device step counter after the collide launch)
     uint32_t* cand;          // claim candidates, lds_words bit words per particle
     int force_box;           // links: >= 0 rebuild every particle of this box (set-up), else -1
+    uint32_t* band;          // narrow band of each particle's last full scan, lds_words bit words per particle
+    int use_band;            // rescans within the band test only its nodes (0: every scan is full)
 };
 
 hipError_t launch_particle_remap(const LaunchPart& a, hipStream_t st);
