@@ -142,9 +142,14 @@ size_t lb_arena_bytes(const lb_config* cfg, int nboxes, const lb_box* boxes);
  * and kept alive until lb_destroy.  hip_stream: the hipStream_t all work is
  * enqueued on (NULL = the default stream).  Populations are initialised to
  * f_eq(rho0, u0) with u0 = 0, or the wall-driven Couette profile (init = 1),
- * including its first-order non-equilibrium part.  The environment variable
- * LBELL_K1_VARIANT picks the initial collide-stream variant (see
- * lb_autotune).  Synchronises the stream. */
+ * including its first-order non-equilibrium part.  Environment variables
+ * read here: LBELL_K1_VARIANT picks the initial collide-stream variant (see
+ * lb_autotune); LBELL_FUSED=0 runs boxes that hold one particle through the
+ * three-kernel particle phase as well; LBELL_BAND=0 makes every remap rescan
+ * test the particle's whole window (by default a rescan between full tests
+ * tests only the nodes the last full test found within one node of the
+ * surface; the results are the same); LBELL_OVERLAP=1 selects the
+ * two-stream schedule.  Synchronises the stream. */
 lb_status lb_init(const lb_config* cfg, int nboxes, const lb_box* boxes,
                   void* dev_arena, size_t arena_bytes, void* hip_stream,
                   lb_ctx** out);
