@@ -255,7 +255,7 @@ def measure(W, steps, warmup, graph_steps, variant=None, psteps=200):
     k1 = ms_c / n
     alg = 2 * W.lattice * BYTES[W.storage] * W.sites  # Q reads + Q writes per site
     # population memory a step touches: one buffer in place (variants 11-14), two otherwise
-    ws = W.lattice * BYTES[W.storage] * W.sites * (1 if variant >= 11 else 2)
+    ws = W.lattice * BYTES[W.storage] * W.sites * (1 if 11 <= variant <= 14 else 2)
     return lat, {
         "mlups": W.sites * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps, "wall_s": wall,
         "variant": variant, "k1_ms": k1, "alg_bytes": alg, "achieved_gbs": alg / (k1 / 1e3) / 1e9,

@@ -218,7 +218,9 @@ lb_status lb_profile_step(lb_ctx* ctx, int n, double* ms_collide, double* ms_par
  *      and scatter to the neighbours); half the population memory
  *  12  in place, XCD-chunked     13  in place, two tiles per block, XCD-chunked
  *  14  in place, XCD-chunked, non-temporal stores
- * Moving between the two-buffer variants (0-10) and the in-place ones
+ *  15  generic, XCD-grouped block order (each XCD takes groups of 16
+ *      consecutive tiles, the XCDs' groups alternating), non-temporal stores
+ * Moving between the two-buffer variants (0-10, 15) and the in-place ones
  * (11-14) permutes the stored populations into the other layout exactly.
  * With the two-stream schedule only 0-2 apply.  All variants give identical
  * bits, so the 2 x (applicable variants) x (reps + 2) steps the tuner takes

@@ -23,6 +23,8 @@
 
 namespace lbd {
 
+constexpr int XGROUP = 16;  // virtual blocks per XCD group of the grouped block order
+
 template <int ST, int Q>
 struct Pull {
     using S = Store<ST>;
@@ -286,16 +288,20 @@ __device__ __forceinline__ void site_update(const BoxDesc* __restrict__ boxes, c
 }
 
 // Generic tile kernel over every box of the context.  A virtual block covers
-// SPT consecutive 256-site tiles (one site per thread and tile).  Block order:
-// with XCD, the grid is 8 * m blocks and the virtual blocks are cut into 8
-// contiguous ranges, range k walked by the blocks with blockIdx % 8 == k (the
-// hardware deals consecutive blocks out to the 8 XCDs in turn, so neighbouring
-// tiles, which share cache lines at their edges, meet in one XCD's L2); a grid
-// smaller than the work (persistent launch) walks its range in strides of m.
-// Without XCD, block b takes virtual blocks b, b + grid, ...  NT: stores that
+// SPT consecutive 256-site tiles (one site per thread and tile).  Block order
+// (the hardware deals consecutive blocks out to the 8 XCDs in turn, and
+// neighbouring tiles share cache lines at their edges, which one XCD's L2
+// serves once): XCD = 1, the grid is 8 * m blocks and the virtual blocks are
+// cut into 8 contiguous ranges, range k walked by the blocks with
+// blockIdx % 8 == k (a grid smaller than the work, a persistent launch, walks
+// its range in strides of m); XCD = 2, the blocks of XCD k take groups of
+// XGROUP consecutive virtual blocks, and the groups of the 8 XCDs alternate,
+// so the sweep keeps the plain order at the scale of 8 XGROUP blocks while
+// most tile edges stay within one L2.  XCD = 0: block b takes virtual blocks
+// b, b + grid, ...  NT: stores that
 // do not allocate in the caches.  The near-set parts (part 1, 2) use SPT = 1
 // and the plain order only.
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int Q>
+template <int ST, int COLL, bool WALLS, int SPT, int XCD, bool NT, int Q>
 __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restrict__ boxes,
                                                          const BoxRT* __restrict__ rt,
                                                          const int* __restrict__ tile_box,
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
         if (next_count) *next_count = 0;
         *step_out = step + 1;  // the other parity's slot, read by the next step
     }
-    if (SPT == 1 && !XCD && part != 0) {
+    if (SPT == 1 && XCD == 0 && part != 0) {
         int tile = blockIdx.x;
         if (part == 2) {
             if (tile >= *ncount) return;
@@ -325,20 +331,27 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
     }
     const int nvb = (ntiles + SPT - 1) / SPT;
     int v, vend, vstep;
-    if (XCD) {
+    if (XCD == 1) {
         const int m = (int)gridDim.x >> 3, chunk = (nvb + 7) >> 3, k = (int)(blockIdx.x & 7);
         v = k * chunk + (int)(blockIdx.x >> 3);
         vend = min(nvb, (k + 1) * chunk);
         vstep = m;
+    } else if (XCD == 2) {
+        // walks this XCD's local index J; v(J) = groups of XGROUP, XCDs interleaved
+        v = (int)(blockIdx.x >> 3);
+        vend = ((nvb + 8 * XGROUP - 1) / (8 * XGROUP)) * XGROUP;
+        vstep = (int)gridDim.x >> 3;
     } else {
         v = blockIdx.x;
         vend = nvb;
         vstep = gridDim.x;
     }
     for (; v < vend; v += vstep) {
+        const int vb = XCD == 2 ? (v / XGROUP) * (8 * XGROUP) + (int)(blockIdx.x & 7) * XGROUP + v % XGROUP : v;
+        if (XCD == 2 && vb >= nvb) continue;
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
-            const int tile = v * SPT + k;
+            const int tile = vb * SPT + k;
             if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CV_PULL, CV_PULL, Q>(boxes, tile_box, fin, fout, kp, tile, step);
         }
     }
@@ -349,7 +362,7 @@ __global__ __launch_bounds__(TILE) void k_collide_stream(const BoxDesc* __restri
 // and scatter to the neighbours).  Every slot is read and written by one
 // thread only, so no block depends on another.  Block order as the generic
 // kernel's; wall rows are not updated.
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int CIN, int Q>
+template <int ST, int COLL, bool WALLS, int SPT, int XCD, bool NT, int CIN, int Q>
 __global__ __launch_bounds__(TILE) void k_collide_stream_aa(const BoxDesc* __restrict__ boxes,
                                                             const int* __restrict__ tile_box,
                                                             typename Store<ST>::T* __restrict__ f, KParams kp,
@@ -360,20 +373,27 @@ __global__ __launch_bounds__(TILE) void k_collide_stream_aa(const BoxDesc* __res
     if (blockIdx.x == 0 && threadIdx.x == 0) *step_out = step + 1;
     const int nvb = (ntiles + SPT - 1) / SPT;
     int v, vend, vstep;
-    if (XCD) {
+    if (XCD == 1) {
         const int m = (int)gridDim.x >> 3, chunk = (nvb + 7) >> 3, k = (int)(blockIdx.x & 7);
         v = k * chunk + (int)(blockIdx.x >> 3);
         vend = min(nvb, (k + 1) * chunk);
         vstep = m;
+    } else if (XCD == 2) {
+        // walks this XCD's local index J; v(J) = groups of XGROUP, XCDs interleaved
+        v = (int)(blockIdx.x >> 3);
+        vend = ((nvb + 8 * XGROUP - 1) / (8 * XGROUP)) * XGROUP;
+        vstep = (int)gridDim.x >> 3;
     } else {
         v = blockIdx.x;
         vend = nvb;
         vstep = gridDim.x;
     }
     for (; v < vend; v += vstep) {
+        const int vb = XCD == 2 ? (v / XGROUP) * (8 * XGROUP) + (int)(blockIdx.x & 7) * XGROUP + v % XGROUP : v;
+        if (XCD == 2 && vb >= nvb) continue;
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
-            const int tile = v * SPT + k;
+            const int tile = vb * SPT + k;
             if (tile < ntiles) site_update<ST, COLL, WALLS, NT, CIN, COUT, Q>(boxes, tile_box, f, f, kp, tile, step);
         }
     }
@@ -772,7 +792,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int block
             hipLaunchKernelGGL(KERNEL, G, B, 0, ST, __VA_ARGS__);                          \
     } while (0)
 
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int Q>
+template <int ST, int COLL, bool WALLS, int SPT, int XCD, bool NT, int Q>
 static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
     const int nvb = (a.ntiles + SPT - 1) / SPT;
@@ -787,7 +807,7 @@ static hipError_t cs_one(const LaunchCS& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int ST, int COLL, bool WALLS, int SPT, bool XCD, bool NT, int Q>
+template <int ST, int COLL, bool WALLS, int SPT, int XCD, bool NT, int Q>
 static hipError_t aa_one(const LaunchCS& a, hipStream_t st) {
     using T = typename Store<ST>::T;
     const int nvb = (a.ntiles + SPT - 1) / SPT;
@@ -808,35 +828,36 @@ static hipError_t aa_one(const LaunchCS& a, hipStream_t st) {
 // or in place); the tuner offers no other.
 template <int ST, int COLL, bool WALLS, int Q>
 static hipError_t cs_shape(const LaunchCS& a, hipStream_t st) {
-    const int key = a.spt * 4 + (a.xcd ? 2 : 0) + (a.nt ? 1 : 0);
+    const int key = a.spt * 8 + a.xcd * 2 + (a.nt ? 1 : 0);  // xcd: 0 plain, 1 chunked, 2 grouped
     if constexpr (Q == 27) {
         if (a.part != 0) return hipErrorInvalidValue;
         switch (key) {
-            case 4: return a.aa ? aa_one<ST, COLL, WALLS, 1, false, false, Q>(a, st)
-                                : cs_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
-            case 6: return a.aa ? aa_one<ST, COLL, WALLS, 1, true, false, Q>(a, st)
-                                : cs_one<ST, COLL, WALLS, 1, true, false, Q>(a, st);
+            case 8: return a.aa ? aa_one<ST, COLL, WALLS, 1, 0, false, Q>(a, st)
+                                : cs_one<ST, COLL, WALLS, 1, 0, false, Q>(a, st);
+            case 10: return a.aa ? aa_one<ST, COLL, WALLS, 1, 1, false, Q>(a, st)
+                                 : cs_one<ST, COLL, WALLS, 1, 1, false, Q>(a, st);
             default: return hipErrorInvalidValue;
         }
     } else {
         if (a.aa) {
             switch (key) {
-                case 4: return aa_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
-                case 6: return aa_one<ST, COLL, WALLS, 1, true, false, Q>(a, st);
-                case 7: return aa_one<ST, COLL, WALLS, 1, true, true, Q>(a, st);
-                case 10: return aa_one<ST, COLL, WALLS, 2, true, false, Q>(a, st);
+                case 8: return aa_one<ST, COLL, WALLS, 1, 0, false, Q>(a, st);
+                case 10: return aa_one<ST, COLL, WALLS, 1, 1, false, Q>(a, st);
+                case 11: return aa_one<ST, COLL, WALLS, 1, 1, true, Q>(a, st);
+                case 18: return aa_one<ST, COLL, WALLS, 2, 1, false, Q>(a, st);
                 default: return hipErrorInvalidValue;
             }
         }
-        if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
+        if (a.part != 0) return cs_one<ST, COLL, WALLS, 1, 0, false, Q>(a, st);
         switch (key) {
-            case 4: return cs_one<ST, COLL, WALLS, 1, false, false, Q>(a, st);
-            case 6: return cs_one<ST, COLL, WALLS, 1, true, false, Q>(a, st);
-            case 7: return cs_one<ST, COLL, WALLS, 1, true, true, Q>(a, st);
-            case 8: return cs_one<ST, COLL, WALLS, 2, false, false, Q>(a, st);
-            case 10: return cs_one<ST, COLL, WALLS, 2, true, false, Q>(a, st);
-            case 11: return cs_one<ST, COLL, WALLS, 2, true, true, Q>(a, st);
-            case 18: return cs_one<ST, COLL, WALLS, 4, true, false, Q>(a, st);
+            case 8: return cs_one<ST, COLL, WALLS, 1, 0, false, Q>(a, st);
+            case 10: return cs_one<ST, COLL, WALLS, 1, 1, false, Q>(a, st);
+            case 11: return cs_one<ST, COLL, WALLS, 1, 1, true, Q>(a, st);
+            case 13: return cs_one<ST, COLL, WALLS, 1, 2, true, Q>(a, st);
+            case 16: return cs_one<ST, COLL, WALLS, 2, 0, false, Q>(a, st);
+            case 18: return cs_one<ST, COLL, WALLS, 2, 1, false, Q>(a, st);
+            case 19: return cs_one<ST, COLL, WALLS, 2, 1, true, Q>(a, st);
+            case 34: return cs_one<ST, COLL, WALLS, 4, 1, false, Q>(a, st);
             default: return hipErrorInvalidValue;
         }
     }

@@ -235,7 +235,7 @@ namespace {
 struct K1Shape {
     int kind;      // 0 generic tiles, 1 row-wave, 2 row-wave with non-temporal stores
     int spt;       // tiles per block (generic)
-    bool xcd;      // XCD-chunked block order (generic)
+    int xcd;       // block order (generic): 0 plain, 1 XCD-chunked, 2 XCD-grouped
     bool persist;  // grid of a few blocks per CU walking the tiles (generic)
     bool nt;       // non-temporal stores (generic)
     bool aa;       // in place (generic)
@@ -246,7 +246,7 @@ constexpr K1Shape K1_SHAPES[] = {
     {0, 1, true, true, false, false},   {0, 2, true, true, false, false},   {0, 4, true, false, false, false},
     {0, 1, true, false, true, false},   {0, 2, true, false, true, false},
     {0, 1, false, false, false, true},  {0, 1, true, false, false, true},   {0, 2, true, false, false, true},
-    {0, 1, true, false, true, true},
+    {0, 1, true, false, true, true},   {0, 1, 2, false, true, false},
 };
 constexpr int K1_NSHAPES = (int)(sizeof(K1_SHAPES) / sizeof(K1_SHAPES[0]));
 

@@ -16,7 +16,7 @@ struct LaunchCS {
     int variant;            // 0 generic tiles, 1 row-wave, 2 row-wave with non-temporal stores
     bool aa;                // generic tiles in place on fin (== fout); kp.conv says even or odd step
     int spt;                // generic tiles: 256-site tiles per block (1 or 2)
-    bool xcd;               // generic tiles: XCD-chunked block order
+    int xcd;                // generic tiles: block order, 0 plain, 1 XCD-chunked, 2 XCD-grouped
     bool nt;                // generic tiles: non-temporal stores
     int grid;               // generic tiles: blocks launched (0 = one per block of tiles; fewer = persistent)
     int rows_k;             // sites per lane of the row-wave kernel (nx = 64 rows_k), 0 = not applicable

@@ -13,8 +13,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-# generic tile shapes: pull (0, 3-10) and in place (11-14)
-GENERIC = (0, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14)
+# generic tile shapes: pull (0, 3-10, 15) and in place (11-14)
+GENERIC = (0, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15)
 
 
 @pytest.fixture(scope="module")
@@ -75,12 +75,12 @@ def test_generic_tile_shapes_bitwise(lb, storage):
 
 
 def test_all_variants_single_box_bitwise(lb):
-    """On a box the row-wave kernel also fits (nx = 128) all fifteen variants
+    """On a box the row-wave kernel also fits (nx = 128) all sixteen variants
     agree."""
     spec = [((128, 20, 18), (60.3, 9.6, 8.7), (6, 2.5, 2), (0.8, 0.3, -0.4, 0.33))]
     ref = _batch(lb, "fp32", 0, spec)
     ref.step(30)
-    for v in range(1, 15):
+    for v in range(1, 16):
         g = _batch(lb, "fp32", v, spec)
         g.step(30)
         _same(g, ref, 1)

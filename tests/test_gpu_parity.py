@@ -511,7 +511,7 @@ def test_autotune_keeps_state(lb):
     h.step(10)
     t0 = g.step_count()
     v, ms = g.autotune(5)
-    assert v in range(15) and ms > 0
+    assert v in range(16) and ms > 0
     h.step(g.step_count() - t0)  # the tuner's timed steps are ordinary steps
     g.step(10)
     h.step(10)
