@@ -1965,8 +1965,12 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_claim(LaunchPart a) {
 //    particle was added to that box at set-up, a.epoch then pointing at the
 //    add's own epoch): the particles of that box whose window meets the
 //    added particle's nodes.
+// At most 128 VGPRs (four waves per SIMD): two work-groups per compute unit,
+// so that the rebuilding work-groups of a large suspension are not queued
+// behind one another (five values spill: six scratch stores and four
+// reloads per thread, none in a loop).
 template <int Q>
-__global__ __launch_bounds__(PBLOCK) void k_particle_links(LaunchPart a) {
+__global__ __launch_bounds__(PBLOCK, 4) void k_particle_links(LaunchPart a) {
     extern __shared__ uint32_t smem[];
     __shared__ PartDev P;
     __shared__ RemapShm sh;
