@@ -207,28 +207,129 @@ def stokes_velocity(d, U, W, R):
     return np.where(r >= R, out, rigid)
 
 
+# Below this eccentricity a prolate spheroid's flow is taken as the sphere's
+# (they differ by O(e^2)).
+E_LINE = 1e-4
+
+
+def _gl_panels(x0, delta, lo, hi, npt=16, ratio=2.0):
+    """Nodes and weights of a composite Gauss-Legendre rule on [lo, hi]
+    (lo <= x0 <= hi) whose panels grow geometrically away from x0: panel j
+    on each side spans distances delta (ratio^j - 1) .. delta (ratio^(j+1) -
+    1) from x0, clipped to the interval.  Arrays over leading dimensions of
+    x0 / delta; returns (xi, w) with a trailing node axis."""
+    t, wt = np.polynomial.legendre.leggauss(npt)
+    span = np.maximum(np.max(np.maximum(x0 - lo, hi - x0) / delta), 1.0)
+    J = int(math.ceil(math.log(1.0 + span) / math.log(ratio))) + 1
+    xs, ws = [], []
+    for j in range(J):
+        d0, d1 = delta * (ratio ** j - 1.0), delta * (ratio ** (j + 1) - 1.0)
+        for sgn, end in ((-1.0, lo), (1.0, hi)):
+            room = np.abs(end - x0)
+            a, b = np.minimum(d0, room), np.minimum(d1, room)
+            half, mid = 0.5 * (b - a), 0.5 * (b + a)
+            xs.append(x0[..., None] + sgn * (mid[..., None] + half[..., None] * t))
+            ws.append(half[..., None] * wt)
+    return np.concatenate(xs, axis=-1), np.concatenate(ws, axis=-1)
+
+
+def spheroid_flow(d, axes, q, F, T, mu):
+    """Creeping flow of an unbounded fluid around a rigid prolate spheroid
+    (semi-axes a > b = c, orientation q) under the load (F, T), at offsets
+    d (n, 3) from its centre; rigid motion inside.
+
+    The body moves with the velocities of the resistance functions
+    (unbounded_velocities).  Outside, the flow is that of singularities on
+    the focal segment |xi| <= f = a e of the axis p (Chwang & Wu, J. Fluid
+    Mech. 63, 1974, and 67, 1975), with g = f^2 - xi^2, r = d - xi p, R = |r|,
+    s = F / (16 pi mu f), t = T / (8 pi mu (4/3) f^3), t_c the part of t
+    across p and m = t_c x p:
+      Stokeslets            s / R + (s.r) r / R^3,
+      potential dipoles     -(1 - e^2) / (2 e^2) g (-s / R^3 + 3 (s.r) r / R^5),
+      rotlets               g t x r / R^3,
+      stresslets            3 e^2 / (2 - e^2) g r (r.p)(r.m) / R^5,
+      potential quadrupoles (1 - e^2) / (4 (2 - e^2)) g^2 (p.grad_r) of the
+                            dipole -m / R^3 + 3 (m.r) r / R^5,
+    integrated over xi by composite Gauss-Legendre quadrature on panels that
+    grow geometrically from the point of the segment nearest d."""
+    d = np.atleast_2d(np.asarray(d, float))
+    a, b, _ = axes
+    e2 = 1.0 - (b / a) ** 2
+    e = math.sqrt(e2)
+    f = a * e
+    U, W = unbounded_velocities(axes, q, F, T, mu)
+    p = rotmat(q)[:, 0]
+    F, T = np.asarray(F, float), np.asarray(T, float)
+    s = F / (16 * math.pi * mu * f)
+    t = T / (8 * math.pi * mu * 4.0 / 3.0 * f ** 3)
+    m = np.cross(t - (t @ p) * p, p)
+    z = d @ p
+    rho2 = np.maximum((d * d).sum(1) - z * z, 0.0)
+    inside = z * z / (a * a) + rho2 / (b * b) < 1.0
+    x0 = np.clip(z, -f, f)
+    delta = np.sqrt(rho2 + (z - x0) ** 2)
+    out = U + np.cross(W, d)
+    o = ~inside
+    if o.any():
+        xi, w = _gl_panels(x0[o], delta[o], -f, f)
+        r = d[o][:, None, :] - xi[..., None] * p                      # (n, k, 3)
+        R = np.sqrt((r * r).sum(-1))[..., None]
+        g = (f * f - xi * xi)[..., None]
+        rp = (r @ p)[..., None]
+        rm = (r @ m)[..., None]
+        sr = (r @ s)[..., None]
+        val = (s / R + sr * r / R ** 3
+               - (1 - e2) / (2 * e2) * g * (-s / R ** 3 + 3 * sr * r / R ** 5)
+               + g * np.cross(t, r) / R ** 3
+               + 3 * e2 / (2 - e2) * g * r * rp * rm / R ** 5
+               + (1 - e2) / (4 * (2 - e2)) * g * g * (3 * (m * rp + rm * p) / R ** 5 - 15 * rm * rp * r / R ** 7))
+        out[o] = (w[..., None] * val).sum(1)
+    return out
+
+
+def particle_flow(d, p, mu):
+    """Free-space flow that particle p (dict: axes, q, F, T) drives at
+    offsets d: spheroid_flow for a prolate spheroid (a > b = c, eccentricity
+    at least E_LINE); otherwise the sphere of the equal-volume radius R moving
+    with F / (6 pi mu R) and turning with T / (8 pi mu R^3) (stokes_velocity)."""
+    a, b, c = p["axes"]
+    F, T = np.asarray(p["F"], float), np.asarray(p["T"], float)
+    if a > b and b == c and 1.0 - (b / a) ** 2 >= E_LINE ** 2:
+        return spheroid_flow(d, p["axes"], p["q"], F, T, mu)
+    R = req(p["axes"])
+    return stokes_velocity(d, F / (6 * math.pi * mu * R), T / (8 * math.pi * mu * R ** 3), R)
+
+
 KMAX = 2  # Fourier modes |n_i| <= KMAX of the box carry the periodic correction
 
 
-def periodic_modes(k, F, T, R, mu, V):
+def periodic_modes(k, F, T, R, mu, V, axes=None, q=None):
     """Fourier coefficients (1/V) u_hat(k) of the creeping flow driven by a
     force F and a torque T spread over a sphere of radius R (uniform surface
     traction), at wave vectors k (m, 3), none zero, for a periodic box of
     volume V, centre at the origin:
-      u_hat = (I - k k / k^2) F sinc(kR) / (mu k^2) + i (k x T) [3 j1(kR) / (kR)] / (2 mu k^2)."""
+      u_hat = (I - k k / k^2) F sinc(kR) / (mu k^2) + i (k x T) [3 j1(kR) / (kR)] / (2 mu k^2).
+    With the semi-axes and orientation of an ellipsoid, the force is spread
+    as the traction on that ellipsoid translating (the sphere's uniform layer
+    mapped by diag(a, b, c) in the body frame), whose transform is
+    sinc(|diag(a, b, c) R(q)^T k|); the torque stays on the sphere R."""
     k = np.atleast_2d(np.asarray(k, float))
     F, T = np.asarray(F, float), np.asarray(T, float)
     k2 = (k * k).sum(1)
     x = np.sqrt(k2) * R
-    sinc = np.sin(x) / x
+    if axes is None:
+        sinc = np.sin(x) / x
+    else:
+        xa = np.linalg.norm((k @ rotmat(q)) * np.asarray(axes, float), axis=1)
+        sinc = np.sin(xa) / xa
     j1f = 3 * (np.sin(x) / x - np.cos(x)) / (x * x)   # 3 j1(x) / x, 1 at x -> 0
     Pf = F[None, :] - k * ((k @ F) / k2)[:, None]
     return (Pf * (sinc / (mu * k2))[:, None] + 1j * np.cross(k, T) * (j1f / (2 * mu * k2))[:, None]) / V
 
 
-def periodic_coefficients(shape, centre, F, T, R, mu):
+def periodic_coefficients(shape, centre, F, T, R, mu, axes=None, q=None):
     """Low-mode content (|n_i| <= KMAX, n != 0; fewer along an axis shorter
-    than 2 KMAX + 1) of the periodic flow of a sphere at `centre`:
+    than 2 KMAX + 1) of the periodic flow of a particle at `centre`:
     periodic_modes at k = 2 pi n / L times exp(-i k . x_c).  Returns (list of
     n, complex array (len, 3))."""
     L = np.asarray(shape, float)
@@ -236,32 +337,29 @@ def periodic_coefficients(shape, centre, F, T, R, mu):
     ns = [(nx, ny, nz) for nz in range(-K[2], K[2] + 1) for ny in range(-K[1], K[1] + 1)
           for nx in range(-K[0], K[0] + 1) if (nx, ny, nz) != (0, 0, 0)]
     k = 2 * np.pi * np.array(ns, float) / L
-    c = periodic_modes(k, F, T, R, mu, float(np.prod(L)))
+    c = periodic_modes(k, F, T, R, mu, float(np.prod(L)), axes, q)
     return ns, c * np.exp(-1j * (k @ np.asarray(centre, float)))[:, None]
 
 
 def free_field(shape, particles, mu):
-    """Sum over the particles of the free-space flow of a sphere (equal-volume
-    radius) driven by the particle's load, at minimum-image offsets: the
-    sphere moves with F / (6 pi mu R) and turns with T / (8 pi mu R^3)."""
+    """Sum over the particles of the free-space flow their loads drive
+    (particle_flow), at minimum-image offsets."""
     nx, ny, nz = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(float)
     u = np.zeros((pos.shape[0], 3))
     for p in particles:
-        R = req(p["axes"])
         d = min_image(pos - np.asarray(p["centre"], float), shape)
-        u += stokes_velocity(d, np.asarray(p["F"], float) / (6 * math.pi * mu * R),
-                             np.asarray(p["T"], float) / (8 * math.pi * mu * R ** 3), R)
+        u += particle_flow(d, p, mu)
     return pos, u
 
 
 def start_field(shape, owner, particles, mu):
     """Velocity of every node of a periodic box for the warm start.
 
-    particles: list of dicts (centre, axes, F, T: the external load, U, W:
-    the particle's velocities, M).  The fluid field is the free-space sphere
-    flow of every particle's load (free_field) whose Fourier modes
+    particles: list of dicts (centre, axes, q, F, T: the external load, U, W:
+    the particle's velocities, M).  The fluid field is the free-space flow
+    of every particle's load (free_field) whose Fourier modes
     |n_i| <= KMAX are replaced by those of the periodic solution
     (periodic_coefficients), so the slow modes of the box start at their
     steady values; the DFT is over all nodes (numpy's FFT).  Fluid nodes
@@ -275,7 +373,7 @@ def start_field(shape, owner, particles, mu):
     S = np.fft.fftn(grid, axes=(0, 1, 2))            # sum_x u exp(-2 pi i n . x / L)
     corr = np.zeros(3 * N, dtype=complex).reshape(N, 3)
     for p in particles:
-        ns, c = periodic_coefficients(shape, p["centre"], p["F"], p["T"], req(p["axes"]), mu)
+        ns, c = periodic_coefficients(shape, p["centre"], p["F"], p["T"], req(p["axes"]), mu, p["axes"], p["q"])
         for n, cn in zip(ns, c):
             corr += cn[None, :] * np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / np.asarray(shape, float))))[:, None]
     ns, _ = periodic_coefficients(shape, (0, 0, 0), (0, 0, 0), (0, 0, 0), 1.0, 1.0)

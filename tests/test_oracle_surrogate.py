@@ -280,8 +280,8 @@ def test_start_field_has_zero_total_momentum():
     z, y, x = np.meshgrid(np.arange(22), np.arange(18), np.arange(20), indexing="ij")
     inside = ((x - 9.3) / 4) ** 2 + ((y - 8.6) / 2) ** 2 + ((z - 10.2) / 2) ** 2 < 1
     owner[inside.ravel()] = 1
-    p = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "F": (1e-4, -2e-5, 3e-5), "T": (0, 1e-4, 2e-4),
-         "U": (1e-3, -2e-4, 5e-4), "W": (1e-5, 2e-5, -3e-5), "M": 4 / 3 * math.pi * 16}
+    p = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "q": (1, 0, 0, 0), "F": (1e-4, -2e-5, 3e-5),
+         "T": (0, 1e-4, 2e-4), "U": (1e-3, -2e-4, 5e-4), "W": (1e-5, 2e-5, -3e-5), "M": 4 / 3 * math.pi * 16}
     u = S.start_field(shape, owner, [p], 1 / 6)
     tot = u[owner == 0].sum(0) + p["M"] * np.array(p["U"])
     assert np.abs(tot).max() < 1e-15 * np.prod(shape)
@@ -337,15 +337,17 @@ def test_start_field_low_modes_are_periodic():
     the rest equal the free field's (before the momentum shift, on a box with
     no particle nodes)."""
     shape, mu = (20, 18, 22), 1 / 6
-    part = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "F": (1e-4, -2e-5, 3e-5), "T": (0, 1e-4, 2e-4),
-            "U": (0, 0, 0), "W": (0, 0, 0), "M": 0.0}
+    q = np.array([0.9, 0.2, -0.3, 0.25]) / np.linalg.norm([0.9, 0.2, -0.3, 0.25])
+    part = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "q": q, "F": (1e-4, -2e-5, 3e-5),
+            "T": (0, 1e-4, 2e-4), "U": (0, 0, 0), "W": (0, 0, 0), "M": 0.0}
     owner = np.zeros(np.prod(shape), dtype=np.uint16)
     u = S.start_field(shape, owner, [part], mu)
     _, uf = S.free_field(shape, [part], mu)
     N = np.prod(shape)
     A = np.fft.fftn(u.reshape(22, 18, 20, 3), axes=(0, 1, 2)) / N
     B = np.fft.fftn(uf.reshape(22, 18, 20, 3), axes=(0, 1, 2)) / N
-    ns, c = S.periodic_coefficients(shape, part["centre"], part["F"], part["T"], S.req(part["axes"]), mu)
+    ns, c = S.periodic_coefficients(shape, part["centre"], part["F"], part["T"], S.req(part["axes"]), mu,
+                                    part["axes"], part["q"])
     for n, cn in zip(ns, c):
         assert np.allclose(A[n[2] % 22, n[1] % 18, n[0] % 20], cn, rtol=0, atol=1e-12 * np.abs(c).max())
     mask = np.ones((22, 18, 20), bool)
@@ -353,3 +355,111 @@ def test_start_field_low_modes_are_periodic():
         mask[n[2] % 22, n[1] % 18, n[0] % 20] = False
     assert np.allclose(A[mask], B[mask], rtol=0, atol=1e-12 * np.abs(B).max())
     assert np.abs(A[0, 0, 0]).max() < 1e-15
+
+
+def _spheroid_case(g, axes):
+    q = g.standard_normal(4)
+    q /= np.linalg.norm(q)
+    return q, g.standard_normal(3), g.standard_normal(3) * axes[0]
+
+
+SPHEROIDS = [(6.0, 3.0, 3.0), (10.0, 2.0, 2.0), (20.0, 4.0, 4.0), (4.2, 4.0, 4.0), (3.003, 3.0, 3.0)]
+
+
+@pytest.mark.parametrize("axes", SPHEROIDS)
+def test_spheroid_flow_meets_the_body(axes):
+    """On the surface the line-singularity flow equals the rigid motion with
+    the resistance functions' velocities (Kim & Karrila's X^A, Y^A, X^C, Y^C,
+    pinned to Perrin's formulas above): together with decay at infinity and
+    each singularity solving the Stokes equations, this fixes the flow as the
+    unique creeping flow of the body moving under (F, T).  A wrong strength,
+    sign or term breaks it."""
+    g = np.random.default_rng(40)
+    q, F, T = _spheroid_case(g, axes)
+    mu = 1 / 6
+    a, b, _ = axes
+    th, ph = g.uniform(0, math.pi, 300), g.uniform(0, 2 * math.pi, 300)
+    d = np.stack([a * np.cos(th), b * np.sin(th) * np.cos(ph), b * np.sin(th) * np.sin(ph)], 1) @ S.rotmat(q).T
+    U, W = S.unbounded_velocities(axes, q, F, T, mu)
+    for load in ((F, 0 * T), (0 * F, T)):
+        Ul, Wl = S.unbounded_velocities(axes, q, *load, mu)
+        u = S.spheroid_flow(d * (1 + 1e-12), axes, q, *load, mu)
+        rig = Ul + np.cross(Wl, d)
+        assert np.abs(u - rig).max() < 1e-10 * np.abs(rig).max()
+
+
+@pytest.mark.parametrize("axes", SPHEROIDS[:3])
+def test_spheroid_flow_is_solenoidal_and_decays_as_the_load(axes):
+    """Divergence free outside the body (central differences); far away the
+    flow of a force is its Stokeslet F / (8 pi mu) (I / r + d d / r^3), and
+    that of a torque about the axis its rotlet T x d / (8 pi mu r^3)."""
+    g = np.random.default_rng(41)
+    q, F, T = _spheroid_case(g, axes)
+    mu = 1 / 6
+    a = axes[0]
+    e = g.standard_normal((40, 3))
+    e /= np.linalg.norm(e, axis=1)[:, None]
+    d = e * g.uniform(1.3 * a, 3 * a, (40, 1))
+    h = 1e-4
+    div = sum((S.spheroid_flow(d + h * np.eye(3)[k], axes, q, F, T, mu)[:, k]
+               - S.spheroid_flow(d - h * np.eye(3)[k], axes, q, F, T, mu)[:, k]) / (2 * h) for k in range(3))
+    scale = np.abs(S.spheroid_flow(d, axes, q, F, T, mu)).max() / a
+    assert np.abs(div).max() < 1e-7 * scale
+    far = 1e4 * a * e
+    r = np.linalg.norm(far, axis=1)[:, None]
+    st = (F / r + (far @ F)[:, None] * far / r ** 3) / (8 * math.pi * mu)
+    assert np.allclose(S.spheroid_flow(far, axes, q, F, 0 * T, mu), st, rtol=0, atol=1e-7 * np.abs(st).max())
+    p = S.rotmat(q)[:, 0]
+    Ta = (T @ p) * p
+    rot = np.cross(Ta, far) / (8 * math.pi * mu * r ** 3)
+    assert np.allclose(S.spheroid_flow(far, axes, q, 0 * F, Ta, mu), rot, rtol=0, atol=1e-7 * np.abs(rot).max())
+
+
+def test_spheroid_flow_tends_to_the_sphere():
+    """Just above E_LINE the spheroid's flow is the sphere's Stokes solution
+    and rotlet to O(e^2)."""
+    g = np.random.default_rng(42)
+    a = 3.0
+    axes = (a, a * math.sqrt(1 - (2 * S.E_LINE) ** 2), a * math.sqrt(1 - (2 * S.E_LINE) ** 2))
+    q, F, T = _spheroid_case(g, axes)
+    mu = 0.1
+    e = g.standard_normal((40, 3))
+    e /= np.linalg.norm(e, axis=1)[:, None]
+    d = e * g.uniform(1.05 * a, 4 * a, (40, 1))
+    u = S.spheroid_flow(d, axes, q, F, T, mu)
+    ref = S.stokes_velocity(d, F / (6 * math.pi * mu * a), T / (8 * math.pi * mu * a ** 3), a)
+    assert np.abs(u - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+def test_translating_spheroid_is_a_single_layer_of_the_mapped_sphere():
+    """Outside a translating prolate spheroid the flow equals the Stokeslets
+    of its force spread over the surface as the uniform measure on the unit
+    sphere mapped by diag(a, b, b) in the body frame (the reading behind the
+    periodic coefficients' form factor sinc(|diag(a, b, c) R^T k|), which is
+    that measure's Fourier transform).  Quadrature over the unit sphere:
+    Gauss-Legendre in cos(theta), trapezoid in phi."""
+    g = np.random.default_rng(43)
+    axes = (7.0, 2.5, 2.5)
+    q, F, _ = _spheroid_case(g, axes)
+    mu = 0.2
+    Rm = S.rotmat(q)
+    ct, wt = np.polynomial.legendre.leggauss(160)
+    ph = np.arange(320) * 2 * math.pi / 320
+    st = np.sqrt(1 - ct * ct)
+    n = np.stack([np.outer(ct, np.ones_like(ph)), np.outer(st, np.cos(ph)), np.outer(st, np.sin(ph))], -1).reshape(-1, 3)
+    w = (np.outer(wt, np.ones_like(ph)) * (2 * math.pi / 320)).ravel() / (4 * math.pi)
+    y = (n * np.asarray(axes)) @ Rm.T
+    assert abs(w.sum() - 1) < 1e-13
+    pts = np.array([[0.0, 0.0, 4.0], [9.0, 1.0, -2.0], [-3.0, 5.0, 2.0], [2.0, -2.0, -6.0]])
+    u = S.spheroid_flow(pts, axes, q, F, 0 * F, mu)
+    for x, ux in zip(pts, u):
+        r = x - y
+        R = np.linalg.norm(r, axis=1)[:, None]
+        G = F / R + (r @ F)[:, None] * r / R ** 3
+        v = (w[:, None] * G).sum(0) / (8 * math.pi * mu)
+        assert np.abs(v - ux).max() < 1e-9 * np.abs(ux).max()
+    # the measure's transform is sinc(|diag(a, b, b) R^T k|)
+    for k in (np.array([0.3, -0.2, 0.5]), np.array([0.05, 0.4, 0.1])):
+        ft = (w * np.exp(-1j * (y @ k))).sum()
+        ka = np.linalg.norm((k @ Rm) * np.asarray(axes))
+        assert abs(ft - math.sin(ka) / ka) < 1e-12
