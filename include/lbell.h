@@ -447,18 +447,23 @@ lb_status lb_warm_status(lb_ctx* ctx, int* status, long long* decided_step);
 
 /* Starts the fluid of every box from the creeping flow its particles'
  * external loads drive.  Each node gets the sum over the box's particles of
- * the free-space flow of a sphere of the particle's equal-volume radius R
- * moving with F_ext / (6 pi mu R) and turning with T_ext / (8 pi mu R^3)
- * (Stokes' solution and the rotlet at minimum-image offsets; rigid motion
- * within R), whose Fourier modes |n_i| <= 2 of the box (fewer along an edge
- * shorter than 5) are replaced by those of the periodic flow of the same
- * loads (uniform surface traction on the sphere), so the box's slowest shear
- * modes start at their steady values.  The fluid nodes then lose the uniform
- * velocity that makes the box's total momentum (fluid at rho0 plus the
- * particles' M U) zero; nodes inside a particle move rigidly with its
- * current U, Omega.  Every node is set to the second-order equilibrium at
- * rho0 and its velocity (mass is unchanged).  LB_EINVAL if a box has walls.
- * Synchronises. */
+ * the free-space flow the load (F_ext, T_ext) drives, at minimum-image
+ * offsets, rigid motion inside the body: for a prolate spheroid (a > b = c)
+ * the exact solution (Chwang & Wu's singularities on the focal segment, the
+ * body moving with the velocities of eq. drag4's resistance functions); for
+ * any other shape the sphere of the equal-volume radius R moving with
+ * F_ext / (6 pi mu R) and turning with T_ext / (8 pi mu R^3) (Stokes'
+ * solution and the rotlet).  Its Fourier modes |n_i| <= 2 of the box (fewer
+ * along an edge shorter than 5) are replaced by those of the periodic flow
+ * of the same loads (the force spread as the traction on the translating
+ * ellipsoid, the torque as uniform traction on the sphere of radius R), so
+ * the box's slowest shear modes start at their steady values.  The fluid
+ * nodes then lose the uniform velocity that makes the box's total momentum
+ * (fluid at rho0 plus the particles' M U) zero; nodes inside a particle move
+ * rigidly with its current U, Omega.  Every node is set to the second-order
+ * equilibrium at rho0 and its velocity (mass is unchanged).  The free flow
+ * is staged in the population buffer that does not hold the state (no
+ * allocation).  LB_EINVAL if a box has walls.  Synchronises. */
 lb_status lb_stokes_start(lb_ctx* ctx);
 
 /* Training sample of every particle at its current state: the surrogate's

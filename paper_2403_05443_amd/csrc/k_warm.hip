@@ -18,16 +18,18 @@
 //
 // Start field: the creeping flow the particles' loads drive in the periodic
 // box.  Per node, the sum over the box's particles of the free-space flow
-// of a sphere of radius Req moving with F / (6 pi mu Req) and turning with
-// T / (8 pi mu Req^3) (Stokes' solution and the rotlet, minimum-image
-// offsets; rigid inside Req) -- whose Fourier modes |n_i| <= 2 are replaced
-// by those of the periodic solution of the same loads (uniform surface
-// traction on the sphere), so the box's slowest shear modes start at their
-// steady values; then the uniform velocity that makes the box's total
-// momentum (fluid at rho0 plus particles) zero is removed from the fluid
-// nodes, and nodes inside particle p move rigidly with its U, Omega.  Every
-// node gets the second-order equilibrium at rho0 and its velocity, written as
-// pre-collision populations (slot (x - c_i, i)).
+// that the particle's load drives (particle_flow: the exact flow of a
+// prolate spheroid, else that of the equal-volume sphere; minimum-image
+// offsets, rigid inside the body), computed once per node (k_stokes_free)
+// -- whose Fourier modes |n_i| <= 2 are replaced by those of the periodic
+// solution of the same loads (the force spread as the traction on the
+// translating ellipsoid, the torque over the sphere of radius Req), so the
+// box's slowest shear modes start at their steady values; then the uniform
+// velocity that makes the box's total momentum (fluid at rho0 plus
+// particles) zero is removed from the fluid nodes, and nodes inside particle
+// p move rigidly with its U, Omega.  Every node gets the second-order
+// equilibrium at rho0 and its velocity, written as pre-collision populations
+// (slot (x - c_i, i)).
 #include <type_traits>
 
 #include "lbell_dev.h"
@@ -162,32 +164,192 @@ constexpr int WM = (2 * WK + 1) * (2 * WK + 1) * (2 * WK + 1);  // mode slots pe
 
 __device__ __forceinline__ int wk_axis(int L) { return min(WK, (L - 1) / 2); }
 
-// Free-space flow at node (x, y, z) of box bi: the sum over the box's
-// particles of the flow of a load-driven sphere (fluid nodes and, for the
-// Fourier analysis, every node).
-__device__ void free_velocity(const BoxDesc& B, int bi, const PartDev* __restrict__ parts, int np, double mu, int x,
-                              int y, int z, double u[3]) {
-    u[0] = u[1] = u[2] = 0.0;
-    for (int p = 0; p < np; ++p) {
-        const PartDev& P = parts[p];
-        if (P.box != bi) continue;
-        double d[3];
-        offset(P, B, x, y, z, d);
+// 24-point Gauss-Legendre rule on [-1, 1]: the positive nodes and their
+// weights (the rule is symmetric).
+__constant__ double GL24[12][2] = {
+    {0.06405689286260563, 0.12793819534675221}, {0.1911188674736163, 0.1258374563468283},
+    {0.3150426796961634, 0.12167047292780342},  {0.4337935076260451, 0.11550566805372561},
+    {0.5454214713888396, 0.1074442701159656},   {0.6480936519369755, 0.09761865210411406},
+    {0.7401241915785544, 0.08619016153195329},  {0.820001985973903, 0.07334648141108041},
+    {0.886415527004401, 0.05929858491543674},   {0.9382745520027328, 0.04427743881741955},
+    {0.9747285559713095, 0.028531388628933743}, {0.9951872199970213, 0.012341229799987091},
+};
+
+// Below this eccentricity a prolate spheroid's flow is taken as the sphere's
+// (the two differ by O(e^2)).
+constexpr double E_LINE = 1e-4;
+
+__device__ __forceinline__ bool loaded(const PartDev& P) {
+    return P.Fext[0] != 0.0 || P.Fext[1] != 0.0 || P.Fext[2] != 0.0 || P.Text[0] != 0.0 || P.Text[1] != 0.0 ||
+           P.Text[2] != 0.0;
+}
+
+// Free-space creeping flow that the load of particle P drives, added to u at
+// offset d from its centre; rigid motion inside the body.
+//
+// Prolate spheroid (a > b = c): the exact solution of Chwang & Wu (J. Fluid
+// Mech. 63, 1974; 67, 1975) as singularities on the focal segment |xi| <= f,
+// f = a e, axis p, g(xi) = f^2 - xi^2, r = d - xi p, R = |r|; with
+// s = F / (16 pi mu f) and t = T / (8 pi mu (4/3) f^3), t_c its part across p:
+//   Stokeslets s / R + (s.r) r / R^3 (uniform: they carry the force),
+//   potential dipoles -(1 - e^2) / (2 e^2) g [-s / R^3 + 3 (s.r) r / R^5],
+//   rotlets g t x r / R^3 (they carry the torque),
+//   stresslets 3 e^2 / (2 - e^2) g r (r.p)(r.m) / R^5, m = t_c x p,
+//   potential quadrupoles (1 - e^2) / (4 (2 - e^2)) g^2 (p.grad) of the
+//   dipole of m: 3 (m (r.p) + (r.m) p) / R^5 - 15 (r.m)(r.p) r / R^7.
+// The body moves with the velocities of eq. drag4's X^A, Y^A, X^C, Y^C:
+// V = F_p / (16 pi mu f alpha_p) + F_c / (16 pi mu f alpha_c), alpha_p =
+// e^2 / D1, alpha_c = 2 e^2 / D2; Omega = t_p D3 / (1 - e^2) + t_c D1 /
+// (2 - e^2); D1 = -2e + (1 + e^2) L, D2 = 2e + (3e^2 - 1) L, D3 = 2e -
+// (1 - e^2) L, L = ln((1 + e) / (1 - e)) (power series below e = 1/2, where
+// they cancel).  The segment integrals are taken with the substitution
+// xi = xi0 -+ delta sinh(t) about the point xi0 of the segment nearest d
+// (delta the distance to it), which smooths the near-tip peaks, and 24
+// Gauss-Legendre points on each side of xi0.
+// Every other shape: the sphere of radius Req = (abc)^(1/3) moving with
+// F / (6 pi mu Req) and turning with T / (8 pi mu Req^3) (Stokes' solution
+// and the rotlet), rigid inside Req.
+__device__ void particle_flow(const PartDev& P, double mu, const double d[3], double u[3]) {
+    const double a = P.axes[0], b = P.axes[1];
+    const double e2 = a > b && b == P.axes[2] ? 1.0 - (b / a) * (b / a) : 0.0;
+    if (e2 < E_LINE * E_LINE) {
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const double R = eq_radius(P);
         const double cu = 1.0 / (6.0 * M_PI * mu * R), cw = 1.0 / (8.0 * M_PI * mu * R * R * R);
         const double U[3] = {P.Fext[0] * cu, P.Fext[1] * cu, P.Fext[2] * cu};
         const double W[3] = {P.Text[0] * cw, P.Text[1] * cw, P.Text[2] * cw};
         const double wx[3] = {W[1] * d[2] - W[2] * d[1], W[2] * d[0] - W[0] * d[2], W[0] * d[1] - W[1] * d[0]};
-        if (r < R) {  // inside the sphere: rigid motion
+        if (r < R) {
             for (int k = 0; k < 3; ++k) u[k] += U[k] + wx[k];
-            continue;
+            return;
         }
-        const double e[3] = {d[0] / r, d[1] / r, d[2] / r};
-        const double Ue = U[0] * e[0] + U[1] * e[1] + U[2] * e[2];
+        const double ex[3] = {d[0] / r, d[1] / r, d[2] / r};
+        const double Ue = U[0] * ex[0] + U[1] * ex[1] + U[2] * ex[2];
         const double a1 = 0.75 * R / r, a3 = 0.25 * R * R * R / (r * r * r), rr = (R / r) * (R / r) * (R / r);
         for (int k = 0; k < 3; ++k)
-            u[k] += a1 * (U[k] + Ue * e[k]) + a3 * (U[k] - 3.0 * Ue * e[k]) + rr * wx[k];
+            u[k] += a1 * (U[k] + Ue * ex[k]) + a3 * (U[k] - 3.0 * Ue * ex[k]) + rr * wx[k];
+        return;
+    }
+    const double e = sqrt(e2), f = a * e;
+    double D1 = 0.0, D2 = 0.0, D3 = 0.0;
+    if (e < 0.5) {  // D1 = sum 8k e^(2k+1) / (4k^2 - 1), D2 = sum 8(k+1) ..., D3 = sum 4 ... (k >= 1)
+        double ek = e * e2;
+        for (int k = 1; k <= 30; ++k) {
+            const double den = 4.0 * k * k - 1.0;
+            D1 += 8.0 * k * ek / den;
+            D2 += 8.0 * (k + 1) * ek / den;
+            D3 += 4.0 * ek / den;
+            ek *= e2;
+        }
+    } else {
+        const double L = log((1.0 + e) / (1.0 - e));
+        D1 = -2.0 * e + (1.0 + e2) * L;
+        D2 = 2.0 * e + (3.0 * e2 - 1.0) * L;
+        D3 = 2.0 * e - (1.0 - e2) * L;
+    }
+    const double bfac = -(1.0 - e2) / (2.0 * e2), dl = 3.0 * e2 / (2.0 - e2), ka = (1.0 - e2) / (4.0 * (2.0 - e2));
+    double Rm[3][3];
+    body_to_lab(P.q, Rm);
+    const double p[3] = {Rm[0][0], Rm[1][0], Rm[2][0]};
+    const double Fp = P.Fext[0] * p[0] + P.Fext[1] * p[1] + P.Fext[2] * p[2];
+    const double Tp = P.Text[0] * p[0] + P.Text[1] * p[1] + P.Text[2] * p[2];
+    const double cf = 1.0 / (16.0 * M_PI * mu * f), ct = 1.0 / (8.0 * M_PI * mu * (4.0 / 3.0) * f * f * f);
+    double U[3], W[3], S1[3], G[3], Gc[3];
+    for (int k = 0; k < 3; ++k) {
+        S1[k] = P.Fext[k] * cf;
+        G[k] = P.Text[k] * ct;
+        Gc[k] = (P.Text[k] - Tp * p[k]) * ct;
+        U[k] = Fp * p[k] * cf * D1 / e2 + (P.Fext[k] - Fp * p[k]) * cf * D2 / (2.0 * e2);
+        W[k] = Tp * p[k] * ct * D3 / (1.0 - e2) + Gc[k] * D1 / (2.0 - e2);
+    }
+    const double m[3] = {Gc[1] * p[2] - Gc[2] * p[1], Gc[2] * p[0] - Gc[0] * p[2], Gc[0] * p[1] - Gc[1] * p[0]};
+    const double z = d[0] * p[0] + d[1] * p[1] + d[2] * p[2];
+    const double rho2 = fmax(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - z * z, 0.0);
+    if (z * z / (a * a) + rho2 / (b * b) < 1.0) {  // inside: rigid motion
+        u[0] += U[0] + W[1] * d[2] - W[2] * d[1];
+        u[1] += U[1] + W[2] * d[0] - W[0] * d[2];
+        u[2] += U[2] + W[0] * d[1] - W[1] * d[0];
+        return;
+    }
+    const double x0 = fmin(fmax(z, -f), f);
+    const double delta = sqrt(rho2 + (z - x0) * (z - x0));  // > 0: the segment lies inside the body
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int side = 0; side < 2; ++side) {
+        const double sgn = side ? 1.0 : -1.0, len = side ? f - x0 : x0 + f;
+        if (len <= 0.0) continue;
+        const double tm = asinh(len / delta);
+        for (int j = 0; j < 24; ++j) {
+            const double tj = j < 12 ? -GL24[11 - j][0] : GL24[j - 12][0];
+            const double wj = j < 12 ? GL24[11 - j][1] : GL24[j - 12][1];
+            const double t = 0.5 * tm * (tj + 1.0), et = exp(t), it = 1.0 / et;
+            const double xi = x0 + sgn * delta * 0.5 * (et - it);
+            const double wq = 0.5 * tm * wj * delta * 0.5 * (et + it);
+            const double r[3] = {d[0] - xi * p[0], d[1] - xi * p[1], d[2] - xi * p[2]};
+            const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double iR = 1.0 / sqrt(R2), iR2 = iR * iR, iR3 = iR * iR2, iR5 = iR3 * iR2, iR7 = iR5 * iR2;
+            const double g = (f - xi) * (f + xi);
+            const double Sr = S1[0] * r[0] + S1[1] * r[1] + S1[2] * r[2];
+            const double rp = r[0] * p[0] + r[1] * p[1] + r[2] * p[2];
+            const double rm = r[0] * m[0] + r[1] * m[1] + r[2] * m[2];
+            const double Gxr[3] = {G[1] * r[2] - G[2] * r[1], G[2] * r[0] - G[0] * r[2], G[0] * r[1] - G[1] * r[0]};
+            const double cS = bfac * g, cQ = ka * g * g;
+            for (int k = 0; k < 3; ++k) {
+                const double v = S1[k] * iR + Sr * r[k] * iR3                      // Stokeslets
+                                 + cS * (-S1[k] * iR3 + 3.0 * Sr * r[k] * iR5)     // potential dipoles
+                                 + g * Gxr[k] * iR3                                // rotlets
+                                 + dl * g * r[k] * rp * rm * iR5                   // stresslets
+                                 + cQ * (3.0 * (m[k] * rp + rm * p[k]) * iR5 - 15.0 * rm * rp * r[k] * iR7);
+                acc[k] += wq * v;
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) u[k] += acc[k];
+}
+
+// Free-space flow of every node of the started boxes (the sum over each
+// box's loaded particles of particle_flow), node-major into uf at
+// 3 (ooff + site - base).  A work-group per tile; the box's loaded particles
+// are listed in index order, TILE at a time, in LDS.
+__global__ __launch_bounds__(TILE) void k_stokes_free(const BoxDesc* __restrict__ boxes,
+                                                      const int* __restrict__ tile_box,
+                                                      const PartDev* __restrict__ parts, int np, double mu,
+                                                      int only_box, long long base, double* __restrict__ uf) {
+    __shared__ int list[TILE];
+    __shared__ int wcnt[TILE / 64];
+    const int tile = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int bi = tile_box[tile];
+    if (only_box >= 0 && bi != only_box) return;  // uniform over the block
+    const BoxDesc& B = boxes[bi];
+    const int s = (tile - B.tile0) * TILE + tid;
+    const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int p0 = 0; p0 < np; p0 += TILE) {
+        const int p = p0 + tid;
+        const bool take = p < np && parts[p].box == bi && loaded(parts[p]);
+        const unsigned long long bal = __ballot(take);
+        if (lane == 0) wcnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0, cnt = 0;
+        for (int w = 0; w < TILE / 64; ++w) {
+            off += w < wv ? wcnt[w] : 0;
+            cnt += wcnt[w];
+        }
+        if (take) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = p;
+        __syncthreads();
+        if (s < B.n)
+            for (int j = 0; j < cnt; ++j) {
+                const PartDev& P = parts[list[j]];
+                double d[3];
+                offset(P, B, x, y, z, d);
+                particle_flow(P, mu, d, u);
+            }
+        __syncthreads();
+    }
+    if (s < B.n) {
+        double* o = uf + 3 * (B.ooff + s - base);
+        o[0] = u[0];
+        o[1] = u[1];
+        o[2] = u[2];
     }
 }
 
@@ -215,10 +377,12 @@ __device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x
     }
 }
 
-// Velocity of node (x, y, z) of box bi before the mean correction: rigid
-// motion inside a particle, else the corrected load-driven flow.
-__device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const PartDev* __restrict__ parts, int np,
-                               double mu, const double* __restrict__ coef, int x, int y, int z, double u[3]) {
+// Velocity of site s = (x, y, z) of box bi before the mean correction: rigid
+// motion inside a particle, else the corrected load-driven flow (uf: the
+// free flow of k_stokes_free).
+__device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const PartDev* __restrict__ parts,
+                               const double* __restrict__ uf, long long base, const double* __restrict__ coef, int s,
+                               int x, int y, int z, double u[3]) {
     if (owner != 0) {
         const PartDev& P = parts[owner - 1];
         double d[3];
@@ -228,7 +392,10 @@ __device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const P
         u[2] = P.U[2] + P.W[0] * d[1] - P.W[1] * d[0];
         return;
     }
-    free_velocity(B, bi, parts, np, mu, x, y, z, u);
+    const double* o = uf + 3 * (B.ooff + s - base);
+    u[0] = o[0];
+    u[1] = o[1];
+    u[2] = o[2];
     correction(B, coef + (long long)bi * WM * 6, x, y, z, u);
 }
 
@@ -240,10 +407,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Discrete Fourier sums S_m = sum_x u_free(x) exp(-i k_m . x) over every node
 // of a box, for the modes of one (ny, nz) pair (blockIdx.y) and all nx.
 __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict__ boxes,
-                                                      const PartDev* __restrict__ parts, int np, double mu,
+                                                      const double* __restrict__ uf, long long base, int only_box,
                                                       double* __restrict__ S) {
     __shared__ double red[4][2 * WK + 1][6];
     const int bi = blockIdx.x, g = blockIdx.y;
+    if (only_box >= 0 && bi != only_box) return;  // uniform over the block
     const BoxDesc& B = boxes[bi];
     const int ny_ = g % (2 * WK + 1) - WK, nz_ = g / (2 * WK + 1) - WK;
     const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
@@ -255,8 +423,8 @@ __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict_
         for (int k = 0; k < 6; ++k) acc[a][k] = 0.0;
     for (int s = threadIdx.x; s < B.n; s += blockDim.x) {
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
-        double u[3];
-        free_velocity(B, bi, parts, np, mu, x, y, z, u);
+        const double* o = uf + 3 * (B.ooff + s - base);
+        const double u[3] = {o[0], o[1], o[2]};
         double syz, cyz;
         sincospi(2.0 * ((double)ny_ * y / B.ny + (double)nz_ * z / B.nz), &syz, &cyz);
 #pragma unroll
@@ -313,8 +481,19 @@ __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, con
     for (int p = 0; p < np; ++p) {
         const PartDev& P = parts[p];
         if (P.box != bi) continue;
-        const double R = eq_radius(P), xr = sqrt(k2) * R;
-        const double sinc = sin(xr) / xr, j1f = 3.0 * (sin(xr) / xr - cos(xr)) / (xr * xr);
+        // translation: the traction on a translating ellipsoid is the
+        // sphere's uniform layer mapped by diag(a, b, c) in the body frame,
+        // whose transform is sinc(|diag(a, b, c) R^T k|); rotation: the
+        // sphere of radius Req
+        double Rm[3][3];
+        body_to_lab(P.q, Rm);
+        double ka2 = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double kb = (k[0] * Rm[0][j] + k[1] * Rm[1][j] + k[2] * Rm[2][j]) * P.axes[j];
+            ka2 += kb * kb;
+        }
+        const double xa = sqrt(ka2), R = eq_radius(P), xr = sqrt(k2) * R;
+        const double sinc = sin(xa) / xa, j1f = 3.0 * (sin(xr) / xr - cos(xr)) / (xr * xr);
         const double kF = k[0] * P.Fext[0] + k[1] * P.Fext[1] + k[2] * P.Fext[2];
         const double kxT[3] = {k[1] * P.Text[2] - k[2] * P.Text[1], k[2] * P.Text[0] - k[0] * P.Text[2],
                                k[0] * P.Text[1] - k[1] * P.Text[0]};
@@ -337,7 +516,8 @@ __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, con
 __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__ boxes,
                                                      const int* __restrict__ tile_box,
                                                      const uint16_t* __restrict__ omap,
-                                                     const PartDev* __restrict__ parts, int np, double mu,
+                                                     const PartDev* __restrict__ parts,
+                                                     const double* __restrict__ uf, long long base, int only_box,
                                                      const double* __restrict__ coef,
                                                      double* __restrict__ partial) {
     __shared__ double red[4][TILE];
@@ -346,9 +526,9 @@ __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + tid;
     double v[4] = {0, 0, 0, 0};
-    if (s < B.n && omap[B.ooff + s] == 0) {
+    if ((only_box < 0 || bi == only_box) && s < B.n && omap[B.ooff + s] == 0) {
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
-        start_velocity(B, bi, 0, parts, np, mu, coef, x, y, z, v);
+        start_velocity(B, bi, 0, parts, uf, base, coef, s, x, y, z, v);
         v[3] = 1.0;
     }
     for (int k = 0; k < 4; ++k) red[k][tid] = v[k];
@@ -380,7 +560,8 @@ template <int ST, int Q>
 __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict__ boxes,
                                                        const int* __restrict__ tile_box,
                                                        const uint16_t* __restrict__ omap,
-                                                       const PartDev* __restrict__ parts, int np, double mu,
+                                                       const PartDev* __restrict__ parts,
+                                                       const double* __restrict__ uf, long long base,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ ubar,
                                                        typename Store<ST>::T* __restrict__ f, KParams kp,
@@ -397,7 +578,7 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
     double u[3];
-    start_velocity(B, bi, owner, parts, np, mu, coef, x, y, z, u);
+    start_velocity(B, bi, owner, parts, uf, base, coef, s, x, y, z, u);
     if (owner == 0)
         for (int k = 0; k < 3; ++k) u[k] -= ubar[3 * bi + k];
     const double rho0 = kp.rho0, uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -582,17 +763,19 @@ size_t stokes_scratch_doubles(int nboxes, int ntiles) { return (size_t)nboxes * 
 
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
                                const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
-                               void* f, const KParams& kp, int only_box, hipStream_t st) {
+                               double* uf, long long base, void* f, const KParams& kp, int only_box, hipStream_t st) {
     double* S = scratch;
     double* C = S + (size_t)nboxes * WM * 6;
     double* partial = C + (size_t)nboxes * WM * 6;
     double* ubar = partial + (size_t)ntiles * 4;
-    hipLaunchKernelGGL(k_stokes_modes, dim3(nboxes, (2 * WK + 1) * (2 * WK + 1)), dim3(256), 0, st, boxes, parts, np,
-                       mu, S);
+    hipLaunchKernelGGL(k_stokes_free, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, parts, np, mu, only_box, base,
+                       uf);
+    hipLaunchKernelGGL(k_stokes_modes, dim3(nboxes, (2 * WK + 1) * (2 * WK + 1)), dim3(256), 0, st, boxes, uf, base,
+                       only_box, S);
     hipLaunchKernelGGL(k_stokes_coef, dim3((nboxes * WM + 127) / 128), dim3(128), 0, st, boxes, nboxes, parts, np, mu,
                        S, C);
-    hipLaunchKernelGGL(k_stokes_sum, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap, parts, np, mu, C,
-                       partial);
+    hipLaunchKernelGGL(k_stokes_sum, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap, parts, uf, base,
+                       only_box, C, partial);
     hipLaunchKernelGGL(k_stokes_mean, dim3((nboxes + 63) / 64), dim3(64), 0, st, boxes, nboxes, parts, np, partial,
                        kp.rho0, ubar);
     auto write = [&](auto q) {
@@ -600,19 +783,19 @@ hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile
         switch (kp.storage) {
             case ST_F64:
                 hipLaunchKernelGGL((k_stokes_write<ST_F64, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (double*)f, kp, only_box);
+                                   omap, parts, uf, base, C, ubar, (double*)f, kp, only_box);
                 break;
             case ST_F32:
                 hipLaunchKernelGGL((k_stokes_write<ST_F32, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (float*)f, kp, only_box);
+                                   omap, parts, uf, base, C, ubar, (float*)f, kp, only_box);
                 break;
             case ST_F16:
                 hipLaunchKernelGGL((k_stokes_write<ST_F16, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (typename Store<ST_F16>::T*)f, kp, only_box);
+                                   omap, parts, uf, base, C, ubar, (typename Store<ST_F16>::T*)f, kp, only_box);
                 break;
             default:
                 hipLaunchKernelGGL((k_stokes_write<ST_BF16, Q>), dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box,
-                                   omap, parts, np, mu, C, ubar, (typename Store<ST_BF16>::T*)f, kp, only_box);
+                                   omap, parts, uf, base, C, ubar, (typename Store<ST_BF16>::T*)f, kp, only_box);
         }
     };
     if (kp.q == 27) write(std::integral_constant<int, 27>{});

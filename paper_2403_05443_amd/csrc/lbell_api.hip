@@ -218,6 +218,8 @@ struct lb_ctx {
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
     void* fbuf(int which) { return arena + ((aa ? aa_buf : which) ? L.f1 : L.f0); }
+    // the population buffer not holding the state
+    void* spare_buf() { return arena + ((aa ? aa_buf : cur) ? L.f0 : L.f1); }
     // every change of cur goes through here so the convention in kp follows
     void set_cur(int c) {
         cur = c;
@@ -1389,10 +1391,16 @@ lb_status stokes_start(lb_ctx* ctx, int only_box = -1) {
         if ((only_box < 0 || (int)b == only_box) && ctx->boxes[b].walls)
             return fail(ctx, LB_EINVAL, "the start field is defined for periodic boxes only");
     double* scratch = ctx->at<double>(ctx->L.warm) + 14 * (size_t)ctx->L.max_particles;
+    // the nodes' free flow goes to the population buffer that does not hold
+    // the state (the next step's output, or unused in place): 3 doubles per
+    // node fit in the Q >= 19 populations of >= 2 bytes each
+    if ((size_t)ctx->L.omap_elems * 3 * sizeof(double) > (size_t)ctx->L.pop_elems * storage_bytes(ctx->cfg.storage))
+        return fail(ctx, LB_EINVAL, "population buffer too small for the start field's scratch");
+    const long long base = only_box >= 0 ? ctx->hbox[only_box].ooff : 0;
     HIPC(launch_stokes_start(ctx->at<BoxDesc>(ctx->L.boxes), (int)ctx->boxes.size(), ctx->at<int>(ctx->L.tile_box),
                              ctx->L.total_tiles, ctx->at<uint16_t>(ctx->L.omap), ctx->at<PartDev>(ctx->L.parts),
-                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, ctx->fbuf(ctx->cur), ctx->kp, only_box,
-                             ctx->stream));
+                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, (double*)ctx->spare_buf(), base,
+                             ctx->fbuf(ctx->cur), ctx->kp, only_box, ctx->stream));
     return LB_OK;
 }
 }  // namespace

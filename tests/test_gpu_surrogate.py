@@ -205,7 +205,7 @@ def test_stokes_start_field_matches_reference(lb):
         o = oracle.OracleSim(boxes[b], "trt", 0.8, counterforce=True)
         po = o.add_ellipsoid(c, a, q)
         assert np.array_equal(o.mask() != 0, g.mask(b) != 0)
-        part = {"centre": o.particle(po)["x"], "axes": a, "F": F, "T": T, "U": vel[pid][0], "W": vel[pid][1],
+        part = {"centre": o.particle(po)["x"], "axes": a, "q": q, "F": F, "T": T, "U": vel[pid][0], "W": vel[pid][1],
                 "M": o.aux(po)["M"]}
         u = S.start_field(boxes[b], o.mask(), [part], (0.8 - 0.5) / 3)
         rho, ug = g.fields(b)
@@ -218,6 +218,24 @@ def test_stokes_start_field_matches_reference(lb):
         P = g.momentum(b) + o.aux(po)["M"] * np.array(vel[pid][0])
         assert np.abs(P).max() < 1e-12 * np.abs(u).sum()
         assert abs(g.mass(b) - m0[b]) < 1e-11 * m0[b]
+
+
+def test_single_box_warm_start_matches_the_full_start_in_that_box(lb):
+    """A warm start of one box (its free flow kept at that box's offset in
+    the scratch) gives that box the fields of the start of every box, bit for
+    bit, and leaves the other boxes' state alone."""
+    s = lb.Surrogate(max_samples=64, params=_params(600, scale=0.5))
+    one, _, _ = _warm_lattice(lb)
+    full, _, _ = _warm_lattice(lb)
+    for g in (one, full):
+        g.step(5)
+    before = [one.fields(b) for b in range(3)]
+    one.warm_start(s, box=2)
+    full.warm_start(s)
+    for b in range(3):
+        rho, u = one.fields(b)
+        rho_ref, u_ref = full.fields(b) if b == 2 else before[b]
+        assert np.array_equal(rho, rho_ref) and np.array_equal(u, u_ref), b
 
 
 def test_warm_started_trajectory_matches_oracle(lb):
@@ -238,7 +256,7 @@ def test_warm_started_trajectory_matches_oracle(lb):
     po = o.add_ellipsoid(c, a, q)
     o.set_external(po, F, T)
     o.set_velocity(po, U, W)
-    _oracle_start(o, shape, [{"centre": c, "axes": a, "F": F, "T": T, "U": U, "W": W, "M": o.aux(po)["M"]}],
+    _oracle_start(o, shape, [{"centre": c, "axes": a, "q": q, "F": F, "T": T, "U": U, "W": W, "M": o.aux(po)["M"]}],
                   (0.8 - 0.5) / 3)
     rho, ug = g.fields()
     _, uo = o.fields()
