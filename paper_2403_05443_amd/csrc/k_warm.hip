@@ -355,16 +355,35 @@ __global__ __launch_bounds__(TILE) void k_stokes_free(const BoxDesc* __restrict_
 
 // Periodic correction Re sum_m c_m exp(i k_m . x) at node (x, y, z); c: the
 // box's WM x 3 complex coefficients (re, im), zero for unused slots.
+// exp(i 2 pi n x / L) for n = -WK..WK (WK = 2) into e[n + WK] (re, im):
+// powers of the n = 1 term, the negative ones conjugate.
+static_assert(WK == 2, "twiddles() builds the modes |n| <= 2");
+__device__ __forceinline__ void twiddles(int x, int L, double e[2 * WK + 1][2]) {
+    double s1, c1;
+    sincospi(2.0 * x / L, &s1, &c1);
+    const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * s1 * c1;
+    e[WK][0] = 1.0;
+    e[WK][1] = 0.0;
+    e[WK + 1][0] = c1;
+    e[WK + 1][1] = s1;
+    e[WK - 1][0] = c1;
+    e[WK - 1][1] = -s1;
+    e[WK + 2][0] = c2;
+    e[WK + 2][1] = s2;
+    e[WK - 2][0] = c2;
+    e[WK - 2][1] = -s2;
+}
+
 __device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x, int y, int z, double u[3]) {
     const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
-    double ex[2 * WK + 1][2];
-    for (int n = -Kx; n <= Kx; ++n) sincospi(2.0 * n * x / B.nx, &ex[n + WK][1], &ex[n + WK][0]);
+    double ex[2 * WK + 1][2], ey[2 * WK + 1][2], ez[2 * WK + 1][2];
+    twiddles(x, B.nx, ex);
+    twiddles(y, B.ny, ey);
+    twiddles(z, B.nz, ez);
     for (int nz = -Kz; nz <= Kz; ++nz) {
-        double sz, cz;
-        sincospi(2.0 * nz * z / B.nz, &sz, &cz);
+        const double cz = ez[nz + WK][0], sz = ez[nz + WK][1];
         for (int ny = -Ky; ny <= Ky; ++ny) {
-            double sy, cy;
-            sincospi(2.0 * ny * y / B.ny, &sy, &cy);
+            const double cy = ey[ny + WK][0], sy = ey[ny + WK][1];
             const double pr = cy * cz - sy * sz, pi = sy * cz + cy * sz;  // exp(i (ky y + kz z))
             for (int nx = -Kx; nx <= Kx; ++nx) {
                 const double er = ex[nx + WK][0] * pr - ex[nx + WK][1] * pi;
@@ -427,11 +446,12 @@ __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict_
         const double u[3] = {o[0], o[1], o[2]};
         double syz, cyz;
         sincospi(2.0 * ((double)ny_ * y / B.ny + (double)nz_ * z / B.nz), &syz, &cyz);
+        double ex[2 * WK + 1][2];
+        twiddles(x, B.nx, ex);
 #pragma unroll
         for (int nx = -WK; nx <= WK; ++nx) {  // fixed trip count: the accumulators stay in registers
             if (nx < -Kx || nx > Kx) continue;
-            double sx, cx_;
-            sincospi(2.0 * nx * x / B.nx, &sx, &cx_);
+            const double cx_ = ex[nx + WK][0], sx = ex[nx + WK][1];
             // exp(-i theta) = cos theta - i sin theta, theta = kx x + ky y + kz z
             const double c = cx_ * cyz - sx * syz, sn = sx * cyz + cx_ * syz;
 #pragma unroll
