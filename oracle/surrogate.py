@@ -287,6 +287,51 @@ def spheroid_flow(d, axes, q, F, T, mu):
     return out
 
 
+def spheroid_pressure(d, axes, q, F, T, mu):
+    """Pressure of spheroid_flow at offsets d (n, 3): that of its Stokeslets,
+    2 mu (s.r) / R^3, and of its stresslets, 3 e^2 / (2 - e^2) g
+    2 mu (r.p)(r.m) / R^5, integrated over the focal segment (the potential
+    dipoles and quadrupoles and the rotlets carry none); 0 inside the body."""
+    d = np.atleast_2d(np.asarray(d, float))
+    a, b, _ = axes
+    e2 = 1.0 - (b / a) ** 2
+    f = a * math.sqrt(e2)
+    p = rotmat(q)[:, 0]
+    F, T = np.asarray(F, float), np.asarray(T, float)
+    s = F / (16 * math.pi * mu * f)
+    t = T / (8 * math.pi * mu * 4.0 / 3.0 * f ** 3)
+    m = np.cross(t - (t @ p) * p, p)
+    z = d @ p
+    rho2 = np.maximum((d * d).sum(1) - z * z, 0.0)
+    inside = z * z / (a * a) + rho2 / (b * b) < 1.0
+    x0 = np.clip(z, -f, f)
+    delta = np.sqrt(rho2 + (z - x0) ** 2)
+    out = np.zeros(len(d))
+    o = ~inside
+    if o.any():
+        xi, w = _gl_panels(x0[o], delta[o], -f, f)
+        r = d[o][:, None, :] - xi[..., None] * p
+        R = np.sqrt((r * r).sum(-1))
+        g = f * f - xi * xi
+        val = 2 * mu * ((r @ s) / R ** 3 + 3 * e2 / (2 - e2) * g * (r @ p) * (r @ m) / R ** 5)
+        out[o] = (w * val).sum(1)
+    return out
+
+
+def particle_pressure(d, p, mu):
+    """Pressure of particle_flow at offsets d: spheroid_pressure, or for the
+    sphere of radius R the Stokes solution's 3 mu R (U.d) / (2 r^3) =
+    F.d / (4 pi r^3) outside R (the rotlet carries none); 0 inside."""
+    a, b, c = p["axes"]
+    F, T = np.asarray(p["F"], float), np.asarray(p["T"], float)
+    if a > b and b == c and 1.0 - (b / a) ** 2 >= E_LINE ** 2:
+        return spheroid_pressure(d, p["axes"], p["q"], F, T, mu)
+    d = np.atleast_2d(np.asarray(d, float))
+    R = req(p["axes"])
+    r = np.linalg.norm(d, axis=1)
+    return np.where(r >= R, (d @ F) / (4 * math.pi * np.maximum(r, 1e-300) ** 3), 0.0)
+
+
 def particle_flow(d, p, mu):
     """Free-space flow that particle p (dict: axes, q, F, T) drives at
     offsets d: spheroid_flow for a prolate spheroid (a > b = c, eccentricity
@@ -327,23 +372,43 @@ def periodic_modes(k, F, T, R, mu, V, axes=None, q=None):
     return (Pf * (sinc / (mu * k2))[:, None] + 1j * np.cross(k, T) * (j1f / (2 * mu * k2))[:, None]) / V
 
 
-def periodic_coefficients(shape, centre, F, T, R, mu, axes=None, q=None):
+def periodic_pressure_modes(k, F, R, V, axes=None, q=None):
+    """Fourier coefficients (1/V) p_hat(k) of the pressure of the periodic
+    flow of periodic_modes: from mu k^2 u_hat = f_hat - i k p_hat with
+    k.u_hat = 0, p_hat = -i (k.f_hat) / k^2, f_hat the force's spread (the
+    torque's has no divergence and drives no pressure)."""
+    k = np.atleast_2d(np.asarray(k, float))
+    F = np.asarray(F, float)
+    k2 = (k * k).sum(1)
+    if axes is None:
+        xa = np.sqrt(k2) * R
+    else:
+        xa = np.linalg.norm((k @ rotmat(q)) * np.asarray(axes, float), axis=1)
+    return -1j * (k @ F) * (np.sin(xa) / xa) / k2 / V
+
+
+def periodic_coefficients(shape, centre, F, T, R, mu, axes=None, q=None, pressure=False):
     """Low-mode content (|n_i| <= KMAX, n != 0; fewer along an axis shorter
     than 2 KMAX + 1) of the periodic flow of a particle at `centre`:
     periodic_modes at k = 2 pi n / L times exp(-i k . x_c).  Returns (list of
-    n, complex array (len, 3))."""
+    n, complex array (len, 3)); with pressure=True those of the pressure
+    (periodic_pressure_modes), complex array (len,)."""
     L = np.asarray(shape, float)
     K = [min(KMAX, (int(l) - 1) // 2) for l in shape]
     ns = [(nx, ny, nz) for nz in range(-K[2], K[2] + 1) for ny in range(-K[1], K[1] + 1)
           for nx in range(-K[0], K[0] + 1) if (nx, ny, nz) != (0, 0, 0)]
     k = 2 * np.pi * np.array(ns, float) / L
+    ph = np.exp(-1j * (k @ np.asarray(centre, float)))
+    if pressure:
+        return ns, periodic_pressure_modes(k, F, R, float(np.prod(L)), axes, q) * ph
     c = periodic_modes(k, F, T, R, mu, float(np.prod(L)), axes, q)
-    return ns, c * np.exp(-1j * (k @ np.asarray(centre, float)))[:, None]
+    return ns, c * ph[:, None]
 
 
-def free_field(shape, particles, mu):
+def free_field(shape, particles, mu, pressure=False):
     """Sum over the particles of the free-space flow their loads drive
-    (particle_flow), at minimum-image offsets."""
+    (particle_flow), at minimum-image offsets; with pressure=True also its
+    pressure (particle_pressure): (pos, u, p)."""
     nx, ny, nz = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(float)
@@ -351,47 +416,71 @@ def free_field(shape, particles, mu):
     for p in particles:
         d = min_image(pos - np.asarray(p["centre"], float), shape)
         u += particle_flow(d, p, mu)
-    return pos, u
+    if not pressure:
+        return pos, u
+    pr = np.zeros(pos.shape[0])
+    for p in particles:
+        pr += particle_pressure(min_image(pos - np.asarray(p["centre"], float), shape), p, mu)
+    return pos, u, pr
 
 
-def start_field(shape, owner, particles, mu):
-    """Velocity of every node of a periodic box for the warm start.
+def start_state(shape, owner, particles, mu):
+    """Density and velocity of every node of a periodic box for the warm
+    start: (rho (N,), u (N, 3)).
 
     particles: list of dicts (centre, axes, q, F, T: the external load, U, W:
-    the particle's velocities, M).  The fluid field is the free-space flow
-    of every particle's load (free_field) whose Fourier modes
-    |n_i| <= KMAX are replaced by those of the periodic solution
-    (periodic_coefficients), so the slow modes of the box start at their
-    steady values; the DFT is over all nodes (numpy's FFT).  Fluid nodes
-    (owner 0) then lose the uniform velocity that makes the total momentum
-    (fluid at rho0 = 1 plus particles M U) zero; nodes of particle p move
-    rigidly with its U, W."""
+    the particle's velocities, M).  The fluid's velocity and pressure are the
+    free-space flow of every particle's load and its pressure (free_field)
+    whose Fourier modes |n_i| <= KMAX are replaced by those of the periodic
+    solution (periodic_coefficients), so the slow modes of the box start at
+    their steady values; the DFT is over all nodes (numpy's FFT).  A fluid
+    node (owner 0) gets the density rho = 1 + 3 (p - pbar) (p = c_s^2
+    (rho - rho0), rho0 = 1, pbar the mean over the fluid nodes: the fluid's
+    mass is unchanged) and loses the uniform velocity
+    ubar = (sum rho u + sum M U) / N_fluid that makes the total momentum
+    (fluid sum rho u plus particles M U) zero; nodes of particle p have
+    rho = 1 and move rigidly with its U, W."""
     nx, ny, nz = shape
-    pos, u = free_field(shape, particles, mu)
+    pos, u, pr = free_field(shape, particles, mu, pressure=True)
     N = nx * ny * nz
-    grid = u.reshape(nz, ny, nx, 3)
-    S = np.fft.fftn(grid, axes=(0, 1, 2))            # sum_x u exp(-2 pi i n . x / L)
-    corr = np.zeros(3 * N, dtype=complex).reshape(N, 3)
+    L = np.asarray(shape, float)
+    Su = np.fft.fftn(u.reshape(nz, ny, nx, 3), axes=(0, 1, 2))   # sum_x u exp(-2 pi i n . x / L)
+    Sp = np.fft.fftn(pr.reshape(nz, ny, nx))
+    cu = np.zeros((N, 3), dtype=complex)
+    cp = np.zeros(N, dtype=complex)
     for p in particles:
-        ns, c = periodic_coefficients(shape, p["centre"], p["F"], p["T"], req(p["axes"]), mu, p["axes"], p["q"])
-        for n, cn in zip(ns, c):
-            corr += cn[None, :] * np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / np.asarray(shape, float))))[:, None]
+        args = (shape, p["centre"], p["F"], p["T"], req(p["axes"]), mu, p["axes"], p["q"])
+        ns, c = periodic_coefficients(*args)
+        _, c_p = periodic_coefficients(*args, pressure=True)
+        for n, cn, pn in zip(ns, c, c_p):
+            ph = np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / L)))
+            cu += cn[None, :] * ph[:, None]
+            cp += pn * ph
     ns, _ = periodic_coefficients(shape, (0, 0, 0), (0, 0, 0), (0, 0, 0), 1.0, 1.0)
     for n in ns:
-        dft = S[n[2] % nz, n[1] % ny, n[0] % nx] / N
-        corr -= dft[None, :] * np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / np.asarray(shape, float))))[:, None]
-    u = u + corr.real
+        ph = np.exp(2j * np.pi * (pos @ (np.asarray(n, float) / L)))
+        cu -= (Su[n[2] % nz, n[1] % ny, n[0] % nx] / N)[None, :] * ph[:, None]
+        cp -= Sp[n[2] % nz, n[1] % ny, n[0] % nx] / N * ph
+    u = u + cu.real
+    pr = pr + cp.real
     owner = np.asarray(owner).ravel()
     fluid = owner == 0
+    rho = np.ones(N)
     P = np.zeros(3)
     for k, p in enumerate(particles):
         mine = owner == k + 1
         d = min_image(pos[mine] - np.asarray(p["centre"], float), shape)
         u[mine] = np.asarray(p["U"], float) + np.cross(np.asarray(p["W"], float), d)
         P += p["M"] * np.asarray(p["U"], float)
-    ubar = (u[fluid].sum(0) + P) / fluid.sum()
+    rho[fluid] = 1.0 + 3.0 * (pr[fluid] - pr[fluid].mean())
+    ubar = ((rho[fluid, None] * u[fluid]).sum(0) + P) / fluid.sum()
     u[fluid] -= ubar
-    return u
+    return rho, u
+
+
+def start_field(shape, owner, particles, mu):
+    """The velocity of start_state."""
+    return start_state(shape, owner, particles, mu)[1]
 
 
 # ----------------------------------------------- unbounded-fluid closed forms --

@@ -282,9 +282,12 @@ def test_start_field_has_zero_total_momentum():
     owner[inside.ravel()] = 1
     p = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "q": (1, 0, 0, 0), "F": (1e-4, -2e-5, 3e-5),
          "T": (0, 1e-4, 2e-4), "U": (1e-3, -2e-4, 5e-4), "W": (1e-5, 2e-5, -3e-5), "M": 4 / 3 * math.pi * 16}
-    u = S.start_field(shape, owner, [p], 1 / 6)
-    tot = u[owner == 0].sum(0) + p["M"] * np.array(p["U"])
+    rho, u = S.start_state(shape, owner, [p], 1 / 6)
+    fl = owner == 0
+    tot = (rho[fl, None] * u[fl]).sum(0) + p["M"] * np.array(p["U"])
     assert np.abs(tot).max() < 1e-15 * np.prod(shape)
+    assert abs(rho[fl].sum() - fl.sum()) < 1e-12 and np.all(rho[~fl] == 1.0)
+    assert np.abs(rho - 1).max() > 1e-6   # the pressure is there
     # solid nodes move rigidly
     pos = np.stack([x.ravel(), y.ravel(), z.ravel()], 1)[owner == 1]
     rig = np.array(p["U"]) + np.cross(p["W"], pos - np.array(p["centre"]))
@@ -333,28 +336,35 @@ def test_periodic_modes_rotlet_near_field():
 
 
 def test_start_field_low_modes_are_periodic():
-    """The start field's modes |n_i| <= 2 equal the periodic solution's and
-    the rest equal the free field's (before the momentum shift, on a box with
-    no particle nodes)."""
+    """The start velocity's and pressure's modes |n_i| <= 2 equal the
+    periodic solution's and the rest equal the free field's (before the
+    momentum shift, on a box with no particle nodes; the pressure read back
+    from the density as (rho - 1) / 3)."""
     shape, mu = (20, 18, 22), 1 / 6
     q = np.array([0.9, 0.2, -0.3, 0.25]) / np.linalg.norm([0.9, 0.2, -0.3, 0.25])
     part = {"centre": (9.3, 8.6, 10.2), "axes": (4, 2, 2), "q": q, "F": (1e-4, -2e-5, 3e-5),
             "T": (0, 1e-4, 2e-4), "U": (0, 0, 0), "W": (0, 0, 0), "M": 0.0}
     owner = np.zeros(np.prod(shape), dtype=np.uint16)
-    u = S.start_field(shape, owner, [part], mu)
-    _, uf = S.free_field(shape, [part], mu)
+    rho, u = S.start_state(shape, owner, [part], mu)
+    _, uf, pf = S.free_field(shape, [part], mu, pressure=True)
     N = np.prod(shape)
-    A = np.fft.fftn(u.reshape(22, 18, 20, 3), axes=(0, 1, 2)) / N
-    B = np.fft.fftn(uf.reshape(22, 18, 20, 3), axes=(0, 1, 2)) / N
-    ns, c = S.periodic_coefficients(shape, part["centre"], part["F"], part["T"], S.req(part["axes"]), mu,
-                                    part["axes"], part["q"])
-    for n, cn in zip(ns, c):
-        assert np.allclose(A[n[2] % 22, n[1] % 18, n[0] % 20], cn, rtol=0, atol=1e-12 * np.abs(c).max())
-    mask = np.ones((22, 18, 20), bool)
-    for n in ns + [(0, 0, 0)]:
-        mask[n[2] % 22, n[1] % 18, n[0] % 20] = False
-    assert np.allclose(A[mask], B[mask], rtol=0, atol=1e-12 * np.abs(B).max())
-    assert np.abs(A[0, 0, 0]).max() < 1e-15
+    args = (shape, part["centre"], part["F"], part["T"], S.req(part["axes"]), mu, part["axes"], part["q"])
+    # the pressure read back from rho ~ 1 carries its rounding, ~1e-16 absolute
+    for field, free, pressure, floor in ((u, uf, False, 0.0), ((rho - 1) / 3, pf, True, 1e-16)):
+        A = np.fft.fftn(field.reshape(22, 18, 20, -1), axes=(0, 1, 2)) / N
+        B = np.fft.fftn(free.reshape(22, 18, 20, -1), axes=(0, 1, 2)) / N
+        ns, c = S.periodic_coefficients(*args, pressure=pressure)
+        c = c.reshape(len(ns), -1)
+        for n, cn in zip(ns, c):
+            assert np.allclose(A[n[2] % 22, n[1] % 18, n[0] % 20], cn, rtol=0,
+                               atol=1e-12 * np.abs(c).max() + floor)
+        mask = np.ones((22, 18, 20), bool)
+        for n in ns + [(0, 0, 0)]:
+            mask[n[2] % 22, n[1] % 18, n[0] % 20] = False
+        assert np.allclose(A[mask], B[mask], rtol=0, atol=1e-12 * np.abs(B).max() + floor)
+    # the mean momentum (M = 0 here) and the mean density change are zero
+    assert np.abs((rho[:, None] * u).mean(0)).max() < 1e-15
+    assert abs((rho - 1).mean()) < 1e-16
 
 
 def _spheroid_case(g, axes):
@@ -463,3 +473,47 @@ def test_translating_spheroid_is_a_single_layer_of_the_mapped_sphere():
         ft = (w * np.exp(-1j * (y @ k))).sum()
         ka = np.linalg.norm((k @ Rm) * np.asarray(axes))
         assert abs(ft - math.sin(ka) / ka) < 1e-12
+
+
+@pytest.mark.parametrize("axes", [(6.0, 3.0, 3.0), (10.0, 2.0, 2.0), (3.0, 3.0, 3.0)])
+def test_start_pressure_balances_the_viscous_stress(axes):
+    """Outside the body the free flow's pressure and velocity satisfy the
+    Stokes equations, grad p = mu lap u (second-order central differences,
+    h = 3e-3; the truncation error is ~h^2 of the fourth derivatives), for a
+    spheroid under force and torque and for the sphere; far away a force's
+    pressure is F.d / (4 pi r^3) (a torque's stresslet adds O(1/r^3))."""
+    g = np.random.default_rng(44)
+    q, F, T = _spheroid_case(g, axes)
+    part = {"axes": axes, "q": q, "F": F, "T": T}
+    mu = 0.3
+    a = axes[0]
+    e = g.standard_normal((30, 3))
+    e /= np.linalg.norm(e, axis=1)[:, None]
+    d = e * g.uniform(1.4 * a, 2.5 * a, (30, 1))
+    h = 3e-3
+    I = np.eye(3)
+    grad = np.stack([(S.particle_pressure(d + h * I[k], part, mu) - S.particle_pressure(d - h * I[k], part, mu))
+                     / (2 * h) for k in range(3)], 1)
+    lap = sum(S.particle_flow(d + h * I[k], part, mu) + S.particle_flow(d - h * I[k], part, mu)
+              for k in range(3)) - 6 * S.particle_flow(d, part, mu)
+    lap /= h * h
+    assert np.abs(grad - mu * lap).max() < 1e-5 * np.abs(grad).max()
+    far = 1e4 * a * e
+    ref = (far @ F) / (4 * math.pi * np.linalg.norm(far, axis=1) ** 3)
+    force_only = dict(part, T=np.zeros(3))
+    assert np.allclose(S.particle_pressure(far, force_only, mu), ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+
+
+def test_periodic_pressure_modes_near_a_small_sphere():
+    """Summed over all wave vectors, the periodic pressure of a force spread
+    on a small sphere gives the point force's F.d / (4 pi r^3) near it, up to
+    the images' O(1/V) correction (the mean force is balanced by the
+    box-wide counter-force, which drives no pressure)."""
+    n = _ball(48)
+    k = 2 * np.pi * n
+    F = np.array([0.3, -1.0, 0.5])
+    pk = S.periodic_pressure_modes(k, F, 0.05, 1.0)
+    for d in (np.array([0.12, 0.03, 0.0]), np.array([0.1, -0.05, 0.04])):
+        v = (pk * np.exp(1j * (k @ d))).sum().real
+        ref = (F @ d) / (4 * math.pi * np.linalg.norm(d) ** 3)
+        assert abs(v - ref) < 0.02 * abs(ref) + 0.05
