@@ -457,13 +457,17 @@ lb_status lb_warm_status(lb_ctx* ctx, int* status, long long* decided_step);
  * along an edge shorter than 5) are replaced by those of the periodic flow
  * of the same loads (the force spread as the traction on the translating
  * ellipsoid, the torque as uniform traction on the sphere of radius R), so
- * the box's slowest shear modes start at their steady values.  The fluid
- * nodes then lose the uniform velocity that makes the box's total momentum
- * (fluid at rho0 plus the particles' M U) zero; nodes inside a particle move
- * rigidly with its current U, Omega.  Every node is set to the second-order
- * equilibrium at rho0 and its velocity (mass is unchanged).  The free flow
- * is staged in the population buffer that does not hold the state (no
- * allocation).  LB_EINVAL if a box has walls.  Synchronises. */
+ * the box's slowest shear modes start at their steady values; the same for
+ * the flow's pressure p (the Stokeslets' and stresslets'; the periodic
+ * modes -i (k.f) / k^2 of the force density f).  A fluid node gets the
+ * density rho0 + 3 (p - pbar), pbar the mean over the box's fluid nodes, and
+ * the fluid nodes then lose the uniform velocity that makes the box's total
+ * momentum (fluid sum rho u plus the particles' M U) zero; nodes inside a
+ * particle have rho0 and move rigidly with its current U, Omega.  Every node
+ * is set to the second-order equilibrium at its density and velocity (mass
+ * is unchanged).  The free flow is staged in the population buffer that
+ * does not hold the state (no allocation).  LB_EINVAL if a box has walls.
+ * Synchronises. */
 lb_status lb_stokes_start(lb_ctx* ctx);
 
 /* Training sample of every particle at its current state: the surrogate's

@@ -18,18 +18,21 @@
 //
 // Start field: the creeping flow the particles' loads drive in the periodic
 // box.  Per node, the sum over the box's particles of the free-space flow
-// that the particle's load drives (particle_flow: the exact flow of a
-// prolate spheroid, else that of the equal-volume sphere; minimum-image
-// offsets, rigid inside the body), computed once per node (k_stokes_free)
-// -- whose Fourier modes |n_i| <= 2 are replaced by those of the periodic
-// solution of the same loads (the force spread as the traction on the
-// translating ellipsoid, the torque over the sphere of radius Req), so the
-// box's slowest shear modes start at their steady values; then the uniform
-// velocity that makes the box's total momentum (fluid at rho0 plus
-// particles) zero is removed from the fluid nodes, and nodes inside particle
-// p move rigidly with its U, Omega.  Every node gets the second-order
-// equilibrium at rho0 and its velocity, written as pre-collision populations
-// (slot (x - c_i, i)).
+// and pressure that the particle's load drives (particle_flow: the exact
+// flow of a prolate spheroid, else that of the equal-volume sphere;
+// minimum-image offsets, rigid inside the body), computed once per node
+// (k_stokes_free) -- whose Fourier modes |n_i| <= 2 are replaced by those of
+// the periodic solution of the same loads (the force spread as the traction
+// on the translating ellipsoid, the torque over the sphere of radius Req),
+// so the box's slowest shear modes start at their steady values.  A fluid
+// node's density carries the pressure, rho = rho0 + (p - pbar) / c_s^2 (pbar
+// the fluid's mean: the mass is unchanged; without it the pressure builds up
+// through sound waves that ring in the box for hundreds of steps), and the
+// uniform velocity that makes the box's total momentum (fluid sum rho u plus
+// particles) zero is removed; nodes inside particle p have rho0 and move
+// rigidly with its U, Omega.  Every node gets the second-order equilibrium
+// at its density and velocity, written as pre-collision populations (slot
+// (x - c_i, i)).
 #include <type_traits>
 
 #include "lbell_dev.h"
@@ -178,14 +181,21 @@ __constant__ double GL24[12][2] = {
 // Below this eccentricity a prolate spheroid's flow is taken as the sphere's
 // (the two differ by O(e^2)).
 constexpr double E_LINE = 1e-4;
+constexpr int UF = 4;  // doubles per node of the staged free field: velocity, pressure
+constexpr int MC = 8;  // doubles per mode: (re, im) of velocity and pressure
+constexpr int NPART = 8;  // partial sums per tile of k_stokes_sum
 
 __device__ __forceinline__ bool loaded(const PartDev& P) {
     return P.Fext[0] != 0.0 || P.Fext[1] != 0.0 || P.Fext[2] != 0.0 || P.Text[0] != 0.0 || P.Text[1] != 0.0 ||
            P.Text[2] != 0.0;
 }
 
-// Free-space creeping flow that the load of particle P drives, added to u at
-// offset d from its centre; rigid motion inside the body.
+// Free-space creeping flow that the load of particle P drives, added to
+// (u[0..2], u[3]) = (velocity, pressure) at offset d from its centre; rigid
+// motion and no pressure inside the body.  The pressure is that of the
+// Stokeslets, 2 mu (s.r) / R^3, and of the stresslets, 2 mu (r.p)(r.m) / R^5
+// times theirs; the potential singularities and the rotlets carry none
+// (the sphere: 3 mu R (U.d) / (2 r^3) = F.d / (4 pi r^3)).
 //
 // Prolate spheroid (a > b = c): the exact solution of Chwang & Wu (J. Fluid
 // Mech. 63, 1974; 67, 1975) as singularities on the focal segment |xi| <= f,
@@ -209,7 +219,7 @@ __device__ __forceinline__ bool loaded(const PartDev& P) {
 // Every other shape: the sphere of radius Req = (abc)^(1/3) moving with
 // F / (6 pi mu Req) and turning with T / (8 pi mu Req^3) (Stokes' solution
 // and the rotlet), rigid inside Req.
-__device__ void particle_flow(const PartDev& P, double mu, const double d[3], double u[3]) {
+__device__ void particle_flow(const PartDev& P, double mu, const double d[3], double u[4]) {
     const double a = P.axes[0], b = P.axes[1];
     const double e2 = a > b && b == P.axes[2] ? 1.0 - (b / a) * (b / a) : 0.0;
     if (e2 < E_LINE * E_LINE) {
@@ -228,6 +238,7 @@ __device__ void particle_flow(const PartDev& P, double mu, const double d[3], do
         const double a1 = 0.75 * R / r, a3 = 0.25 * R * R * R / (r * r * r), rr = (R / r) * (R / r) * (R / r);
         for (int k = 0; k < 3; ++k)
             u[k] += a1 * (U[k] + Ue * ex[k]) + a3 * (U[k] - 3.0 * Ue * ex[k]) + rr * wx[k];
+        u[3] += 1.5 * mu * R * Ue / (r * r);
         return;
     }
     const double e = sqrt(e2), f = a * e;
@@ -273,7 +284,7 @@ __device__ void particle_flow(const PartDev& P, double mu, const double d[3], do
     }
     const double x0 = fmin(fmax(z, -f), f);
     const double delta = sqrt(rho2 + (z - x0) * (z - x0));  // > 0: the segment lies inside the body
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int side = 0; side < 2; ++side) {
         const double sgn = side ? 1.0 : -1.0, len = side ? f - x0 : x0 + f;
         if (len <= 0.0) continue;
@@ -301,14 +312,15 @@ __device__ void particle_flow(const PartDev& P, double mu, const double d[3], do
                                  + cQ * (3.0 * (m[k] * rp + rm * p[k]) * iR5 - 15.0 * rm * rp * r[k] * iR7);
                 acc[k] += wq * v;
             }
+            acc[3] += wq * 2.0 * mu * (Sr * iR3 + dl * g * rp * rm * iR5);
         }
     }
-    for (int k = 0; k < 3; ++k) u[k] += acc[k];
+    for (int k = 0; k < 4; ++k) u[k] += acc[k];
 }
 
-// Free-space flow of every node of the started boxes (the sum over each
-// box's loaded particles of particle_flow), node-major into uf at
-// 3 (ooff + site - base).  A work-group per tile; the box's loaded particles
+// Free-space flow and pressure of every node of the started boxes (the sum
+// over each box's loaded particles of particle_flow), node-major into uf at
+// UF * (ooff + site - base).  A work-group per tile; the box's loaded particles
 // are listed in index order, TILE at a time, in LDS.
 __global__ __launch_bounds__(TILE) void k_stokes_free(const BoxDesc* __restrict__ boxes,
                                                       const int* __restrict__ tile_box,
@@ -322,7 +334,7 @@ __global__ __launch_bounds__(TILE) void k_stokes_free(const BoxDesc* __restrict_
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + tid;
     const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
-    double u[3] = {0.0, 0.0, 0.0};
+    double u[UF] = {0.0, 0.0, 0.0, 0.0};
     for (int p0 = 0; p0 < np; p0 += TILE) {
         const int p = p0 + tid;
         const bool take = p < np && parts[p].box == bi && loaded(parts[p]);
@@ -346,10 +358,8 @@ __global__ __launch_bounds__(TILE) void k_stokes_free(const BoxDesc* __restrict_
         __syncthreads();
     }
     if (s < B.n) {
-        double* o = uf + 3 * (B.ooff + s - base);
-        o[0] = u[0];
-        o[1] = u[1];
-        o[2] = u[2];
+        double* o = uf + UF * (B.ooff + s - base);
+        for (int k = 0; k < UF; ++k) o[k] = u[k];
     }
 }
 
@@ -374,7 +384,7 @@ __device__ __forceinline__ void twiddles(int x, int L, double e[2 * WK + 1][2]) 
     e[WK - 2][1] = -s2;
 }
 
-__device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x, int y, int z, double u[3]) {
+__device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x, int y, int z, double u[UF]) {
     const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
     double ex[2 * WK + 1][2], ey[2 * WK + 1][2], ez[2 * WK + 1][2];
     twiddles(x, B.nx, ex);
@@ -389,19 +399,19 @@ __device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x
                 const double er = ex[nx + WK][0] * pr - ex[nx + WK][1] * pi;
                 const double ei = ex[nx + WK][0] * pi + ex[nx + WK][1] * pr;
                 const int m = (nx + WK) + (2 * WK + 1) * ((ny + WK) + (2 * WK + 1) * (nz + WK));
-                const double* cm = c + 6 * m;
-                for (int k = 0; k < 3; ++k) u[k] += cm[2 * k] * er - cm[2 * k + 1] * ei;
+                const double* cm = c + MC * m;
+                for (int k = 0; k < UF; ++k) u[k] += cm[2 * k] * er - cm[2 * k + 1] * ei;
             }
         }
     }
 }
 
-// Velocity of site s = (x, y, z) of box bi before the mean correction: rigid
-// motion inside a particle, else the corrected load-driven flow (uf: the
-// free flow of k_stokes_free).
+// Velocity and pressure of site s = (x, y, z) of box bi before the mean
+// corrections: rigid motion and no pressure inside a particle, else the
+// corrected load-driven flow (uf: the free flow of k_stokes_free).
 __device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const PartDev* __restrict__ parts,
                                const double* __restrict__ uf, long long base, const double* __restrict__ coef, int s,
-                               int x, int y, int z, double u[3]) {
+                               int x, int y, int z, double u[UF]) {
     if (owner != 0) {
         const PartDev& P = parts[owner - 1];
         double d[3];
@@ -409,13 +419,12 @@ __device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const P
         u[0] = P.U[0] + P.W[1] * d[2] - P.W[2] * d[1];
         u[1] = P.U[1] + P.W[2] * d[0] - P.W[0] * d[2];
         u[2] = P.U[2] + P.W[0] * d[1] - P.W[1] * d[0];
+        u[3] = 0.0;
         return;
     }
-    const double* o = uf + 3 * (B.ooff + s - base);
-    u[0] = o[0];
-    u[1] = o[1];
-    u[2] = o[2];
-    correction(B, coef + (long long)bi * WM * 6, x, y, z, u);
+    const double* o = uf + UF * (B.ooff + s - base);
+    for (int k = 0; k < UF; ++k) u[k] = o[k];
+    correction(B, coef + (long long)bi * WM * MC, x, y, z, u);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -423,27 +432,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Discrete Fourier sums S_m = sum_x u_free(x) exp(-i k_m . x) over every node
-// of a box, for the modes of one (ny, nz) pair (blockIdx.y) and all nx.
+// Discrete Fourier sums S_m = sum_x (u, p)_free(x) exp(-i k_m . x) over every
+// node of a box, for the modes of one (ny, nz) pair (blockIdx.y) and all nx.
 __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict__ boxes,
                                                       const double* __restrict__ uf, long long base, int only_box,
                                                       double* __restrict__ S) {
-    __shared__ double red[4][2 * WK + 1][6];
+    __shared__ double red[4][2 * WK + 1][MC];
     const int bi = blockIdx.x, g = blockIdx.y;
     if (only_box >= 0 && bi != only_box) return;  // uniform over the block
     const BoxDesc& B = boxes[bi];
     const int ny_ = g % (2 * WK + 1) - WK, nz_ = g / (2 * WK + 1) - WK;
     const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
     if (abs(ny_) > Ky || abs(nz_) > Kz) return;  // uniform over the block
-    double acc[2 * WK + 1][6];
+    double acc[2 * WK + 1][MC];
 #pragma unroll
     for (int a = 0; a < 2 * WK + 1; ++a)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc[a][k] = 0.0;
+        for (int k = 0; k < MC; ++k) acc[a][k] = 0.0;
     for (int s = threadIdx.x; s < B.n; s += blockDim.x) {
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
-        const double* o = uf + 3 * (B.ooff + s - base);
-        const double u[3] = {o[0], o[1], o[2]};
+        const double* o = uf + UF * (B.ooff + s - base);
+        const double u[UF] = {o[0], o[1], o[2], o[3]};
         double syz, cyz;
         sincospi(2.0 * ((double)ny_ * y / B.ny + (double)nz_ * z / B.nz), &syz, &cyz);
         double ex[2 * WK + 1][2];
@@ -455,7 +464,7 @@ __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict_
             // exp(-i theta) = cos theta - i sin theta, theta = kx x + ky y + kz z
             const double c = cx_ * cyz - sx * syz, sn = sx * cyz + cx_ * syz;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < UF; ++k) {
                 acc[nx + WK][2 * k] += u[k] * c;
                 acc[nx + WK][2 * k + 1] -= u[k] * sn;
             }
@@ -465,22 +474,24 @@ __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict_
 #pragma unroll
     for (int a = 0; a < 2 * WK + 1; ++a)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < MC; ++k) {
             const double v = wave_sum(acc[a][k]);
             if (lane == 0) red[wv][a][k] = v;
         }
     __syncthreads();
-    if (threadIdx.x < (2 * WK + 1) * 6) {
-        const int a = threadIdx.x / 6, k = threadIdx.x % 6;
+    if (threadIdx.x < (2 * WK + 1) * MC) {
+        const int a = threadIdx.x / MC, k = threadIdx.x % MC;
         const double v = red[0][a][k] + red[1][a][k] + red[2][a][k] + red[3][a][k];
         const int m = a + (2 * WK + 1) * ((ny_ + WK) + (2 * WK + 1) * (nz_ + WK));
-        S[((long long)bi * WM + m) * 6 + k] = v;
+        S[((long long)bi * WM + m) * MC + k] = v;
     }
 }
 
 // Correction coefficients: one thread per (box, mode slot): the periodic
 // solution's coefficient of every particle of the box minus the free flow's
-// DFT coefficient S_m / N; zero for slots outside the box's mode set.
+// DFT coefficient S_m / N; zero for slots outside the box's mode set.  The
+// pressure's is -i (k.f) / k^2 of the force density f (the torque's has no
+// divergence and drives none).
 __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, const PartDev* __restrict__ parts,
                               int np, double mu, const double* __restrict__ S, double* __restrict__ C) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -489,10 +500,10 @@ __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, con
     const BoxDesc& B = boxes[bi];
     const int n[3] = {m % (2 * WK + 1) - WK, (m / (2 * WK + 1)) % (2 * WK + 1) - WK, m / ((2 * WK + 1) * (2 * WK + 1)) - WK};
     const int L[3] = {B.nx, B.ny, B.nz};
-    double* c = C + (long long)id * 6;
+    double* c = C + (long long)id * MC;
     bool use = !(n[0] == 0 && n[1] == 0 && n[2] == 0);
     for (int a = 0; a < 3; ++a) use = use && abs(n[a]) <= wk_axis(L[a]);
-    for (int k = 0; k < 6; ++k) c[k] = 0.0;
+    for (int k = 0; k < MC; ++k) c[k] = 0.0;
     if (!use) return;
     const double V = (double)B.n;
     double k[3];
@@ -525,14 +536,18 @@ __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, con
             c[2 * a] += re * cp - im * sp;
             c[2 * a + 1] += re * sp + im * cp;
         }
+        const double pim = -kF * sinc / k2 / V;  // p_hat / V = i pim
+        c[6] += -pim * sp;
+        c[7] += pim * cp;
     }
-    for (int a = 0; a < 3; ++a) {
-        c[2 * a] -= S[(long long)id * 6 + 2 * a] / V;
-        c[2 * a + 1] -= S[(long long)id * 6 + 2 * a + 1] / V;
+    for (int a = 0; a < UF; ++a) {
+        c[2 * a] -= S[(long long)id * MC + 2 * a] / V;
+        c[2 * a + 1] -= S[(long long)id * MC + 2 * a + 1] / V;
     }
 }
 
-// partial sums over the fluid nodes of each tile: sum of u (3) and the count
+// partial sums over the fluid nodes of each tile: sum of u (3), of p u (3),
+// of p and the count
 __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__ boxes,
                                                      const int* __restrict__ tile_box,
                                                      const uint16_t* __restrict__ omap,
@@ -540,40 +555,54 @@ __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__
                                                      const double* __restrict__ uf, long long base, int only_box,
                                                      const double* __restrict__ coef,
                                                      double* __restrict__ partial) {
-    __shared__ double red[4][TILE];
+    __shared__ double red[NPART][TILE];
     const int tile = blockIdx.x, tid = threadIdx.x;
     const int bi = tile_box[tile];
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + tid;
-    double v[4] = {0, 0, 0, 0};
+    double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
     if ((only_box < 0 || bi == only_box) && s < B.n && omap[B.ooff + s] == 0) {
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
-        start_velocity(B, bi, 0, parts, uf, base, coef, s, x, y, z, v);
-        v[3] = 1.0;
+        double u[UF];
+        start_velocity(B, bi, 0, parts, uf, base, coef, s, x, y, z, u);
+        for (int k = 0; k < 3; ++k) {
+            v[k] = u[k];
+            v[3 + k] = u[3] * u[k];
+        }
+        v[6] = u[3];
+        v[7] = 1.0;
     }
-    for (int k = 0; k < 4; ++k) red[k][tid] = v[k];
+    for (int k = 0; k < NPART; ++k) red[k][tid] = v[k];
     __syncthreads();
     for (int h = TILE / 2; h > 0; h >>= 1) {
         if (tid < h)
-            for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + h];
+            for (int k = 0; k < NPART; ++k) red[k][tid] += red[k][tid + h];
         __syncthreads();
     }
-    if (tid < 4) partial[(long long)tile * 4 + tid] = red[tid][0];
+    if (tid < NPART) partial[(long long)tile * NPART + tid] = red[tid][0];
 }
 
-// one thread per box: the uniform velocity removed from its fluid nodes
+// One thread per box: the mean pressure pbar of its fluid nodes and the
+// uniform velocity ubar removed from them.  A fluid node gets the density
+// rho = rho0 + 3 (p - pbar) (p = c_s^2 (rho - rho0)), so the fluid's mass is
+// unchanged, and ubar = (sum rho u + sum_p M U) / (N rho0) makes the box's
+// momentum sum rho (u - ubar) + sum_p M U zero.
 __global__ void k_stokes_mean(const BoxDesc* __restrict__ boxes, int nboxes, const PartDev* __restrict__ parts,
                               int np, const double* __restrict__ partial, double rho0, double* __restrict__ ubar) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nboxes) return;
     const BoxDesc& B = boxes[b];
-    double S[4] = {0, 0, 0, 0};
+    double S[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int t = B.tile0; t < B.tile0 + B.ntiles; ++t)
-        for (int k = 0; k < 4; ++k) S[k] += partial[(long long)t * 4 + k];
+        for (int k = 0; k < NPART; ++k) S[k] += partial[(long long)t * NPART + k];
+    const double N = S[7], pbar = N > 0 ? S[6] / N : 0.0;
+    double J[3];
+    for (int k = 0; k < 3; ++k) J[k] = rho0 * S[k] + 3.0 * (S[3 + k] - pbar * S[k]);
     for (int p = 0; p < np; ++p)
         if (parts[p].box == b)
-            for (int k = 0; k < 3; ++k) S[k] += parts[p].M * parts[p].U[k] / rho0;
-    for (int k = 0; k < 3; ++k) ubar[3 * b + k] = S[3] > 0 ? S[k] / S[3] : 0.0;
+            for (int k = 0; k < 3; ++k) J[k] += parts[p].M * parts[p].U[k];
+    for (int k = 0; k < 3; ++k) ubar[4 * b + k] = N > 0 ? J[k] / (N * rho0) : 0.0;
+    ubar[4 * b + 3] = pbar;
 }
 
 template <int ST, int Q>
@@ -597,16 +626,20 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     if (owner == 0xFFFF) return;
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
-    double u[3];
+    double u[UF];
     start_velocity(B, bi, owner, parts, uf, base, coef, s, x, y, z, u);
-    if (owner == 0)
-        for (int k = 0; k < 3; ++k) u[k] -= ubar[3 * bi + k];
-    const double rho0 = kp.rho0, uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double rho0 = kp.rho0;
+    double rho = rho0;
+    if (owner == 0) {
+        for (int k = 0; k < 3; ++k) u[k] -= ubar[4 * bi + k];
+        rho = rho0 + 3.0 * (u[3] - ubar[4 * bi + 3]);
+    }
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     typename S::T* fb = f + B.foff;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-        const double dev = wgt<Q>(i) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const double dev = wgt<Q>(i) * ((rho - rho0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
         // the slot node (x, y, z) reads f_i from at the next step (no walls here)
         int d, slot;
         pre_slot_open(kp.conv, i, x, y, z, nx, ny, nz, d, slot);
@@ -779,15 +812,18 @@ hipError_t launch_warm_targets(const PartDev* parts, int np, const double* s, do
     return hipGetLastError();
 }
 
-size_t stokes_scratch_doubles(int nboxes, int ntiles) { return (size_t)nboxes * WM * 6 * 2 + (size_t)ntiles * 4 + 3 * (size_t)nboxes; }
+size_t stokes_scratch_doubles(int nboxes, int ntiles) {
+    return (size_t)nboxes * WM * MC * 2 + (size_t)ntiles * NPART + 4 * (size_t)nboxes;
+}
+int stokes_free_doubles() { return UF; }
 
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
                                const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
                                double* uf, long long base, void* f, const KParams& kp, int only_box, hipStream_t st) {
     double* S = scratch;
-    double* C = S + (size_t)nboxes * WM * 6;
-    double* partial = C + (size_t)nboxes * WM * 6;
-    double* ubar = partial + (size_t)ntiles * 4;
+    double* C = S + (size_t)nboxes * WM * MC;
+    double* partial = C + (size_t)nboxes * WM * MC;
+    double* ubar = partial + (size_t)ntiles * NPART;
     hipLaunchKernelGGL(k_stokes_free, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, parts, np, mu, only_box, base,
                        uf);
     hipLaunchKernelGGL(k_stokes_modes, dim3(nboxes, (2 * WK + 1) * (2 * WK + 1)), dim3(256), 0, st, boxes, uf, base,

@@ -1391,10 +1391,11 @@ lb_status stokes_start(lb_ctx* ctx, int only_box = -1) {
         if ((only_box < 0 || (int)b == only_box) && ctx->boxes[b].walls)
             return fail(ctx, LB_EINVAL, "the start field is defined for periodic boxes only");
     double* scratch = ctx->at<double>(ctx->L.warm) + 14 * (size_t)ctx->L.max_particles;
-    // the nodes' free flow goes to the population buffer that does not hold
-    // the state (the next step's output, or unused in place): 3 doubles per
-    // node fit in the Q >= 19 populations of >= 2 bytes each
-    if ((size_t)ctx->L.omap_elems * 3 * sizeof(double) > (size_t)ctx->L.pop_elems * storage_bytes(ctx->cfg.storage))
+    // the nodes' free flow and pressure go to the population buffer that does
+    // not hold the state (the next step's output, or unused in place): 4
+    // doubles per node fit in the Q >= 19 populations of >= 2 bytes each
+    if ((size_t)ctx->L.omap_elems * stokes_free_doubles() * sizeof(double) >
+        (size_t)ctx->L.pop_elems * storage_bytes(ctx->cfg.storage))
         return fail(ctx, LB_EINVAL, "population buffer too small for the start field's scratch");
     const long long base = only_box >= 0 ? ctx->hbox[only_box].ooff : 0;
     HIPC(launch_stokes_start(ctx->at<BoxDesc>(ctx->L.boxes), (int)ctx->boxes.size(), ctx->at<int>(ctx->L.tile_box),

@@ -133,8 +133,10 @@ hipError_t launch_warm_apply(PartDev* parts, int np, const float* Y, const doubl
                              int only_box, hipStream_t st);
 hipError_t launch_warm_targets(const PartDev* parts, int np, const double* s, double mu, float* Y, hipStream_t st);
 size_t stokes_scratch_doubles(int nboxes, int ntiles);  // scratch of launch_stokes_start
-// only_box >= 0: that box only (every box otherwise).  uf: 3 doubles per
-// node of the started boxes, node (box B, site s) at 3 (B.ooff + s - base).
+int stokes_free_doubles();  // doubles per node of its staged free field (uf)
+// only_box >= 0: that box only (every box otherwise).  uf: stokes_free_doubles()
+// doubles per node of the started boxes, node (box B, site s) at that many
+// times (B.ooff + s - base).
 hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile_box, int ntiles,
                                const uint16_t* omap, const PartDev* parts, int np, double mu, double* scratch,
                                double* uf, long long base, void* f, const KParams& kp, int only_box, hipStream_t st);
