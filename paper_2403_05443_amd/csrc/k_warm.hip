@@ -167,15 +167,23 @@ constexpr int WM = (2 * WK + 1) * (2 * WK + 1) * (2 * WK + 1);  // mode slots pe
 
 __device__ __forceinline__ int wk_axis(int L) { return min(WK, (L - 1) / 2); }
 
-// 24-point Gauss-Legendre rule on [-1, 1]: the positive nodes and their
-// weights (the rule is symmetric).
-__constant__ double GL24[12][2] = {
+// Gauss-Legendre rules on [-1, 1] of 24, 16 and 12 points, one table: the
+// positive nodes and their weights of each (the rules are symmetric), at
+// rows 0, 12 and 20.
+__constant__ double GLTAB[26][2] = {
     {0.06405689286260563, 0.12793819534675221}, {0.1911188674736163, 0.1258374563468283},
     {0.3150426796961634, 0.12167047292780342},  {0.4337935076260451, 0.11550566805372561},
     {0.5454214713888396, 0.1074442701159656},   {0.6480936519369755, 0.09761865210411406},
     {0.7401241915785544, 0.08619016153195329},  {0.820001985973903, 0.07334648141108041},
     {0.886415527004401, 0.05929858491543674},   {0.9382745520027328, 0.04427743881741955},
     {0.9747285559713095, 0.028531388628933743}, {0.9951872199970213, 0.012341229799987091},
+    {0.09501250983763745, 0.18945061045506859}, {0.2816035507792589, 0.1826034150449236},
+    {0.45801677765722737, 0.16915651939500262}, {0.6178762444026438, 0.14959598881657676},
+    {0.755404408355003, 0.12462897125553403},   {0.8656312023878318, 0.09515851168249259},
+    {0.9445750230732326, 0.062253523938647706}, {0.9894009349916499, 0.027152459411754037},
+    {0.1252334085114689, 0.2491470458134027},   {0.3678314989981802, 0.23349253653835464},
+    {0.5873179542866175, 0.20316742672306565},  {0.7699026741943047, 0.1600783285433461},
+    {0.9041172563704748, 0.10693932599531888},  {0.9815606342467192, 0.04717533638651202},
 };
 
 // Below this eccentricity a prolate spheroid's flow is taken as the sphere's
@@ -214,8 +222,10 @@ __device__ __forceinline__ bool loaded(const PartDev& P) {
 // (1 - e^2) L, L = ln((1 + e) / (1 - e)) (power series below e = 1/2, where
 // they cancel).  The segment integrals are taken with the substitution
 // xi = xi0 -+ delta sinh(t) about the point xi0 of the segment nearest d
-// (delta the distance to it), which smooths the near-tip peaks, and 24
-// Gauss-Legendre points on each side of xi0.
+// (delta the distance to it), which smooths the near-tip peaks, and
+// Gauss-Legendre points on each side of xi0: 24 within delta < f / 2, 16
+// within delta < 3 f / 2, 12 beyond (each within ~2e-15 of the integral,
+// relative to the velocity, measured against adaptive quadrature).
 // Every other shape: the sphere of radius Req = (abc)^(1/3) moving with
 // F / (6 pi mu Req) and turning with T / (8 pi mu Req^3) (Stokes' solution
 // and the rotlet), rigid inside Req.
@@ -285,13 +295,15 @@ __device__ void particle_flow(const PartDev& P, double mu, const double d[3], do
     const double x0 = fmin(fmax(z, -f), f);
     const double delta = sqrt(rho2 + (z - x0) * (z - x0));  // > 0: the segment lies inside the body
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int ng = delta < 0.5 * f ? 24 : delta < 1.5 * f ? 16 : 12, half = ng / 2;
+    const int row = ng == 24 ? 0 : ng == 16 ? 12 : 20;
     for (int side = 0; side < 2; ++side) {
         const double sgn = side ? 1.0 : -1.0, len = side ? f - x0 : x0 + f;
         if (len <= 0.0) continue;
         const double tm = asinh(len / delta);
-        for (int j = 0; j < 24; ++j) {
-            const double tj = j < 12 ? -GL24[11 - j][0] : GL24[j - 12][0];
-            const double wj = j < 12 ? GL24[11 - j][1] : GL24[j - 12][1];
+        for (int j = 0; j < ng; ++j) {
+            const int ri = row + (j < half ? half - 1 - j : j - half);
+            const double tj = j < half ? -GLTAB[ri][0] : GLTAB[ri][0], wj = GLTAB[ri][1];
             const double t = 0.5 * tm * (tj + 1.0), et = exp(t), it = 1.0 / et;
             const double xi = x0 + sgn * delta * 0.5 * (et - it);
             const double wq = 0.5 * tm * wj * delta * 0.5 * (et + it);

@@ -1393,14 +1393,24 @@ lb_status stokes_start(lb_ctx* ctx, int only_box = -1) {
     double* scratch = ctx->at<double>(ctx->L.warm) + 14 * (size_t)ctx->L.max_particles;
     // the nodes' free flow and pressure go to the population buffer that does
     // not hold the state (the next step's output, or unused in place): 4
-    // doubles per node fit in the Q >= 19 populations of >= 2 bytes each
-    if ((size_t)ctx->L.omap_elems * stokes_free_doubles() * sizeof(double) >
-        (size_t)ctx->L.pop_elems * storage_bytes(ctx->cfg.storage))
+    // doubles per node fit in the Q >= 19 populations of >= 2 bytes each.
+    // One box: into that box's own block of it, so other boxes' blocks (a
+    // walled box's never-written wall rows among them) keep their contents.
+    const size_t es = storage_bytes(ctx->cfg.storage), need = stokes_free_doubles() * sizeof(double);
+    char* spare = (char*)ctx->spare_buf();
+    long long base = 0;
+    if (only_box >= 0) {
+        const BoxDesc& B = ctx->hbox[only_box];
+        if ((size_t)B.n * need > (size_t)ctx->cfg.lattice * B.stride * es)
+            return fail(ctx, LB_EINVAL, "population block too small for the start field's scratch");
+        spare += (size_t)B.foff * es;  // foff is a multiple of 128 elements: 8-byte aligned
+        base = B.ooff;
+    } else if ((size_t)ctx->L.omap_elems * need > (size_t)ctx->L.pop_elems * es) {
         return fail(ctx, LB_EINVAL, "population buffer too small for the start field's scratch");
-    const long long base = only_box >= 0 ? ctx->hbox[only_box].ooff : 0;
+    }
     HIPC(launch_stokes_start(ctx->at<BoxDesc>(ctx->L.boxes), (int)ctx->boxes.size(), ctx->at<int>(ctx->L.tile_box),
                              ctx->L.total_tiles, ctx->at<uint16_t>(ctx->L.omap), ctx->at<PartDev>(ctx->L.parts),
-                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, (double*)ctx->spare_buf(), base,
+                             ctx->np, viscosity(ctx) * ctx->kp.rho0, scratch, (double*)spare, base,
                              ctx->fbuf(ctx->cur), ctx->kp, only_box, ctx->stream));
     return LB_OK;
 }
