@@ -380,9 +380,7 @@ __global__ __launch_bounds__(TILE) void k_stokes_free(const BoxDesc* __restrict_
 // exp(i 2 pi n x / L) for n = -WK..WK (WK = 2) into e[n + WK] (re, im):
 // powers of the n = 1 term, the negative ones conjugate.
 static_assert(WK == 2, "twiddles() builds the modes |n| <= 2");
-__device__ __forceinline__ void twiddles(int x, int L, double e[2 * WK + 1][2]) {
-    double s1, c1;
-    sincospi(2.0 * x / L, &s1, &c1);
+__device__ __forceinline__ void powers(double c1, double s1, double e[2 * WK + 1][2]) {
     const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * s1 * c1;
     e[WK][0] = 1.0;
     e[WK][1] = 0.0;
@@ -396,34 +394,61 @@ __device__ __forceinline__ void twiddles(int x, int L, double e[2 * WK + 1][2]) 
     e[WK - 2][1] = -s2;
 }
 
-__device__ void correction(const BoxDesc& B, const double* __restrict__ c, int x, int y, int z, double u[UF]) {
-    const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
-    double ex[2 * WK + 1][2], ey[2 * WK + 1][2], ez[2 * WK + 1][2];
-    twiddles(x, B.nx, ex);
-    twiddles(y, B.ny, ey);
-    twiddles(z, B.nz, ez);
-    for (int nz = -Kz; nz <= Kz; ++nz) {
-        const double cz = ez[nz + WK][0], sz = ez[nz + WK][1];
-        for (int ny = -Ky; ny <= Ky; ++ny) {
-            const double cy = ey[ny + WK][0], sy = ey[ny + WK][1];
-            const double pr = cy * cz - sy * sz, pi = sy * cz + cy * sz;  // exp(i (ky y + kz z))
-            for (int nx = -Kx; nx <= Kx; ++nx) {
-                const double er = ex[nx + WK][0] * pr - ex[nx + WK][1] * pi;
-                const double ei = ex[nx + WK][0] * pi + ex[nx + WK][1] * pr;
-                const int m = (nx + WK) + (2 * WK + 1) * ((ny + WK) + (2 * WK + 1) * (nz + WK));
-                const double* cm = c + MC * m;
-                for (int k = 0; k < UF; ++k) u[k] += cm[2 * k] * er - cm[2 * k + 1] * ei;
-            }
-        }
-    }
+__device__ __forceinline__ void twiddles(int x, int L, double e[2 * WK + 1][2]) {
+    double s1, c1;
+    sincospi(2.0 * x / L, &s1, &c1);
+    powers(c1, s1, e);
 }
 
-// Velocity and pressure of site s = (x, y, z) of box bi before the mean
+// The periodic correction Re sum_m c_m exp(i k_m . x) at the nodes of one
+// tile, in two stages.  row_coefs (every thread of the work-group calls it):
+// for each row (y, z) the tile touches, R[a][k] = sum over (ny, nz) of
+// c_(a, ny, nz)[k] exp(i (ky y + kz z)) into LDS (slots outside the box's
+// mode set hold c = 0); then a node's correction is Re sum_a R[a][k]
+// exp(i kx x) (start_velocity).  c: the box's WM x MC coefficients.
+constexpr int CROWS = TILE / 4 + 2;  // rows a tile can touch (edges are at least 4)
+struct RowCoefs {
+    double tw[CROWS][2][2 * WK + 1][2];  // exp(i 2 pi n y / ny), exp(i 2 pi n z / nz) of each row
+    double R[CROWS][2 * WK + 1][UF][2];
+    int row0;
+};
+
+__device__ void row_coefs(const BoxDesc& B, const double* __restrict__ c, int s0, RowCoefs& rc) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int row0 = s0 / B.nx, nrows = (min(s0 + TILE, B.n) - 1) / B.nx - row0 + 1;
+    if (tid == 0) rc.row0 = row0;
+    for (int r = tid; r < nrows; r += nt) {
+        const int row = row0 + r;
+        twiddles(row % B.ny, B.ny, rc.tw[r][0]);
+        twiddles(row / B.ny, B.nz, rc.tw[r][1]);
+    }
+    __syncthreads();
+    for (int t = tid; t < nrows * (2 * WK + 1) * UF; t += nt) {
+        const int r = t / ((2 * WK + 1) * UF), a = (t / UF) % (2 * WK + 1), k = t % UF;
+        double re = 0.0, im = 0.0;
+        for (int iz = 0; iz < 2 * WK + 1; ++iz) {
+            const double cz = rc.tw[r][1][iz][0], sz = rc.tw[r][1][iz][1];
+            for (int iy = 0; iy < 2 * WK + 1; ++iy) {
+                const double cy = rc.tw[r][0][iy][0], sy = rc.tw[r][0][iy][1];
+                const double er = cy * cz - sy * sz, ei = sy * cz + cy * sz;  // exp(i (ky y + kz z))
+                const double* cm = c + MC * (a + (2 * WK + 1) * (iy + (2 * WK + 1) * iz));
+                re += cm[2 * k] * er - cm[2 * k + 1] * ei;
+                im += cm[2 * k] * ei + cm[2 * k + 1] * er;
+            }
+        }
+        rc.R[r][a][k][0] = re;
+        rc.R[r][a][k][1] = im;
+    }
+    __syncthreads();
+}
+
+// Velocity and pressure of site s = (x, y, z) of box B before the mean
 // corrections: rigid motion and no pressure inside a particle, else the
-// corrected load-driven flow (uf: the free flow of k_stokes_free).
-__device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const PartDev* __restrict__ parts,
-                               const double* __restrict__ uf, long long base, const double* __restrict__ coef, int s,
-                               int x, int y, int z, double u[UF]) {
+// corrected load-driven flow (uf: the free flow of k_stokes_free; rc: the
+// tile's row_coefs).
+__device__ void start_velocity(const BoxDesc& B, uint16_t owner, const PartDev* __restrict__ parts,
+                               const double* __restrict__ uf, long long base, const RowCoefs& rc, int s, int x,
+                               int y, int z, double u[UF]) {
     if (owner != 0) {
         const PartDev& P = parts[owner - 1];
         double d[3];
@@ -436,7 +461,11 @@ __device__ void start_velocity(const BoxDesc& B, int bi, uint16_t owner, const P
     }
     const double* o = uf + UF * (B.ooff + s - base);
     for (int k = 0; k < UF; ++k) u[k] = o[k];
-    correction(B, coef + (long long)bi * WM * MC, x, y, z, u);
+    double ex[2 * WK + 1][2];
+    twiddles(x, B.nx, ex);
+    const int r = s / B.nx - rc.row0;
+    for (int a = 0; a < 2 * WK + 1; ++a)
+        for (int k = 0; k < UF; ++k) u[k] += rc.R[r][a][k][0] * ex[a][0] - rc.R[r][a][k][1] * ex[a][1];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -445,17 +474,31 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Discrete Fourier sums S_m = sum_x (u, p)_free(x) exp(-i k_m . x) over every
-// node of a box, for the modes of one (ny, nz) pair (blockIdx.y) and all nx.
+// node of a box, for the modes of one (ny, nz) pair and all nx: work-group
+// 25 b + g takes box b and pair g, so the 25 work-groups of a box run
+// together and stream its staged field through the caches about once.  Edges up to
+// TW_MAX take their phase factors from tables in LDS.
+constexpr int TW_MAX = 1024;
 __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict__ boxes,
                                                       const double* __restrict__ uf, long long base, int only_box,
                                                       double* __restrict__ S) {
     __shared__ double red[4][2 * WK + 1][MC];
-    const int bi = blockIdx.x, g = blockIdx.y;
+    __shared__ double tw[3][TW_MAX][2];  // exp(i 2 pi x / nx), exp(i 2 pi ny' y / ny), exp(i 2 pi nz' z / nz)
+    const int g = blockIdx.x % ((2 * WK + 1) * (2 * WK + 1)), bi = blockIdx.x / ((2 * WK + 1) * (2 * WK + 1));
     if (only_box >= 0 && bi != only_box) return;  // uniform over the block
     const BoxDesc& B = boxes[bi];
     const int ny_ = g % (2 * WK + 1) - WK, nz_ = g / (2 * WK + 1) - WK;
     const int Kx = wk_axis(B.nx), Ky = wk_axis(B.ny), Kz = wk_axis(B.nz);
     if (abs(ny_) > Ky || abs(nz_) > Kz) return;  // uniform over the block
+    const bool tab = B.nx <= TW_MAX && B.ny <= TW_MAX && B.nz <= TW_MAX;
+    if (tab) {
+        for (int i = threadIdx.x; i < B.nx; i += blockDim.x) sincospi(2.0 * i / B.nx, &tw[0][i][1], &tw[0][i][0]);
+        for (int i = threadIdx.x; i < B.ny; i += blockDim.x)
+            sincospi(2.0 * ny_ * i / B.ny, &tw[1][i][1], &tw[1][i][0]);
+        for (int i = threadIdx.x; i < B.nz; i += blockDim.x)
+            sincospi(2.0 * nz_ * i / B.nz, &tw[2][i][1], &tw[2][i][0]);
+    }
+    __syncthreads();
     double acc[2 * WK + 1][MC];
 #pragma unroll
     for (int a = 0; a < 2 * WK + 1; ++a)
@@ -465,10 +508,15 @@ __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict_
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
         const double* o = uf + UF * (B.ooff + s - base);
         const double u[UF] = {o[0], o[1], o[2], o[3]};
-        double syz, cyz;
-        sincospi(2.0 * ((double)ny_ * y / B.ny + (double)nz_ * z / B.nz), &syz, &cyz);
-        double ex[2 * WK + 1][2];
-        twiddles(x, B.nx, ex);
+        double syz, cyz, ex[2 * WK + 1][2];
+        if (tab) {
+            cyz = tw[1][y][0] * tw[2][z][0] - tw[1][y][1] * tw[2][z][1];
+            syz = tw[1][y][1] * tw[2][z][0] + tw[1][y][0] * tw[2][z][1];
+            powers(tw[0][x][0], tw[0][x][1], ex);
+        } else {
+            sincospi(2.0 * ((double)ny_ * y / B.ny + (double)nz_ * z / B.nz), &syz, &cyz);
+            twiddles(x, B.nx, ex);
+        }
 #pragma unroll
         for (int nx = -WK; nx <= WK; ++nx) {  // fixed trip count: the accumulators stay in registers
             if (nx < -Kx || nx > Kx) continue;
@@ -568,15 +616,18 @@ __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__
                                                      const double* __restrict__ coef,
                                                      double* __restrict__ partial) {
     __shared__ double red[NPART][TILE];
+    __shared__ RowCoefs rc;
     const int tile = blockIdx.x, tid = threadIdx.x;
     const int bi = tile_box[tile];
     const BoxDesc& B = boxes[bi];
     const int s = (tile - B.tile0) * TILE + tid;
     double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if ((only_box < 0 || bi == only_box) && s < B.n && omap[B.ooff + s] == 0) {
+    const bool started = only_box < 0 || bi == only_box;  // uniform over the block
+    if (started) row_coefs(B, coef + (long long)bi * WM * MC, (tile - B.tile0) * TILE, rc);
+    if (started && s < B.n && omap[B.ooff + s] == 0) {
         const int x = s % B.nx, t = s / B.nx, y = t % B.ny, z = t / B.ny;
         double u[UF];
-        start_velocity(B, bi, 0, parts, uf, base, coef, s, x, y, z, u);
+        start_velocity(B, 0, parts, uf, base, rc, s, x, y, z, u);
         for (int k = 0; k < 3; ++k) {
             v[k] = u[k];
             v[3 + k] = u[3] * u[k];
@@ -628,10 +679,12 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
                                                        typename Store<ST>::T* __restrict__ f, KParams kp,
                                                        int only_box) {
     using S = Store<ST>;
+    __shared__ RowCoefs rc;
     const int tile = blockIdx.x;
     const int bi = tile_box[tile];
-    if (only_box >= 0 && bi != only_box) return;
+    if (only_box >= 0 && bi != only_box) return;  // uniform over the block
     const BoxDesc& B = boxes[bi];
+    row_coefs(B, coef + (long long)bi * WM * MC, (tile - B.tile0) * TILE, rc);
     const int s = (tile - B.tile0) * TILE + (int)threadIdx.x;
     if (s >= B.n) return;
     const uint16_t owner = omap[B.ooff + s];
@@ -639,7 +692,7 @@ __global__ __launch_bounds__(TILE) void k_stokes_write(const BoxDesc* __restrict
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
     double u[UF];
-    start_velocity(B, bi, owner, parts, uf, base, coef, s, x, y, z, u);
+    start_velocity(B, owner, parts, uf, base, rc, s, x, y, z, u);
     const double rho0 = kp.rho0;
     double rho = rho0;
     if (owner == 0) {
@@ -838,7 +891,7 @@ hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile
     double* ubar = partial + (size_t)ntiles * NPART;
     hipLaunchKernelGGL(k_stokes_free, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, parts, np, mu, only_box, base,
                        uf);
-    hipLaunchKernelGGL(k_stokes_modes, dim3(nboxes, (2 * WK + 1) * (2 * WK + 1)), dim3(256), 0, st, boxes, uf, base,
+    hipLaunchKernelGGL(k_stokes_modes, dim3((2 * WK + 1) * (2 * WK + 1) * nboxes), dim3(256), 0, st, boxes, uf, base,
                        only_box, S);
     hipLaunchKernelGGL(k_stokes_coef, dim3((nboxes * WM + 127) / 128), dim3(128), 0, st, boxes, nboxes, parts, np, mu,
                        S, C);
