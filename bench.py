@@ -302,6 +302,17 @@ def steps_to_steady(runs, eval_boxes, monitor_tol=0.1, wrong_tol=0.02):
     wrong = lbell.Surrogate(max_samples=4096, params=2.0 * sur.params())
     bad = runner.compare_starts(We, wrong, monitor_tol=wrong_tol)
     t_eval = time.perf_counter() - t0 - t_train
+    # the whole warm start (features, network, start field) of the headline
+    # ensemble, best of three
+    lat = runner.build_lattice(workloads.c4("fp16", 256))
+    t_head = []
+    for _ in range(3):
+        lat.sync()
+        t1 = time.perf_counter()
+        lat.warm_start(sur)
+        lat.sync()
+        t_head.append(1e3 * (time.perf_counter() - t1))
+    del lat
     m = res["median_steps"]
     rates = lambda r: {k: round(r[k + "_rate"], 4) for k in ("accepted", "fallback", "steady_miss")}  # noqa: E731
     return {"eval_workload": We.name, "storage": "fp16", "boxes": res["boxes"], "steady_boxes": res["steady_boxes"],
@@ -311,6 +322,8 @@ def steps_to_steady(runs, eval_boxes, monitor_tol=0.1, wrong_tol=0.02):
             "surrogate_over_plain": round(res["surrogate_over_plain"], 4),
             "control_over_plain": round(res["control_over_plain"], 4),
             "median_prediction_error": round(res["median_prediction_error"], 5),
+            "start_ms": {k: round(v, 2) for k, v in res["start_ms"].items()},
+            "warm_start_ms_c4_ensemble_256": round(min(t_head), 2),
             "monitor": {"tol": monitor_tol, **rates(res), "queued_for_training": len(res["queued"])},
             "wrong_network": {"params": "trained x 2", "monitor_tol": wrong_tol, **rates(bad),
                               "median_prediction_error": round(bad["median_prediction_error"], 5),

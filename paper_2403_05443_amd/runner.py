@@ -10,6 +10,7 @@ it (launch sizes, step counts, book-keeping of the sampled velocities) and
 shapes the training data.
 """
 import math
+import time
 
 import numpy as np
 
@@ -366,12 +367,14 @@ def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25,
     starts: 'plain' (rest), 'surrogate' (lb_warm_start; with tol > 0 its
     boxes are watched on the device and fall back to the plain start when the
     prediction fails), 'control' (closed forms + Stokes start field).  Returns
-    (times, U (nt, np, 3), pred, info) with info holding, for the surrogate
-    start, the device's decision per box and the samples (X, Y) of every
-    particle at the end of the run."""
+    (times, U (nt, np, 3), pred, info) with info holding the start's wall
+    time (start_ms) and, for the surrogate start, the device's decision per
+    box and the samples (X, Y) of every particle at the end of the run."""
     lat = build_lattice(W)
     pred = None
     info = {}
+    lat.sync()
+    t0 = time.perf_counter()
     if start == "surrogate":
         pred = lat.warm_start(surrogate, tol=tol)
     elif start == "control":
@@ -382,6 +385,8 @@ def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25,
             lat.set_velocity(i, U, Wv)
             pred[i] = np.concatenate([U, Wv])
         lat.stokes_start()
+    lat.sync()
+    info["start_ms"] = 1e3 * (time.perf_counter() - t0)
     lat.set_graph(graph)
     times, Us = [], []
     t = 0
@@ -574,7 +579,7 @@ def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0
     steps = (steps + every - 1) // every * every
     tp, Up, _, _ = trajectory(W, "plain", steps=steps, every=every)
     ts, Us, pred, info = trajectory(W, "surrogate", surrogate, steps=steps, every=every, tol=monitor_tol)
-    tc, Uc, _, _ = trajectory(W, "control", steps=steps, every=every)
+    tc, Uc, _, cinfo = trajectory(W, "control", steps=steps, every=every)
     Uinf = Up[-1]
     ok = np.ones(len(W.particles), dtype=bool)
     for i, p in enumerate(W.particles):
@@ -606,4 +611,5 @@ def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0
                 [info["decided"][p.box] for p in W.particles])[ok & (status == 3)]))
                 if (ok & (status == 3)).any() else None),
             "queued": queued.tolist(), "queued_samples": (X[queued], Y[queued]),
+            "start_ms": {"surrogate": info["start_ms"], "control": cinfo["start_ms"]},
             "per_box": n, "steady": ok, "status": status}
