@@ -645,25 +645,29 @@ __global__ __launch_bounds__(TILE) void k_stokes_sum(const BoxDesc* __restrict__
     if (tid < NPART) partial[(long long)tile * NPART + tid] = red[tid][0];
 }
 
-// One thread per box: the mean pressure pbar of its fluid nodes and the
+// One wave per box: the mean pressure pbar of its fluid nodes and the
 // uniform velocity ubar removed from them.  A fluid node gets the density
 // rho = rho0 + 3 (p - pbar) (p = c_s^2 (rho - rho0)), so the fluid's mass is
 // unchanged, and ubar = (sum rho u + sum_p M U) / (N rho0) makes the box's
 // momentum sum rho (u - ubar) + sum_p M U zero.
-__global__ void k_stokes_mean(const BoxDesc* __restrict__ boxes, int nboxes, const PartDev* __restrict__ parts,
-                              int np, const double* __restrict__ partial, double rho0, double* __restrict__ ubar) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nboxes) return;
+__global__ __launch_bounds__(64) void k_stokes_mean(const BoxDesc* __restrict__ boxes,
+                                                    const PartDev* __restrict__ parts, int np,
+                                                    const double* __restrict__ partial, double rho0,
+                                                    double* __restrict__ ubar) {
+    const int b = blockIdx.x, lane = threadIdx.x;  // one 64-wide work-group per box
     const BoxDesc& B = boxes[b];
-    double S[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = B.tile0; t < B.tile0 + B.ntiles; ++t)
+    double S[NPART] = {0, 0, 0, 0, 0, 0, 0, 0}, MU[3] = {0, 0, 0};
+    for (int t = B.tile0 + lane; t < B.tile0 + B.ntiles; t += 64)
         for (int k = 0; k < NPART; ++k) S[k] += partial[(long long)t * NPART + k];
+    for (int p = lane; p < np; p += 64)
+        if (parts[p].box == b)
+            for (int k = 0; k < 3; ++k) MU[k] += parts[p].M * parts[p].U[k];
+    for (int k = 0; k < NPART; ++k) S[k] = wave_sum(S[k]);
+    for (int k = 0; k < 3; ++k) MU[k] = wave_sum(MU[k]);
+    if (lane != 0) return;
     const double N = S[7], pbar = N > 0 ? S[6] / N : 0.0;
     double J[3];
-    for (int k = 0; k < 3; ++k) J[k] = rho0 * S[k] + 3.0 * (S[3 + k] - pbar * S[k]);
-    for (int p = 0; p < np; ++p)
-        if (parts[p].box == b)
-            for (int k = 0; k < 3; ++k) J[k] += parts[p].M * parts[p].U[k];
+    for (int k = 0; k < 3; ++k) J[k] = rho0 * S[k] + 3.0 * (S[3 + k] - pbar * S[k]) + MU[k];
     for (int k = 0; k < 3; ++k) ubar[4 * b + k] = N > 0 ? J[k] / (N * rho0) : 0.0;
     ubar[4 * b + 3] = pbar;
 }
@@ -897,8 +901,7 @@ hipError_t launch_stokes_start(const BoxDesc* boxes, int nboxes, const int* tile
                        S, C);
     hipLaunchKernelGGL(k_stokes_sum, dim3(ntiles), dim3(TILE), 0, st, boxes, tile_box, omap, parts, uf, base,
                        only_box, C, partial);
-    hipLaunchKernelGGL(k_stokes_mean, dim3((nboxes + 63) / 64), dim3(64), 0, st, boxes, nboxes, parts, np, partial,
-                       kp.rho0, ubar);
+    hipLaunchKernelGGL(k_stokes_mean, dim3(nboxes), dim3(64), 0, st, boxes, parts, np, partial, kp.rho0, ubar);
     auto write = [&](auto q) {
         constexpr int Q = decltype(q)::value;
         switch (kp.storage) {
