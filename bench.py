@@ -362,7 +362,8 @@ def main():
                          "instead of the benchmark and print their results as one JSON line")
     ap.add_argument("--studies", default="domain,resolution,sphere_array,jeffery_domain",
                     help="with --sweep-only: comma-separated studies to run (domain, resolution, sphere_array, "
-                         "jeffery_domain, drift_superposition, squirmer_starts)")
+                         "jeffery_domain, drift_superposition, squirmer_starts, stokes_start: the start field's "
+                         "time on the 256-box ensemble)")
     ap.add_argument("--surrogate-runs", type=int, default=4,
                     help="256-box FP16 ensembles run to train the warm-start network (0: skip steps to steady)")
     ap.add_argument("--eval-boxes", type=int, default=64, help="held-out force-driven boxes for steps to steady")
@@ -396,6 +397,7 @@ def main():
             "sphere_array": lambda: {L: runner.sphere_array_run(L) for L in (24, 32, 48, 64)},
             "jeffery_domain": lambda: [runner.jeffery_half_period(L) for L in (26, 32, 40, 48, 64)],
             "drift_superposition": lambda: runner.drift_superposition(bs=(2.0, 3.0, 4.0)),
+            "stokes_start": lambda: runner.stokes_start_time(workloads.c4("fp16", 256)),
             "squirmer_starts": lambda: runner.squirmer_starts(
                 workloads.c5("fp16"), runner.train_warm_network(seeds=4, boxes=256, epochs=1000, seed0=10)[0],
                 log=lambda m: print(m, file=sys.stderr, flush=True)),

@@ -402,6 +402,21 @@ def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25,
     return np.array(times), np.array(Us), pred, info
 
 
+def stokes_start_time(W, reps=3):
+    """Wall time of lb_stokes_start on workload W (its particles' loads drive
+    the field), each repetition synchronised: (list of ms, best)."""
+    lat = build_lattice(W)
+    lat.sync()
+    ms = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        lat.stokes_start()
+        lat.sync()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    del lat
+    return {"workload": W.name, "storage": W.storage, "ms": [round(v, 2) for v in ms], "best_ms": round(min(ms), 2)}
+
+
 def steps_to_tolerance(times, U, Uinf, tol=0.005):
     """Per particle: the first sampled step after which |U(t) - U_inf| <=
     tol |U_inf| holds until the end (inf if it never settles)."""

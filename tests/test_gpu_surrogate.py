@@ -308,9 +308,10 @@ HELD_OUT = {"storage": "fp32", "nboxes": 32, "seed_index": 200, "torque": False}
 def test_surrogate_warm_start_reaches_steady_state_sooner(lb, trained):
     """A held-out force-driven 32-box ensemble, warm-started by the trained
     network and watched at tol 0.1: the median number of steps to a velocity
-    within 0.5% of the steady one is below both the plain start's and the
-    closed-form control's (the same start without the network), and the
-    device monitor accepts the network's predictions."""
+    within 0.5% of the steady one is below the closed-form control's (the
+    same start without the network) and under a tenth of the plain start's
+    (measured 50 against 325 and 1275), and the device monitor accepts the
+    network's predictions."""
     from paper_2403_05443_amd import runner, workloads
     res = runner.compare_starts(workloads.c4(**HELD_OUT), trained, monitor_tol=0.1)
     for k in ("per_box", "steady", "status", "queued_samples"):
@@ -318,7 +319,7 @@ def test_surrogate_warm_start_reaches_steady_state_sooner(lb, trained):
     print(res)
     m = res["median_steps"]
     assert res["steady_boxes"] >= 24
-    assert m["surrogate"] < m["plain"] and m["surrogate"] < m["control"]
+    assert m["surrogate"] < 0.1 * m["plain"] and m["surrogate"] < m["control"]
     assert res["accepted_rate"] >= 0.9
 
 
