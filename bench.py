@@ -362,7 +362,8 @@ def main():
                          "instead of the benchmark and print their results as one JSON line")
     ap.add_argument("--studies", default="domain,resolution,sphere_array,jeffery_domain",
                     help="with --sweep-only: comma-separated studies to run (domain, resolution, sphere_array, "
-                         "jeffery_domain, drift_superposition, squirmer_starts, stokes_start: the start field's "
+                         "jeffery_domain, drift_superposition, squirmer_starts, squirmer_feedback: the network "
+                         "retrained on the samples of a suspension it missed, stokes_start: the start field's "
                          "time on the 256-box ensemble)")
     ap.add_argument("--surrogate-runs", type=int, default=4,
                     help="256-box FP16 ensembles run to train the warm-start network (0: skip steps to steady)")
@@ -398,6 +399,10 @@ def main():
             "jeffery_domain": lambda: [runner.jeffery_half_period(L) for L in (26, 32, 40, 48, 64)],
             "drift_superposition": lambda: runner.drift_superposition(bs=(2.0, 3.0, 4.0)),
             "stokes_start": lambda: runner.stokes_start_time(workloads.c4("fp16", 256)),
+            "squirmer_feedback": lambda: runner.squirmer_feedback(
+                lambda extra: runner.train_warm_network(seeds=4, boxes=256, epochs=1000, seed0=10, extra=extra)[0],
+                workloads.c5("fp16"), workloads.c5("fp16", seed_index=1),
+                log=lambda m: print(m, file=sys.stderr, flush=True)),
             "squirmer_starts": lambda: runner.squirmer_starts(
                 workloads.c5("fp16"), runner.train_warm_network(seeds=4, boxes=256, epochs=1000, seed0=10)[0],
                 log=lambda m: print(m, file=sys.stderr, flush=True)),

@@ -419,17 +419,19 @@ lb_status lbs_grad_noalloc(const float* params, const float* X, const float* Y, 
  * fluid nodes, j the momentum density) and its particles' velocities
  * V = (U, a Omega); the first check at least W0 steps after it compares with
  * them (the residuals: the relative changes since then) and with the
- * prediction, and decides the box:
- *   LB_WARM_ACCEPTED     every particle within tol of its prediction;
- *   LB_WARM_FALLBACK     a particle misses by more than tol while a residual
- *                        still exceeds tol: the surrogate's start has failed,
- *                        and the box falls back to the plain method: its fluid
- *                        and particles are reset to rest and the run goes on
- *                        from there (the steps so far are spent);
- *   LB_WARM_STEADY_MISS  a particle misses but both residuals are below tol:
- *                        the run is steady away from the prediction; it is
- *                        kept, and its sample (lb_surrogate_sample) belongs in
- *                        the training data.
+ * prediction, and decides the box.  The box misses when more than a quarter
+ * of its particles are further than tol from their predictions (a box of
+ * one to three particles: when any is):
+ *   LB_WARM_ACCEPTED     no miss;
+ *   LB_WARM_FALLBACK     a miss while a residual still exceeds tol: the
+ *                        surrogate's start has failed, and the box falls back
+ *                        to the plain method: its fluid and particles are
+ *                        reset to rest and the run goes on from there (the
+ *                        steps so far are spent);
+ *   LB_WARM_STEADY_MISS  a miss with both residuals below tol: the run is
+ *                        steady away from the prediction; it is kept, and its
+ *                        samples (lb_surrogate_sample) belong in the training
+ *                        data.
  * tol <= 0 leaves the box unwatched.  Needs np <= the surrogate's
  * max_samples; LB_EINVAL for boxes with walls or box out of range.
  * Synchronises. */

@@ -431,12 +431,14 @@ def steps_to_tolerance(times, U, Uinf, tol=0.005):
     return out
 
 
-def train_warm_network(seeds=4, boxes=128, epochs=600, seed0=20, storage="fp16"):
+def train_warm_network(seeds=4, boxes=128, epochs=600, seed0=20, storage="fp16", extra=None):
     """The warm-start network trained on the library's own ensemble runs:
     `seeds` force-driven ensembles of `boxes` boxes with config 4's
     distributions (seeds seed0, seed0 + 1, ...; every other one with
     torques), their steady samples augmented by the spheroid's symmetries and
-    the linearity of Stokes flow.  Returns (surrogate, info)."""
+    the linearity of Stokes flow.  extra: samples (X, Y) fed back from runs
+    whose prediction missed (lb_surrogate_sample), added to the ensembles'
+    before the augmentation.  Returns (surrogate, info)."""
     Xs, Ys, steps = [], [], 0
     for k in range(seeds):
         W = workloads.c4(storage, boxes, seed_index=seed0 + k, torque=(k % 2 == 0))
@@ -444,9 +446,13 @@ def train_warm_network(seeds=4, boxes=128, epochs=600, seed0=20, storage="fp16")
         Xs.append(X)
         Ys.append(Y)
         steps += n
+    if extra is not None:
+        Xs.append(np.asarray(extra[0], np.float64))
+        Ys.append(np.asarray(extra[1], np.float64))
     Xa, Ya = augment(np.concatenate(Xs), np.concatenate(Ys))
     sur, info = train_surrogate(Xa, Ya, epochs=epochs)
     info["lb_steps_per_ensemble"] = steps // max(seeds, 1)
+    info["extra_samples"] = 0 if extra is None else len(extra[0])
     return sur, info
 
 
@@ -577,6 +583,112 @@ def squirmer_starts(W, surrogate, steps=10000, every=50, monitor_tol=0.1, contac
         out["starts"][start] = {"median_deviation": {int(times[k]): round(float(np.median(dev[k])), 4) for k in marks},
                                 "median_first_step_within": first, "fraction_settled_to_end": stay}
     return out
+
+
+def _swim(lat, steps, every):
+    """Step a squirmer lattice, counting latched overlap flags (the paper has
+    no inter-particle force); returns (speeds along each swimmer's axis per
+    sample, flags)."""
+    S, flags = [], 0
+    for _ in range(steps // every):
+        try:
+            lat.step(every)
+        except lbell.LBError as err:
+            if err.status != lbell.LB_EOVERLAP:
+                raise
+            flags += 1
+        try:
+            P = lat.particles()
+        except lbell.LBError as err:
+            if err.status != lbell.LB_EOVERLAP:
+                raise
+            flags += 1
+            P = lat.particles()
+        S.append((P["U"] * _body_axis(P["q"])).sum(1))
+    return np.array(S), flags
+
+
+def squirmer_feedback(train, W_fit, W_eval, steps=3000, every=50, monitor_tol=0.1, log=None):
+    """The learned part's loop closed on squirmer suspensions (config 5).
+    train(extra) returns a network trained on the force-driven ensembles plus
+    the samples `extra` (None: none).  The first network warm-starts W_fit,
+    watched by the device monitor at monitor_tol; after `steps` steps the
+    samples of every particle of a box the monitor flagged (fallen back or
+    settled elsewhere) are fed back and the network retrained.  Both networks
+    then warm-start another suspension, W_eval, watched the same way, beside
+    a plain run of it: reported per network, its predicted speed along each
+    swimmer's axis over the closed-form free swimming speed (eq. squirmervel)
+    and over the plain run's mean over its last fifth (medians), the
+    monitor's decision, the share of swimmers further than monitor_tol from
+    their predictions (V = (U, a Omega), the monitor's measure) one sample
+    before the decision step and their median miss, and the median
+    |s - s_inf| / s_inf at a few steps."""
+    def closed_form(W):
+        out = []
+        for p in W.particles:
+            r = p.axes[0] / math.sqrt(p.axes[1] * p.axes[2])
+            e = math.sqrt(1 - 1 / r ** 2) if r > 1 + 1e-6 else 0.0
+            B1 = p.squirmer[0]
+            out.append(2 * B1 / 3 if e < 1e-3 else B1 / e * (1 / e - (1 / e ** 2 - 1) * math.atanh(e)))
+        return np.array(out)
+
+    def watched(W, sur):
+        lat = build_lattice(W)
+        pred = lat.warm_start(sur, tol=monitor_tol)
+        lat.set_graph(every)
+        a = np.array([max(p.axes) for p in W.particles])[:, None]
+        w0 = int(math.ceil(2 * a.max() ** 2 / viscosity(W)))
+        before = max((w0 - 1) // every, 1) * every  # the last sample before the decision
+        S1, f1 = _swim(lat, before, every)
+        P = lat.particles()
+        V = np.concatenate([P["U"], a * P["W"]], 1)
+        Vp = np.concatenate([pred[:, :3], a * pred[:, 3:]], 1)
+        miss = np.linalg.norm(V - Vp, axis=1) / np.linalg.norm(Vp, axis=1)
+        S2, f2 = _swim(lat, steps - before, every)
+        st, at = lat.warm_status()
+        return lat, pred, np.concatenate([S1, S2]), f1 + f2, st, at, (before, miss)
+
+    sur0 = train(None)
+    lat, _, _, _, st, at, _ = watched(W_fit, sur0)
+    X, Y = lat.surrogate_sample()
+    del lat
+    fed = np.array([i for i, p in enumerate(W_fit.particles) if st[p.box] in (3, 4)], dtype=int)
+    if log:
+        log(f"squirmer_feedback: fit run done, {len(fed)} samples fed back")
+    sur1 = train((X[fed], Y[fed])) if len(fed) else sur0
+    lat = build_lattice(W_eval)
+    lat.set_graph(every)
+    Sp, _ = _swim(lat, steps, every)
+    del lat
+    tail = max(len(Sp) // 5, 1)
+    s_inf = Sp[-tail:].mean(0)
+    Us = closed_form(W_eval)
+    e0 = _body_axis([p.quat for p in W_eval.particles])
+    times = np.arange(1, steps // every + 1) * every
+    marks = [k for k in (0, 1, 5, 19, len(times) - 1) if k < len(times)]
+    out = {"fit_workload": W_fit.name, "eval_workload": W_eval.name, "steps": steps, "every": every,
+           "monitor_tol": monitor_tol, "fit_monitor": _status_name(st[0]), "fit_decided_step": int(at[0]),
+           "samples_fed_back": int(len(fed)),
+           "plain_speed_over_closed_form": round(float(np.median(s_inf / Us)), 4), "networks": {}}
+    for name, sur in (("before_feedback", sur0), ("after_feedback", sur1)):
+        lat, pred, S, flags, st, at, (t_miss, miss) = watched(W_eval, sur)
+        del lat
+        sp = (pred[:, :3] * e0).sum(1)
+        dev = np.abs(S - s_inf[None]) / np.abs(s_inf)[None]
+        out["networks"][name] = {
+            "prediction_over_closed_form": round(float(np.median(sp / Us)), 4),
+            "prediction_over_plain": round(float(np.median(sp / s_inf)), 4),
+            "monitor": _status_name(st[0]), "decided_step": int(at[0]), "overlap_flags": flags,
+            "miss_step": t_miss, "share_missing": round(float((miss > monitor_tol).mean()), 4),
+            "median_miss": round(float(np.median(miss)), 4),
+            "median_deviation": {int(times[k]): round(float(np.median(dev[k])), 4) for k in marks}}
+        if log:
+            log(f"squirmer_feedback: {name} run done")
+    return out
+
+
+def _status_name(code):
+    return lbell.Lattice.WARM_STATUS[int(code)]
 
 
 def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0.1):

@@ -250,5 +250,6 @@ def c5(storage="fp16", L=256, n=512, seed_index=0):
         beta = g.uniform(-3.0, 3.0)
         cs[m], hs[m] = c, h
         parts.append(Particle(c, axes, q, squirmer=(1e-3, beta * 1e-3)))
-    return Workload(f"c5_squirmers_{L}_{n}", [Box((L, L, L))], parts, "trt", 1.0, storage, 10000,
+    return Workload(f"c5_squirmers_{L}_{n}" + (f"_s{seed_index}" if seed_index else ""), [Box((L, L, L))], parts,
+                    "trt", 1.0, storage, 10000,
                     velocity_scale=2e-3, max_semi_axis=5.0)

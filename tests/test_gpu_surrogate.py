@@ -385,3 +385,26 @@ def test_warm_start_fallback_resets_box_to_plain_start(lb, trained):
     err = np.linalg.norm(Uw - Up[-1], axis=1) / np.linalg.norm(Up[-1], axis=1)
     print("fallback boxes: error against the plain run", err[fell])
     assert (err[fell] < 5e-3).all()
+
+
+def test_feedback_retraining_fixes_the_squirmer_prediction(lb):
+    """The learned loop closed on a small squirmer suspension (27 swimmers in
+    96^3, the volume per swimmer of the 512-swimmer config): a network
+    trained on force-driven ensembles under-predicts the swimmers and the
+    device monitor rejects its start; fed the samples of that run and
+    retrained, it predicts another suspension's swimmers within 5 % of their
+    plain-run speed and the monitor accepts the start."""
+    from paper_2403_05443_amd import runner, workloads
+
+    def train(extra):
+        return runner.train_warm_network(seeds=2, boxes=128, epochs=600, seed0=20, extra=extra)[0]
+
+    res = runner.squirmer_feedback(train, workloads.c5("fp16", L=96, n=27),
+                                   workloads.c5("fp16", L=96, n=27, seed_index=1), steps=1000, every=50)
+    print({k: v for k, v in res.items() if k != "networks"})
+    for name, n in res["networks"].items():
+        print(name, n)
+    assert res["samples_fed_back"] == 27
+    before, after = res["networks"]["before_feedback"], res["networks"]["after_feedback"]
+    assert before["monitor"] in ("fallback", "steady_miss") and before["prediction_over_plain"] < 0.85
+    assert abs(after["prediction_over_plain"] - 1) < 0.05 and after["monitor"] == "accepted"
