@@ -67,6 +67,7 @@ def workload_by_name(name, storage):
         "c2_inclined_128_d3q27": lambda: workloads.c2(storage, 128, lattice=27),
         "c5_squirmers_256_512": lambda: workloads.c5(storage),
         "c5_squirmers_256_6400": lambda: workloads.c5(storage, n=6400),
+        "empty_256": lambda: workloads.empty(storage),
     }
     if name not in table:
         raise SystemExit(f"unknown workload {name}; one of {sorted(table)}")
@@ -81,6 +82,8 @@ LEGS = {
     "inclined_128_fp32": ("c2_inclined_128", "fp32", 1000, 50),
     "inclined_128_fp16": ("c2_inclined_128", "fp16", 1000, 50),
     "inclined_128_d3q27_fp32": ("c2_inclined_128_d3q27", "fp32", 500, 50),
+    "empty_256_fp16": ("empty_256", "fp16", 200, 20),
+    "empty_256_fp32": ("empty_256", "fp32", 200, 20),
 }
 
 
@@ -350,7 +353,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c4_ensemble_256",
                     help="headline workload (c4_ensemble_256, c5_squirmers_256_512, c5_squirmers_256_6400, "
-                         "c2_inclined_128, c2_inclined_128_d3q27)")
+                         "c2_inclined_128, c2_inclined_128_d3q27, empty_256)")
     ap.add_argument("--storage", default="fp16", choices=sorted(BYTES))
     ap.add_argument("--graph", type=int, default=50, help="steps per HIP graph replay (0: plain launches)")
     ap.add_argument("--variant", type=int, default=None,

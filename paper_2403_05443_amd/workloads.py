@@ -200,6 +200,12 @@ def c4(storage="fp16", nboxes=256, seed_index=0, torque=True):
                     velocity_scale=1e-3, max_semi_axis=20.0)
 
 
+def empty(storage="fp16", L=256):
+    """A periodic L^3 box with no particle (TRT, Lambda = 3/16, tau+ = 1,
+    fluid at rest): the collide-stream kernel alone, for its roofline."""
+    return Workload(f"empty_{L}", [Box((L, L, L))], [], "trt", 1.0, storage, 0)
+
+
 MLP_LAYERS = ((64, 8), (64, 64), (6, 64))   # (fan_out, fan_in) of the surrogate's three layers
 
 
