@@ -223,6 +223,42 @@ def test_stokes_start_field_matches_reference(lb):
         assert abs(g.mass(b) - m0[b]) < 1e-11 * m0[b]
 
 
+def test_stokes_start_of_several_loaded_particles_in_one_box(lb):
+    """Three loaded particles share a box (a prolate spheroid, a sphere and
+    an oblate one, whose flows are the line solution, the sphere's and the
+    equal-volume sphere's): the start state is the oracle's sum of their
+    flows, pressures and periodic modes, to the same bar."""
+    import oracle
+    shape = (40, 36, 44)
+    nu = (0.8 - 0.5) / 3
+    specs = [((10.3, 9.6, 11.2), (7.0, 2.5, 2.5), (0.8, 0.3, -0.4, 0.33), (6e-5, -2e-5, 3e-5), (0, 1e-4, 5e-5)),
+             ((28.1, 24.7, 30.4), (3.0, 3.0, 3.0), (1, 0, 0, 0), (-3e-5, 4e-5, 0), (0, 0, 2e-4)),
+             ((29.5, 8.9, 12.6), (2.0, 4.0, 4.0), (0.5, 0.5, 0.5, 0.5), (0, 0, -5e-5), (1e-4, 0, 0))]
+    g = lb.Lattice([lb.make_box(*shape)], collision="trt", tau=0.8, storage="fp64", counterforce=True,
+                   max_particles=3)
+    o = oracle.OracleSim(shape, "trt", 0.8, counterforce=True)
+    parts = []
+    for c, a, q, F, T in specs:
+        q = np.array(q) / np.linalg.norm(q)
+        pg = g.add_ellipsoid(c, a, q)
+        g.set_external(pg, F, T)
+        po = o.add_ellipsoid(c, a, q)
+        parts.append({"centre": o.particle(po)["x"], "axes": a, "q": q, "F": F, "T": T, "U": (0, 0, 0),
+                      "W": (0, 0, 0), "M": o.aux(po)["M"]})
+    assert np.array_equal(o.mask(), g.mask())
+    m0 = g.mass()
+    g.stokes_start()
+    rho_o, u_o = S.start_state(shape, o.mask(), parts, nu)
+    rho, u = g.fields()
+    fl = o.mask() == 0
+    err = np.abs(u[fl] - u_o[fl]).max() / np.abs(u_o[fl]).max()
+    err_rho = np.abs(rho[fl] - rho_o[fl]).max() / np.abs(rho_o[fl] - 1).max()
+    print(f"start field error {err:.2e}, density {err_rho:.2e}")
+    assert err < 1e-11
+    assert np.abs(rho[fl] - rho_o[fl]).max() < 1e-10 * np.abs(rho_o[fl] - 1).max() + 1e-15
+    assert abs(g.mass() - m0) < 1e-11 * m0
+
+
 def test_single_box_warm_start_matches_the_full_start_in_that_box(lb):
     """A warm start of one box (its free flow kept at that box's offset in
     the scratch) gives that box the fields of the start of every box, bit for
