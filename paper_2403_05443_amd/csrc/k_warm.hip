@@ -476,8 +476,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Discrete Fourier sums S_m = sum_x (u, p)_free(x) exp(-i k_m . x) over every
 // node of a box, for the modes of one (ny, nz) pair and all nx: work-group
 // 25 b + g takes box b and pair g, so the 25 work-groups of a box run
-// together and stream its staged field through the caches about once.  Edges up to
-// TW_MAX take their phase factors from tables in LDS.
+// together and stream its staged field through the caches about once.
+// Edges up to TW_MAX take their phase factors from tables in LDS.
 constexpr int TW_MAX = 1024;
 __global__ __launch_bounds__(256) void k_stokes_modes(const BoxDesc* __restrict__ boxes,
                                                       const double* __restrict__ uf, long long base, int only_box,
