@@ -259,6 +259,31 @@ def test_stokes_start_of_several_loaded_particles_in_one_box(lb):
     assert abs(g.mass() - m0) < 1e-11 * m0
 
 
+@pytest.mark.parametrize("storage,tol", [("fp32", 2.0 ** -23), ("fp16", 2.0 ** -10), ("bf16", 2.0 ** -7)])
+def test_stokes_start_in_narrow_storage(lb, storage, tol):
+    """The start state written into FP32, FP16 and BF16 storage: the fluid
+    velocity read back matches the oracle's within one unit in the last
+    place of the storage format (24, 11 and 8 significant bits, the narrow
+    ones rounded stochastically: at most one ulp), relative to the largest
+    speed: the velocity is sum c_i d_i over deviations d_i ~ 3 w_i |u|, and
+    sum w_i |c_ix| = 1/3, so each ulp-rounded deviation moves it by at most
+    about one ulp of |u| (measured 1.7e-8, 1.5e-4, 1.3e-3)."""
+    import oracle
+    g, boxes, specs = _warm_lattice(lb, storage=storage)
+    g.stokes_start()
+    for pid, b, c, a, q, F, T in specs:
+        o = oracle.OracleSim(boxes[b], "trt", 0.8, counterforce=True)
+        po = o.add_ellipsoid(c, a, q)
+        part = {"centre": o.particle(po)["x"], "axes": a, "q": q, "F": F, "T": T, "U": (0, 0, 0), "W": (0, 0, 0),
+                "M": o.aux(po)["M"]}
+        _, u_o = S.start_state(boxes[b], o.mask(), [part], (0.8 - 0.5) / 3)
+        _, u = g.fields(b)
+        fl = o.mask() == 0
+        err = np.abs(u[fl] - u_o[fl]).max() / np.abs(u_o[fl]).max()
+        print(storage, b, f"start field error {err:.2e}")
+        assert err < tol
+
+
 def test_single_box_warm_start_matches_the_full_start_in_that_box(lb):
     """A warm start of one box (its free flow kept at that box's offset in
     the scratch) gives that box the fields of the start of every box, bit for
