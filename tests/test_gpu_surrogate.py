@@ -284,6 +284,33 @@ def test_stokes_start_in_narrow_storage(lb, storage, tol):
         assert err < tol
 
 
+def test_stokes_start_on_d3q27(lb):
+    """The start state on the D3Q27 lattice: its equilibria carry the same
+    density and velocity, so the fields read back equal the oracle's start
+    state (computed without a lattice) to the FP64 bar."""
+    import oracle
+    shape, c, a = (30, 26, 28), (14.2, 12.7, 13.9), (6.0, 2.5, 2.5)
+    q = np.array([0.7, -0.2, 0.5, 0.4])
+    q /= np.linalg.norm(q)
+    F, T = (4e-5, 3e-5, -2e-5), (1e-4, 0, 1e-4)
+    g = lb.Lattice([lb.make_box(*shape)], collision="trt", tau=0.8, storage="fp64", counterforce=True, lattice=27)
+    pg = g.add_ellipsoid(c, a, q)
+    g.set_external(pg, F, T)
+    g.stokes_start()
+    o = oracle.OracleSim(shape, "trt", 0.8, counterforce=True)
+    po = o.add_ellipsoid(c, a, q)
+    assert np.array_equal(o.mask() != 0, g.mask() != 0)
+    part = {"centre": o.particle(po)["x"], "axes": a, "q": q, "F": F, "T": T, "U": (0, 0, 0), "W": (0, 0, 0),
+            "M": o.aux(po)["M"]}
+    rho_o, u_o = S.start_state(shape, o.mask(), [part], (0.8 - 0.5) / 3)
+    rho, u = g.fields()
+    fl = o.mask() == 0
+    err = np.abs(u[fl] - u_o[fl]).max() / np.abs(u_o[fl]).max()
+    print(f"D3Q27 start field error {err:.2e}")
+    assert err < 1e-12
+    assert np.abs(rho[fl] - rho_o[fl]).max() < 1e-10 * np.abs(rho_o[fl] - 1).max() + 1e-15
+
+
 def test_single_box_warm_start_matches_the_full_start_in_that_box(lb):
     """A warm start of one box (its free flow kept at that box's offset in
     the scratch) gives that box the fields of the start of every box, bit for
