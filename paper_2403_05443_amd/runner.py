@@ -526,26 +526,10 @@ def squirmer_starts(W, surrogate, steps=10000, every=50, monitor_tol=0.1, contac
                 lat.set_velocity(i, e0[i] * Us[i], np.zeros(3))
             lat.stokes_start()
         lat.set_graph(every)
-        S, X, flags = [], [], 0
-        for _ in range(steps // every):
-            try:
-                lat.step(every)
-            except lbell.LBError as err:
-                if err.status != lbell.LB_EOVERLAP:
-                    raise
-                flags += 1
-            try:
-                P = lat.particles()
-            except lbell.LBError as err:
-                if err.status != lbell.LB_EOVERLAP:
-                    raise
-                flags += 1
-                P = lat.particles()
-            S.append((P["U"] * _body_axis(P["q"])).sum(1))
-            X.append(P["x"].copy())
+        S, flags, X = _swim(lat, steps, every, positions=True)
         if start == "surrogate_watched":
             st, at = lat.warm_status()
-            info["monitor"] = {"status": lbell.Lattice.WARM_STATUS[int(st[0])], "decided_step": int(at[0])}
+            info["monitor"] = {"status": _status_name(st[0]), "decided_step": int(at[0])}
         info.setdefault("overlap_flags", {})[start] = flags
         runs[start], pos[start] = np.array(S), np.array(X)
         del lat
@@ -585,11 +569,11 @@ def squirmer_starts(W, surrogate, steps=10000, every=50, monitor_tol=0.1, contac
     return out
 
 
-def _swim(lat, steps, every):
+def _swim(lat, steps, every, positions=False):
     """Step a squirmer lattice, counting latched overlap flags (the paper has
     no inter-particle force); returns (speeds along each swimmer's axis per
-    sample, flags)."""
-    S, flags = [], 0
+    sample, flags) and, with positions, the centres per sample as well."""
+    S, X, flags = [], [], 0
     for _ in range(steps // every):
         try:
             lat.step(every)
@@ -605,7 +589,9 @@ def _swim(lat, steps, every):
             flags += 1
             P = lat.particles()
         S.append((P["U"] * _body_axis(P["q"])).sum(1))
-    return np.array(S), flags
+        if positions:
+            X.append(P["x"].copy())
+    return (np.array(S), flags, np.array(X)) if positions else (np.array(S), flags)
 
 
 def squirmer_feedback(train, W_fit, W_eval, steps=3000, every=50, monitor_tol=0.1, log=None):
