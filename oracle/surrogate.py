@@ -348,16 +348,54 @@ def particle_flow(d, p, mu):
 KMAX = 2  # Fourier modes |n_i| <= KMAX of the box carry the periodic correction
 
 
+def _is_line(axes):
+    """A prolate spheroid a > b = c of eccentricity at least E_LINE."""
+    if axes is None:
+        return False
+    a, b, c = axes
+    return a > b and b == c and 1.0 - (b / a) ** 2 >= E_LINE ** 2
+
+
+def rotation_traction(k, T, R, axes=None, q=None):
+    """Transform of the traction a torque T spreads over a body, f_hat(k) =
+    -3 i (Q^T k) j1(kappa) / kappa, at wave vectors k (m, 3).  The traction
+    of a body in rigid motion is sigma(x) C x, sigma the uniform layer of the
+    unit sphere mapped onto the surface and C constant, so its transform is
+    C (i grad_k) sinc(kappa) with C = 3 Q^T A^-2, Q = integral of x f^T its
+    first moment: the torque's antisymmetric part Q_kj = eps_kji T_i / 2, and
+    for a prolate spheroid (axis p, eccentricity e) the stresslet of its
+    line solution (spheroid_flow), e^2 / (2 - e^2) sym(p (T_c x p)), T_c the
+    torque across p, kappa = |diag(a, b, c) R(q)^T k|; any other body is
+    taken as the sphere of radius R (kappa = |k| R, no stresslet).  Returns
+    (Q^T k, j1(kappa) / kappa)."""
+    k = np.atleast_2d(np.asarray(k, float))
+    T = np.asarray(T, float)
+    g = -0.5 * np.cross(k, T)              # Q_A^T k
+    if _is_line(axes):
+        a, b, _ = axes
+        e2 = 1.0 - (b / a) ** 2
+        p = rotmat(q)[:, 0]
+        m = np.cross(T - (T @ p) * p, p)
+        cs = e2 / (2 - e2) / 2
+        g = g + cs * (np.outer(k @ m, p) + np.outer(k @ p, m))   # + Q_S k
+        kap = np.linalg.norm((k @ rotmat(q)) * np.asarray(axes, float), axis=1)
+    else:
+        kap = np.sqrt((k * k).sum(1)) * R
+    return g, (np.sin(kap) - kap * np.cos(kap)) / kap ** 3
+
+
 def periodic_modes(k, F, T, R, mu, V, axes=None, q=None):
     """Fourier coefficients (1/V) u_hat(k) of the creeping flow driven by a
     force F and a torque T spread over a sphere of radius R (uniform surface
     traction), at wave vectors k (m, 3), none zero, for a periodic box of
     volume V, centre at the origin:
-      u_hat = (I - k k / k^2) F sinc(kR) / (mu k^2) + i (k x T) [3 j1(kR) / (kR)] / (2 mu k^2).
+      u_hat = (I - k k / k^2) f_hat / (mu k^2),
+      f_hat = F sinc(kR) + i (k x T) 3 j1(kR) / (2 kR).
     With the semi-axes and orientation of an ellipsoid, the force is spread
     as the traction on that ellipsoid translating (the sphere's uniform layer
     mapped by diag(a, b, c) in the body frame), whose transform is
-    sinc(|diag(a, b, c) R(q)^T k|); the torque stays on the sphere R."""
+    sinc(|diag(a, b, c) R(q)^T k|), and the torque as rotation_traction (the
+    rotating prolate spheroid's, the sphere's otherwise)."""
     k = np.atleast_2d(np.asarray(k, float))
     F, T = np.asarray(F, float), np.asarray(T, float)
     k2 = (k * k).sum(1)
@@ -367,16 +405,18 @@ def periodic_modes(k, F, T, R, mu, V, axes=None, q=None):
     else:
         xa = np.linalg.norm((k @ rotmat(q)) * np.asarray(axes, float), axis=1)
         sinc = np.sin(xa) / xa
-    j1f = 3 * (np.sin(x) / x - np.cos(x)) / (x * x)   # 3 j1(x) / x, 1 at x -> 0
-    Pf = F[None, :] - k * ((k @ F) / k2)[:, None]
-    return (Pf * (sinc / (mu * k2))[:, None] + 1j * np.cross(k, T) * (j1f / (2 * mu * k2))[:, None]) / V
+    g, j1k = rotation_traction(k, T, R, axes, q)
+    f = F[None, :] * sinc[:, None] - 3j * g * j1k[:, None]
+    Pf = f - k * ((k * f).sum(1) / k2)[:, None]
+    return Pf / (mu * k2)[:, None] / V
 
 
-def periodic_pressure_modes(k, F, R, V, axes=None, q=None):
+def periodic_pressure_modes(k, F, R, V, axes=None, q=None, T=None):
     """Fourier coefficients (1/V) p_hat(k) of the pressure of the periodic
     flow of periodic_modes: from mu k^2 u_hat = f_hat - i k p_hat with
-    k.u_hat = 0, p_hat = -i (k.f_hat) / k^2, f_hat the force's spread (the
-    torque's has no divergence and drives no pressure)."""
+    k.u_hat = 0, p_hat = -i (k.f_hat) / k^2, f_hat the spread force and
+    torque (the torque's antisymmetric part has no divergence and drives
+    none; a prolate spheroid's stresslet does)."""
     k = np.atleast_2d(np.asarray(k, float))
     F = np.asarray(F, float)
     k2 = (k * k).sum(1)
@@ -384,7 +424,11 @@ def periodic_pressure_modes(k, F, R, V, axes=None, q=None):
         xa = np.sqrt(k2) * R
     else:
         xa = np.linalg.norm((k @ rotmat(q)) * np.asarray(axes, float), axis=1)
-    return -1j * (k @ F) * (np.sin(xa) / xa) / k2 / V
+    f = F[None, :] * (np.sin(xa) / xa)[:, None]
+    if T is not None:
+        g, j1k = rotation_traction(k, T, R, axes, q)
+        f = f - 3j * g * j1k[:, None]
+    return -1j * (k * f).sum(1) / k2 / V
 
 
 def periodic_coefficients(shape, centre, F, T, R, mu, axes=None, q=None, pressure=False):
@@ -400,7 +444,7 @@ def periodic_coefficients(shape, centre, F, T, R, mu, axes=None, q=None, pressur
     k = 2 * np.pi * np.array(ns, float) / L
     ph = np.exp(-1j * (k @ np.asarray(centre, float)))
     if pressure:
-        return ns, periodic_pressure_modes(k, F, R, float(np.prod(L)), axes, q) * ph
+        return ns, periodic_pressure_modes(k, F, R, float(np.prod(L)), axes, q, T) * ph
     c = periodic_modes(k, F, T, R, mu, float(np.prod(L)), axes, q)
     return ns, c * ph[:, None]
 

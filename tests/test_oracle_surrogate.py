@@ -517,3 +517,45 @@ def test_periodic_pressure_modes_near_a_small_sphere():
         v = (pk * np.exp(1j * (k @ d))).sum().real
         ref = (F @ d) / (4 * math.pi * np.linalg.norm(d) ** 3)
         assert abs(v - ref) < 0.02 * abs(ref) + 0.05
+
+
+@pytest.mark.parametrize("axes", [(7.0, 2.5, 2.5), (5.0, 4.0, 4.0)])
+def test_rotating_spheroid_is_a_linear_single_layer(axes):
+    """Outside a prolate spheroid turned by a torque the flow equals the
+    Stokeslets of the traction sigma C x, sigma the unit sphere's uniform
+    measure mapped by diag(a, b, b), C = 3 Q^T A^-2 with Q the first moment
+    that rotation_traction carries (the torque's antisymmetric part and the
+    line solution's stresslet); that traction has the torque T, and its
+    transform is rotation_traction's -3 i (Q^T k) j1(kappa) / kappa.
+    Quadrature over the unit sphere: Gauss-Legendre in cos(theta),
+    trapezoid in phi."""
+    g = np.random.default_rng(45)
+    q = g.standard_normal(4)
+    q /= np.linalg.norm(q)
+    T = g.standard_normal(3)
+    mu = 0.2
+    Rm = S.rotmat(q)
+    QT = np.stack([S.rotation_traction(np.eye(3)[j][None], T, 1.0, axes, q)[0][0] for j in range(3)], 1)
+    A2 = Rm @ np.diag(np.asarray(axes) ** 2) @ Rm.T
+    C = 3 * QT @ np.linalg.inv(A2)
+    ct, wt = np.polynomial.legendre.leggauss(160)
+    ph = np.arange(320) * 2 * math.pi / 320
+    st = np.sqrt(1 - ct * ct)
+    n = np.stack([np.outer(ct, np.ones_like(ph)), np.outer(st, np.cos(ph)), np.outer(st, np.sin(ph))], -1).reshape(-1, 3)
+    w = (np.outer(wt, np.ones_like(ph)) * (2 * math.pi / 320)).ravel() / (4 * math.pi)
+    y = (n * np.asarray(axes)) @ Rm.T
+    f = y @ C.T
+    assert np.abs((w[:, None] * np.cross(y, f)).sum(0) - T).max() < 1e-12 * np.abs(T).max()
+    a = axes[0]
+    pts = np.array([[0.0, 0.0, 1.5 * a], [1.6 * a, 1.0, -2.0], [-3.0, 1.5 * a, 2.0]])
+    u = S.spheroid_flow(pts, axes, q, np.zeros(3), T, mu)
+    for x, ux in zip(pts, u):
+        r = x - y
+        R = np.linalg.norm(r, axis=1)[:, None]
+        G = f / R + (r * f).sum(1)[:, None] * r / R ** 3
+        v = (w[:, None] * G).sum(0) / (8 * math.pi * mu)
+        assert np.abs(v - ux).max() < 1e-9 * np.abs(ux).max()
+    for k in (np.array([0.3, -0.2, 0.5]), np.array([0.05, 0.4, 0.1])):
+        ft = (w[:, None] * f * np.exp(-1j * (y @ k))[:, None]).sum(0)
+        gk, j1k = S.rotation_traction(k[None], T, 1.0, axes, q)
+        assert np.abs(ft - (-3j * gk[0] * j1k[0])).max() < 1e-12 * np.abs(ft).max()
