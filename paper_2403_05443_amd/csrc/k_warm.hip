@@ -572,10 +572,16 @@ __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, con
     for (int p = 0; p < np; ++p) {
         const PartDev& P = parts[p];
         if (P.box != bi) continue;
-        // translation: the traction on a translating ellipsoid is the
-        // sphere's uniform layer mapped by diag(a, b, c) in the body frame,
-        // whose transform is sinc(|diag(a, b, c) R^T k|); rotation: the
-        // sphere of radius Req
+        // The traction of a body in rigid motion is sigma(x) (F + C x), sigma
+        // the unit sphere's uniform layer mapped onto the surface: for an
+        // ellipsoid (diag(a, b, c) in the body frame) its transform is
+        // F sinc(kappa) - 3 i (Q^T k) j1(kappa) / kappa, kappa = |diag(a, b, c)
+        // R^T k|, Q = integral of x f^T the first moment: the torque's
+        // antisymmetric part, Q^T k = -(k x T) / 2, and for a prolate spheroid
+        // the line solution's stresslet e^2 / (2 - e^2) sym(p (T_c x p)).
+        // The force is spread on every ellipsoid so; the torque on the
+        // prolate spheroid so and on any other body over the sphere of
+        // radius Req (kappa = |k| Req, no stresslet).
         double Rm[3][3];
         body_to_lab(P.q, Rm);
         double ka2 = 0.0;
@@ -583,22 +589,38 @@ __global__ void k_stokes_coef(const BoxDesc* __restrict__ boxes, int nboxes, con
             const double kb = (k[0] * Rm[0][j] + k[1] * Rm[1][j] + k[2] * Rm[2][j]) * P.axes[j];
             ka2 += kb * kb;
         }
-        const double xa = sqrt(ka2), R = eq_radius(P), xr = sqrt(k2) * R;
-        const double sinc = sin(xa) / xa, j1f = 3.0 * (sin(xr) / xr - cos(xr)) / (xr * xr);
+        const double xa = sqrt(ka2), sinc = sin(xa) / xa;
         const double kF = k[0] * P.Fext[0] + k[1] * P.Fext[1] + k[2] * P.Fext[2];
-        const double kxT[3] = {k[1] * P.Text[2] - k[2] * P.Text[1], k[2] * P.Text[0] - k[0] * P.Text[2],
-                               k[0] * P.Text[1] - k[1] * P.Text[0]};
+        double g[3] = {-0.5 * (k[1] * P.Text[2] - k[2] * P.Text[1]), -0.5 * (k[2] * P.Text[0] - k[0] * P.Text[2]),
+                       -0.5 * (k[0] * P.Text[1] - k[1] * P.Text[0])};  // Q^T k
+        const double a_ = P.axes[0], b_ = P.axes[1];
+        const double e2 = a_ > b_ && b_ == P.axes[2] ? 1.0 - (b_ / a_) * (b_ / a_) : 0.0;
+        double xk = sqrt(k2) * eq_radius(P);
+        if (e2 >= E_LINE * E_LINE) {
+            const double p[3] = {Rm[0][0], Rm[1][0], Rm[2][0]};
+            const double Tp = P.Text[0] * p[0] + P.Text[1] * p[1] + P.Text[2] * p[2];
+            const double Tc[3] = {P.Text[0] - Tp * p[0], P.Text[1] - Tp * p[1], P.Text[2] - Tp * p[2]};
+            const double m[3] = {Tc[1] * p[2] - Tc[2] * p[1], Tc[2] * p[0] - Tc[0] * p[2], Tc[0] * p[1] - Tc[1] * p[0]};
+            const double cs = 0.5 * e2 / (2.0 - e2);
+            const double km = k[0] * m[0] + k[1] * m[1] + k[2] * m[2], kp = k[0] * p[0] + k[1] * p[1] + k[2] * p[2];
+            for (int j = 0; j < 3; ++j) g[j] += cs * (km * p[j] + kp * m[j]);
+            xk = xa;
+        }
+        const double j1k = (sin(xk) - xk * cos(xk)) / (xk * xk * xk);  // j1(kappa) / kappa
+        const double kg = k[0] * g[0] + k[1] * g[1] + k[2] * g[2];
         double sp, cp;
         sincos(-(k[0] * P.xc[0] + k[1] * P.xc[1] + k[2] * P.xc[2]), &sp, &cp);  // exp(-i k . x_c)
         for (int a = 0; a < 3; ++a) {
-            const double re = (P.Fext[a] - k[a] * kF / k2) * sinc / (mu * k2) / V;  // real part of u_hat / V
-            const double im = kxT[a] * j1f / (2.0 * mu * k2) / V;                   // imaginary part
+            // u_hat / V = (I - k k / k^2) f_hat / (mu k^2 V), f_hat = F sinc - 3 i g j1k
+            const double re = (P.Fext[a] - k[a] * kF / k2) * sinc / (mu * k2) / V;
+            const double im = -3.0 * (g[a] - k[a] * kg / k2) * j1k / (mu * k2) / V;
             c[2 * a] += re * cp - im * sp;
             c[2 * a + 1] += re * sp + im * cp;
         }
-        const double pim = -kF * sinc / k2 / V;  // p_hat / V = i pim
-        c[6] += -pim * sp;
-        c[7] += pim * cp;
+        // p_hat / V = -i (k . f_hat) / (k^2 V) = pre + i pim
+        const double pre = -3.0 * kg * j1k / k2 / V, pim = -kF * sinc / k2 / V;
+        c[6] += pre * cp - pim * sp;
+        c[7] += pre * sp + pim * cp;
     }
     for (int a = 0; a < UF; ++a) {
         c[2 * a] -= S[(long long)id * MC + 2 * a] / V;
