@@ -458,7 +458,8 @@ lb_status lb_warm_status(lb_ctx* ctx, int* status, long long* decided_step);
  * solution and the rotlet).  Its Fourier modes |n_i| <= 2 of the box (fewer
  * along an edge shorter than 5) are replaced by those of the periodic flow
  * of the same loads (the force spread as the traction on the translating
- * ellipsoid, the torque as uniform traction on the sphere of radius R), so
+ * ellipsoid, the torque as that on the rotating prolate spheroid, or over
+ * the sphere of radius R for any other body), so
  * the box's slowest shear modes start at their steady values; the same for
  * the flow's pressure p (the Stokeslets' and stresslets'; the periodic
  * modes -i (k.f) / k^2 of the force density f).  A fluid node gets the

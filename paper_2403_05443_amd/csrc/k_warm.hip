@@ -23,7 +23,8 @@
 // minimum-image offsets, rigid inside the body), computed once per node
 // (k_stokes_free) -- whose Fourier modes |n_i| <= 2 are replaced by those of
 // the periodic solution of the same loads (the force spread as the traction
-// on the translating ellipsoid, the torque over the sphere of radius Req),
+// on the translating ellipsoid, the torque as that on the rotating prolate
+// spheroid, or over the sphere of radius Req for other bodies),
 // so the box's slowest shear modes start at their steady values.  A fluid
 // node's density carries the pressure, rho = rho0 + (p - pbar) / c_s^2 (pbar
 // the fluid's mean: the mass is unchanged; without it the pressure builds up
