@@ -322,6 +322,7 @@ def steps_to_steady(runs, eval_boxes, monitor_tol=0.1, wrong_tol=0.02):
             "tol": res["tol"], "sample_every": res["every"],
             "median_steps_plain": m["plain"], "median_steps_surrogate": m["surrogate"],
             "median_steps_control": m["control"],
+            "median_steps_exact_velocity": m["exact_velocity"],
             "surrogate_over_plain": round(res["surrogate_over_plain"], 4),
             "control_over_plain": round(res["control_over_plain"], 4),
             "median_prediction_error": round(res["median_prediction_error"], 5),

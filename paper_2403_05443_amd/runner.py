@@ -362,11 +362,13 @@ def sphere_array_run(L, R=4.0, force=2e-3, steps=None):
 
 # ------------------------------------------------------- steps to steady --
 
-def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25, tol=0.0):
-    """Velocities U of every particle every `every` steps from one of three
+def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25, tol=0.0, velocities=None):
+    """Velocities U of every particle every `every` steps from one of four
     starts: 'plain' (rest), 'surrogate' (lb_warm_start; with tol > 0 its
     boxes are watched on the device and fall back to the plain start when the
-    prediction fails), 'control' (closed forms + Stokes start field).  Returns
+    prediction fails), 'control' (closed forms + Stokes start field), 'given'
+    (the particles' velocities `velocities` (np, 3), no rotation, + Stokes
+    start field: with the steady velocities it tests the field alone).  Returns
     (times, U (nt, np, 3), pred, info) with info holding the start's wall
     time (start_ms) and, for the surrogate start, the device's decision per
     box and the samples (X, Y) of every particle at the end of the run."""
@@ -384,6 +386,10 @@ def trajectory(W, start="plain", surrogate=None, steps=1000, every=25, graph=25,
             U, Wv = unbounded_velocities(p, nu)
             lat.set_velocity(i, U, Wv)
             pred[i] = np.concatenate([U, Wv])
+        lat.stokes_start()
+    elif start == "given":
+        for i in range(len(W.particles)):
+            lat.set_velocity(i, velocities[i], (0.0, 0.0, 0.0))
         lat.stokes_start()
     lat.sync()
     info["start_ms"] = 1e3 * (time.perf_counter() - t0)
@@ -679,9 +685,10 @@ def _status_name(code):
 
 def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0.1):
     """Steps to a tol-accurate steady velocity for each particle of the
-    force-driven ensemble W from the three starts.  The steady velocity is
-    the end of the plain run; a box counts only if that run changed by less
-    than 0.05% over its last slow time.  The surrogate run is watched on the
+    force-driven ensemble W from the three starts, and from the start field
+    with the exact steady velocities (the field's own share).  The steady
+    velocity is the end of the plain run; a box counts only if that run
+    changed by less than 0.05% over its last slow time.  The surrogate run is watched on the
     device (lb_warm_start with monitor_tol): at W0 = ceil(2 a^2 / nu) steps a
     box whose velocity missed the prediction while the run still moved falls
     back to the plain start, and its steps count from the warm start; boxes
@@ -694,13 +701,14 @@ def compare_starts(W, surrogate, efolds=12.0, every=25, tol=0.005, monitor_tol=0
     ts, Us, pred, info = trajectory(W, "surrogate", surrogate, steps=steps, every=every, tol=monitor_tol)
     tc, Uc, _, cinfo = trajectory(W, "control", steps=steps, every=every)
     Uinf = Up[-1]
+    tx, Ux, _, _ = trajectory(W, "given", steps=steps, every=every, velocities=Uinf)
     ok = np.ones(len(W.particles), dtype=bool)
     for i, p in enumerate(W.particles):
         lag = int(round(slow_time(box_edge(W, i), nu) / every))
         ok[i] = np.linalg.norm(Up[-1, i] - Up[-1 - lag, i]) < 5e-4 * np.linalg.norm(Uinf[i])
     status = np.array([info["status"][p.box] for p in W.particles])
     n = {"plain": steps_to_tolerance(tp, Up, Uinf, tol), "surrogate": steps_to_tolerance(ts, Us, Uinf, tol),
-         "control": steps_to_tolerance(tc, Uc, Uinf, tol)}
+         "control": steps_to_tolerance(tc, Uc, Uinf, tol), "exact_velocity": steps_to_tolerance(tx, Ux, Uinf, tol)}
     err0 = {"surrogate": np.linalg.norm(Us[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1),
             "control": np.linalg.norm(Uc[0] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)}
     pred_err = np.linalg.norm(pred[:, :3] - Uinf, axis=1) / np.linalg.norm(Uinf, axis=1)
