@@ -399,7 +399,8 @@ def test_surrogate_warm_start_reaches_steady_state_sooner(lb, trained):
     within 0.5% of the steady one is below the closed-form control's (the
     same start without the network) and under a tenth of the plain start's
     (measured 50 against 325 and 1275), and the device monitor accepts the
-    network's predictions."""
+    network's predictions.  Started at the exact steady velocities, the
+    start field alone is steady within two samples (50 steps)."""
     from paper_2403_05443_amd import runner, workloads
     res = runner.compare_starts(workloads.c4(**HELD_OUT), trained, monitor_tol=0.1)
     for k in ("per_box", "steady", "status", "queued_samples"):
@@ -408,6 +409,7 @@ def test_surrogate_warm_start_reaches_steady_state_sooner(lb, trained):
     m = res["median_steps"]
     assert res["steady_boxes"] >= 24
     assert m["surrogate"] < 0.1 * m["plain"] and m["surrogate"] < m["control"]
+    assert m["exact_velocity"] <= 50
     assert res["accepted_rate"] >= 0.9
 
 
