@@ -310,7 +310,7 @@ __device__ void particle_flow(const PartDev& P, double mu, const double d[3], do
             const double wq = 0.5 * tm * wj * delta * 0.5 * (et + it);
             const double r[3] = {d[0] - xi * p[0], d[1] - xi * p[1], d[2] - xi * p[2]};
             const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const double iR = 1.0 / sqrt(R2), iR2 = iR * iR, iR3 = iR * iR2, iR5 = iR3 * iR2, iR7 = iR5 * iR2;
+            const double iR = rsqrt(R2), iR2 = iR * iR, iR3 = iR * iR2, iR5 = iR3 * iR2, iR7 = iR5 * iR2;
             const double g = (f - xi) * (f + xi);
             const double Sr = S1[0] * r[0] + S1[1] * r[1] + S1[2] * r[2];
             const double rp = r[0] * p[0] + r[1] * p[1] + r[2] * p[2];
