@@ -329,6 +329,34 @@ def test_single_box_warm_start_matches_the_full_start_in_that_box(lb):
         assert np.array_equal(rho, rho_ref) and np.array_equal(u, u_ref), b
 
 
+def test_one_box_warm_start_beside_a_walled_box(lb):
+    """A context holding a walled Couette box and a periodic box: a warm
+    start of the periodic box alone (its free flow staged in its own block of
+    the spare populations) leaves the walled box's run bit for bit what it is
+    without the warm start, before and over the following steps."""
+    s = lb.Surrogate(max_samples=8, params=_params(600, scale=0.5))
+    runs = []
+    for warm in (False, True):
+        wall = lb.make_box(24, 20, 22, walls=True, wall_lo=(-0.01, 0, 0), wall_hi=(0.01, 0, 0), init="couette")
+        g = lb.Lattice([wall, lb.make_box(28, 24, 26)], collision="trt", tau=0.8, storage="fp32",
+                       counterforce=True, max_particles=2)
+        g.add_ellipsoid((11.5, 9.7, 10.8), (4.0, 2.0, 2.0), (1, 0, 0, 0), box=0)
+        q = np.array([0.8, 0.3, -0.4, 0.33]) / np.linalg.norm([0.8, 0.3, -0.4, 0.33])
+        pid = g.add_ellipsoid((13.2, 11.6, 12.9), (6.0, 2.5, 2.5), q, box=1)
+        g.set_external(pid, (3e-5, -2e-5, 1e-5), (0, 1e-4, 0))
+        g.step(5)
+        if warm:
+            g.warm_start(s, box=1)
+        first = g.fields(0)
+        g.step(20)
+        runs.append((first, g.fields(0), g.particle(0)))
+    (f0, f1, p0), (g0, g1, q0) = runs
+    for a, b in ((f0, g0), (f1, g1)):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for k in p0:
+        assert np.array_equal(p0[k], q0[k]), k
+
+
 def test_warm_started_trajectory_matches_oracle(lb):
     """From the start field, 60 steps of the library and of the oracle agree
     at the FP64 bar."""
